@@ -1,0 +1,203 @@
+/*
+ * gmresir.h -- C ABI of the MI355X mixed-precision GMRES-IR solver with
+ * Krylov subspace recycling (RGMRES-IR).
+ *
+ * Method: Oktay & Carson, "Mixed Precision GMRES-based Iterative Refinement
+ * with Recycling".  gmresir_factor is line 1 of Algorithm 3 (LU factorisation
+ * in precision u_f); gmresir_solve is lines 2-7 of Algorithm 3 (refinement
+ * loop whose correction equation U^-1 L^-1 A d = U^-1 L^-1 r is solved by the
+ * GCRO-DR algorithm of Section 2, with the preconditioned product computed in
+ * precision u^2).  With k = 0 the correction solver is restarted GMRES(m),
+ * i.e. Algorithm 2 (GMRES-IR).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are dense, row-major (C order), float64, leading dimension
+ *     lda >= n (elements).  Vectors are float64 and contiguous (stride 1).
+ *   - "device pointer": memory allocated on the HIP device that is current
+ *     when the call is made (hipMalloc, or a torch CUDA tensor on ROCm).
+ *     "host pointer": ordinary CPU memory.
+ *   - stream: a hipStream_t passed as void*; NULL means the null stream.
+ *     Every call is blocking: it synchronises the stream before returning,
+ *     so inputs may be reused and outputs read as soon as it returns.
+ *   - Return value: 0 on success.  Negative values are caller or runtime
+ *     errors, positive values are numerical outcomes (see gmresir_status).
+ *     No C++ exception crosses this interface.
+ *   - A handle is not re-entrant: calls on one handle must not overlap.
+ *     Distinct handles are independent.
+ */
+#ifndef GMRESIR_H
+#define GMRESIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GMRESIR_ABI_VERSION 1
+
+typedef enum {
+  GMRESIR_OK = 0,
+  GMRESIR_EINVAL = -1,      /* invalid argument (null pointer, n <= 0, lda < n,
+                               m <= k, k < 0, tau <= 0, unsupported or
+                               mis-ordered precisions, struct_size mismatch) */
+  GMRESIR_ENOMEM = -2,      /* device or host allocation failed             */
+  GMRESIR_EHIP = -3,        /* HIP runtime error (text: gmresir_last_error) */
+  GMRESIR_EINTERNAL = -4,   /* a device-side wait exceeded its bound        */
+  GMRESIR_ESINGULAR = 1,    /* exact zero pivot in u_f (column in info)     */
+  GMRESIR_ERANGE = 2,       /* non-finite input, or overflow to u_f         */
+  GMRESIR_ENOCONV = 3       /* i_max refinement steps without reaching the
+                               backward-error target; x holds the last
+                               iterate                                       */
+} gmresir_status;
+
+/* Precisions of Algorithm 3 (Section 3): u_f factorisation, u working
+ * precision of GCRO-DR, u_r residual.  u^2 (the precision of the
+ * preconditioned product) is fp64 for u = fp32 and double-double for
+ * u = fp64.  Supported triples: u_f in {FP16, BF16, FP32}, u in {FP32, FP64},
+ * u_r in {FP64, DD}, with unit roundoff u_f >= u >= u_r. */
+typedef enum {
+  GMRESIR_BF16 = 1,
+  GMRESIR_FP16 = 2,
+  GMRESIR_FP32 = 3,
+  GMRESIR_FP64 = 4,
+  GMRESIR_DD = 5
+} gmresir_prec;
+
+typedef struct {
+  uint32_t struct_size;   /* must equal sizeof(gmresir_opts)                 */
+  int32_t uf, u, ur;      /* gmresir_prec values                             */
+  int32_t m;              /* restart length (maximum subspace size), m >= 1  */
+  int32_t k;              /* recycled dimension, 0 <= k < m (0: GMRES(m))    */
+  double tau;             /* GMRES tolerance on the relative preconditioned
+                             residual (Section 4), tau > 0                    */
+  int32_t imax;           /* maximum refinement steps (Algorithm 3 i_max)     */
+  int32_t maxit;          /* Arnoldi steps per correction solve; 0 -> 10 m    */
+  double berr_target;     /* stop when ||r||_inf / (||A||_inf ||x||_inf +
+                             ||b||_inf) <= berr_target                        */
+  int32_t scale_pow2;     /* -1 auto (on for FP16), 0 off, 1 on: multiply A by
+                             2^e before rounding to u_f (exact; undone in the
+                             preconditioner)                                  */
+  int32_t keep_recycle;   /* 1: the recycled pair survives between
+                             gmresir_solve calls on the same handle          */
+  int32_t reserved[4];    /* must be zero                                    */
+} gmresir_opts;
+
+/* Per-solve record, filled by gmresir_solve (host struct). */
+#define GMRESIR_MAX_STEPS 64
+typedef struct {
+  int32_t status;                      /* gmresir_status of the solve       */
+  int32_t steps;                       /* corrections applied               */
+  int32_t total_its;                   /* sum of its[]                      */
+  int32_t its[GMRESIR_MAX_STEPS];      /* Arnoldi steps per correction, the
+                                          paper's "total (i1, i2, ...)"     */
+  double berr[GMRESIR_MAX_STEPS + 1];  /* normwise backward error before
+                                          each correction and at the end    */
+  int32_t singular_col;                /* 1-based column of the zero pivot  */
+  int32_t recycle_dim;                 /* dimension of U_k at the end       */
+  double t_factor_s;                   /* wall time of gmresir_factor       */
+  double t_solve_s;                    /* wall time of this gmresir_solve   */
+} gmresir_info;
+
+typedef struct gmresir_ctx gmresir_ctx;
+
+/* Fill *opts with defaults: (FP16, FP32, FP64), m = 30, k = 10, tau = 1e-4,
+ * imax = 10, maxit = 0, berr_target = 1e-14, scale_pow2 = -1,
+ * keep_recycle = 0. */
+void gmresir_default_opts(gmresir_opts* opts);
+
+/*
+ * gmresir_factor -- Algorithm 3, line 1: LU factorisation with partial
+ * pivoting of A in precision u_f (Section 1, GEPP), plus the copies of A
+ * the solve needs (A in fp64 for the residual, A_u = fl_u(A) for the
+ * preconditioned product) and ||A||_inf.
+ *
+ *   A      device pointer, n x n float64, row-major, leading dimension lda.
+ *          Read only; the library copies what it needs.
+ *   n      order of A (n >= 1); lda >= n.
+ *   opts   host pointer to options (copied).
+ *   stream hipStream_t or NULL.
+ *   out    host pointer receiving a new handle (set to NULL on failure).
+ *
+ * Returns 0, GMRESIR_ESINGULAR (a handle is still returned so the caller can
+ * inspect or free it; gmresir_solve on it returns ESINGULAR),
+ * GMRESIR_ERANGE (non-finite entry or overflow in u_f; handle returned
+ * likewise), EINVAL, ENOMEM, EHIP or EINTERNAL (no handle).
+ * The handle owns all device memory it uses; release it with gmresir_free.
+ */
+int gmresir_factor(const double* A, int64_t n, int64_t lda,
+                   const gmresir_opts* opts, void* stream, gmresir_ctx** out);
+
+/*
+ * gmresir_solve -- Algorithm 3, lines 2-7: x0 = M^-1 b, then refinement
+ * steps r = b - A x (in u_r), r-hat = r / ||r||_inf, GCRO-DR(m, k) on
+ * U^-1 L^-1 P A d = U^-1 L^-1 P r-hat with the product in u^2, and
+ * x = x + ||r||_inf d, until the backward error reaches opts.berr_target.
+ *
+ *   h      handle from gmresir_factor or gmresir_import_factors.
+ *   b      device pointer, nrhs right-hand sides of length n, column j at
+ *          b + j * ldb (ldb >= n).  Read only.
+ *   x      device pointer, same layout as b; receives the solutions.
+ *   nrhs   >= 1; the columns are solved one after another, and the recycled
+ *          space carries over between them when opts.keep_recycle = 1.
+ *   stream hipStream_t or NULL (overrides the factor stream for this call).
+ *   info   host pointer or NULL; describes the LAST right-hand side.
+ *
+ * Returns the status of the last column (0, ENOCONV, ESINGULAR, ERANGE for a
+ * non-finite b) or a negative error.  On ENOCONV x holds the last iterate.
+ */
+int gmresir_solve(gmresir_ctx* h, const double* b, double* x, int64_t nrhs,
+                  int64_t ldb, void* stream, gmresir_info* info);
+
+/* Release every resource of the handle.  NULL is accepted.  The handle must
+ * not be used afterwards. */
+void gmresir_free(gmresir_ctx* h);
+
+/* Static description of a status code. */
+const char* gmresir_strerror(int status);
+
+/* Text of the last HIP or validation error seen in this thread. */
+const char* gmresir_last_error(void);
+
+/*
+ * gmresir_import_factors -- build a handle from LU factors computed
+ * elsewhere (same meaning as after gmresir_factor): P 2^e A = L U with L unit
+ * lower and U upper packed row-major in lu (device pointer, n x n, leading
+ * dimension ldlu, element type u_f: 2-byte IEEE half or bfloat16 bits, or
+ * float32), ipiv host pointer of n LAPACK-style 0-based interchanges (row i
+ * was swapped with row ipiv[i] at step i), e the power-of-two scale.
+ * A (device, float64) is the unscaled matrix.  Used to run the solve phase on
+ * given factors.  Same return values as gmresir_factor except ESINGULAR.
+ */
+int gmresir_import_factors(const double* A, int64_t n, int64_t lda,
+                           const void* lu, int64_t ldlu, const int32_t* ipiv,
+                           int32_t e, const gmresir_opts* opts, void* stream,
+                           gmresir_ctx** out);
+
+/*
+ * gmresir_export_factors -- copy the factors of a handle: lu (host pointer,
+ * n x n row-major, element type u_f as in gmresir_import_factors, leading
+ * dimension n), ipiv (host, n int32, LAPACK style, 0-based) and *e.  Any
+ * output pointer may be NULL.
+ */
+int gmresir_export_factors(gmresir_ctx* h, void* lu, int32_t* ipiv, int32_t* e);
+
+/*
+ * gmresir_apply -- one preconditioned product of the solve phase, for
+ * inspection: op = 0: y = M^-1 v = 2^e U^-1 L^-1 P v; op = 1:
+ * y = A-tilde v = M^-1 A_u v.  Both are computed in u^2 and returned
+ * unrounded (float64; the high part for double-double).  v and y are device
+ * pointers of n float64 values (v must hold u values for op = 1).
+ */
+int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y,
+                  void* stream);
+
+/* Size n and ABI version of a handle (either pointer may be NULL). */
+int gmresir_query(gmresir_ctx* h, int64_t* n, int32_t* abi_version);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMRESIR_H */

@@ -1,0 +1,305 @@
+"""Python binding of libgmresir (mixed-precision GMRES-IR with recycling).
+
+Argument marshalling only: every step of the method runs in the HIP library
+(``libgmresir.so``, C ABI in ``include/gmresir.h``).  PyTorch provides device
+memory and the stream.  There is no fallback: when the library is missing or
+cannot be loaded, every entry point raises.
+
+Method: Oktay & Carson, "Mixed Precision GMRES-based Iterative Refinement
+with Recycling" -- Algorithm 3 (RGMRES-IR), with GMRES-IR (Algorithm 2) as
+the k = 0 case.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "GmresirError",
+    "PREC",
+    "STATUS",
+    "library_path",
+    "load_library",
+    "default_opts",
+    "factor",
+    "import_factors",
+    "Handle",
+    "EXPORTED",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+PREC = {"bf16": 1, "fp16": 2, "fp32": 3, "fp64": 4, "dd": 5}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EINTERNAL",
+          1: "ESINGULAR", 2: "ERANGE", 3: "ENOCONV"}
+MAX_STEPS = 64
+
+# every symbol declared in include/gmresir.h
+EXPORTED = (
+    "gmresir_default_opts", "gmresir_factor", "gmresir_solve", "gmresir_free",
+    "gmresir_strerror", "gmresir_last_error", "gmresir_import_factors",
+    "gmresir_export_factors", "gmresir_apply", "gmresir_query",
+)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("uf", ctypes.c_int32),
+        ("u", ctypes.c_int32),
+        ("ur", ctypes.c_int32),
+        ("m", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("imax", ctypes.c_int32),
+        ("maxit", ctypes.c_int32),
+        ("berr_target", ctypes.c_double),
+        ("scale_pow2", ctypes.c_int32),
+        ("keep_recycle", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("total_its", ctypes.c_int32),
+        ("its", ctypes.c_int32 * MAX_STEPS),
+        ("berr", ctypes.c_double * (MAX_STEPS + 1)),
+        ("singular_col", ctypes.c_int32),
+        ("recycle_dim", ctypes.c_int32),
+        ("t_factor_s", ctypes.c_double),
+        ("t_solve_s", ctypes.c_double),
+    ]
+
+
+class GmresirError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gmresir status {status} ({STATUS.get(status, '?')}): {message}")
+        self.status = status
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return os.environ.get("GMRESIR_LIB", os.path.join(_HERE, "libgmresir.so"))
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libgmresir.so (raises OSError if it is missing)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with `python -m paper_2201_09827_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.gmresir_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.gmresir_default_opts.restype = None
+    lib.gmresir_factor.argtypes = [vp, i64, i64, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    lib.gmresir_factor.restype = ctypes.c_int
+    lib.gmresir_solve.argtypes = [vp, vp, vp, i64, i64, vp, ctypes.POINTER(Info)]
+    lib.gmresir_solve.restype = ctypes.c_int
+    lib.gmresir_free.argtypes = [vp]
+    lib.gmresir_free.restype = None
+    lib.gmresir_strerror.argtypes = [ctypes.c_int]
+    lib.gmresir_strerror.restype = ctypes.c_char_p
+    lib.gmresir_last_error.argtypes = []
+    lib.gmresir_last_error.restype = ctypes.c_char_p
+    lib.gmresir_import_factors.argtypes = [vp, i64, i64, vp, i64, ctypes.POINTER(i32), i32,
+                                           ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    lib.gmresir_import_factors.restype = ctypes.c_int
+    lib.gmresir_export_factors.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.gmresir_export_factors.restype = ctypes.c_int
+    lib.gmresir_apply.argtypes = [vp, i32, vp, vp, vp]
+    lib.gmresir_apply.restype = ctypes.c_int
+    lib.gmresir_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    lib.gmresir_query.restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    load_library().gmresir_default_opts(ctypes.byref(o))
+    return o
+
+
+def _opts(**kw) -> Opts:
+    o = default_opts()
+    for key, val in kw.items():
+        if key in ("uf", "u", "ur") and isinstance(val, str):
+            val = PREC[val]
+        if key == "keep_recycle" or key == "scale_pow2":
+            val = int(val)
+        if not hasattr(o, key):
+            raise TypeError(f"unknown option {key!r}")
+        setattr(o, key, val)
+    return o
+
+
+def _err(lib, status: int) -> GmresirError:
+    msg = lib.gmresir_strerror(status).decode()
+    last = lib.gmresir_last_error().decode()
+    return GmresirError(status, f"{msg}; {last}" if last else msg)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_matrix(a):
+    import torch
+    if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64
+            and a.dim() == 2 and a.shape[0] == a.shape[1] and a.stride(1) == 1):
+        raise ValueError("A must be a square row-major float64 CUDA tensor")
+
+
+def _info_dict(info: Info) -> dict:
+    steps = int(info.steps)
+    return {
+        "status": int(info.status),
+        "status_name": STATUS.get(int(info.status), "?"),
+        "steps": steps,
+        "total_its": int(info.total_its),
+        "its": [int(info.its[i]) for i in range(min(steps, MAX_STEPS))],
+        "berr": [float(info.berr[i]) for i in range(min(steps, MAX_STEPS) + 1)],
+        "singular_col": int(info.singular_col),
+        "recycle_dim": int(info.recycle_dim),
+        "t_factor_s": float(info.t_factor_s),
+        "t_solve_s": float(info.t_solve_s),
+    }
+
+
+class Handle:
+    """A factorised matrix (owns the library handle)."""
+
+    def __init__(self, lib, ptr: ctypes.c_void_p, n: int, opts: Opts, status: int):
+        self._lib = lib
+        self._ptr = ptr
+        self.n = n
+        self.opts = opts
+        self.status = status
+
+    def _live(self):
+        if not self._ptr:
+            raise RuntimeError("handle has been freed")
+        return self._ptr
+
+    def solve(self, b, stream=None):
+        """Solve A x = b (b: float64 CUDA tensor, (n,) or (n, nrhs) column-major
+        via the transpose of a C-contiguous (nrhs, n) tensor).  Returns
+        (x, info) with info describing the last column; raises on a negative
+        status, reports ENOCONV/ESINGULAR/ERANGE in info['status']."""
+        import torch
+        ptr = self._live()
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64):
+            raise ValueError("b must be a float64 CUDA tensor")
+        if b.dim() == 1:
+            if b.shape[0] != self.n or b.stride(0) != 1:
+                raise ValueError("b has the wrong length or stride")
+            nrhs, ldb = 1, self.n
+            x = torch.empty_like(b)
+        else:
+            bt = b.t()
+            if b.shape[0] != self.n or not bt.is_contiguous():
+                raise ValueError("2-D b must be the transpose of a contiguous (nrhs, n) tensor")
+            nrhs, ldb = b.shape[1], self.n
+            x = torch.empty((nrhs, self.n), dtype=torch.float64, device=b.device).t()
+        info = Info()
+        rc = self._lib.gmresir_solve(ptr, ctypes.c_void_p(b.data_ptr()),
+                                     ctypes.c_void_p(x.data_ptr()), nrhs, ldb, _stream(stream),
+                                     ctypes.byref(info))
+        if rc < 0:
+            raise _err(self._lib, rc)
+        return x, _info_dict(info)
+
+    def apply(self, op: int, v, stream=None):
+        """op 0: M^-1 v; op 1: A-tilde v (both in u^2, unrounded fp64)."""
+        import torch
+        ptr = self._live()
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64
+                and v.shape == (self.n,) and v.is_contiguous()):
+            raise ValueError("v must be a contiguous float64 CUDA vector of length n")
+        y = torch.empty_like(v)
+        rc = self._lib.gmresir_apply(ptr, int(op), ctypes.c_void_p(v.data_ptr()),
+                                     ctypes.c_void_p(y.data_ptr()), _stream(stream))
+        if rc != 0:
+            raise _err(self._lib, rc)
+        return y
+
+    def export_factors(self):
+        """(lu, ipiv, e): lu as numpy uint16 (fp16/bf16 bits) or float32,
+        row-major n x n in logical (pivoted) row order; ipiv LAPACK style."""
+        import numpy as np
+        ptr = self._live()
+        dt = np.float32 if self.opts.uf == PREC["fp32"] else np.uint16
+        lu = np.empty((self.n, self.n), dtype=dt)
+        ipiv = np.empty(self.n, dtype=np.int32)
+        e = ctypes.c_int32(0)
+        rc = self._lib.gmresir_export_factors(
+            ptr, lu.ctypes.data_as(ctypes.c_void_p),
+            ipiv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(e))
+        if rc != 0:
+            raise _err(self._lib, rc)
+        return lu, ipiv, int(e.value)
+
+    def free(self):
+        if self._ptr:
+            self._lib.gmresir_free(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def factor(a, stream=None, **opts) -> Handle:
+    """LU-factorise A (Algorithm 3, line 1).  ``a``: square row-major float64
+    CUDA tensor.  Options: uf, u, ur ('fp16', 'bf16', 'fp32', 'fp64', 'dd'),
+    m, k, tau, imax, maxit, berr_target, scale_pow2, keep_recycle.  Raises
+    GmresirError on a negative status; ESINGULAR/ERANGE return a handle whose
+    ``status`` says so."""
+    lib = load_library()
+    _check_matrix(a)
+    o = _opts(**opts)
+    out = ctypes.c_void_p()
+    rc = lib.gmresir_factor(ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0),
+                            ctypes.byref(o), _stream(stream), ctypes.byref(out))
+    if rc < 0:
+        raise _err(lib, rc)
+    return Handle(lib, out, a.shape[0], o, rc)
+
+
+def import_factors(a, lu, ipiv, e: int, stream=None, **opts) -> Handle:
+    """Handle from given factors: ``lu`` a CUDA tensor of u_f elements
+    (int16/uint16 bits for fp16/bf16, float32 for fp32), row-major n x n in
+    logical row order; ``ipiv`` a host sequence of n LAPACK-style 0-based
+    interchanges; ``e`` the power-of-two scale."""
+    import numpy as np
+    lib = load_library()
+    _check_matrix(a)
+    o = _opts(**opts)
+    piv = np.ascontiguousarray(np.asarray(ipiv, dtype=np.int32))
+    out = ctypes.c_void_p()
+    rc = lib.gmresir_import_factors(
+        ctypes.c_void_p(a.data_ptr()), a.shape[0], a.stride(0), ctypes.c_void_p(lu.data_ptr()),
+        lu.stride(0), piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(e),
+        ctypes.byref(o), _stream(stream), ctypes.byref(out))
+    if rc < 0:
+        raise _err(lib, rc)
+    return Handle(lib, out, a.shape[0], o, rc)

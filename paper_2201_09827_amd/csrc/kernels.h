@@ -1,0 +1,126 @@
+// Host-side launchers of the gmresir HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace gir {
+
+enum StoreType { kStoreF16 = 0, kStoreBF16 = 1, kStoreF32 = 2 };
+
+// ---- factorisation ---------------------------------------------------------
+
+// scan A (fp64): out[0] = max |a| bits, out[1] = max row-sum bits, flag[0] = 1
+// if a non-finite entry exists.  out/flag must be zeroed.
+void launch_scan(const double* A, int64_t n, int64_t lda,
+                 unsigned long long* out, int* flag, hipStream_t s);
+// S = fl_uf(2^e A) if S != nullptr (row-major, ld), Au = fl32(A) if Au != nullptr; padding
+// columns [n, ld) are zeroed; flag[0] = 1 if a u_f value overflowed.
+void launch_convert(const double* A, int64_t n, int64_t lda, int e, int store,
+                    void* S, float* Au, int64_t ld, int* flag, hipStream_t s);
+void launch_iota(int* p, int64_t n, hipStream_t s);
+
+struct PanelArgs {
+  void* S;          // u_f storage, physical row order
+  int64_t ld;
+  int n;
+  int k0;           // first column of the panel
+  int kb;           // panel width (<= nb)
+  int* perm;        // logical -> physical rows
+  int* ptmp;        // [n] scratch: new order of logical rows k0..n-1
+  float* P;         // panel work buffer, column-major, ldp
+  int ldp;
+  int* pstep;       // [n]
+  int* piv_prow;    // [nb]
+  int* lidx;        // [n]
+  int* ipiv;        // [n] LAPACK-style (0-based)
+  int* sync;        // [2] zeroed before the panel kernel
+  CycleState* st;   // abort + singular reporting
+};
+// one block column of the blocked right-looking GEPP (lazy row interchanges)
+void launch_panel_step(const PanelArgs& a, int store, int nhelpers, hipStream_t s);
+// the block row to the right of the panel and the trailing update
+void launch_trsm_update(const PanelArgs& a, int store, hipStream_t s);
+// after the last panel: non-finite check of the factors
+void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,
+                          hipStream_t s);
+
+// ---- solve phase -----------------------------------------------------------
+
+// t[i] = sum_c Au[permA[i]][c] v[c] in fp64 (v float or double)
+void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const float* v32,
+                    const double* v64, double* t, const CycleState* gate, int step,
+                    hipStream_t s);
+// r = b - A x (fp64); norms[0] = max|r| bits, norms[1] = max|x| bits (zeroed here)
+void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
+                     double* r, unsigned long long* norms, hipStream_t s);
+// y = L^-1 (in gathered by permIn), fp64; L unit lower in S rows permS
+void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
+                       const double* in, const int* permIn, double* y, int* flags, int epoch,
+                       const CycleState* gate, int step, int* abort, hipStream_t s);
+// z = U^-1 y; out64 = 2^e z, out32 = fl32(2^e z) (either may be null)
+void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
+                       const double* y, double* z, double scale, double* out64, float* out32,
+                       int* flags, int epoch, const CycleState* gate, int step, int* abort,
+                       hipStream_t s);
+
+struct Basis {
+  const double* c64;  // kc columns, column-major, ld ldc
+  int kc;
+  int64_t ldc;
+  const float* v32;   // nv columns, column-major, ld ldv
+  int nv;
+  int64_t ldv;
+};
+
+enum OrthoMode { kOrthoDots = 1, kOrthoUpdate = 2, kOrthoNorm = 4, kOrthoFinish = 8 };
+struct OrthoArgs {
+  Basis X;
+  int n;
+  const float* w_in;
+  float* w_out;           // may equal w_in
+  const double* coef;     // update coefficients (kc + nv) when kOrthoUpdate
+  double* dots_out;       // kc + nv inner products (kOrthoDots)
+  double* norm_out;       // squared 2-norm of the (updated) vector (kOrthoNorm)
+  double* partial;        // grid * (kc + nv + 1)
+  unsigned int* counter;  // zeroed, reset by the last block
+  // finish (Arnoldi step j): H (m+1) x m col-major, B k x m col-major
+  const double* h_prev;   // first-pass coefficients (h = h_prev + coef)
+  double* H;
+  double* B;
+  int ldh, ldb;
+  int step;
+  double* cs;
+  double* sn;
+  double* g;
+  CycleState* st;
+  const CycleState* gate;
+};
+void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s);
+// v_out = fl32(w / H[j+1][j])
+void launch_normalize(const float* w, float* vout, const double* H, int ldh, int step, int n,
+                      const CycleState* gate, hipStream_t s);
+
+// out (n x nout, col-major fp64, ld ldo) = X M, M (ncol x nout col-major) on device
+void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,
+                    hipStream_t s);
+// d = fl32(d + Xd cd), r = fl32(r - Xr cr); either part skipped when its vector is null
+void launch_cycle_update(const Basis& Xd, const double* cd, float* d, const Basis& Xr,
+                         const double* cr, float* r, int n, hipStream_t s);
+// G (nx x ny, col-major) = X^T Y for fp64 Y (n x ny, ld ldy)
+void launch_gram(const Basis& X, const double* Y, int ny, int64_t ldy, int n, double* G,
+                 double* partial, unsigned int* counter, hipStream_t s);
+// out = fl32(r / s), held in fp64
+void launch_scale_round(const double* r, double s, double* out, int n, hipStream_t st);
+// x = x + s d (two roundings, no fused multiply-add)
+void launch_x_update(double* x, const float* d, double s, int n, hipStream_t st);
+// out = fl32(w / s)
+void launch_div_f32(const float* w, double s, float* out, int n, hipStream_t st);
+// out[0] = max |v_i| (as bits)
+void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t st);
+void launch_copy_f32_to_f64(const float* a, double* b, int n, hipStream_t s);
+void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
+
+}  // namespace gir

@@ -1,0 +1,629 @@
+// Solve-phase kernels of RGMRES-IR (Algorithm 3 and the GCRO-DR algorithm of
+// Section 2) on gfx950.
+//
+//  * preconditioned product A-tilde v = 2^e U^-1 L^-1 P A_u v in u^2 = fp64:
+//    a row-gathered GEMV with fp32 A_u and fp64 accumulation, then two
+//    blocked triangular solves with the u_f factors (fp64 arithmetic);
+//  * residual r = b - A x in fp64 with the infinity norms of r and x;
+//  * Arnoldi orthogonalisation against [C_k, V_j] by classical Gram-Schmidt
+//    applied twice; inner products in fp64, vectors stored in fp32; the
+//    Hessenberg column, its Givens rotation and the residual estimate are
+//    updated on the device so that no host round trip sits inside a cycle;
+//  * skinny products with the recycle space (combine, gram, updates).
+#include "kernels.h"
+
+namespace gir {
+
+namespace {
+
+constexpr int kTB = 64;  // triangular-solve block (rows per workgroup)
+
+// ---------------------------------------------------------------------------
+// GEMV: t[i] = sum_c Au[permA[i]][c] v[c], one wave per row, fp64 accumulate
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, int64_t ld,
+                                                 const int* __restrict__ permA, int n,
+                                                 const VT* __restrict__ v, double* __restrict__ t,
+                                                 const CycleState* gate, int step) {
+  if (gated_off(gate, step)) return;
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= n) return;
+  const int prow = permA ? permA[row] : row;
+  const float* a = Au + (int64_t)prow * ld;
+  double acc0 = 0.0, acc1 = 0.0;
+  const int n4 = n & ~3;
+  int c = lane * 4;
+  for (; c + 256 < n4; c += 512) {
+    const float4 x0 = *reinterpret_cast<const float4*>(a + c);
+    const float4 x1 = *reinterpret_cast<const float4*>(a + c + 256);
+    acc0 = fma((double)x0.x, (double)v[c + 0], acc0);
+    acc1 = fma((double)x0.y, (double)v[c + 1], acc1);
+    acc0 = fma((double)x0.z, (double)v[c + 2], acc0);
+    acc1 = fma((double)x0.w, (double)v[c + 3], acc1);
+    acc0 = fma((double)x1.x, (double)v[c + 256], acc0);
+    acc1 = fma((double)x1.y, (double)v[c + 257], acc1);
+    acc0 = fma((double)x1.z, (double)v[c + 258], acc0);
+    acc1 = fma((double)x1.w, (double)v[c + 259], acc1);
+  }
+  for (; c < n4; c += 256) {
+    const float4 x0 = *reinterpret_cast<const float4*>(a + c);
+    acc0 = fma((double)x0.x, (double)v[c + 0], acc0);
+    acc1 = fma((double)x0.y, (double)v[c + 1], acc1);
+    acc0 = fma((double)x0.z, (double)v[c + 2], acc0);
+    acc1 = fma((double)x0.w, (double)v[c + 3], acc1);
+  }
+  for (int cc = n4 + lane; cc < n; cc += kWave) acc0 = fma((double)a[cc], (double)v[cc], acc0);
+  const double s = wave_sum(acc0 + acc1);
+  if (lane == 0) t[row] = s;
+}
+
+// ---------------------------------------------------------------------------
+// residual r = b - A x (fp64), norms[0] = max |r_i|, norms[1] = max |x_i|
+// ---------------------------------------------------------------------------
+__global__ void k_zero_u64(unsigned long long* p, int k) {
+  if (threadIdx.x < k) p[threadIdx.x] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, int64_t ld, int n,
+                                                  const double* __restrict__ b,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ r,
+                                                  unsigned long long* norms) {
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= n) return;
+  const double* a = A + (int64_t)row * ld;
+  double acc0 = 0.0, acc1 = 0.0;
+  const int n2 = n & ~1;
+  int c = lane * 2;
+  for (; c + 128 < n2; c += 256) {
+    const double2 x0 = *reinterpret_cast<const double2*>(a + c);
+    const double2 x1 = *reinterpret_cast<const double2*>(a + c + 128);
+    acc0 = fma(x0.x, x[c], acc0);
+    acc1 = fma(x0.y, x[c + 1], acc1);
+    acc0 = fma(x1.x, x[c + 128], acc0);
+    acc1 = fma(x1.y, x[c + 129], acc1);
+  }
+  for (; c < n2; c += 128) {
+    const double2 x0 = *reinterpret_cast<const double2*>(a + c);
+    acc0 = fma(x0.x, x[c], acc0);
+    acc1 = fma(x0.y, x[c + 1], acc1);
+  }
+  for (int cc = n2 + lane; cc < n; cc += kWave) acc0 = fma(a[cc], x[cc], acc0);
+  const double s = wave_sum(acc0 + acc1);
+  if (lane == 0) {
+    const double ri = b[row] - s;
+    r[row] = ri;
+    atomic_max_nonneg(norms + 0, fabs(ri));
+    atomic_max_nonneg(norms + 1, fabs(x[row]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Triangular solves: one workgroup (4 waves) per block of 64 rows.  The
+// off-diagonal tiles of a block row are consumed as soon as the producing
+// block has published its solution (flag == epoch); the diagonal block is
+// solved by substitution in wave 0 with the running values held one per lane.
+// ---------------------------------------------------------------------------
+// 64 consecutive u_f values (16-byte aligned) widened to fp64
+template <class F>
+__device__ __forceinline__ void load_row64(const typename F::T* p, double (&out)[kTB]) {
+  using T = typename F::T;
+  if constexpr (sizeof(T) == 2) {
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+    for (int v = 0; v < kTB / 8; ++v) {
+      const uint4 w = q[v];
+      const uint32_t parts[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        T lo, hi;
+        const uint16_t a = (uint16_t)(parts[h] & 0xFFFFu), b = (uint16_t)(parts[h] >> 16);
+        __builtin_memcpy(&lo, &a, 2);
+        __builtin_memcpy(&hi, &b, 2);
+        out[8 * v + 2 * h] = (double)F::to_f(lo);
+        out[8 * v + 2 * h + 1] = (double)F::to_f(hi);
+      }
+    }
+  } else {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int v = 0; v < kTB / 4; ++v) {
+      const float4 w = q[v];
+      out[4 * v] = w.x;
+      out[4 * v + 1] = w.y;
+      out[4 * v + 2] = w.z;
+      out[4 * v + 3] = w.w;
+    }
+  }
+}
+
+template <class F>
+__global__ __launch_bounds__(256) void k_trsv_lower(const typename F::T* __restrict__ S, int64_t ld,
+                                                    const int* __restrict__ permS, int n,
+                                                    const double* __restrict__ in,
+                                                    const int* __restrict__ permIn,
+                                                    double* y, int* flags, int epoch,
+                                                    const CycleState* gate, int step, int* abortp) {
+  if (gated_off(gate, step)) return;
+  __shared__ double red[4][kTB];
+  __shared__ int wok[4];
+  const int blk = blockIdx.x;
+  const int r0 = blk * kTB;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int row = r0 + lane;
+  const bool valid = row < n;
+  const int prow = valid ? (permS ? permS[row] : row) : 0;
+  const typename F::T* srow = S + (int64_t)prow * ld;
+  double acc = 0.0;
+  bool ok = true;
+  for (int J = wave; J < blk && ok; J += 4) {
+    double lv[kTB];
+    if (valid) load_row64<F>(srow + (int64_t)J * kTB, lv);
+    else {
+#pragma unroll
+      for (int c = 0; c < kTB; ++c) lv[c] = 0.0;
+    }
+    if (lane == 0) ok = wait_eq(&flags[J], epoch, abortp);
+    ok = __shfl(ok ? 1 : 0, 0, kWave) != 0;
+    if (!ok) break;
+    const double yl = y[J * kTB + lane];
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) acc = fma(lv[c], readlane_d(yl, c), acc);
+  }
+  red[wave][lane] = acc;
+  if (lane == 0) wok[wave] = ok ? 1 : 0;
+  __syncthreads();
+  if (!(wok[0] & wok[1] & wok[2] & wok[3])) return;
+  if (wave != 0) return;
+  double z = 0.0;
+  if (valid) {
+    const int src = permIn ? permIn[row] : row;
+    z = in[src] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+  }
+  double lv[kTB];
+  if (valid) load_row64<F>(srow + r0, lv);
+  else {
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) lv[c] = 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < kTB; ++c) {
+    const double yc = readlane_d(z, c);
+    if (lane > c) z = fma(-lv[c], yc, z);
+  }
+  if (valid) y[row] = z;
+  __threadfence();
+  if (lane == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class F>
+__global__ __launch_bounds__(256) void k_trsv_upper(const typename F::T* __restrict__ S, int64_t ld,
+                                                    const int* __restrict__ permS, int n,
+                                                    const double* __restrict__ yin, double* z,
+                                                    double scale, double* __restrict__ out64,
+                                                    float* __restrict__ out32, int* flags,
+                                                    int epoch, const CycleState* gate, int step,
+                                                    int* abortp) {
+  if (gated_off(gate, step)) return;
+  __shared__ double red[4][kTB];
+  __shared__ int wok[4];
+  const int nblk = (n + kTB - 1) / kTB;
+  const int blk = nblk - 1 - blockIdx.x;  // last block first
+  const int r0 = blk * kTB;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int row = r0 + lane;
+  const bool valid = row < n;
+  const int prow = valid ? (permS ? permS[row] : row) : 0;
+  const typename F::T* srow = S + (int64_t)prow * ld;
+  double acc = 0.0;
+  bool ok = true;
+  for (int J = nblk - 1 - wave; J > blk && ok; J -= 4) {
+    double lv[kTB];
+    const int cbase = J * kTB;
+    if (valid && cbase + kTB <= n) {
+      load_row64<F>(srow + cbase, lv);
+    } else {
+#pragma unroll
+      for (int c = 0; c < kTB; ++c)
+        lv[c] = (valid && cbase + c < n) ? (double)F::to_f(srow[cbase + c]) : 0.0;
+    }
+    if (lane == 0) ok = wait_eq(&flags[J], epoch, abortp);
+    ok = __shfl(ok ? 1 : 0, 0, kWave) != 0;
+    if (!ok) break;
+    const double yl = (cbase + lane < n) ? z[cbase + lane] : 0.0;
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) acc = fma(lv[c], readlane_d(yl, c), acc);
+  }
+  red[wave][lane] = acc;
+  if (lane == 0) wok[wave] = ok ? 1 : 0;
+  __syncthreads();
+  if (!(wok[0] & wok[1] & wok[2] & wok[3])) return;
+  if (wave != 0) return;
+  double v = 0.0;
+  if (valid) v = yin[row] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+  double lv[kTB];
+#pragma unroll
+  for (int c = 0; c < kTB; ++c)
+    lv[c] = (valid && r0 + c < n) ? (double)F::to_f(srow[r0 + c]) : 1.0;
+  const double diag = valid ? (double)F::to_f(srow[row]) : 1.0;
+#pragma unroll
+  for (int c = kTB - 1; c >= 0; --c) {
+    if (lane == c) v = v / diag;
+    const double yc = readlane_d(v, c);
+    if (lane < c) v = fma(-lv[c], yc, v);
+  }
+  if (valid) {
+    z[row] = v;
+    const double o = v * scale;
+    if (out64) out64[row] = o;
+    if (out32) out32[row] = (float)o;
+  }
+  __threadfence();
+  if (lane == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// orthogonalisation passes (CGS2) with last-block reduction
+// ---------------------------------------------------------------------------
+constexpr int kRowsPerBlock = 256;
+
+__device__ __forceinline__ double basis_at(const Basis& X, int c, int row) {
+  return (c < X.kc) ? X.c64[(int64_t)c * X.ldc + row]
+                    : (double)X.v32[(int64_t)(c - X.kc) * X.ldv + row];
+}
+
+__global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
+  if (gated_off(a.gate, a.step)) return;
+  __shared__ double wsh[kRowsPerBlock];
+  __shared__ double red[4][kWave + 1];
+  __shared__ double coef_sh[256];
+  __shared__ unsigned int s_ticket;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int ncol = a.X.kc + a.X.nv;
+  const int rbase = blockIdx.x * kRowsPerBlock;
+  const int row = rbase + tid;
+  const bool valid = row < a.n;
+  if (mode & kOrthoUpdate) {
+    for (int c = tid; c < ncol; c += 256) coef_sh[c] = a.coef[c];
+    __syncthreads();
+  }
+  double wv = valid ? (double)a.w_in[row] : 0.0;
+  if ((mode & kOrthoUpdate) && valid) {
+    double s = 0.0;
+    for (int c = 0; c < ncol; ++c) s = fma(basis_at(a.X, c, row), coef_sh[c], s);
+    wv = (double)(float)(wv - s);
+    a.w_out[row] = (float)wv;
+  }
+  wsh[tid] = wv;
+  __syncthreads();
+  const int nout = ncol + 1;  // dots then the squared norm
+  double* part = a.partial + (int64_t)blockIdx.x * nout;
+  if (mode & kOrthoDots) {
+    for (int cg = 0; cg < ncol; cg += kWave) {
+      const int c = cg + lane;
+      double acc = 0.0;
+      if (c < ncol) {
+        const int r0 = wave * kWave;
+#pragma unroll 8
+        for (int r = 0; r < kWave; ++r) {
+          const int rr = rbase + r0 + r;
+          if (rr < a.n) acc = fma(basis_at(a.X, c, rr), wsh[r0 + r], acc);
+        }
+      }
+      red[wave][lane] = acc;
+      __syncthreads();
+      if (wave == 0 && c < ncol) part[c] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+      __syncthreads();
+    }
+  }
+  if (mode & kOrthoNorm) {
+    double sq = wave_sum(wv * wv);
+    if (lane == 0) red[wave][0] = sq;
+    __syncthreads();
+    if (tid == 0) part[ncol] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+  }
+  // last block reduces the partial results
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_ticket = atomicAdd(a.counter, 1u);
+  __syncthreads();
+  if (s_ticket != gridDim.x - 1) return;
+  __threadfence();
+  if (mode & kOrthoDots) {
+    for (int c = tid; c < ncol; c += 256) {
+      double s = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += a.partial[(int64_t)b * nout + c];
+      a.dots_out[c] = s;
+    }
+  }
+  if ((mode & kOrthoNorm) && tid == 0) {
+    double s = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) s += a.partial[(int64_t)b * nout + ncol];
+    a.norm_out[0] = s;
+  }
+  if (tid == 0) *a.counter = 0u;
+  if (!(mode & kOrthoFinish)) return;
+  __syncthreads();
+  if (tid != 0) return;
+  // Arnoldi step j: h = h1 + h2, beta = ||w||, Givens update of column j
+  const int j = a.step;
+  const int kc = a.X.kc;
+  double col[129];
+  for (int i = 0; i < kc; ++i) a.B[(int64_t)j * a.ldb + i] = a.h_prev[i] + a.coef[i];
+  for (int i = 0; i <= j; ++i) {
+    col[i] = a.h_prev[kc + i] + a.coef[kc + i];
+    a.H[(int64_t)j * a.ldh + i] = col[i];
+  }
+  const double beta = sqrt(a.norm_out[0]);
+  a.H[(int64_t)j * a.ldh + j + 1] = beta;
+  col[j + 1] = beta;
+  for (int i = 0; i < j; ++i) {
+    const double t = a.cs[i] * col[i] + a.sn[i] * col[i + 1];
+    col[i + 1] = -a.sn[i] * col[i] + a.cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double aa = col[j], bb = col[j + 1];
+  const double rr = hypot(aa, bb);
+  double c = 1.0, s = 0.0;
+  if (rr != 0.0) {
+    c = aa / rr;
+    s = bb / rr;
+  }
+  a.cs[j] = c;
+  a.sn[j] = s;
+  const double gj = a.g[j];
+  a.g[j + 1] = -s * gj;
+  a.g[j] = c * gj;
+  const double est = fabs(a.g[j + 1]);
+  a.st->est = est;
+  a.st->jdone = j + 1;
+  if (est <= a.st->tol || beta == 0.0) a.st->done = 1;
+}
+
+__global__ void k_normalize(const float* __restrict__ w, float* __restrict__ vout,
+                            const double* __restrict__ H, int ldh, int step, int n,
+                            const CycleState* gate) {
+  if (gated_off(gate, step)) return;
+  const double beta = H[(int64_t)step * ldh + step + 1];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  vout[i] = (beta > 0.0) ? (float)((double)w[i] / beta) : 0.0f;
+}
+
+// out[:, o] = sum_c X[:, c] M[c, o]
+__global__ __launch_bounds__(256) void k_combine(Basis X, int n, const double* __restrict__ M,
+                                                 int nout, double* __restrict__ out, int64_t ldo) {
+  __shared__ double Msh[4096];
+  const int ncol = X.kc + X.nv;
+  for (int i = threadIdx.x; i < ncol * nout; i += blockDim.x) Msh[i] = M[i];
+  __syncthreads();
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double xv[96];
+  const int nc = min(ncol, 96);
+  for (int c = 0; c < nc; ++c) xv[c] = basis_at(X, c, row);
+  for (int o = 0; o < nout; ++o) {
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s = fma(xv[c], Msh[(int64_t)o * ncol + c], s);
+    out[(int64_t)o * ldo + row] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cycle_update(Basis Xd, const double* __restrict__ cd,
+                                                      float* __restrict__ d, Basis Xr,
+                                                      const double* __restrict__ cr,
+                                                      float* __restrict__ r, int n) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  if (d) {
+    const int nc = Xd.kc + Xd.nv;
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s = fma(basis_at(Xd, c, row), cd[c], s);
+    d[row] = (float)((double)d[row] + s);
+  }
+  if (r) {
+    const int nc = Xr.kc + Xr.nv;
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s = fma(basis_at(Xr, c, row), cr[c], s);
+    r[row] = (float)((double)r[row] - s);
+  }
+}
+
+// G[o * nx + c] = sum_rows X[row, c] Y[row, o]
+__global__ __launch_bounds__(256) void k_gram(Basis X, const double* __restrict__ Y, int ny,
+                                              int64_t ldy, int n, double* __restrict__ G,
+                                              double* __restrict__ partial,
+                                              unsigned int* counter) {
+  __shared__ double ysh[kRowsPerBlock];
+  __shared__ double red[4][kWave + 1];
+  __shared__ unsigned int s_ticket;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int nx = X.kc + X.nv;
+  const int rbase = blockIdx.x * kRowsPerBlock;
+  const int nout = nx * ny;
+  double* part = partial + (int64_t)blockIdx.x * nout;
+  for (int o = 0; o < ny; ++o) {
+    const int row = rbase + tid;
+    ysh[tid] = (row < n) ? Y[(int64_t)o * ldy + row] : 0.0;
+    __syncthreads();
+    for (int cg = 0; cg < nx; cg += kWave) {
+      const int c = cg + lane;
+      double acc = 0.0;
+      if (c < nx) {
+        const int r0 = wave * kWave;
+        for (int r = 0; r < kWave; ++r) {
+          const int rr = rbase + r0 + r;
+          if (rr < n) acc = fma(basis_at(X, c, rr), ysh[r0 + r], acc);
+        }
+      }
+      red[wave][lane] = acc;
+      __syncthreads();
+      if (wave == 0 && c < nx)
+        part[o * nx + c] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+      __syncthreads();
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_ticket = atomicAdd(counter, 1u);
+  __syncthreads();
+  if (s_ticket != gridDim.x - 1) return;
+  __threadfence();
+  for (int c = tid; c < nout; c += 256) {
+    double s = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(int64_t)b * nout + c];
+    G[c] = s;
+  }
+  if (tid == 0) *counter = 0u;
+}
+
+__global__ void k_scale_round(const double* __restrict__ r, double s, double* __restrict__ out,
+                              int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)(float)(r[i] / s);
+}
+
+__global__ void k_x_update(double* __restrict__ x, const float* __restrict__ d, double s, int n) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double t = s * (double)d[i];
+    x[i] = x[i] + t;
+  }
+}
+
+__global__ void k_div_f32(const float* __restrict__ w, double s, float* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)((double)w[i] / s);
+}
+
+__global__ void k_maxabs(const double* __restrict__ v, int n, unsigned long long* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double a = (i < n) ? fabs(v[i]) : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a = fmax(a, __shfl_xor(a, o, kWave));
+  if ((threadIdx.x % kWave) == 0) atomic_max_nonneg(out, a);
+}
+
+__global__ void k_copy_f32_f64(const float* __restrict__ a, double* __restrict__ b, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const float* v32,
+                    const double* v64, double* t, const CycleState* gate, int step,
+                    hipStream_t s) {
+  const unsigned grid = nblocks(n, 4);
+  if (v32)
+    hipLaunchKernelGGL(k_gemv_au<float>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, v32, t,
+                       gate, step);
+  else
+    hipLaunchKernelGGL(k_gemv_au<double>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, v64, t,
+                       gate, step);
+}
+
+void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
+                     double* r, unsigned long long* norms, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, norms, 2);
+  hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 4)), dim3(256), 0, s, A, ld, n, b, x, r, norms);
+}
+
+void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
+                       const double* in, const int* permIn, double* y, int* flags, int epoch,
+                       const CycleState* gate, int step, int* abortp, hipStream_t s) {
+  const unsigned grid = nblocks(n, kTB);
+  if (store == kStoreF16)
+    hipLaunchKernelGGL(k_trsv_lower<Fp16>, dim3(grid), dim3(256), 0, s,
+                       reinterpret_cast<const _Float16*>(S), ld, permS, n, in, permIn, y, flags,
+                       epoch, gate, step, abortp);
+  else if (store == kStoreBF16)
+    hipLaunchKernelGGL(k_trsv_lower<Bf16>, dim3(grid), dim3(256), 0, s,
+                       reinterpret_cast<const uint16_t*>(S), ld, permS, n, in, permIn, y, flags,
+                       epoch, gate, step, abortp);
+  else
+    hipLaunchKernelGGL(k_trsv_lower<Fp32>, dim3(grid), dim3(256), 0, s,
+                       reinterpret_cast<const float*>(S), ld, permS, n, in, permIn, y, flags,
+                       epoch, gate, step, abortp);
+}
+
+void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
+                       const double* y, double* z, double scale, double* out64, float* out32,
+                       int* flags, int epoch, const CycleState* gate, int step, int* abortp,
+                       hipStream_t s) {
+  const unsigned grid = nblocks(n, kTB);
+  if (store == kStoreF16)
+    hipLaunchKernelGGL(k_trsv_upper<Fp16>, dim3(grid), dim3(256), 0, s,
+                       reinterpret_cast<const _Float16*>(S), ld, permS, n, y, z, scale, out64,
+                       out32, flags, epoch, gate, step, abortp);
+  else if (store == kStoreBF16)
+    hipLaunchKernelGGL(k_trsv_upper<Bf16>, dim3(grid), dim3(256), 0, s,
+                       reinterpret_cast<const uint16_t*>(S), ld, permS, n, y, z, scale, out64,
+                       out32, flags, epoch, gate, step, abortp);
+  else
+    hipLaunchKernelGGL(k_trsv_upper<Fp32>, dim3(grid), dim3(256), 0, s,
+                       reinterpret_cast<const float*>(S), ld, permS, n, y, z, scale, out64, out32,
+                       flags, epoch, gate, step, abortp);
+}
+
+void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_ortho, dim3(nblocks(a.n, kRowsPerBlock)), dim3(256), 0, s, a, mode);
+}
+
+void launch_normalize(const float* w, float* vout, const double* H, int ldh, int step, int n,
+                      const CycleState* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_normalize, dim3(nblocks(n, 256)), dim3(256), 0, s, w, vout, H, ldh, step,
+                     n, gate);
+}
+
+void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(nblocks(n, 256)), dim3(256), 0, s, X, n, M, nout, out, ldo);
+}
+
+void launch_cycle_update(const Basis& Xd, const double* cd, float* d, const Basis& Xr,
+                         const double* cr, float* r, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_update, dim3(nblocks(n, 256)), dim3(256), 0, s, Xd, cd, d, Xr, cr, r,
+                     n);
+}
+
+void launch_gram(const Basis& X, const double* Y, int ny, int64_t ldy, int n, double* G,
+                 double* partial, unsigned int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram, dim3(nblocks(n, kRowsPerBlock)), dim3(256), 0, s, X, Y, ny, ldy, n,
+                     G, partial, counter);
+}
+
+void launch_scale_round(const double* r, double sc, double* out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_round, dim3(nblocks(n, 256)), dim3(256), 0, s, r, sc, out, n);
+}
+
+void launch_x_update(double* x, const float* d, double sc, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_x_update, dim3(nblocks(n, 256)), dim3(256), 0, s, x, d, sc, n);
+}
+
+void launch_div_f32(const float* w, double sc, float* out, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_div_f32, dim3(nblocks(n, 256)), dim3(256), 0, s, w, sc, out, n);
+}
+
+void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out, 1);
+  hipLaunchKernelGGL(k_maxabs, dim3(nblocks(n, 256)), dim3(256), 0, s, v, n, out);
+}
+
+void launch_copy_f32_to_f64(const float* a, double* b, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_f32_f64, dim3(nblocks(n, 256)), dim3(256), 0, s, a, b, n);
+}
+
+}  // namespace gir

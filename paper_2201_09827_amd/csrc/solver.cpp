@@ -1,0 +1,1027 @@
+// Host driver of RGMRES-IR on one MI355X: Algorithm 3 of Oktay & Carson
+// (refinement loop) with the GCRO-DR correction solver of Section 2, and the
+// extern "C" boundary declared in include/gmresir.h.
+//
+// Control lives on the host; every vector operation runs in the HIP kernels
+// of kernels_lu.hip / kernels_solve.hip.  Inside an Arnoldi cycle the host
+// only enqueues work: convergence of the Givens estimate is detected on the
+// device, later steps of the cycle turn into no-ops, and the host polls the
+// device state one step behind the work it has queued.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gmresir.h"
+#include "host_la.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& s) { g_last_error = s; }
+
+#define GIR_HIP(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_) + " (" __FILE__ ":" + \
+                std::to_string(__LINE__) + ")");                                      \
+      return GMRESIR_EHIP;                                                            \
+    }                                                                                 \
+  } while (0)
+
+#define GIR_TRY(expr)          \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != 0) return rc_;  \
+  } while (0)
+
+constexpr int kNb = 64;           // LU block size (sets the u_f rounding points)
+constexpr int kMaxM = 95;         // limit from the skinny-product kernels
+constexpr int kLaunchAhead = 1;   // Arnoldi steps queued before polling
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+int store_of(int uf) {
+  switch (uf) {
+    case GMRESIR_FP16: return gir::kStoreF16;
+    case GMRESIR_BF16: return gir::kStoreBF16;
+    default: return gir::kStoreF32;
+  }
+}
+
+size_t store_bytes(int store) { return store == gir::kStoreF32 ? 4 : 2; }
+
+int prec_rank(int p) {
+  switch (p) {
+    case GMRESIR_BF16:
+    case GMRESIR_FP16: return 0;
+    case GMRESIR_FP32: return 1;
+    case GMRESIR_FP64: return 2;
+    case GMRESIR_DD: return 3;
+    default: return -1;
+  }
+}
+
+// Largest integer e with 2^e * amax * sqrt(n) <= 2^-4 * 65504 (fp16 range
+// headroom for the element growth of partial pivoting).
+int scale_exponent(double amax, int64_t n) {
+  if (!(amax > 0.0) || !std::isfinite(amax)) return 0;
+  const double t = amax * std::sqrt((double)std::max<int64_t>(n, 1));
+  const double limit = 4094.0;
+  int e = (int)std::floor(std::log2(limit) - std::log2(t));
+  while (std::ldexp(t, e) > limit) --e;
+  while (std::ldexp(t, e + 1) <= limit) ++e;
+  return e;
+}
+
+template <class T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count);
+  if (e != hipSuccess) {
+    set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+    return GMRESIR_ENOMEM;
+  }
+  return 0;
+}
+
+}  // namespace
+
+struct gmresir_ctx {
+  int64_t n = 0, ld = 0;
+  gmresir_opts o{};
+  int store = 0;
+  hipStream_t stream = nullptr;
+  int status = 0;
+  int singular_col = 0;
+  int e = 0;
+  double scale = 1.0;
+  double norm_a = 0.0;
+  double t_factor = 0.0;
+  int m = 0, k = 0;
+
+  // matrices
+  double* A64 = nullptr;
+  float* Au = nullptr;
+  void* S = nullptr;
+  int* perm = nullptr;    // logical -> physical row of S
+  int* permP = nullptr;   // logical -> row of A (P)
+  int* permS = nullptr;   // equals perm after gmresir_factor, null after import
+  int* ipiv = nullptr;
+  // LU scratch
+  float* P = nullptr;
+  int *ptmp = nullptr, *pstep = nullptr, *piv_prow = nullptr, *lidx = nullptr, *sync = nullptr;
+  // solve buffers (length ld, zero padded)
+  double *x = nullptr, *b = nullptr, *r64 = nullptr, *t64 = nullptr, *y64 = nullptr,
+         *z64 = nullptr;
+  float *z32 = nullptr, *w32 = nullptr, *d32 = nullptr, *r32 = nullptr;
+  float* V = nullptr;
+  double *C = nullptr, *U = nullptr, *Cn = nullptr, *Un = nullptr;
+  int kc_keep = 0;  // columns of U carried to the next correction solve
+  double *Hd = nullptr, *Bd = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *coefA = nullptr, *coefB = nullptr,
+         *Mdev = nullptr, *Gdev = nullptr, *partial = nullptr;
+  unsigned int* counter = nullptr;
+  unsigned long long* norms = nullptr;
+  gir::CycleState* st = nullptr;
+  int *flagsL = nullptr, *flagsU = nullptr;
+  int epoch = 0;
+  // pinned host staging
+  gir::CycleState* st_host = nullptr;  // one slot per queued step
+  double* hbuf = nullptr;              // general small transfers
+  size_t hbuf_len = 0;
+  std::vector<hipEvent_t> ev;
+
+  ~gmresir_ctx() {
+    // permP and permS alias perm
+    void* bufs[] = {A64, Au, S, perm, ipiv, P, ptmp, pstep, piv_prow, lidx, sync,
+                    x, b, r64, t64, y64, z64, z32, w32, d32, r32, V, C, U, Cn, Un, Hd, Bd, cs,
+                    sn, g, h1, h2, nrm, coefA, coefB, Mdev, Gdev, partial, counter, norms, st,
+                    flagsL, flagsU};
+    for (void* p : bufs)
+      if (p) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+    if (hbuf) (void)hipHostFree(hbuf);
+    for (auto& e2 : ev) (void)hipEventDestroy(e2);
+  }
+};
+
+namespace {
+
+int validate_opts(const gmresir_opts* o) {
+  if (!o) {
+    set_error("opts is NULL");
+    return GMRESIR_EINVAL;
+  }
+  if (o->struct_size != sizeof(gmresir_opts)) {
+    set_error("opts.struct_size mismatch");
+    return GMRESIR_EINVAL;
+  }
+  const int rf = prec_rank(o->uf), ru = prec_rank(o->u), rr = prec_rank(o->ur);
+  if (rf != 0 && o->uf != GMRESIR_FP32) {
+    set_error("uf must be FP16, BF16 or FP32");
+    return GMRESIR_EINVAL;
+  }
+  if (o->u != GMRESIR_FP32) {
+    set_error("this build supports u = FP32 (u^2 = fp64)");
+    return GMRESIR_EINVAL;
+  }
+  if (o->ur != GMRESIR_FP64) {
+    set_error("this build supports ur = FP64");
+    return GMRESIR_EINVAL;
+  }
+  if (!(rf <= ru && ru <= rr)) {
+    set_error("precisions must satisfy uf >= u >= ur");
+    return GMRESIR_EINVAL;
+  }
+  if (o->m < 1 || o->m > kMaxM || o->k < 0 || o->k >= o->m ||
+      (o->m + 1) * std::max(o->k, 1) > 4096) {
+    set_error("need 0 <= k < m <= 95 and (m + 1) k <= 4096");
+    return GMRESIR_EINVAL;
+  }
+  if (!(o->tau > 0.0) || o->imax < 0 || o->imax > GMRESIR_MAX_STEPS || o->maxit < 0) {
+    set_error("invalid tau, imax or maxit");
+    return GMRESIR_EINVAL;
+  }
+  for (int i = 0; i < 4; ++i)
+    if (o->reserved[i] != 0) {
+      set_error("reserved fields must be zero");
+      return GMRESIR_EINVAL;
+    }
+  return 0;
+}
+
+int alloc_solve(gmresir_ctx* h) {
+  const size_t ld = (size_t)h->ld;
+  const int m = h->m, k = std::max(h->k, 1);
+  GIR_TRY(dalloc(&h->x, ld));
+  GIR_TRY(dalloc(&h->b, ld));
+  GIR_TRY(dalloc(&h->r64, ld));
+  GIR_TRY(dalloc(&h->t64, ld));
+  GIR_TRY(dalloc(&h->y64, ld));
+  GIR_TRY(dalloc(&h->z64, ld));
+  GIR_TRY(dalloc(&h->z32, ld));
+  GIR_TRY(dalloc(&h->w32, ld));
+  GIR_TRY(dalloc(&h->d32, ld));
+  GIR_TRY(dalloc(&h->r32, ld));
+  GIR_TRY(dalloc(&h->V, ld * (m + 1)));
+  GIR_TRY(dalloc(&h->C, ld * k));
+  GIR_TRY(dalloc(&h->U, ld * k));
+  GIR_TRY(dalloc(&h->Cn, ld * k));
+  GIR_TRY(dalloc(&h->Un, ld * k));
+  GIR_TRY(dalloc(&h->Hd, (size_t)(m + 1) * m));
+  GIR_TRY(dalloc(&h->Bd, (size_t)k * m));
+  GIR_TRY(dalloc(&h->cs, m + 1));
+  GIR_TRY(dalloc(&h->sn, m + 1));
+  GIR_TRY(dalloc(&h->g, m + 2));
+  GIR_TRY(dalloc(&h->h1, 256));
+  GIR_TRY(dalloc(&h->h2, 256));
+  GIR_TRY(dalloc(&h->nrm, 4));
+  GIR_TRY(dalloc(&h->coefA, 256));
+  GIR_TRY(dalloc(&h->coefB, 256));
+  GIR_TRY(dalloc(&h->Mdev, 4096));
+  GIR_TRY(dalloc(&h->Gdev, 4096));
+  const size_t grid = (ld + 255) / 256;
+  GIR_TRY(dalloc(&h->partial, grid * 4096));
+  const int nblk = (int)((h->n + 63) / 64);
+  GIR_TRY(dalloc(&h->flagsL, nblk));
+  GIR_TRY(dalloc(&h->flagsU, nblk));
+  GIR_HIP(hipMemsetAsync(h->flagsL, 0, sizeof(int) * nblk, h->stream));
+  GIR_HIP(hipMemsetAsync(h->flagsU, 0, sizeof(int) * nblk, h->stream));
+  // zero padding of every vector
+  double* dv[] = {h->x, h->b, h->r64, h->t64, h->y64, h->z64};
+  for (double* p : dv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(double) * ld, h->stream));
+  float* fv[] = {h->z32, h->w32, h->d32, h->r32};
+  for (float* p : fv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(float) * ld, h->stream));
+  GIR_HIP(hipMemsetAsync(h->V, 0, sizeof(float) * ld * (m + 1), h->stream));
+  GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->st_host),
+                        sizeof(gir::CycleState) * (size_t)(m + 2), hipHostMallocDefault));
+  h->hbuf_len = 8192;
+  GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hbuf), sizeof(double) * h->hbuf_len,
+                        hipHostMallocDefault));
+  h->ev.resize(m + 2);
+  for (auto& e2 : h->ev) GIR_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+  return 0;
+}
+
+int alloc_common(gmresir_ctx* h) {
+  const size_t ld = (size_t)h->ld, n = (size_t)h->n;
+  GIR_TRY(dalloc(&h->A64, n * ld));
+  GIR_TRY(dalloc(&h->Au, n * ld));
+  GIR_TRY(dalloc(reinterpret_cast<char**>(&h->S), n * ld * store_bytes(h->store)));
+  GIR_TRY(dalloc(&h->perm, n));
+  GIR_TRY(dalloc(&h->ipiv, n));
+  GIR_TRY(dalloc(&h->st, 1));
+  GIR_TRY(dalloc(&h->counter, 4));
+  GIR_TRY(dalloc(&h->norms, 4));
+  GIR_HIP(hipMemsetAsync(h->st, 0, sizeof(gir::CycleState), h->stream));
+  GIR_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned) * 4, h->stream));
+  return 0;
+}
+
+int upload(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
+  GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+  GIR_HIP(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+int download(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
+  GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+  GIR_HIP(hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+// copy A into the padded fp64 buffer, scan it, and form A_u
+int ingest(gmresir_ctx* h, const double* A, int64_t lda, bool make_lu_copy) {
+  const int64_t n = h->n, ld = h->ld;
+  GIR_HIP(hipMemsetAsync(h->A64, 0, sizeof(double) * n * ld, h->stream));
+  GIR_HIP(hipMemcpy2DAsync(h->A64, ld * sizeof(double), A, lda * sizeof(double),
+                           n * sizeof(double), n, hipMemcpyDeviceToDevice, h->stream));
+  unsigned long long* scanout = h->norms;  // [0] max|a|, [1] max row sum
+  int* flag = reinterpret_cast<int*>(h->counter + 2);
+  GIR_HIP(hipMemsetAsync(scanout, 0, sizeof(unsigned long long) * 2, h->stream));
+  GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+  gir::launch_scan(h->A64, n, ld, scanout, flag, h->stream);
+  GIR_HIP(hipGetLastError());
+  unsigned long long hv[2];
+  int hflag = 0;
+  GIR_TRY(download(h, hv, scanout, sizeof(hv)));
+  GIR_TRY(download(h, &hflag, flag, sizeof(int)));
+  double amax, rowsum;
+  std::memcpy(&amax, &hv[0], 8);
+  std::memcpy(&rowsum, &hv[1], 8);
+  h->norm_a = rowsum;
+  if (hflag) {
+    h->status = GMRESIR_ERANGE;
+    return 0;
+  }
+  const bool scaled = (h->o.scale_pow2 < 0) ? (h->o.uf == GMRESIR_FP16) : (h->o.scale_pow2 != 0);
+  h->e = scaled ? scale_exponent(amax, n) : 0;
+  h->scale = std::ldexp(1.0, h->e);
+  if (make_lu_copy) {
+    GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+    gir::launch_convert(h->A64, n, ld, h->e, h->store, h->S, h->Au, ld, flag, h->stream);
+    GIR_HIP(hipGetLastError());
+    GIR_TRY(download(h, &hflag, flag, sizeof(int)));
+    if (hflag) h->status = GMRESIR_ERANGE;
+  }
+  return 0;
+}
+
+int run_lu(gmresir_ctx* h) {
+  const int n = (int)h->n;
+  gir::launch_iota(h->perm, n, h->stream);
+  GIR_TRY(dalloc(&h->P, (size_t)n * kNb));
+  GIR_TRY(dalloc(&h->ptmp, n));
+  GIR_TRY(dalloc(&h->pstep, n));
+  GIR_TRY(dalloc(&h->piv_prow, kNb));
+  GIR_TRY(dalloc(&h->lidx, n));
+  GIR_TRY(dalloc(&h->sync, 4));
+  gir::PanelArgs a{};
+  a.S = h->S;
+  a.ld = h->ld;
+  a.n = n;
+  a.perm = h->perm;
+  a.ptmp = h->ptmp;
+  a.P = h->P;
+  a.ldp = n;
+  a.pstep = h->pstep;
+  a.piv_prow = h->piv_prow;
+  a.lidx = h->lidx;
+  a.ipiv = h->ipiv;
+  a.sync = h->sync;
+  a.st = h->st;
+  for (int k0 = 0; k0 < n; k0 += kNb) {
+    a.k0 = k0;
+    a.kb = std::min(kNb, n - k0);
+    const int hrows = n - k0;
+    const int nhelpers = std::min(127, std::max(1, (hrows + 63) / 64));
+    gir::launch_panel_step(a, h->store, nhelpers, h->stream);
+    gir::launch_trsm_update(a, h->store, h->stream);
+  }
+  GIR_HIP(hipGetLastError());
+  int* flag = reinterpret_cast<int*>(h->counter + 2);
+  GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+  gir::launch_check_factors(h->S, n, h->ld, h->store, flag, h->stream);
+  gir::CycleState hs{};
+  int hflag = 0;
+  GIR_TRY(download(h, &hs, h->st, sizeof(hs)));
+  GIR_TRY(download(h, &hflag, flag, sizeof(int)));
+  if (hs.abort) {
+    set_error("LU: a device-side wait exceeded its bound");
+    return GMRESIR_EINTERNAL;
+  }
+  if (hs.singular) {
+    h->status = GMRESIR_ESINGULAR;
+    h->singular_col = hs.singular;
+  } else if (hflag) {
+    h->status = GMRESIR_ERANGE;
+  }
+  // the LU scratch is not needed by the solve phase
+  (void)hipFree(h->P);
+  (void)hipFree(h->ptmp);
+  (void)hipFree(h->pstep);
+  (void)hipFree(h->piv_prow);
+  (void)hipFree(h->lidx);
+  (void)hipFree(h->sync);
+  h->P = nullptr;
+  h->ptmp = h->pstep = h->piv_prow = h->lidx = h->sync = nullptr;
+  return 0;
+}
+
+int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, void* stream,
+             gmresir_ctx** out, gmresir_ctx** hp) {
+  if (!out) {
+    set_error("out is NULL");
+    return GMRESIR_EINVAL;
+  }
+  *out = nullptr;
+  GIR_TRY(validate_opts(opts));
+  if (!A || n <= 0 || lda < n || n > (1 << 30)) {
+    set_error("invalid A, n or lda");
+    return GMRESIR_EINVAL;
+  }
+  gmresir_ctx* h = new (std::nothrow) gmresir_ctx();
+  if (!h) return GMRESIR_ENOMEM;
+  h->n = n;
+  h->ld = (n + 63) / 64 * 64;
+  h->o = *opts;
+  h->m = opts->m;
+  h->k = opts->k;
+  h->store = store_of(opts->uf);
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  *hp = h;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// solve phase
+// ---------------------------------------------------------------------------
+
+int next_epoch(gmresir_ctx* h) {
+  if (++h->epoch >= 0x3fffffff) h->epoch = 1;
+  return h->epoch;
+}
+
+// y (fp64 or fp32 rounded) = M^-1 in (2^e U^-1 L^-1 P in), P applied by gather
+int precond(gmresir_ctx* h, const double* in, const int* permIn, double* out64, float* out32,
+            const gir::CycleState* gate, int step) {
+  const int n = (int)h->n;
+  gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->y64, h->flagsL,
+                         next_epoch(h), gate, step, &h->st->abort, h->stream);
+  gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->z64, h->scale, out64,
+                         out32, h->flagsU, next_epoch(h), gate, step, &h->st->abort, h->stream);
+  return 0;
+}
+
+// A-tilde v (v float or double)
+int atilde(gmresir_ctx* h, const float* v32, const double* v64, double* out64, float* out32,
+           const gir::CycleState* gate, int step) {
+  gir::launch_gemv_au(h->Au, h->ld, h->permP, (int)h->n, v32, v64, h->t64, gate, step,
+                      h->stream);
+  return precond(h, h->t64, nullptr, out64, out32, gate, step);
+}
+
+gir::Basis basis(const double* c, int kc, int64_t ldc, const float* v, int nv, int64_t ldv) {
+  gir::Basis X;
+  X.c64 = c;
+  X.kc = kc;
+  X.ldc = ldc;
+  X.v32 = v;
+  X.nv = nv;
+  X.ldv = ldv;
+  return X;
+}
+
+// dots (X^T w) and/or squared norm of a fp32 vector, synchronous result
+int dots_norm(gmresir_ctx* h, const gir::Basis& X, const float* w, double* dots, double* nrm2) {
+  gir::OrthoArgs a{};
+  a.X = X;
+  a.n = (int)h->n;
+  a.w_in = w;
+  a.w_out = nullptr;
+  a.dots_out = h->h1;
+  a.norm_out = h->nrm;
+  a.partial = h->partial;
+  a.counter = h->counter;
+  int mode = gir::kOrthoNorm;
+  if (X.kc + X.nv > 0 && dots) mode |= gir::kOrthoDots;
+  gir::launch_ortho(a, mode, h->stream);
+  GIR_HIP(hipGetLastError());
+  const int nc = X.kc + X.nv;
+  if (nc > 0 && dots) GIR_TRY(download(h, dots, h->h1, sizeof(double) * nc));
+  GIR_TRY(download(h, nrm2, h->nrm, sizeof(double)));
+  return 0;
+}
+
+int gram(gmresir_ctx* h, const gir::Basis& X, const double* Y, int ny, std::vector<double>& G) {
+  const int nx = X.kc + X.nv;
+  G.assign((size_t)nx * ny, 0.0);
+  if (nx == 0 || ny == 0) return 0;
+  gir::launch_gram(X, Y, ny, h->ld, (int)h->n, h->Gdev, h->partial, h->counter, h->stream);
+  GIR_HIP(hipGetLastError());
+  GIR_TRY(download(h, G.data(), h->Gdev, sizeof(double) * nx * ny));
+  return 0;
+}
+
+int combine(gmresir_ctx* h, const gir::Basis& X, const std::vector<double>& M, int nout,
+            double* out) {
+  const int nc = X.kc + X.nv;
+  if (nout == 0) return 0;
+  GIR_TRY(upload(h, h->Mdev, M.data(), sizeof(double) * (size_t)nc * nout));
+  gir::launch_combine(X, (int)h->n, h->Mdev, nout, out, h->ld, h->stream);
+  GIR_HIP(hipGetLastError());
+  return 0;
+}
+
+struct SolveStats {
+  int its = 0;
+};
+
+// GCRO-DR(m, k) for A-tilde d = z (z in h->z32); result in h->d32.
+int gcrodr(gmresir_ctx* h, SolveStats& stats) {
+  const int n = (int)h->n;
+  const int64_t ld = h->ld;
+  const int m = h->m, k = h->k;
+  const int cap = h->o.maxit > 0 ? h->o.maxit : 10 * m;
+  hipStream_t s = h->stream;
+  double beta0 = 0.0;
+  {
+    double n2 = 0.0;
+    GIR_TRY(dots_norm(h, basis(nullptr, 0, ld, nullptr, 0, ld), h->z32, nullptr, &n2));
+    beta0 = std::sqrt(n2);
+  }
+  GIR_HIP(hipMemcpyAsync(h->r32, h->z32, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+  GIR_HIP(hipMemsetAsync(h->d32, 0, sizeof(float) * n, s));
+  stats.its = 0;
+  if (beta0 == 0.0) return 0;
+  const double tol = h->o.tau * beta0;
+  int kc = 0;
+
+  // recycled space from the previous system: C = QR(A-tilde Y), U = Y R^-1
+  if (k > 0 && h->kc_keep > 0) {
+    const int kk = h->kc_keep;
+    for (int c = 0; c < kk; ++c)
+      GIR_TRY(atilde(h, nullptr, h->U + (size_t)c * ld, h->C + (size_t)c * ld, nullptr, nullptr, 0));
+    GIR_HIP(hipGetLastError());
+    // CholeskyQR2 in fp64
+    std::vector<double> G1, G2, R1(kk * kk), R2(kk * kk), Ri(kk * kk), Rt(kk * kk);
+    bool ok = true;
+    GIR_TRY(gram(h, basis(h->C, kk, ld, nullptr, 0, ld), h->C, kk, G1));
+    ok = gir::la::cholesky_upper(G1.data(), kk, R1.data());
+    if (ok) {
+      gir::la::inv_upper(R1.data(), kk, Ri.data());
+      GIR_TRY(combine(h, basis(h->C, kk, ld, nullptr, 0, ld), Ri, kk, h->Cn));
+      GIR_TRY(gram(h, basis(h->Cn, kk, ld, nullptr, 0, ld), h->Cn, kk, G2));
+      ok = gir::la::cholesky_upper(G2.data(), kk, R2.data());
+    }
+    if (ok) {
+      gir::la::inv_upper(R2.data(), kk, Ri.data());
+      GIR_TRY(combine(h, basis(h->Cn, kk, ld, nullptr, 0, ld), Ri, kk, h->C));
+      // R = R2 R1, U = Y R^-1
+      for (int j = 0; j < kk; ++j)
+        for (int i = 0; i < kk; ++i) {
+          double sum = 0.0;
+          for (int t = 0; t < kk; ++t) sum += R2[(size_t)t * kk + i] * R1[(size_t)j * kk + t];
+          Rt[(size_t)j * kk + i] = sum;
+        }
+      gir::la::inv_upper(Rt.data(), kk, Ri.data());
+      GIR_TRY(combine(h, basis(h->U, kk, ld, nullptr, 0, ld), Ri, kk, h->Un));
+      std::swap(h->U, h->Un);
+      kc = kk;
+      // d = U (C^T r), r = r - C (C^T r)
+      std::vector<double> ctr(kc);
+      double n2;
+      GIR_TRY(dots_norm(h, basis(h->C, kc, ld, nullptr, 0, ld), h->r32, ctr.data(), &n2));
+      GIR_TRY(upload(h, h->coefA, ctr.data(), sizeof(double) * kc));
+      gir::launch_cycle_update(basis(h->U, kc, ld, nullptr, 0, ld), h->coefA, h->d32,
+                               basis(h->C, kc, ld, nullptr, 0, ld), h->coefA, h->r32, n, s);
+      GIR_HIP(hipGetLastError());
+    }
+  }
+
+  std::vector<double> Hh((size_t)(m + 1) * m), Bh((size_t)std::max(k, 1) * m), y((size_t)m + 1);
+  while (true) {
+    std::vector<double> ctr(std::max(kc, 1));
+    double n2 = 0.0;
+    GIR_TRY(dots_norm(h, basis(h->C, kc, ld, nullptr, 0, ld), h->r32, kc ? ctr.data() : nullptr,
+                      &n2));
+    const double rn = std::sqrt(n2);
+    if (rn <= tol) break;
+    if (stats.its >= cap) break;
+    const int nsteps = std::min(m - kc, cap - stats.its);
+    // v1 = r / ||r||; device cycle state and Givens right-hand side
+    gir::launch_div_f32(h->r32, rn, h->V, n, s);
+    gir::CycleState st0{};
+    st0.tol = tol;
+    st0.est = rn;
+    double* hb = h->hbuf;
+    std::fill(hb, hb + m + 2, 0.0);
+    hb[0] = rn;
+    GIR_HIP(hipMemcpyAsync(h->g, hb, sizeof(double) * (m + 2), hipMemcpyHostToDevice, s));
+    // keep the abort and singular fields of the state
+    GIR_HIP(hipMemcpyAsync(h->st, &st0, offsetof(gir::CycleState, abort), hipMemcpyHostToDevice, s));
+    GIR_HIP(hipMemcpyAsync(&h->st->tol, &st0.tol, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+    GIR_HIP(hipStreamSynchronize(s));
+    int queued = 0;
+    for (int j = 0; j < nsteps; ++j) {
+      float* vj = h->V + (size_t)j * ld;
+      GIR_TRY(atilde(h, vj, nullptr, nullptr, h->w32, h->st, j));
+      gir::OrthoArgs a{};
+      a.X = basis(h->C, kc, ld, h->V, j + 1, ld);
+      a.n = n;
+      a.w_in = h->w32;
+      a.w_out = h->w32;
+      a.partial = h->partial;
+      a.counter = h->counter;
+      a.gate = h->st;
+      a.step = j;
+      a.dots_out = h->h1;
+      gir::launch_ortho(a, gir::kOrthoDots, s);
+      a.coef = h->h1;
+      a.dots_out = h->h2;
+      gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s);
+      a.coef = h->h2;
+      a.h_prev = h->h1;
+      a.norm_out = h->nrm;
+      a.H = h->Hd;
+      a.B = h->Bd;
+      a.ldh = m + 1;
+      a.ldb = std::max(k, 1);
+      a.cs = h->cs;
+      a.sn = h->sn;
+      a.g = h->g;
+      a.st = h->st;
+      gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
+      gir::launch_normalize(h->w32, h->V + (size_t)(j + 1) * ld, h->Hd, m + 1, j, n, h->st, s);
+      GIR_HIP(hipMemcpyAsync(&h->st_host[j], h->st, sizeof(gir::CycleState),
+                             hipMemcpyDeviceToHost, s));
+      GIR_HIP(hipEventRecord(h->ev[j], s));
+      queued = j + 1;
+      if (j >= kLaunchAhead) {
+        GIR_HIP(hipEventSynchronize(h->ev[j - kLaunchAhead]));
+        const gir::CycleState& sj = h->st_host[j - kLaunchAhead];
+        if (sj.done || sj.abort) break;
+      }
+    }
+    (void)queued;
+    GIR_HIP(hipStreamSynchronize(s));
+    gir::CycleState fin{};
+    GIR_TRY(download(h, &fin, h->st, sizeof(fin)));
+    if (fin.abort) {
+      set_error("triangular solve: a device-side wait exceeded its bound");
+      return GMRESIR_EINTERNAL;
+    }
+    const int J = fin.jdone;
+    GIR_TRY(download(h, Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m));
+    if (kc > 0) GIR_TRY(download(h, Bh.data(), h->Bd, sizeof(double) * (size_t)std::max(k, 1) * m));
+    const int ldh = m + 1, ldb = std::max(k, 1);
+    std::fill(y.begin(), y.end(), 0.0);
+    gir::la::givens_lsq(Hh.data(), ldh, J, rn, y.data());
+    // Hbar y (J+1)
+    std::vector<double> hy(J + 1, 0.0);
+    for (int c = 0; c < J; ++c)
+      for (int i = 0; i <= c + 1 && i <= J; ++i) hy[i] += Hh[(size_t)c * ldh + i] * y[c];
+    stats.its += J;
+    if (kc == 0) {
+      std::vector<double> cdv(y.begin(), y.begin() + J);
+      GIR_TRY(upload(h, h->coefA, cdv.data(), sizeof(double) * std::max(J, 1)));
+      GIR_TRY(upload(h, h->coefB, hy.data(), sizeof(double) * (J + 1)));
+      gir::launch_cycle_update(basis(nullptr, 0, ld, h->V, J, ld), h->coefA, h->d32,
+                               basis(nullptr, 0, ld, h->V, J + 1, ld), h->coefB, h->r32, n, s);
+      GIR_HIP(hipGetLastError());
+      if (k > 0 && J > 0) {
+        // first-cycle harmonic Ritz: Hbar^T Hbar z = theta H^T z
+        std::vector<double> Gm((size_t)(J + 1) * J), Mm((size_t)(J + 1) * J, 0.0);
+        for (int c = 0; c < J; ++c) {
+          for (int i = 0; i <= J; ++i) Gm[(size_t)c * (J + 1) + i] = (i <= c + 1) ? Hh[(size_t)c * ldh + i] : 0.0;
+          Mm[(size_t)c * (J + 1) + c] = 1.0;
+        }
+        std::vector<double> Pk((size_t)J * k);
+        const int kn = gir::la::harmonic_ritz(Gm.data(), Mm.data(), J + 1, J, k, Pk.data());
+        if (kn > 0) {
+          std::vector<double> GP((size_t)(J + 1) * kn, 0.0), Q((size_t)(J + 1) * kn), R((size_t)kn * kn),
+              Ri((size_t)kn * kn), PR((size_t)J * kn, 0.0);
+          for (int o = 0; o < kn; ++o)
+            for (int i = 0; i <= J; ++i) {
+              double sum = 0.0;
+              for (int c = 0; c < J; ++c) sum += Gm[(size_t)c * (J + 1) + i] * Pk[(size_t)o * J + c];
+              GP[(size_t)o * (J + 1) + i] = sum;
+            }
+          if (gir::la::qr_thin(GP.data(), J + 1, J + 1, kn, Q.data(), R.data())) {
+            gir::la::inv_upper(R.data(), kn, Ri.data());
+            for (int o = 0; o < kn; ++o)
+              for (int c = 0; c < J; ++c) {
+                double sum = 0.0;
+                for (int t = 0; t < kn; ++t) sum += Pk[(size_t)t * J + c] * Ri[(size_t)o * kn + t];
+                PR[(size_t)o * J + c] = sum;
+              }
+            GIR_TRY(combine(h, basis(nullptr, 0, ld, h->V, J + 1, ld), Q, kn, h->Cn));
+            GIR_TRY(combine(h, basis(nullptr, 0, ld, h->V, J, ld), PR, kn, h->Un));
+            std::swap(h->C, h->Cn);
+            std::swap(h->U, h->Un);
+            kc = kn;
+          }
+        }
+      }
+    } else {
+      // D = diag(1 / ||U e_i||)
+      std::vector<double> UU;
+      GIR_TRY(gram(h, basis(h->U, kc, ld, nullptr, 0, ld), h->U, kc, UU));
+      std::vector<double> dk(kc);
+      for (int i = 0; i < kc; ++i) dk[i] = 1.0 / std::sqrt(UU[(size_t)i * kc + i]);
+      std::vector<double> y1(kc), by2(kc, 0.0);
+      for (int i = 0; i < kc; ++i) {
+        for (int c = 0; c < J; ++c) by2[i] += Bh[(size_t)c * ldb + i] * y[c];
+        y1[i] = (ctr[i] - by2[i]) / dk[i];
+      }
+      std::vector<double> cdv(kc + J), crv(kc + J + 1);
+      for (int i = 0; i < kc; ++i) {
+        cdv[i] = dk[i] * y1[i];
+        crv[i] = dk[i] * y1[i] + by2[i];
+      }
+      for (int c = 0; c < J; ++c) cdv[kc + c] = y[c];
+      for (int i = 0; i <= J; ++i) crv[kc + i] = hy[i];
+      GIR_TRY(upload(h, h->coefA, cdv.data(), sizeof(double) * cdv.size()));
+      GIR_TRY(upload(h, h->coefB, crv.data(), sizeof(double) * crv.size()));
+      gir::launch_cycle_update(basis(h->U, kc, ld, h->V, J, ld), h->coefA, h->d32,
+                               basis(h->C, kc, ld, h->V, J + 1, ld), h->coefB, h->r32, n, s);
+      GIR_HIP(hipGetLastError());
+      if (J > 0) {
+        const int rows = kc + J + 1, cols = kc + J;
+        std::vector<double> W;  // [C V_{J+1}]^T U  (rows x kc)
+        GIR_TRY(gram(h, basis(h->C, kc, ld, h->V, J + 1, ld), h->U, kc, W));
+        std::vector<double> Gm((size_t)rows * cols, 0.0), Mm((size_t)rows * cols, 0.0);
+        for (int i = 0; i < kc; ++i) Gm[(size_t)i * rows + i] = dk[i];
+        for (int c = 0; c < J; ++c) {
+          for (int i = 0; i < kc; ++i) Gm[(size_t)(kc + c) * rows + i] = Bh[(size_t)c * ldb + i];
+          for (int i = 0; i <= J; ++i)
+            Gm[(size_t)(kc + c) * rows + kc + i] = (i <= c + 1) ? Hh[(size_t)c * ldh + i] : 0.0;
+          Mm[(size_t)(kc + c) * rows + kc + c] = 1.0;
+        }
+        for (int c = 0; c < kc; ++c)
+          for (int i = 0; i < rows; ++i) Mm[(size_t)c * rows + i] = W[(size_t)c * rows + i] * dk[c];
+        std::vector<double> Pk((size_t)cols * k);
+        const int kn = gir::la::harmonic_ritz(Gm.data(), Mm.data(), rows, cols, k, Pk.data());
+        if (kn > 0) {
+          std::vector<double> GP((size_t)rows * kn, 0.0), Q((size_t)rows * kn), R((size_t)kn * kn),
+              Ri((size_t)kn * kn), PR((size_t)cols * kn, 0.0);
+          for (int o = 0; o < kn; ++o)
+            for (int i = 0; i < rows; ++i) {
+              double sum = 0.0;
+              for (int c = 0; c < cols; ++c) sum += Gm[(size_t)c * rows + i] * Pk[(size_t)o * cols + c];
+              GP[(size_t)o * rows + i] = sum;
+            }
+          if (gir::la::qr_thin(GP.data(), rows, rows, kn, Q.data(), R.data())) {
+            gir::la::inv_upper(R.data(), kn, Ri.data());
+            for (int o = 0; o < kn; ++o)
+              for (int c = 0; c < cols; ++c) {
+                double sum = 0.0;
+                for (int t = 0; t < kn; ++t) sum += Pk[(size_t)t * cols + c] * Ri[(size_t)o * kn + t];
+                // U-tilde = U D: fold D into the coefficients of the U columns
+                PR[(size_t)o * cols + c] = (c < kc) ? sum * dk[c] : sum;
+              }
+            GIR_TRY(combine(h, basis(h->C, kc, ld, h->V, J + 1, ld), Q, kn, h->Cn));
+            GIR_TRY(combine(h, basis(h->U, kc, ld, h->V, J, ld), PR, kn, h->Un));
+            std::swap(h->C, h->Cn);
+            std::swap(h->U, h->Un);
+            kc = kn;
+          }
+        }
+      }
+    }
+    GIR_HIP(hipStreamSynchronize(s));
+  }
+  h->kc_keep = (k > 0) ? kc : 0;
+  return 0;
+}
+
+int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* info) {
+  const int n = (int)h->n;
+  hipStream_t s = h->stream;
+  const double t0 = now_s();
+  gmresir_info inf{};
+  inf.singular_col = h->singular_col;
+  if (h->status == GMRESIR_ESINGULAR || h->status == GMRESIR_ERANGE) {
+    inf.status = h->status;
+    if (info) *info = inf;
+    return h->status;
+  }
+  if (!h->o.keep_recycle) h->kc_keep = 0;
+  GIR_HIP(hipMemcpyAsync(h->b, bcol, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  gir::launch_maxabs(h->b, n, h->norms + 2, s);
+  unsigned long long bbits = 0;
+  GIR_TRY(download(h, &bbits, h->norms + 2, 8));
+  double bmax;
+  std::memcpy(&bmax, &bbits, 8);
+  if (!std::isfinite(bmax)) {
+    inf.status = GMRESIR_ERANGE;
+    if (info) *info = inf;
+    return GMRESIR_ERANGE;
+  }
+  // x0 = M^-1 b in u^2, kept in fp64
+  GIR_TRY(precond(h, h->b, h->permP, h->x, nullptr, nullptr, 0));
+  int status = GMRESIR_ENOCONV;
+  const int imax = h->o.imax;
+  int i = 0;
+  for (;; ++i) {
+    gir::launch_residual(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s);
+    GIR_HIP(hipGetLastError());
+    unsigned long long nb[2];
+    GIR_TRY(download(h, nb, h->norms, sizeof(nb)));
+    double rmax, xmax;
+    std::memcpy(&rmax, &nb[0], 8);
+    std::memcpy(&xmax, &nb[1], 8);
+    const double den = h->norm_a * xmax + bmax;
+    const double eta = (rmax == 0.0) ? 0.0 : (den > 0.0 ? rmax / den : INFINITY);
+    if (i <= GMRESIR_MAX_STEPS) inf.berr[i] = eta;
+    if (!std::isfinite(eta)) {
+      status = GMRESIR_ERANGE;
+      break;
+    }
+    if (eta <= h->o.berr_target) {
+      status = GMRESIR_OK;
+      break;
+    }
+    if (i >= imax) break;
+    gir::launch_scale_round(h->r64, rmax, h->t64, n, s);  // r-hat = fl32(r / s)
+    GIR_TRY(precond(h, h->t64, h->permP, nullptr, h->z32, nullptr, 0));
+    SolveStats ss;
+    GIR_TRY(gcrodr(h, ss));
+    inf.its[i] = ss.its;
+    inf.total_its += ss.its;
+    gir::launch_x_update(h->x, h->d32, rmax, n, s);
+    GIR_HIP(hipGetLastError());
+  }
+  inf.steps = i;
+  inf.status = status;
+  inf.recycle_dim = h->kc_keep;
+  GIR_HIP(hipMemcpyAsync(xcol, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  GIR_HIP(hipStreamSynchronize(s));
+  inf.t_factor_s = h->t_factor;
+  inf.t_solve_s = now_s() - t0;
+  if (info) *info = inf;
+  return status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void gmresir_default_opts(gmresir_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(gmresir_opts);
+  o->uf = GMRESIR_FP16;
+  o->u = GMRESIR_FP32;
+  o->ur = GMRESIR_FP64;
+  o->m = 30;
+  o->k = 10;
+  o->tau = 1e-4;
+  o->imax = 10;
+  o->maxit = 0;
+  o->berr_target = 1e-14;
+  o->scale_pow2 = -1;
+  o->keep_recycle = 0;
+}
+
+int gmresir_factor(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts,
+                   void* stream, gmresir_ctx** out) {
+  gmresir_ctx* h = nullptr;
+  const double t0 = now_s();
+  GIR_TRY(make_ctx(A, n, lda, opts, stream, out, &h));
+  int rc = alloc_common(h);
+  if (rc == 0) rc = ingest(h, A, lda, true);
+  if (rc == 0 && h->status == 0) {
+    h->permP = h->perm;
+    h->permS = h->perm;
+    rc = run_lu(h);
+  }
+  if (rc == 0) rc = alloc_solve(h);
+  if (rc == 0) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      set_error(std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+      rc = GMRESIR_EHIP;
+    }
+  }
+  if (rc != 0) {
+    delete h;
+    return rc;
+  }
+  h->t_factor = now_s() - t0;
+  *out = h;
+  return h->status;
+}
+
+int gmresir_import_factors(const double* A, int64_t n, int64_t lda, const void* lu, int64_t ldlu,
+                           const int32_t* ipiv, int32_t e, const gmresir_opts* opts, void* stream,
+                           gmresir_ctx** out) {
+  gmresir_ctx* h = nullptr;
+  GIR_TRY(make_ctx(A, n, lda, opts, stream, out, &h));
+  if (!lu || !ipiv || ldlu < n) {
+    delete h;
+    set_error("invalid lu, ipiv or ldlu");
+    return GMRESIR_EINVAL;
+  }
+  int rc = alloc_common(h);
+  if (rc == 0) rc = ingest(h, A, lda, false);
+  if (rc == 0) {
+    // factors in logical row order: S is read without a row gather
+    const size_t eb = store_bytes(h->store);
+    hipError_t err = hipMemcpy2DAsync(h->S, h->ld * eb, lu, ldlu * eb, n * eb, n,
+                                      hipMemcpyDeviceToDevice, h->stream);
+    if (err != hipSuccess) {
+      set_error(std::string("hipMemcpy2DAsync: ") + hipGetErrorString(err));
+      rc = GMRESIR_EHIP;
+    }
+  }
+  if (rc == 0) {
+    int* flag = reinterpret_cast<int*>(h->counter + 2);
+    gir::launch_convert(h->A64, n, h->ld, 0, h->store, nullptr, h->Au, h->ld, flag, h->stream);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = GMRESIR_EHIP;
+  }
+  if (rc == 0) {
+    h->e = e;
+    h->scale = std::ldexp(1.0, e);
+    std::vector<int> perm(n), ip(ipiv, ipiv + n);
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+    for (int64_t i = 0; i < n; ++i) {
+      if (ip[i] < 0 || ip[i] >= n) {
+        set_error("ipiv out of range");
+        rc = GMRESIR_EINVAL;
+        break;
+      }
+      std::swap(perm[i], perm[ip[i]]);
+    }
+    if (rc == 0) rc = upload(h, h->perm, perm.data(), sizeof(int) * n);
+    if (rc == 0) rc = upload(h, h->ipiv, ipiv, sizeof(int) * n);
+    h->permP = h->perm;
+    h->permS = nullptr;
+  }
+  if (rc == 0) rc = alloc_solve(h);
+  if (rc == 0 && hipStreamSynchronize(h->stream) != hipSuccess) rc = GMRESIR_EHIP;
+  if (rc != 0) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return h->status == GMRESIR_ESINGULAR ? 0 : h->status;
+}
+
+int gmresir_solve(gmresir_ctx* h, const double* b, double* x, int64_t nrhs, int64_t ldb,
+                  void* stream, gmresir_info* info) {
+  if (!h || !b || !x || nrhs < 1 || ldb < h->n) {
+    set_error("invalid solve arguments");
+    return GMRESIR_EINVAL;
+  }
+  if (stream) h->stream = reinterpret_cast<hipStream_t>(stream);
+  int rc = 0;
+  for (int64_t j = 0; j < nrhs; ++j) {
+    rc = solve_one(h, b + j * ldb, x + j * ldb, info);
+    if (rc < 0) return rc;
+  }
+  return rc;
+}
+
+void gmresir_free(gmresir_ctx* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+const char* gmresir_strerror(int status) {
+  switch (status) {
+    case GMRESIR_OK: return "success";
+    case GMRESIR_EINVAL: return "invalid argument";
+    case GMRESIR_ENOMEM: return "out of memory";
+    case GMRESIR_EHIP: return "HIP runtime error";
+    case GMRESIR_EINTERNAL: return "device-side wait exceeded its bound";
+    case GMRESIR_ESINGULAR: return "exact zero pivot in the factorization precision";
+    case GMRESIR_ERANGE: return "non-finite value or overflow in the factorization precision";
+    case GMRESIR_ENOCONV: return "backward-error target not reached within imax steps";
+    default: return "unknown status";
+  }
+}
+
+const char* gmresir_last_error(void) { return g_last_error.c_str(); }
+
+int gmresir_export_factors(gmresir_ctx* h, void* lu, int32_t* ipiv, int32_t* e) {
+  if (!h) {
+    set_error("handle is NULL");
+    return GMRESIR_EINVAL;
+  }
+  const int64_t n = h->n;
+  if (e) *e = h->e;
+  if (ipiv) GIR_TRY(download(h, ipiv, h->ipiv, sizeof(int) * n));
+  if (lu) {
+    const size_t eb = store_bytes(h->store);
+    std::vector<int> perm(n);
+    if (h->permS) {
+      GIR_TRY(download(h, perm.data(), h->permS, sizeof(int) * n));
+    } else {
+      for (int64_t i = 0; i < n; ++i) perm[i] = (int)i;
+    }
+    std::vector<char> row((size_t)h->ld * eb);
+    char* dst = reinterpret_cast<char*>(lu);
+    for (int64_t i = 0; i < n; ++i) {
+      const char* src = reinterpret_cast<const char*>(h->S) + (size_t)perm[i] * h->ld * eb;
+      GIR_HIP(hipMemcpyAsync(dst + (size_t)i * n * eb, src, n * eb, hipMemcpyDeviceToHost,
+                             h->stream));
+    }
+    GIR_HIP(hipStreamSynchronize(h->stream));
+  }
+  return 0;
+}
+
+int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y, void* stream) {
+  if (!h || !v || !y || (op != 0 && op != 1)) {
+    set_error("invalid apply arguments");
+    return GMRESIR_EINVAL;
+  }
+  if (h->status == GMRESIR_ERANGE) return GMRESIR_ERANGE;
+  if (stream) h->stream = reinterpret_cast<hipStream_t>(stream);
+  const int n = (int)h->n;
+  GIR_HIP(hipMemcpyAsync(h->r64, v, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+  if (op == 0) {
+    GIR_TRY(precond(h, h->r64, h->permP, h->x, nullptr, nullptr, 0));
+  } else {
+    GIR_TRY(atilde(h, nullptr, h->r64, h->x, nullptr, nullptr, 0));
+  }
+  GIR_HIP(hipGetLastError());
+  GIR_HIP(hipMemcpyAsync(y, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+  GIR_HIP(hipStreamSynchronize(h->stream));
+  gir::CycleState hs{};
+  GIR_TRY(download(h, &hs, h->st, sizeof(hs)));
+  if (hs.abort) {
+    set_error("triangular solve: a device-side wait exceeded its bound");
+    return GMRESIR_EINTERNAL;
+  }
+  return 0;
+}
+
+int gmresir_query(gmresir_ctx* h, int64_t* n, int32_t* abi) {
+  if (abi) *abi = GMRESIR_ABI_VERSION;
+  if (!h) return GMRESIR_EINVAL;
+  if (n) *n = h->n;
+  return 0;
+}
+
+}  // extern "C"
