@@ -25,7 +25,7 @@ ARCH = os.environ.get("GMRESIR_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     "-fno-gpu-flush-denormals-to-zero",
     # packed fp32 instructions are kept out of every kernel

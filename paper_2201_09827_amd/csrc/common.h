@@ -80,15 +80,45 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double(((int64_t)(uint32_t)lo) | (((int64_t)hi) << 32));
 }
 
+// Wave-wide maximum of a 64-bit unsigned key with DPP row shifts and row
+// broadcasts (no LDS round trips); every lane receives the maximum.
+__device__ __forceinline__ uint64_t dpp_max_step(uint64_t v, int lo_nb, int hi_nb) {
+  return v > (((uint64_t)(uint32_t)hi_nb << 32) | (uint32_t)lo_nb) ? v
+         : (((uint64_t)(uint32_t)hi_nb << 32) | (uint32_t)lo_nb);
+}
+
+#define GIR_DPP_MAX(v, ctrl, rmask)                                                        \
+  do {                                                                                   \
+    const int lo_ = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v), ctrl, rmask, 0xf, false); \
+    const int hi_ = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((v) >> 32), ctrl, rmask, 0xf, false); \
+    v = dpp_max_step(v, lo_, hi_);                                                       \
+  } while (0)
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  GIR_DPP_MAX(v, 0x111, 0xf);  // row_shr:1
+  GIR_DPP_MAX(v, 0x112, 0xf);  // row_shr:2
+  GIR_DPP_MAX(v, 0x114, 0xf);  // row_shr:4
+  GIR_DPP_MAX(v, 0x118, 0xf);  // row_shr:8  -> lane 15 of each row holds the row max
+  GIR_DPP_MAX(v, 0x142, 0xa);  // row_bcast:15 -> rows 1, 3
+  GIR_DPP_MAX(v, 0x143, 0xc);  // row_bcast:31 -> rows 2, 3
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // atomic max of a non-negative double stored as its bit pattern
 __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double v) {
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
-// bounded wait on a device-scope flag; returns false on timeout or abort
-__device__ __forceinline__ bool wait_geq(const int* flag, int target, int* abort_flag) {
+// Bounded waits on a device-scope flag.  The flag is polled with relaxed
+// loads (an acquire load would invalidate the caches on every poll) and a
+// single acquire fence follows the successful poll.  Returns false on
+// timeout (which also raises the abort flag) or when another wave aborted.
+template <class Pred>
+__device__ __forceinline__ bool wait_until(const int* flag, Pred ok, int* abort_flag) {
   long long spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  while (!ok(__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
     __builtin_amdgcn_s_sleep(1);
     if (((++spins) & 1023) == 0) {
       if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
@@ -98,22 +128,35 @@ __device__ __forceinline__ bool wait_geq(const int* flag, int target, int* abort
       }
     }
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
+__device__ __forceinline__ bool wait_geq(const int* flag, int target, int* abort_flag) {
+  return wait_until(flag, [target](int v) { return v >= target; }, abort_flag);
+}
+
 __device__ __forceinline__ bool wait_eq(const int* flag, int target, int* abort_flag) {
-  long long spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
-    __builtin_amdgcn_s_sleep(1);
-    if (((++spins) & 1023) == 0) {
-      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-      if (spins > (1ll << 25)) {
-        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
+  return wait_until(flag, [target](int v) { return v == target; }, abort_flag);
+}
+
+// Publish the stores of the whole workgroup, then set the flag: the
+// workgroup barrier completes every wave's stores, one device-scope release
+// fence makes them visible to the other XCDs, then thread 0 stores.
+__device__ __forceinline__ void publish_store(int* flag, int value) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  return true;
+}
+
+__device__ __forceinline__ void publish_add(int* flag, int value) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Device-side state of one Arnoldi cycle (shared with the host driver).

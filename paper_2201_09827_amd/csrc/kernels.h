@@ -56,15 +56,21 @@ void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const 
 // r = b - A x (fp64); norms[0] = max|r| bits, norms[1] = max|x| bits (zeroed here)
 void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
                      double* r, unsigned long long* norms, hipStream_t s);
-// y = L^-1 (in gathered by permIn), fp64; L unit lower in S rows permS
+// y = L^-1 (in gathered by permIn), fp64; L unit lower in S rows permS;
+// Linv holds the fp64 inverses of the 64 x 64 diagonal blocks
 void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
-                       const double* in, const int* permIn, double* y, int* flags, int epoch,
-                       const CycleState* gate, int step, int* abort, hipStream_t s);
-// z = U^-1 y; out64 = 2^e z, out32 = fl32(2^e z) (either may be null)
-void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
-                       const double* y, double* z, double scale, double* out64, float* out32,
+                       const double* in, const int* permIn, const double* Linv, double* y,
                        int* flags, int epoch, const CycleState* gate, int step, int* abort,
                        hipStream_t s);
+// z = U^-1 y; out64 = 2^e z, out32 = fl32(2^e z) (either may be null)
+void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
+                       const double* y, const double* Uinv, double* z, double scale,
+                       double* out64, float* out32, int* flags, int epoch, const CycleState* gate,
+                       int step, int* abort, hipStream_t s);
+// fp64 inverses of the 64 x 64 diagonal blocks of L and U (ceil(n/64) blocks
+// of 64 x 64 each, row-major)
+void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,
+                          double* Linv, double* Uinv, hipStream_t s);
 
 struct Basis {
   const double* c64;  // kc columns, column-major, ld ldc

@@ -21,11 +21,18 @@
 // device-scope counters with bounded waits.
 #include "kernels.h"
 
+// Phase hooks of the block-column kernel; empty unless a timing harness
+// defines them before including this file.
+#ifndef GIR_PANEL_MARK
+#define GIR_PANEL_MARK(tag)
+#define GIR_PANEL_MARK_INIT
+#endif
+
 namespace gir {
 
 namespace {
 
-constexpr int kPanelThreads = 1024;
+constexpr int kPanelThreads = 512;
 constexpr int kMaxNb = 64;
 
 __device__ __forceinline__ double wave_max_d(double v) {
@@ -117,7 +124,7 @@ struct Cand {
 };
 
 template <int R, int W>
-__device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int k0,
+__device__ __forceinline__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int k0,
                              int* __restrict__ pstep, int* __restrict__ piv_prow,
                              int* __restrict__ lidx_out, int* __restrict__ ipiv, int* sync,
                              CycleState* st, int nhelpers) {
@@ -141,11 +148,13 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
   }
   if (tid == 0) s_abort = 0;
   __syncthreads();
+  GIR_PANEL_MARK_INIT
 
   const int nblk = (kb + W - 1) / W;
   for (int ib = 0; ib < nblk; ++ib) {
     const int c0 = ib * W;
     const int wcols = min(W, kb - c0);
+    GIR_PANEL_MARK(0);
     if (ib > 0) {
       if (lane == 0) {
         if (!wait_geq(&sync[1], ib * nhelpers, abortp)) s_abort = 1;
@@ -153,6 +162,7 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
       __syncthreads();
       if (s_abort) return;
     }
+    GIR_PANEL_MARK(1);
     bool pvb[R];
 #pragma unroll
     for (int s = 0; s < R; ++s) {
@@ -162,6 +172,7 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
       for (int c = 0; c < W; ++c)
         x[s][c] = (!pv[s] && c < wcols) ? P[(int64_t)(c0 + c) * ldp + q] : 0.0f;
     }
+    GIR_PANEL_MARK(2);
 
 #pragma unroll
     for (int c = 0; c < W; ++c) {
@@ -172,15 +183,13 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
         int bs = -1;
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-          if (!pv[s]) {
-            const float a = fabsf(x[s][c]);
-            if (a > bv || (a == bv && lid[s] < bl)) {
-              bv = a;
-              bl = lid[s];
-              bs = s;
-            }
-          }
+          const float a = pv[s] ? -1.0f : fabsf(x[s][c]);
+          const bool better = a > bv || (a == bv && lid[s] < bl);
+          bv = better ? a : bv;
+          bl = better ? lid[s] : bl;
+          bs = better ? s : bs;
         }
+        if (bv < 0.0f) bs = -1;
         float wv = bv;
         int wl = bl;
 #pragma unroll
@@ -192,6 +201,7 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
             wl = ol;
           }
         }
+        GIR_PANEL_MARK(10 + c);
         Cand* cb = &cand[c & 1][wave];
         if (bs >= 0 && bl == wl && bv == wv) {
           cb->val = bv;
@@ -211,6 +221,7 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
           cb->prow = -1;
         }
         __syncthreads();
+        GIR_PANEL_MARK(20 + c);
         float gv = -1.0f;
         int gl = 0x7fffffff;
         int gw = 0;
@@ -226,41 +237,54 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
         }
         const Cand* win = &cand[c & 1][gw];
         const int p = win->prow;
-        float u[W];
-#pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) u[c2] = win->row[c2];
+        const float* u = win->row;  // pivot row, read from LDS (broadcast)
         const float piv = u[c];
         if (tid == 0) {
           ipiv[k0 + cc] = k0 + gl;
           piv_prow[cc] = p;
           blk_prow[c] = p;
-#pragma unroll
-          for (int c2 = 0; c2 < W; ++c2) Lblk[c][c2] = u[c2];
           if (piv == 0.0f) atomicCAS(&st->singular, 0, k0 + cc + 1);
         }
+        if (tid < W) Lblk[c][tid] = u[tid];
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const int q = tid + kPanelThreads * s;
-          if (!pv[s] && lid[s] == cc) lid[s] = gl;
-          if (q == p) {
-            lid[s] = cc;
-            pv[s] = true;
-          }
+          lid[s] = (!pv[s] && lid[s] == cc) ? gl : lid[s];
+          lid[s] = (q == p) ? cc : lid[s];
+          pv[s] = pv[s] || (q == p);
         }
         if (piv != 0.0f) {
+          // multipliers fl32(a / piv): reciprocal, product and one fused
+          // correction give the correctly rounded quotient (Markstein); a
+          // quotient in the subnormal range falls back to the division
+          const float rinv = 1.0f / piv;
+          const bool rok = __builtin_isfinite(rinv);
+          float ucol[W];
+#pragma unroll
+          for (int c2 = c + 1; c2 < W; ++c2) ucol[c2] = u[c2];
 #pragma unroll
           for (int s = 0; s < R; ++s) {
-            if (!pv[s]) {
-              const float l = x[s][c] / piv;
-              x[s][c] = l;
-#pragma unroll
-              for (int c2 = c + 1; c2 < W; ++c2) x[s][c2] = __builtin_fmaf(-l, u[c2], x[s][c2]);
+            const float a = x[s][c];
+            float l;
+            if (rok) {
+              const float q0 = a * rinv;
+              const float e = __builtin_fmaf(-q0, piv, a);
+              l = __builtin_fmaf(e, rinv, q0);
+              if (__builtin_expect(fabsf(l) < 0x1p-100f, 0) && a != 0.0f) l = a / piv;
+            } else {
+              l = a / piv;
             }
+            const bool upd = !pv[s];
+            x[s][c] = upd ? l : a;
+#pragma unroll
+            for (int c2 = c + 1; c2 < W; ++c2)
+              x[s][c2] = upd ? __builtin_fmaf(-l, ucol[c2], x[s][c2]) : x[s][c2];
           }
         }
       }
     }
 
+    GIR_PANEL_MARK(3);
     // write the block back (rows that were not pivots before this block)
 #pragma unroll
     for (int s = 0; s < R; ++s) {
@@ -273,6 +297,7 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
       }
     }
     __syncthreads();
+    GIR_PANEL_MARK(4);
     // U part of the new pivot rows in the remaining columns of the panel
     const int rem0 = c0 + W;
     for (int cr = rem0 + tid; cr < kb; cr += kPanelThreads) {
@@ -287,10 +312,8 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
 #pragma unroll
       for (int t = 0; t < W; ++t) P[(int64_t)cr * ldp + blk_prow[t]] = y[t];
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0 && ib < nblk - 1)
-      __hip_atomic_store(&sync[0], ib + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (ib < nblk - 1) publish_store(&sync[0], ib + 1);
+    GIR_PANEL_MARK(5);
   }
 #pragma unroll
   for (int s = 0; s < R; ++s) {
@@ -300,7 +323,7 @@ __device__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int 
 }
 
 template <int W>
-__device__ void panel_helper(float* __restrict__ P, int ldp, int h, int kb,
+__device__ __forceinline__ void panel_helper(float* __restrict__ P, int ldp, int h, int kb,
                              const int* __restrict__ pstep, const int* __restrict__ piv_prow,
                              int* sync, CycleState* st, int nhelpers, int hid) {
   __shared__ float Ush[W][kMaxNb];
@@ -333,18 +356,24 @@ __device__ void panel_helper(float* __restrict__ P, int ldp, int h, int kb,
       Ush[t][cr] = P[(int64_t)(rem0 + cr) * ldp + prow_sh[t]];
     }
     __syncthreads();
-    for (int idx = tid; idx < nrows * nrem; idx += kPanelThreads) {
-      const int cr = idx / nrows;
-      const int q = qb + (idx - cr * nrows);
+    // lane -> row, wave -> group of columns; the row's W multipliers are
+    // loaded once and applied to every remaining column it owns
+    const int rl = tid % kWave;
+    const int cg = tid / kWave;
+    constexpr int kGroups = kPanelThreads / kWave;
+    for (int q = qb + rl; q < qb + nrows; q += kWave) {
       if (pstep[q] >= 0) continue;
-      float a = P[(int64_t)(rem0 + cr) * ldp + q];
+      float l[W];
 #pragma unroll
-      for (int t = 0; t < W; ++t) a = __builtin_fmaf(-P[(int64_t)(c0 + t) * ldp + q], Ush[t][cr], a);
-      P[(int64_t)(rem0 + cr) * ldp + q] = a;
+      for (int t = 0; t < W; ++t) l[t] = P[(int64_t)(c0 + t) * ldp + q];
+      for (int cr = cg; cr < nrem; cr += kGroups) {
+        float a = P[(int64_t)(rem0 + cr) * ldp + q];
+#pragma unroll
+        for (int t = 0; t < W; ++t) a = __builtin_fmaf(-l[t], Ush[t][cr], a);
+        P[(int64_t)(rem0 + cr) * ldp + q] = a;
+      }
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(&sync[1], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    publish_add(&sync[1], 1);
   }
 }
 
@@ -377,15 +406,20 @@ __global__ void k_perm_copy(int* perm, const int* ptmp, int k0, int h) {
   if (i < h) perm[k0 + i] = ptmp[i];
 }
 
-// U12 = L11^-1 A12 in fp32, one thread per column (row order of the updates
-// as in forward substitution); L11 is the stored (u_f) unit lower triangle.
+// U12 = L11^-1 A12 in fp32 with the stored (u_f) unit lower triangle L11.
+// A workgroup owns 64 columns staged in LDS; elimination step t updates rows
+// r > t with one fused multiply-add each, so every entry receives its terms
+// in the order t = 0, 1, ... of forward substitution.
+constexpr int kTrsmCols = 64;
 template <class F>
 __global__ __launch_bounds__(256) void k_trsm(typename F::T* __restrict__ S, int64_t ld,
                                               const int* __restrict__ perm, int k0, int kb,
                                               int n) {
   __shared__ float Lsh[kMaxNb][kMaxNb + 1];
+  __shared__ float Y[kMaxNb][kTrsmCols + 1];
   __shared__ int prow[kMaxNb];
   const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)k0 + kb + (int64_t)blockIdx.x * kTrsmCols;
   if (tid < kMaxNb) prow[tid] = (tid < kb) ? perm[k0 + tid] : 0;
   __syncthreads();
   for (int idx = tid; idx < kMaxNb * kMaxNb; idx += blockDim.x) {
@@ -393,20 +427,24 @@ __global__ __launch_bounds__(256) void k_trsm(typename F::T* __restrict__ S, int
     const int s = idx % kMaxNb;
     Lsh[t][s] = (t < kb && s < t) ? F::to_f(S[(int64_t)prow[t] * ld + k0 + s]) : 0.0f;
   }
-  __syncthreads();
-  const int64_t col = (int64_t)k0 + kb + (int64_t)blockIdx.x * blockDim.x + tid;
-  if (col >= n) return;
-  float y[kMaxNb];
-#pragma unroll
-  for (int t = 0; t < kMaxNb; ++t) y[t] = (t < kb) ? F::to_f(S[(int64_t)prow[t] * ld + col]) : 0.0f;
-#pragma unroll
-  for (int t = 1; t < kMaxNb; ++t) {
-#pragma unroll
-    for (int s = 0; s < t; ++s) y[t] = __builtin_fmaf(-Lsh[t][s], y[s], y[t]);
+  for (int idx = tid; idx < kMaxNb * kTrsmCols; idx += blockDim.x) {
+    const int t = idx / kTrsmCols;
+    const int c = idx % kTrsmCols;
+    Y[t][c] = (t < kb && c0 + c < n) ? F::to_f(S[(int64_t)prow[t] * ld + c0 + c]) : 0.0f;
   }
-#pragma unroll
-  for (int t = 0; t < kMaxNb; ++t)
-    if (t < kb) S[(int64_t)prow[t] * ld + col] = F::from_f(y[t]);
+  __syncthreads();
+  const int c = tid % kTrsmCols;
+  const int rg = tid / kTrsmCols;  // 4 row groups
+  for (int t = 0; t < kb - 1; ++t) {
+    const float yt = Y[t][c];
+    for (int r = t + 1 + rg; r < kb; r += 4) Y[r][c] = __builtin_fmaf(-Lsh[r][t], yt, Y[r][c]);
+    __syncthreads();
+  }
+  for (int idx = tid; idx < kMaxNb * kTrsmCols; idx += blockDim.x) {
+    const int t = idx / kTrsmCols;
+    const int cc = idx % kTrsmCols;
+    if (t < kb && c0 + cc < n) S[(int64_t)prow[t] * ld + c0 + cc] = F::from_f(Y[t][cc]);
+  }
 }
 
 // ---- trailing update on the matrix cores ----------------------------------
@@ -556,18 +594,20 @@ void panel_step_t(const PanelArgs& a, int nhelpers, hipStream_t s) {
 #define GIR_PANEL(R, W)                                                                       \
   hipLaunchKernelGGL((k_panel<R, W>), dim3(nwg), dim3(kPanelThreads), 0, s, a.P, a.ldp, h, \
                      a.kb, a.k0, a.pstep, a.piv_prow, a.lidx, a.ipiv, a.sync, a.st, nhelpers)
-  if (h <= 1024)
-    GIR_PANEL(1, 64);
+  // rows per thread x block width chosen so that the leader's register block
+  // stays in registers (no scratch) at 512 threads
+  if (h <= 512)
+    GIR_PANEL(1, 16);
+  else if (h <= 1024)
+    GIR_PANEL(2, 16);
   else if (h <= 2048)
-    GIR_PANEL(2, 32);
+    GIR_PANEL(4, 8);
   else if (h <= 4096)
-    GIR_PANEL(4, 16);
-  else if (h <= 8192)
     GIR_PANEL(8, 8);
-  else if (h <= 16384)
-    GIR_PANEL(16, 4);
+  else if (h <= 8192)
+    GIR_PANEL(16, 8);
   else
-    GIR_PANEL(32, 2);
+    GIR_PANEL(32, 2);  // h <= 16384
 #undef GIR_PANEL
   hipLaunchKernelGGL(k_panel_scatter<F>, dim3((h + blk - 1) / blk), dim3(blk), 0, s, S, a.ld,
                      a.perm, a.k0, a.kb, h, a.P, a.ldp, a.lidx, a.ptmp);
@@ -581,8 +621,8 @@ void trsm_update_t(const PanelArgs& a, hipStream_t s) {
   T* S = reinterpret_cast<T*>(a.S);
   const int M = a.n - a.k0 - a.kb;
   if (M <= 0) return;
-  hipLaunchKernelGGL(k_trsm<F>, dim3((M + 255) / 256), dim3(256), 0, s, S, a.ld, a.perm, a.k0,
-                     a.kb, a.n);
+  hipLaunchKernelGGL(k_trsm<F>, dim3((M + kTrsmCols - 1) / kTrsmCols), dim3(256), 0, s, S, a.ld,
+                     a.perm, a.k0, a.kb, a.n);
   const int t = (M + kTile - 1) / kTile;
   hipLaunchKernelGGL(k_gemm_update<F>, dim3(t, t), dim3(256), 0, s, S, a.ld, a.perm, a.k0, a.kb,
                      a.n);

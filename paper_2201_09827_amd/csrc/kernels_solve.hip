@@ -71,41 +71,73 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, 
                                                   const double* __restrict__ x,
                                                   double* __restrict__ r,
                                                   unsigned long long* norms) {
-  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int row0 = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  if (row >= n) return;
+  const bool rvalid = row0 < n;
+  const int row = rvalid ? row0 : n - 1;  // out-of-range waves recompute a valid row
   const double* a = A + (int64_t)row * ld;
-  double acc0 = 0.0, acc1 = 0.0;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   const int n2 = n & ~1;
   int c = lane * 2;
-  for (; c + 128 < n2; c += 256) {
-    const double2 x0 = *reinterpret_cast<const double2*>(a + c);
-    const double2 x1 = *reinterpret_cast<const double2*>(a + c + 128);
-    acc0 = fma(x0.x, x[c], acc0);
-    acc1 = fma(x0.y, x[c + 1], acc1);
-    acc0 = fma(x1.x, x[c + 128], acc0);
-    acc1 = fma(x1.y, x[c + 129], acc1);
+  for (; c + 384 < n2; c += 512) {
+    const double2 a0 = *reinterpret_cast<const double2*>(a + c);
+    const double2 a1 = *reinterpret_cast<const double2*>(a + c + 128);
+    const double2 a2 = *reinterpret_cast<const double2*>(a + c + 256);
+    const double2 a3 = *reinterpret_cast<const double2*>(a + c + 384);
+    const double2 x0 = *reinterpret_cast<const double2*>(x + c);
+    const double2 x1 = *reinterpret_cast<const double2*>(x + c + 128);
+    const double2 x2 = *reinterpret_cast<const double2*>(x + c + 256);
+    const double2 x3 = *reinterpret_cast<const double2*>(x + c + 384);
+    acc0 = fma(a0.x, x0.x, acc0);
+    acc1 = fma(a0.y, x0.y, acc1);
+    acc2 = fma(a1.x, x1.x, acc2);
+    acc3 = fma(a1.y, x1.y, acc3);
+    acc0 = fma(a2.x, x2.x, acc0);
+    acc1 = fma(a2.y, x2.y, acc1);
+    acc2 = fma(a3.x, x3.x, acc2);
+    acc3 = fma(a3.y, x3.y, acc3);
   }
   for (; c < n2; c += 128) {
-    const double2 x0 = *reinterpret_cast<const double2*>(a + c);
-    acc0 = fma(x0.x, x[c], acc0);
-    acc1 = fma(x0.y, x[c + 1], acc1);
+    const double2 a0 = *reinterpret_cast<const double2*>(a + c);
+    const double2 x0 = *reinterpret_cast<const double2*>(x + c);
+    acc0 = fma(a0.x, x0.x, acc0);
+    acc1 = fma(a0.y, x0.y, acc1);
   }
   for (int cc = n2 + lane; cc < n; cc += kWave) acc0 = fma(a[cc], x[cc], acc0);
+  acc0 += acc2;
+  acc1 += acc3;
   const double s = wave_sum(acc0 + acc1);
+  __shared__ double mr[4], mx[4];
+  const int wave = threadIdx.x / kWave;
   if (lane == 0) {
     const double ri = b[row] - s;
-    r[row] = ri;
-    atomic_max_nonneg(norms + 0, fabs(ri));
-    atomic_max_nonneg(norms + 1, fabs(x[row]));
+    if (rvalid) r[row] = ri;
+    mr[wave] = fabs(ri);
+    mx[wave] = fabs(x[row]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    const int nw = min(4, (n - blockIdx.x * 4));
+    for (int w = 0; w < nw; ++w) {
+      a = fmax(a, mr[w]);
+      c = fmax(c, mx[w]);
+    }
+    atomic_max_nonneg(norms + 0, a);
+    atomic_max_nonneg(norms + 1, c);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Triangular solves: one workgroup (4 waves) per block of 64 rows.  The
-// off-diagonal tiles of a block row are consumed as soon as the producing
-// block has published its solution (flag == epoch); the diagonal block is
-// solved by substitution in wave 0 with the running values held one per lane.
+// Triangular solves with the u_f factors in fp64 arithmetic.
+//
+// One workgroup (4 waves) per block of 64 rows.  The off-diagonal tiles of a
+// block row are consumed as soon as the producing block has published its
+// part of the solution (flag == epoch): wave w handles the tiles J = w mod 4,
+// each lane one row, with the tile prefetched before the wait.  The diagonal
+// block is applied through its fp64 inverse (formed once per factorisation),
+// so no dependent chain of 64 substitution steps sits on the critical path;
+// all four waves share that 64 x 64 product.
 // ---------------------------------------------------------------------------
 // 64 consecutive u_f values (16-byte aligned) widened to fp64
 template <class F>
@@ -140,79 +172,73 @@ __device__ __forceinline__ void load_row64(const typename F::T* p, double (&out)
   }
 }
 
+// A tile row of 64 u_f values kept as raw bits (32 registers for 16-bit
+// formats) and widened to fp64 when used.
 template <class F>
-__global__ __launch_bounds__(256) void k_trsv_lower(const typename F::T* __restrict__ S, int64_t ld,
-                                                    const int* __restrict__ permS, int n,
-                                                    const double* __restrict__ in,
-                                                    const int* __restrict__ permIn,
-                                                    double* y, int* flags, int epoch,
-                                                    const CycleState* gate, int step, int* abortp) {
-  if (gated_off(gate, step)) return;
-  __shared__ double red[4][kTB];
-  __shared__ int wok[4];
-  const int blk = blockIdx.x;
-  const int r0 = blk * kTB;
-  const int wave = threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  const int row = r0 + lane;
-  const bool valid = row < n;
-  const int prow = valid ? (permS ? permS[row] : row) : 0;
-  const typename F::T* srow = S + (int64_t)prow * ld;
-  double acc = 0.0;
-  bool ok = true;
-  for (int J = wave; J < blk && ok; J += 4) {
-    double lv[kTB];
-    if (valid) load_row64<F>(srow + (int64_t)J * kTB, lv);
-    else {
-#pragma unroll
-      for (int c = 0; c < kTB; ++c) lv[c] = 0.0;
-    }
-    if (lane == 0) ok = wait_eq(&flags[J], epoch, abortp);
-    ok = __shfl(ok ? 1 : 0, 0, kWave) != 0;
-    if (!ok) break;
-    const double yl = y[J * kTB + lane];
-#pragma unroll
-    for (int c = 0; c < kTB; ++c) acc = fma(lv[c], readlane_d(yl, c), acc);
-  }
-  red[wave][lane] = acc;
-  if (lane == 0) wok[wave] = ok ? 1 : 0;
-  __syncthreads();
-  if (!(wok[0] & wok[1] & wok[2] & wok[3])) return;
-  if (wave != 0) return;
-  double z = 0.0;
-  if (valid) {
-    const int src = permIn ? permIn[row] : row;
-    z = in[src] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
-  }
-  double lv[kTB];
-  if (valid) load_row64<F>(srow + r0, lv);
-  else {
-#pragma unroll
-    for (int c = 0; c < kTB; ++c) lv[c] = 0.0;
-  }
-#pragma unroll
-  for (int c = 0; c < kTB; ++c) {
-    const double yc = readlane_d(z, c);
-    if (lane > c) z = fma(-lv[c], yc, z);
-  }
-  if (valid) y[row] = z;
-  __threadfence();
-  if (lane == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
+struct RawRow {
+  static constexpr int kWords = kTB * (int)sizeof(typename F::T) / 4;
+  uint32_t w[kWords];
 
-template <class F>
-__global__ __launch_bounds__(256) void k_trsv_upper(const typename F::T* __restrict__ S, int64_t ld,
-                                                    const int* __restrict__ permS, int n,
-                                                    const double* __restrict__ yin, double* z,
-                                                    double scale, double* __restrict__ out64,
-                                                    float* __restrict__ out32, int* flags,
-                                                    int epoch, const CycleState* gate, int step,
-                                                    int* abortp) {
+  __device__ __forceinline__ void load(const typename F::T* srow, int cbase, int n, bool valid) {
+    if (valid && cbase + kTB <= n) {
+      const uint4* q = reinterpret_cast<const uint4*>(srow + cbase);
+#pragma unroll
+      for (int v = 0; v < kWords / 4; ++v) {
+        const uint4 x = q[v];
+        w[4 * v] = x.x;
+        w[4 * v + 1] = x.y;
+        w[4 * v + 2] = x.z;
+        w[4 * v + 3] = x.w;
+      }
+    } else {
+      using T = typename F::T;
+      constexpr int per = 4 / (int)sizeof(T);
+#pragma unroll
+      for (int i = 0; i < kWords; ++i) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int e = 0; e < per; ++e) {
+          const int c = cbase + i * per + e;
+          T v{};
+          if (valid && c < n) v = srow[c];
+          uint32_t bits = 0;
+          __builtin_memcpy(&bits, &v, sizeof(T));
+          word |= bits << (8 * sizeof(T) * e);
+        }
+        w[i] = word;
+      }
+    }
+  }
+
+  __device__ __forceinline__ double at(int c) const {
+    using T = typename F::T;
+    T v;
+    if constexpr (sizeof(T) == 2) {
+      const uint16_t b = (uint16_t)(w[c >> 1] >> (16 * (c & 1)));
+      __builtin_memcpy(&v, &b, 2);
+    } else {
+      __builtin_memcpy(&v, &w[c], 4);
+    }
+    return (double)F::to_f(v);
+  }
+};
+
+template <class F, bool kUpper>
+__global__ __launch_bounds__(256) void k_trsv(const typename F::T* __restrict__ S, int64_t ld,
+                                              const int* __restrict__ permS, int n,
+                                              const double* __restrict__ in,
+                                              const int* __restrict__ permIn,
+                                              const double* __restrict__ Dinv, double* y,
+                                              double scale, double* __restrict__ out64,
+                                              float* __restrict__ out32, int* flags, int epoch,
+                                              const CycleState* gate, int step, int* abortp) {
   if (gated_off(gate, step)) return;
   __shared__ double red[4][kTB];
+  __shared__ double ysh[4][kTB];
+  __shared__ double zsh[kTB];
   __shared__ int wok[4];
   const int nblk = (n + kTB - 1) / kTB;
-  const int blk = nblk - 1 - blockIdx.x;  // last block first
+  const int blk = kUpper ? nblk - 1 - (int)blockIdx.x : (int)blockIdx.x;
   const int r0 = blk * kTB;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -220,51 +246,101 @@ __global__ __launch_bounds__(256) void k_trsv_upper(const typename F::T* __restr
   const bool valid = row < n;
   const int prow = valid ? (permS ? permS[row] : row) : 0;
   const typename F::T* srow = S + (int64_t)prow * ld;
-  double acc = 0.0;
-  bool ok = true;
-  for (int J = nblk - 1 - wave; J > blk && ok; J -= 4) {
-    double lv[kTB];
-    const int cbase = J * kTB;
-    if (valid && cbase + kTB <= n) {
-      load_row64<F>(srow + cbase, lv);
-    } else {
+  // this thread's quarter of its row of the inverse diagonal block
+  double dq[kTB / 4];
+  {
+    const double* drow = Dinv + ((int64_t)blk * kTB + lane) * kTB + wave * (kTB / 4);
 #pragma unroll
-      for (int c = 0; c < kTB; ++c)
-        lv[c] = (valid && cbase + c < n) ? (double)F::to_f(srow[cbase + c]) : 0.0;
+    for (int c = 0; c < kTB / 4; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(drow + c);
+      dq[c] = v.x;
+      dq[c + 1] = v.y;
     }
+  }
+  double rhs = 0.0;
+  if (valid) rhs = in[permIn ? permIn[row] : row];
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  bool ok = true;
+  const int first = kUpper ? nblk - 1 - wave : wave;
+  for (int J = first; kUpper ? (J > blk) : (J < blk); J += kUpper ? -4 : 4) {
+    RawRow<F> lv;
+    lv.load(srow, J * kTB, n, valid);
     if (lane == 0) ok = wait_eq(&flags[J], epoch, abortp);
     ok = __shfl(ok ? 1 : 0, 0, kWave) != 0;
     if (!ok) break;
-    const double yl = (cbase + lane < n) ? z[cbase + lane] : 0.0;
+    ysh[wave][lane] = (J * kTB + lane < n) ? y[J * kTB + lane] : 0.0;
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int c = 0; c < kTB; ++c) acc = fma(lv[c], readlane_d(yl, c), acc);
+    for (int c = 0; c < kTB; c += 4) {
+      acc0 = fma(lv.at(c), ysh[wave][c], acc0);
+      acc1 = fma(lv.at(c + 1), ysh[wave][c + 1], acc1);
+      acc2 = fma(lv.at(c + 2), ysh[wave][c + 2], acc2);
+      acc3 = fma(lv.at(c + 3), ysh[wave][c + 3], acc3);
+    }
+    __builtin_amdgcn_wave_barrier();
   }
-  red[wave][lane] = acc;
+  red[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
   if (lane == 0) wok[wave] = ok ? 1 : 0;
   __syncthreads();
   if (!(wok[0] & wok[1] & wok[2] & wok[3])) return;
+  if (wave == 0)
+    zsh[lane] = valid ? rhs - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) : 0.0;
+  __syncthreads();
+  double part = 0.0;
+#pragma unroll
+  for (int c = 0; c < kTB / 4; ++c) part = fma(dq[c], zsh[wave * (kTB / 4) + c], part);
+  red[wave][lane] = part;
+  __syncthreads();
   if (wave != 0) return;
-  double v = 0.0;
-  if (valid) v = yin[row] - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
-  double lv[kTB];
-#pragma unroll
-  for (int c = 0; c < kTB; ++c)
-    lv[c] = (valid && r0 + c < n) ? (double)F::to_f(srow[r0 + c]) : 1.0;
-  const double diag = valid ? (double)F::to_f(srow[row]) : 1.0;
-#pragma unroll
-  for (int c = kTB - 1; c >= 0; --c) {
-    if (lane == c) v = v / diag;
-    const double yc = readlane_d(v, c);
-    if (lane < c) v = fma(-lv[c], yc, v);
-  }
+  const double v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
   if (valid) {
-    z[row] = v;
-    const double o = v * scale;
-    if (out64) out64[row] = o;
-    if (out32) out32[row] = (float)o;
+    y[row] = v;
+    if (out64) out64[row] = v * scale;
+    if (out32) out32[row] = (float)(v * scale);
   }
-  __threadfence();
-  if (lane == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (lane == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inverse of each 64 x 64 diagonal block of L (unit lower) or U (upper) in
+// fp64, row-major per block; rows/columns beyond n get the identity.
+template <class F, bool kUpper>
+__global__ __launch_bounds__(64) void k_diag_inverse(const typename F::T* __restrict__ S, int64_t ld,
+                                                     const int* __restrict__ permS, int n,
+                                                     double* __restrict__ Dinv) {
+  __shared__ double B[kTB][kTB + 1];
+  __shared__ double X[kTB][kTB + 1];
+  const int blk = blockIdx.x;
+  const int r0 = blk * kTB;
+  const int j = threadIdx.x;  // column of the inverse
+  for (int r = 0; r < kTB; ++r) {
+    const int row = r0 + r;
+    double v = (r == j) ? 1.0 : 0.0;
+    if (row < n && r0 + j < n) {
+      const int prow = permS ? permS[row] : row;
+      v = (double)F::to_f(S[(int64_t)prow * ld + r0 + j]);
+      if (!kUpper && r == j) v = 1.0;
+    }
+    B[r][j] = v;
+  }
+  __syncthreads();
+  if (!kUpper) {
+    for (int r = 0; r < kTB; ++r) {
+      double v = (r == j) ? 1.0 : 0.0;
+      for (int t = 0; t < r; ++t) v = fma(-B[r][t], X[t][j], v);
+      X[r][j] = v;
+    }
+  } else {
+    for (int r = kTB - 1; r >= 0; --r) {
+      double v = (r == j) ? 1.0 : 0.0;
+      for (int t = r + 1; t < kTB; ++t) v = fma(-B[r][t], X[t][j], v);
+      X[r][j] = v / B[r][r];
+    }
+  }
+  for (int r = 0; r < kTB; ++r) {
+    const bool lowerpart = kUpper ? (j >= r) : (j <= r);
+    Dinv[((int64_t)blk * kTB + r) * kTB + j] = lowerpart ? X[r][j] : 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -541,41 +617,68 @@ void launch_residual(const double* A, int64_t ld, int n, const double* b, const 
   hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 4)), dim3(256), 0, s, A, ld, n, b, x, r, norms);
 }
 
-void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
-                       const double* in, const int* permIn, double* y, int* flags, int epoch,
-                       const CycleState* gate, int step, int* abortp, hipStream_t s) {
+template <class F>
+void trsv_pair(const void* S, int64_t ld, const int* permS, int n, bool upper, const double* in,
+               const int* permIn, const double* Dinv, double* y, double scale, double* out64,
+               float* out32, int* flags, int epoch, const CycleState* gate, int step, int* abortp,
+               hipStream_t s) {
+  using T = typename F::T;
   const unsigned grid = nblocks(n, kTB);
-  if (store == kStoreF16)
-    hipLaunchKernelGGL(k_trsv_lower<Fp16>, dim3(grid), dim3(256), 0, s,
-                       reinterpret_cast<const _Float16*>(S), ld, permS, n, in, permIn, y, flags,
-                       epoch, gate, step, abortp);
-  else if (store == kStoreBF16)
-    hipLaunchKernelGGL(k_trsv_lower<Bf16>, dim3(grid), dim3(256), 0, s,
-                       reinterpret_cast<const uint16_t*>(S), ld, permS, n, in, permIn, y, flags,
-                       epoch, gate, step, abortp);
+  const T* Sp = reinterpret_cast<const T*>(S);
+  if (upper)
+    hipLaunchKernelGGL((k_trsv<F, true>), dim3(grid), dim3(256), 0, s, Sp, ld, permS, n, in,
+                       permIn, Dinv, y, scale, out64, out32, flags, epoch, gate, step, abortp);
   else
-    hipLaunchKernelGGL(k_trsv_lower<Fp32>, dim3(grid), dim3(256), 0, s,
-                       reinterpret_cast<const float*>(S), ld, permS, n, in, permIn, y, flags,
-                       epoch, gate, step, abortp);
+    hipLaunchKernelGGL((k_trsv<F, false>), dim3(grid), dim3(256), 0, s, Sp, ld, permS, n, in,
+                       permIn, Dinv, y, 1.0, nullptr, nullptr, flags, epoch, gate, step, abortp);
+}
+
+void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
+                       const double* in, const int* permIn, const double* Linv, double* y,
+                       int* flags, int epoch, const CycleState* gate, int step, int* abortp,
+                       hipStream_t s) {
+  if (store == kStoreF16)
+    trsv_pair<Fp16>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, flags,
+                    epoch, gate, step, abortp, s);
+  else if (store == kStoreBF16)
+    trsv_pair<Bf16>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, flags,
+                    epoch, gate, step, abortp, s);
+  else
+    trsv_pair<Fp32>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, flags,
+                    epoch, gate, step, abortp, s);
 }
 
 void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
-                       const double* y, double* z, double scale, double* out64, float* out32,
-                       int* flags, int epoch, const CycleState* gate, int step, int* abortp,
-                       hipStream_t s) {
-  const unsigned grid = nblocks(n, kTB);
+                       const double* yin, const double* Uinv, double* z, double scale,
+                       double* out64, float* out32, int* flags, int epoch, const CycleState* gate,
+                       int step, int* abortp, hipStream_t s) {
   if (store == kStoreF16)
-    hipLaunchKernelGGL(k_trsv_upper<Fp16>, dim3(grid), dim3(256), 0, s,
-                       reinterpret_cast<const _Float16*>(S), ld, permS, n, y, z, scale, out64,
-                       out32, flags, epoch, gate, step, abortp);
+    trsv_pair<Fp16>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, flags,
+                    epoch, gate, step, abortp, s);
   else if (store == kStoreBF16)
-    hipLaunchKernelGGL(k_trsv_upper<Bf16>, dim3(grid), dim3(256), 0, s,
-                       reinterpret_cast<const uint16_t*>(S), ld, permS, n, y, z, scale, out64,
-                       out32, flags, epoch, gate, step, abortp);
+    trsv_pair<Bf16>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, flags,
+                    epoch, gate, step, abortp, s);
   else
-    hipLaunchKernelGGL(k_trsv_upper<Fp32>, dim3(grid), dim3(256), 0, s,
-                       reinterpret_cast<const float*>(S), ld, permS, n, y, z, scale, out64, out32,
-                       flags, epoch, gate, step, abortp);
+    trsv_pair<Fp32>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, flags,
+                    epoch, gate, step, abortp, s);
+}
+
+void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,
+                          double* Linv, double* Uinv, hipStream_t s) {
+  const unsigned grid = nblocks(n, kTB);
+#define GIR_DINV(F)                                                                          \
+  hipLaunchKernelGGL((k_diag_inverse<F, false>), dim3(grid), dim3(kTB), 0, s,                \
+                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, Linv);         \
+  hipLaunchKernelGGL((k_diag_inverse<F, true>), dim3(grid), dim3(kTB), 0, s,                 \
+                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, Uinv)
+  if (store == kStoreF16) {
+    GIR_DINV(Fp16);
+  } else if (store == kStoreBF16) {
+    GIR_DINV(Bf16);
+  } else {
+    GIR_DINV(Fp32);
+  }
+#undef GIR_DINV
 }
 
 void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s) {

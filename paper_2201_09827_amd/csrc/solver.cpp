@@ -122,6 +122,7 @@ struct gmresir_ctx {
   int* permP = nullptr;   // logical -> row of A (P)
   int* permS = nullptr;   // equals perm after gmresir_factor, null after import
   int* ipiv = nullptr;
+  double *Linv = nullptr, *Uinv = nullptr;  // inverses of the diagonal blocks
   // LU scratch
   float* P = nullptr;
   int *ptmp = nullptr, *pstep = nullptr, *piv_prow = nullptr, *lidx = nullptr, *sync = nullptr;
@@ -148,7 +149,7 @@ struct gmresir_ctx {
 
   ~gmresir_ctx() {
     // permP and permS alias perm
-    void* bufs[] = {A64, Au, S, perm, ipiv, P, ptmp, pstep, piv_prow, lidx, sync,
+    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, P, ptmp, pstep, piv_prow, lidx, sync,
                     x, b, r64, t64, y64, z64, z32, w32, d32, r32, V, C, U, Cn, Un, Hd, Bd, cs,
                     sn, g, h1, h2, nrm, coefA, coefB, Mdev, Gdev, partial, counter, norms, st,
                     flagsL, flagsU};
@@ -265,6 +266,9 @@ int alloc_common(gmresir_ctx* h) {
   GIR_TRY(dalloc(reinterpret_cast<char**>(&h->S), n * ld * store_bytes(h->store)));
   GIR_TRY(dalloc(&h->perm, n));
   GIR_TRY(dalloc(&h->ipiv, n));
+  const size_t nblk = (n + 63) / 64;
+  GIR_TRY(dalloc(&h->Linv, nblk * 64 * 64));
+  GIR_TRY(dalloc(&h->Uinv, nblk * 64 * 64));
   GIR_TRY(dalloc(&h->st, 1));
   GIR_TRY(dalloc(&h->counter, 4));
   GIR_TRY(dalloc(&h->norms, 4));
@@ -349,7 +353,7 @@ int run_lu(gmresir_ctx* h) {
     a.k0 = k0;
     a.kb = std::min(kNb, n - k0);
     const int hrows = n - k0;
-    const int nhelpers = std::min(127, std::max(1, (hrows + 63) / 64));
+    const int nhelpers = std::min(128, std::max(1, (hrows + 63) / 64));
     gir::launch_panel_step(a, h->store, nhelpers, h->stream);
     gir::launch_trsm_update(a, h->store, h->stream);
   }
@@ -357,6 +361,7 @@ int run_lu(gmresir_ctx* h) {
   int* flag = reinterpret_cast<int*>(h->counter + 2);
   GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
   gir::launch_check_factors(h->S, n, h->ld, h->store, flag, h->stream);
+  gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->stream);
   gir::CycleState hs{};
   int hflag = 0;
   GIR_TRY(download(h, &hs, h->st, sizeof(hs)));
@@ -391,8 +396,8 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
   }
   *out = nullptr;
   GIR_TRY(validate_opts(opts));
-  if (!A || n <= 0 || lda < n || n > (1 << 30)) {
-    set_error("invalid A, n or lda");
+  if (!A || n <= 0 || lda < n || n > 16384) {
+    set_error("invalid A, n (1..16384) or lda");
     return GMRESIR_EINVAL;
   }
   gmresir_ctx* h = new (std::nothrow) gmresir_ctx();
@@ -421,10 +426,11 @@ int next_epoch(gmresir_ctx* h) {
 int precond(gmresir_ctx* h, const double* in, const int* permIn, double* out64, float* out32,
             const gir::CycleState* gate, int step) {
   const int n = (int)h->n;
-  gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->y64, h->flagsL,
-                         next_epoch(h), gate, step, &h->st->abort, h->stream);
-  gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->z64, h->scale, out64,
-                         out32, h->flagsU, next_epoch(h), gate, step, &h->st->abort, h->stream);
+  gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->Linv, h->y64,
+                         h->flagsL, next_epoch(h), gate, step, &h->st->abort, h->stream);
+  gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->Uinv, h->z64, h->scale,
+                         out64, out32, h->flagsU, next_epoch(h), gate, step, &h->st->abort,
+                         h->stream);
   return 0;
 }
 
@@ -915,6 +921,11 @@ int gmresir_import_factors(const double* A, int64_t n, int64_t lda, const void* 
     if (rc == 0) rc = upload(h, h->ipiv, ipiv, sizeof(int) * n);
     h->permP = h->perm;
     h->permS = nullptr;
+    if (rc == 0) {
+      gir::launch_diag_inverses(h->S, h->ld, nullptr, h->store, (int)n, h->Linv, h->Uinv,
+                                h->stream);
+      if (hipGetLastError() != hipSuccess) rc = GMRESIR_EHIP;
+    }
   }
   if (rc == 0) rc = alloc_solve(h);
   if (rc == 0 && hipStreamSynchronize(h->stream) != hipSuccess) rc = GMRESIR_EHIP;

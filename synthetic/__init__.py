@@ -36,6 +36,7 @@ __all__ = [
     "Problem",
     "randsvd_problem",
     "prolate_problem",
+    "randsvd_problem_torch",
 ]
 
 
@@ -137,3 +138,32 @@ def prolate_problem(n: int, w: float, seed: int | None = None) -> Problem:
     x = normal_vector(n, g)
     return Problem(f"prolate(n={n},w={w:g},seed={seed})", a, x,
                    rhs_from_solution(a, x))
+
+
+def randsvd_problem_torch(n: int, kappa: float, seed: int, device="cuda"):
+    """randsvd mode-3 system drawn with torch on ``device`` (same recipe as
+    :func:`randsvd_problem`: Haar U then V from the QR of Gaussian matrices
+    with R's diagonal signs moved into Q, geometric singular values,
+    x_true ~ U(-1, 1), b = A x_true in float64).  A different random stream
+    from the numpy version; used where generating n ~ 1e4 on the CPU would
+    dominate the run.  Returns float64 tensors (a, x_true, b) on ``device``.
+    """
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+
+    def haar():
+        z = torch.randn((n, n), generator=gen, dtype=torch.float64, device=device)
+        q, r = torch.linalg.qr(z)
+        s = torch.sign(torch.diagonal(r))
+        s[s == 0] = 1.0
+        return q * s[None, :]
+
+    u = haar()
+    v = haar()
+    sigma = torch.from_numpy(randsvd_singular_values(n, kappa)).to(device)
+    a = (u * sigma[None, :]) @ v.T.contiguous()
+    del u, v
+    x = torch.rand(n, generator=gen, dtype=torch.float64, device=device) * 2.0 - 1.0
+    b = a @ x
+    return a.contiguous(), x, b
