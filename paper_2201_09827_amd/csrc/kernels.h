@@ -28,19 +28,15 @@ struct PanelArgs {
   int n;
   int k0;           // first column of the panel
   int kb;           // panel width (<= nb)
-  int* perm;        // logical -> physical rows
-  int* ptmp;        // [n] scratch: new order of logical rows k0..n-1
-  float* P;         // panel work buffer, column-major, ldp
-  int ldp;
-  int* pstep;       // [n]
-  int* piv_prow;    // [nb]
-  int* lidx;        // [n]
+  int* perm;        // logical -> physical rows, rewritten for rows k0.. by the panel
   int* ipiv;        // [n] LAPACK-style (0-based)
-  int* sync;        // [2] zeroed before the panel kernel
+  uint64_t* xch;    // [kPanelXchWords] pivot exchange, zeroed before the first panel
   CycleState* st;   // abort + singular reporting
 };
+// words of the exchange buffer: 2 column parities x 32 workgroups x 80 words
+constexpr int64_t kPanelXchWords = 2 * 32 * 80;
 // one block column of the blocked right-looking GEPP (lazy row interchanges)
-void launch_panel_step(const PanelArgs& a, int store, int nhelpers, hipStream_t s);
+void launch_panel_step(const PanelArgs& a, int store, hipStream_t s);
 // the block row to the right of the panel and the trailing update
 void launch_trsm_update(const PanelArgs& a, int store, hipStream_t s);
 // after the last panel: non-finite check of the factors

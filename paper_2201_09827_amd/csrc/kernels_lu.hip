@@ -14,25 +14,15 @@
 // with u_f inputs on the matrix cores with fp32 accumulation and rounded to
 // u_f once per block column.
 //
-// Block column = one persistent kernel: workgroup 0 (the leader) holds the
-// unfactored rows of W columns in registers and performs the pivot searches
-// (one workgroup barrier per column); the other workgroups apply the rank-W
-// updates to the rest of the block column.  They synchronise through two
-// device-scope counters with bounded waits.
+// Block column = one kernel: every thread keeps one row of the block column
+// in registers while the workgroups agree on each pivot through tagged words
+// in a small exchange buffer (one record per workgroup and column parity).
 #include "kernels.h"
-
-// Phase hooks of the block-column kernel; empty unless a timing harness
-// defines them before including this file.
-#ifndef GIR_PANEL_MARK
-#define GIR_PANEL_MARK(tag)
-#define GIR_PANEL_MARK_INIT
-#endif
 
 namespace gir {
 
 namespace {
 
-constexpr int kPanelThreads = 512;
 constexpr int kMaxNb = 64;
 
 __device__ __forceinline__ double wave_max_d(double v) {
@@ -102,308 +92,256 @@ __global__ void k_fill_i32(int* p, int v, int64_t n) {
     p[i] = v;
 }
 
-// P[c][q] = S[perm[k0 + q]][k0 + c]  (column-major fp32 panel)
-template <class F>
-__global__ void k_panel_gather(const typename F::T* __restrict__ S, int64_t ld,
-                               const int* __restrict__ perm, int k0, int kb, int h,
-                               float* __restrict__ P, int ldp, int* pstep, int* sync) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < 2) sync[threadIdx.x] = 0;
-  if (q >= h) return;
-  const typename F::T* row = S + (int64_t)perm[k0 + q] * ld + k0;
-  for (int c = 0; c < kb; ++c) P[(int64_t)c * ldp + q] = F::to_f(row[c]);
-  pstep[q] = -1;
+// ---- block column: one pivot search per column across workgroups -----------
+//
+// G = ceil(h / 512) workgroups; thread t of workgroup g owns logical row
+// q = 512 g + t of the block column and keeps all of its (at most 64) values in
+// registers from the gather to the write-back.  Per column c:
+//   1. every unpivoted row forms the key (|a_qc| bits, inverted logical index),
+//      so that the maximum key is LAPACK's pivot: largest magnitude, first
+//      logical row among equals;
+//   2. the workgroup maximum is found with DPP reductions and one LDS pass,
+//      and the owner of that key copies its row to LDS;
+//   3. with G > 1, wave 0 publishes the key and the row as 64-bit words whose
+//      upper half carries the column's tag (k0 + c + 1), reads the G keys,
+//      picks the winner and reads its row.  A word is valid once its tag
+//      matches, so no fences or flags are needed; records alternate between
+//      two slots by column parity (a workgroup can be at most one column
+//      ahead of any other);
+//   4. every row eliminates column c with the correctly rounded quotient and
+//      one fused multiply-add per remaining column, in the order of the
+//      unblocked algorithm.
+// Row interchanges stay lazy: lid tracks each row's logical position, and the
+// permutation is rewritten once at the end.
+constexpr int kRowThreads = 512;
+constexpr int kRowWaves = kRowThreads / kWave;
+constexpr int kRecWords = 80;  // 64 row words + key word, padded to 640 bytes
+
+__device__ __forceinline__ uint64_t xch_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-struct Cand {
-  float val;
-  int lidx;
-  int prow;
-  int pad;
-  float row[kMaxNb];
-};
+__device__ __forceinline__ void xch_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
-template <int R, int W>
-__device__ __forceinline__ void panel_leader(float* __restrict__ P, int ldp, int h, int kb, int k0,
-                             int* __restrict__ pstep, int* __restrict__ piv_prow,
-                             int* __restrict__ lidx_out, int* __restrict__ ipiv, int* sync,
-                             CycleState* st, int nhelpers) {
-  __shared__ Cand cand[2][kPanelThreads / kWave];
-  __shared__ float Lblk[W][W];
-  __shared__ int blk_prow[W];
+// Wave-uniform poll: returns once every lane with `need` has read a word whose
+// bits above `shift` equal `tag`; false on abort or when the bound is hit.
+__device__ __forceinline__ bool poll_tagged(const uint64_t* p, bool need, uint32_t tag, int shift,
+                                            uint64_t& v, int* abortp) {
+  long long spins = 0;
+  for (;;) {
+    if (need) v = xch_load(p);
+    const bool ok = !need || (uint32_t)(v >> shift) == tag;
+    if (__all(ok)) return true;
+    __builtin_amdgcn_s_sleep(1);
+    if (((++spins) & 1023) == 0) {
+      if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if (spins > (1ll << 22)) {
+        __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void load_panel_row(const typename F::T* src, int kb, bool in,
+                                               float (&x)[kMaxNb]) {
+  using T = typename F::T;
+  constexpr int kPer = 16 / sizeof(T);
+  if (in && kb == kMaxNb) {
+#pragma unroll
+    for (int v = 0; v < kMaxNb / kPer; ++v) {
+      const uint4 w = reinterpret_cast<const uint4*>(src)[v];
+      T t[kPer];
+      __builtin_memcpy(t, &w, 16);
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) x[v * kPer + e] = F::to_f(t[e]);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kMaxNb; ++c) x[c] = (in && c < kb) ? F::to_f(src[c]) : 0.0f;
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void store_panel_row(typename F::T* dst, int kb,
+                                                const float (&x)[kMaxNb]) {
+  using T = typename F::T;
+  constexpr int kPer = 16 / sizeof(T);
+  if (kb == kMaxNb) {
+#pragma unroll
+    for (int v = 0; v < kMaxNb / kPer; ++v) {
+      T t[kPer];
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) t[e] = F::from_f(x[v * kPer + e]);
+      uint4 w;
+      __builtin_memcpy(&w, t, 16);
+      reinterpret_cast<uint4*>(dst)[v] = w;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kMaxNb; ++c)
+      if (c < kb) dst[c] = F::from_f(x[c]);
+  }
+}
+
+// elimination of column C for one row: x_C <- l, x_j <- fma(-l, u_j, x_j) for
+// j > C; returns the row's value in column C + 1 (the next pivot search)
+template <int C>
+__device__ __forceinline__ float eliminate_col(float (&x)[kMaxNb], float l, const float* u,
+                                               bool upd) {
+  if (upd) {
+    x[C] = l;
+#pragma unroll
+    for (int j = C + 1; j < kMaxNb; ++j) x[j] = __builtin_fmaf(-l, u[j], x[j]);
+  }
+  return x[C + 1 < kMaxNb ? C + 1 : C];
+}
+
+template <class F>
+__global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __restrict__ S,
+                                                            int64_t ld, int* __restrict__ perm,
+                                                            int k0, int kb, int h,
+                                                            int* __restrict__ ipiv,
+                                                            uint64_t* __restrict__ xch,
+                                                            CycleState* st) {
+  using T = typename F::T;
+  __shared__ uint64_t kw[kRowWaves];
+  __shared__ __align__(16) float rowbuf[kMaxNb];
+  __shared__ __align__(16) float ush[kMaxNb];
+  __shared__ uint64_t s_win;
   __shared__ int s_abort;
   const int tid = threadIdx.x;
-  const int wave = tid / kWave;
   const int lane = tid % kWave;
+  const int wave = tid / kWave;
+  const int G = gridDim.x;
+  const int g = blockIdx.x;
+  const int q = g * kRowThreads + tid;
+  const bool in = q < h;
   int* abortp = &st->abort;
 
-  int lid[R];
-  bool pv[R];
-  float x[R][W];
+  const int phys = in ? perm[k0 + q] : 0;
+  T* row = S + (int64_t)phys * ld + k0;
+  float x[kMaxNb];
+  load_panel_row<F>(row, kb, in, x);
+  // materialise the fp32 values now (keeps the compiler from carrying the
+  // narrow inputs and converting them at every later use)
 #pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int q = tid + kPanelThreads * s;
-    lid[s] = q;
-    pv[s] = (q >= h);
-  }
+  for (int c = 0; c < kMaxNb; ++c) asm volatile("" : "+v"(x[c]));
+  int lid = q;
+  bool pv = !in;  // pivoted (or absent) rows take no further part
+  float xc = x[0];
   if (tid == 0) s_abort = 0;
-  __syncthreads();
-  GIR_PANEL_MARK_INIT
 
-  const int nblk = (kb + W - 1) / W;
-  for (int ib = 0; ib < nblk; ++ib) {
-    const int c0 = ib * W;
-    const int wcols = min(W, kb - c0);
-    GIR_PANEL_MARK(0);
-    if (ib > 0) {
-      if (lane == 0) {
-        if (!wait_geq(&sync[1], ib * nhelpers, abortp)) s_abort = 1;
+  for (int c = 0; c < kb; ++c) {
+    const uint32_t tag = (uint32_t)(k0 + c + 1);
+    const float ac = fabsf(xc);
+    const uint32_t ab = (ac == ac) ? __float_as_uint(ac) : 0u;  // NaN ranks as zero
+    const uint64_t mykey =
+        pv ? 0ull : (((uint64_t)ab << 17) | (uint64_t)(0x1FFFFu - (uint32_t)lid));
+    const uint64_t wmax = wave_max_u64(mykey);
+    if (lane == 0) kw[wave] = wmax;
+    __syncthreads();
+    uint64_t K = kw[0];
+#pragma unroll
+    for (int w = 1; w < kRowWaves; ++w) K = kw[w] > K ? kw[w] : K;
+    if (!pv && mykey == K) {
+#pragma unroll
+      for (int j = 0; j < kMaxNb; j += 4)
+        *reinterpret_cast<float4*>(&rowbuf[j]) = make_float4(x[j], x[j + 1], x[j + 2], x[j + 3]);
+    }
+    __syncthreads();
+    uint64_t W = K;
+    const float* u = rowbuf;
+    if (G > 1) {
+      if (wave == 0) {
+        uint64_t* base = xch + (size_t)(c & 1) * G * kRecWords;
+        uint64_t* mine = base + (size_t)g * kRecWords;
+        if (lane >= c) xch_store(mine + lane, ((uint64_t)tag << 32) | __float_as_uint(rowbuf[lane]));
+        if (lane == 0) xch_store(mine + kMaxNb, ((uint64_t)tag << 48) | K);
+        uint64_t kk = 0;
+        bool ok = poll_tagged(base + (size_t)(lane < G ? lane : 0) * kRecWords + kMaxNb, lane < G,
+                              tag, 48, kk, abortp);
+        uint64_t wk = 0;
+        if (ok) {
+          const uint64_t kv = (lane < G) ? (kk & 0xFFFFFFFFFFFFull) : 0ull;
+          wk = wave_max_u64(kv);
+          const unsigned long long bal = __ballot(lane < G && kv == wk);
+          const int gw = (int)__builtin_ctzll(bal);
+          uint64_t rv = 0;
+          ok = poll_tagged(base + (size_t)gw * kRecWords + lane, lane >= c, tag, 32, rv, abortp);
+          if (lane >= c) ush[lane] = __uint_as_float((uint32_t)rv);
+        }
+        if (lane == 0) {
+          s_win = wk;
+          if (!ok) s_abort = 1;
+        }
       }
       __syncthreads();
       if (s_abort) return;
+      W = s_win;
+      u = ush;
     }
-    GIR_PANEL_MARK(1);
-    bool pvb[R];
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      pvb[s] = pv[s];
-      const int q = tid + kPanelThreads * s;
-#pragma unroll
-      for (int c = 0; c < W; ++c)
-        x[s][c] = (!pv[s] && c < wcols) ? P[(int64_t)(c0 + c) * ldp + q] : 0.0f;
+    const int wl = (int)(0x1FFFFu - (uint32_t)(W & 0x1FFFFull));
+    const float piv = u[c];
+    if (g == 0 && tid == 0) {
+      ipiv[k0 + c] = k0 + wl;
+      if (piv == 0.0f) atomicCAS(&st->singular, 0, k0 + c + 1);
     }
-    GIR_PANEL_MARK(2);
-
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-      if (c < wcols) {
-        const int cc = c0 + c;
-        float bv = -1.0f;
-        int bl = 0x7fffffff;
-        int bs = -1;
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-          const float a = pv[s] ? -1.0f : fabsf(x[s][c]);
-          const bool better = a > bv || (a == bv && lid[s] < bl);
-          bv = better ? a : bv;
-          bl = better ? lid[s] : bl;
-          bs = better ? s : bs;
-        }
-        if (bv < 0.0f) bs = -1;
-        float wv = bv;
-        int wl = bl;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const float ov = __shfl_xor(wv, o, kWave);
-          const int ol = __shfl_xor(wl, o, kWave);
-          if (ov > wv || (ov == wv && ol < wl)) {
-            wv = ov;
-            wl = ol;
-          }
-        }
-        GIR_PANEL_MARK(10 + c);
-        Cand* cb = &cand[c & 1][wave];
-        if (bs >= 0 && bl == wl && bv == wv) {
-          cb->val = bv;
-          cb->lidx = bl;
-          cb->prow = tid + kPanelThreads * bs;
-#pragma unroll
-          for (int s = 0; s < R; ++s) {
-            if (s == bs) {
-#pragma unroll
-              for (int c2 = 0; c2 < W; ++c2) cb->row[c2] = x[s][c2];
-            }
-          }
-        }
-        if (wv < 0.0f && lane == 0) {
-          cb->val = -1.0f;
-          cb->lidx = 0x7fffffff;
-          cb->prow = -1;
-        }
-        __syncthreads();
-        GIR_PANEL_MARK(20 + c);
-        float gv = -1.0f;
-        int gl = 0x7fffffff;
-        int gw = 0;
-#pragma unroll
-        for (int w2 = 0; w2 < kPanelThreads / kWave; ++w2) {
-          const float v = cand[c & 1][w2].val;
-          const int l = cand[c & 1][w2].lidx;
-          if (v > gv || (v == gv && l < gl)) {
-            gv = v;
-            gl = l;
-            gw = w2;
-          }
-        }
-        const Cand* win = &cand[c & 1][gw];
-        const int p = win->prow;
-        const float* u = win->row;  // pivot row, read from LDS (broadcast)
-        const float piv = u[c];
-        if (tid == 0) {
-          ipiv[k0 + cc] = k0 + gl;
-          piv_prow[cc] = p;
-          blk_prow[c] = p;
-          if (piv == 0.0f) atomicCAS(&st->singular, 0, k0 + cc + 1);
-        }
-        if (tid < W) Lblk[c][tid] = u[tid];
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-          const int q = tid + kPanelThreads * s;
-          lid[s] = (!pv[s] && lid[s] == cc) ? gl : lid[s];
-          lid[s] = (q == p) ? cc : lid[s];
-          pv[s] = pv[s] || (q == p);
-        }
-        if (piv != 0.0f) {
-          // multipliers fl32(a / piv): reciprocal, product and one fused
-          // correction give the correctly rounded quotient (Markstein); a
-          // quotient in the subnormal range falls back to the division
-          const float rinv = 1.0f / piv;
-          const bool rok = __builtin_isfinite(rinv);
-          float ucol[W];
-#pragma unroll
-          for (int c2 = c + 1; c2 < W; ++c2) ucol[c2] = u[c2];
-#pragma unroll
-          for (int s = 0; s < R; ++s) {
-            const float a = x[s][c];
-            float l;
-            if (rok) {
-              const float q0 = a * rinv;
-              const float e = __builtin_fmaf(-q0, piv, a);
-              l = __builtin_fmaf(e, rinv, q0);
-              if (__builtin_expect(fabsf(l) < 0x1p-100f, 0) && a != 0.0f) l = a / piv;
-            } else {
-              l = a / piv;
-            }
-            const bool upd = !pv[s];
-            x[s][c] = upd ? l : a;
-#pragma unroll
-            for (int c2 = c + 1; c2 < W; ++c2)
-              x[s][c2] = upd ? __builtin_fmaf(-l, ucol[c2], x[s][c2]) : x[s][c2];
-          }
-        }
+    const bool me = !pv && lid == wl;
+    if (!pv && lid == c) lid = wl;
+    if (me) {
+      lid = c;
+      pv = true;
+    }
+    const bool upd = !pv && piv != 0.0f;
+    float l = 0.0f;
+    if (upd) {
+      // fl32(a / piv) from the reciprocal, the product and one fused
+      // correction (Markstein); quotients near the subnormal range and an
+      // infinite reciprocal fall back to the division
+      const float a = xc;
+      const float rinv = 1.0f / piv;
+      if (__builtin_isfinite(rinv)) {
+        const float q0 = a * rinv;
+        const float e = __builtin_fmaf(-q0, piv, a);
+        l = __builtin_fmaf(e, rinv, q0);
+        if (__builtin_expect(fabsf(l) < 0x1p-100f, 0) && a != 0.0f) l = a / piv;
+      } else {
+        l = a / piv;
       }
     }
-
-    GIR_PANEL_MARK(3);
-    // write the block back (rows that were not pivots before this block)
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      if (!pvb[s]) {
-        const int q = tid + kPanelThreads * s;
-#pragma unroll
-        for (int c = 0; c < W; ++c)
-          if (c < wcols) P[(int64_t)(c0 + c) * ldp + q] = x[s][c];
-        if (pv[s]) pstep[q] = ib;
-      }
+    switch (c) {
+#define GIR_ELIM(C) \
+  case C:           \
+    xc = eliminate_col<C>(x, l, u, upd); \
+    break;
+#define GIR_ELIM8(C) \
+  GIR_ELIM(C) GIR_ELIM(C + 1) GIR_ELIM(C + 2) GIR_ELIM(C + 3) GIR_ELIM(C + 4) GIR_ELIM(C + 5) \
+  GIR_ELIM(C + 6) GIR_ELIM(C + 7)
+      GIR_ELIM8(0)
+      GIR_ELIM8(8)
+      GIR_ELIM8(16)
+      GIR_ELIM8(24)
+      GIR_ELIM8(32)
+      GIR_ELIM8(40)
+      GIR_ELIM8(48)
+      GIR_ELIM8(56)
+#undef GIR_ELIM8
+#undef GIR_ELIM
+      default:
+        break;
     }
-    __syncthreads();
-    GIR_PANEL_MARK(4);
-    // U part of the new pivot rows in the remaining columns of the panel
-    const int rem0 = c0 + W;
-    for (int cr = rem0 + tid; cr < kb; cr += kPanelThreads) {
-      float y[W];
-#pragma unroll
-      for (int t = 0; t < W; ++t) y[t] = P[(int64_t)cr * ldp + blk_prow[t]];
-#pragma unroll
-      for (int t = 1; t < W; ++t) {
-#pragma unroll
-        for (int s2 = 0; s2 < t; ++s2) y[t] = __builtin_fmaf(-Lblk[t][s2], y[s2], y[t]);
-      }
-#pragma unroll
-      for (int t = 0; t < W; ++t) P[(int64_t)cr * ldp + blk_prow[t]] = y[t];
-    }
-    if (ib < nblk - 1) publish_store(&sync[0], ib + 1);
-    GIR_PANEL_MARK(5);
   }
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int q = tid + kPanelThreads * s;
-    if (q < h) lidx_out[q] = lid[s];
+  if (in) {
+    store_panel_row<F>(row, kb, x);
+    // every workgroup read its permutation entries before publishing its
+    // first key, and no workgroup gets here before it has read every
+    // workgroup's last key: the in-place rewrite is safe
+    perm[k0 + lid] = phys;
   }
-}
-
-template <int W>
-__device__ __forceinline__ void panel_helper(float* __restrict__ P, int ldp, int h, int kb,
-                             const int* __restrict__ pstep, const int* __restrict__ piv_prow,
-                             int* sync, CycleState* st, int nhelpers, int hid) {
-  __shared__ float Ush[W][kMaxNb];
-  __shared__ int prow_sh[W];
-  __shared__ int s_abort;
-  const int tid = threadIdx.x;
-  const int lane = tid % kWave;
-  int* abortp = &st->abort;
-  const int nblk = (kb + W - 1) / W;
-  const int slab = (h + nhelpers - 1) / nhelpers;
-  const int qb = hid * slab;
-  const int qe = min(h, qb + slab);
-  const int nrows = max(0, qe - qb);
-  if (tid == 0) s_abort = 0;
-  __syncthreads();
-  for (int ib = 0; ib < nblk - 1; ++ib) {
-    const int c0 = ib * W;
-    const int rem0 = c0 + W;
-    const int nrem = kb - rem0;
-    if (lane == 0) {
-      if (!wait_geq(&sync[0], ib + 1, abortp)) s_abort = 1;
-    }
-    __syncthreads();
-    if (s_abort) return;
-    if (tid < W) prow_sh[tid] = piv_prow[c0 + tid];
-    __syncthreads();
-    for (int idx = tid; idx < W * nrem; idx += kPanelThreads) {
-      const int t = idx / nrem;
-      const int cr = idx - t * nrem;
-      Ush[t][cr] = P[(int64_t)(rem0 + cr) * ldp + prow_sh[t]];
-    }
-    __syncthreads();
-    // lane -> row, wave -> group of columns; the row's W multipliers are
-    // loaded once and applied to every remaining column it owns
-    const int rl = tid % kWave;
-    const int cg = tid / kWave;
-    constexpr int kGroups = kPanelThreads / kWave;
-    for (int q = qb + rl; q < qb + nrows; q += kWave) {
-      if (pstep[q] >= 0) continue;
-      float l[W];
-#pragma unroll
-      for (int t = 0; t < W; ++t) l[t] = P[(int64_t)(c0 + t) * ldp + q];
-      for (int cr = cg; cr < nrem; cr += kGroups) {
-        float a = P[(int64_t)(rem0 + cr) * ldp + q];
-#pragma unroll
-        for (int t = 0; t < W; ++t) a = __builtin_fmaf(-l[t], Ush[t][cr], a);
-        P[(int64_t)(rem0 + cr) * ldp + q] = a;
-      }
-    }
-    publish_add(&sync[1], 1);
-  }
-}
-
-template <int R, int W>
-__global__ __launch_bounds__(kPanelThreads) void k_panel(float* P, int ldp, int h, int kb, int k0,
-                                                         int* pstep, int* piv_prow, int* lidx,
-                                                         int* ipiv, int* sync, CycleState* st,
-                                                         int nhelpers) {
-  if (blockIdx.x == 0)
-    panel_leader<R, W>(P, ldp, h, kb, k0, pstep, piv_prow, lidx, ipiv, sync, st, nhelpers);
-  else
-    panel_helper<W>(P, ldp, h, kb, pstep, piv_prow, sync, st, nhelpers, blockIdx.x - 1);
-}
-
-template <class F>
-__global__ void k_panel_scatter(typename F::T* __restrict__ S, int64_t ld,
-                                const int* __restrict__ perm, int k0, int kb, int h,
-                                const float* __restrict__ P, int ldp,
-                                const int* __restrict__ lidx, int* __restrict__ ptmp) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= h) return;
-  const int phys = perm[k0 + q];
-  typename F::T* row = S + (int64_t)phys * ld + k0;
-  for (int c = 0; c < kb; ++c) row[c] = F::from_f(P[(int64_t)c * ldp + q]);
-  ptmp[lidx[q]] = phys;
-}
-
-__global__ void k_perm_copy(int* perm, const int* ptmp, int k0, int h) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < h) perm[k0 + i] = ptmp[i];
 }
 
 // U12 = L11^-1 A12 in fp32 with the stored (u_f) unit lower triangle L11.
@@ -583,36 +521,12 @@ __global__ void k_check(const typename F::T* __restrict__ S, int64_t n, int64_t 
 }
 
 template <class F>
-void panel_step_t(const PanelArgs& a, int nhelpers, hipStream_t s) {
+void panel_step_t(const PanelArgs& a, hipStream_t s) {
   using T = typename F::T;
-  T* S = reinterpret_cast<T*>(a.S);
   const int h = a.n - a.k0;
-  const int blk = 256;
-  hipLaunchKernelGGL(k_panel_gather<F>, dim3((h + blk - 1) / blk), dim3(blk), 0, s, S, a.ld,
-                     a.perm, a.k0, a.kb, h, a.P, a.ldp, a.pstep, a.sync);
-  const int nwg = 1 + nhelpers;
-#define GIR_PANEL(R, W)                                                                       \
-  hipLaunchKernelGGL((k_panel<R, W>), dim3(nwg), dim3(kPanelThreads), 0, s, a.P, a.ldp, h, \
-                     a.kb, a.k0, a.pstep, a.piv_prow, a.lidx, a.ipiv, a.sync, a.st, nhelpers)
-  // rows per thread x block width chosen so that the leader's register block
-  // stays in registers (no scratch) at 512 threads
-  if (h <= 512)
-    GIR_PANEL(1, 16);
-  else if (h <= 1024)
-    GIR_PANEL(2, 16);
-  else if (h <= 2048)
-    GIR_PANEL(4, 8);
-  else if (h <= 4096)
-    GIR_PANEL(8, 8);
-  else if (h <= 8192)
-    GIR_PANEL(16, 8);
-  else
-    GIR_PANEL(32, 2);  // h <= 16384
-#undef GIR_PANEL
-  hipLaunchKernelGGL(k_panel_scatter<F>, dim3((h + blk - 1) / blk), dim3(blk), 0, s, S, a.ld,
-                     a.perm, a.k0, a.kb, h, a.P, a.ldp, a.lidx, a.ptmp);
-  hipLaunchKernelGGL(k_perm_copy, dim3((h + blk - 1) / blk), dim3(blk), 0, s, a.perm, a.ptmp,
-                     a.k0, h);
+  const int G = (h + kRowThreads - 1) / kRowThreads;
+  hipLaunchKernelGGL(k_panel_rows<F>, dim3(G), dim3(kRowThreads), 0, s,
+                     reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0, a.kb, h, a.ipiv, a.xch, a.st);
 }
 
 template <class F>
@@ -662,13 +576,13 @@ void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
                      dim3(256), 0, s, p, v, n);
 }
 
-void launch_panel_step(const PanelArgs& a, int store, int nhelpers, hipStream_t s) {
+void launch_panel_step(const PanelArgs& a, int store, hipStream_t s) {
   if (store == kStoreF16)
-    panel_step_t<Fp16>(a, nhelpers, s);
+    panel_step_t<Fp16>(a, s);
   else if (store == kStoreBF16)
-    panel_step_t<Bf16>(a, nhelpers, s);
+    panel_step_t<Bf16>(a, s);
   else
-    panel_step_t<Fp32>(a, nhelpers, s);
+    panel_step_t<Fp32>(a, s);
 }
 
 void launch_trsm_update(const PanelArgs& a, int store, hipStream_t s) {

@@ -124,8 +124,7 @@ struct gmresir_ctx {
   int* ipiv = nullptr;
   double *Linv = nullptr, *Uinv = nullptr;  // inverses of the diagonal blocks
   // LU scratch
-  float* P = nullptr;
-  int *ptmp = nullptr, *pstep = nullptr, *piv_prow = nullptr, *lidx = nullptr, *sync = nullptr;
+  uint64_t* xch = nullptr;  // pivot exchange of the block-column kernel (LU only)
   // solve buffers (length ld, zero padded)
   double *x = nullptr, *b = nullptr, *r64 = nullptr, *t64 = nullptr, *y64 = nullptr,
          *z64 = nullptr;
@@ -149,7 +148,7 @@ struct gmresir_ctx {
 
   ~gmresir_ctx() {
     // permP and permS alias perm
-    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, P, ptmp, pstep, piv_prow, lidx, sync,
+    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, xch,
                     x, b, r64, t64, y64, z64, z32, w32, d32, r32, V, C, U, Cn, Un, Hd, Bd, cs,
                     sn, g, h1, h2, nrm, coefA, coefB, Mdev, Gdev, partial, counter, norms, st,
                     flagsL, flagsU};
@@ -329,32 +328,22 @@ int ingest(gmresir_ctx* h, const double* A, int64_t lda, bool make_lu_copy) {
 int run_lu(gmresir_ctx* h) {
   const int n = (int)h->n;
   gir::launch_iota(h->perm, n, h->stream);
-  GIR_TRY(dalloc(&h->P, (size_t)n * kNb));
-  GIR_TRY(dalloc(&h->ptmp, n));
-  GIR_TRY(dalloc(&h->pstep, n));
-  GIR_TRY(dalloc(&h->piv_prow, kNb));
-  GIR_TRY(dalloc(&h->lidx, n));
-  GIR_TRY(dalloc(&h->sync, 4));
+  uint64_t* xch = nullptr;
+  GIR_TRY(dalloc(&xch, (size_t)gir::kPanelXchWords));
+  h->xch = xch;
+  gir::launch_fill_i32(reinterpret_cast<int*>(xch), 0, 2 * gir::kPanelXchWords, h->stream);
   gir::PanelArgs a{};
   a.S = h->S;
   a.ld = h->ld;
   a.n = n;
   a.perm = h->perm;
-  a.ptmp = h->ptmp;
-  a.P = h->P;
-  a.ldp = n;
-  a.pstep = h->pstep;
-  a.piv_prow = h->piv_prow;
-  a.lidx = h->lidx;
   a.ipiv = h->ipiv;
-  a.sync = h->sync;
+  a.xch = xch;
   a.st = h->st;
   for (int k0 = 0; k0 < n; k0 += kNb) {
     a.k0 = k0;
     a.kb = std::min(kNb, n - k0);
-    const int hrows = n - k0;
-    const int nhelpers = std::min(128, std::max(1, (hrows + 63) / 64));
-    gir::launch_panel_step(a, h->store, nhelpers, h->stream);
+    gir::launch_panel_step(a, h->store, h->stream);
     gir::launch_trsm_update(a, h->store, h->stream);
   }
   GIR_HIP(hipGetLastError());
@@ -376,15 +365,9 @@ int run_lu(gmresir_ctx* h) {
   } else if (hflag) {
     h->status = GMRESIR_ERANGE;
   }
-  // the LU scratch is not needed by the solve phase
-  (void)hipFree(h->P);
-  (void)hipFree(h->ptmp);
-  (void)hipFree(h->pstep);
-  (void)hipFree(h->piv_prow);
-  (void)hipFree(h->lidx);
-  (void)hipFree(h->sync);
-  h->P = nullptr;
-  h->ptmp = h->pstep = h->piv_prow = h->lidx = h->sync = nullptr;
+  // the exchange buffer is not needed by the solve phase
+  (void)hipFree(h->xch);
+  h->xch = nullptr;
   return 0;
 }
 
