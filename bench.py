@@ -1,19 +1,35 @@
 #!/usr/bin/env python3
 """Refined solves/s to backward error 1e-14, recycled vs plain GMRES-IR, n=8192.
 
-One timed "step" is the whole hot path on one system: gmresir_factor (LU in
-u_f = fp16 on the MI355X, conversions of A) followed by gmresir_solve
+One timed step is the whole hot path on one system: gmresir_factor (LU in
+u_f = fp16 with the copies of A the solve needs) followed by gmresir_solve
 (x0, refinement steps with the fp64 residual and the GCRO-DR(30, 10)
-correction solve), on a seeded synthetic randsvd matrix (mode 3, geometric
-singular values from 1 to 1/kappa, Haar factors) with x_true ~ U(-1, 1) and
-b = A x_true, precisions (fp16, fp32, fp64).  The same steps are timed with
-k = 0 (plain GMRES-IR(30)) for the comparison the metric names.
+correction solve, x update), on a seeded synthetic randsvd matrix (mode 3:
+geometric singular values from 1 to 1/kappa, Haar factors) with
+x_true ~ U(-1, 1), b = A x_true, precisions (fp16, fp32, fp64).  The inputs
+are generated on the GPU and are resident in HBM before the timed region.
+The same steps are then timed with k = 0 (plain GMRES-IR(30)), and the
+outcome (status, refinement steps, Arnoldi iterations) of the kappa = 1e6
+and 1e10 systems of the same size is reported for both.
 
-Prints one JSON line (rank 0).  See the design doc for the roofline model.
+Live kernel timing: the library brackets every launch of its kernel classes
+with HIP events on the stream they run on (opts.timing); the class with the
+largest share of the timed steps gives the roofline object (algorithmic
+bytes of its launches / their summed duration, against 8 TB/s).  HBM
+traffic measured with rocprofv3 counters is read from profiles/traffic.json
+when that file was taken on the current source of the kernel.
+
+cpu_baseline: the CPU oracle (test infrastructure, numpy) on a bounded
+sample of the same workload -- factor and solve of one randsvd system of
+order 6144 -- scaled to n = 8192 by the cost orders of its parts (n^3 for the
+factorisation, n^2 per Arnoldi step for the solve).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,7 +39,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP16_PEAK_TFLOPS = 2500.0
+FP16_MFMA_PEAK_TFLOPS = 2500.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+# source files whose text determines each kernel class (traffic validity)
+KERNEL_SOURCES = {
+    "lu_panel": "kernels_lu.hip", "lu_trsm": "kernels_lu.hip", "lu_gemm": "kernels_lu.hip",
+    "trsv_lower": "kernels_solve.hip", "trsv_upper": "kernels_solve.hip",
+    "gemv_au": "kernels_solve.hip", "residual": "kernels_solve.hip", "ortho": "kernels_solve.hip",
+}
 
 
 def parse():
@@ -39,7 +63,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--outcomes", default="1e6,1e10",
-                    help="extra kappa values whose outcome (status, iterations) is reported")
+                    help="kappa values whose outcome is reported ('' for none)")
+    ap.add_argument("--cpu-n", type=int, default=6144, help="order of the oracle sample")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="first run one plain fp32 copy kernel (out = -in) over this many MiB, "
+                         "the reference for scaling HBM traffic counters")
     return ap.parse_args()
 
 
@@ -47,14 +75,64 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def source_digest(name: str) -> str:
+    path = os.path.join(ROOT, "paper_2201_09827_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel: str, launches_per_step: float):
+    """HBM bytes per launch from the counter summary, or None when missing or
+    taken on another version of the kernel's source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = t.get("kernels", {}).get(kernel)
+    if not rec or rec.get("source_sha256_16") != source_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n_sample: int, n_target: int, kappa: float, seed: int, m: int, k: int):
+    """The oracle (as it stands) on one system of order n_sample."""
+    import numpy as np  # noqa: F401
+    from oracle import refine
+    from synthetic import randsvd_problem
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    prob = randsvd_problem(n_sample, kappa, seed)
+    o = refine.Options(uf="fp16", u="fp32", ur="fp64", m=m, k=k, tau=1e-4, imax=10,
+                       berr_target=1e-14, nb=64)
+    t0 = time.perf_counter()
+    f = refine.factor(prob.a, o)
+    t1 = time.perf_counter()
+    x, info = refine.solve(f, prob.b)
+    t2 = time.perf_counter()
+    r = n_target / n_sample
+    t_scaled = (t1 - t0) * r ** 3 + (t2 - t1) * r ** 2
+    return {
+        "value": 1.0 / t_scaled,
+        "unit": "solves/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle factor ({t1 - t0:.1f} s) + solve ({t2 - t1:.1f} s, its {info.its}, "
+                   f"status {info.status}) of randsvd n={n_sample} kappa={kappa:g} seed={seed}, "
+                   f"scaled to n={n_target} by (n/{n_sample})^3 for the factor and "
+                   f"(n/{n_sample})^2 for the solve"),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)",
-              file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described, not built)", file=sys.stderr)
         return 2
-    import numpy as np
     import torch
 
     import paper_2201_09827_amd as g
@@ -65,6 +143,14 @@ def main():
         return 2
     g.load_library()
     dev = torch.device("cuda:0")
+    if args.copy_ref_mib > 0:
+        src = torch.ones(args.copy_ref_mib * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy reference: {args.copy_ref_mib} MiB read, {args.copy_ref_mib} MiB written")
+        del src, dst
     t0 = time.time()
     a, xt_dev, b = randsvd_problem_torch(args.n, args.kappa, args.seed, dev)
     torch.cuda.synchronize()
@@ -73,26 +159,44 @@ def main():
     opts = dict(uf="fp16", u="fp32", ur="fp64", m=args.m, tau=1e-4, imax=10,
                 berr_target=1e-14)
 
-    def one_step(k):
-        h = g.factor(a, k=k, **opts)
-        x, info = h.solve(b)
+    def one_step(k, a_, b_, stats=None, mask=0):
+        h = g.factor(a_, k=k, timing=mask if stats is not None else 0, **opts)
+        x, info = h.solve(b_)
+        if stats is not None:
+            for r in h.kernel_stats():
+                acc = stats.setdefault(r["name"], {"launches": 0, "total_ms": 0.0, "work": 0.0,
+                                                   "bound": r["bound"]})
+                acc["launches"] += r["launches"]
+                acc["total_ms"] += r["total_ms"]
+                acc["work"] += r["work"]
         h.free()
         return x, info
 
-    def timed(k, steps, warmup):
+    def timed(k, steps, warmup, stats=None, mask=0):
         for _ in range(warmup):
-            one_step(k)
+            one_step(k, a, b)
         torch.cuda.synchronize()
         t = time.perf_counter()
         infos = []
         for _ in range(steps):
-            x, info = one_step(k)
+            x, info = one_step(k, a, b, stats, mask)
             infos.append(info)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         return dt, infos, x
 
-    dt, infos, x = timed(args.k, args.steps, args.warmup)
+    # one untimed-region step with every kernel class timed picks the class
+    # with the largest share; the timed steps then bracket only that class
+    survey = {}
+    one_step(args.k, a, b, survey, (1 << len(g.KERNEL_CLASSES)) - 1)
+    dom = max(survey, key=lambda kk: survey[kk]["total_ms"])
+    kernels = {name: {"launches_per_step": r["launches"], "ms_per_step": r["total_ms"],
+                      "avg_us": r["total_ms"] / max(r["launches"], 1) * 1e3,
+                      "GBps": r["work"] / (r["total_ms"] * 1e-3) / 1e9 if r["total_ms"] > 0 else 0.0}
+               for name, r in survey.items()}
+    kstats = {}
+    dt, infos, x = timed(args.k, args.steps, args.warmup, kstats,
+                         1 << g.KERNEL_CLASSES.index(dom))
     info = infos[-1]
     converged = all(i["status"] == 0 for i in infos)
     ferr = float(torch.max(torch.abs(x - xt_dev)) / torch.max(torch.abs(xt_dev)))
@@ -108,6 +212,42 @@ def main():
                  "ms_per_step": dtp / args.steps * 1e3, "status": ip["status"], "its": ip["its"],
                  "berr": ip["berr"][-1]}
         log(f"plain k=0: {dtp / args.steps * 1e3:.2f} ms/step its={ip['its']}")
+
+    # roofline of the dominant class, from its launches in the timed steps
+    r = kstats[dom]
+    achieved = r["work"] / (r["total_ms"] * 1e-3) / 1e9
+    traffic = traffic_for(dom, r["launches"] / args.steps)
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                "launches": r["launches"], "avg_us": r["total_ms"] / r["launches"] * 1e3,
+                "algorithmic_bytes_per_launch": r["work"] / r["launches"],
+                "kernels_one_step": kernels}
+    log(f"dominant kernel class {dom}: {r['launches']} launches, avg "
+        f"{r['total_ms'] / r['launches'] * 1e3:.1f} us, {achieved:.1f} GB/s")
+
+    outcomes = []
+    for ks in [s for s in args.outcomes.split(",") if s.strip()]:
+        kap = float(ks)
+        a2, xt2, b2 = randsvd_problem_torch(args.n, kap, args.seed, dev)
+        for kk in (args.k, 0):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x2, i2 = one_step(kk, a2, b2)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            fe = float(torch.max(torch.abs(x2 - xt2)) / torch.max(torch.abs(xt2)))
+            outcomes.append({"kappa2": kap, "k": kk, "status": i2["status_name"],
+                             "steps": i2["steps"], "its": i2["its"], "berr": i2["berr"][-1],
+                             "ferr": fe, "seconds": el})
+            log(f"outcome kappa={kap:g} k={kk}: {i2['status_name']} its={i2['its']} "
+                f"berr={i2['berr'][-1]:.2e} in {el:.2f} s")
+        del a2, xt2, b2
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.time()
+        cpu = cpu_baseline(args.cpu_n, args.n, args.kappa, args.seed, args.m, args.k)
+        log(f"cpu baseline ({time.time() - t:.1f} s): {cpu['value']:.3g} solves/s; {cpu['sample']}")
 
     out = {
         "metric": "refined solves/s to backward err 1e-14, recycled vs plain GMRES-IR, n=8192",
@@ -136,7 +276,10 @@ def main():
             "t_solve_ms": info["t_solve_s"] * 1e3,
             "plain": plain,
             "recycled_over_plain": (value / plain["solves_per_s"]) if plain and plain["solves_per_s"] else None,
+            "outcomes": outcomes,
         },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0

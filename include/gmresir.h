@@ -81,7 +81,10 @@ typedef struct {
                              preconditioner)                                  */
   int32_t keep_recycle;   /* 1: the recycled pair survives between
                              gmresir_solve calls on the same handle          */
-  int32_t reserved[4];    /* must be zero                                    */
+  int32_t timing;         /* bit c set: bracket every launch of kernel class c
+                             (the order listed at gmresir_kernel_stats) with
+                             HIP events on the stream it runs on; 0: off     */
+  int32_t reserved[3];    /* must be zero                                    */
 } gmresir_opts;
 
 /* Per-solve record, filled by gmresir_solve (host struct). */
@@ -104,7 +107,7 @@ typedef struct gmresir_ctx gmresir_ctx;
 
 /* Fill *opts with defaults: (FP16, FP32, FP64), m = 30, k = 10, tau = 1e-4,
  * imax = 10, maxit = 0, berr_target = 1e-14, scale_pow2 = -1,
- * keep_recycle = 0. */
+ * keep_recycle = 0, timing = 0. */
 void gmresir_default_opts(gmresir_opts* opts);
 
 /*
@@ -192,6 +195,34 @@ int gmresir_export_factors(gmresir_ctx* h, void* lu, int32_t* ipiv, int32_t* e);
  */
 int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y,
                   void* stream);
+
+/*
+ * Per-kernel-class launch timing (handles created with opts.timing != 0).
+ * One record per timed class that ran since the handle was created: the
+ * number of
+ * launches, the sum of their durations measured with HIP events recorded on
+ * the stream the kernels were launched on (launches an Arnoldi step skipped
+ * on the device after convergence are not counted), and the algorithmic work
+ * of those launches: bytes that must cross HBM (bound = 0) or floating-point
+ * operations on the matrix cores (bound = 1).  Classes, bit 0 first:
+ * "lu_panel", "lu_trsm", "lu_gemm" (factorisation), "trsv_lower",
+ * "trsv_upper", "gemv_au", "residual", "ortho" (solve phase).  Each event
+ * pair costs a few microseconds of stream time, so time only the classes of
+ * interest.
+ *
+ *   out    host array of cap records; count receives the number written.
+ * Waits for the recorded events.  Returns EINVAL when timing is off.
+ */
+typedef struct {
+  char name[24];
+  int32_t launches;
+  int32_t bound;      /* 0: HBM bytes, 1: matrix-core flops */
+  double total_ms;
+  double work;
+} gmresir_kernel_stat;
+
+int gmresir_kernel_stats(gmresir_ctx* h, gmresir_kernel_stat* out, int32_t cap,
+                         int32_t* count);
 
 /* Size n and ABI version of a handle (either pointer may be NULL). */
 int gmresir_query(gmresir_ctx* h, int64_t* n, int32_t* abi_version);

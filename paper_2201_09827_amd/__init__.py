@@ -25,6 +25,7 @@ __all__ = [
     "import_factors",
     "Handle",
     "EXPORTED",
+    "KERNEL_CLASSES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,12 +34,15 @@ PREC = {"bf16": 1, "fp16": 2, "fp32": 3, "fp64": 4, "dd": 5}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EINTERNAL",
           1: "ESINGULAR", 2: "ERANGE", 3: "ENOCONV"}
 MAX_STEPS = 64
+# kernel classes of gmresir_kernel_stats, bit 0 first
+KERNEL_CLASSES = ("lu_panel", "lu_trsm", "lu_gemm", "trsv_lower", "trsv_upper", "gemv_au",
+                  "residual", "ortho")
 
 # every symbol declared in include/gmresir.h
 EXPORTED = (
     "gmresir_default_opts", "gmresir_factor", "gmresir_solve", "gmresir_free",
     "gmresir_strerror", "gmresir_last_error", "gmresir_import_factors",
-    "gmresir_export_factors", "gmresir_apply", "gmresir_query",
+    "gmresir_export_factors", "gmresir_apply", "gmresir_kernel_stats", "gmresir_query",
 )
 
 
@@ -56,7 +60,18 @@ class Opts(ctypes.Structure):
         ("berr_target", ctypes.c_double),
         ("scale_pow2", ctypes.c_int32),
         ("keep_recycle", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("timing", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 24),
+        ("launches", ctypes.c_int32),
+        ("bound", ctypes.c_int32),
+        ("total_ms", ctypes.c_double),
+        ("work", ctypes.c_double),
     ]
 
 
@@ -116,6 +131,8 @@ def load_library() -> ctypes.CDLL:
     lib.gmresir_export_factors.restype = ctypes.c_int
     lib.gmresir_apply.argtypes = [vp, i32, vp, vp, vp]
     lib.gmresir_apply.restype = ctypes.c_int
+    lib.gmresir_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+    lib.gmresir_kernel_stats.restype = ctypes.c_int
     lib.gmresir_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.gmresir_query.restype = ctypes.c_int
     _LIB = lib
@@ -133,7 +150,7 @@ def _opts(**kw) -> Opts:
     for key, val in kw.items():
         if key in ("uf", "u", "ur") and isinstance(val, str):
             val = PREC[val]
-        if key == "keep_recycle" or key == "scale_pow2":
+        if key in ("keep_recycle", "scale_pow2", "timing"):
             val = int(val)
         if not hasattr(o, key):
             raise TypeError(f"unknown option {key!r}")
@@ -250,6 +267,23 @@ class Handle:
             raise _err(self._lib, rc)
         return lu, ipiv, int(e.value)
 
+    def kernel_stats(self) -> list:
+        """Per-kernel-class launch timing (handle created with timing = a bit
+        mask of KERNEL_CLASSES, 0xFF for all):
+        list of dicts name, launches, bound ('hbm' or 'mfma'), total_ms, work
+        (algorithmic bytes or flops summed over the launches)."""
+        ptr = self._live()
+        cap = 16
+        arr = (KernelStat * cap)()
+        cnt = ctypes.c_int32(0)
+        rc = self._lib.gmresir_kernel_stats(ptr, arr, cap, ctypes.byref(cnt))
+        if rc != 0:
+            raise _err(self._lib, rc)
+        return [{"name": arr[i].name.decode(), "launches": int(arr[i].launches),
+                 "bound": "mfma" if arr[i].bound == 1 else "hbm",
+                 "total_ms": float(arr[i].total_ms), "work": float(arr[i].work)}
+                for i in range(cnt.value)]
+
     def free(self):
         if self._ptr:
             self._lib.gmresir_free(self._ptr)
@@ -271,7 +305,7 @@ class Handle:
 def factor(a, stream=None, **opts) -> Handle:
     """LU-factorise A (Algorithm 3, line 1).  ``a``: square row-major float64
     CUDA tensor.  Options: uf, u, ur ('fp16', 'bf16', 'fp32', 'fp64', 'dd'),
-    m, k, tau, imax, maxit, berr_target, scale_pow2, keep_recycle.  Raises
+    m, k, tau, imax, maxit, berr_target, scale_pow2, keep_recycle, timing.  Raises
     GmresirError on a negative status; ESINGULAR/ERANGE return a handle whose
     ``status`` says so."""
     lib = load_library()

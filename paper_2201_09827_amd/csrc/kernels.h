@@ -37,8 +37,10 @@ struct PanelArgs {
 constexpr int64_t kPanelXchWords = 2 * 32 * 80;
 // one block column of the blocked right-looking GEPP (lazy row interchanges)
 void launch_panel_step(const PanelArgs& a, int store, hipStream_t s);
-// the block row to the right of the panel and the trailing update
-void launch_trsm_update(const PanelArgs& a, int store, hipStream_t s);
+// the block row to the right of the panel (U12 = L11^-1 A12)
+void launch_trsm(const PanelArgs& a, int store, hipStream_t s);
+// the trailing update A22 -= L21 U12 on the matrix cores
+void launch_gemm_update(const PanelArgs& a, int store, hipStream_t s);
 // after the last panel: non-finite check of the factors
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,
                           hipStream_t s);

@@ -166,10 +166,13 @@ __device__ __forceinline__ void load_panel_row(const typename F::T* src, int kb,
 }
 
 template <class F>
-__device__ __forceinline__ void store_panel_row(typename F::T* dst, int kb,
-                                                const float (&x)[kMaxNb]) {
+__device__ __forceinline__ void store_panel_row(typename F::T* dst, int kb, float (&x)[kMaxNb]) {
   using T = typename F::T;
   constexpr int kPer = 16 / sizeof(T);
+  // fp32 values first, then the rounding to u_f (no fma fused with the
+  // narrowing conversion, which would round once instead of twice)
+#pragma unroll
+  for (int c = 0; c < kMaxNb; ++c) asm volatile("" : "+v"(x[c]));
   if (kb == kMaxNb) {
 #pragma unroll
     for (int v = 0; v < kMaxNb / kPer; ++v) {
@@ -189,16 +192,26 @@ __device__ __forceinline__ void store_panel_row(typename F::T* dst, int kb,
 
 // elimination of column C for one row: x_C <- l, x_j <- fma(-l, u_j, x_j) for
 // j > C; returns the row's value in column C + 1 (the next pivot search)
+// (u is 16-byte aligned: the aligned part is read four values at a time)
 template <int C>
-__device__ __forceinline__ float eliminate_col(float (&x)[kMaxNb], float l, const float* u,
-                                               bool upd) {
-  if (upd) {
-    x[C] = l;
+__device__ __forceinline__ float eliminate_col(float (&x)[kMaxNb], float l, const float* u) {
+  constexpr int kJ0 = C + 1;
+  constexpr int kJA = (kJ0 + 3) & ~3;
+  x[C] = l;
 #pragma unroll
-    for (int j = C + 1; j < kMaxNb; ++j) x[j] = __builtin_fmaf(-l, u[j], x[j]);
+  for (int j = kJ0; j < kJA && j < kMaxNb; ++j) x[j] = __builtin_fmaf(-l, u[j], x[j]);
+#pragma unroll
+  for (int j = kJA; j < kMaxNb; j += 4) {
+    const float4 w = *reinterpret_cast<const float4*>(u + j);
+    x[j] = __builtin_fmaf(-l, w.x, x[j]);
+    x[j + 1] = __builtin_fmaf(-l, w.y, x[j + 1]);
+    x[j + 2] = __builtin_fmaf(-l, w.z, x[j + 2]);
+    x[j + 3] = __builtin_fmaf(-l, w.w, x[j + 3]);
   }
   return x[C + 1 < kMaxNb ? C + 1 : C];
 }
+
+constexpr int kMaxPanelWgs = 32;  // h <= 16384
 
 template <class F>
 __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __restrict__ S,
@@ -210,8 +223,9 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
   using T = typename F::T;
   __shared__ uint64_t kw[kRowWaves];
   __shared__ __align__(16) float rowbuf[kMaxNb];
-  __shared__ __align__(16) float ush[kMaxNb];
+  __shared__ __align__(16) float recv[kMaxPanelWgs][kMaxNb];
   __shared__ uint64_t s_win;
+  __shared__ int s_gw;
   __shared__ int s_abort;
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
@@ -231,7 +245,7 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
 #pragma unroll
   for (int c = 0; c < kMaxNb; ++c) asm volatile("" : "+v"(x[c]));
   int lid = q;
-  bool pv = !in;  // pivoted (or absent) rows take no further part
+  bool pv = !in;  // pivoted (or absent) rows take no part in the pivot search
   float xc = x[0];
   if (tid == 0) s_abort = 0;
 
@@ -256,33 +270,63 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
     uint64_t W = K;
     const float* u = rowbuf;
     if (G > 1) {
+      // one round trip: every record's row words are fetched together with
+      // the keys, the winner's row is then taken from LDS
+      uint64_t* base = xch + (size_t)(c & 1) * G * kRecWords;
       if (wave == 0) {
-        uint64_t* base = xch + (size_t)(c & 1) * G * kRecWords;
         uint64_t* mine = base + (size_t)g * kRecWords;
-        if (lane >= c) xch_store(mine + lane, ((uint64_t)tag << 32) | __float_as_uint(rowbuf[lane]));
+        xch_store(mine + lane, ((uint64_t)tag << 32) | __float_as_uint(rowbuf[lane]));
         if (lane == 0) xch_store(mine + kMaxNb, ((uint64_t)tag << 48) | K);
-        uint64_t kk = 0;
-        bool ok = poll_tagged(base + (size_t)(lane < G ? lane : 0) * kRecWords + kMaxNb, lane < G,
-                              tag, 48, kk, abortp);
-        uint64_t wk = 0;
-        if (ok) {
-          const uint64_t kv = (lane < G) ? (kk & 0xFFFFFFFFFFFFull) : 0ull;
-          wk = wave_max_u64(kv);
-          const unsigned long long bal = __ballot(lane < G && kv == wk);
-          const int gw = (int)__builtin_ctzll(bal);
-          uint64_t rv = 0;
-          ok = poll_tagged(base + (size_t)gw * kRecWords + lane, lane >= c, tag, 32, rv, abortp);
-          if (lane >= c) ush[lane] = __uint_as_float((uint32_t)rv);
-        }
-        if (lane == 0) {
-          s_win = wk;
-          if (!ok) s_abort = 1;
+      }
+      bool ok = true;
+      uint64_t v[kMaxPanelWgs * kMaxNb / kRowThreads];
+      {
+        long long spins = 0;
+        for (;;) {
+          bool got = true;
+#pragma unroll
+          for (int i = 0; i < kMaxPanelWgs * kMaxNb / kRowThreads; ++i) {
+            const int f = tid + kRowThreads * i;
+            if ((f >> 6) < G) {
+              v[i] = xch_load(base + (size_t)(f >> 6) * kRecWords + (f & 63));
+              got = got && (uint32_t)(v[i] >> 32) == tag;
+            }
+          }
+          if (__all(got)) break;
+          __builtin_amdgcn_s_sleep(1);
+          if (((++spins) & 1023) == 0) {
+            if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                spins > (1ll << 22)) {
+              __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              ok = false;
+              break;
+            }
+          }
         }
       }
+#pragma unroll
+      for (int i = 0; i < kMaxPanelWgs * kMaxNb / kRowThreads; ++i) {
+        const int f = tid + kRowThreads * i;
+        if ((f >> 6) < G) recv[f >> 6][f & 63] = __uint_as_float((uint32_t)v[i]);
+      }
+      if (wave == 0) {
+        uint64_t kk = 0;
+        if (ok)
+          ok = poll_tagged(base + (size_t)(lane < G ? lane : 0) * kRecWords + kMaxNb, lane < G,
+                           tag, 48, kk, abortp);
+        const uint64_t kv = (lane < G) ? (kk & 0xFFFFFFFFFFFFull) : 0ull;
+        const uint64_t wk = wave_max_u64(kv);
+        const unsigned long long bal = __ballot(lane < G && kv == wk);
+        if (lane == 0) {
+          s_win = wk;
+          s_gw = (int)__builtin_ctzll(bal);
+        }
+      }
+      if (!ok) s_abort = 1;
       __syncthreads();
       if (s_abort) return;
       W = s_win;
-      u = ush;
+      u = recv[s_gw];
     }
     const int wl = (int)(0x1FFFFu - (uint32_t)(W & 0x1FFFFull));
     const float piv = u[c];
@@ -290,20 +334,22 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
       ipiv[k0 + c] = k0 + wl;
       if (piv == 0.0f) atomicCAS(&st->singular, 0, k0 + c + 1);
     }
-    const bool me = !pv && lid == wl;
-    if (!pv && lid == c) lid = wl;
-    if (me) {
+    if (!pv && lid == wl) {
+      // the pivot row is final: write it now; its registers are eliminated
+      // with the others below (to zeros) and never stored again
+      store_panel_row<F>(row, kb, x);
       lid = c;
       pv = true;
+    } else if (!pv && lid == c) {
+      lid = wl;
     }
-    const bool upd = !pv && piv != 0.0f;
-    float l = 0.0f;
-    if (upd) {
+    if (piv != 0.0f) {
       // fl32(a / piv) from the reciprocal, the product and one fused
       // correction (Markstein); quotients near the subnormal range and an
       // infinite reciprocal fall back to the division
       const float a = xc;
       const float rinv = 1.0f / piv;
+      float l;
       if (__builtin_isfinite(rinv)) {
         const float q0 = a * rinv;
         const float e = __builtin_fmaf(-q0, piv, a);
@@ -312,31 +358,54 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
       } else {
         l = a / piv;
       }
-    }
-    switch (c) {
+      switch (c) {
 #define GIR_ELIM(C) \
   case C:           \
-    xc = eliminate_col<C>(x, l, u, upd); \
+    xc = eliminate_col<C>(x, l, u); \
     break;
 #define GIR_ELIM8(C) \
   GIR_ELIM(C) GIR_ELIM(C + 1) GIR_ELIM(C + 2) GIR_ELIM(C + 3) GIR_ELIM(C + 4) GIR_ELIM(C + 5) \
   GIR_ELIM(C + 6) GIR_ELIM(C + 7)
-      GIR_ELIM8(0)
-      GIR_ELIM8(8)
-      GIR_ELIM8(16)
-      GIR_ELIM8(24)
-      GIR_ELIM8(32)
-      GIR_ELIM8(40)
-      GIR_ELIM8(48)
-      GIR_ELIM8(56)
+        GIR_ELIM8(0)
+        GIR_ELIM8(8)
+        GIR_ELIM8(16)
+        GIR_ELIM8(24)
+        GIR_ELIM8(32)
+        GIR_ELIM8(40)
+        GIR_ELIM8(48)
+        GIR_ELIM8(56)
 #undef GIR_ELIM8
 #undef GIR_ELIM
-      default:
-        break;
+        default:
+          break;
+      }
+    } else {
+      // singular column: nothing is eliminated (LAPACK's convention)
+      switch (c) {
+#define GIR_NEXT(C) \
+  case C:           \
+    xc = x[C + 1 < kMaxNb ? C + 1 : C]; \
+    break;
+#define GIR_NEXT8(C) \
+  GIR_NEXT(C) GIR_NEXT(C + 1) GIR_NEXT(C + 2) GIR_NEXT(C + 3) GIR_NEXT(C + 4) GIR_NEXT(C + 5) \
+  GIR_NEXT(C + 6) GIR_NEXT(C + 7)
+        GIR_NEXT8(0)
+        GIR_NEXT8(8)
+        GIR_NEXT8(16)
+        GIR_NEXT8(24)
+        GIR_NEXT8(32)
+        GIR_NEXT8(40)
+        GIR_NEXT8(48)
+        GIR_NEXT8(56)
+#undef GIR_NEXT8
+#undef GIR_NEXT
+        default:
+          break;
+      }
     }
   }
   if (in) {
-    store_panel_row<F>(row, kb, x);
+    if (!pv) store_panel_row<F>(row, kb, x);
     // every workgroup read its permutation entries before publishing its
     // first key, and no workgroup gets here before it has read every
     // workgroup's last key: the in-place rewrite is safe
@@ -344,45 +413,52 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
   }
 }
 
-// U12 = L11^-1 A12 in fp32 with the stored (u_f) unit lower triangle L11.
-// A workgroup owns 64 columns staged in LDS; elimination step t updates rows
-// r > t with one fused multiply-add each, so every entry receives its terms
-// in the order t = 0, 1, ... of forward substitution.
-constexpr int kTrsmCols = 64;
+// U12 = L11^-1 A12 in fp32 with the stored (u_f) unit lower triangle L11
+// (the block column is always 64 wide here: a narrower one is the last and
+// has nothing to its right).  One thread per column keeps the column's 64
+// values in registers; L11 is staged transposed in LDS and read as broadcast
+// vectors.  Step t updates rows r > t with one fused multiply-add each, so
+// every entry receives its terms in the order t = 0, 1, ... of forward
+// substitution.
+constexpr int kTrsmThreads = 64;
 template <class F>
-__global__ __launch_bounds__(256) void k_trsm(typename F::T* __restrict__ S, int64_t ld,
-                                              const int* __restrict__ perm, int k0, int kb,
-                                              int n) {
-  __shared__ float Lsh[kMaxNb][kMaxNb + 1];
-  __shared__ float Y[kMaxNb][kTrsmCols + 1];
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict__ S, int64_t ld,
+                                                       const int* __restrict__ perm, int k0,
+                                                       int n) {
+  __shared__ __align__(16) float Lt[kMaxNb][kMaxNb];  // Lt[t][r] = L11[r][t]
   __shared__ int prow[kMaxNb];
   const int tid = threadIdx.x;
-  const int64_t c0 = (int64_t)k0 + kb + (int64_t)blockIdx.x * kTrsmCols;
-  if (tid < kMaxNb) prow[tid] = (tid < kb) ? perm[k0 + tid] : 0;
+  const int64_t c = (int64_t)k0 + kMaxNb + (int64_t)blockIdx.x * kTrsmThreads + tid;
+  prow[tid] = perm[k0 + tid];
   __syncthreads();
-  for (int idx = tid; idx < kMaxNb * kMaxNb; idx += blockDim.x) {
-    const int t = idx / kMaxNb;
-    const int s = idx % kMaxNb;
-    Lsh[t][s] = (t < kb && s < t) ? F::to_f(S[(int64_t)prow[t] * ld + k0 + s]) : 0.0f;
-  }
-  for (int idx = tid; idx < kMaxNb * kTrsmCols; idx += blockDim.x) {
-    const int t = idx / kTrsmCols;
-    const int c = idx % kTrsmCols;
-    Y[t][c] = (t < kb && c0 + c < n) ? F::to_f(S[(int64_t)prow[t] * ld + c0 + c]) : 0.0f;
+  for (int t = 0; t < kMaxNb; ++t) {
+    const int r = tid;
+    Lt[t][r] = (r > t) ? F::to_f(S[(int64_t)prow[r] * ld + k0 + t]) : 0.0f;
   }
   __syncthreads();
-  const int c = tid % kTrsmCols;
-  const int rg = tid / kTrsmCols;  // 4 row groups
-  for (int t = 0; t < kb - 1; ++t) {
-    const float yt = Y[t][c];
-    for (int r = t + 1 + rg; r < kb; r += 4) Y[r][c] = __builtin_fmaf(-Lsh[r][t], yt, Y[r][c]);
-    __syncthreads();
+  if (c >= n) return;
+  float y[kMaxNb];
+#pragma unroll
+  for (int t = 0; t < kMaxNb; ++t) y[t] = F::to_f(S[(int64_t)prow[t] * ld + c]);
+#pragma unroll
+  for (int t = 0; t < kMaxNb; ++t) asm volatile("" : "+v"(y[t]));
+#pragma unroll
+  for (int t = 0; t < kMaxNb - 1; ++t) {
+#pragma unroll
+    for (int r = ((t + 1) & ~3); r < kMaxNb; r += 4) {
+      const float4 lv = *reinterpret_cast<const float4*>(&Lt[t][r]);
+      if (r > t) y[r] = __builtin_fmaf(-lv.x, y[t], y[r]);
+      if (r + 1 > t) y[r + 1] = __builtin_fmaf(-lv.y, y[t], y[r + 1]);
+      if (r + 2 > t) y[r + 2] = __builtin_fmaf(-lv.z, y[t], y[r + 2]);
+      if (r + 3 > t) y[r + 3] = __builtin_fmaf(-lv.w, y[t], y[r + 3]);
+    }
   }
-  for (int idx = tid; idx < kMaxNb * kTrsmCols; idx += blockDim.x) {
-    const int t = idx / kTrsmCols;
-    const int cc = idx % kTrsmCols;
-    if (t < kb && c0 + cc < n) S[(int64_t)prow[t] * ld + c0 + cc] = F::from_f(Y[t][cc]);
-  }
+  // the fp32 result is rounded to u_f in a separate step (an fma fused with
+  // the narrowing conversion would round only once)
+#pragma unroll
+  for (int t = 0; t < kMaxNb; ++t) asm volatile("" : "+v"(y[t]));
+#pragma unroll
+  for (int t = 0; t < kMaxNb; ++t) S[(int64_t)prow[t] * ld + c] = F::from_f(y[t]);
 }
 
 // ---- trailing update on the matrix cores ----------------------------------
@@ -530,16 +606,22 @@ void panel_step_t(const PanelArgs& a, hipStream_t s) {
 }
 
 template <class F>
-void trsm_update_t(const PanelArgs& a, hipStream_t s) {
+void trsm_t(const PanelArgs& a, hipStream_t s) {
   using T = typename F::T;
-  T* S = reinterpret_cast<T*>(a.S);
+  const int M = a.n - a.k0 - a.kb;
+  if (M <= 0) return;  // kb == 64 whenever M > 0
+  hipLaunchKernelGGL(k_trsm<F>, dim3((M + kTrsmThreads - 1) / kTrsmThreads), dim3(kTrsmThreads),
+                     0, s, reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0, a.n);
+}
+
+template <class F>
+void gemm_update_t(const PanelArgs& a, hipStream_t s) {
+  using T = typename F::T;
   const int M = a.n - a.k0 - a.kb;
   if (M <= 0) return;
-  hipLaunchKernelGGL(k_trsm<F>, dim3((M + kTrsmCols - 1) / kTrsmCols), dim3(256), 0, s, S, a.ld,
-                     a.perm, a.k0, a.kb, a.n);
   const int t = (M + kTile - 1) / kTile;
-  hipLaunchKernelGGL(k_gemm_update<F>, dim3(t, t), dim3(256), 0, s, S, a.ld, a.perm, a.k0, a.kb,
-                     a.n);
+  hipLaunchKernelGGL(k_gemm_update<F>, dim3(t, t), dim3(256), 0, s, reinterpret_cast<T*>(a.S),
+                     a.ld, a.perm, a.k0, a.kb, a.n);
 }
 
 }  // namespace
@@ -585,13 +667,22 @@ void launch_panel_step(const PanelArgs& a, int store, hipStream_t s) {
     panel_step_t<Fp32>(a, s);
 }
 
-void launch_trsm_update(const PanelArgs& a, int store, hipStream_t s) {
+void launch_trsm(const PanelArgs& a, int store, hipStream_t s) {
   if (store == kStoreF16)
-    trsm_update_t<Fp16>(a, s);
+    trsm_t<Fp16>(a, s);
   else if (store == kStoreBF16)
-    trsm_update_t<Bf16>(a, s);
+    trsm_t<Bf16>(a, s);
   else
-    trsm_update_t<Fp32>(a, s);
+    trsm_t<Fp32>(a, s);
+}
+
+void launch_gemm_update(const PanelArgs& a, int store, hipStream_t s) {
+  if (store == kStoreF16)
+    gemm_update_t<Fp16>(a, s);
+  else if (store == kStoreBF16)
+    gemm_update_t<Bf16>(a, s);
+  else
+    gemm_update_t<Fp32>(a, s);
 }
 
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,

@@ -99,6 +99,23 @@ int dalloc(T** p, size_t count) {
   return 0;
 }
 
+// kernel classes of gmresir_kernel_stats
+enum KClass { kKcPanel, kKcTrsm, kKcGemm, kKcTrsvL, kKcTrsvU, kKcGemv, kKcResid, kKcOrtho,
+              kKcCount };
+const char* const kKcName[kKcCount] = {"lu_panel", "lu_trsm",  "lu_gemm",  "trsv_lower",
+                                       "trsv_upper", "gemv_au", "residual", "ortho"};
+struct TimedRec {
+  int cls;
+  double work;
+  bool gated;  // launched for an Arnoldi step the device may skip
+  int step;
+  hipEvent_t a, b;
+};
+struct KStat {
+  int64_t launches = 0;
+  double ms = 0.0, work = 0.0;
+};
+
 }  // namespace
 
 struct gmresir_ctx {
@@ -145,6 +162,11 @@ struct gmresir_ctx {
   double* hbuf = nullptr;              // general small transfers
   size_t hbuf_len = 0;
   std::vector<hipEvent_t> ev;
+  // launch timing (opts.timing): pooled events and pending records
+  std::vector<hipEvent_t> tpool;
+  size_t tnext = 0;
+  std::vector<TimedRec> trec;
+  KStat kstat[kKcCount];
 
   ~gmresir_ctx() {
     // permP and permS alias perm
@@ -157,10 +179,66 @@ struct gmresir_ctx {
     if (st_host) (void)hipHostFree(st_host);
     if (hbuf) (void)hipHostFree(hbuf);
     for (auto& e2 : ev) (void)hipEventDestroy(e2);
+    for (auto& e2 : tpool) (void)hipEventDestroy(e2);
   }
 };
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// launch timing
+// ---------------------------------------------------------------------------
+
+int pool_event(gmresir_ctx* h, hipEvent_t* e) {
+  if (h->tnext == h->tpool.size()) {
+    hipEvent_t ne = nullptr;
+    GIR_HIP(hipEventCreate(&ne));
+    h->tpool.push_back(ne);
+  }
+  *e = h->tpool[h->tnext++];
+  return 0;
+}
+
+// Runs launch() bracketed by two events on s when timing is on.
+template <class Fn>
+int timed(gmresir_ctx* h, int cls, double work, hipStream_t s, const void* gate, int step,
+          Fn&& launch) {
+  if (!((h->o.timing >> cls) & 1)) {
+    launch();
+    return 0;
+  }
+  TimedRec r{cls, work, gate != nullptr, step, nullptr, nullptr};
+  GIR_TRY(pool_event(h, &r.a));
+  GIR_TRY(pool_event(h, &r.b));
+  GIR_HIP(hipEventRecord(r.a, s));
+  launch();
+  GIR_HIP(hipEventRecord(r.b, s));
+  h->trec.push_back(r);
+  return 0;
+}
+
+// drop the records of gated launches from step `done` on (skipped on device)
+void drop_skipped(gmresir_ctx* h, size_t from, int done) {
+  size_t w = from;
+  for (size_t i = from; i < h->trec.size(); ++i)
+    if (!(h->trec[i].gated && h->trec[i].step >= done)) h->trec[w++] = h->trec[i];
+  h->trec.resize(w);
+}
+
+int flush_timing(gmresir_ctx* h) {
+  for (const TimedRec& r : h->trec) {
+    GIR_HIP(hipEventSynchronize(r.b));
+    float ms = 0.0f;
+    GIR_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    KStat& k = h->kstat[r.cls];
+    k.launches += 1;
+    k.ms += ms;
+    k.work += r.work;
+  }
+  h->trec.clear();
+  h->tnext = 0;
+  return 0;
+}
 
 int validate_opts(const gmresir_opts* o) {
   if (!o) {
@@ -197,7 +275,11 @@ int validate_opts(const gmresir_opts* o) {
     set_error("invalid tau, imax or maxit");
     return GMRESIR_EINVAL;
   }
-  for (int i = 0; i < 4; ++i)
+  if (o->timing < 0 || o->timing >= (1 << kKcCount)) {
+    set_error("timing must be a bit mask of the kernel classes");
+    return GMRESIR_EINVAL;
+  }
+  for (int i = 0; i < 3; ++i)
     if (o->reserved[i] != 0) {
       set_error("reserved fields must be zero");
       return GMRESIR_EINVAL;
@@ -343,8 +425,16 @@ int run_lu(gmresir_ctx* h) {
   for (int k0 = 0; k0 < n; k0 += kNb) {
     a.k0 = k0;
     a.kb = std::min(kNb, n - k0);
-    gir::launch_panel_step(a, h->store, h->stream);
-    gir::launch_trsm_update(a, h->store, h->stream);
+    const double es = (double)store_bytes(h->store);
+    const double hr = (double)(n - k0), kb = (double)a.kb, M = hr - kb;
+    GIR_TRY(timed(h, kKcPanel, 2.0 * hr * kb * es, h->stream, nullptr, 0,
+                  [&] { gir::launch_panel_step(a, h->store, h->stream); }));
+    if (M > 0) {
+      GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * M) * es, h->stream, nullptr, 0,
+                    [&] { gir::launch_trsm(a, h->store, h->stream); }));
+      GIR_TRY(timed(h, kKcGemm, (2.0 * M * M + 2.0 * M * kb) * es, h->stream, nullptr, 0,
+                    [&] { gir::launch_gemm_update(a, h->store, h->stream); }));
+    }
   }
   GIR_HIP(hipGetLastError());
   int* flag = reinterpret_cast<int*>(h->counter + 2);
@@ -409,19 +499,32 @@ int next_epoch(gmresir_ctx* h) {
 int precond(gmresir_ctx* h, const double* in, const int* permIn, double* out64, float* out32,
             const gir::CycleState* gate, int step) {
   const int n = (int)h->n;
-  gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->Linv, h->y64,
-                         h->flagsL, next_epoch(h), gate, step, &h->st->abort, h->stream);
-  gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->Uinv, h->z64, h->scale,
-                         out64, out32, h->flagsU, next_epoch(h), gate, step, &h->st->abort,
-                         h->stream);
+  // the stored triangle and three vectors of n float64 values
+  const double bytes = 0.5 * (double)n * (double)(n + 1) * (double)store_bytes(h->store) +
+                       24.0 * (double)n;
+  const int eL = next_epoch(h);
+  GIR_TRY(timed(h, kKcTrsvL, bytes, h->stream, gate, step, [&] {
+    gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->Linv, h->y64,
+                           h->flagsL, eL, gate, step, &h->st->abort, h->stream);
+  }));
+  const int eU = next_epoch(h);
+  GIR_TRY(timed(h, kKcTrsvU, bytes, h->stream, gate, step, [&] {
+    gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->Uinv, h->z64,
+                           h->scale, out64, out32, h->flagsU, eU, gate, step, &h->st->abort,
+                           h->stream);
+  }));
   return 0;
 }
 
 // A-tilde v (v float or double)
 int atilde(gmresir_ctx* h, const float* v32, const double* v64, double* out64, float* out32,
            const gir::CycleState* gate, int step) {
-  gir::launch_gemv_au(h->Au, h->ld, h->permP, (int)h->n, v32, v64, h->t64, gate, step,
-                      h->stream);
+  const double nn = (double)h->n;
+  GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + (v32 ? 4.0 : 8.0) * nn + 8.0 * nn, h->stream, gate,
+                step, [&] {
+                  gir::launch_gemv_au(h->Au, h->ld, h->permP, (int)h->n, v32, v64, h->t64, gate,
+                                      step, h->stream);
+                }));
   return precond(h, h->t64, nullptr, out64, out32, gate, step);
 }
 
@@ -567,6 +670,7 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     GIR_HIP(hipMemcpyAsync(&h->st->tol, &st0.tol, 2 * sizeof(double), hipMemcpyHostToDevice, s));
     GIR_HIP(hipStreamSynchronize(s));
     int queued = 0;
+    const size_t trec0 = h->trec.size();
     for (int j = 0; j < nsteps; ++j) {
       float* vj = h->V + (size_t)j * ld;
       GIR_TRY(atilde(h, vj, nullptr, nullptr, h->w32, h->st, j));
@@ -580,10 +684,14 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       a.gate = h->st;
       a.step = j;
       a.dots_out = h->h1;
-      gir::launch_ortho(a, gir::kOrthoDots, s);
+      // basis read once per pass; the update pass also reads and writes w
+      const double xb = (8.0 * kc + 4.0 * (j + 1)) * n;
+      GIR_TRY(timed(h, kKcOrtho, xb + 4.0 * n, s, h->st, j,
+                    [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
       a.coef = h->h1;
       a.dots_out = h->h2;
-      gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s);
+      GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 8.0 * n, s, h->st, j,
+                    [&] { gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s); }));
       a.coef = h->h2;
       a.h_prev = h->h1;
       a.norm_out = h->nrm;
@@ -595,7 +703,9 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       a.sn = h->sn;
       a.g = h->g;
       a.st = h->st;
-      gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
+      GIR_TRY(timed(h, kKcOrtho, xb + 8.0 * n, s, h->st, j, [&] {
+        gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
+      }));
       gir::launch_normalize(h->w32, h->V + (size_t)(j + 1) * ld, h->Hd, m + 1, j, n, h->st, s);
       GIR_HIP(hipMemcpyAsync(&h->st_host[j], h->st, sizeof(gir::CycleState),
                              hipMemcpyDeviceToHost, s));
@@ -616,6 +726,7 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       return GMRESIR_EINTERNAL;
     }
     const int J = fin.jdone;
+    drop_skipped(h, trec0, J);
     GIR_TRY(download(h, Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m));
     if (kc > 0) GIR_TRY(download(h, Bh.data(), h->Bd, sizeof(double) * (size_t)std::max(k, 1) * m));
     const int ldh = m + 1, ldb = std::max(k, 1);
@@ -768,7 +879,8 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   const int imax = h->o.imax;
   int i = 0;
   for (;; ++i) {
-    gir::launch_residual(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s);
+    GIR_TRY(timed(h, kKcResid, 8.0 * (double)n * (double)n + 24.0 * (double)n, s, nullptr, 0,
+                  [&] { gir::launch_residual(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s); }));
     GIR_HIP(hipGetLastError());
     unsigned long long nb[2];
     GIR_TRY(download(h, nb, h->norms, sizeof(nb)));
@@ -1008,6 +1120,35 @@ int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y, void* 
     set_error("triangular solve: a device-side wait exceeded its bound");
     return GMRESIR_EINTERNAL;
   }
+  return 0;
+}
+
+int gmresir_kernel_stats(gmresir_ctx* h, gmresir_kernel_stat* out, int32_t cap,
+                         int32_t* count) {
+  if (!h || !count || cap < 0 || (cap > 0 && !out)) {
+    set_error("invalid handle or output");
+    return GMRESIR_EINVAL;
+  }
+  if (!h->o.timing) {
+    set_error("the handle was created with timing = 0");
+    return GMRESIR_EINVAL;
+  }
+  GIR_TRY(flush_timing(h));
+  int32_t c = 0;
+  for (int k = 0; k < kKcCount; ++k) {
+    if (h->kstat[k].launches == 0) continue;
+    if (c < cap) {
+      gmresir_kernel_stat& r = out[c];
+      std::memset(&r, 0, sizeof(r));
+      std::strncpy(r.name, kKcName[k], sizeof(r.name) - 1);
+      r.launches = (int32_t)h->kstat[k].launches;
+      r.bound = 0;
+      r.total_ms = h->kstat[k].ms;
+      r.work = h->kstat[k].work;
+    }
+    ++c;
+  }
+  *count = std::min(c, cap);
   return 0;
 }
 

@@ -44,6 +44,10 @@ int main(void) {
          offsetof(gmresir_opts, tau), offsetof(gmresir_opts, imax),
          offsetof(gmresir_opts, berr_target), offsetof(gmresir_opts, scale_pow2),
          offsetof(gmresir_opts, keep_recycle), offsetof(gmresir_opts, reserved));
+  printf("timing %zu\n", offsetof(gmresir_opts, timing));
+  printf("kstat %zu %zu %zu %zu %zu\n", sizeof(gmresir_kernel_stat),
+         offsetof(gmresir_kernel_stat, launches), offsetof(gmresir_kernel_stat, bound),
+         offsetof(gmresir_kernel_stat, total_ms), offsetof(gmresir_kernel_stat, work));
   printf("info %zu %zu %zu %zu %zu\n", sizeof(gmresir_info), offsetof(gmresir_info, its),
          offsetof(gmresir_info, berr), offsetof(gmresir_info, singular_col),
          offsetof(gmresir_info, t_solve_s));
@@ -65,6 +69,11 @@ def test_struct_layout_matches_header():
     assert o == [ctypes.sizeof(g.Opts), g.Opts.tau.offset, g.Opts.imax.offset,
                  g.Opts.berr_target.offset, g.Opts.scale_pow2.offset,
                  g.Opts.keep_recycle.offset, g.Opts.reserved.offset]
+    assert int(lines["timing"]) == g.Opts.timing.offset
+    ks = [int(v) for v in lines["kstat"].split()]
+    assert ks == [ctypes.sizeof(g.KernelStat), g.KernelStat.launches.offset,
+                  g.KernelStat.bound.offset, g.KernelStat.total_ms.offset,
+                  g.KernelStat.work.offset]
     i = [int(v) for v in lines["info"].split()]
     assert i == [ctypes.sizeof(g.Info), g.Info.its.offset, g.Info.berr.offset,
                  g.Info.singular_col.offset, g.Info.t_solve_s.offset]

@@ -69,6 +69,10 @@ def test_lu_factors_match_oracle(lib, n, uf):
     log(f"[lu] n={n} uf={uf} first block column/row max ulp {d_col.max():.1f}/"
         f"{d_row.max() if d_row.size else 0:.1f}; pivots identical up to column {diverge}; "
         f"entries > 1 ulp apart {np.mean(d > 1):.2e}")
+    if d_row.size and d_row.max() > 0:
+        bad = np.argwhere(d_row > 0)[:8]
+        log(f"[lu] first block row mismatches (row, col): {bad.tolist()} "
+            f"gpu {[lu_gpu[r, nbk + c] for r, c in bad]} oracle {[res.lu[r, nbk + c] for r, c in bad]}")
     assert d_col.max() == 0.0
     assert d_row.size == 0 or d_row.max() == 0.0
     # later block columns see the fp32-accumulated trailing update (the CPU
