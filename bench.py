@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--outcomes", default="1e6,1e10",
                     help="kappa values whose outcome is reported ('' for none)")
     ap.add_argument("--cpu-n", type=int, default=6144, help="order of the oracle sample")
+    ap.add_argument("--gen", choices=("gpu", "cpu"), default="gpu",
+                    help="draw the system on the GPU (torch) or on the CPU (numpy, slower)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain fp32 copy kernel (out = -in) over this many MiB, "
                          "the reference for scaling HBM traffic counters")
@@ -152,10 +154,16 @@ def main():
         log(f"copy reference: {args.copy_ref_mib} MiB read, {args.copy_ref_mib} MiB written")
         del src, dst
     t0 = time.time()
-    a, xt_dev, b = randsvd_problem_torch(args.n, args.kappa, args.seed, dev)
+    if args.gen == "gpu":
+        a, xt_dev, b = randsvd_problem_torch(args.n, args.kappa, args.seed, dev)
+    else:
+        from synthetic import randsvd_problem
+        p = randsvd_problem(args.n, args.kappa, args.seed)
+        a, xt_dev, b = (torch.from_numpy(v).to(dev) for v in (p.a, p.x_true, p.b))
+        del p
     torch.cuda.synchronize()
-    log(f"generated randsvd(n={args.n}, kappa={args.kappa:g}, seed={args.seed}) on the GPU "
-        f"in {time.time() - t0:.1f} s")
+    log(f"generated randsvd(n={args.n}, kappa={args.kappa:g}, seed={args.seed}) on the "
+        f"{args.gen.upper()} in {time.time() - t0:.1f} s")
     opts = dict(uf="fp16", u="fp32", ur="fp64", m=args.m, tau=1e-4, imax=10,
                 berr_target=1e-14)
 

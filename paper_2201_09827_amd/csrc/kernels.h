@@ -56,19 +56,22 @@ void launch_residual(const double* A, int64_t ld, int n, const double* b, const 
                      double* r, unsigned long long* norms, hipStream_t s);
 // y = L^-1 (in gathered by permIn), fp64; L unit lower in S rows permS;
 // Linv holds the fp64 inverses of the 64 x 64 diagonal blocks
+// xw: [2 * ceil(n/128) * 128] tagged words, zeroed once; epoch: a new
+// nonzero value per launch
 void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
                        const double* in, const int* permIn, const double* Linv, double* y,
-                       int* flags, int epoch, const CycleState* gate, int step, int* abort,
+                       uint64_t* xw, int epoch, const CycleState* gate, int step, int* abort,
                        hipStream_t s);
 // z = U^-1 y; out64 = 2^e z, out32 = fl32(2^e z) (either may be null)
 void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
                        const double* y, const double* Uinv, double* z, double scale,
-                       double* out64, float* out32, int* flags, int epoch, const CycleState* gate,
-                       int step, int* abort, hipStream_t s);
-// fp64 inverses of the 64 x 64 diagonal blocks of L and U (ceil(n/64) blocks
-// of 64 x 64 each, row-major)
+                       double* out64, float* out32, uint64_t* xw, int epoch,
+                       const CycleState* gate, int step, int* abort, hipStream_t s);
+// fp64 inverses of the 128 x 128 diagonal blocks of L and U (ceil(n/128)
+// blocks of 128 x 128 each, row-major); tmp: ceil(n/64) * 64 * 64 doubles
+constexpr int kTrsvBlock = 128;
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,
-                          double* Linv, double* Uinv, hipStream_t s);
+                          double* Linv, double* Uinv, double* tmp, hipStream_t s);
 
 struct Basis {
   const double* c64;  // kc columns, column-major, ld ldc

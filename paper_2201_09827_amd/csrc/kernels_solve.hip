@@ -223,52 +223,117 @@ struct RawRow {
   }
 };
 
-template <class F, bool kUpper>
-__global__ __launch_bounds__(256) void k_trsv(const typename F::T* __restrict__ S, int64_t ld,
-                                              const int* __restrict__ permS, int n,
-                                              const double* __restrict__ in,
-                                              const int* __restrict__ permIn,
-                                              const double* __restrict__ Dinv, double* y,
-                                              double scale, double* __restrict__ out64,
-                                              float* __restrict__ out32, int* flags, int epoch,
-                                              const CycleState* gate, int step, int* abortp) {
-  if (gated_off(gate, step)) return;
-  __shared__ double red[4][kTB];
-  __shared__ double ysh[4][kTB];
-  __shared__ double zsh[kTB];
-  __shared__ int wok[4];
-  const int nblk = (n + kTB - 1) / kTB;
-  const int blk = kUpper ? nblk - 1 - (int)blockIdx.x : (int)blockIdx.x;
-  const int r0 = blk * kTB;
-  const int wave = threadIdx.x / kWave;
+// Blocked triangular solve, one workgroup per 128-row block (two 64-row
+// tiles), fp64 arithmetic with the u_f factor entries taken exactly:
+//   lower: y_I = Dinv_I (in_I - sum_{J < I} L_IJ y_J)
+//   upper: z_I = Dinv_I (y_I  - sum_{J > I} U_IJ z_J)
+// Dinv_I is the fp64 inverse of the 128 x 128 diagonal block.  Waves 0-3 own
+// the first 64 rows, waves 4-7 the second; wave w takes the 64-column tiles
+// J = w mod 4, stepping by 4, and widens each tile row from raw u_f bits.
+// Finished blocks are published as tagged words: row i's fp64 value is split
+// into two 64-bit words (tag << 32 | half) in xw[2i], xw[2i+1], written with
+// relaxed device-scope atomic stores; a reader polls until both tags equal
+// this launch's epoch, so a block is consumed one memory round trip after it
+// is written, with no flags and no fences.
+constexpr int kTS = 128;  // rows per workgroup
+constexpr int kTSThreads = 512;
+
+__device__ __forceinline__ void put_tagged(uint64_t* xw, int row, double v, uint32_t tag) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  __hip_atomic_store(xw + 2 * row, ((uint64_t)tag << 32) | (b & 0xFFFFFFFFull),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(xw + 2 * row + 1, ((uint64_t)tag << 32) | (b >> 32), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// wave-uniform: every lane reads row (c0 + lane)'s value; false on abort
+__device__ __forceinline__ bool get_tagged64(const uint64_t* xw, int c0, uint32_t tag, double& v,
+                                             int* abortp) {
   const int lane = threadIdx.x % kWave;
-  const int row = r0 + lane;
+  const uint64_t* p = xw + 2 * (c0 + lane);
+  long long spins = 0;
+  for (;;) {
+    const uint64_t lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t hi = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool ok = (uint32_t)(lo >> 32) == tag && (uint32_t)(hi >> 32) == tag;
+    if (__all(ok)) {
+      v = __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if (((++spins) & 1023) == 0) {
+      if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if (spins > (1ll << 22)) {
+        __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+  }
+}
+
+template <class F, bool kUpper>
+__global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __restrict__ S,
+                                                     int64_t ld, const int* __restrict__ permS,
+                                                     int n, const double* __restrict__ in,
+                                                     const int* __restrict__ permIn,
+                                                     const double* __restrict__ Dinv, double* y,
+                                                     double scale, double* __restrict__ out64,
+                                                     float* __restrict__ out32, uint64_t* xw,
+                                                     uint32_t epoch, const CycleState* gate,
+                                                     int step, int* abortp) {
+  if (gated_off(gate, step)) return;
+  __shared__ double red[8][kTB];
+  __shared__ double ysh[8][kTB];
+  __shared__ double zsh[kTS];
+  __shared__ double part[4][kTS];
+  __shared__ int wok[8];
+  const int nb = (n + kTS - 1) / kTS;
+  const int nt = (n + kTB - 1) / kTB;  // 64-column tiles
+  const int blk = kUpper ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int r0 = blk * kTS;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int half = wave >> 2;
+  const int wq = wave & 3;
+  const int row = r0 + half * kTB + lane;
   const bool valid = row < n;
   const int prow = valid ? (permS ? permS[row] : row) : 0;
   const typename F::T* srow = S + (int64_t)prow * ld;
   // this thread's quarter of its row of the inverse diagonal block
-  double dq[kTB / 4];
+  const int di = tid % kTS;
+  const int dq4 = tid / kTS;
+  double dq[kTS / 4];
   {
-    const double* drow = Dinv + ((int64_t)blk * kTB + lane) * kTB + wave * (kTB / 4);
+    const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
 #pragma unroll
-    for (int c = 0; c < kTB / 4; c += 2) {
+    for (int c = 0; c < kTS / 4; c += 2) {
       const double2 v = *reinterpret_cast<const double2*>(drow + c);
       dq[c] = v.x;
       dq[c + 1] = v.y;
     }
   }
   double rhs = 0.0;
-  if (valid) rhs = in[permIn ? permIn[row] : row];
+  if (tid < kTS && r0 + tid < n) {
+    const int rr = r0 + tid;
+    rhs = in[permIn ? permIn[rr] : rr];
+  }
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   bool ok = true;
-  const int first = kUpper ? nblk - 1 - wave : wave;
-  for (int J = first; kUpper ? (J > blk) : (J < blk); J += kUpper ? -4 : 4) {
+  const int t0 = kUpper ? 2 * blk + 2 : 0;  // first off-diagonal tile (upper: first to the right)
+  const int t1 = kUpper ? nt : 2 * blk;     // one past the last
+  // lower: ascending from tile wq; upper: descending from the last tile
+  for (int i = wq;; i += 4) {
+    const int J = kUpper ? t1 - 1 - i : t0 + i;
+    if (kUpper ? (J < t0) : (J >= t1)) break;
     RawRow<F> lv;
     lv.load(srow, J * kTB, n, valid);
-    if (lane == 0) ok = wait_eq(&flags[J], epoch, abortp);
-    ok = __shfl(ok ? 1 : 0, 0, kWave) != 0;
-    if (!ok) break;
-    ysh[wave][lane] = (J * kTB + lane < n) ? y[J * kTB + lane] : 0.0;
+    double yv;
+    if (!get_tagged64(xw, J * kTB, epoch, yv, abortp)) {
+      ok = false;
+      break;
+    }
+    ysh[wave][lane] = yv;
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int c = 0; c < kTB; c += 4) {
@@ -282,24 +347,90 @@ __global__ __launch_bounds__(256) void k_trsv(const typename F::T* __restrict__ 
   red[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
   if (lane == 0) wok[wave] = ok ? 1 : 0;
   __syncthreads();
-  if (!(wok[0] & wok[1] & wok[2] & wok[3])) return;
-  if (wave == 0)
-    zsh[lane] = valid ? rhs - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) : 0.0;
-  __syncthreads();
-  double part = 0.0;
+  int allok = 1;
 #pragma unroll
-  for (int c = 0; c < kTB / 4; ++c) part = fma(dq[c], zsh[wave * (kTB / 4) + c], part);
-  red[wave][lane] = part;
-  __syncthreads();
-  if (wave != 0) return;
-  const double v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-  if (valid) {
-    y[row] = v;
-    if (out64) out64[row] = v * scale;
-    if (out32) out32[row] = (float)(v * scale);
+  for (int w = 0; w < 8; ++w) allok &= wok[w];
+  if (!allok) return;
+  if (tid < kTS) {
+    const int h = tid / kTB, l = tid % kTB;
+    const double sum = (red[4 * h][l] + red[4 * h + 1][l]) + (red[4 * h + 2][l] + red[4 * h + 3][l]);
+    zsh[tid] = (r0 + tid < n) ? rhs - sum : 0.0;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  if (lane == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  double p = 0.0;
+#pragma unroll
+  for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[dq4 * (kTS / 4) + c], p);
+  part[dq4][di] = p;
+  __syncthreads();
+  if (tid >= kTS) return;
+  const int rr = r0 + tid;
+  const double v = (rr < n) ? (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]) : 0.0;
+  if (rr < n) {
+    y[rr] = v;
+    if (out64) out64[rr] = v * scale;
+    if (out32) out32[rr] = (float)(v * scale);
+  }
+  put_tagged(xw, rr, v, epoch);
+}
+
+// 128 x 128 inverses of the diagonal blocks from the 64 x 64 ones (D64):
+//   lower [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1]
+//   upper [A B; 0 C]^-1 = [A^-1  -A^-1 B C^-1; 0 C^-1]
+// (fp64, B taken exactly from the u_f factor; a missing second 64-block or
+// rows beyond n act as the identity).
+template <class F, bool kUpper>
+__global__ __launch_bounds__(256) void k_diag_combine(const typename F::T* __restrict__ S,
+                                                      int64_t ld, const int* __restrict__ permS,
+                                                      int n, const double* __restrict__ D64,
+                                                      double* __restrict__ D128) {
+  __shared__ double Ai[kTB][kTB + 1];
+  __shared__ double Ci[kTB][kTB + 1];
+  __shared__ double Bm[kTB][kTB + 1];
+  __shared__ double T[kTB][kTB + 1];
+  const int blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int nt = (n + kTB - 1) / kTB;
+  const int ta = 2 * blk, tc = 2 * blk + 1;
+  const bool hasC = tc < nt;
+  for (int idx = tid; idx < kTB * kTB; idx += 256) {
+    const int r = idx / kTB, c = idx % kTB;
+    Ai[r][c] = D64[(int64_t)ta * kTB * kTB + idx];
+    Ci[r][c] = hasC ? D64[(int64_t)tc * kTB * kTB + idx] : (r == c ? 1.0 : 0.0);
+    // off-diagonal block: lower B = L[rows of C][cols of A]; upper B = U[rows of A][cols of C]
+    const int gr = kUpper ? ta * kTB + r : tc * kTB + r;
+    const int gc = kUpper ? tc * kTB + c : ta * kTB + c;
+    double bv = 0.0;
+    if (hasC && gr < n && gc < n) {
+      const int pr = permS ? permS[gr] : gr;
+      bv = (double)F::to_f(S[(int64_t)pr * ld + gc]);
+    }
+    Bm[r][c] = bv;
+  }
+  __syncthreads();
+  // lower: T = B A^-1, X = -C^-1 T;  upper: T = B C^-1, X = -A^-1 T
+  for (int idx = tid; idx < kTB * kTB; idx += 256) {
+    const int r = idx / kTB, c = idx % kTB;
+    double sum = 0.0;
+    for (int t = 0; t < kTB; ++t) sum = fma(Bm[r][t], kUpper ? Ci[t][c] : Ai[t][c], sum);
+    T[r][c] = sum;
+  }
+  __syncthreads();
+  double* out = D128 + (int64_t)blk * kTS * kTS;
+  for (int idx = tid; idx < kTS * kTS; idx += 256) {
+    const int r = idx / kTS, c = idx % kTS;
+    const int rh = r / kTB, ch = c / kTB, rl = r % kTB, cl = c % kTB;
+    double v = 0.0;
+    if (rh == 0 && ch == 0) {
+      v = Ai[rl][cl];
+    } else if (rh == 1 && ch == 1) {
+      v = Ci[rl][cl];
+    } else if (kUpper ? (rh == 0 && ch == 1) : (rh == 1 && ch == 0)) {
+      double sum = 0.0;
+      for (int t = 0; t < kTB; ++t) sum = fma(kUpper ? Ai[rl][t] : Ci[rl][t], T[t][cl], sum);
+      v = -sum;
+    }
+    out[idx] = v;
+  }
 }
 
 // Inverse of each 64 x 64 diagonal block of L (unit lower) or U (upper) in
@@ -620,57 +751,67 @@ void launch_residual(const double* A, int64_t ld, int n, const double* b, const 
 template <class F>
 void trsv_pair(const void* S, int64_t ld, const int* permS, int n, bool upper, const double* in,
                const int* permIn, const double* Dinv, double* y, double scale, double* out64,
-               float* out32, int* flags, int epoch, const CycleState* gate, int step, int* abortp,
-               hipStream_t s) {
+               float* out32, uint64_t* xw, int epoch, const CycleState* gate, int step,
+               int* abortp, hipStream_t s) {
   using T = typename F::T;
-  const unsigned grid = nblocks(n, kTB);
+  const unsigned grid = nblocks(n, kTS);
   const T* Sp = reinterpret_cast<const T*>(S);
   if (upper)
-    hipLaunchKernelGGL((k_trsv<F, true>), dim3(grid), dim3(256), 0, s, Sp, ld, permS, n, in,
-                       permIn, Dinv, y, scale, out64, out32, flags, epoch, gate, step, abortp);
+    hipLaunchKernelGGL((k_trsv<F, true>), dim3(grid), dim3(kTSThreads), 0, s, Sp, ld, permS, n,
+                       in, permIn, Dinv, y, scale, out64, out32, xw, (uint32_t)epoch, gate, step,
+                       abortp);
   else
-    hipLaunchKernelGGL((k_trsv<F, false>), dim3(grid), dim3(256), 0, s, Sp, ld, permS, n, in,
-                       permIn, Dinv, y, 1.0, nullptr, nullptr, flags, epoch, gate, step, abortp);
+    hipLaunchKernelGGL((k_trsv<F, false>), dim3(grid), dim3(kTSThreads), 0, s, Sp, ld, permS, n,
+                       in, permIn, Dinv, y, 1.0, nullptr, nullptr, xw, (uint32_t)epoch, gate,
+                       step, abortp);
 }
 
 void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
                        const double* in, const int* permIn, const double* Linv, double* y,
-                       int* flags, int epoch, const CycleState* gate, int step, int* abortp,
+                       uint64_t* xw, int epoch, const CycleState* gate, int step, int* abortp,
                        hipStream_t s) {
   if (store == kStoreF16)
-    trsv_pair<Fp16>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, flags,
+    trsv_pair<Fp16>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, xw,
                     epoch, gate, step, abortp, s);
   else if (store == kStoreBF16)
-    trsv_pair<Bf16>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, flags,
+    trsv_pair<Bf16>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, xw,
                     epoch, gate, step, abortp, s);
   else
-    trsv_pair<Fp32>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, flags,
+    trsv_pair<Fp32>(S, ld, permS, n, false, in, permIn, Linv, y, 1.0, nullptr, nullptr, xw,
                     epoch, gate, step, abortp, s);
 }
 
 void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
                        const double* yin, const double* Uinv, double* z, double scale,
-                       double* out64, float* out32, int* flags, int epoch, const CycleState* gate,
-                       int step, int* abortp, hipStream_t s) {
+                       double* out64, float* out32, uint64_t* xw, int epoch,
+                       const CycleState* gate, int step, int* abortp, hipStream_t s) {
   if (store == kStoreF16)
-    trsv_pair<Fp16>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, flags,
+    trsv_pair<Fp16>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, xw,
                     epoch, gate, step, abortp, s);
   else if (store == kStoreBF16)
-    trsv_pair<Bf16>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, flags,
+    trsv_pair<Bf16>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, xw,
                     epoch, gate, step, abortp, s);
   else
-    trsv_pair<Fp32>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, flags,
+    trsv_pair<Fp32>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, xw,
                     epoch, gate, step, abortp, s);
 }
 
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,
-                          double* Linv, double* Uinv, hipStream_t s) {
-  const unsigned grid = nblocks(n, kTB);
+                          double* Linv, double* Uinv, double* tmp, hipStream_t s) {
+  const unsigned g64 = nblocks(n, kTB);
+  const unsigned g128 = nblocks(n, kTS);
 #define GIR_DINV(F)                                                                          \
-  hipLaunchKernelGGL((k_diag_inverse<F, false>), dim3(grid), dim3(kTB), 0, s,                \
-                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, Linv);         \
-  hipLaunchKernelGGL((k_diag_inverse<F, true>), dim3(grid), dim3(kTB), 0, s,                 \
-                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, Uinv)
+  do {                                                                                       \
+    const typename F::T* Sp = reinterpret_cast<const typename F::T*>(S);                     \
+    hipLaunchKernelGGL((k_diag_inverse<F, false>), dim3(g64), dim3(kTB), 0, s, Sp, ld, permS, \
+                       n, tmp);                                                              \
+    hipLaunchKernelGGL((k_diag_combine<F, false>), dim3(g128), dim3(256), 0, s, Sp, ld, permS, \
+                       n, tmp, Linv);                                                        \
+    hipLaunchKernelGGL((k_diag_inverse<F, true>), dim3(g64), dim3(kTB), 0, s, Sp, ld, permS,  \
+                       n, tmp);                                                              \
+    hipLaunchKernelGGL((k_diag_combine<F, true>), dim3(g128), dim3(256), 0, s, Sp, ld, permS, \
+                       n, tmp, Uinv);                                                        \
+  } while (0)
   if (store == kStoreF16) {
     GIR_DINV(Fp16);
   } else if (store == kStoreBF16) {

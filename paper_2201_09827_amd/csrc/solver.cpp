@@ -140,6 +140,7 @@ struct gmresir_ctx {
   int* permS = nullptr;   // equals perm after gmresir_factor, null after import
   int* ipiv = nullptr;
   double *Linv = nullptr, *Uinv = nullptr;  // inverses of the diagonal blocks
+  double* dtmp = nullptr;                    // 64 x 64 inverses (factor time)
   // LU scratch
   uint64_t* xch = nullptr;  // pivot exchange of the block-column kernel (LU only)
   // solve buffers (length ld, zero padded)
@@ -155,7 +156,7 @@ struct gmresir_ctx {
   unsigned int* counter = nullptr;
   unsigned long long* norms = nullptr;
   gir::CycleState* st = nullptr;
-  int *flagsL = nullptr, *flagsU = nullptr;
+  uint64_t *xwL = nullptr, *xwU = nullptr;  // tagged partial solutions of the two solves
   int epoch = 0;
   // pinned host staging
   gir::CycleState* st_host = nullptr;  // one slot per queued step
@@ -170,10 +171,10 @@ struct gmresir_ctx {
 
   ~gmresir_ctx() {
     // permP and permS alias perm
-    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, xch,
+    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, dtmp, xch,
                     x, b, r64, t64, y64, z64, z32, w32, d32, r32, V, C, U, Cn, Un, Hd, Bd, cs,
                     sn, g, h1, h2, nrm, coefA, coefB, Mdev, Gdev, partial, counter, norms, st,
-                    flagsL, flagsU};
+                    xwL, xwU};
     for (void* p : bufs)
       if (p) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
@@ -319,11 +320,11 @@ int alloc_solve(gmresir_ctx* h) {
   GIR_TRY(dalloc(&h->Gdev, 4096));
   const size_t grid = (ld + 255) / 256;
   GIR_TRY(dalloc(&h->partial, grid * 4096));
-  const int nblk = (int)((h->n + 63) / 64);
-  GIR_TRY(dalloc(&h->flagsL, nblk));
-  GIR_TRY(dalloc(&h->flagsU, nblk));
-  GIR_HIP(hipMemsetAsync(h->flagsL, 0, sizeof(int) * nblk, h->stream));
-  GIR_HIP(hipMemsetAsync(h->flagsU, 0, sizeof(int) * nblk, h->stream));
+  const int64_t nxw = 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
+  GIR_TRY(dalloc(&h->xwL, (size_t)nxw));
+  GIR_TRY(dalloc(&h->xwU, (size_t)nxw));
+  gir::launch_fill_i32(reinterpret_cast<int*>(h->xwL), 0, 2 * nxw, h->stream);
+  gir::launch_fill_i32(reinterpret_cast<int*>(h->xwU), 0, 2 * nxw, h->stream);
   // zero padding of every vector
   double* dv[] = {h->x, h->b, h->r64, h->t64, h->y64, h->z64};
   for (double* p : dv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(double) * ld, h->stream));
@@ -347,9 +348,10 @@ int alloc_common(gmresir_ctx* h) {
   GIR_TRY(dalloc(reinterpret_cast<char**>(&h->S), n * ld * store_bytes(h->store)));
   GIR_TRY(dalloc(&h->perm, n));
   GIR_TRY(dalloc(&h->ipiv, n));
-  const size_t nblk = (n + 63) / 64;
-  GIR_TRY(dalloc(&h->Linv, nblk * 64 * 64));
-  GIR_TRY(dalloc(&h->Uinv, nblk * 64 * 64));
+  const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
+  GIR_TRY(dalloc(&h->Linv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+  GIR_TRY(dalloc(&h->Uinv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+  GIR_TRY(dalloc(&h->dtmp, ((n + 63) / 64) * 64 * 64));
   GIR_TRY(dalloc(&h->st, 1));
   GIR_TRY(dalloc(&h->counter, 4));
   GIR_TRY(dalloc(&h->norms, 4));
@@ -440,7 +442,8 @@ int run_lu(gmresir_ctx* h) {
   int* flag = reinterpret_cast<int*>(h->counter + 2);
   GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
   gir::launch_check_factors(h->S, n, h->ld, h->store, flag, h->stream);
-  gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->stream);
+  gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->dtmp,
+                            h->stream);
   gir::CycleState hs{};
   int hflag = 0;
   GIR_TRY(download(h, &hs, h->st, sizeof(hs)));
@@ -505,12 +508,12 @@ int precond(gmresir_ctx* h, const double* in, const int* permIn, double* out64, 
   const int eL = next_epoch(h);
   GIR_TRY(timed(h, kKcTrsvL, bytes, h->stream, gate, step, [&] {
     gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->Linv, h->y64,
-                           h->flagsL, eL, gate, step, &h->st->abort, h->stream);
+                           h->xwL, eL, gate, step, &h->st->abort, h->stream);
   }));
   const int eU = next_epoch(h);
   GIR_TRY(timed(h, kKcTrsvU, bytes, h->stream, gate, step, [&] {
     gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->Uinv, h->z64,
-                           h->scale, out64, out32, h->flagsU, eU, gate, step, &h->st->abort,
+                           h->scale, out64, out32, h->xwU, eU, gate, step, &h->st->abort,
                            h->stream);
   }));
   return 0;
@@ -1018,7 +1021,7 @@ int gmresir_import_factors(const double* A, int64_t n, int64_t lda, const void* 
     h->permS = nullptr;
     if (rc == 0) {
       gir::launch_diag_inverses(h->S, h->ld, nullptr, h->store, (int)n, h->Linv, h->Uinv,
-                                h->stream);
+                                h->dtmp, h->stream);
       if (hipGetLastError() != hipSuccess) rc = GMRESIR_EHIP;
     }
   }

@@ -110,6 +110,43 @@ def test_preconditioned_products_with_shared_factors(lib, n):
     assert same > 0.99
 
 
+@pytest.mark.parametrize("n", [4097, 8192])
+def test_preconditioner_full_size_properties(lib, n):
+    """At the benchmark's size (oracle too slow): y = M^-1 v must satisfy
+    L U (2^-e y) = P v to the fp64 substitution bound with the library's own
+    factors (checked on the GPU in fp64), likewise A-tilde v against P A_u v;
+    the same launch configuration as the benchmark's solves."""
+    from synthetic import randsvd_problem_torch
+    log(f"[apply-full] n={n}")
+    a, _, _ = randsvd_problem_torch(n, 1e2, 3, "cuda")
+    h = lib.factor(a, m=30, k=10)
+    assert h.status == 0
+    raw, ipiv, e = h.export_factors()
+    lu = torch.from_numpy(raw.view(np.float16)).to("cuda").to(torch.float64)
+    del raw
+    L = torch.tril(lu, -1) + torch.eye(n, dtype=torch.float64, device="cuda")
+    U = torch.triu(lu)
+    del lu
+    perm = np.arange(n)
+    for i, j in enumerate(ipiv):
+        perm[[i, j]] = perm[[j, i]]
+    pt = torch.from_numpy(perm).to("cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    v = torch.randn(n, dtype=torch.float64, device="cuda", generator=g).float().double()
+    au = a.float().double()
+    for op, rhs in ((0, v[pt]), (1, (au @ v)[pt])):
+        y = h.apply(op, v) * 2.0 ** (-e)
+        lhs = L @ (U @ y)
+        res = torch.max(torch.abs(lhs - rhs)).item()
+        bound = (torch.max(torch.sum(torch.abs(L), 1)) * torch.max(torch.sum(torch.abs(U), 1))
+                 * torch.max(torch.abs(y))).item()
+        rel = res / bound
+        log(f"[apply-full] n={n} op={op} relative residual {rel:.2e}")
+        assert rel <= 4 * n * U64
+    h.free()
+
+
 def _run_oracle(p, o, f=None):
     f = refine.factor(p.a, o) if f is None else f
     x, info = refine.solve(f, p.b)
