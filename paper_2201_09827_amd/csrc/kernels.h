@@ -37,10 +37,15 @@ struct PanelArgs {
 constexpr int64_t kPanelXchWords = 2 * 32 * 80;
 // one block column of the blocked right-looking GEPP (lazy row interchanges)
 void launch_panel_step(const PanelArgs& a, int store, hipStream_t s);
-// the block row to the right of the panel (U12 = L11^-1 A12)
-void launch_trsm(const PanelArgs& a, int store, hipStream_t s);
-// the trailing update A22 -= L21 U12 on the matrix cores
-void launch_gemm_update(const PanelArgs& a, int store, hipStream_t s);
+// the block row to the right of the panel (U12 = L11^-1 A12), columns
+// [c_begin, c_end)
+void launch_trsm(const PanelArgs& a, int store, int c_begin, int c_end, hipStream_t s);
+// the trailing update A22 -= L21 U12 on the matrix cores for columns
+// [c_begin, c_end); trailing rows located through rows[k0 + kb ..] (perm or
+// a copy of it)
+void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_begin, int c_end,
+                        hipStream_t s);
+void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s);
 // after the last panel: non-finite check of the factors
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,
                           hipStream_t s);

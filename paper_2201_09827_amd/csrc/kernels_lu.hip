@@ -86,6 +86,12 @@ __global__ void k_iota(int* p, int64_t n) {
     p[i] = (int)i;
 }
 
+__global__ void k_copy_i32(int* __restrict__ dst, const int* __restrict__ src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 __global__ void k_fill_i32(int* p, int v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -424,11 +430,11 @@ constexpr int kTrsmThreads = 64;
 template <class F>
 __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict__ S, int64_t ld,
                                                        const int* __restrict__ perm, int k0,
-                                                       int n) {
+                                                       int c_begin, int c_end) {
   __shared__ __align__(16) float Lt[kMaxNb][kMaxNb];  // Lt[t][r] = L11[r][t]
   __shared__ int prow[kMaxNb];
   const int tid = threadIdx.x;
-  const int64_t c = (int64_t)k0 + kMaxNb + (int64_t)blockIdx.x * kTrsmThreads + tid;
+  const int64_t c = (int64_t)c_begin + (int64_t)blockIdx.x * kTrsmThreads + tid;
   prow[tid] = perm[k0 + tid];
   __syncthreads();
   for (int t = 0; t < kMaxNb; ++t) {
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict
     Lt[t][r] = (r > t) ? F::to_f(S[(int64_t)prow[r] * ld + k0 + t]) : 0.0f;
   }
   __syncthreads();
-  if (c >= n) return;
+  if (c >= c_end) return;
   float y[kMaxNb];
 #pragma unroll
   for (int t = 0; t < kMaxNb; ++t) y[t] = F::to_f(S[(int64_t)prow[t] * ld + c]);
@@ -510,18 +516,19 @@ struct Mfma<Fp32> {
 
 template <class F>
 __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__ S, int64_t ld,
-                                                     const int* __restrict__ perm, int k0,
-                                                     int kb, int n) {
+                                                     const int* __restrict__ perm,
+                                                     const int* __restrict__ rows, int k0,
+                                                     int kb, int n, int c_begin, int c_end) {
   using T = typename F::T;
   __shared__ T As[kTile][kKP];
   __shared__ T Bs[kTile][kKP];
   __shared__ int rowp[kTile];
   __shared__ int krow[kMaxNb];
   const int tid = threadIdx.x;
-  const int M = n - k0 - kb;
+  const int M = n - k0 - kb;  // trailing rows (logical k0 + kb ..), through `rows`
   const int tm = blockIdx.y * kTile;
-  const int tn = blockIdx.x * kTile;
-  if (tid < kTile) rowp[tid] = (tm + tid < M) ? perm[k0 + kb + tm + tid] : -1;
+  const int tn = c_begin + blockIdx.x * kTile;  // first column of the tile
+  if (tid < kTile) rowp[tid] = (tm + tid < M) ? rows[k0 + kb + tm + tid] : -1;
   if (tid < kMaxNb) krow[tid] = (tid < kb) ? perm[k0 + tid] : -1;
   __syncthreads();
   // A = -L21 (negated so that the product accumulates C - A B)
@@ -537,7 +544,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
     const int k = idx / kTile;
     const int c = idx % kTile;
     T v = F::from_f(0.0f);
-    if (k < kb && tn + c < M) v = S[(int64_t)krow[k] * ld + k0 + kb + tn + c];
+    if (k < kb && tn + c < c_end) v = S[(int64_t)krow[k] * ld + tn + c];
     Bs[c][k] = v;
   }
   __syncthreads();
@@ -559,7 +566,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
           const int r = wr + i * 32 + 8 * g + 4 * hi + e;
           const int c = wc + j * 32 + l32;
           float v = 0.0f;
-          if (rowp[r] >= 0 && tn + c < M) v = F::to_f(S[(int64_t)rowp[r] * ld + k0 + kb + tn + c]);
+          if (rowp[r] >= 0 && tn + c < c_end) v = F::to_f(S[(int64_t)rowp[r] * ld + tn + c]);
           acc[i][j][4 * g + e] = v;
         }
   const int kchunks = (kb + 7) / 8;
@@ -581,8 +588,8 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
         for (int e = 0; e < 4; ++e) {
           const int r = wr + i * 32 + 8 * g + 4 * hi + e;
           const int c = wc + j * 32 + l32;
-          if (rowp[r] >= 0 && tn + c < M)
-            S[(int64_t)rowp[r] * ld + k0 + kb + tn + c] = F::from_f(acc[i][j][4 * g + e]);
+          if (rowp[r] >= 0 && tn + c < c_end)
+            S[(int64_t)rowp[r] * ld + tn + c] = F::from_f(acc[i][j][4 * g + e]);
         }
 }
 
@@ -606,22 +613,22 @@ void panel_step_t(const PanelArgs& a, hipStream_t s) {
 }
 
 template <class F>
-void trsm_t(const PanelArgs& a, hipStream_t s) {
+void trsm_t(const PanelArgs& a, int c_begin, int c_end, hipStream_t s) {
   using T = typename F::T;
-  const int M = a.n - a.k0 - a.kb;
-  if (M <= 0) return;  // kb == 64 whenever M > 0
-  hipLaunchKernelGGL(k_trsm<F>, dim3((M + kTrsmThreads - 1) / kTrsmThreads), dim3(kTrsmThreads),
-                     0, s, reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0, a.n);
+  if (c_end <= c_begin) return;  // kb == 64 whenever a column lies right of the panel
+  hipLaunchKernelGGL(k_trsm<F>, dim3((c_end - c_begin + kTrsmThreads - 1) / kTrsmThreads),
+                     dim3(kTrsmThreads), 0, s, reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0,
+                     c_begin, c_end);
 }
 
 template <class F>
-void gemm_update_t(const PanelArgs& a, hipStream_t s) {
+void gemm_update_t(const PanelArgs& a, const int* rows, int c_begin, int c_end, hipStream_t s) {
   using T = typename F::T;
   const int M = a.n - a.k0 - a.kb;
-  if (M <= 0) return;
-  const int t = (M + kTile - 1) / kTile;
-  hipLaunchKernelGGL(k_gemm_update<F>, dim3(t, t), dim3(256), 0, s, reinterpret_cast<T*>(a.S),
-                     a.ld, a.perm, a.k0, a.kb, a.n);
+  if (M <= 0 || c_end <= c_begin) return;
+  const dim3 grid((c_end - c_begin + kTile - 1) / kTile, (M + kTile - 1) / kTile);
+  hipLaunchKernelGGL(k_gemm_update<F>, grid, dim3(256), 0, s, reinterpret_cast<T*>(a.S), a.ld,
+                     a.perm, rows, a.k0, a.kb, a.n, c_begin, c_end);
 }
 
 }  // namespace
@@ -667,22 +674,29 @@ void launch_panel_step(const PanelArgs& a, int store, hipStream_t s) {
     panel_step_t<Fp32>(a, s);
 }
 
-void launch_trsm(const PanelArgs& a, int store, hipStream_t s) {
+void launch_trsm(const PanelArgs& a, int store, int c_begin, int c_end, hipStream_t s) {
   if (store == kStoreF16)
-    trsm_t<Fp16>(a, s);
+    trsm_t<Fp16>(a, c_begin, c_end, s);
   else if (store == kStoreBF16)
-    trsm_t<Bf16>(a, s);
+    trsm_t<Bf16>(a, c_begin, c_end, s);
   else
-    trsm_t<Fp32>(a, s);
+    trsm_t<Fp32>(a, c_begin, c_end, s);
 }
 
-void launch_gemm_update(const PanelArgs& a, int store, hipStream_t s) {
+void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_begin, int c_end,
+                        hipStream_t s) {
   if (store == kStoreF16)
-    gemm_update_t<Fp16>(a, s);
+    gemm_update_t<Fp16>(a, rows, c_begin, c_end, s);
   else if (store == kStoreBF16)
-    gemm_update_t<Bf16>(a, s);
+    gemm_update_t<Bf16>(a, rows, c_begin, c_end, s);
   else
-    gemm_update_t<Fp32>(a, s);
+    gemm_update_t<Fp32>(a, rows, c_begin, c_end, s);
+}
+
+void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)),
+                     dim3(256), 0, s, dst, src, n);
 }
 
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,

@@ -143,6 +143,9 @@ struct gmresir_ctx {
   double* dtmp = nullptr;                    // 64 x 64 inverses (factor time)
   // LU scratch
   uint64_t* xch = nullptr;  // pivot exchange of the block-column kernel (LU only)
+  int* perm_rest = nullptr;  // permutation copy read by the lookahead remainder (LU only)
+  hipStream_t s_aux = nullptr;
+  hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
   // solve buffers (length ld, zero padded)
   double *x = nullptr, *b = nullptr, *r64 = nullptr, *t64 = nullptr, *y64 = nullptr,
          *z64 = nullptr;
@@ -171,7 +174,7 @@ struct gmresir_ctx {
 
   ~gmresir_ctx() {
     // permP and permS alias perm
-    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, dtmp, xch,
+    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, dtmp, xch, perm_rest,
                     x, b, r64, t64, y64, z64, z32, w32, d32, r32, V, C, U, Cn, Un, Hd, Bd, cs,
                     sn, g, h1, h2, nrm, coefA, coefB, Mdev, Gdev, partial, counter, norms, st,
                     xwL, xwU};
@@ -181,6 +184,9 @@ struct gmresir_ctx {
     if (hbuf) (void)hipHostFree(hbuf);
     for (auto& e2 : ev) (void)hipEventDestroy(e2);
     for (auto& e2 : tpool) (void)hipEventDestroy(e2);
+    if (ev_panel) (void)hipEventDestroy(ev_panel);
+    if (ev_rest) (void)hipEventDestroy(ev_rest);
+    if (s_aux) (void)hipStreamDestroy(s_aux);
   }
 };
 
@@ -424,20 +430,60 @@ int run_lu(gmresir_ctx* h) {
   a.ipiv = h->ipiv;
   a.xch = xch;
   a.st = h->st;
+  // Lookahead: after block column k is factored, the update of block column
+  // k + 1 (TRSM + GEMM on its 64 columns) runs on the main stream, followed
+  // by the factorisation of block column k + 1, while the update of the
+  // columns beyond it runs on a second stream.  That remainder reads the
+  // trailing rows through a copy of the permutation taken before block
+  // column k + 1 rewrites it; the main stream waits for it before it touches
+  // those columns again.
+  hipStream_t s0 = h->stream;
+  if (!h->s_aux) GIR_HIP(hipStreamCreateWithFlags(&h->s_aux, hipStreamNonBlocking));
+  if (!h->ev_panel) GIR_HIP(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
+  if (!h->ev_rest) GIR_HIP(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming));
+  hipStream_t s1 = h->s_aux;
+  int* prow = nullptr;
+  GIR_TRY(dalloc(&prow, (size_t)n));
+  h->perm_rest = prow;
+  const double es = (double)store_bytes(h->store);
+  bool rest_pending = false;
   for (int k0 = 0; k0 < n; k0 += kNb) {
     a.k0 = k0;
     a.kb = std::min(kNb, n - k0);
-    const double es = (double)store_bytes(h->store);
     const double hr = (double)(n - k0), kb = (double)a.kb, M = hr - kb;
-    GIR_TRY(timed(h, kKcPanel, 2.0 * hr * kb * es, h->stream, nullptr, 0,
-                  [&] { gir::launch_panel_step(a, h->store, h->stream); }));
-    if (M > 0) {
-      GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * M) * es, h->stream, nullptr, 0,
-                    [&] { gir::launch_trsm(a, h->store, h->stream); }));
-      GIR_TRY(timed(h, kKcGemm, (2.0 * M * M + 2.0 * M * kb) * es, h->stream, nullptr, 0,
-                    [&] { gir::launch_gemm_update(a, h->store, h->stream); }));
+    if (k0 == 0)
+      GIR_TRY(timed(h, kKcPanel, 2.0 * hr * kb * es, s0, nullptr, 0,
+                    [&] { gir::launch_panel_step(a, h->store, s0); }));
+    if (M <= 0) break;
+    const int c1 = k0 + a.kb;                    // next block column
+    const int c2 = std::min(n, c1 + kNb);        // ... and the columns beyond it
+    // the remainder of step k - 1 must be done before this step's update
+    if (rest_pending) GIR_HIP(hipStreamWaitEvent(s0, h->ev_rest, 0));
+    if (c2 < n) {
+      gir::launch_copy_i32(prow + c1, h->perm + c1, n - c1, s0);
+      GIR_HIP(hipEventRecord(h->ev_panel, s0));
+      GIR_HIP(hipStreamWaitEvent(s1, h->ev_panel, 0));
+      GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (n - c2)) * es, s1, nullptr, 0,
+                    [&] { gir::launch_trsm(a, h->store, c2, n, s1); }));
+      GIR_TRY(timed(h, kKcGemm, (2.0 * M * (n - c2) + M * kb + kb * (n - c2)) * es, s1, nullptr,
+                    0, [&] { gir::launch_gemm_update(a, h->store, prow, c2, n, s1); }));
+      GIR_HIP(hipEventRecord(h->ev_rest, s1));
+      rest_pending = true;
+    } else {
+      rest_pending = false;
     }
+    GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (c2 - c1)) * es, s0, nullptr, 0,
+                  [&] { gir::launch_trsm(a, h->store, c1, c2, s0); }));
+    GIR_TRY(timed(h, kKcGemm, (2.0 * M * (c2 - c1) + M * kb + kb * (c2 - c1)) * es, s0, nullptr,
+                  0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
+    gir::PanelArgs an = a;
+    an.k0 = c1;
+    an.kb = std::min(kNb, n - c1);
+    const double hn = (double)(n - c1);
+    GIR_TRY(timed(h, kKcPanel, 2.0 * hn * an.kb * es, s0, nullptr, 0,
+                  [&] { gir::launch_panel_step(an, h->store, s0); }));
   }
+  if (rest_pending) GIR_HIP(hipStreamWaitEvent(s0, h->ev_rest, 0));
   GIR_HIP(hipGetLastError());
   int* flag = reinterpret_cast<int*>(h->counter + 2);
   GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
@@ -458,9 +504,11 @@ int run_lu(gmresir_ctx* h) {
   } else if (hflag) {
     h->status = GMRESIR_ERANGE;
   }
-  // the exchange buffer is not needed by the solve phase
+  // the exchange buffer and the permutation copy are not needed by the solve
   (void)hipFree(h->xch);
+  (void)hipFree(h->perm_rest);
   h->xch = nullptr;
+  h->perm_rest = nullptr;
   return 0;
 }
 
