@@ -474,7 +474,7 @@ typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kTile = 128;
-constexpr int kKP = kMaxNb + 4;  // padded LDS row (elements)
+constexpr int kKP = kMaxNb + 8;  // padded LDS row of -L21 and U12^T (elements, 16-byte multiple)
 
 template <class F>
 struct Mfma;
@@ -514,14 +514,23 @@ struct Mfma<Fp32> {
   }
 };
 
+// C tile 128 x 128 of the trailing matrix, rows gathered through `rows`:
+// C <- fl_uf(C + sum_k (-L21)(:,k) U12(k,:)).  The product is accumulated in
+// fp32 on the matrix cores from zero (4 waves, 2 x 2 blocks of 32 x 32 each)
+// and added to C once; every operand moves between HBM and LDS in 16-byte
+// coalesced pieces (the -L21 block, U12 transposed, and C both ways).
+constexpr int kCP = kTile + 8;  // padded LDS row of the C tile (elements)
+
 template <class F>
 __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__ S, int64_t ld,
                                                      const int* __restrict__ perm,
                                                      const int* __restrict__ rows, int k0,
                                                      int kb, int n, int c_begin, int c_end) {
   using T = typename F::T;
-  __shared__ T As[kTile][kKP];
-  __shared__ T Bs[kTile][kKP];
+  constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte piece
+  __shared__ __align__(16) T As[kTile][kKP];
+  __shared__ __align__(16) T Bt[kTile][kKP];
+  __shared__ __align__(16) T Cs[kTile][kCP];
   __shared__ int rowp[kTile];
   __shared__ int krow[kMaxNb];
   const int tid = threadIdx.x;
@@ -531,21 +540,42 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
   if (tid < kTile) rowp[tid] = (tm + tid < M) ? rows[k0 + kb + tm + tid] : -1;
   if (tid < kMaxNb) krow[tid] = (tid < kb) ? perm[k0 + tid] : -1;
   __syncthreads();
-  // A = -L21 (negated so that the product accumulates C - A B)
-  for (int idx = tid; idx < kTile * kMaxNb; idx += 256) {
-    const int r = idx / kMaxNb;
-    const int k = idx % kMaxNb;
-    T v = F::from_f(0.0f);
-    if (rowp[r] >= 0 && k < kb) v = F::from_f(-F::to_f(S[(int64_t)rowp[r] * ld + k0 + k]));
-    As[r][k] = v;
+  // -L21: 128 rows x 64 (kb == 64 whenever there is a trailing matrix)
+  for (int q = tid; q < kTile * (kMaxNb / V); q += 256) {
+    const int r = q / (kMaxNb / V), kc = q % (kMaxNb / V);
+    T t[V];
+    if (rowp[r] >= 0) {
+      const uint4 w = *reinterpret_cast<const uint4*>(S + (int64_t)rowp[r] * ld + k0 + kc * V);
+      __builtin_memcpy(t, &w, 16);
+#pragma unroll
+      for (int e = 0; e < V; ++e) t[e] = F::from_f(-F::to_f(t[e]));
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; ++e) t[e] = F::from_f(0.0f);
+    }
+    uint4 w2;
+    __builtin_memcpy(&w2, t, 16);
+    *reinterpret_cast<uint4*>(&As[r][kc * V]) = w2;
   }
-  // B = U12 transposed into LDS
-  for (int idx = tid; idx < kTile * kMaxNb; idx += 256) {
-    const int k = idx / kTile;
-    const int c = idx % kTile;
-    T v = F::from_f(0.0f);
-    if (k < kb && tn + c < c_end) v = S[(int64_t)krow[k] * ld + tn + c];
-    Bs[c][k] = v;
+  // U12 rows k, columns tn .. tn + 127, stored transposed
+  for (int q = tid; q < kMaxNb * (kTile / V); q += 256) {
+    const int k = q / (kTile / V), cc = q % (kTile / V);
+    const int c = tn + cc * V;
+    T t[V];
+    if (c < ld) {
+      const uint4 w = *reinterpret_cast<const uint4*>(S + (int64_t)krow[k] * ld + c);
+      __builtin_memcpy(t, &w, 16);
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) Bt[cc * V + e][k] = (c + e < c_end) ? t[e] : F::from_f(0.0f);
+  }
+  // C tile
+  for (int q = tid; q < kTile * (kTile / V); q += 256) {
+    const int r = q / (kTile / V), cc = q % (kTile / V);
+    const int c = tn + cc * V;
+    uint4 w = make_uint4(0, 0, 0, 0);
+    if (rowp[r] >= 0 && c < ld) w = *reinterpret_cast<const uint4*>(S + (int64_t)rowp[r] * ld + c);
+    *reinterpret_cast<uint4*>(&Cs[r][cc * V]) = w;
   }
   __syncthreads();
   const int wave = tid / kWave;
@@ -560,24 +590,17 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = wr + i * 32 + 8 * g + 4 * hi + e;
-          const int c = wc + j * 32 + l32;
-          float v = 0.0f;
-          if (rowp[r] >= 0 && tn + c < c_end) v = F::to_f(S[(int64_t)rowp[r] * ld + tn + c]);
-          acc[i][j][4 * g + e] = v;
-        }
-  const int kchunks = (kb + 7) / 8;
-  for (int kk = 0; kk < kchunks; ++kk) {
+  for (int kk = 0; kk < kMaxNb / 8; ++kk) {
     const int ko = kk * 8 + 4 * hi;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        acc[i][j] = Mfma<F>::step(&As[wr + i * 32 + l32][ko], &Bs[wc + j * 32 + l32][ko], acc[i][j]);
+        acc[i][j] = Mfma<F>::step(&As[wr + i * 32 + l32][ko], &Bt[wc + j * 32 + l32][ko], acc[i][j]);
   }
+  // C + product in fp32, rounded to u_f once
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -588,9 +611,20 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
         for (int e = 0; e < 4; ++e) {
           const int r = wr + i * 32 + 8 * g + 4 * hi + e;
           const int c = wc + j * 32 + l32;
-          if (rowp[r] >= 0 && tn + c < c_end)
-            S[(int64_t)rowp[r] * ld + tn + c] = F::from_f(acc[i][j][4 * g + e]);
+          Cs[r][c] = F::from_f(F::to_f(Cs[r][c]) + acc[i][j][4 * g + e]);
         }
+  __syncthreads();
+  for (int q = tid; q < kTile * (kTile / V); q += 256) {
+    const int r = q / (kTile / V), cc = q % (kTile / V);
+    const int c = tn + cc * V;
+    if (rowp[r] < 0 || c >= c_end) continue;
+    T* dst = S + (int64_t)rowp[r] * ld + c;
+    if (c + V <= c_end) {
+      *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(&Cs[r][cc * V]);
+    } else {
+      for (int e = 0; c + e < c_end; ++e) dst[e] = Cs[r][cc * V + e];
+    }
+  }
 }
 
 template <class F>
