@@ -72,6 +72,14 @@ void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, i
                        const double* y, const double* Uinv, double* z, double scale,
                        double* out64, float* out32, uint64_t* xw, int epoch,
                        const CycleState* gate, int step, int* abort, hipStream_t s);
+// the lower (upper = false) or upper solve for nr <= 8 right-hand sides at
+// once: in / out column-major (ldi / ldo), out = scale * solution; xw holds
+// nr slots of xstride >= 2 * ceil(n/128) * 128 tagged words
+constexpr int kTrsvMaxRhs = 8;
+void launch_trsv_multi(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
+                       const double* in, int64_t ldi, const int* permIn, int nr,
+                       const double* Dinv, double* out, int64_t ldo, double scale, uint64_t* xw,
+                       int64_t xstride, int epoch, int* abortp, hipStream_t s);
 // fp64 inverses of the 128 x 128 diagonal blocks of L and U (ceil(n/128)
 // blocks of 128 x 128 each, row-major); tmp: ceil(n/64) * 64 * 64 doubles
 constexpr int kTrsvBlock = 128;

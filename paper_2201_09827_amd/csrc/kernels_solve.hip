@@ -373,6 +373,151 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   put_tagged(xw, rr, v, epoch);
 }
 
+// The same blocked solve for nr <= 8 right-hand sides at once (the recycle
+// set-up applies M^-1 to k vectors): each tile row of the factor is read once
+// for all of them, and one round trip fetches the nr published values of a
+// row.  in / out are column-major (ldi / ldo); right-hand side r exchanges its
+// words in xw + r * xstride.
+
+template <class F, bool kUpper>
+__global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
+    const typename F::T* __restrict__ S, int64_t ld, const int* __restrict__ permS, int n,
+    const double* __restrict__ in, int64_t ldi, const int* __restrict__ permIn, int nr,
+    const double* __restrict__ Dinv, double* __restrict__ out, int64_t ldo, double scale,
+    uint64_t* xw, int64_t xstride, uint32_t epoch, int* abortp) {
+  constexpr int NR = kTrsvMaxRhs;
+  __shared__ double ysh[8][NR][kTB];
+  __shared__ double zsh[NR][kTS];
+  __shared__ double part[4][NR][kTS];
+  __shared__ int wok[8];
+  const int nb = (n + kTS - 1) / kTS;
+  const int nt = (n + kTB - 1) / kTB;
+  const int blk = kUpper ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int r0 = blk * kTS;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int half = wave >> 2;
+  const int wq = wave & 3;
+  const int row = r0 + half * kTB + lane;
+  const bool valid = row < n;
+  const int prow = valid ? (permS ? permS[row] : row) : 0;
+  const typename F::T* srow = S + (int64_t)prow * ld;
+  const int di = tid % kTS;
+  const int dq4 = tid / kTS;
+  double dq[kTS / 4];
+  {
+    const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
+#pragma unroll
+    for (int c = 0; c < kTS / 4; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(drow + c);
+      dq[c] = v.x;
+      dq[c + 1] = v.y;
+    }
+  }
+  double rhs[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    rhs[r] = 0.0;
+    if (r < nr && tid < kTS && r0 + tid < n) {
+      const int rr = r0 + tid;
+      rhs[r] = in[(int64_t)r * ldi + (permIn ? permIn[rr] : rr)];
+    }
+  }
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  bool ok = true;
+  const int t0 = kUpper ? 2 * blk + 2 : 0;
+  const int t1 = kUpper ? nt : 2 * blk;
+  for (int i = wq;; i += 4) {
+    const int J = kUpper ? t1 - 1 - i : t0 + i;
+    if (kUpper ? (J < t0) : (J >= t1)) break;
+    RawRow<F> lv;
+    lv.load(srow, J * kTB, n, valid);
+    // the nr published values of row J * 64 + lane, fetched together
+    {
+      const int c = J * kTB + lane;
+      long long spins = 0;
+      for (;;) {
+        bool got = true;
+        double v[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          v[r] = 0.0;
+          if (r < nr) {
+            const uint64_t* p = xw + (int64_t)r * xstride + 2 * c;
+            const uint64_t lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t hi = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            got = got && (uint32_t)(lo >> 32) == epoch && (uint32_t)(hi >> 32) == epoch;
+            v[r] = __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
+          }
+        }
+        if (__all(got)) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) ysh[wave][r][lane] = v[r];
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (((++spins) & 1023) == 0) {
+          if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+              spins > (1ll << 22)) {
+            __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+          }
+        }
+      }
+    }
+    if (!ok) break;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < kTB; ++c) {
+      const double a = lv.at(c);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] = fma(a, ysh[wave][r][c], acc[r]);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) ysh[wave][r][lane] = acc[r];
+  if (lane == 0) wok[wave] = ok ? 1 : 0;
+  __syncthreads();
+  int allok = 1;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) allok &= wok[w];
+  if (!allok) return;
+  if (tid < kTS) {
+    const int h = tid / kTB, l = tid % kTB;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double sum = (ysh[4 * h][r][l] + ysh[4 * h + 1][r][l]) +
+                         (ysh[4 * h + 2][r][l] + ysh[4 * h + 3][r][l]);
+      zsh[r][tid] = (r0 + tid < n) ? rhs[r] - sum : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double p = 0.0;
+#pragma unroll
+    for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[r][dq4 * (kTS / 4) + c], p);
+    part[dq4][r][di] = p;
+  }
+  __syncthreads();
+  if (tid >= kTS) return;
+  const int rr = r0 + tid;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) break;
+    const double v =
+        (rr < n) ? (part[0][r][tid] + part[1][r][tid]) + (part[2][r][tid] + part[3][r][tid]) : 0.0;
+    if (rr < n) out[(int64_t)r * ldo + rr] = v * scale;
+    put_tagged(xw + (int64_t)r * xstride, rr, v, epoch);
+  }
+}
+
 // 128 x 128 inverses of the diagonal blocks from the 64 x 64 ones (D64):
 //   lower [A 0; B C]^-1 = [A^-1 0; -C^-1 B A^-1  C^-1]
 //   upper [A B; 0 C]^-1 = [A^-1  -A^-1 B C^-1; 0 C^-1]
@@ -794,6 +939,25 @@ void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, i
   else
     trsv_pair<Fp32>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, xw,
                     epoch, gate, step, abortp, s);
+}
+
+void launch_trsv_multi(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
+                       const double* in, int64_t ldi, const int* permIn, int nr,
+                       const double* Dinv, double* out, int64_t ldo, double scale, uint64_t* xw,
+                       int64_t xstride, int epoch, int* abortp, hipStream_t s) {
+  const unsigned grid = nblocks(n, kTS);
+#define GIR_TM(F, U)                                                                          \
+  hipLaunchKernelGGL((k_trsv_multi<F, U>), dim3(grid), dim3(kTSThreads), 0, s,                \
+                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, ldi, permIn, \
+                     nr, Dinv, out, ldo, scale, xw, xstride, (uint32_t)epoch, abortp)
+  if (store == kStoreF16) {
+    if (upper) GIR_TM(Fp16, true); else GIR_TM(Fp16, false);
+  } else if (store == kStoreBF16) {
+    if (upper) GIR_TM(Bf16, true); else GIR_TM(Bf16, false);
+  } else {
+    if (upper) GIR_TM(Fp32, true); else GIR_TM(Fp32, false);
+  }
+#undef GIR_TM
 }
 
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,

@@ -160,6 +160,8 @@ struct gmresir_ctx {
   unsigned long long* norms = nullptr;
   gir::CycleState* st = nullptr;
   uint64_t *xwL = nullptr, *xwU = nullptr;  // tagged partial solutions of the two solves
+  uint64_t *xwLm = nullptr, *xwUm = nullptr;  // the same for the multi-vector solves
+  double *Tb = nullptr, *Yb = nullptr;        // ld x 8 blocks for the multi-vector product
   int epoch = 0;
   // pinned host staging
   gir::CycleState* st_host = nullptr;  // one slot per queued step
@@ -177,7 +179,7 @@ struct gmresir_ctx {
     void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, dtmp, xch, perm_rest,
                     x, b, r64, t64, y64, z64, z32, w32, d32, r32, V, C, U, Cn, Un, Hd, Bd, cs,
                     sn, g, h1, h2, nrm, coefA, coefB, Mdev, Gdev, partial, counter, norms, st,
-                    xwL, xwU};
+                    xwL, xwU, xwLm, xwUm, Tb, Yb};
     for (void* p : bufs)
       if (p) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
@@ -331,6 +333,15 @@ int alloc_solve(gmresir_ctx* h) {
   GIR_TRY(dalloc(&h->xwU, (size_t)nxw));
   gir::launch_fill_i32(reinterpret_cast<int*>(h->xwL), 0, 2 * nxw, h->stream);
   gir::launch_fill_i32(reinterpret_cast<int*>(h->xwU), 0, 2 * nxw, h->stream);
+  if (h->k > 0) {
+    const int64_t nm = nxw * gir::kTrsvMaxRhs;
+    GIR_TRY(dalloc(&h->xwLm, (size_t)nm));
+    GIR_TRY(dalloc(&h->xwUm, (size_t)nm));
+    gir::launch_fill_i32(reinterpret_cast<int*>(h->xwLm), 0, 2 * nm, h->stream);
+    gir::launch_fill_i32(reinterpret_cast<int*>(h->xwUm), 0, 2 * nm, h->stream);
+    GIR_TRY(dalloc(&h->Tb, (size_t)h->ld * gir::kTrsvMaxRhs));
+    GIR_TRY(dalloc(&h->Yb, (size_t)h->ld * gir::kTrsvMaxRhs));
+  }
   // zero padding of every vector
   double* dv[] = {h->x, h->b, h->r64, h->t64, h->y64, h->z64};
   for (double* p : dv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(double) * ld, h->stream));
@@ -579,6 +590,38 @@ int atilde(gmresir_ctx* h, const float* v32, const double* v64, double* out64, f
   return precond(h, h->t64, nullptr, out64, out32, gate, step);
 }
 
+// C(:, 0:kk) = A-tilde Y(:, 0:kk) for fp64 columns (ld apart): the products
+// with A_u one column at a time, the two triangular solves for up to eight
+// columns at once
+int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
+  const int n = (int)h->n;
+  const int64_t ld = h->ld;
+  const int64_t xstride = 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
+  const double nn = (double)n;
+  const double tbytes = 0.5 * nn * (nn + 1.0) * (double)store_bytes(h->store);
+  for (int c0 = 0; c0 < kk; c0 += gir::kTrsvMaxRhs) {
+    const int nr = std::min(gir::kTrsvMaxRhs, kk - c0);
+    for (int r = 0; r < nr; ++r)
+      GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + 16.0 * nn, h->stream, nullptr, 0, [&] {
+        gir::launch_gemv_au(h->Au, ld, h->permP, n, nullptr, Y + (size_t)(c0 + r) * ld,
+                            h->Tb + (size_t)r * ld, nullptr, 0, h->stream);
+      }));
+    const int eL = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvL, tbytes + 16.0 * nr * nn, h->stream, nullptr, 0, [&] {
+      gir::launch_trsv_multi(h->S, ld, h->permS, h->store, n, false, h->Tb, ld, nullptr, nr,
+                             h->Linv, h->Yb, ld, 1.0, h->xwLm, xstride, eL, &h->st->abort,
+                             h->stream);
+    }));
+    const int eU = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvU, tbytes + 16.0 * nr * nn, h->stream, nullptr, 0, [&] {
+      gir::launch_trsv_multi(h->S, ld, h->permS, h->store, n, true, h->Yb, ld, nullptr, nr,
+                             h->Uinv, C + (size_t)c0 * ld, ld, h->scale, h->xwUm, xstride, eU,
+                             &h->st->abort, h->stream);
+    }));
+  }
+  return 0;
+}
+
 gir::Basis basis(const double* c, int kc, int64_t ldc, const float* v, int nv, int64_t ldv) {
   gir::Basis X;
   X.c64 = c;
@@ -658,8 +701,7 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   // recycled space from the previous system: C = QR(A-tilde Y), U = Y R^-1
   if (k > 0 && h->kc_keep > 0) {
     const int kk = h->kc_keep;
-    for (int c = 0; c < kk; ++c)
-      GIR_TRY(atilde(h, nullptr, h->U + (size_t)c * ld, h->C + (size_t)c * ld, nullptr, nullptr, 0));
+    GIR_TRY(atilde_block(h, h->U, kk, h->C));
     GIR_HIP(hipGetLastError());
     // CholeskyQR2 in fp64
     std::vector<double> G1, G2, R1(kk * kk), R2(kk * kk), Ri(kk * kk), Rt(kk * kk);
