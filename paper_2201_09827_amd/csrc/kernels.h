@@ -30,6 +30,7 @@ struct PanelArgs {
   int kb;           // panel width (<= nb)
   int* perm;        // logical -> physical rows, rewritten for rows k0.. by the panel
   int* ipiv;        // [n] LAPACK-style (0-based)
+  int* perm_copy;   // null, or receives the same rewrite of rows k0.. as perm
   uint64_t* xch;    // [kPanelXchWords] pivot exchange, zeroed before the first panel
   CycleState* st;   // abort + singular reporting
 };

@@ -151,23 +151,26 @@ __device__ __forceinline__ bool poll_tagged(const uint64_t* p, bool need, uint32
   }
 }
 
+// 64 values of a row from a 16-byte aligned address whose 64-element span
+// lies inside the padded row (k0 + 64 <= ld); columns >= kb read as zero
 template <class F>
 __device__ __forceinline__ void load_panel_row(const typename F::T* src, int kb, bool in,
                                                float (&x)[kMaxNb]) {
   using T = typename F::T;
   constexpr int kPer = 16 / sizeof(T);
-  if (in && kb == kMaxNb) {
+  if (in) {
 #pragma unroll
     for (int v = 0; v < kMaxNb / kPer; ++v) {
       const uint4 w = reinterpret_cast<const uint4*>(src)[v];
       T t[kPer];
       __builtin_memcpy(t, &w, 16);
 #pragma unroll
-      for (int e = 0; e < kPer; ++e) x[v * kPer + e] = F::to_f(t[e]);
+      for (int e = 0; e < kPer; ++e)
+        x[v * kPer + e] = (v * kPer + e < kb) ? F::to_f(t[e]) : 0.0f;
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < kMaxNb; ++c) x[c] = (in && c < kb) ? F::to_f(src[c]) : 0.0f;
+    for (int c = 0; c < kMaxNb; ++c) x[c] = 0.0f;
   }
 }
 
@@ -224,12 +227,14 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
                                                             int64_t ld, int* __restrict__ perm,
                                                             int k0, int kb, int h,
                                                             int* __restrict__ ipiv,
+                                                            int* __restrict__ perm_copy,
                                                             uint64_t* __restrict__ xch,
                                                             CycleState* st) {
   using T = typename F::T;
   __shared__ uint64_t kw[kRowWaves];
   __shared__ __align__(16) float rowbuf[kMaxNb];
   __shared__ __align__(16) float recv[kMaxPanelWgs][kMaxNb];
+  __shared__ __align__(16) float rowsave[kMaxNb][kMaxNb];  // pivot rows owned by this workgroup
   __shared__ uint64_t s_win;
   __shared__ int s_gw;
   __shared__ int s_abort;
@@ -334,6 +339,9 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
       W = s_win;
       u = recv[s_gw];
     }
+    // the workgroup that owns the pivot row keeps its values (final once
+    // chosen) for the write-back at the end
+    if (wave == 0 && (G == 1 || s_gw == g)) rowsave[c][lane] = rowbuf[lane];
     const int wl = (int)(0x1FFFFu - (uint32_t)(W & 0x1FFFFull));
     const float piv = u[c];
     if (g == 0 && tid == 0) {
@@ -341,9 +349,8 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
       if (piv == 0.0f) atomicCAS(&st->singular, 0, k0 + c + 1);
     }
     if (!pv && lid == wl) {
-      // the pivot row is final: write it now; its registers are eliminated
-      // with the others below (to zeros) and never stored again
-      store_panel_row<F>(row, kb, x);
+      // the pivot row: its final values are in rowsave[c]; its registers are
+      // eliminated with the others below (to zeros) and not stored
       lid = c;
       pv = true;
     } else if (!pv && lid == c) {
@@ -411,11 +418,16 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
     }
   }
   if (in) {
-    if (!pv) store_panel_row<F>(row, kb, x);
+    if (pv) {
+#pragma unroll
+      for (int j = 0; j < kMaxNb; ++j) x[j] = rowsave[lid][j];
+    }
+    store_panel_row<F>(row, kb, x);
     // every workgroup read its permutation entries before publishing its
     // first key, and no workgroup gets here before it has read every
     // workgroup's last key: the in-place rewrite is safe
     perm[k0 + lid] = phys;
+    if (perm_copy) perm_copy[k0 + lid] = phys;
   }
 }
 
@@ -437,9 +449,13 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict
   const int64_t c = (int64_t)c_begin + (int64_t)blockIdx.x * kTrsmThreads + tid;
   prow[tid] = perm[k0 + tid];
   __syncthreads();
-  for (int t = 0; t < kMaxNb; ++t) {
-    const int r = tid;
-    Lt[t][r] = (r > t) ? F::to_f(S[(int64_t)prow[r] * ld + k0 + t]) : 0.0f;
+  {
+    // row r = tid of L11 in 16-byte pieces (all loads in flight at once),
+    // written transposed; entries on and above the diagonal are zero
+    float lrow[kMaxNb];
+    load_panel_row<F>(S + (int64_t)prow[tid] * ld + k0, kMaxNb, true, lrow);
+#pragma unroll
+    for (int t = 0; t < kMaxNb; ++t) Lt[t][tid] = (tid > t) ? lrow[t] : 0.0f;
   }
   __syncthreads();
   if (c >= c_end) return;
@@ -643,7 +659,8 @@ void panel_step_t(const PanelArgs& a, hipStream_t s) {
   const int h = a.n - a.k0;
   const int G = (h + kRowThreads - 1) / kRowThreads;
   hipLaunchKernelGGL(k_panel_rows<F>, dim3(G), dim3(kRowThreads), 0, s,
-                     reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0, a.kb, h, a.ipiv, a.xch, a.st);
+                     reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0, a.kb, h, a.ipiv, a.perm_copy,
+                     a.xch, a.st);
 }
 
 template <class F>

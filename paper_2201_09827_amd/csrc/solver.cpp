@@ -444,52 +444,57 @@ int run_lu(gmresir_ctx* h) {
   // Lookahead: after block column k is factored, the update of block column
   // k + 1 (TRSM + GEMM on its 64 columns) runs on the main stream, followed
   // by the factorisation of block column k + 1, while the update of the
-  // columns beyond it runs on a second stream.  That remainder reads the
-  // trailing rows through a copy of the permutation taken before block
-  // column k + 1 rewrites it; the main stream waits for it before it touches
-  // those columns again.
+  // columns beyond it runs on a second stream.  That remainder locates the
+  // trailing rows through a copy of the permutation written by block column
+  // k (two copies, alternating, so that block column k + 1 can write the
+  // other); the main stream waits for the remainder before it touches those
+  // columns again.
   hipStream_t s0 = h->stream;
   if (!h->s_aux) GIR_HIP(hipStreamCreateWithFlags(&h->s_aux, hipStreamNonBlocking));
   if (!h->ev_panel) GIR_HIP(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
   if (!h->ev_rest) GIR_HIP(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming));
   hipStream_t s1 = h->s_aux;
   int* prow = nullptr;
-  GIR_TRY(dalloc(&prow, (size_t)n));
+  GIR_TRY(dalloc(&prow, 2 * (size_t)n));
   h->perm_rest = prow;
   const double es = (double)store_bytes(h->store);
   bool rest_pending = false;
-  for (int k0 = 0; k0 < n; k0 += kNb) {
+  int step = 0;
+  for (int k0 = 0; k0 < n; k0 += kNb, ++step) {
     a.k0 = k0;
     a.kb = std::min(kNb, n - k0);
     const double hr = (double)(n - k0), kb = (double)a.kb, M = hr - kb;
-    if (k0 == 0)
+    int* pcopy = prow + (size_t)(step & 1) * n;  // written by block column `step`
+    if (k0 == 0) {
+      a.perm_copy = pcopy;
       GIR_TRY(timed(h, kKcPanel, 2.0 * hr * kb * es, s0, nullptr, 0,
                     [&] { gir::launch_panel_step(a, h->store, s0); }));
+    }
     if (M <= 0) break;
-    const int c1 = k0 + a.kb;                    // next block column
-    const int c2 = std::min(n, c1 + kNb);        // ... and the columns beyond it
-    // the remainder of step k - 1 must be done before this step's update
+    const int c1 = k0 + a.kb;                // next block column
+    const int c2 = std::min(n, c1 + kNb);    // ... and the columns beyond it
+    // the remainder of the previous step must be done before this update
     if (rest_pending) GIR_HIP(hipStreamWaitEvent(s0, h->ev_rest, 0));
+    GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (c2 - c1)) * es, s0, nullptr, 0,
+                  [&] { gir::launch_trsm(a, h->store, c1, c2, s0); }));
+    GIR_TRY(timed(h, kKcGemm, (2.0 * M * (c2 - c1) + M * kb + kb * (c2 - c1)) * es, s0, nullptr,
+                  0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
     if (c2 < n) {
-      gir::launch_copy_i32(prow + c1, h->perm + c1, n - c1, s0);
       GIR_HIP(hipEventRecord(h->ev_panel, s0));
       GIR_HIP(hipStreamWaitEvent(s1, h->ev_panel, 0));
       GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (n - c2)) * es, s1, nullptr, 0,
                     [&] { gir::launch_trsm(a, h->store, c2, n, s1); }));
       GIR_TRY(timed(h, kKcGemm, (2.0 * M * (n - c2) + M * kb + kb * (n - c2)) * es, s1, nullptr,
-                    0, [&] { gir::launch_gemm_update(a, h->store, prow, c2, n, s1); }));
+                    0, [&] { gir::launch_gemm_update(a, h->store, pcopy, c2, n, s1); }));
       GIR_HIP(hipEventRecord(h->ev_rest, s1));
       rest_pending = true;
     } else {
       rest_pending = false;
     }
-    GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (c2 - c1)) * es, s0, nullptr, 0,
-                  [&] { gir::launch_trsm(a, h->store, c1, c2, s0); }));
-    GIR_TRY(timed(h, kKcGemm, (2.0 * M * (c2 - c1) + M * kb + kb * (c2 - c1)) * es, s0, nullptr,
-                  0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
     gir::PanelArgs an = a;
     an.k0 = c1;
     an.kb = std::min(kNb, n - c1);
+    an.perm_copy = prow + (size_t)((step + 1) & 1) * n;
     const double hn = (double)(n - c1);
     GIR_TRY(timed(h, kKcPanel, 2.0 * hn * an.kb * es, s0, nullptr, 0,
                   [&] { gir::launch_panel_step(an, h->store, s0); }));
