@@ -3,9 +3,10 @@
  * Krylov subspace recycling (RGMRES-IR).
  *
  * Method: Oktay & Carson, "Mixed Precision GMRES-based Iterative Refinement
- * with Recycling".  gmresir_factor is line 1 of Algorithm 3 (LU factorisation
- * in precision u_f); gmresir_solve is lines 2-7 of Algorithm 3 (refinement
- * loop whose correction equation U^-1 L^-1 A d = U^-1 L^-1 r is solved by the
+ * with Recycling".  gmresir_factor is the factorisation step of Algorithm 3
+ * (LU factorisation in precision u_f); gmresir_solve is the rest of
+ * Algorithm 3 (the initial solve and the refinement loop, whose correction
+ * equation U^-1 L^-1 A d = U^-1 L^-1 r is solved by the
  * GCRO-DR algorithm of Section 2, with the preconditioned product computed in
  * precision u^2).  With k = 0 the correction solver is restarted GMRES(m),
  * i.e. Algorithm 2 (GMRES-IR).
@@ -111,7 +112,7 @@ typedef struct gmresir_ctx gmresir_ctx;
 void gmresir_default_opts(gmresir_opts* opts);
 
 /*
- * gmresir_factor -- Algorithm 3, line 1: LU factorisation with partial
+ * gmresir_factor -- Algorithm 3, factorisation step: LU with partial
  * pivoting of A in precision u_f (Section 1, GEPP), plus the copies of A
  * the solve needs (A in fp64 for the residual, A_u = fl_u(A) for the
  * preconditioned product) and ||A||_inf.
@@ -133,7 +134,7 @@ int gmresir_factor(const double* A, int64_t n, int64_t lda,
                    const gmresir_opts* opts, void* stream, gmresir_ctx** out);
 
 /*
- * gmresir_solve -- Algorithm 3, lines 2-7: x0 = M^-1 b, then refinement
+ * gmresir_solve -- Algorithm 3 after the factorisation: x0 = M^-1 b, then refinement
  * steps r = b - A x (in u_r), r-hat = r / ||r||_inf, GCRO-DR(m, k) on
  * U^-1 L^-1 P A d = U^-1 L^-1 P r-hat with the product in u^2, and
  * x = x + ||r||_inf d, until the backward error reaches opts.berr_target.

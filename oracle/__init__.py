@@ -11,7 +11,7 @@ Refinement with Recycling"):
 * :mod:`oracle.fp` -- rounding to fp16/bf16/fp32 and double-double
   arithmetic (the paper's simulated precisions, Section 3 and Table
   "tab:eps");
-* :mod:`oracle.lu` -- GEPP in u_f (line 1 of Algorithms 1-3);
+* :mod:`oracle.lu` -- GEPP in u_f (the factorisation step of Algorithms 1-3);
 * :mod:`oracle.krylov` -- GMRES(m) and GCRO-DR(m, k) (Algorithm "GCRO-DR",
   Section 2);
 * :mod:`oracle.refine` -- GMRES-IR (Algorithm 2) and RGMRES-IR (Algorithm 3).

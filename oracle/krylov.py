@@ -4,7 +4,8 @@ Test infrastructure only.  Follows Algorithm "GCRO-DR" in Section 2 of the
 paper (Parks et al. 2006) as used inside RGMRES-IR (Algorithm 3), on a
 preconditioned operator passed as a callback.  With k = 0 every cycle is a
 plain GMRES(m) cycle, which is GMRES-IR's correction solve (Algorithm 2);
-the paper's "fair comparison" uses exactly that (Section 3).
+the paper compares RGMRES-IR(m, k) against GMRES-IR with the same m
+(Section 3).
 
 Readings of the paper used here (the paper is silent or has misprints):
 

@@ -1,11 +1,11 @@
 """LU factorisation with partial pivoting in precision u_f (oracle).
 
-Test infrastructure only.  Follows line 1 of Algorithms 1-3 of the paper
-("compute the LU factorisation A ~ LU in precision u_f") with Gaussian
+Test infrastructure only.  Follows the factorisation step of Algorithms 1-3
+of the paper (an LU factorisation of A in precision u_f) with Gaussian
 elimination with partial pivoting (GEPP, Section 1), written out step by step.
 
-Build mode (:func:`lu_blocked`) fixes where rounding happens, because the
-paper only says "in u_f":
+Build mode (:func:`lu_blocked`) fixes where rounding happens, which the paper
+leaves open beyond naming the precision u_f:
 
 * the matrix lives in u_f between block steps;
 * a panel of ``nb`` columns is copied into the LU work precision wp (fp32 for

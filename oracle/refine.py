@@ -122,7 +122,7 @@ class Info:
 
 
 def factor(a: np.ndarray, opts: Options) -> Factors:
-    """Line 1 of Algorithm 3: LU factorisation in u_f (with conversions)."""
+    """The factorisation step of Algorithm 3: LU in u_f (with conversions)."""
     opts.validate()
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
     n = a.shape[0]
@@ -262,7 +262,7 @@ def solve(f: Factors, b: np.ndarray, state: RecycleState | None = None,
     if x0 is not None:
         x = np.array(x0, dtype=np.float64)
     elif o.mode == "paper":
-        # substitution in u_f, stored in u (paper, line 2)
+        # substitution in u_f, stored in u (the paper's initial solve)
         t = b[f.perm]
         y = np.zeros(f.n)
         for i in range(f.n):

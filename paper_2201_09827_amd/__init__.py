@@ -303,7 +303,7 @@ class Handle:
 
 
 def factor(a, stream=None, **opts) -> Handle:
-    """LU-factorise A (Algorithm 3, line 1).  ``a``: square row-major float64
+    """LU-factorise A (the factorisation step of Algorithm 3).  ``a``: square row-major float64
     CUDA tensor.  Options: uf, u, ur ('fp16', 'bf16', 'fp32', 'fp64', 'dd'),
     m, k, tau, imax, maxit, berr_target, scale_pow2, keep_recycle, timing.  Raises
     GmresirError on a negative status; ESINGULAR/ERANGE return a handle whose

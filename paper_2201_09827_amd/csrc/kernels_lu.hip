@@ -1,5 +1,5 @@
-// LU factorisation with partial pivoting in u_f on gfx950 (Algorithm 1-3,
-// line 1; GEPP as in Section 1 of the paper).
+// LU factorisation with partial pivoting in u_f on gfx950 (the factorisation
+// step of Algorithms 1-3; GEPP as in Section 1 of the paper).
 //
 // Blocked right-looking GEPP with "lazy" row interchanges: rows are never
 // moved in memory during the factorisation; a permutation vector maps the

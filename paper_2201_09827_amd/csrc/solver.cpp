@@ -264,11 +264,11 @@ int validate_opts(const gmresir_opts* o) {
     return GMRESIR_EINVAL;
   }
   if (o->u != GMRESIR_FP32) {
-    set_error("this build supports u = FP32 (u^2 = fp64)");
+    set_error("this library supports u = FP32 (u^2 = fp64)");
     return GMRESIR_EINVAL;
   }
   if (o->ur != GMRESIR_FP64) {
-    set_error("this build supports ur = FP64");
+    set_error("this library supports ur = FP64");
     return GMRESIR_EINVAL;
   }
   if (!(rf <= ru && ru <= rr)) {

@@ -5,7 +5,7 @@ random numbers and builds the test matrices the paper uses; it contains none
 of the solver's arithmetic (no rounding to low precision, no factorisation,
 no Krylov method).
 
-Matrices (Section 3 of the paper, "Implementation and experimental setup"):
+Matrices (Section 3 of the paper, the experimental setup):
 
 * ``randsvd``: dense A = U diag(sigma) V^T with U, V Haar-distributed
   orthogonal matrices and geometrically spaced singular values from 1 down to

@@ -1,7 +1,7 @@
 """GPU parity: the HIP library against the CPU oracle on the same seeded
 inputs (all calls go through the C ABI via the ctypes binding).
 
-Bars (from the specification of the build):
+Bars:
 * LU: pivots identical; u_f entries identical except rare one-ulp splits of
   the fp32-accumulated trailing update; componentwise backward error within
   the blocked-GEPP bound.
