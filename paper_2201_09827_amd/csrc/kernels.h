@@ -46,6 +46,10 @@ void launch_trsm(const PanelArgs& a, int store, int c_begin, int c_end, hipStrea
 // a copy of it)
 void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_begin, int c_end,
                         hipStream_t s);
+// block column p and, in the same launch, the trailing update of step u for
+// columns [c_begin, c_end) (disjoint from block column p), rows through `rows`
+void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
+                         int c_begin, int c_end, hipStream_t s);
 void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s);
 // after the last panel: non-finite check of the factors
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,

@@ -222,27 +222,35 @@ __device__ __forceinline__ float eliminate_col(float (&x)[kMaxNb], float l, cons
 
 constexpr int kMaxPanelWgs = 32;  // h <= 16384
 
+struct PanelSmem {
+  uint64_t kw[kRowWaves];
+  uint64_t s_win;
+  int s_gw;
+  int s_abort;
+  alignas(16) float rowbuf[kMaxNb];
+  alignas(16) float recv[kMaxPanelWgs][kMaxNb];
+  alignas(16) float rowsave[kMaxNb][kMaxNb];  // pivot rows owned by this workgroup
+};
+
+// Block column k0 .. k0 + kb - 1 over rows k0 .. k0 + h - 1 (logical), run by
+// workgroup g of the G that share it (512 threads each).
 template <class F>
-__global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __restrict__ S,
-                                                            int64_t ld, int* __restrict__ perm,
-                                                            int k0, int kb, int h,
-                                                            int* __restrict__ ipiv,
-                                                            int* __restrict__ perm_copy,
-                                                            uint64_t* __restrict__ xch,
-                                                            CycleState* st) {
+__device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restrict__ S,
+                                           int64_t ld, int* __restrict__ perm, int k0, int kb,
+                                           int h, int G, int g, int* __restrict__ ipiv,
+                                           int* __restrict__ perm_copy,
+                                           uint64_t* __restrict__ xch, CycleState* st) {
   using T = typename F::T;
-  __shared__ uint64_t kw[kRowWaves];
-  __shared__ __align__(16) float rowbuf[kMaxNb];
-  __shared__ __align__(16) float recv[kMaxPanelWgs][kMaxNb];
-  __shared__ __align__(16) float rowsave[kMaxNb][kMaxNb];  // pivot rows owned by this workgroup
-  __shared__ uint64_t s_win;
-  __shared__ int s_gw;
-  __shared__ int s_abort;
+  uint64_t* kw = sm.kw;
+  float* rowbuf = sm.rowbuf;
+  auto& recv = sm.recv;
+  auto& rowsave = sm.rowsave;
+  uint64_t& s_win = sm.s_win;
+  int& s_gw = sm.s_gw;
+  int& s_abort = sm.s_abort;
   const int tid = threadIdx.x;
   const int lane = tid % kWave;
   const int wave = tid / kWave;
-  const int G = gridDim.x;
-  const int g = blockIdx.x;
   const int q = g * kRowThreads + tid;
   const bool in = q < h;
   int* abortp = &st->abort;
@@ -431,6 +439,18 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_rows(typename F::T* __res
   }
 }
 
+template <class F>
+__global__ __launch_bounds__(kRowThreads) void k_panel(typename F::T* __restrict__ S, int64_t ld,
+                                                       int* __restrict__ perm, int k0, int kb,
+                                                       int h, int* __restrict__ ipiv,
+                                                       int* __restrict__ perm_copy,
+                                                       uint64_t* __restrict__ xch,
+                                                       CycleState* st) {
+  __shared__ PanelSmem sm;
+  panel_rows<F>(sm, S, ld, perm, k0, kb, h, (int)gridDim.x, (int)blockIdx.x, ipiv, perm_copy, xch,
+                st);
+}
+
 // U12 = L11^-1 A12 in fp32 with the stored (u_f) unit lower triangle L11
 // (the block column is always 64 wide here: a narrower one is the last and
 // has nothing to its right).  One thread per column keeps the column's 64
@@ -537,27 +557,41 @@ struct Mfma<Fp32> {
 // coalesced pieces (the -L21 block, U12 transposed, and C both ways).
 constexpr int kCP = kTile + 8;  // padded LDS row of the C tile (elements)
 
+template <class T>
+struct GemmSmem {
+  alignas(16) T As[kTile][kKP];
+  alignas(16) T Bt[kTile][kKP];
+  alignas(16) T Cs[kTile][kCP];
+  int rowp[kTile];
+  int krow[kMaxNb];
+};
+
+// One 128 x 128 tile (bx, by) of the trailing update for columns
+// [c_begin, c_end), rows through `rows`, by a workgroup of 512 threads
+// (8 waves: 2 x 4 blocks of 64 x 32).
 template <class F>
-__global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__ S, int64_t ld,
-                                                     const int* __restrict__ perm,
-                                                     const int* __restrict__ rows, int k0,
-                                                     int kb, int n, int c_begin, int c_end) {
+__device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
+                                          typename F::T* __restrict__ S, int64_t ld,
+                                          const int* __restrict__ perm,
+                                          const int* __restrict__ rows, int k0, int kb, int n,
+                                          int c_begin, int c_end, int bx, int by) {
   using T = typename F::T;
   constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte piece
-  __shared__ __align__(16) T As[kTile][kKP];
-  __shared__ __align__(16) T Bt[kTile][kKP];
-  __shared__ __align__(16) T Cs[kTile][kCP];
-  __shared__ int rowp[kTile];
-  __shared__ int krow[kMaxNb];
+  constexpr int NT = kRowThreads;
+  auto& As = sm.As;
+  auto& Bt = sm.Bt;
+  auto& Cs = sm.Cs;
+  int* rowp = sm.rowp;
+  int* krow = sm.krow;
   const int tid = threadIdx.x;
   const int M = n - k0 - kb;  // trailing rows (logical k0 + kb ..), through `rows`
-  const int tm = blockIdx.y * kTile;
-  const int tn = c_begin + blockIdx.x * kTile;  // first column of the tile
+  const int tm = by * kTile;
+  const int tn = c_begin + bx * kTile;  // first column of the tile
   if (tid < kTile) rowp[tid] = (tm + tid < M) ? rows[k0 + kb + tm + tid] : -1;
   if (tid < kMaxNb) krow[tid] = (tid < kb) ? perm[k0 + tid] : -1;
   __syncthreads();
   // -L21: 128 rows x 64 (kb == 64 whenever there is a trailing matrix)
-  for (int q = tid; q < kTile * (kMaxNb / V); q += 256) {
+  for (int q = tid; q < kTile * (kMaxNb / V); q += NT) {
     const int r = q / (kMaxNb / V), kc = q % (kMaxNb / V);
     T t[V];
     if (rowp[r] >= 0) {
@@ -574,7 +608,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
     *reinterpret_cast<uint4*>(&As[r][kc * V]) = w2;
   }
   // U12 rows k, columns tn .. tn + 127, stored transposed
-  for (int q = tid; q < kMaxNb * (kTile / V); q += 256) {
+  for (int q = tid; q < kMaxNb * (kTile / V); q += NT) {
     const int k = q / (kTile / V), cc = q % (kTile / V);
     const int c = tn + cc * V;
     T t[V];
@@ -586,7 +620,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
     for (int e = 0; e < V; ++e) Bt[cc * V + e][k] = (c + e < c_end) ? t[e] : F::from_f(0.0f);
   }
   // C tile
-  for (int q = tid; q < kTile * (kTile / V); q += 256) {
+  for (int q = tid; q < kTile * (kTile / V); q += NT) {
     const int r = q / (kTile / V), cc = q % (kTile / V);
     const int c = tn + cc * V;
     uint4 w = make_uint4(0, 0, 0, 0);
@@ -596,41 +630,35 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
   __syncthreads();
   const int wave = tid / kWave;
   const int lane = tid % kWave;
-  const int wr = (wave / 2) * 64;
-  const int wc = (wave % 2) * 64;
+  const int wr = (wave / 4) * 64;
+  const int wc = (wave % 4) * 32;
   const int l32 = lane % 32;
   const int hi = lane / 32;
-  float16_t acc[2][2];
+  float16_t acc[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+    for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
 #pragma unroll
   for (int kk = 0; kk < kMaxNb / 8; ++kk) {
     const int ko = kk * 8 + 4 * hi;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = Mfma<F>::step(&As[wr + i * 32 + l32][ko], &Bt[wc + j * 32 + l32][ko], acc[i][j]);
+      acc[i] = Mfma<F>::step(&As[wr + i * 32 + l32][ko], &Bt[wc + l32][ko], acc[i]);
   }
   // C + product in fp32, rounded to u_f once
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = wr + i * 32 + 8 * g + 4 * hi + e;
-          const int c = wc + j * 32 + l32;
-          Cs[r][c] = F::from_f(F::to_f(Cs[r][c]) + acc[i][j][4 * g + e]);
-        }
+      for (int e = 0; e < 4; ++e) {
+        const int r = wr + i * 32 + 8 * g + 4 * hi + e;
+        const int c = wc + l32;
+        Cs[r][c] = F::from_f(F::to_f(Cs[r][c]) + acc[i][4 * g + e]);
+      }
   __syncthreads();
-  for (int q = tid; q < kTile * (kTile / V); q += 256) {
+  for (int q = tid; q < kTile * (kTile / V); q += NT) {
     const int r = q / (kTile / V), cc = q % (kTile / V);
     const int c = tn + cc * V;
     if (rowp[r] < 0 || c >= c_end) continue;
@@ -640,6 +668,42 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename F::T* __restrict__
     } else {
       for (int e = 0; c + e < c_end; ++e) dst[e] = Cs[r][cc * V + e];
     }
+  }
+}
+
+template <class F>
+__global__ __launch_bounds__(kRowThreads) void k_gemm_update(typename F::T* __restrict__ S,
+                                                             int64_t ld,
+                                                             const int* __restrict__ perm,
+                                                             const int* __restrict__ rows, int k0,
+                                                             int kb, int n, int c_begin,
+                                                             int c_end) {
+  __shared__ GemmSmem<typename F::T> sm;
+  gemm_tile<F>(sm, S, ld, perm, rows, k0, kb, n, c_begin, c_end, (int)blockIdx.x,
+               (int)blockIdx.y);
+}
+
+// Block column k + 1 and the remainder of step k's trailing update in one
+// launch: workgroups 0 .. G-1 factor the block column (dispatched first, so
+// they are resident together), the others take the update tiles (columns
+// right of block column k + 1, disjoint from it; the trailing rows are
+// located through the permutation copy of step k, since the block column
+// rewrites perm meanwhile).
+template <class F>
+__global__ __launch_bounds__(kRowThreads) void k_panel_update(
+    typename F::T* __restrict__ S, int64_t ld, int* __restrict__ perm, int pk0, int pkb, int ph,
+    int G, int* __restrict__ ipiv, int* __restrict__ perm_copy, uint64_t* __restrict__ xch,
+    CycleState* st, const int* __restrict__ rows, int k0, int kb, int n, int c_begin, int c_end,
+    int tiles_x) {
+  __shared__ union {
+    PanelSmem p;
+    GemmSmem<typename F::T> g;
+  } sm;
+  if ((int)blockIdx.x < G) {
+    panel_rows<F>(sm.p, S, ld, perm, pk0, pkb, ph, G, (int)blockIdx.x, ipiv, perm_copy, xch, st);
+  } else {
+    const int t = (int)blockIdx.x - G;
+    gemm_tile<F>(sm.g, S, ld, perm, rows, k0, kb, n, c_begin, c_end, t % tiles_x, t / tiles_x);
   }
 }
 
@@ -658,9 +722,22 @@ void panel_step_t(const PanelArgs& a, hipStream_t s) {
   using T = typename F::T;
   const int h = a.n - a.k0;
   const int G = (h + kRowThreads - 1) / kRowThreads;
-  hipLaunchKernelGGL(k_panel_rows<F>, dim3(G), dim3(kRowThreads), 0, s,
-                     reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0, a.kb, h, a.ipiv, a.perm_copy,
-                     a.xch, a.st);
+  hipLaunchKernelGGL(k_panel<F>, dim3(G), dim3(kRowThreads), 0, s, reinterpret_cast<T*>(a.S),
+                     a.ld, a.perm, a.k0, a.kb, h, a.ipiv, a.perm_copy, a.xch, a.st);
+}
+
+template <class F>
+void panel_update_t(const PanelArgs& p, const PanelArgs& u, const int* rows, int c_begin,
+                    int c_end, hipStream_t s) {
+  using T = typename F::T;
+  const int h = p.n - p.k0;
+  const int G = (h + kRowThreads - 1) / kRowThreads;
+  const int M = u.n - u.k0 - u.kb;
+  const int tx = (c_end - c_begin + kTile - 1) / kTile;
+  const int ty = (M + kTile - 1) / kTile;
+  hipLaunchKernelGGL(k_panel_update<F>, dim3(G + tx * ty), dim3(kRowThreads), 0, s,
+                     reinterpret_cast<T*>(p.S), p.ld, p.perm, p.k0, p.kb, h, G, p.ipiv,
+                     p.perm_copy, p.xch, p.st, rows, u.k0, u.kb, u.n, c_begin, c_end, tx);
 }
 
 template <class F>
@@ -678,8 +755,8 @@ void gemm_update_t(const PanelArgs& a, const int* rows, int c_begin, int c_end, 
   const int M = a.n - a.k0 - a.kb;
   if (M <= 0 || c_end <= c_begin) return;
   const dim3 grid((c_end - c_begin + kTile - 1) / kTile, (M + kTile - 1) / kTile);
-  hipLaunchKernelGGL(k_gemm_update<F>, grid, dim3(256), 0, s, reinterpret_cast<T*>(a.S), a.ld,
-                     a.perm, rows, a.k0, a.kb, a.n, c_begin, c_end);
+  hipLaunchKernelGGL(k_gemm_update<F>, grid, dim3(kRowThreads), 0, s, reinterpret_cast<T*>(a.S),
+                     a.ld, a.perm, rows, a.k0, a.kb, a.n, c_begin, c_end);
 }
 
 }  // namespace
@@ -742,6 +819,16 @@ void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_be
     gemm_update_t<Bf16>(a, rows, c_begin, c_end, s);
   else
     gemm_update_t<Fp32>(a, rows, c_begin, c_end, s);
+}
+
+void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
+                         int c_begin, int c_end, hipStream_t s) {
+  if (store == kStoreF16)
+    panel_update_t<Fp16>(p, u, rows, c_begin, c_end, s);
+  else if (store == kStoreBF16)
+    panel_update_t<Bf16>(p, u, rows, c_begin, c_end, s);
+  else
+    panel_update_t<Fp32>(p, u, rows, c_begin, c_end, s);
 }
 
 void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s) {

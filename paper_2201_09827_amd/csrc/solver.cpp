@@ -441,24 +441,18 @@ int run_lu(gmresir_ctx* h) {
   a.ipiv = h->ipiv;
   a.xch = xch;
   a.st = h->st;
-  // Lookahead: after block column k is factored, the update of block column
-  // k + 1 (TRSM + GEMM on its 64 columns) runs on the main stream, followed
-  // by the factorisation of block column k + 1, while the update of the
-  // columns beyond it runs on a second stream.  That remainder locates the
-  // trailing rows through a copy of the permutation written by block column
-  // k (two copies, alternating, so that block column k + 1 can write the
-  // other); the main stream waits for the remainder before it touches those
-  // columns again.
+  // Lookahead on one stream.  Step k: the block row right of block column k
+  // is solved (TRSM, all columns), the next block column k + 1 is updated
+  // (trailing GEMM on its 64 columns), then one launch factors block column
+  // k + 1 while its other workgroups apply step k's update to the columns
+  // beyond it.  That remainder locates the trailing rows through the copy of
+  // the permutation written by block column k (two copies, alternating),
+  // because block column k + 1 rewrites perm at the same time.
   hipStream_t s0 = h->stream;
-  if (!h->s_aux) GIR_HIP(hipStreamCreateWithFlags(&h->s_aux, hipStreamNonBlocking));
-  if (!h->ev_panel) GIR_HIP(hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming));
-  if (!h->ev_rest) GIR_HIP(hipEventCreateWithFlags(&h->ev_rest, hipEventDisableTiming));
-  hipStream_t s1 = h->s_aux;
   int* prow = nullptr;
   GIR_TRY(dalloc(&prow, 2 * (size_t)n));
   h->perm_rest = prow;
   const double es = (double)store_bytes(h->store);
-  bool rest_pending = false;
   int step = 0;
   for (int k0 = 0; k0 < n; k0 += kNb, ++step) {
     a.k0 = k0;
@@ -473,33 +467,26 @@ int run_lu(gmresir_ctx* h) {
     if (M <= 0) break;
     const int c1 = k0 + a.kb;                // next block column
     const int c2 = std::min(n, c1 + kNb);    // ... and the columns beyond it
-    // the remainder of the previous step must be done before this update
-    if (rest_pending) GIR_HIP(hipStreamWaitEvent(s0, h->ev_rest, 0));
-    GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (c2 - c1)) * es, s0, nullptr, 0,
-                  [&] { gir::launch_trsm(a, h->store, c1, c2, s0); }));
+    GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (n - c1)) * es, s0, nullptr, 0,
+                  [&] { gir::launch_trsm(a, h->store, c1, n, s0); }));
     GIR_TRY(timed(h, kKcGemm, (2.0 * M * (c2 - c1) + M * kb + kb * (c2 - c1)) * es, s0, nullptr,
                   0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
-    if (c2 < n) {
-      GIR_HIP(hipEventRecord(h->ev_panel, s0));
-      GIR_HIP(hipStreamWaitEvent(s1, h->ev_panel, 0));
-      GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (n - c2)) * es, s1, nullptr, 0,
-                    [&] { gir::launch_trsm(a, h->store, c2, n, s1); }));
-      GIR_TRY(timed(h, kKcGemm, (2.0 * M * (n - c2) + M * kb + kb * (n - c2)) * es, s1, nullptr,
-                    0, [&] { gir::launch_gemm_update(a, h->store, pcopy, c2, n, s1); }));
-      GIR_HIP(hipEventRecord(h->ev_rest, s1));
-      rest_pending = true;
-    } else {
-      rest_pending = false;
-    }
     gir::PanelArgs an = a;
     an.k0 = c1;
     an.kb = std::min(kNb, n - c1);
     an.perm_copy = prow + (size_t)((step + 1) & 1) * n;
     const double hn = (double)(n - c1);
-    GIR_TRY(timed(h, kKcPanel, 2.0 * hn * an.kb * es, s0, nullptr, 0,
-                  [&] { gir::launch_panel_step(an, h->store, s0); }));
+    const double pbytes = 2.0 * hn * an.kb * es;
+    if (c2 < n) {
+      const double gbytes = (2.0 * M * (n - c2) + M * kb + kb * (n - c2)) * es;
+      GIR_TRY(timed(h, kKcPanel, pbytes + gbytes, s0, nullptr, 0, [&] {
+        gir::launch_panel_update(an, a, h->store, pcopy, c2, n, s0);
+      }));
+    } else {
+      GIR_TRY(timed(h, kKcPanel, pbytes, s0, nullptr, 0,
+                    [&] { gir::launch_panel_step(an, h->store, s0); }));
+    }
   }
-  if (rest_pending) GIR_HIP(hipStreamWaitEvent(s0, h->ev_rest, 0));
   GIR_HIP(hipGetLastError());
   int* flag = reinterpret_cast<int*>(h->counter + 2);
   GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
