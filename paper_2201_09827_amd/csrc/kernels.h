@@ -12,14 +12,16 @@ enum StoreType { kStoreF16 = 0, kStoreBF16 = 1, kStoreF32 = 2 };
 
 // ---- factorisation ---------------------------------------------------------
 
-// scan A (fp64): out[0] = max |a| bits, out[1] = max row-sum bits, flag[0] = 1
-// if a non-finite entry exists.  out/flag must be zeroed.
-void launch_scan(const double* A, int64_t n, int64_t lda,
-                 unsigned long long* out, int* flag, hipStream_t s);
-// S = fl_uf(2^e A) if S != nullptr (row-major, ld), Au = fl32(A) if Au != nullptr; padding
-// columns [n, ld) are zeroed; flag[0] = 1 if a u_f value overflowed.
-void launch_convert(const double* A, int64_t n, int64_t lda, int e, int store,
-                    void* S, float* Au, int64_t ld, int* flag, hipStream_t s);
+// one pass over the caller's A (lda): A64 and Au (if not null) copies with
+// zero padding to ld, norms[0] = max |a| bits, norms[1] = max row-sum bits,
+// flag[0] = 1 on a non-finite entry (norms/flag zeroed beforehand)
+void launch_ingest(const double* A, int64_t n, int64_t lda, double* A64, float* Au, int64_t ld,
+                   unsigned long long* norms, int* flag, hipStream_t s);
+// S = fl_uf(2^e A64), e = the fp16 scale exponent from norms[0] and sqrtn
+// (sqrt(n) as computed on the host) when scaled != 0, else 0; *e_out = e
+void launch_convert_scaled(const double* A64, int64_t n, int64_t ld, int store, void* S,
+                           const unsigned long long* norms, double sqrtn, int scaled, int* e_out,
+                           int* flag, hipStream_t s);
 void launch_iota(int* p, int64_t n, hipStream_t s);
 
 struct PanelArgs {

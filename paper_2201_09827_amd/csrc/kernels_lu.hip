@@ -31,53 +31,99 @@ __device__ __forceinline__ double wave_max_d(double v) {
   return v;
 }
 
-__global__ void k_scan(const double* __restrict__ A, int64_t n, int64_t lda,
-                       unsigned long long* out, int* flag) {
-  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+// One pass over the caller's A: the fp64 copy (A64, zero padded to ld), the
+// fp32 copy A_u (if requested), max |a| and the largest row sum (one atomic
+// per block each) and a flag for non-finite entries.  One wave per row.
+__global__ __launch_bounds__(256) void k_ingest(const double* __restrict__ A, int64_t n,
+                                                int64_t lda, double* __restrict__ A64,
+                                                float* __restrict__ Au, int64_t ld,
+                                                unsigned long long* norms, int* flag) {
+  __shared__ double smax[4], ssum[4];
+  __shared__ int sbad[4];
+  const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  if (row >= n) return;
-  const double* a = A + row * lda;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   double s = 0.0, mx = 0.0;
   int bad = 0;
-  for (int64_t c = lane; c < n; c += kWave) {
-    double v = a[c];
-    if (!__builtin_isfinite(v)) bad = 1;
-    v = fabs(v);
-    s += v;
-    mx = fmax(mx, v);
+  if (row < n) {
+    const double* a = A + row * lda;
+    double* d = A64 + row * ld;
+    float* f = Au ? Au + row * ld : nullptr;
+    for (int64_t c = lane; c < ld; c += kWave) {
+      const double v = (c < n) ? a[c] : 0.0;
+      d[c] = v;
+      if (f) f[c] = (float)v;
+      if (!__builtin_isfinite(v)) bad = 1;
+      const double av = fabs(v);
+      s += av;
+      mx = fmax(mx, av);
+    }
   }
   s = wave_sum(s);
   mx = wave_max_d(mx);
   bad = __any(bad);
   if (lane == 0) {
-    atomic_max_nonneg(out + 0, mx);
-    atomic_max_nonneg(out + 1, s);
-    if (bad) atomicOr(flag, 1);
+    smax[wave] = mx;
+    ssum[wave] = s;
+    sbad[wave] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0, r = 0.0;
+    int b = 0;
+    for (int w = 0; w < 4; ++w) {
+      m = fmax(m, smax[w]);
+      r = fmax(r, ssum[w]);
+      b |= sbad[w];
+    }
+    atomic_max_nonneg(norms + 0, m);
+    atomic_max_nonneg(norms + 1, r);
+    if (b) atomicOr(flag, 1);
   }
 }
 
+// Largest integer e with 2^e * amax * sqrt(n) <= 4094 (exact power-of-two
+// scaling of A before rounding to fp16; sqrt(n) is passed in so that host and
+// device agree bit for bit).
+__device__ __forceinline__ int fp16_scale_exponent_dev(double amax, double sqrtn) {
+  if (!(amax > 0.0) || !__builtin_isfinite(amax)) return 0;
+  const double t = amax * sqrtn;
+  const double limit = 4094.0;
+  int e = (int)floor(log2(limit) - log2(t));
+  while (ldexp(t, e) > limit) --e;
+  while (ldexp(t, e + 1) <= limit) ++e;
+  return e;
+}
+
+// S = fl_uf(2^e A64) with e from max |a| (norms[0]) when `scaled`, else 0;
+// e is also written to e_out; flag[0] = 1 if a u_f value overflowed.
 template <class F>
-__global__ void k_convert(const double* __restrict__ A, int64_t n, int64_t lda, int e,
-                          typename F::T* __restrict__ S, float* __restrict__ Au, int64_t ld,
-                          int* flag) {
-  int bad = 0;
-  for (int64_t r = blockIdx.y; r < n; r += gridDim.y) {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ld;
-         c += (int64_t)gridDim.x * blockDim.x) {
-      const double a = (c < n) ? A[r * lda + c] : 0.0;
-      if (S) {
-        const typename F::T v = F::from_d(ldexp(a, e));
-        if (!F::finite(v)) bad = 1;
-        S[r * ld + c] = v;
-      }
-      if (Au) {
-        const float f = (float)a;
-        if (!__builtin_isfinite(f)) bad = 1;
-        Au[r * ld + c] = f;
-      }
-    }
+__global__ __launch_bounds__(256) void k_convert_scaled(const double* __restrict__ A64, int64_t n,
+                                                        int64_t ld, typename F::T* __restrict__ S,
+                                                        const unsigned long long* __restrict__ norms,
+                                                        double sqrtn, int scaled, int* e_out,
+                                                        int* flag) {
+  __shared__ int se;
+  if (threadIdx.x == 0) {
+    se = scaled ? fp16_scale_exponent_dev(__longlong_as_double((long long)norms[0]), sqrtn) : 0;
+    if (blockIdx.x == 0) *e_out = se;
   }
-  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  const int e = se;
+  int bad = 0;
+  // ld is a multiple of 64: the matrix is a whole number of 2-element pieces
+  const int64_t pairs = n * ld / 2;
+  const double2* src = reinterpret_cast<const double2*>(A64);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < pairs;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double2 v = src[i];
+    const typename F::T a = F::from_d(ldexp(v.x, e));
+    const typename F::T b = F::from_d(ldexp(v.y, e));
+    if (!F::finite(a) || !F::finite(b)) bad = 1;
+    S[2 * i] = a;
+    S[2 * i + 1] = b;
+  }
+  if (__any(bad) && (threadIdx.x % kWave) == 0) atomicOr(flag, 1);
 }
 
 __global__ void k_iota(int* p, int64_t n) {
@@ -761,26 +807,25 @@ void gemm_update_t(const PanelArgs& a, const int* rows, int c_begin, int c_end, 
 
 }  // namespace
 
-void launch_scan(const double* A, int64_t n, int64_t lda, unsigned long long* out, int* flag,
-                 hipStream_t s) {
-  const int rows_per_block = 4;
-  const int64_t blocks = (n + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL(k_scan, dim3((unsigned)blocks), dim3(rows_per_block * kWave), 0, s, A, n,
-                     lda, out, flag);
+void launch_ingest(const double* A, int64_t n, int64_t lda, double* A64, float* Au, int64_t ld,
+                   unsigned long long* norms, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_ingest, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, A, n, lda, A64, Au,
+                     ld, norms, flag);
 }
 
-void launch_convert(const double* A, int64_t n, int64_t lda, int e, int store, void* S,
-                    float* Au, int64_t ld, int* flag, hipStream_t s) {
-  dim3 grid((unsigned)((ld + 255) / 256), (unsigned)std::min<int64_t>(n, 65535));
+void launch_convert_scaled(const double* A64, int64_t n, int64_t ld, int store, void* S,
+                           const unsigned long long* norms, double sqrtn, int scaled, int* e_out,
+                           int* flag, hipStream_t s) {
+  const dim3 grid((unsigned)std::min<int64_t>((n * ld / 2 + 255) / 256, 4096));
   if (store == kStoreF16)
-    hipLaunchKernelGGL(k_convert<Fp16>, grid, dim3(256), 0, s, A, n, lda, e,
-                       reinterpret_cast<_Float16*>(S), Au, ld, flag);
+    hipLaunchKernelGGL(k_convert_scaled<Fp16>, grid, dim3(256), 0, s, A64, n, ld,
+                       reinterpret_cast<_Float16*>(S), norms, sqrtn, scaled, e_out, flag);
   else if (store == kStoreBF16)
-    hipLaunchKernelGGL(k_convert<Bf16>, grid, dim3(256), 0, s, A, n, lda, e,
-                       reinterpret_cast<uint16_t*>(S), Au, ld, flag);
+    hipLaunchKernelGGL(k_convert_scaled<Bf16>, grid, dim3(256), 0, s, A64, n, ld,
+                       reinterpret_cast<uint16_t*>(S), norms, sqrtn, scaled, e_out, flag);
   else
-    hipLaunchKernelGGL(k_convert<Fp32>, grid, dim3(256), 0, s, A, n, lda, e,
-                       reinterpret_cast<float*>(S), Au, ld, flag);
+    hipLaunchKernelGGL(k_convert_scaled<Fp32>, grid, dim3(256), 0, s, A64, n, ld,
+                       reinterpret_cast<float*>(S), norms, sqrtn, scaled, e_out, flag);
 }
 
 void launch_iota(int* p, int64_t n, hipStream_t s) {

@@ -167,6 +167,8 @@ struct gmresir_ctx {
   gir::CycleState* st_host = nullptr;  // one slot per queued step
   double* hbuf = nullptr;              // general small transfers
   size_t hbuf_len = 0;
+  char *up_stage = nullptr, *dl_stage = nullptr;  // pinned staging of small transfers
+  size_t up_off = 0;
   std::vector<hipEvent_t> ev;
   // launch timing (opts.timing): pooled events and pending records
   std::vector<hipEvent_t> tpool;
@@ -184,6 +186,8 @@ struct gmresir_ctx {
       if (p) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
     if (hbuf) (void)hipHostFree(hbuf);
+    if (up_stage) (void)hipHostFree(up_stage);
+    if (dl_stage) (void)hipHostFree(dl_stage);
     for (auto& e2 : ev) (void)hipEventDestroy(e2);
     for (auto& e2 : tpool) (void)hipEventDestroy(e2);
     if (ev_panel) (void)hipEventDestroy(ev_panel);
@@ -370,59 +374,99 @@ int alloc_common(gmresir_ctx* h) {
   GIR_TRY(dalloc(&h->Uinv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
   GIR_TRY(dalloc(&h->dtmp, ((n + 63) / 64) * 64 * 64));
   GIR_TRY(dalloc(&h->st, 1));
-  GIR_TRY(dalloc(&h->counter, 4));
+  GIR_TRY(dalloc(&h->counter, 8));
   GIR_TRY(dalloc(&h->norms, 4));
   GIR_HIP(hipMemsetAsync(h->st, 0, sizeof(gir::CycleState), h->stream));
-  GIR_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned) * 4, h->stream));
+  GIR_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned) * 8, h->stream));
+  return 0;
+}
+
+// Small host <-> device transfers go through pinned staging memory.  An
+// upload copies into the next free piece of the staging arena and queues the
+// copy without waiting; the arena is recycled after the next synchronisation
+// (every download synchronises the stream, so all queued uploads are done).
+constexpr size_t kStageBytes = 64 * 1024;
+
+int stage_init(gmresir_ctx* h) {
+  if (!h->up_stage)
+    GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->up_stage), kStageBytes,
+                          hipHostMallocDefault));
+  if (!h->dl_stage)
+    GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->dl_stage), kStageBytes,
+                          hipHostMallocDefault));
   return 0;
 }
 
 int upload(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
-  GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
-  GIR_HIP(hipStreamSynchronize(h->stream));
+  GIR_TRY(stage_init(h));
+  if (bytes > kStageBytes) {
+    GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
+    GIR_HIP(hipStreamSynchronize(h->stream));
+    h->up_off = 0;
+    return 0;
+  }
+  if (h->up_off + bytes > kStageBytes) {
+    GIR_HIP(hipStreamSynchronize(h->stream));
+    h->up_off = 0;
+  }
+  char* p = h->up_stage + h->up_off;
+  std::memcpy(p, src, bytes);
+  GIR_HIP(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, h->stream));
+  h->up_off += (bytes + 255) & ~size_t(255);
   return 0;
 }
 
 int download(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
-  GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
-  GIR_HIP(hipStreamSynchronize(h->stream));
+  GIR_TRY(stage_init(h));
+  if (bytes > kStageBytes) {
+    GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    GIR_HIP(hipStreamSynchronize(h->stream));
+  } else {
+    GIR_HIP(hipMemcpyAsync(h->dl_stage, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    GIR_HIP(hipStreamSynchronize(h->stream));
+    std::memcpy(dst, h->dl_stage, bytes);
+  }
+  h->up_off = 0;
   return 0;
 }
 
 // copy A into the padded fp64 buffer, scan it, and form A_u
+// Copies of A (fp64 and fp32, zero padded), ||A||_inf, max |a|, the
+// non-finite check and, with make_lu_copy, A_f = fl_uf(2^e A) with the scale
+// exponent chosen on the device: no host round trip.  ingest_finish reads the
+// results back after the next synchronisation.
 int ingest(gmresir_ctx* h, const double* A, int64_t lda, bool make_lu_copy) {
   const int64_t n = h->n, ld = h->ld;
-  GIR_HIP(hipMemsetAsync(h->A64, 0, sizeof(double) * n * ld, h->stream));
-  GIR_HIP(hipMemcpy2DAsync(h->A64, ld * sizeof(double), A, lda * sizeof(double),
-                           n * sizeof(double), n, hipMemcpyDeviceToDevice, h->stream));
-  unsigned long long* scanout = h->norms;  // [0] max|a|, [1] max row sum
-  int* flag = reinterpret_cast<int*>(h->counter + 2);
-  GIR_HIP(hipMemsetAsync(scanout, 0, sizeof(unsigned long long) * 2, h->stream));
-  GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
-  gir::launch_scan(h->A64, n, ld, scanout, flag, h->stream);
+  unsigned long long* norms = h->norms;  // [0] max|a|, [1] max row sum
+  int* iflag = reinterpret_cast<int*>(h->counter + 4);
+  int* e_dev = reinterpret_cast<int*>(h->counter + 5);
+  gir::launch_fill_i32(reinterpret_cast<int*>(norms), 0, 4, h->stream);
+  gir::launch_fill_i32(iflag, 0, 2, h->stream);
+  gir::launch_ingest(A, n, lda, h->A64, h->Au, ld, norms, iflag, h->stream);
+  if (make_lu_copy) {
+    const bool scaled =
+        (h->o.scale_pow2 < 0) ? (h->o.uf == GMRESIR_FP16) : (h->o.scale_pow2 != 0);
+    gir::launch_convert_scaled(h->A64, n, ld, h->store, h->S, norms,
+                               std::sqrt((double)std::max<int64_t>(n, 1)), scaled ? 1 : 0, e_dev,
+                               iflag, h->stream);
+  }
   GIR_HIP(hipGetLastError());
+  return 0;
+}
+
+int ingest_finish(gmresir_ctx* h, bool has_e) {
   unsigned long long hv[2];
-  int hflag = 0;
-  GIR_TRY(download(h, hv, scanout, sizeof(hv)));
-  GIR_TRY(download(h, &hflag, flag, sizeof(int)));
-  double amax, rowsum;
-  std::memcpy(&amax, &hv[0], 8);
+  int hi[2];
+  GIR_TRY(download(h, hv, h->norms, sizeof(hv)));
+  GIR_TRY(download(h, hi, h->counter + 4, sizeof(hi)));
+  double rowsum;
   std::memcpy(&rowsum, &hv[1], 8);
   h->norm_a = rowsum;
-  if (hflag) {
-    h->status = GMRESIR_ERANGE;
-    return 0;
+  if (has_e) {
+    h->e = hi[1];
+    h->scale = std::ldexp(1.0, h->e);
   }
-  const bool scaled = (h->o.scale_pow2 < 0) ? (h->o.uf == GMRESIR_FP16) : (h->o.scale_pow2 != 0);
-  h->e = scaled ? scale_exponent(amax, n) : 0;
-  h->scale = std::ldexp(1.0, h->e);
-  if (make_lu_copy) {
-    GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
-    gir::launch_convert(h->A64, n, ld, h->e, h->store, h->S, h->Au, ld, flag, h->stream);
-    GIR_HIP(hipGetLastError());
-    GIR_TRY(download(h, &hflag, flag, sizeof(int)));
-    if (hflag) h->status = GMRESIR_ERANGE;
-  }
+  if (hi[0]) h->status = GMRESIR_ERANGE;
   return 0;
 }
 
@@ -497,11 +541,14 @@ int run_lu(gmresir_ctx* h) {
   int hflag = 0;
   GIR_TRY(download(h, &hs, h->st, sizeof(hs)));
   GIR_TRY(download(h, &hflag, flag, sizeof(int)));
+  GIR_TRY(ingest_finish(h, true));
   if (hs.abort) {
     set_error("LU: a device-side wait exceeded its bound");
     return GMRESIR_EINTERNAL;
   }
-  if (hs.singular) {
+  if (h->status == GMRESIR_ERANGE) {
+    // non-finite A: the factors are meaningless; nothing more to report
+  } else if (hs.singular) {
     h->status = GMRESIR_ESINGULAR;
     h->singular_col = hs.singular;
   } else if (hflag) {
@@ -683,8 +730,9 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     GIR_TRY(dots_norm(h, basis(nullptr, 0, ld, nullptr, 0, ld), h->z32, nullptr, &n2));
     beta0 = std::sqrt(n2);
   }
-  GIR_HIP(hipMemcpyAsync(h->r32, h->z32, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-  GIR_HIP(hipMemsetAsync(h->d32, 0, sizeof(float) * n, s));
+  // small device copies and fills run as kernels (no copy-engine latency)
+  gir::launch_copy_i32(reinterpret_cast<int*>(h->r32), reinterpret_cast<const int*>(h->z32), n, s);
+  gir::launch_fill_i32(reinterpret_cast<int*>(h->d32), 0, n, s);
   stats.its = 0;
   if (beta0 == 0.0) return 0;
   const double tol = h->o.tau * beta0;
@@ -749,11 +797,10 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     double* hb = h->hbuf;
     std::fill(hb, hb + m + 2, 0.0);
     hb[0] = rn;
-    GIR_HIP(hipMemcpyAsync(h->g, hb, sizeof(double) * (m + 2), hipMemcpyHostToDevice, s));
+    GIR_TRY(upload(h, h->g, hb, sizeof(double) * (m + 2)));
     // keep the abort and singular fields of the state
-    GIR_HIP(hipMemcpyAsync(h->st, &st0, offsetof(gir::CycleState, abort), hipMemcpyHostToDevice, s));
-    GIR_HIP(hipMemcpyAsync(&h->st->tol, &st0.tol, 2 * sizeof(double), hipMemcpyHostToDevice, s));
-    GIR_HIP(hipStreamSynchronize(s));
+    GIR_TRY(upload(h, h->st, &st0, offsetof(gir::CycleState, abort)));
+    GIR_TRY(upload(h, &h->st->tol, &st0.tol, 2 * sizeof(double)));
     int queued = 0;
     const size_t trec0 = h->trec.size();
     for (int j = 0; j < nsteps; ++j) {
@@ -947,7 +994,7 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     return h->status;
   }
   if (!h->o.keep_recycle) h->kc_keep = 0;
-  GIR_HIP(hipMemcpyAsync(h->b, bcol, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  gir::launch_copy_i32(reinterpret_cast<int*>(h->b), reinterpret_cast<const int*>(bcol), 2 * n, s);
   gir::launch_maxabs(h->b, n, h->norms + 2, s);
   unsigned long long bbits = 0;
   GIR_TRY(download(h, &bbits, h->norms + 2, 8));
@@ -996,7 +1043,7 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   inf.steps = i;
   inf.status = status;
   inf.recycle_dim = h->kc_keep;
-  GIR_HIP(hipMemcpyAsync(xcol, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  gir::launch_copy_i32(reinterpret_cast<int*>(xcol), reinterpret_cast<const int*>(h->x), 2 * n, s);
   GIR_HIP(hipStreamSynchronize(s));
   inf.t_factor_s = h->t_factor;
   inf.t_solve_s = now_s() - t0;
@@ -1035,7 +1082,7 @@ int gmresir_factor(const double* A, int64_t n, int64_t lda, const gmresir_opts* 
   GIR_TRY(make_ctx(A, n, lda, opts, stream, out, &h));
   int rc = alloc_common(h);
   if (rc == 0) rc = ingest(h, A, lda, true);
-  if (rc == 0 && h->status == 0) {
+  if (rc == 0) {
     h->permP = h->perm;
     h->permS = h->perm;
     rc = run_lu(h);
@@ -1069,6 +1116,7 @@ int gmresir_import_factors(const double* A, int64_t n, int64_t lda, const void* 
   }
   int rc = alloc_common(h);
   if (rc == 0) rc = ingest(h, A, lda, false);
+  if (rc == 0) rc = ingest_finish(h, false);
   if (rc == 0) {
     // factors in logical row order: S is read without a row gather
     const size_t eb = store_bytes(h->store);
@@ -1079,11 +1127,7 @@ int gmresir_import_factors(const double* A, int64_t n, int64_t lda, const void* 
       rc = GMRESIR_EHIP;
     }
   }
-  if (rc == 0) {
-    int* flag = reinterpret_cast<int*>(h->counter + 2);
-    gir::launch_convert(h->A64, n, h->ld, 0, h->store, nullptr, h->Au, h->ld, flag, h->stream);
-    if (hipStreamSynchronize(h->stream) != hipSuccess) rc = GMRESIR_EHIP;
-  }
+  if (rc == 0 && hipStreamSynchronize(h->stream) != hipSuccess) rc = GMRESIR_EHIP;
   if (rc == 0) {
     h->e = e;
     h->scale = std::ldexp(1.0, e);
