@@ -53,6 +53,8 @@ void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_be
 void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
                          int c_begin, int c_end, hipStream_t s);
 void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s);
+// copy of `words` 4-byte words; either side may be mapped pinned host memory
+void launch_copy_words(void* dst, const void* src, int64_t words, hipStream_t s);
 // after the last panel: non-finite check of the factors
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,
                           hipStream_t s);

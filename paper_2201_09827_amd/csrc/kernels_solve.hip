@@ -866,6 +866,15 @@ __global__ void k_maxabs(const double* __restrict__ v, int n, unsigned long long
   if ((threadIdx.x % kWave) == 0) atomic_max_nonneg(out, a);
 }
 
+// word copy for small transfers between device memory and mapped pinned host
+// memory (the kernel reads or writes the host side directly)
+__global__ void k_copy_words(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                             int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 __global__ void k_copy_f32_f64(const float* __restrict__ a, double* __restrict__ b, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (double)a[i];
@@ -874,6 +883,13 @@ __global__ void k_copy_f32_f64(const float* __restrict__ a, double* __restrict__
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+void launch_copy_words(void* dst, const void* src, int64_t words, hipStream_t s) {
+  if (words <= 0) return;
+  hipLaunchKernelGGL(k_copy_words, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 64)),
+                     dim3(256), 0, s, reinterpret_cast<uint32_t*>(dst),
+                     reinterpret_cast<const uint32_t*>(src), words);
+}
 
 void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const float* v32,
                     const double* v64, double* t, const CycleState* gate, int step,

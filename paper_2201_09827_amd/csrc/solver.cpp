@@ -45,6 +45,7 @@ void set_error(const std::string& s) { g_last_error = s; }
     if (rc_ != 0) return rc_;  \
   } while (0)
 
+constexpr int kEventRing = 4;   // events of the Arnoldi loop (> kLaunchAhead + 1)
 constexpr int kNb = 64;           // LU block size (sets the u_f rounding points)
 constexpr int kMaxM = 95;         // limit from the skinny-product kernels
 constexpr int kLaunchAhead = 1;   // Arnoldi steps queued before polling
@@ -87,15 +88,45 @@ int scale_exponent(double amax, int64_t n) {
   return e;
 }
 
+// Device memory of a handle: buffers above 4 MiB get their own allocation,
+// smaller ones are carved from 32 MiB chunks (256-byte aligned), so that a
+// handle costs a handful of hipMalloc / hipFree calls.
+struct Arena {
+  std::vector<void*> chunks;
+  char* cur = nullptr;
+  size_t left = 0;
+  ~Arena() {
+    for (void* c : chunks) (void)hipFree(c);
+  }
+};
+
+constexpr size_t kOwnAllocation = size_t(4) << 20;
+constexpr size_t kChunk = size_t(32) << 20;
+
 template <class T>
-int dalloc(T** p, size_t count) {
+int dalloc(Arena& a, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count);
-  if (e != hipSuccess) {
-    set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
-    return GMRESIR_ENOMEM;
+  const size_t bytes = (sizeof(T) * count + 255) & ~size_t(255);
+  if (bytes > kOwnAllocation || bytes > a.left) {
+    void* q = nullptr;
+    const size_t want = bytes > kOwnAllocation ? bytes : kChunk;
+    hipError_t e = hipMalloc(&q, want);
+    if (e != hipSuccess) {
+      set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+      return GMRESIR_ENOMEM;
+    }
+    a.chunks.push_back(q);
+    if (bytes > kOwnAllocation) {
+      *p = reinterpret_cast<T*>(q);
+      return 0;
+    }
+    a.cur = reinterpret_cast<char*>(q);
+    a.left = kChunk;
   }
+  *p = reinterpret_cast<T*>(a.cur);
+  a.cur += bytes;
+  a.left -= bytes;
   return 0;
 }
 
@@ -119,6 +150,7 @@ struct KStat {
 }  // namespace
 
 struct gmresir_ctx {
+  Arena arena;  // declared first: destroyed last
   int64_t n = 0, ld = 0;
   gmresir_opts o{};
   int store = 0;
@@ -177,24 +209,14 @@ struct gmresir_ctx {
   KStat kstat[kKcCount];
 
   ~gmresir_ctx() {
-    // permP and permS alias perm
-    void* bufs[] = {A64, Au, S, perm, ipiv, Linv, Uinv, dtmp, xch, perm_rest,
-                    x, b, r64, t64, y64, z64, z32, w32, d32, r32, V, C, U, Cn, Un, Hd, Bd, cs,
-                    sn, g, h1, h2, nrm, coefA, coefB, Mdev, Gdev, partial, counter, norms, st,
-                    xwL, xwU, xwLm, xwUm, Tb, Yb};
-    for (void* p : bufs)
-      if (p) (void)hipFree(p);
+    // device buffers belong to `arena` (freed by its destructor)
     if (st_host) (void)hipHostFree(st_host);
-    if (hbuf) (void)hipHostFree(hbuf);
-    if (up_stage) (void)hipHostFree(up_stage);
-    if (dl_stage) (void)hipHostFree(dl_stage);
     for (auto& e2 : ev) (void)hipEventDestroy(e2);
     for (auto& e2 : tpool) (void)hipEventDestroy(e2);
     if (ev_panel) (void)hipEventDestroy(ev_panel);
     if (ev_rest) (void)hipEventDestroy(ev_rest);
     if (s_aux) (void)hipStreamDestroy(s_aux);
-  }
-};
+  }};
 
 namespace {
 
@@ -300,51 +322,75 @@ int validate_opts(const gmresir_opts* o) {
   return 0;
 }
 
+// Small host <-> device transfers go through pinned staging memory.  An
+// upload copies into the next free piece of the staging arena and queues the
+// copy without waiting; the arena is recycled after the next synchronisation
+// (every download synchronises the stream, so all queued uploads are done).
+constexpr size_t kStageBytes = 64 * 1024;
+
+// one pinned block: per-step cycle states (m + 2), a general buffer of 8192
+// doubles and the two staging areas
+int pinned_init(gmresir_ctx* h) {
+  if (h->st_host) return 0;
+  const size_t st_bytes = (sizeof(gir::CycleState) * (size_t)(h->m + 2) + 255) & ~size_t(255);
+  h->hbuf_len = 8192;
+  const size_t total = st_bytes + sizeof(double) * h->hbuf_len + 2 * kStageBytes;
+  char* p = nullptr;
+  GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), total, hipHostMallocDefault));
+  h->st_host = reinterpret_cast<gir::CycleState*>(p);
+  h->hbuf = reinterpret_cast<double*>(p + st_bytes);
+  h->up_stage = p + st_bytes + sizeof(double) * h->hbuf_len;
+  h->dl_stage = h->up_stage + kStageBytes;
+  return 0;
+}
+
+int stage_init(gmresir_ctx* h) { return pinned_init(h); }
+
 int alloc_solve(gmresir_ctx* h) {
   const size_t ld = (size_t)h->ld;
   const int m = h->m, k = std::max(h->k, 1);
-  GIR_TRY(dalloc(&h->x, ld));
-  GIR_TRY(dalloc(&h->b, ld));
-  GIR_TRY(dalloc(&h->r64, ld));
-  GIR_TRY(dalloc(&h->t64, ld));
-  GIR_TRY(dalloc(&h->y64, ld));
-  GIR_TRY(dalloc(&h->z64, ld));
-  GIR_TRY(dalloc(&h->z32, ld));
-  GIR_TRY(dalloc(&h->w32, ld));
-  GIR_TRY(dalloc(&h->d32, ld));
-  GIR_TRY(dalloc(&h->r32, ld));
-  GIR_TRY(dalloc(&h->V, ld * (m + 1)));
-  GIR_TRY(dalloc(&h->C, ld * k));
-  GIR_TRY(dalloc(&h->U, ld * k));
-  GIR_TRY(dalloc(&h->Cn, ld * k));
-  GIR_TRY(dalloc(&h->Un, ld * k));
-  GIR_TRY(dalloc(&h->Hd, (size_t)(m + 1) * m));
-  GIR_TRY(dalloc(&h->Bd, (size_t)k * m));
-  GIR_TRY(dalloc(&h->cs, m + 1));
-  GIR_TRY(dalloc(&h->sn, m + 1));
-  GIR_TRY(dalloc(&h->g, m + 2));
-  GIR_TRY(dalloc(&h->h1, 256));
-  GIR_TRY(dalloc(&h->h2, 256));
-  GIR_TRY(dalloc(&h->nrm, 4));
-  GIR_TRY(dalloc(&h->coefA, 256));
-  GIR_TRY(dalloc(&h->coefB, 256));
-  GIR_TRY(dalloc(&h->Mdev, 4096));
-  GIR_TRY(dalloc(&h->Gdev, 4096));
+  GIR_TRY(dalloc(h->arena, &h->x, ld));
+  GIR_TRY(dalloc(h->arena, &h->b, ld));
+  GIR_TRY(dalloc(h->arena, &h->r64, ld));
+  GIR_TRY(dalloc(h->arena, &h->t64, ld));
+  GIR_TRY(dalloc(h->arena, &h->y64, ld));
+  GIR_TRY(dalloc(h->arena, &h->z64, ld));
+  GIR_TRY(dalloc(h->arena, &h->z32, ld));
+  GIR_TRY(dalloc(h->arena, &h->w32, ld));
+  GIR_TRY(dalloc(h->arena, &h->d32, ld));
+  GIR_TRY(dalloc(h->arena, &h->r32, ld));
+  GIR_TRY(dalloc(h->arena, &h->V, ld * (m + 1)));
+  GIR_TRY(dalloc(h->arena, &h->C, ld * k));
+  GIR_TRY(dalloc(h->arena, &h->U, ld * k));
+  GIR_TRY(dalloc(h->arena, &h->Cn, ld * k));
+  GIR_TRY(dalloc(h->arena, &h->Un, ld * k));
+  GIR_TRY(dalloc(h->arena, &h->Hd, (size_t)(m + 1) * m));
+  GIR_TRY(dalloc(h->arena, &h->Bd, (size_t)k * m));
+  GIR_TRY(dalloc(h->arena, &h->cs, m + 1));
+  GIR_TRY(dalloc(h->arena, &h->sn, m + 1));
+  GIR_TRY(dalloc(h->arena, &h->g, m + 2));
+  GIR_TRY(dalloc(h->arena, &h->h1, 256));
+  GIR_TRY(dalloc(h->arena, &h->h2, 256));
+  GIR_TRY(dalloc(h->arena, &h->nrm, 4));
+  GIR_TRY(dalloc(h->arena, &h->coefA, 256));
+  GIR_TRY(dalloc(h->arena, &h->coefB, 256));
+  GIR_TRY(dalloc(h->arena, &h->Mdev, 4096));
+  GIR_TRY(dalloc(h->arena, &h->Gdev, 4096));
   const size_t grid = (ld + 255) / 256;
-  GIR_TRY(dalloc(&h->partial, grid * 4096));
+  GIR_TRY(dalloc(h->arena, &h->partial, grid * 4096));
   const int64_t nxw = 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
-  GIR_TRY(dalloc(&h->xwL, (size_t)nxw));
-  GIR_TRY(dalloc(&h->xwU, (size_t)nxw));
+  GIR_TRY(dalloc(h->arena, &h->xwL, (size_t)nxw));
+  GIR_TRY(dalloc(h->arena, &h->xwU, (size_t)nxw));
   gir::launch_fill_i32(reinterpret_cast<int*>(h->xwL), 0, 2 * nxw, h->stream);
   gir::launch_fill_i32(reinterpret_cast<int*>(h->xwU), 0, 2 * nxw, h->stream);
   if (h->k > 0) {
     const int64_t nm = nxw * gir::kTrsvMaxRhs;
-    GIR_TRY(dalloc(&h->xwLm, (size_t)nm));
-    GIR_TRY(dalloc(&h->xwUm, (size_t)nm));
+    GIR_TRY(dalloc(h->arena, &h->xwLm, (size_t)nm));
+    GIR_TRY(dalloc(h->arena, &h->xwUm, (size_t)nm));
     gir::launch_fill_i32(reinterpret_cast<int*>(h->xwLm), 0, 2 * nm, h->stream);
     gir::launch_fill_i32(reinterpret_cast<int*>(h->xwUm), 0, 2 * nm, h->stream);
-    GIR_TRY(dalloc(&h->Tb, (size_t)h->ld * gir::kTrsvMaxRhs));
-    GIR_TRY(dalloc(&h->Yb, (size_t)h->ld * gir::kTrsvMaxRhs));
+    GIR_TRY(dalloc(h->arena, &h->Tb, (size_t)h->ld * gir::kTrsvMaxRhs));
+    GIR_TRY(dalloc(h->arena, &h->Yb, (size_t)h->ld * gir::kTrsvMaxRhs));
   }
   // zero padding of every vector
   double* dv[] = {h->x, h->b, h->r64, h->t64, h->y64, h->z64};
@@ -352,54 +398,37 @@ int alloc_solve(gmresir_ctx* h) {
   float* fv[] = {h->z32, h->w32, h->d32, h->r32};
   for (float* p : fv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(float) * ld, h->stream));
   GIR_HIP(hipMemsetAsync(h->V, 0, sizeof(float) * ld * (m + 1), h->stream));
-  GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->st_host),
-                        sizeof(gir::CycleState) * (size_t)(m + 2), hipHostMallocDefault));
-  h->hbuf_len = 8192;
-  GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hbuf), sizeof(double) * h->hbuf_len,
-                        hipHostMallocDefault));
-  h->ev.resize(m + 2);
+  GIR_TRY(pinned_init(h));
+  h->ev.resize(kEventRing);
   for (auto& e2 : h->ev) GIR_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
   return 0;
 }
 
 int alloc_common(gmresir_ctx* h) {
   const size_t ld = (size_t)h->ld, n = (size_t)h->n;
-  GIR_TRY(dalloc(&h->A64, n * ld));
-  GIR_TRY(dalloc(&h->Au, n * ld));
-  GIR_TRY(dalloc(reinterpret_cast<char**>(&h->S), n * ld * store_bytes(h->store)));
-  GIR_TRY(dalloc(&h->perm, n));
-  GIR_TRY(dalloc(&h->ipiv, n));
+  GIR_TRY(dalloc(h->arena, &h->A64, n * ld));
+  GIR_TRY(dalloc(h->arena, &h->Au, n * ld));
+  GIR_TRY(dalloc(h->arena, reinterpret_cast<char**>(&h->S), n * ld * store_bytes(h->store)));
+  GIR_TRY(dalloc(h->arena, &h->perm, n));
+  GIR_TRY(dalloc(h->arena, &h->ipiv, n));
   const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
-  GIR_TRY(dalloc(&h->Linv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
-  GIR_TRY(dalloc(&h->Uinv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
-  GIR_TRY(dalloc(&h->dtmp, ((n + 63) / 64) * 64 * 64));
-  GIR_TRY(dalloc(&h->st, 1));
-  GIR_TRY(dalloc(&h->counter, 8));
-  GIR_TRY(dalloc(&h->norms, 4));
+  GIR_TRY(dalloc(h->arena, &h->Linv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+  GIR_TRY(dalloc(h->arena, &h->Uinv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+  GIR_TRY(dalloc(h->arena, &h->dtmp, ((n + 63) / 64) * 64 * 64));
+  GIR_TRY(dalloc(h->arena, &h->st, 1));
+  GIR_TRY(dalloc(h->arena, &h->counter, 8));
+  GIR_TRY(dalloc(h->arena, &h->norms, 4));
   GIR_HIP(hipMemsetAsync(h->st, 0, sizeof(gir::CycleState), h->stream));
   GIR_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned) * 8, h->stream));
   return 0;
 }
 
-// Small host <-> device transfers go through pinned staging memory.  An
-// upload copies into the next free piece of the staging arena and queues the
-// copy without waiting; the arena is recycled after the next synchronisation
-// (every download synchronises the stream, so all queued uploads are done).
-constexpr size_t kStageBytes = 64 * 1024;
-
-int stage_init(gmresir_ctx* h) {
-  if (!h->up_stage)
-    GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->up_stage), kStageBytes,
-                          hipHostMallocDefault));
-  if (!h->dl_stage)
-    GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->dl_stage), kStageBytes,
-                          hipHostMallocDefault));
-  return 0;
-}
-
+// Small transfers (whole 4-byte words) are done by a copy kernel that reads or
+// writes the mapped pinned staging memory directly, which keeps them off the
+// copy engines (tens of microseconds of latency each).
 int upload(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
   GIR_TRY(stage_init(h));
-  if (bytes > kStageBytes) {
+  if (bytes > kStageBytes || bytes % 4 != 0) {
     GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
     GIR_HIP(hipStreamSynchronize(h->stream));
     h->up_off = 0;
@@ -411,18 +440,20 @@ int upload(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
   }
   char* p = h->up_stage + h->up_off;
   std::memcpy(p, src, bytes);
-  GIR_HIP(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, h->stream));
+  gir::launch_copy_words(dst, p, (int64_t)(bytes / 4), h->stream);
+  GIR_HIP(hipGetLastError());
   h->up_off += (bytes + 255) & ~size_t(255);
   return 0;
 }
 
 int download(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
   GIR_TRY(stage_init(h));
-  if (bytes > kStageBytes) {
+  if (bytes > kStageBytes || bytes % 4 != 0) {
     GIR_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
     GIR_HIP(hipStreamSynchronize(h->stream));
   } else {
-    GIR_HIP(hipMemcpyAsync(h->dl_stage, src, bytes, hipMemcpyDeviceToHost, h->stream));
+    gir::launch_copy_words(h->dl_stage, src, (int64_t)(bytes / 4), h->stream);
+    GIR_HIP(hipGetLastError());
     GIR_HIP(hipStreamSynchronize(h->stream));
     std::memcpy(dst, h->dl_stage, bytes);
   }
@@ -430,7 +461,6 @@ int download(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
   return 0;
 }
 
-// copy A into the padded fp64 buffer, scan it, and form A_u
 // Copies of A (fp64 and fp32, zero padded), ||A||_inf, max |a|, the
 // non-finite check and, with make_lu_copy, A_f = fl_uf(2^e A) with the scale
 // exponent chosen on the device: no host round trip.  ingest_finish reads the
@@ -474,7 +504,7 @@ int run_lu(gmresir_ctx* h) {
   const int n = (int)h->n;
   gir::launch_iota(h->perm, n, h->stream);
   uint64_t* xch = nullptr;
-  GIR_TRY(dalloc(&xch, (size_t)gir::kPanelXchWords));
+  GIR_TRY(dalloc(h->arena, &xch, (size_t)gir::kPanelXchWords));
   h->xch = xch;
   gir::launch_fill_i32(reinterpret_cast<int*>(xch), 0, 2 * gir::kPanelXchWords, h->stream);
   gir::PanelArgs a{};
@@ -494,7 +524,7 @@ int run_lu(gmresir_ctx* h) {
   // because block column k + 1 rewrites perm at the same time.
   hipStream_t s0 = h->stream;
   int* prow = nullptr;
-  GIR_TRY(dalloc(&prow, 2 * (size_t)n));
+  GIR_TRY(dalloc(h->arena, &prow, 2 * (size_t)n));
   h->perm_rest = prow;
   const double es = (double)store_bytes(h->store);
   int step = 0;
@@ -554,11 +584,7 @@ int run_lu(gmresir_ctx* h) {
   } else if (hflag) {
     h->status = GMRESIR_ERANGE;
   }
-  // the exchange buffer and the permutation copy are not needed by the solve
-  (void)hipFree(h->xch);
-  (void)hipFree(h->perm_rest);
-  h->xch = nullptr;
-  h->perm_rest = nullptr;
+
   return 0;
 }
 
@@ -839,12 +865,12 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
         gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
       }));
       gir::launch_normalize(h->w32, h->V + (size_t)(j + 1) * ld, h->Hd, m + 1, j, n, h->st, s);
-      GIR_HIP(hipMemcpyAsync(&h->st_host[j], h->st, sizeof(gir::CycleState),
-                             hipMemcpyDeviceToHost, s));
-      GIR_HIP(hipEventRecord(h->ev[j], s));
+      static_assert(sizeof(gir::CycleState) % 4 == 0, "CycleState is copied as words");
+      gir::launch_copy_words(&h->st_host[j], h->st, sizeof(gir::CycleState) / 4, s);
+      GIR_HIP(hipEventRecord(h->ev[j % kEventRing], s));
       queued = j + 1;
       if (j >= kLaunchAhead) {
-        GIR_HIP(hipEventSynchronize(h->ev[j - kLaunchAhead]));
+        GIR_HIP(hipEventSynchronize(h->ev[(j - kLaunchAhead) % kEventRing]));
         const gir::CycleState& sj = h->st_host[j - kLaunchAhead];
         if (sj.done || sj.abort) break;
       }
