@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgmresir.so")
 
-SOURCES = ["kernels_lu.hip", "kernels_solve.hip", "host_la.cpp", "solver.cpp"]
+SOURCES = ["kernels_lu.hip", "kernels_solve.hip", "kernels_dd.hip", "host_la.cpp", "solver.cpp"]
 
 ARCH = os.environ.get("GMRESIR_OFFLOAD_ARCH", "gfx950")
 

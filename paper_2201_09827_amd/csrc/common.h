@@ -174,4 +174,61 @@ __device__ __forceinline__ bool gated_off(const CycleState* st, int j) {
   return st != nullptr && st->done && st->jdone <= j;
 }
 
+// ---------------------------------------------------------------------------
+// factor tiles
+// ---------------------------------------------------------------------------
+constexpr int kTileCols = 64;
+
+// A tile row of 64 u_f values kept as raw bits (32 registers for 16-bit
+// formats) and widened to fp64 when used.
+template <class F>
+struct RawRow {
+  static constexpr int kWords = kTileCols * (int)sizeof(typename F::T) / 4;
+  uint32_t w[kWords];
+
+  __device__ __forceinline__ void load(const typename F::T* srow, int cbase, int n, bool valid) {
+    if (valid && cbase + kTileCols <= n) {
+      const uint4* q = reinterpret_cast<const uint4*>(srow + cbase);
+#pragma unroll
+      for (int v = 0; v < kWords / 4; ++v) {
+        const uint4 x = q[v];
+        w[4 * v] = x.x;
+        w[4 * v + 1] = x.y;
+        w[4 * v + 2] = x.z;
+        w[4 * v + 3] = x.w;
+      }
+    } else {
+      using T = typename F::T;
+      constexpr int per = 4 / (int)sizeof(T);
+#pragma unroll
+      for (int i = 0; i < kWords; ++i) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int e = 0; e < per; ++e) {
+          const int c = cbase + i * per + e;
+          T v{};
+          if (valid && c < n) v = srow[c];
+          uint32_t bits = 0;
+          __builtin_memcpy(&bits, &v, sizeof(T));
+          word |= bits << (8 * sizeof(T) * e);
+        }
+        w[i] = word;
+      }
+    }
+  }
+
+  __device__ __forceinline__ double at(int c) const {
+    using T = typename F::T;
+    T v;
+    if constexpr (sizeof(T) == 2) {
+      const uint16_t b = (uint16_t)(w[c >> 1] >> (16 * (c & 1)));
+      __builtin_memcpy(&v, &b, 2);
+    } else {
+      __builtin_memcpy(&v, &w[c], 4);
+    }
+    return (double)F::to_f(v);
+  }
+};
+
+
 }  // namespace gir

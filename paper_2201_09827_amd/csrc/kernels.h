@@ -99,17 +99,18 @@ struct Basis {
   const double* c64;  // kc columns, column-major, ld ldc
   int kc;
   int64_t ldc;
-  const float* v32;   // nv columns, column-major, ld ldv
+  const void* v;      // nv columns in u (fp32, or fp64 when v64), column-major, ld ldv
   int nv;
   int64_t ldv;
+  int v64;
 };
 
 enum OrthoMode { kOrthoDots = 1, kOrthoUpdate = 2, kOrthoNorm = 4, kOrthoFinish = 8 };
 struct OrthoArgs {
   Basis X;
   int n;
-  const float* w_in;
-  float* w_out;           // may equal w_in
+  const void* w_in;       // vectors in u: fp32, or fp64 when X.v64
+  void* w_out;            // may equal w_in
   const double* coef;     // update coefficients (kc + nv) when kOrthoUpdate
   double* dots_out;       // kc + nv inner products (kOrthoDots)
   double* norm_out;       // squared 2-norm of the (updated) vector (kOrthoNorm)
@@ -128,28 +129,49 @@ struct OrthoArgs {
   const CycleState* gate;
 };
 void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s);
-// v_out = fl32(w / H[j+1][j])
-void launch_normalize(const float* w, float* vout, const double* H, int ldh, int step, int n,
-                      const CycleState* gate, hipStream_t s);
+// v_out = fl_u(w / H[j+1][j]) (u = fp32, or fp64 when v64)
+void launch_normalize(const void* w, void* vout, int v64, const double* H, int ldh, int step,
+                      int n, const CycleState* gate, hipStream_t s);
 
 // out (n x nout, col-major fp64, ld ldo) = X M, M (ncol x nout col-major) on device
 void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,
                     hipStream_t s);
-// d = fl32(d + Xd cd), r = fl32(r - Xr cr); either part skipped when its vector is null
-void launch_cycle_update(const Basis& Xd, const double* cd, float* d, const Basis& Xr,
-                         const double* cr, float* r, int n, hipStream_t s);
+// d = fl_u(d + Xd cd), r = fl_u(r - Xr cr) (u = fp32, or fp64 when v64); either
+// part skipped when its vector is null
+void launch_cycle_update(const Basis& Xd, const double* cd, void* d, const Basis& Xr,
+                         const double* cr, void* r, int n, int v64, hipStream_t s);
 // G (nx x ny, col-major) = X^T Y for fp64 Y (n x ny, ld ldy)
 void launch_gram(const Basis& X, const double* Y, int ny, int64_t ldy, int n, double* G,
                  double* partial, unsigned int* counter, hipStream_t s);
-// out = fl32(r / s), held in fp64
-void launch_scale_round(const double* r, double s, double* out, int n, hipStream_t st);
-// x = x + s d (two roundings, no fused multiply-add)
-void launch_x_update(double* x, const float* d, double s, int n, hipStream_t st);
-// out = fl32(w / s)
-void launch_div_f32(const float* w, double s, float* out, int n, hipStream_t st);
+// out = fl_u(r / s), held in fp64 (u = fp32, or fp64 when v64)
+void launch_scale_round(const double* r, double s, double* out, int n, int v64, hipStream_t st);
+// x = x + s d (two roundings, no fused multiply-add); d in u
+void launch_x_update(double* x, const void* d, int v64, double s, int n, hipStream_t st);
+// out = fl_u(w / s)
+void launch_div_u(const void* w, double s, void* out, int v64, int n, hipStream_t st);
 // out[0] = max |v_i| (as bits)
 void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t st);
 void launch_copy_f32_to_f64(const float* a, double* b, int n, hipStream_t s);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
+
+// ---- double-double (u = fp64, u^2 = double-double; u_r = double-double) -----
+
+// th + tl = A[permA[i]] . v for each row i, in double-double (A fp64)
+void launch_gemv_dd(const double* A, int64_t ld, const int* permA, int n, const double* v,
+                    double* th, double* tl, const CycleState* gate, int step, hipStream_t s);
+// r = fl64(b - A x) with A x in double-double; norms as launch_residual
+void launch_residual_dd(const double* A, int64_t ld, int n, const double* b, const double* x,
+                        double* r, unsigned long long* norms, hipStream_t s);
+// Blocked triangular solve with the u_f factor (rows permS of S) in
+// double-double arithmetic, 64 rows per workgroup.  Right-hand side
+// (inh + inl)[permIn[i]] (inl may be null: zero low parts).  The solution goes
+// to yh / yl (either may be null) and, rounded to fp64 and times scale, to
+// out64 (may be null).  xw: kDdWordsPerRow * ceil(n/64) * 64 tagged words,
+// zeroed once; epoch: a new nonzero value per launch.
+constexpr int kDdWordsPerRow = 4;
+void launch_trsv_dd(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
+                    const double* inh, const double* inl, const int* permIn, double* yh,
+                    double* yl, double scale, double* out64, uint64_t* xw, int epoch,
+                    const CycleState* gate, int step, int* abortp, hipStream_t s);
 
 }  // namespace gir

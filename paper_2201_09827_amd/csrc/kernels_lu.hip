@@ -554,6 +554,7 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 128;
 constexpr int kKP = kMaxNb + 8;  // padded LDS row of -L21 and U12^T (elements, 16-byte multiple)
@@ -582,25 +583,14 @@ struct Mfma<Bf16> {
   }
 };
 
-template <>
-struct Mfma<Fp32> {
-  // the 8-deep chunk as four 2-deep steps; a/b point at k = 4*(lane/32)
-  static __device__ __forceinline__ float16_t step(const float* a, const float* b,
-                                                   float16_t acc) {
-    // lanes 0-31 hold k = 0..3 of their half, lanes 32-63 k = 4..7; the
-    // 2-deep instruction takes k = lane/32 -> issue k pairs (0,4),(1,5),...
-    // which covers the same 8 products in a different order.
-#pragma unroll
-    for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], acc, 0, 0, 0);
-    return acc;
-  }
-};
-
 // C tile 128 x 128 of the trailing matrix, rows gathered through `rows`:
-// C <- fl_uf(C + sum_k (-L21)(:,k) U12(k,:)).  The product is accumulated in
-// fp32 on the matrix cores from zero (4 waves, 2 x 2 blocks of 32 x 32 each)
-// and added to C once; every operand moves between HBM and LDS in 16-byte
-// coalesced pieces (the -L21 block, U12 transposed, and C both ways).
+// C <- fl_uf(C + sum_k (-L21)(:,k) U12(k,:)).  The product is accumulated on
+// the matrix cores from zero and added to C once: in fp32 for fp16 / bf16
+// factors (32 x 32 blocks), in fp64 for fp32 factors (16 x 16 x 4 fp64
+// blocks: the fp32 products are exact and their sum is rounded to fp32 once,
+// as fp32 accumulation of 64 terms would not be for an fp32 result).  Every
+// operand moves between HBM and LDS in 16-byte coalesced pieces (the -L21
+// block, U12 transposed, and C both ways).
 constexpr int kCP = kTile + 8;  // padded LDS row of the C tile (elements)
 
 template <class T>
@@ -678,31 +668,71 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
   const int lane = tid % kWave;
   const int wr = (wave / 4) * 64;
   const int wc = (wave % 4) * 32;
-  const int l32 = lane % 32;
-  const int hi = lane / 32;
-  float16_t acc[2];
+  if constexpr (sizeof(T) == 4) {
+    // 4 x 2 blocks of 16 x 16 per wave; a 4-deep step takes A(i = lane % 16,
+    // k = lane / 16) and B(k = lane / 16, j = lane % 16); lane holds
+    // D(4 r + lane / 16, lane % 16) in element r
+    const int l16 = lane % 16;
+    const int q = lane / 16;
+    double4_t acc[4][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-  for (int kk = 0; kk < kMaxNb / 8; ++kk) {
-    const int ko = kk * 8 + 4 * hi;
+        for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0;
+#pragma unroll 4
+    for (int kk = 0; kk < kMaxNb / 4; ++kk) {
+      const int k = kk * 4 + q;
+      double av[4], bv[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = (double)F::to_f(As[wr + i * 16 + l16][k]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bv[j] = (double)F::to_f(Bt[wc + j * 16 + l16][k]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    // C + product in fp64, rounded to fp32 once
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = wr + i * 16 + 4 * e + q;
+          const int c = wc + j * 16 + l16;
+          Cs[r][c] = F::from_d((double)F::to_f(Cs[r][c]) + acc[i][j][e]);
+        }
+  } else {
+    const int l32 = lane % 32;
+    const int hi = lane / 32;
+    float16_t acc[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-      acc[i] = Mfma<F>::step(&As[wr + i * 32 + l32][ko], &Bt[wc + l32][ko], acc[i]);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < kMaxNb / 8; ++kk) {
+      const int ko = kk * 8 + 4 * hi;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        acc[i] = Mfma<F>::step(&As[wr + i * 32 + l32][ko], &Bt[wc + l32][ko], acc[i]);
+    }
+    // C + product in fp32, rounded to u_f once
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = wr + i * 32 + 8 * g + 4 * hi + e;
+          const int c = wc + l32;
+          Cs[r][c] = F::from_f(F::to_f(Cs[r][c]) + acc[i][4 * g + e]);
+        }
   }
-  // C + product in fp32, rounded to u_f once
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wr + i * 32 + 8 * g + 4 * hi + e;
-        const int c = wc + l32;
-        Cs[r][c] = F::from_f(F::to_f(Cs[r][c]) + acc[i][4 * g + e]);
-      }
   __syncthreads();
   for (int q = tid; q < kTile * (kTile / V); q += NT) {
     const int r = q / (kTile / V), cc = q % (kTile / V);

@@ -172,57 +172,6 @@ __device__ __forceinline__ void load_row64(const typename F::T* p, double (&out)
   }
 }
 
-// A tile row of 64 u_f values kept as raw bits (32 registers for 16-bit
-// formats) and widened to fp64 when used.
-template <class F>
-struct RawRow {
-  static constexpr int kWords = kTB * (int)sizeof(typename F::T) / 4;
-  uint32_t w[kWords];
-
-  __device__ __forceinline__ void load(const typename F::T* srow, int cbase, int n, bool valid) {
-    if (valid && cbase + kTB <= n) {
-      const uint4* q = reinterpret_cast<const uint4*>(srow + cbase);
-#pragma unroll
-      for (int v = 0; v < kWords / 4; ++v) {
-        const uint4 x = q[v];
-        w[4 * v] = x.x;
-        w[4 * v + 1] = x.y;
-        w[4 * v + 2] = x.z;
-        w[4 * v + 3] = x.w;
-      }
-    } else {
-      using T = typename F::T;
-      constexpr int per = 4 / (int)sizeof(T);
-#pragma unroll
-      for (int i = 0; i < kWords; ++i) {
-        uint32_t word = 0;
-#pragma unroll
-        for (int e = 0; e < per; ++e) {
-          const int c = cbase + i * per + e;
-          T v{};
-          if (valid && c < n) v = srow[c];
-          uint32_t bits = 0;
-          __builtin_memcpy(&bits, &v, sizeof(T));
-          word |= bits << (8 * sizeof(T) * e);
-        }
-        w[i] = word;
-      }
-    }
-  }
-
-  __device__ __forceinline__ double at(int c) const {
-    using T = typename F::T;
-    T v;
-    if constexpr (sizeof(T) == 2) {
-      const uint16_t b = (uint16_t)(w[c >> 1] >> (16 * (c & 1)));
-      __builtin_memcpy(&v, &b, 2);
-    } else {
-      __builtin_memcpy(&v, &w[c], 4);
-    }
-    return (double)F::to_f(v);
-  }
-};
-
 // Blocked triangular solve, one workgroup per 128-row block (two 64-row
 // tiles), fp64 arithmetic with the u_f factor entries taken exactly:
 //   lower: y_I = Dinv_I (in_I - sum_{J < I} L_IJ y_J)
@@ -624,11 +573,20 @@ __global__ __launch_bounds__(64) void k_diag_inverse(const typename F::T* __rest
 // ---------------------------------------------------------------------------
 constexpr int kRowsPerBlock = 256;
 
+// vectors in the working precision u: VT = float (u = fp32) or double (fp64)
+template <typename VT>
 __device__ __forceinline__ double basis_at(const Basis& X, int c, int row) {
   return (c < X.kc) ? X.c64[(int64_t)c * X.ldc + row]
-                    : (double)X.v32[(int64_t)(c - X.kc) * X.ldv + row];
+                    : (double)static_cast<const VT*>(X.v)[(int64_t)(c - X.kc) * X.ldv + row];
 }
 
+// fl_u(x) held in fp64
+template <typename VT>
+__device__ __forceinline__ double round_u(double x) {
+  return (double)(VT)x;
+}
+
+template <typename VT>
 __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   if (gated_off(a.gate, a.step)) return;
   __shared__ double wsh[kRowsPerBlock];
@@ -646,12 +604,13 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
     for (int c = tid; c < ncol; c += 256) coef_sh[c] = a.coef[c];
     __syncthreads();
   }
-  double wv = valid ? (double)a.w_in[row] : 0.0;
+  const VT* w_in = static_cast<const VT*>(a.w_in);
+  double wv = valid ? (double)w_in[row] : 0.0;
   if ((mode & kOrthoUpdate) && valid) {
     double s = 0.0;
-    for (int c = 0; c < ncol; ++c) s = fma(basis_at(a.X, c, row), coef_sh[c], s);
-    wv = (double)(float)(wv - s);
-    a.w_out[row] = (float)wv;
+    for (int c = 0; c < ncol; ++c) s = fma(basis_at<VT>(a.X, c, row), coef_sh[c], s);
+    wv = round_u<VT>(wv - s);
+    static_cast<VT*>(a.w_out)[row] = (VT)wv;
   }
   wsh[tid] = wv;
   __syncthreads();
@@ -666,7 +625,7 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
 #pragma unroll 8
         for (int r = 0; r < kWave; ++r) {
           const int rr = rbase + r0 + r;
-          if (rr < a.n) acc = fma(basis_at(a.X, c, rr), wsh[r0 + r], acc);
+          if (rr < a.n) acc = fma(basis_at<VT>(a.X, c, rr), wsh[r0 + r], acc);
         }
       }
       red[wave][lane] = acc;
@@ -739,17 +698,19 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   if (est <= a.st->tol || beta == 0.0) a.st->done = 1;
 }
 
-__global__ void k_normalize(const float* __restrict__ w, float* __restrict__ vout,
+template <typename VT>
+__global__ void k_normalize(const VT* __restrict__ w, VT* __restrict__ vout,
                             const double* __restrict__ H, int ldh, int step, int n,
                             const CycleState* gate) {
   if (gated_off(gate, step)) return;
   const double beta = H[(int64_t)step * ldh + step + 1];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  vout[i] = (beta > 0.0) ? (float)((double)w[i] / beta) : 0.0f;
+  vout[i] = (beta > 0.0) ? (VT)((double)w[i] / beta) : (VT)0;
 }
 
 // out[:, o] = sum_c X[:, c] M[c, o]
+template <typename VT>
 __global__ __launch_bounds__(256) void k_combine(Basis X, int n, const double* __restrict__ M,
                                                  int nout, double* __restrict__ out, int64_t ldo) {
   __shared__ double Msh[4096];
@@ -760,7 +721,7 @@ __global__ __launch_bounds__(256) void k_combine(Basis X, int n, const double* _
   if (row >= n) return;
   double xv[96];
   const int nc = min(ncol, 96);
-  for (int c = 0; c < nc; ++c) xv[c] = basis_at(X, c, row);
+  for (int c = 0; c < nc; ++c) xv[c] = basis_at<VT>(X, c, row);
   for (int o = 0; o < nout; ++o) {
     double s = 0.0;
     for (int c = 0; c < nc; ++c) s = fma(xv[c], Msh[(int64_t)o * ncol + c], s);
@@ -768,27 +729,29 @@ __global__ __launch_bounds__(256) void k_combine(Basis X, int n, const double* _
   }
 }
 
+template <typename VT>
 __global__ __launch_bounds__(256) void k_cycle_update(Basis Xd, const double* __restrict__ cd,
-                                                      float* __restrict__ d, Basis Xr,
+                                                      VT* __restrict__ d, Basis Xr,
                                                       const double* __restrict__ cr,
-                                                      float* __restrict__ r, int n) {
+                                                      VT* __restrict__ r, int n) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
   if (d) {
     const int nc = Xd.kc + Xd.nv;
     double s = 0.0;
-    for (int c = 0; c < nc; ++c) s = fma(basis_at(Xd, c, row), cd[c], s);
-    d[row] = (float)((double)d[row] + s);
+    for (int c = 0; c < nc; ++c) s = fma(basis_at<VT>(Xd, c, row), cd[c], s);
+    d[row] = (VT)((double)d[row] + s);
   }
   if (r) {
     const int nc = Xr.kc + Xr.nv;
     double s = 0.0;
-    for (int c = 0; c < nc; ++c) s = fma(basis_at(Xr, c, row), cr[c], s);
-    r[row] = (float)((double)r[row] - s);
+    for (int c = 0; c < nc; ++c) s = fma(basis_at<VT>(Xr, c, row), cr[c], s);
+    r[row] = (VT)((double)r[row] - s);
   }
 }
 
 // G[o * nx + c] = sum_rows X[row, c] Y[row, o]
+template <typename VT>
 __global__ __launch_bounds__(256) void k_gram(Basis X, const double* __restrict__ Y, int ny,
                                               int64_t ldy, int n, double* __restrict__ G,
                                               double* __restrict__ partial,
@@ -814,7 +777,7 @@ __global__ __launch_bounds__(256) void k_gram(Basis X, const double* __restrict_
         const int r0 = wave * kWave;
         for (int r = 0; r < kWave; ++r) {
           const int rr = rbase + r0 + r;
-          if (rr < n) acc = fma(basis_at(X, c, rr), ysh[r0 + r], acc);
+          if (rr < n) acc = fma(basis_at<VT>(X, c, rr), ysh[r0 + r], acc);
         }
       }
       red[wave][lane] = acc;
@@ -838,13 +801,15 @@ __global__ __launch_bounds__(256) void k_gram(Basis X, const double* __restrict_
   if (tid == 0) *counter = 0u;
 }
 
+template <typename VT>
 __global__ void k_scale_round(const double* __restrict__ r, double s, double* __restrict__ out,
                               int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (double)(float)(r[i] / s);
+  if (i < n) out[i] = round_u<VT>(r[i] / s);
 }
 
-__global__ void k_x_update(double* __restrict__ x, const float* __restrict__ d, double s, int n) {
+template <typename VT>
+__global__ void k_x_update(double* __restrict__ x, const VT* __restrict__ d, double s, int n) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -853,9 +818,10 @@ __global__ void k_x_update(double* __restrict__ x, const float* __restrict__ d, 
   }
 }
 
-__global__ void k_div_f32(const float* __restrict__ w, double s, float* __restrict__ out, int n) {
+template <typename VT>
+__global__ void k_div_u(const VT* __restrict__ w, double s, VT* __restrict__ out, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (float)((double)w[i] / s);
+  if (i < n) out[i] = (VT)((double)w[i] / s);
 }
 
 __global__ void k_maxabs(const double* __restrict__ v, int n, unsigned long long* out) {
@@ -1003,42 +969,81 @@ void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store
 }
 
 void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_ortho, dim3(nblocks(a.n, kRowsPerBlock)), dim3(256), 0, s, a, mode);
+  if (a.X.v64)
+    hipLaunchKernelGGL(k_ortho<double>, dim3(nblocks(a.n, kRowsPerBlock)), dim3(256), 0, s, a,
+                       mode);
+  else
+    hipLaunchKernelGGL(k_ortho<float>, dim3(nblocks(a.n, kRowsPerBlock)), dim3(256), 0, s, a,
+                       mode);
 }
 
-void launch_normalize(const float* w, float* vout, const double* H, int ldh, int step, int n,
-                      const CycleState* gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_normalize, dim3(nblocks(n, 256)), dim3(256), 0, s, w, vout, H, ldh, step,
-                     n, gate);
+void launch_normalize(const void* w, void* vout, int v64, const double* H, int ldh, int step,
+                      int n, const CycleState* gate, hipStream_t s) {
+  if (v64)
+    hipLaunchKernelGGL(k_normalize<double>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                       static_cast<const double*>(w), static_cast<double*>(vout), H, ldh, step,
+                       n, gate);
+  else
+    hipLaunchKernelGGL(k_normalize<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                       static_cast<const float*>(w), static_cast<float*>(vout), H, ldh, step, n,
+                       gate);
 }
 
 void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(nblocks(n, 256)), dim3(256), 0, s, X, n, M, nout, out, ldo);
+  if (X.v64)
+    hipLaunchKernelGGL(k_combine<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, X, n, M, nout,
+                       out, ldo);
+  else
+    hipLaunchKernelGGL(k_combine<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, X, n, M, nout,
+                       out, ldo);
 }
 
-void launch_cycle_update(const Basis& Xd, const double* cd, float* d, const Basis& Xr,
-                         const double* cr, float* r, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_update, dim3(nblocks(n, 256)), dim3(256), 0, s, Xd, cd, d, Xr, cr, r,
-                     n);
+void launch_cycle_update(const Basis& Xd, const double* cd, void* d, const Basis& Xr,
+                         const double* cr, void* r, int n, int v64, hipStream_t s) {
+  if (v64)
+    hipLaunchKernelGGL(k_cycle_update<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, Xd, cd,
+                       static_cast<double*>(d), Xr, cr, static_cast<double*>(r), n);
+  else
+    hipLaunchKernelGGL(k_cycle_update<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, Xd, cd,
+                       static_cast<float*>(d), Xr, cr, static_cast<float*>(r), n);
 }
 
 void launch_gram(const Basis& X, const double* Y, int ny, int64_t ldy, int n, double* G,
                  double* partial, unsigned int* counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_gram, dim3(nblocks(n, kRowsPerBlock)), dim3(256), 0, s, X, Y, ny, ldy, n,
-                     G, partial, counter);
+  if (X.v64)
+    hipLaunchKernelGGL(k_gram<double>, dim3(nblocks(n, kRowsPerBlock)), dim3(256), 0, s, X, Y,
+                       ny, ldy, n, G, partial, counter);
+  else
+    hipLaunchKernelGGL(k_gram<float>, dim3(nblocks(n, kRowsPerBlock)), dim3(256), 0, s, X, Y, ny,
+                       ldy, n, G, partial, counter);
 }
 
-void launch_scale_round(const double* r, double sc, double* out, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_round, dim3(nblocks(n, 256)), dim3(256), 0, s, r, sc, out, n);
+void launch_scale_round(const double* r, double sc, double* out, int n, int v64, hipStream_t s) {
+  if (v64)
+    hipLaunchKernelGGL(k_scale_round<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, r, sc, out,
+                       n);
+  else
+    hipLaunchKernelGGL(k_scale_round<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, r, sc, out,
+                       n);
 }
 
-void launch_x_update(double* x, const float* d, double sc, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_x_update, dim3(nblocks(n, 256)), dim3(256), 0, s, x, d, sc, n);
+void launch_x_update(double* x, const void* d, int v64, double sc, int n, hipStream_t s) {
+  if (v64)
+    hipLaunchKernelGGL(k_x_update<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, x,
+                       static_cast<const double*>(d), sc, n);
+  else
+    hipLaunchKernelGGL(k_x_update<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, x,
+                       static_cast<const float*>(d), sc, n);
 }
 
-void launch_div_f32(const float* w, double sc, float* out, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_div_f32, dim3(nblocks(n, 256)), dim3(256), 0, s, w, sc, out, n);
+void launch_div_u(const void* w, double sc, void* out, int v64, int n, hipStream_t s) {
+  if (v64)
+    hipLaunchKernelGGL(k_div_u<double>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                       static_cast<const double*>(w), sc, static_cast<double*>(out), n);
+  else
+    hipLaunchKernelGGL(k_div_u<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
+                       static_cast<const float*>(w), sc, static_cast<float*>(out), n);
 }
 
 void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t s) {

@@ -162,10 +162,13 @@ struct gmresir_ctx {
   double norm_a = 0.0;
   double t_factor = 0.0;
   int m = 0, k = 0;
+  int u64 = 0;    // working precision fp64: vectors in fp64, A-tilde in double-double
+  int rdd = 0;    // residual in double-double
+  size_t ue = 4;  // bytes per element of a vector in u
 
   // matrices
   double* A64 = nullptr;
-  float* Au = nullptr;
+  float* Au = nullptr;  // fl32(A) (u = fp32; for u = fp64, A_u is A64)
   void* S = nullptr;
   int* perm = nullptr;    // logical -> physical row of S
   int* permP = nullptr;   // logical -> row of A (P)
@@ -181,8 +184,10 @@ struct gmresir_ctx {
   // solve buffers (length ld, zero padded)
   double *x = nullptr, *b = nullptr, *r64 = nullptr, *t64 = nullptr, *y64 = nullptr,
          *z64 = nullptr;
-  float *z32 = nullptr, *w32 = nullptr, *d32 = nullptr, *r32 = nullptr;
-  float* V = nullptr;
+  // vectors in u (fp32, or fp64 when u64)
+  void *zu = nullptr, *wu = nullptr, *du = nullptr, *ru = nullptr;
+  void* V = nullptr;
+  double *tl = nullptr, *yl = nullptr;  // low parts of the double-double products (u64)
   double *C = nullptr, *U = nullptr, *Cn = nullptr, *Un = nullptr;
   int kc_keep = 0;  // columns of U carried to the next correction solve
   double *Hd = nullptr, *Bd = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
@@ -289,12 +294,12 @@ int validate_opts(const gmresir_opts* o) {
     set_error("uf must be FP16, BF16 or FP32");
     return GMRESIR_EINVAL;
   }
-  if (o->u != GMRESIR_FP32) {
-    set_error("this library supports u = FP32 (u^2 = fp64)");
+  if (o->u != GMRESIR_FP32 && o->u != GMRESIR_FP64) {
+    set_error("u must be FP32 (u^2 = fp64) or FP64 (u^2 = double-double)");
     return GMRESIR_EINVAL;
   }
-  if (o->ur != GMRESIR_FP64) {
-    set_error("this library supports ur = FP64");
+  if (o->ur != GMRESIR_FP64 && o->ur != GMRESIR_DD) {
+    set_error("ur must be FP64 or DD");
     return GMRESIR_EINVAL;
   }
   if (!(rf <= ru && ru <= rr)) {
@@ -355,11 +360,9 @@ int alloc_solve(gmresir_ctx* h) {
   GIR_TRY(dalloc(h->arena, &h->t64, ld));
   GIR_TRY(dalloc(h->arena, &h->y64, ld));
   GIR_TRY(dalloc(h->arena, &h->z64, ld));
-  GIR_TRY(dalloc(h->arena, &h->z32, ld));
-  GIR_TRY(dalloc(h->arena, &h->w32, ld));
-  GIR_TRY(dalloc(h->arena, &h->d32, ld));
-  GIR_TRY(dalloc(h->arena, &h->r32, ld));
-  GIR_TRY(dalloc(h->arena, &h->V, ld * (m + 1)));
+  void** uv[] = {&h->zu, &h->wu, &h->du, &h->ru};
+  for (void** p : uv) GIR_TRY(dalloc(h->arena, reinterpret_cast<char**>(p), ld * h->ue));
+  GIR_TRY(dalloc(h->arena, reinterpret_cast<char**>(&h->V), ld * (m + 1) * h->ue));
   GIR_TRY(dalloc(h->arena, &h->C, ld * k));
   GIR_TRY(dalloc(h->arena, &h->U, ld * k));
   GIR_TRY(dalloc(h->arena, &h->Cn, ld * k));
@@ -378,12 +381,19 @@ int alloc_solve(gmresir_ctx* h) {
   GIR_TRY(dalloc(h->arena, &h->Gdev, 4096));
   const size_t grid = (ld + 255) / 256;
   GIR_TRY(dalloc(h->arena, &h->partial, grid * 4096));
-  const int64_t nxw = 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
+  // tagged words of the two solves: 2 per row in 128-row blocks (fp64), 4 per
+  // row in 64-row blocks (double-double)
+  const int64_t nxw =
+      h->u64 ? gir::kDdWordsPerRow * ((h->n + 63) / 64) * 64
+             : 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
   GIR_TRY(dalloc(h->arena, &h->xwL, (size_t)nxw));
   GIR_TRY(dalloc(h->arena, &h->xwU, (size_t)nxw));
   gir::launch_fill_i32(reinterpret_cast<int*>(h->xwL), 0, 2 * nxw, h->stream);
   gir::launch_fill_i32(reinterpret_cast<int*>(h->xwU), 0, 2 * nxw, h->stream);
-  if (h->k > 0) {
+  if (h->u64) {
+    GIR_TRY(dalloc(h->arena, &h->tl, ld));
+    GIR_TRY(dalloc(h->arena, &h->yl, ld));
+  } else if (h->k > 0) {
     const int64_t nm = nxw * gir::kTrsvMaxRhs;
     GIR_TRY(dalloc(h->arena, &h->xwLm, (size_t)nm));
     GIR_TRY(dalloc(h->arena, &h->xwUm, (size_t)nm));
@@ -395,9 +405,13 @@ int alloc_solve(gmresir_ctx* h) {
   // zero padding of every vector
   double* dv[] = {h->x, h->b, h->r64, h->t64, h->y64, h->z64};
   for (double* p : dv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(double) * ld, h->stream));
-  float* fv[] = {h->z32, h->w32, h->d32, h->r32};
-  for (float* p : fv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(float) * ld, h->stream));
-  GIR_HIP(hipMemsetAsync(h->V, 0, sizeof(float) * ld * (m + 1), h->stream));
+  void* fv[] = {h->zu, h->wu, h->du, h->ru};
+  for (void* p : fv) GIR_HIP(hipMemsetAsync(p, 0, h->ue * ld, h->stream));
+  GIR_HIP(hipMemsetAsync(h->V, 0, h->ue * ld * (m + 1), h->stream));
+  if (h->u64) {
+    GIR_HIP(hipMemsetAsync(h->tl, 0, sizeof(double) * ld, h->stream));
+    GIR_HIP(hipMemsetAsync(h->yl, 0, sizeof(double) * ld, h->stream));
+  }
   GIR_TRY(pinned_init(h));
   h->ev.resize(kEventRing);
   for (auto& e2 : h->ev) GIR_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
@@ -407,14 +421,18 @@ int alloc_solve(gmresir_ctx* h) {
 int alloc_common(gmresir_ctx* h) {
   const size_t ld = (size_t)h->ld, n = (size_t)h->n;
   GIR_TRY(dalloc(h->arena, &h->A64, n * ld));
-  GIR_TRY(dalloc(h->arena, &h->Au, n * ld));
+  if (!h->u64) GIR_TRY(dalloc(h->arena, &h->Au, n * ld));
   GIR_TRY(dalloc(h->arena, reinterpret_cast<char**>(&h->S), n * ld * store_bytes(h->store)));
   GIR_TRY(dalloc(h->arena, &h->perm, n));
   GIR_TRY(dalloc(h->arena, &h->ipiv, n));
-  const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
-  GIR_TRY(dalloc(h->arena, &h->Linv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
-  GIR_TRY(dalloc(h->arena, &h->Uinv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
-  GIR_TRY(dalloc(h->arena, &h->dtmp, ((n + 63) / 64) * 64 * 64));
+  if (!h->u64) {
+    // fp64 inverses of the diagonal blocks (the double-double solves
+    // substitute within the block instead)
+    const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
+    GIR_TRY(dalloc(h->arena, &h->Linv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    GIR_TRY(dalloc(h->arena, &h->Uinv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    GIR_TRY(dalloc(h->arena, &h->dtmp, ((n + 63) / 64) * 64 * 64));
+  }
   GIR_TRY(dalloc(h->arena, &h->st, 1));
   GIR_TRY(dalloc(h->arena, &h->counter, 8));
   GIR_TRY(dalloc(h->arena, &h->norms, 4));
@@ -565,8 +583,9 @@ int run_lu(gmresir_ctx* h) {
   int* flag = reinterpret_cast<int*>(h->counter + 2);
   GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
   gir::launch_check_factors(h->S, n, h->ld, h->store, flag, h->stream);
-  gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->dtmp,
-                            h->stream);
+  if (!h->u64)
+    gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->dtmp,
+                              h->stream);
   gir::CycleState hs{};
   int hflag = 0;
   GIR_TRY(download(h, &hs, h->st, sizeof(hs)));
@@ -608,6 +627,9 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
   h->m = opts->m;
   h->k = opts->k;
   h->store = store_of(opts->uf);
+  h->u64 = opts->u == GMRESIR_FP64 ? 1 : 0;
+  h->rdd = opts->ur == GMRESIR_DD ? 1 : 0;
+  h->ue = h->u64 ? 8 : 4;
   h->stream = reinterpret_cast<hipStream_t>(stream);
   *hp = h;
   return 0;
@@ -622,13 +644,32 @@ int next_epoch(gmresir_ctx* h) {
   return h->epoch;
 }
 
-// y (fp64 or fp32 rounded) = M^-1 in (2^e U^-1 L^-1 P in), P applied by gather
-int precond(gmresir_ctx* h, const double* in, const int* permIn, double* out64, float* out32,
-            const gir::CycleState* gate, int step) {
+// M^-1 in = 2^e U^-1 L^-1 P in (P applied by gather through permIn) in u^2:
+// fp64 for u = fp32, double-double for u = fp64 (inl: low parts of in, or
+// null).  The result goes to out64 (fp64) or outu (rounded to u), either may
+// be null.
+int precond(gmresir_ctx* h, const double* in, const double* inl, const int* permIn, double* out64,
+            void* outu, const gir::CycleState* gate, int step) {
   const int n = (int)h->n;
-  // the stored triangle and three vectors of n float64 values
-  const double bytes = 0.5 * (double)n * (double)(n + 1) * (double)store_bytes(h->store) +
-                       24.0 * (double)n;
+  // the stored triangle and the vectors read and written
+  const double tri = 0.5 * (double)n * (double)(n + 1) * (double)store_bytes(h->store);
+  if (h->u64) {
+    double* out = out64 ? out64 : static_cast<double*>(outu);
+    const int eL = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvL, tri + 32.0 * n, h->stream, gate, step, [&] {
+      gir::launch_trsv_dd(h->S, h->ld, h->permS, h->store, n, false, in, inl, permIn, h->y64,
+                          h->yl, 1.0, nullptr, h->xwL, eL, gate, step, &h->st->abort, h->stream);
+    }));
+    const int eU = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvU, tri + 24.0 * n, h->stream, gate, step, [&] {
+      gir::launch_trsv_dd(h->S, h->ld, h->permS, h->store, n, true, h->y64, h->yl, nullptr,
+                          nullptr, nullptr, h->scale, out, h->xwU, eU, gate, step,
+                          &h->st->abort, h->stream);
+    }));
+    return 0;
+  }
+  const double bytes = tri + 24.0 * (double)n;
+  float* out32 = static_cast<float*>(outu);
   const int eL = next_epoch(h);
   GIR_TRY(timed(h, kKcTrsvL, bytes, h->stream, gate, step, [&] {
     gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->Linv, h->y64,
@@ -643,24 +684,39 @@ int precond(gmresir_ctx* h, const double* in, const int* permIn, double* out64, 
   return 0;
 }
 
-// A-tilde v (v float or double)
-int atilde(gmresir_ctx* h, const float* v32, const double* v64, double* out64, float* out32,
+// A-tilde v for v in u (vu) or in fp64 (v64): the product with A_u in u^2
+// (fp64, or double-double from A itself for u = fp64), then M^-1
+int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, void* outu,
            const gir::CycleState* gate, int step) {
   const double nn = (double)h->n;
+  if (h->u64) {
+    const double* v = vu ? static_cast<const double*>(vu) : v64;
+    GIR_TRY(timed(h, kKcGemv, 8.0 * nn * nn + 24.0 * nn, h->stream, gate, step, [&] {
+      gir::launch_gemv_dd(h->A64, h->ld, h->permP, (int)h->n, v, h->t64, h->tl, gate, step,
+                          h->stream);
+    }));
+    return precond(h, h->t64, h->tl, nullptr, out64, outu, gate, step);
+  }
+  const float* v32 = static_cast<const float*>(vu);
   GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + (v32 ? 4.0 : 8.0) * nn + 8.0 * nn, h->stream, gate,
                 step, [&] {
                   gir::launch_gemv_au(h->Au, h->ld, h->permP, (int)h->n, v32, v64, h->t64, gate,
                                       step, h->stream);
                 }));
-  return precond(h, h->t64, nullptr, out64, out32, gate, step);
+  return precond(h, h->t64, nullptr, nullptr, out64, outu, gate, step);
 }
 
 // C(:, 0:kk) = A-tilde Y(:, 0:kk) for fp64 columns (ld apart): the products
 // with A_u one column at a time, the two triangular solves for up to eight
-// columns at once
+// columns at once (double-double: one column at a time)
 int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
   const int n = (int)h->n;
   const int64_t ld = h->ld;
+  if (h->u64) {
+    for (int c = 0; c < kk; ++c)
+      GIR_TRY(atilde(h, nullptr, Y + (size_t)c * ld, C + (size_t)c * ld, nullptr, nullptr, 0));
+    return 0;
+  }
   const int64_t xstride = 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
   const double nn = (double)n;
   const double tbytes = 0.5 * nn * (nn + 1.0) * (double)store_bytes(h->store);
@@ -687,19 +743,25 @@ int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
   return 0;
 }
 
-gir::Basis basis(const double* c, int kc, int64_t ldc, const float* v, int nv, int64_t ldv) {
+// fp64 columns c (kc of them) followed by nv columns v in u
+gir::Basis basis(const gmresir_ctx* h, const double* c, int kc, int64_t ldc, const void* v,
+                 int nv, int64_t ldv) {
   gir::Basis X;
   X.c64 = c;
   X.kc = kc;
   X.ldc = ldc;
-  X.v32 = v;
+  X.v = v;
   X.nv = nv;
   X.ldv = ldv;
+  X.v64 = h->u64;
   return X;
 }
 
-// dots (X^T w) and/or squared norm of a fp32 vector, synchronous result
-int dots_norm(gmresir_ctx* h, const gir::Basis& X, const float* w, double* dots, double* nrm2) {
+// column j of V
+void* vcol(gmresir_ctx* h, int j) { return static_cast<char*>(h->V) + (size_t)j * h->ld * h->ue; }
+
+// dots (X^T w) and/or squared norm of a vector in u, synchronous result
+int dots_norm(gmresir_ctx* h, const gir::Basis& X, const void* w, double* dots, double* nrm2) {
   gir::OrthoArgs a{};
   a.X = X;
   a.n = (int)h->n;
@@ -743,7 +805,7 @@ struct SolveStats {
   int its = 0;
 };
 
-// GCRO-DR(m, k) for A-tilde d = z (z in h->z32); result in h->d32.
+// GCRO-DR(m, k) for A-tilde d = z (z in h->zu); result in h->du.
 int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   const int n = (int)h->n;
   const int64_t ld = h->ld;
@@ -753,12 +815,13 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   double beta0 = 0.0;
   {
     double n2 = 0.0;
-    GIR_TRY(dots_norm(h, basis(nullptr, 0, ld, nullptr, 0, ld), h->z32, nullptr, &n2));
+    GIR_TRY(dots_norm(h, basis(h, nullptr, 0, ld, nullptr, 0, ld), h->zu, nullptr, &n2));
     beta0 = std::sqrt(n2);
   }
   // small device copies and fills run as kernels (no copy-engine latency)
-  gir::launch_copy_i32(reinterpret_cast<int*>(h->r32), reinterpret_cast<const int*>(h->z32), n, s);
-  gir::launch_fill_i32(reinterpret_cast<int*>(h->d32), 0, n, s);
+  const int64_t uw = (int64_t)n * (int64_t)(h->ue / 4);  // 4-byte words of a vector in u
+  gir::launch_copy_i32(static_cast<int*>(h->ru), static_cast<const int*>(h->zu), uw, s);
+  gir::launch_fill_i32(static_cast<int*>(h->du), 0, uw, s);
   stats.its = 0;
   if (beta0 == 0.0) return 0;
   const double tol = h->o.tau * beta0;
@@ -772,17 +835,17 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     // CholeskyQR2 in fp64
     std::vector<double> G1, G2, R1(kk * kk), R2(kk * kk), Ri(kk * kk), Rt(kk * kk);
     bool ok = true;
-    GIR_TRY(gram(h, basis(h->C, kk, ld, nullptr, 0, ld), h->C, kk, G1));
+    GIR_TRY(gram(h, basis(h, h->C, kk, ld, nullptr, 0, ld), h->C, kk, G1));
     ok = gir::la::cholesky_upper(G1.data(), kk, R1.data());
     if (ok) {
       gir::la::inv_upper(R1.data(), kk, Ri.data());
-      GIR_TRY(combine(h, basis(h->C, kk, ld, nullptr, 0, ld), Ri, kk, h->Cn));
-      GIR_TRY(gram(h, basis(h->Cn, kk, ld, nullptr, 0, ld), h->Cn, kk, G2));
+      GIR_TRY(combine(h, basis(h, h->C, kk, ld, nullptr, 0, ld), Ri, kk, h->Cn));
+      GIR_TRY(gram(h, basis(h, h->Cn, kk, ld, nullptr, 0, ld), h->Cn, kk, G2));
       ok = gir::la::cholesky_upper(G2.data(), kk, R2.data());
     }
     if (ok) {
       gir::la::inv_upper(R2.data(), kk, Ri.data());
-      GIR_TRY(combine(h, basis(h->Cn, kk, ld, nullptr, 0, ld), Ri, kk, h->C));
+      GIR_TRY(combine(h, basis(h, h->Cn, kk, ld, nullptr, 0, ld), Ri, kk, h->C));
       // R = R2 R1, U = Y R^-1
       for (int j = 0; j < kk; ++j)
         for (int i = 0; i < kk; ++i) {
@@ -791,16 +854,16 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
           Rt[(size_t)j * kk + i] = sum;
         }
       gir::la::inv_upper(Rt.data(), kk, Ri.data());
-      GIR_TRY(combine(h, basis(h->U, kk, ld, nullptr, 0, ld), Ri, kk, h->Un));
+      GIR_TRY(combine(h, basis(h, h->U, kk, ld, nullptr, 0, ld), Ri, kk, h->Un));
       std::swap(h->U, h->Un);
       kc = kk;
       // d = U (C^T r), r = r - C (C^T r)
       std::vector<double> ctr(kc);
       double n2;
-      GIR_TRY(dots_norm(h, basis(h->C, kc, ld, nullptr, 0, ld), h->r32, ctr.data(), &n2));
+      GIR_TRY(dots_norm(h, basis(h, h->C, kc, ld, nullptr, 0, ld), h->ru, ctr.data(), &n2));
       GIR_TRY(upload(h, h->coefA, ctr.data(), sizeof(double) * kc));
-      gir::launch_cycle_update(basis(h->U, kc, ld, nullptr, 0, ld), h->coefA, h->d32,
-                               basis(h->C, kc, ld, nullptr, 0, ld), h->coefA, h->r32, n, s);
+      gir::launch_cycle_update(basis(h, h->U, kc, ld, nullptr, 0, ld), h->coefA, h->du,
+                               basis(h, h->C, kc, ld, nullptr, 0, ld), h->coefA, h->ru, n, h->u64, s);
       GIR_HIP(hipGetLastError());
     }
   }
@@ -809,14 +872,14 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   while (true) {
     std::vector<double> ctr(std::max(kc, 1));
     double n2 = 0.0;
-    GIR_TRY(dots_norm(h, basis(h->C, kc, ld, nullptr, 0, ld), h->r32, kc ? ctr.data() : nullptr,
+    GIR_TRY(dots_norm(h, basis(h, h->C, kc, ld, nullptr, 0, ld), h->ru, kc ? ctr.data() : nullptr,
                       &n2));
     const double rn = std::sqrt(n2);
     if (rn <= tol) break;
     if (stats.its >= cap) break;
     const int nsteps = std::min(m - kc, cap - stats.its);
     // v1 = r / ||r||; device cycle state and Givens right-hand side
-    gir::launch_div_f32(h->r32, rn, h->V, n, s);
+    gir::launch_div_u(h->ru, rn, h->V, h->u64, n, s);
     gir::CycleState st0{};
     st0.tol = tol;
     st0.est = rn;
@@ -830,25 +893,24 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     int queued = 0;
     const size_t trec0 = h->trec.size();
     for (int j = 0; j < nsteps; ++j) {
-      float* vj = h->V + (size_t)j * ld;
-      GIR_TRY(atilde(h, vj, nullptr, nullptr, h->w32, h->st, j));
+      GIR_TRY(atilde(h, vcol(h, j), nullptr, nullptr, h->wu, h->st, j));
       gir::OrthoArgs a{};
-      a.X = basis(h->C, kc, ld, h->V, j + 1, ld);
+      a.X = basis(h, h->C, kc, ld, h->V, j + 1, ld);
       a.n = n;
-      a.w_in = h->w32;
-      a.w_out = h->w32;
+      a.w_in = h->wu;
+      a.w_out = h->wu;
       a.partial = h->partial;
       a.counter = h->counter;
       a.gate = h->st;
       a.step = j;
       a.dots_out = h->h1;
       // basis read once per pass; the update pass also reads and writes w
-      const double xb = (8.0 * kc + 4.0 * (j + 1)) * n;
-      GIR_TRY(timed(h, kKcOrtho, xb + 4.0 * n, s, h->st, j,
+      const double xb = (8.0 * kc + (double)h->ue * (j + 1)) * n;
+      GIR_TRY(timed(h, kKcOrtho, xb + (double)h->ue * n, s, h->st, j,
                     [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
       a.coef = h->h1;
       a.dots_out = h->h2;
-      GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 8.0 * n, s, h->st, j,
+      GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 2.0 * h->ue * n, s, h->st, j,
                     [&] { gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s); }));
       a.coef = h->h2;
       a.h_prev = h->h1;
@@ -861,10 +923,10 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       a.sn = h->sn;
       a.g = h->g;
       a.st = h->st;
-      GIR_TRY(timed(h, kKcOrtho, xb + 8.0 * n, s, h->st, j, [&] {
+      GIR_TRY(timed(h, kKcOrtho, xb + 2.0 * h->ue * n, s, h->st, j, [&] {
         gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
       }));
-      gir::launch_normalize(h->w32, h->V + (size_t)(j + 1) * ld, h->Hd, m + 1, j, n, h->st, s);
+      gir::launch_normalize(h->wu, vcol(h, j + 1), h->u64, h->Hd, m + 1, j, n, h->st, s);
       static_assert(sizeof(gir::CycleState) % 4 == 0, "CycleState is copied as words");
       gir::launch_copy_words(&h->st_host[j], h->st, sizeof(gir::CycleState) / 4, s);
       GIR_HIP(hipEventRecord(h->ev[j % kEventRing], s));
@@ -899,8 +961,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       std::vector<double> cdv(y.begin(), y.begin() + J);
       GIR_TRY(upload(h, h->coefA, cdv.data(), sizeof(double) * std::max(J, 1)));
       GIR_TRY(upload(h, h->coefB, hy.data(), sizeof(double) * (J + 1)));
-      gir::launch_cycle_update(basis(nullptr, 0, ld, h->V, J, ld), h->coefA, h->d32,
-                               basis(nullptr, 0, ld, h->V, J + 1, ld), h->coefB, h->r32, n, s);
+      gir::launch_cycle_update(basis(h, nullptr, 0, ld, h->V, J, ld), h->coefA, h->du,
+                               basis(h, nullptr, 0, ld, h->V, J + 1, ld), h->coefB, h->ru, n, h->u64, s);
       GIR_HIP(hipGetLastError());
       if (k > 0 && J > 0) {
         // first-cycle harmonic Ritz: Hbar^T Hbar z = theta H^T z
@@ -928,8 +990,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
                 for (int t = 0; t < kn; ++t) sum += Pk[(size_t)t * J + c] * Ri[(size_t)o * kn + t];
                 PR[(size_t)o * J + c] = sum;
               }
-            GIR_TRY(combine(h, basis(nullptr, 0, ld, h->V, J + 1, ld), Q, kn, h->Cn));
-            GIR_TRY(combine(h, basis(nullptr, 0, ld, h->V, J, ld), PR, kn, h->Un));
+            GIR_TRY(combine(h, basis(h, nullptr, 0, ld, h->V, J + 1, ld), Q, kn, h->Cn));
+            GIR_TRY(combine(h, basis(h, nullptr, 0, ld, h->V, J, ld), PR, kn, h->Un));
             std::swap(h->C, h->Cn);
             std::swap(h->U, h->Un);
             kc = kn;
@@ -939,7 +1001,7 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     } else {
       // D = diag(1 / ||U e_i||)
       std::vector<double> UU;
-      GIR_TRY(gram(h, basis(h->U, kc, ld, nullptr, 0, ld), h->U, kc, UU));
+      GIR_TRY(gram(h, basis(h, h->U, kc, ld, nullptr, 0, ld), h->U, kc, UU));
       std::vector<double> dk(kc);
       for (int i = 0; i < kc; ++i) dk[i] = 1.0 / std::sqrt(UU[(size_t)i * kc + i]);
       std::vector<double> y1(kc), by2(kc, 0.0);
@@ -956,13 +1018,13 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       for (int i = 0; i <= J; ++i) crv[kc + i] = hy[i];
       GIR_TRY(upload(h, h->coefA, cdv.data(), sizeof(double) * cdv.size()));
       GIR_TRY(upload(h, h->coefB, crv.data(), sizeof(double) * crv.size()));
-      gir::launch_cycle_update(basis(h->U, kc, ld, h->V, J, ld), h->coefA, h->d32,
-                               basis(h->C, kc, ld, h->V, J + 1, ld), h->coefB, h->r32, n, s);
+      gir::launch_cycle_update(basis(h, h->U, kc, ld, h->V, J, ld), h->coefA, h->du,
+                               basis(h, h->C, kc, ld, h->V, J + 1, ld), h->coefB, h->ru, n, h->u64, s);
       GIR_HIP(hipGetLastError());
       if (J > 0) {
         const int rows = kc + J + 1, cols = kc + J;
         std::vector<double> W;  // [C V_{J+1}]^T U  (rows x kc)
-        GIR_TRY(gram(h, basis(h->C, kc, ld, h->V, J + 1, ld), h->U, kc, W));
+        GIR_TRY(gram(h, basis(h, h->C, kc, ld, h->V, J + 1, ld), h->U, kc, W));
         std::vector<double> Gm((size_t)rows * cols, 0.0), Mm((size_t)rows * cols, 0.0);
         for (int i = 0; i < kc; ++i) Gm[(size_t)i * rows + i] = dk[i];
         for (int c = 0; c < J; ++c) {
@@ -993,8 +1055,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
                 // U-tilde = U D: fold D into the coefficients of the U columns
                 PR[(size_t)o * cols + c] = (c < kc) ? sum * dk[c] : sum;
               }
-            GIR_TRY(combine(h, basis(h->C, kc, ld, h->V, J + 1, ld), Q, kn, h->Cn));
-            GIR_TRY(combine(h, basis(h->U, kc, ld, h->V, J, ld), PR, kn, h->Un));
+            GIR_TRY(combine(h, basis(h, h->C, kc, ld, h->V, J + 1, ld), Q, kn, h->Cn));
+            GIR_TRY(combine(h, basis(h, h->U, kc, ld, h->V, J, ld), PR, kn, h->Un));
             std::swap(h->C, h->Cn);
             std::swap(h->U, h->Un);
             kc = kn;
@@ -1032,13 +1094,18 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     return GMRESIR_ERANGE;
   }
   // x0 = M^-1 b in u^2, kept in fp64
-  GIR_TRY(precond(h, h->b, h->permP, h->x, nullptr, nullptr, 0));
+  GIR_TRY(precond(h, h->b, nullptr, h->permP, h->x, nullptr, nullptr, 0));
   int status = GMRESIR_ENOCONV;
   const int imax = h->o.imax;
   int i = 0;
   for (;; ++i) {
     GIR_TRY(timed(h, kKcResid, 8.0 * (double)n * (double)n + 24.0 * (double)n, s, nullptr, 0,
-                  [&] { gir::launch_residual(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s); }));
+                  [&] {
+                    if (h->rdd)
+                      gir::launch_residual_dd(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s);
+                    else
+                      gir::launch_residual(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s);
+                  }));
     GIR_HIP(hipGetLastError());
     unsigned long long nb[2];
     GIR_TRY(download(h, nb, h->norms, sizeof(nb)));
@@ -1057,13 +1124,13 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
       break;
     }
     if (i >= imax) break;
-    gir::launch_scale_round(h->r64, rmax, h->t64, n, s);  // r-hat = fl32(r / s)
-    GIR_TRY(precond(h, h->t64, h->permP, nullptr, h->z32, nullptr, 0));
+    gir::launch_scale_round(h->r64, rmax, h->t64, n, h->u64, s);  // r-hat = fl_u(r / s)
+    GIR_TRY(precond(h, h->t64, nullptr, h->permP, nullptr, h->zu, nullptr, 0));
     SolveStats ss;
     GIR_TRY(gcrodr(h, ss));
     inf.its[i] = ss.its;
     inf.total_its += ss.its;
-    gir::launch_x_update(h->x, h->d32, rmax, n, s);
+    gir::launch_x_update(h->x, h->du, h->u64, rmax, n, s);
     GIR_HIP(hipGetLastError());
   }
   inf.steps = i;
@@ -1171,7 +1238,7 @@ int gmresir_import_factors(const double* A, int64_t n, int64_t lda, const void* 
     if (rc == 0) rc = upload(h, h->ipiv, ipiv, sizeof(int) * n);
     h->permP = h->perm;
     h->permS = nullptr;
-    if (rc == 0) {
+    if (rc == 0 && !h->u64) {
       gir::launch_diag_inverses(h->S, h->ld, nullptr, h->store, (int)n, h->Linv, h->Uinv,
                                 h->dtmp, h->stream);
       if (hipGetLastError() != hipSuccess) rc = GMRESIR_EHIP;
@@ -1262,7 +1329,7 @@ int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y, void* 
   const int n = (int)h->n;
   GIR_HIP(hipMemcpyAsync(h->r64, v, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
   if (op == 0) {
-    GIR_TRY(precond(h, h->r64, h->permP, h->x, nullptr, nullptr, 0));
+    GIR_TRY(precond(h, h->r64, nullptr, h->permP, h->x, nullptr, nullptr, 0));
   } else {
     GIR_TRY(atilde(h, nullptr, h->r64, h->x, nullptr, nullptr, 0));
   }

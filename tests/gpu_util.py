@@ -18,8 +18,9 @@ def log(*args):
     sys.stdout.flush()
 
 
-def oracle_options(uf="fp16", m=20, k=5, tau=1e-4, imax=10, maxit=0, berr=1e-14):
-    return Options(uf=uf, u="fp32", ur="fp64", m=m, k=k, tau=tau, imax=imax, maxit=maxit,
+def oracle_options(uf="fp16", m=20, k=5, tau=1e-4, imax=10, maxit=0, berr=1e-14, u="fp32",
+                   ur="fp64"):
+    return Options(uf=uf, u=u, ur=ur, m=m, k=k, tau=tau, imax=imax, maxit=maxit,
                    berr_target=berr, nb=NB)
 
 

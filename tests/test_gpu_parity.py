@@ -39,7 +39,7 @@ def _dev(x):
 
 
 @pytest.mark.parametrize("n,uf", [(100, "fp16"), (257, "fp16"), (1000, "fp16"),
-                                  (300, "bf16"), (200, "fp32")])
+                                  (300, "bf16"), (200, "fp32"), (1000, "fp32")])
 def test_lu_factors_match_oracle(lib, n, uf):
     p = randsvd_problem(n, 1e4, 11)
     log(f"[lu] n={n} uf={uf}")
@@ -75,6 +75,12 @@ def test_lu_factors_match_oracle(lib, n, uf):
             f"gpu {[lu_gpu[r, nbk + c] for r, c in bad]} oracle {[res.lu[r, nbk + c] for r, c in bad]}")
     assert d_col.max() == 0.0
     assert d_row.size == 0 or d_row.max() == 0.0
+    if uf == "fp32":
+        # fp32 factors: the trailing update is accumulated in fp64 on both
+        # sides and rounded once, so the factors agree everywhere but for
+        # fp64 summation-order ties
+        assert np.array_equal(ipiv, res.ipiv)
+        assert np.mean(d > 0) <= 1e-4
     # later block columns see the fp32-accumulated trailing update (the CPU
     # reference accumulates exactly), so near-ties may pick other pivots:
     # the GPU factors must still satisfy the blocked-GEPP backward error bound
@@ -110,19 +116,25 @@ def test_preconditioned_products_with_shared_factors(lib, n):
     assert same > 0.99
 
 
-@pytest.mark.parametrize("n", [4097, 8192])
-def test_preconditioner_full_size_properties(lib, n):
-    """At the benchmark's size (oracle too slow): y = M^-1 v must satisfy
+@pytest.mark.parametrize("n,uf,u", [(4097, "fp16", "fp32"), (8192, "fp16", "fp32"),
+                                    (16384, "fp32", "fp64")])
+def test_preconditioner_full_size_properties(lib, n, uf, u):
+    """At the full sizes (oracle too slow): y = M^-1 v must satisfy
     L U (2^-e y) = P v to the fp64 substitution bound with the library's own
     factors (checked on the GPU in fp64), likewise A-tilde v against P A_u v;
-    the same launch configuration as the benchmark's solves."""
+    the same launch configuration as the solves (u = fp64: the double-double
+    kernels, A_u = A)."""
     from synthetic import randsvd_problem_torch
-    log(f"[apply-full] n={n}")
+    log(f"[apply-full] n={n} uf={uf} u={u}")
     a, _, _ = randsvd_problem_torch(n, 1e2, 3, "cuda")
-    h = lib.factor(a, m=30, k=10)
+    ur = "dd" if u == "fp64" else "fp64"
+    h = lib.factor(a, uf=uf, u=u, ur=ur, m=30, k=10)
     assert h.status == 0
     raw, ipiv, e = h.export_factors()
-    lu = torch.from_numpy(raw.view(np.float16)).to("cuda").to(torch.float64)
+    if uf == "fp16":
+        lu = torch.from_numpy(raw.view(np.float16)).to("cuda").to(torch.float64)
+    else:
+        lu = torch.from_numpy(raw).to("cuda").to(torch.float64)
     del raw
     L = torch.tril(lu, -1) + torch.eye(n, dtype=torch.float64, device="cuda")
     U = torch.triu(lu)
@@ -133,8 +145,10 @@ def test_preconditioner_full_size_properties(lib, n):
     pt = torch.from_numpy(perm).to("cuda")
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
-    v = torch.randn(n, dtype=torch.float64, device="cuda", generator=g).float().double()
-    au = a.float().double()
+    v = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    if u == "fp32":
+        v = v.float().double()
+    au = a.float().double() if u == "fp32" else a
     for op, rhs in ((0, v[pt]), (1, (au @ v)[pt])):
         y = h.apply(op, v) * 2.0 ** (-e)
         lhs = L @ (U @ y)
@@ -230,6 +244,72 @@ def test_solve_other_factor_precisions(lib, uf, kind):
     x, info = h.solve(_dev(p.b))
     h.free()
     _compare(p, x_ref, info_ref, x.cpu().numpy(), info, 300)
+
+
+@pytest.mark.parametrize("n", [64, 200, 333])
+def test_double_double_products_with_shared_factors(lib, n):
+    """u = fp64: M^-1 v and A-tilde v in double-double with the oracle's fp32
+    factors; after rounding to fp64 the two agree to an ulp or so (the sums
+    differ only in order, far below fp64 resolution)."""
+    p = randsvd_problem(n, 1e8, 6)
+    o = oracle_options(uf="fp32", u="fp64", ur="dd", tau=1e-8)
+    f = refine.factor(p.a, o)
+    log(f"[apply-dd] n={n}")
+    h = lib.import_factors(_dev(p.a), _dev(encode_factors(f.lu, "fp32")),
+                           f.ipiv.astype(np.int32), f.e, **lib_options(o))
+    g = np.random.default_rng(n + 11)
+    v = g.standard_normal(n)
+    y0 = h.apply(0, _dev(v)).cpu().numpy()
+    y1 = h.apply(1, _dev(v)).cpu().numpy()
+    h.free()
+    r0 = refine.minv_hi(f, v, "dd")
+    r1 = refine.atilde(f, v)
+    for name, y, r in (("M^-1 v", y0, r0), ("A~v", y1, r1)):
+        err = np.max(np.abs(y - r)) / np.max(np.abs(r))
+        same = np.mean(y == r)
+        log(f"[apply-dd] n={n} {name}: max rel diff {err:.2e}, identical {same:.3f}")
+        assert err <= 4 * U64
+        assert same > 0.9
+    # the fp64 solve of the same system is visibly less accurate
+    r64 = refine.minv_hi(f, v, "fp64")
+    log(f"[apply-dd] n={n} fp64 solve differs by "
+        f"{np.max(np.abs(r64 - r0)) / np.max(np.abs(r0)):.2e}")
+
+
+def test_solve_fp64_shared_factors(lib):
+    """u = fp64 with the oracle's own fp32 factors: a system near the edge of
+    convergence (kappa u_f ~ 60, three GCRO-DR cycles, 49 Arnoldi steps)
+    isolates the fp64 Arnoldi and double-double paths from the LU."""
+    p = randsvd_problem(200, 1e9, 4)
+    o = oracle_options(uf="fp32", u="fp64", ur="dd", m=20, k=5, tau=1e-8)
+    x_ref, info_ref, f = _run_oracle(p, o)
+    log("[solve-dd-shared] randsvd n=200 kappa=1e9")
+    h = lib.import_factors(_dev(p.a), _dev(encode_factors(f.lu, "fp32")),
+                           f.ipiv.astype(np.int32), f.e, **lib_options(o))
+    x, info = h.solve(_dev(p.b))
+    h.free()
+    _compare(p, x_ref, info_ref, x.cpu().numpy(), info, 200)
+
+
+@pytest.mark.parametrize("kind,n,m,k,kappa,seed", [("randsvd", 300, 5, 2, 1e8, 3),
+                                                    ("randsvd", 200, 4, 2, 1e8, 4),
+                                                    ("randsvd", 333, 20, 0, 1e8, 4),
+                                                    ("prolate", 240, 6, 3, 0.0, 3)])
+def test_solve_fp64_working_precision(lib, kind, n, m, k, kappa, seed):
+    """(u_f, u, u_r) = (fp32, fp64, double-double) end to end, tau = 1e-8
+    (randsvd: 11-12 Arnoldi steps over four GCRO-DR cycles; prolate
+    w = 0.48: two refinement steps, the second with the recycled space)."""
+    if kind == "prolate":
+        p = prolate_problem(n, 0.48, seed=seed)
+    else:
+        p = randsvd_problem(n, kappa, seed)
+    o = oracle_options(uf="fp32", u="fp64", ur="dd", m=m, k=k, tau=1e-8)
+    x_ref, info_ref, _ = _run_oracle(p, o)
+    log(f"[solve-dd] {kind} n={n} m={m} k={k}")
+    h = lib.factor(_dev(p.a), **lib_options(o))
+    x, info = h.solve(_dev(p.b))
+    h.free()
+    _compare(p, x_ref, info_ref, x.cpu().numpy(), info, n)
 
 
 def test_edge_cases(lib):
