@@ -155,11 +155,11 @@ __global__ void k_fill_i32(int* p, int v, int64_t n) {
 //   2. the workgroup maximum is found with DPP reductions and one LDS pass,
 //      and the owner of that key copies its row to LDS;
 //   3. with G > 1, wave 0 publishes the key and the row as 64-bit words whose
-//      upper half carries the column's tag (k0 + c + 1), reads the G keys,
-//      picks the winner and reads its row.  A word is valid once its tag
-//      matches, so no fences or flags are needed; records alternate between
-//      two slots by column parity (a workgroup can be at most one column
-//      ahead of any other);
+//      upper half carries the column's tag (k0 + c + 1); one poll fetches
+//      all G records (keys and rows) and the winner is picked locally.  A
+//      word is valid once its tag matches, so no fences or flags are needed;
+//      records alternate between two slots by column parity (a workgroup can
+//      be at most one column ahead of any other);
 //   4. every row eliminates column c with the correctly rounded quotient and
 //      one fused multiply-add per remaining column, in the order of the
 //      unblocked algorithm.
@@ -175,26 +175,6 @@ __device__ __forceinline__ uint64_t xch_load(const uint64_t* p) {
 
 __device__ __forceinline__ void xch_store(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Wave-uniform poll: returns once every lane with `need` has read a word whose
-// bits above `shift` equal `tag`; false on abort or when the bound is hit.
-__device__ __forceinline__ bool poll_tagged(const uint64_t* p, bool need, uint32_t tag, int shift,
-                                            uint64_t& v, int* abortp) {
-  long long spins = 0;
-  for (;;) {
-    if (need) v = xch_load(p);
-    const bool ok = !need || (uint32_t)(v >> shift) == tag;
-    if (__all(ok)) return true;
-    __builtin_amdgcn_s_sleep(1);
-    if (((++spins) & 1023) == 0) {
-      if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-      if (spins > (1ll << 22)) {
-        __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-  }
 }
 
 // 64 values of a row from a 16-byte aligned address whose 64-element span
@@ -345,6 +325,8 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
       }
       bool ok = true;
       uint64_t v[kMaxPanelWgs * kMaxNb / kRowThreads];
+      uint64_t kk = 0;  // wave 0, lane < G: the key word of record `lane`
+      const bool kneed = wave == 0 && lane < G;
       {
         long long spins = 0;
         for (;;) {
@@ -356,6 +338,10 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
               v[i] = xch_load(base + (size_t)(f >> 6) * kRecWords + (f & 63));
               got = got && (uint32_t)(v[i] >> 32) == tag;
             }
+          }
+          if (kneed) {
+            kk = xch_load(base + (size_t)lane * kRecWords + kMaxNb);
+            got = got && (uint32_t)(kk >> 48) == tag;
           }
           if (__all(got)) break;
           __builtin_amdgcn_s_sleep(1);
@@ -375,10 +361,6 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
         if ((f >> 6) < G) recv[f >> 6][f & 63] = __uint_as_float((uint32_t)v[i]);
       }
       if (wave == 0) {
-        uint64_t kk = 0;
-        if (ok)
-          ok = poll_tagged(base + (size_t)(lane < G ? lane : 0) * kRecWords + kMaxNb, lane < G,
-                           tag, 48, kk, abortp);
         const uint64_t kv = (lane < G) ? (kk & 0xFFFFFFFFFFFFull) : 0ull;
         const uint64_t wk = wave_max_u64(kv);
         const unsigned long long bal = __ballot(lane < G && kv == wk);
