@@ -24,6 +24,10 @@ sample of the same workload -- factor and solve of one randsvd system of
 order 6144 -- scaled to n = 8192 by the cost orders of its parts (n^3 for the
 factorisation, n^2 per Arnoldi step for the solve).
 
+Other configurations (precision triple, order, kappa, m, k) are selected by
+flags; --prolate16k adds the outcome of the ill-conditioned Toeplitz system of
+order 16384 at both of its precision triples.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -60,10 +64,19 @@ def parse():
     ap.add_argument("--m", type=int, default=30)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--uf", default="fp16", choices=("fp16", "bf16", "fp32"))
+    ap.add_argument("--u", default="fp32", choices=("fp32", "fp64"))
+    ap.add_argument("--ur", default="fp64", choices=("fp64", "dd"))
+    ap.add_argument("--tau", type=float, default=None,
+                    help="GMRES tolerance (default 1e-4 for u = fp32, 1e-8 for u = fp64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--outcomes", default="1e6,1e10",
                     help="kappa values whose outcome is reported ('' for none)")
+    ap.add_argument("--prolate16k", action="store_true",
+                    help="also report the outcome of the ill-conditioned Toeplitz system "
+                         "(prolate w = 0.48, n = 16384, m = 50, k = 20 and 0) at "
+                         "(bf16, fp32, fp64) and (fp32, fp64, double-double); about 2 minutes")
     ap.add_argument("--cpu-n", type=int, default=6144, help="order of the oracle sample")
     ap.add_argument("--gen", choices=("gpu", "cpu"), default="gpu",
                     help="draw the system on the GPU (torch) or on the CPU (numpy, slower)")
@@ -164,7 +177,8 @@ def main():
     torch.cuda.synchronize()
     log(f"generated randsvd(n={args.n}, kappa={args.kappa:g}, seed={args.seed}) on the "
         f"{args.gen.upper()} in {time.time() - t0:.1f} s")
-    opts = dict(uf="fp16", u="fp32", ur="fp64", m=args.m, tau=1e-4, imax=10,
+    tau = args.tau if args.tau is not None else (1e-4 if args.u == "fp32" else 1e-8)
+    opts = dict(uf=args.uf, u=args.u, ur=args.ur, m=args.m, tau=tau, imax=10,
                 berr_target=1e-14)
 
     def one_step(k, a_, b_, stats=None, mask=0):
@@ -224,7 +238,9 @@ def main():
     # roofline of the dominant class, from its launches in the timed steps
     r = kstats[dom]
     achieved = r["work"] / (r["total_ms"] * 1e-3) / 1e9
-    traffic = traffic_for(dom, r["launches"] / args.steps)
+    # the counter summary was taken on the default workload only
+    default_workload = (args.uf, args.u, args.ur, args.n) == ("fp16", "fp32", "fp64", 8192)
+    traffic = traffic_for(dom, r["launches"] / args.steps) if default_workload else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                 "launches": r["launches"], "avg_us": r["total_ms"] / r["launches"] * 1e3,
@@ -251,6 +267,37 @@ def main():
                 f"berr={i2['berr'][-1]:.2e} in {el:.2f} s")
         del a2, xt2, b2
 
+    prolate = []
+    if args.prolate16k:
+        from synthetic import prolate_problem_torch
+        n3 = 16384
+        a3, xt3, b3 = prolate_problem_torch(n3, 0.48, args.seed, dev)
+        for uf, u, ur, tau in (("bf16", "fp32", "fp64", 1e-4), ("fp32", "fp64", "dd", 1e-8)):
+            for kk in (20, 0):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                h3 = g.factor(a3, uf=uf, u=u, ur=ur, m=50, k=kk, tau=tau, imax=10,
+                              berr_target=1e-14)
+                rec = {"n": n3, "w": 0.48, "uf": uf, "u": u, "ur": ur, "m": 50, "k": kk,
+                       "tau": tau}
+                if h3.status in (0, 3):
+                    x3, i3 = h3.solve(b3)
+                    torch.cuda.synchronize()
+                    fe = float(torch.max(torch.abs(x3 - xt3)) / torch.max(torch.abs(xt3)))
+                    rec.update(status=i3["status_name"], steps=i3["steps"], its=i3["its"],
+                               berr=i3["berr"][-1], ferr=fe,
+                               t_factor_ms=i3["t_factor_s"] * 1e3,
+                               t_solve_ms=i3["t_solve_s"] * 1e3)
+                else:
+                    rec.update(status=f"factor status {h3.status}")
+                rec["seconds"] = time.perf_counter() - t
+                h3.free()
+                prolate.append(rec)
+                log(f"prolate n={n3} ({uf},{u},{ur}) k={kk}: {rec['status']} "
+                    f"its={rec.get('its')} berr={rec.get('berr', float('nan')):.2e} "
+                    f"in {rec['seconds']:.1f} s")
+        del a3, xt3, b3
+
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()
@@ -268,11 +315,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp16-lu/fp32-krylov/fp64-residual",
+        "dtype": f"{args.uf}-lu/{args.u}-krylov/{args.ur}-residual",
         "data": "synthetic",
         "config": {
             "workload": f"randsvd mode 3, n={args.n}, kappa2={args.kappa:g}, seed={args.seed}; "
-                        f"(uf,u,ur)=(fp16,fp32,fp64); RGMRES-IR m={args.m} k={args.k} tau=1e-4",
+                        f"(uf,u,ur)=({args.uf},{args.u},{args.ur}); RGMRES-IR m={args.m} "
+                        f"k={args.k} tau={tau:g}",
             "n": args.n,
             "kappa2": args.kappa,
             "status": info["status"],
@@ -285,6 +333,7 @@ def main():
             "plain": plain,
             "recycled_over_plain": (value / plain["solves_per_s"]) if plain and plain["solves_per_s"] else None,
             "outcomes": outcomes,
+            "outcomes_prolate16k": prolate or None,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -389,18 +389,21 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
       const int c = J * kTB + lane;
       long long spins = 0;
       for (;;) {
+        // every load is issued before any is checked (one memory round trip;
+        // slots beyond nr repeat the last one)
+        uint64_t lo[NR], hi[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const uint64_t* p = xw + (int64_t)min(r, nr - 1) * xstride + 2 * c;
+          lo[r] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          hi[r] = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         bool got = true;
         double v[NR];
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          v[r] = 0.0;
-          if (r < nr) {
-            const uint64_t* p = xw + (int64_t)r * xstride + 2 * c;
-            const uint64_t lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t hi = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            got = got && (uint32_t)(lo >> 32) == epoch && (uint32_t)(hi >> 32) == epoch;
-            v[r] = __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
-          }
+          got = got && (uint32_t)(lo[r] >> 32) == epoch && (uint32_t)(hi[r] >> 32) == epoch;
+          v[r] = __longlong_as_double((long long)((hi[r] << 32) | (lo[r] & 0xFFFFFFFFull)));
         }
         if (__all(got)) {
 #pragma unroll

@@ -167,3 +167,26 @@ def randsvd_problem_torch(n: int, kappa: float, seed: int, device="cuda"):
     x = torch.rand(n, generator=gen, dtype=torch.float64, device=device) * 2.0 - 1.0
     b = a @ x
     return a.contiguous(), x, b
+
+
+def prolate_problem_torch(n: int, w: float, seed: int, device="cuda"):
+    """Prolate system assembled on ``device``: the Toeplitz matrix of
+    :func:`prolate` (first column computed in numpy, entries gathered by
+    |i - j| in row blocks), x_true ~ N(0, 1) from the numpy generator seeded
+    with ``seed`` (the same x_true as :func:`prolate_problem`), b = A x_true in
+    float64 on the device.  Returns float64 tensors (a, x_true, b)."""
+    import torch
+    k = np.arange(n, dtype=np.float64)
+    col = np.empty(n)
+    col[0] = 2.0 * w
+    col[1:] = np.sin(2.0 * np.pi * w * k[1:]) / (np.pi * k[1:])
+    colt = torch.from_numpy(col).to(device)
+    a = torch.empty((n, n), dtype=torch.float64, device=device)
+    j = torch.arange(n, device=device)
+    step = 1024
+    for r0 in range(0, n, step):
+        i = torch.arange(r0, min(n, r0 + step), device=device)
+        a[r0:r0 + i.numel()] = colt[torch.abs(i[:, None] - j[None, :])]
+    x = torch.from_numpy(normal_vector(n, generator(seed))).to(device)
+    b = a @ x
+    return a, x, b
