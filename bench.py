@@ -71,6 +71,8 @@ def parse():
                     help="GMRES tolerance (default 1e-4 for u = fp32, 1e-8 for u = fp64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip timing the gradient (forward solve + adjoint solve + rank-1)")
     ap.add_argument("--outcomes", default="1e6,1e10",
                     help="kappa values whose outcome is reported ('' for none)")
     ap.add_argument("--prolate16k", action="store_true",
@@ -249,6 +251,38 @@ def main():
     log(f"dominant kernel class {dom}: {r['launches']} launches, avg "
         f"{r['total_ms'] / r['launches'] * 1e3:.1f} us, {achieved:.1f} GB/s")
 
+    # the differentiated solve: forward solve, the adjoint A^T lambda = x - y
+    # with its own recycle space, dL/dA = -lambda x^T (L = 0.5 ||x - y||^2)
+    adjoint = None
+    if not args.no_adjoint and args.u == "fp32" and args.ur == "fp64":
+        gy = torch.Generator(device=dev)
+        gy.manual_seed(args.seed + 7)
+        yv = torch.randn(args.n, generator=gy, dtype=torch.float64, device=dev)
+        da = torch.empty((args.n, args.n), dtype=torch.float64, device=dev)
+
+        def adj_step():
+            h = g.factor(a, k=args.k, **opts)
+            x1, i1 = h.solve(b)
+            lam, i2 = h.solve_transposed(x1 - yv)
+            g.rank1(-1.0, lam, x1, out=da)
+            h.free()
+            return i1, i2
+
+        adj_step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            i1, i2 = adj_step()
+        torch.cuda.synchronize()
+        dta = (time.perf_counter() - t) / args.steps
+        adjoint = {"ms_per_step": dta * 1e3, "forward_status": i1["status_name"],
+                   "forward_its": i1["its"], "adjoint_status": i2["status_name"],
+                   "adjoint_its": i2["its"], "adjoint_berr": i2["berr"][-1],
+                   "adjoint_solve_ms": i2["t_solve_s"] * 1e3}
+        log(f"gradient (factor + solve + adjoint solve + rank-1): {dta * 1e3:.2f} ms/step, "
+            f"adjoint {i2['status_name']} its={i2['its']} berr={i2['berr'][-1]:.2e}")
+        del da
+
     outcomes = []
     for ks in [s for s in args.outcomes.split(",") if s.strip()]:
         kap = float(ks)
@@ -334,6 +368,7 @@ def main():
             "recycled_over_plain": (value / plain["solves_per_s"]) if plain and plain["solves_per_s"] else None,
             "outcomes": outcomes,
             "outcomes_prolate16k": prolate or None,
+            "gradient": adjoint,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

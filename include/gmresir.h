@@ -154,6 +154,33 @@ int gmresir_factor(const double* A, int64_t n, int64_t lda,
 int gmresir_solve(gmresir_ctx* h, const double* b, double* x, int64_t nrhs,
                   int64_t ldb, void* stream, gmresir_info* info);
 
+/*
+ * gmresir_solve_transposed -- the adjoint system A^T lambda = g by the same
+ * refinement with the transposed factors (A^T = 2^-e U^T L^T P):
+ * lambda0 = M^-T g with M^-T = 2^e P^T L^-T U^-T, residual g - A^T lambda in
+ * fp64, GCRO-DR(m, k) on M^-T A_u^T with the product in u^2 = fp64, and a
+ * recycle space of its own, separate from gmresir_solve's (kept across calls
+ * when opts.keep_recycle = 1).  The backward error uses ||A^T||_inf = ||A||_1
+ * (computed on the first call).  Used for the gradient of a loss through
+ * x = A^-1 b: with g = dL/dx, dL/db = lambda and dL/dA = -lambda x^T.
+ *
+ * Arguments, layout, ownership and return values as for gmresir_solve (g in
+ * place of b, lambda in place of x).  Supported for u = FP32, ur = FP64; EINVAL
+ * for other precision triples.
+ */
+int gmresir_solve_transposed(gmresir_ctx* h, const double* g, double* lambda,
+                             int64_t nrhs, int64_t ldb, void* stream,
+                             gmresir_info* info);
+
+/*
+ * gmresir_rank1 -- out = alpha x y^T: x, y device pointers of n float64
+ * values, out a device pointer to n x n float64, row-major, leading dimension
+ * ldo >= n (overwritten).  Forms the matrix gradient -lambda x^T of the
+ * adjoint.  Blocks on stream; EINVAL on null pointers or ldo < n.
+ */
+int gmresir_rank1(double alpha, const double* x, const double* y, int64_t n,
+                  double* out, int64_t ldo, void* stream);
+
 /* Release every resource of the handle.  NULL is accepted.  The handle must
  * not be used afterwards. */
 void gmresir_free(gmresir_ctx* h);
@@ -190,9 +217,11 @@ int gmresir_export_factors(gmresir_ctx* h, void* lu, int32_t* ipiv, int32_t* e);
 /*
  * gmresir_apply -- one preconditioned product of the solve phase, for
  * inspection: op = 0: y = M^-1 v = 2^e U^-1 L^-1 P v; op = 1:
- * y = A-tilde v = M^-1 A_u v.  Both are computed in u^2 and returned
- * unrounded (float64; the high part for double-double).  v and y are device
- * pointers of n float64 values (v must hold u values for op = 1).
+ * y = A-tilde v = M^-1 A_u v; op = 2: y = M^-T v = 2^e P^T L^-T U^-T v;
+ * op = 3: y = M^-T A_u^T v (the adjoint's operator; ops 2 and 3 for u = FP32,
+ * ur = FP64 only).  All are computed in u^2 and returned rounded to fp64
+ * (float64).  v and y are device pointers of n float64 values (v must hold u
+ * values for ops 1 and 3).
  */
 int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y,
                   void* stream);

@@ -42,6 +42,7 @@ from .krylov import KrylovOptions, RecycleState, gcrodr
 from .lu import fp16_scale_exponent, lu_blocked, lu_chop, unpack
 
 __all__ = ["Options", "Factors", "Info", "factor", "solve", "gmresir",
+           "minv_t", "atilde_t", "residual_t", "solve_transposed", "gradient",
            "STATUS_OK", "STATUS_SINGULAR", "STATUS_RANGE", "STATUS_NOCONV"]
 
 STATUS_OK = 0
@@ -232,8 +233,9 @@ def residual(f: Factors, b: np.ndarray, x: np.ndarray) -> np.ndarray:
     return rh + rl
 
 
-def backward_error(f: Factors, b, x, r) -> float:
-    den = f.norm_a_inf * float(np.max(np.abs(x))) + float(np.max(np.abs(b)))
+def backward_error(f: Factors, b, x, r, norm_a: float | None = None) -> float:
+    na = f.norm_a_inf if norm_a is None else norm_a
+    den = na * float(np.max(np.abs(x))) + float(np.max(np.abs(b)))
     num = float(np.max(np.abs(r)))
     if num == 0.0:
         return 0.0
@@ -244,9 +246,69 @@ def backward_error(f: Factors, b, x, r) -> float:
 # Algorithm 3
 # ---------------------------------------------------------------------------
 
+# ---------------------------------------------------------------------------
+# the adjoint system A^T lambda = g with the same factors:
+# P 2^e A = L U gives A^T = 2^-e U^T L^T P, so M^-T = 2^e P^T L^-T U^-T
+# ---------------------------------------------------------------------------
+
+def minv_t(f: Factors, v: np.ndarray) -> np.ndarray:
+    """M^-T v = 2^e P^T L^-T U^-T v in fp64 ((P^T z)[perm[i]] = z[i])."""
+    y = sla.solve_triangular(f.U, v, lower=False, trans="T", check_finite=False)
+    z = sla.solve_triangular(f.L, y, lower=True, unit_diagonal=True, trans="T",
+                             check_finite=False)
+    out = np.empty_like(z)
+    out[f.perm] = z
+    return np.ldexp(out, f.e)
+
+
+def atilde_t(f: Factors, v: np.ndarray) -> np.ndarray:
+    """fl_u(M^-T A_u^T v) with the arithmetic in u^2 = fp64 (u = fp32)."""
+    return fl(minv_t(f, f.au.T @ v), f.opts.u)
+
+
+def atilde64_t(f: Factors, y: np.ndarray) -> np.ndarray:
+    out = np.zeros_like(y)
+    for c in range(y.shape[1]):
+        out[:, c] = minv_t(f, f.au.T @ y[:, c])
+    return out
+
+
+def residual_t(f: Factors, g: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """g - A^T lambda in fp64."""
+    return g - f.a.T @ lam
+
+
+def solve_transposed(f: Factors, g: np.ndarray, state: RecycleState | None = None):
+    """The refinement loop of Algorithm 3 applied to A^T lambda = g with the
+    transposed factors (u = fp32, u_r = fp64); ||A^T||_inf = ||A||_1.
+    Returns (lambda, Info)."""
+    o = f.opts
+    if o.u != "fp32" or o.ur != "fp64" or o.mode != "build":
+        raise ValueError("the adjoint solve is defined for u = fp32, u_r = fp64, build mode")
+    norm_a1 = float(np.max(np.sum(np.abs(f.a), axis=0)))
+    return _refine(f, g, state, None,
+                   lambda v: minv_t(f, v), lambda v: atilde_t(f, v),
+                   lambda y: atilde64_t(f, y), lambda bb, x: residual_t(f, bb, x), norm_a1)
+
+
+def gradient(f: Factors, x: np.ndarray, gx: np.ndarray, state: RecycleState | None = None):
+    """Gradient of a loss through x = A^-1 b: with g = dL/dx the adjoint
+    lambda = A^-T g gives dL/db = lambda and dL/dA = -lambda x^T.
+    Returns (dA, db, Info of the adjoint solve)."""
+    lam, info = solve_transposed(f, gx, state)
+    return -np.outer(lam, x), lam, info
+
+
 def solve(f: Factors, b: np.ndarray, state: RecycleState | None = None,
           x0: np.ndarray | None = None):
     """Refinement loop of Algorithm 3 (k = 0: Algorithm 2).  Returns (x, Info)."""
+    wide = fp.square_precision(f.opts.u)
+    return _refine(f, b, state, x0,
+                   lambda v: minv_hi(f, v, wide), lambda v: atilde(f, v),
+                   lambda y: atilde64(f, y), lambda bb, x: residual(f, bb, x), None)
+
+
+def _refine(f: Factors, b: np.ndarray, state, x0, minv, apply_u, apply64, resid, norm_a):
     o = f.opts
     info = Info()
     if f.status != STATUS_OK:
@@ -258,7 +320,6 @@ def solve(f: Factors, b: np.ndarray, state: RecycleState | None = None,
         return np.zeros(f.n), info
     if state is None or not o.keep_recycle:
         state = RecycleState()
-    wide = fp.square_precision(o.u)
     if x0 is not None:
         x = np.array(x0, dtype=np.float64)
     elif o.mode == "paper":
@@ -272,12 +333,12 @@ def solve(f: Factors, b: np.ndarray, state: RecycleState | None = None,
             x[i] = fl((y[i] - fl(f.U[i, i + 1:] @ x[i + 1:], o.uf)) / f.U[i, i], o.uf)
         x = fl(np.ldexp(x, f.e), o.u)
     else:
-        x = minv_hi(f, b, wide)
+        x = minv(b)
     kopts = KrylovOptions(m=o.m, k=o.k, tau=o.tau, maxit=o.maxit, u=o.u,
                           ortho=o.ortho)
     for i in range(o.imax + 1):
-        r = residual(f, b, x)
-        eta = backward_error(f, b, x, r)
+        r = resid(b, x)
+        eta = backward_error(f, b, x, r, norm_a)
         info.berr.append(eta)
         if eta <= o.berr_target:
             info.steps = i
@@ -287,9 +348,8 @@ def solve(f: Factors, b: np.ndarray, state: RecycleState | None = None,
             break
         s = float(np.max(np.abs(r)))
         rhat = fl(r / s, o.u)
-        z = fl(minv_hi(f, rhat, wide), o.u)
-        d, rec = gcrodr(lambda v: atilde(f, v), lambda y: atilde64(f, y), z,
-                        kopts, state, info.resid_log)
+        z = fl(minv(rhat), o.u)
+        d, rec = gcrodr(apply_u, apply64, z, kopts, state, info.resid_log)
         info.its.append(rec.its)
         info.cycles.append(rec.cycles)
         if o.mode == "paper":

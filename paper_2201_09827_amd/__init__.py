@@ -26,6 +26,7 @@ __all__ = [
     "Handle",
     "EXPORTED",
     "KERNEL_CLASSES",
+    "rank1",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +44,7 @@ EXPORTED = (
     "gmresir_default_opts", "gmresir_factor", "gmresir_solve", "gmresir_free",
     "gmresir_strerror", "gmresir_last_error", "gmresir_import_factors",
     "gmresir_export_factors", "gmresir_apply", "gmresir_kernel_stats", "gmresir_query",
+    "gmresir_solve_transposed", "gmresir_rank1",
 )
 
 
@@ -135,6 +137,10 @@ def load_library() -> ctypes.CDLL:
     lib.gmresir_kernel_stats.restype = ctypes.c_int
     lib.gmresir_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.gmresir_query.restype = ctypes.c_int
+    lib.gmresir_solve_transposed.argtypes = [vp, vp, vp, i64, i64, vp, ctypes.POINTER(Info)]
+    lib.gmresir_solve_transposed.restype = ctypes.c_int
+    lib.gmresir_rank1.argtypes = [ctypes.c_double, vp, vp, i64, vp, i64, vp]
+    lib.gmresir_rank1.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -214,6 +220,14 @@ class Handle:
         via the transpose of a C-contiguous (nrhs, n) tensor).  Returns
         (x, info) with info describing the last column; raises on a negative
         status, reports ENOCONV/ESINGULAR/ERANGE in info['status']."""
+        return self._solve(self._lib.gmresir_solve, b, stream)
+
+    def solve_transposed(self, g, stream=None):
+        """Solve the adjoint system A^T lambda = g with the transposed factors
+        and a recycle space of its own (same conventions as ``solve``)."""
+        return self._solve(self._lib.gmresir_solve_transposed, g, stream)
+
+    def _solve(self, fn, b, stream):
         import torch
         ptr = self._live()
         if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64):
@@ -230,15 +244,15 @@ class Handle:
             nrhs, ldb = b.shape[1], self.n
             x = torch.empty((nrhs, self.n), dtype=torch.float64, device=b.device).t()
         info = Info()
-        rc = self._lib.gmresir_solve(ptr, ctypes.c_void_p(b.data_ptr()),
-                                     ctypes.c_void_p(x.data_ptr()), nrhs, ldb, _stream(stream),
-                                     ctypes.byref(info))
+        rc = fn(ptr, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), nrhs, ldb,
+                _stream(stream), ctypes.byref(info))
         if rc < 0:
             raise _err(self._lib, rc)
         return x, _info_dict(info)
 
     def apply(self, op: int, v, stream=None):
-        """op 0: M^-1 v; op 1: A-tilde v (both in u^2, unrounded fp64)."""
+        """op 0: M^-1 v; op 1: A-tilde v; op 2: M^-T v; op 3: M^-T A_u^T v
+        (all in u^2, returned in fp64)."""
         import torch
         ptr = self._live()
         if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64
@@ -337,3 +351,24 @@ def import_factors(a, lu, ipiv, e: int, stream=None, **opts) -> Handle:
     if rc < 0:
         raise _err(lib, rc)
     return Handle(lib, out, a.shape[0], o, rc)
+
+
+def rank1(alpha: float, x, y, out=None, stream=None):
+    """out = alpha x y^T for float64 CUDA vectors x, y of length n (out: a new or
+    given row-major n x n float64 CUDA tensor)."""
+    import torch
+    lib = load_library()
+    n = x.shape[0]
+    for v in (x, y):
+        if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.float64
+                and v.shape == (n,) and v.is_contiguous()):
+            raise ValueError("x and y must be contiguous float64 CUDA vectors of one length")
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device=x.device)
+    _check_matrix(out)
+    rc = lib.gmresir_rank1(float(alpha), ctypes.c_void_p(x.data_ptr()),
+                           ctypes.c_void_p(y.data_ptr()), n, ctypes.c_void_p(out.data_ptr()),
+                           out.stride(0), _stream(stream))
+    if rc != 0:
+        raise _err(lib, rc)
+    return out

@@ -174,4 +174,30 @@ void launch_trsv_dd(const void* S, int64_t ld, const int* permS, int store, int 
                     double* yl, double scale, double* out64, uint64_t* xw, int epoch,
                     const CycleState* gate, int step, int* abortp, hipStream_t s);
 
+// ---- transposed system (adjoint) --------------------------------------------
+
+// t_j = sum_i A[i][j] v_i (A row-major, fp64 when a64 else fp32; v fp64 when
+// v64 else fp32), fp64 accumulation in row chunks of 128 (partial: ceil(n/128)
+// x n doubles); with b: t = b - A^T x (x = v) and norms[0] = max|t|,
+// norms[1] = max|x| (norms zeroed here)
+void launch_colsum(const void* A, int a64, int64_t ld, int n, const void* v, int v64,
+                   double* partial, const double* b, const double* x, double* t,
+                   unsigned long long* norms, const CycleState* gate, int step, hipStream_t s);
+// out[0] = max_j sum_i |A[i][j]| (= ||A||_1, as bits; out[1] cleared); t
+// receives the column sums
+void launch_colsum_abs(const double* A, int64_t ld, int n, double* partial, double* t,
+                       unsigned long long* out, hipStream_t s);
+// U^T y = in (upperT = false) or L^T z = in (upperT = true) with the stored
+// factor (rows permS of S) and the fp64 inverses of its 128 x 128 diagonal
+// blocks (transposed on use); y (may be null) receives the solution,
+// out64 / out32 (either may be null) scale * solution scattered through
+// permOut (null: identity); xw / epoch as for launch_trsv_lower
+void launch_trsv_t(const void* S, int64_t ld, const int* permS, int store, int n, bool upperT,
+                   const double* in, const double* Dinv, double* y, double scale,
+                   const int* permOut, double* out64, float* out32, uint64_t* xw, int epoch,
+                   const CycleState* gate, int step, int* abortp, hipStream_t s);
+// out = alpha x y^T (n x n row-major, leading dimension ld)
+void launch_rank1(double alpha, const double* x, const double* y, int n, int64_t ld, double* out,
+                  hipStream_t s);
+
 }  // namespace gir

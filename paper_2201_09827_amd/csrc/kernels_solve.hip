@@ -849,6 +849,204 @@ __global__ void k_copy_f32_f64(const float* __restrict__ a, double* __restrict__
   if (i < n) b[i] = (double)a[i];
 }
 
+// ---------------------------------------------------------------------------
+// Products with the transpose of a row-major matrix (the adjoint system
+// A^T lambda = g): t_j = sum_i A[i][j] v_i.  Pass 1: workgroup (bx, by) sums
+// rows [by R, (by + 1) R) for 256 consecutive columns (each row segment is
+// one coalesced read), fp64 accumulation, partial sums by chunk; pass 2 adds
+// the chunks in order (deterministic) and, for the residual, forms b - t and
+// the infinity norms.
+// ---------------------------------------------------------------------------
+constexpr int kColRows = 128;  // rows per chunk
+
+template <typename AT, typename VT>
+__global__ __launch_bounds__(256) void k_colsum_partial(const AT* __restrict__ A, int64_t ld,
+                                                        int n, const VT* __restrict__ v,
+                                                        double* __restrict__ partial,
+                                                        const CycleState* gate, int step) {
+  if (gated_off(gate, step)) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int i0 = blockIdx.y * kColRows;
+  const int i1 = min(n, i0 + kColRows);
+  if (j >= n) return;
+  const AT* a = A + (int64_t)i0 * ld + j;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int i = i0;
+  for (; i + 4 <= i1; i += 4, a += 4 * ld) {
+    acc0 = fma((double)a[0], (double)v[i], acc0);
+    acc1 = fma((double)a[ld], (double)v[i + 1], acc1);
+    acc2 = fma((double)a[2 * ld], (double)v[i + 2], acc2);
+    acc3 = fma((double)a[3 * ld], (double)v[i + 3], acc3);
+  }
+  for (; i < i1; ++i, a += ld) acc0 = fma((double)a[0], (double)v[i], acc0);
+  partial[(int64_t)blockIdx.y * n + j] = (acc0 + acc1) + (acc2 + acc3);
+}
+
+// column sums of |A| (fp64, row-major) by chunks, as k_colsum_partial
+__global__ __launch_bounds__(256) void k_colsum_abs_partial(const double* __restrict__ A,
+                                                            int64_t ld, int n,
+                                                            double* __restrict__ partial) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int i0 = blockIdx.y * kColRows;
+  const int i1 = min(n, i0 + kColRows);
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int i = i0; i < i1; ++i) acc += fabs(A[(int64_t)i * ld + j]);
+  partial[(int64_t)blockIdx.y * n + j] = acc;
+}
+
+// t = sum of the chunks; with b: t = b - sum, norms[0] = max|t|, norms[1] =
+// max|x| (x: the vector the product was taken with)
+__global__ __launch_bounds__(256) void k_colsum_finish(const double* __restrict__ partial,
+                                                       int nchunks, int n,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ t,
+                                                       unsigned long long* norms,
+                                                       const CycleState* gate, int step) {
+  if (gated_off(gate, step)) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  double s = 0.0;
+  if (j < n)
+    for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * n + j];
+  double ra = 0.0, xa = 0.0;
+  if (j < n) {
+    const double v = b ? b[j] - s : s;
+    t[j] = v;
+    ra = fabs(v);
+    xa = x ? fabs(x[j]) : 0.0;
+  }
+  if (norms) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      ra = fmax(ra, __shfl_xor(ra, o, kWave));
+      xa = fmax(xa, __shfl_xor(xa, o, kWave));
+    }
+    if ((threadIdx.x % kWave) == 0) {
+      atomic_max_nonneg(norms + 0, ra);
+      atomic_max_nonneg(norms + 1, xa);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked solves with the transposed factors (the adjoint preconditioner
+// M^-T = 2^e P^T L^-T U^-T):
+//   U^T y = w  (lower triangular): y_I = (U_II^-1)^T (w_I - sum_{J<I} U_JI^T y_J)
+//   L^T z = y  (unit upper):       z_I = (L_II^-1)^T (y_I - sum_{J>I} L_JI^T z_J)
+// Same scheme as k_trsv (128-row blocks of the transposed system, 8 waves,
+// wave-strided 64-column tiles, epoch-tagged partial solutions), but a tile
+// row of the transposed factor is a column of the stored one: lane c of a
+// wave reads S[row j][c] for the 64 logical rows j of the tile (each read
+// coalesced across the wave).  The result of the L^T solve is scattered
+// through P^T: out[permOut[i]] = scale * z_i.
+// ---------------------------------------------------------------------------
+template <class F, bool kUpperT>
+__global__ __launch_bounds__(kTSThreads) void k_trsv_t(
+    const typename F::T* __restrict__ S, int64_t ld, const int* __restrict__ permS, int n,
+    const double* __restrict__ in, const double* __restrict__ Dinv, double* __restrict__ y,
+    double scale, const int* __restrict__ permOut, double* __restrict__ out64,
+    float* __restrict__ out32, uint64_t* xw, uint32_t epoch, const CycleState* gate, int step,
+    int* abortp) {
+  if (gated_off(gate, step)) return;
+  __shared__ double red[8][kTB];
+  __shared__ double ysh[8][kTB];
+  __shared__ double zsh[kTS];
+  __shared__ double part[4][kTS];
+  __shared__ int wok[8];
+  using T = typename F::T;
+  const int nb = (n + kTS - 1) / kTS;
+  const int nt = (n + kTB - 1) / kTB;
+  const int blk = kUpperT ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int r0 = blk * kTS;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int half = wave >> 2;
+  const int wq = wave & 3;
+  const int col = r0 + half * kTB + lane;  // this thread's row of the transposed system
+  // this thread's quarter of its row of (D^-1)^T, i.e. of column di of D^-1
+  const int di = tid % kTS;
+  const int dq4 = tid / kTS;
+  double dq[kTS / 4];
+  {
+    const double* dcol = Dinv + (int64_t)blk * kTS * kTS + (int64_t)(dq4 * (kTS / 4)) * kTS + di;
+#pragma unroll
+    for (int c = 0; c < kTS / 4; ++c) dq[c] = dcol[(int64_t)c * kTS];
+  }
+  double rhs = 0.0;
+  if (tid < kTS && r0 + tid < n) rhs = in[r0 + tid];
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  bool ok = true;
+  const int t0 = kUpperT ? 2 * blk + 2 : 0;
+  const int t1 = kUpperT ? nt : 2 * blk;
+  for (int i = wq;; i += 4) {
+    const int J = kUpperT ? t1 - 1 - i : t0 + i;
+    if (kUpperT ? (J < t0) : (J >= t1)) break;
+    // the 64 physical rows of tile J, then one column read per row
+    const int jr = J * kTB + lane;
+    const int pr = (jr < n) ? (permS ? permS[jr] : jr) : 0;
+    float tv[kTB];
+#pragma unroll
+    for (int jj = 0; jj < kTB; ++jj) {
+      const int prj = __builtin_amdgcn_readlane(pr, jj);
+      tv[jj] = (col < n) ? (float)F::to_f(S[(int64_t)prj * ld + col]) : 0.0f;
+    }
+    double yv;
+    if (!get_tagged64(xw, J * kTB, epoch, yv, abortp)) {
+      ok = false;
+      break;
+    }
+    ysh[wave][lane] = yv;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < kTB; c += 4) {
+      acc0 = fma((double)tv[c], ysh[wave][c], acc0);
+      acc1 = fma((double)tv[c + 1], ysh[wave][c + 1], acc1);
+      acc2 = fma((double)tv[c + 2], ysh[wave][c + 2], acc2);
+      acc3 = fma((double)tv[c + 3], ysh[wave][c + 3], acc3);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  red[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
+  if (lane == 0) wok[wave] = ok ? 1 : 0;
+  __syncthreads();
+  int allok = 1;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) allok &= wok[w];
+  if (!allok) return;
+  if (tid < kTS) {
+    const int h = tid / kTB, l = tid % kTB;
+    const double sum = (red[4 * h][l] + red[4 * h + 1][l]) + (red[4 * h + 2][l] + red[4 * h + 3][l]);
+    zsh[tid] = (r0 + tid < n) ? rhs - sum : 0.0;
+  }
+  __syncthreads();
+  double p = 0.0;
+#pragma unroll
+  for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[dq4 * (kTS / 4) + c], p);
+  part[dq4][di] = p;
+  __syncthreads();
+  if (tid >= kTS) return;
+  const int rr = r0 + tid;
+  const double v = (rr < n) ? (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]) : 0.0;
+  if (rr < n) {
+    if (y) y[rr] = v;
+    const int o = permOut ? permOut[rr] : rr;
+    if (out64) out64[o] = v * scale;
+    if (out32) out32[o] = (float)(v * scale);
+  }
+  put_tagged(xw, rr, v, epoch);
+}
+
+// out = alpha x y^T (n x n, row-major, leading dimension ld)
+__global__ __launch_bounds__(256) void k_rank1(double alpha, const double* __restrict__ x,
+                                               const double* __restrict__ yv, int n, int64_t ld,
+                                               double* __restrict__ out) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j < n) out[(int64_t)i * ld + j] = alpha * x[i] * yv[j];
+}
+
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -1056,6 +1254,61 @@ void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t 
 
 void launch_copy_f32_to_f64(const float* a, double* b, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_f32_f64, dim3(nblocks(n, 256)), dim3(256), 0, s, a, b, n);
+}
+
+void launch_colsum(const void* A, int a64, int64_t ld, int n, const void* v, int v64,
+                   double* partial, const double* b, const double* x, double* t,
+                   unsigned long long* norms, const CycleState* gate, int step, hipStream_t s) {
+  const int nchunks = (n + kColRows - 1) / kColRows;
+  const dim3 g1(nblocks(n, 256), (unsigned)nchunks);
+#define GIR_CS(AT, VT)                                                                       \
+  hipLaunchKernelGGL((k_colsum_partial<AT, VT>), g1, dim3(256), 0, s,                         \
+                     static_cast<const AT*>(A), ld, n, static_cast<const VT*>(v), partial, gate, \
+                     step)
+  if (a64) {
+    if (v64) GIR_CS(double, double); else GIR_CS(double, float);
+  } else {
+    if (v64) GIR_CS(float, double); else GIR_CS(float, float);
+  }
+#undef GIR_CS
+  if (norms) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, norms, 2);
+  hipLaunchKernelGGL(k_colsum_finish, dim3(nblocks(n, 256)), dim3(256), 0, s, partial, nchunks, n,
+                     b, x, t, norms, gate, step);
+}
+
+void launch_colsum_abs(const double* A, int64_t ld, int n, double* partial, double* t,
+                       unsigned long long* out, hipStream_t s) {
+  const int nchunks = (n + kColRows - 1) / kColRows;
+  hipLaunchKernelGGL(k_colsum_abs_partial, dim3(nblocks(n, 256), (unsigned)nchunks), dim3(256), 0,
+                     s, A, ld, n, partial);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out, 2);
+  hipLaunchKernelGGL(k_colsum_finish, dim3(nblocks(n, 256)), dim3(256), 0, s, partial, nchunks, n,
+                     nullptr, nullptr, t, out, nullptr, 0);
+}
+
+void launch_trsv_t(const void* S, int64_t ld, const int* permS, int store, int n, bool upperT,
+                   const double* in, const double* Dinv, double* y, double scale,
+                   const int* permOut, double* out64, float* out32, uint64_t* xw, int epoch,
+                   const CycleState* gate, int step, int* abortp, hipStream_t s) {
+  const unsigned grid = nblocks(n, kTS);
+#define GIR_TT(F, U)                                                                        \
+  hipLaunchKernelGGL((k_trsv_t<F, U>), dim3(grid), dim3(kTSThreads), 0, s,                  \
+                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, Dinv, y,   \
+                     scale, permOut, out64, out32, xw, (uint32_t)epoch, gate, step, abortp)
+  if (store == kStoreF16) {
+    if (upperT) GIR_TT(Fp16, true); else GIR_TT(Fp16, false);
+  } else if (store == kStoreBF16) {
+    if (upperT) GIR_TT(Bf16, true); else GIR_TT(Bf16, false);
+  } else {
+    if (upperT) GIR_TT(Fp32, true); else GIR_TT(Fp32, false);
+  }
+#undef GIR_TT
+}
+
+void launch_rank1(double alpha, const double* x, const double* y, int n, int64_t ld, double* out,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_rank1, dim3(nblocks(n, 256), (unsigned)n), dim3(256), 0, s, alpha, x, y,
+                     n, ld, out);
 }
 
 }  // namespace gir

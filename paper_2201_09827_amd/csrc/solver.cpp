@@ -159,7 +159,9 @@ struct gmresir_ctx {
   int singular_col = 0;
   int e = 0;
   double scale = 1.0;
-  double norm_a = 0.0;
+  double norm_a = 0.0;   // ||A||_inf
+  double norm_a1 = -1.0;  // ||A||_1 = ||A^T||_inf (computed on first use)
+  int trans = 0;          // the current solve is the adjoint one (A^T lambda = g)
   double t_factor = 0.0;
   int m = 0, k = 0;
   int u64 = 0;    // working precision fp64: vectors in fp64, A-tilde in double-double
@@ -190,6 +192,11 @@ struct gmresir_ctx {
   double *tl = nullptr, *yl = nullptr;  // low parts of the double-double products (u64)
   double *C = nullptr, *U = nullptr, *Cn = nullptr, *Un = nullptr;
   int kc_keep = 0;  // columns of U carried to the next correction solve
+  // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
+  // it runs) and the partial sums of the products with A^T
+  double *Ct = nullptr, *Ut = nullptr;
+  int kc_keep_t = 0;
+  double* colpart = nullptr;
   double *Hd = nullptr, *Bd = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *coefA = nullptr, *coefB = nullptr,
          *Mdev = nullptr, *Gdev = nullptr, *partial = nullptr;
@@ -648,9 +655,32 @@ int next_epoch(gmresir_ctx* h) {
 // fp64 for u = fp32, double-double for u = fp64 (inl: low parts of in, or
 // null).  The result goes to out64 (fp64) or outu (rounded to u), either may
 // be null.
+// M^-T in = 2^e P^T L^-T U^-T in in fp64 (the adjoint system; u = fp32):
+// the solve with U^T, then with L^T, scattered through P^T
+int precond_t(gmresir_ctx* h, const double* in, double* out64, void* outu,
+              const gir::CycleState* gate, int step) {
+  const int n = (int)h->n;
+  const double bytes = 0.5 * (double)n * (double)(n + 1) * (double)store_bytes(h->store) +
+                       24.0 * (double)n;
+  const int eL = next_epoch(h);
+  GIR_TRY(timed(h, kKcTrsvL, bytes, h->stream, gate, step, [&] {
+    gir::launch_trsv_t(h->S, h->ld, h->permS, h->store, n, false, in, h->Uinv, h->y64, 1.0,
+                       nullptr, nullptr, nullptr, h->xwL, eL, gate, step, &h->st->abort,
+                       h->stream);
+  }));
+  const int eU = next_epoch(h);
+  GIR_TRY(timed(h, kKcTrsvU, bytes, h->stream, gate, step, [&] {
+    gir::launch_trsv_t(h->S, h->ld, h->permS, h->store, n, true, h->y64, h->Linv, nullptr,
+                       h->scale, h->permP, out64, static_cast<float*>(outu), h->xwU, eU, gate,
+                       step, &h->st->abort, h->stream);
+  }));
+  return 0;
+}
+
 int precond(gmresir_ctx* h, const double* in, const double* inl, const int* permIn, double* out64,
             void* outu, const gir::CycleState* gate, int step) {
   const int n = (int)h->n;
+  if (h->trans) return precond_t(h, in, out64, outu, gate, step);
   // the stored triangle and the vectors read and written
   const double tri = 0.5 * (double)n * (double)(n + 1) * (double)store_bytes(h->store);
   if (h->u64) {
@@ -689,6 +719,15 @@ int precond(gmresir_ctx* h, const double* in, const double* inl, const int* perm
 int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, void* outu,
            const gir::CycleState* gate, int step) {
   const double nn = (double)h->n;
+  if (h->trans) {
+    // A_u^T v (column sums in fp64), then M^-T
+    GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + 12.0 * nn, h->stream, gate, step, [&] {
+      gir::launch_colsum(h->Au, 0, h->ld, (int)h->n, vu ? vu : static_cast<const void*>(v64),
+                         vu ? 0 : 1, h->colpart, nullptr, nullptr, h->t64, nullptr, gate, step,
+                         h->stream);
+    }));
+    return precond_t(h, h->t64, out64, outu, gate, step);
+  }
   if (h->u64) {
     const double* v = vu ? static_cast<const double*>(vu) : v64;
     GIR_TRY(timed(h, kKcGemv, 8.0 * nn * nn + 24.0 * nn, h->stream, gate, step, [&] {
@@ -712,7 +751,7 @@ int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, voi
 int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
   const int n = (int)h->n;
   const int64_t ld = h->ld;
-  if (h->u64) {
+  if (h->u64 || h->trans) {
     for (int c = 0; c < kk; ++c)
       GIR_TRY(atilde(h, nullptr, Y + (size_t)c * ld, C + (size_t)c * ld, nullptr, nullptr, 0));
     return 0;
@@ -1101,7 +1140,10 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   for (;; ++i) {
     GIR_TRY(timed(h, kKcResid, 8.0 * (double)n * (double)n + 24.0 * (double)n, s, nullptr, 0,
                   [&] {
-                    if (h->rdd)
+                    if (h->trans)
+                      gir::launch_colsum(h->A64, 1, h->ld, n, h->x, 1, h->colpart, h->b, h->x,
+                                         h->r64, h->norms, nullptr, 0, s);
+                    else if (h->rdd)
                       gir::launch_residual_dd(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s);
                     else
                       gir::launch_residual(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s);
@@ -1112,7 +1154,7 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     double rmax, xmax;
     std::memcpy(&rmax, &nb[0], 8);
     std::memcpy(&xmax, &nb[1], 8);
-    const double den = h->norm_a * xmax + bmax;
+    const double den = (h->trans ? h->norm_a1 : h->norm_a) * xmax + bmax;
     const double eta = (rmax == 0.0) ? 0.0 : (den > 0.0 ? rmax / den : INFINITY);
     if (i <= GMRESIR_MAX_STEPS) inf.berr[i] = eta;
     if (!std::isfinite(eta)) {
@@ -1142,6 +1184,38 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   inf.t_solve_s = now_s() - t0;
   if (info) *info = inf;
   return status;
+}
+
+// The adjoint system A^T lambda = g: buffers on first use (partial sums of
+// the products with A^T, the adjoint recycle space), ||A||_1 from the column
+// sums of |A| (one product with A^T on a vector of ones would not do: the
+// entries' signs matter).
+int adjoint_setup(gmresir_ctx* h) {
+  const size_t ld = (size_t)h->ld;
+  const int n = (int)h->n;
+  if (!h->colpart) {
+    const size_t nchunks = ((size_t)n + 127) / 128;
+    GIR_TRY(dalloc(h->arena, &h->colpart, nchunks * (size_t)n));
+  }
+  if (h->k > 0 && !h->Ut) {
+    GIR_TRY(dalloc(h->arena, &h->Ut, ld * h->k));
+    GIR_TRY(dalloc(h->arena, &h->Ct, ld * h->k));
+  }
+  if (h->norm_a1 < 0.0) {
+    gir::launch_colsum_abs(h->A64, h->ld, n, h->colpart, h->t64, h->norms + 2, h->stream);
+    GIR_HIP(hipGetLastError());
+    unsigned long long bits = 0;
+    GIR_TRY(download(h, &bits, h->norms + 2, 8));
+    std::memcpy(&h->norm_a1, &bits, 8);
+  }
+  return 0;
+}
+
+// swaps the forward and the adjoint recycle spaces
+void swap_recycle(gmresir_ctx* h) {
+  std::swap(h->C, h->Ct);
+  std::swap(h->U, h->Ut);
+  std::swap(h->kc_keep, h->kc_keep_t);
 }
 
 }  // namespace
@@ -1269,6 +1343,51 @@ int gmresir_solve(gmresir_ctx* h, const double* b, double* x, int64_t nrhs, int6
   return rc;
 }
 
+int gmresir_solve_transposed(gmresir_ctx* h, const double* g, double* lambda, int64_t nrhs,
+                             int64_t ldb, void* stream, gmresir_info* info) {
+  if (!h || !g || !lambda || nrhs < 1 || ldb < h->n) {
+    set_error("invalid solve arguments");
+    return GMRESIR_EINVAL;
+  }
+  if (h->u64 || h->rdd) {
+    set_error("the adjoint solve supports u = FP32, ur = FP64");
+    return GMRESIR_EINVAL;
+  }
+  if (stream) h->stream = reinterpret_cast<hipStream_t>(stream);
+  if (h->status == GMRESIR_ESINGULAR || h->status == GMRESIR_ERANGE) {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = h->status;
+      info->singular_col = h->singular_col;
+    }
+    return h->status;
+  }
+  GIR_TRY(adjoint_setup(h));
+  swap_recycle(h);
+  h->trans = 1;
+  int rc = 0;
+  for (int64_t j = 0; j < nrhs; ++j) {
+    rc = solve_one(h, g + j * ldb, lambda + j * ldb, info);
+    if (rc < 0) break;
+  }
+  h->trans = 0;
+  swap_recycle(h);
+  return rc;
+}
+
+int gmresir_rank1(double alpha, const double* x, const double* y, int64_t n, double* out,
+                  int64_t ldo, void* stream) {
+  if (!x || !y || !out || n <= 0 || ldo < n || n > (1 << 30)) {
+    set_error("invalid rank-1 arguments");
+    return GMRESIR_EINVAL;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  gir::launch_rank1(alpha, x, y, (int)n, ldo, out, s);
+  GIR_HIP(hipGetLastError());
+  GIR_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
 void gmresir_free(gmresir_ctx* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
@@ -1320,19 +1439,27 @@ int gmresir_export_factors(gmresir_ctx* h, void* lu, int32_t* ipiv, int32_t* e) 
 }
 
 int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y, void* stream) {
-  if (!h || !v || !y || (op != 0 && op != 1)) {
+  if (!h || !v || !y || op < 0 || op > 3) {
     set_error("invalid apply arguments");
+    return GMRESIR_EINVAL;
+  }
+  if (op >= 2 && (h->u64 || h->rdd)) {
+    set_error("the adjoint products support u = FP32, ur = FP64");
     return GMRESIR_EINVAL;
   }
   if (h->status == GMRESIR_ERANGE) return GMRESIR_ERANGE;
   if (stream) h->stream = reinterpret_cast<hipStream_t>(stream);
   const int n = (int)h->n;
   GIR_HIP(hipMemcpyAsync(h->r64, v, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-  if (op == 0) {
-    GIR_TRY(precond(h, h->r64, nullptr, h->permP, h->x, nullptr, nullptr, 0));
-  } else {
-    GIR_TRY(atilde(h, nullptr, h->r64, h->x, nullptr, nullptr, 0));
-  }
+  if (op >= 2) GIR_TRY(adjoint_setup(h));
+  h->trans = op >= 2 ? 1 : 0;
+  int rc = 0;
+  if (op == 0 || op == 2)
+    rc = precond(h, h->r64, nullptr, h->permP, h->x, nullptr, nullptr, 0);
+  else
+    rc = atilde(h, nullptr, h->r64, h->x, nullptr, nullptr, 0);
+  h->trans = 0;
+  GIR_TRY(rc);
   GIR_HIP(hipGetLastError());
   GIR_HIP(hipMemcpyAsync(y, h->x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
   GIR_HIP(hipStreamSynchronize(h->stream));

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "gmresir.h")
 
 def _declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(gmresir_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(gmresir_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declarations_match_binding_list():
