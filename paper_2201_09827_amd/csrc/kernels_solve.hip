@@ -983,15 +983,17 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
   for (int i = wq;; i += 4) {
     const int J = kUpperT ? t1 - 1 - i : t0 + i;
     if (kUpperT ? (J < t0) : (J >= t1)) break;
-    // the 64 physical rows of tile J, then one column read per row
+    // the 64 physical rows of tile J, then one column read per row: all
+    // loads are issued unconditionally (a column beyond the padded row reads
+    // the last one; its results are discarded) and converted only after the
+    // wait for the published values, so they overlap one another and the wait
     const int jr = J * kTB + lane;
     const int pr = (jr < n) ? (permS ? permS[jr] : jr) : 0;
-    float tv[kTB];
+    const T* scol = S + min(col, (int)ld - 1);
+    T tv[kTB];
 #pragma unroll
-    for (int jj = 0; jj < kTB; ++jj) {
-      const int prj = __builtin_amdgcn_readlane(pr, jj);
-      tv[jj] = (col < n) ? (float)F::to_f(S[(int64_t)prj * ld + col]) : 0.0f;
-    }
+    for (int jj = 0; jj < kTB; ++jj)
+      tv[jj] = scol[(int64_t)__builtin_amdgcn_readlane(pr, jj) * ld];
     double yv;
     if (!get_tagged64(xw, J * kTB, epoch, yv, abortp)) {
       ok = false;
@@ -1001,10 +1003,10 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int c = 0; c < kTB; c += 4) {
-      acc0 = fma((double)tv[c], ysh[wave][c], acc0);
-      acc1 = fma((double)tv[c + 1], ysh[wave][c + 1], acc1);
-      acc2 = fma((double)tv[c + 2], ysh[wave][c + 2], acc2);
-      acc3 = fma((double)tv[c + 3], ysh[wave][c + 3], acc3);
+      acc0 = fma((double)F::to_f(tv[c]), ysh[wave][c], acc0);
+      acc1 = fma((double)F::to_f(tv[c + 1]), ysh[wave][c + 1], acc1);
+      acc2 = fma((double)F::to_f(tv[c + 2]), ysh[wave][c + 2], acc2);
+      acc3 = fma((double)F::to_f(tv[c + 3]), ysh[wave][c + 3], acc3);
     }
     __builtin_amdgcn_wave_barrier();
   }
