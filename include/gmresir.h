@@ -181,6 +181,30 @@ int gmresir_solve_transposed(gmresir_ctx* h, const double* g, double* lambda,
 int gmresir_rank1(double alpha, const double* x, const double* y, int64_t n,
                   double* out, int64_t ldo, void* stream);
 
+/*
+ * gmresir_choose_k -- automatic recycle dimension, "finding the knee"
+ * (Section 3, the discussion of the total iterations against k): solves
+ * A x = b once for every k = 0 .. kmax, without carrying a recycle space
+ * between the solves, and sets *k_best to the smallest k with the fewest
+ * total Arnoldi steps among the solves that reach the backward-error target.
+ * k is limited to (Arnoldi steps of the first refinement step at k = 0) - 1,
+ * as the first step runs without recycling and k harmonic Ritz vectors need
+ * at least k + 1 Arnoldi steps.
+ *
+ *   h      handle; kmax <= the k it was created with (its buffers).
+ *   b      device pointer, n float64.
+ *   k_best host pointer, receives the chosen k.
+ *   its    host pointer to kmax + 1 int32 or NULL: total Arnoldi steps per k,
+ *          -1 where the solve did not converge or k was beyond the limit.
+ *   stream hipStream_t or NULL.
+ *
+ * Returns 0, ENOCONV (no k converged; *k_best = 0), ESINGULAR / ERANGE as
+ * gmresir_solve, or a negative error.  The handle's k and recycle state are
+ * left as they were.
+ */
+int gmresir_choose_k(gmresir_ctx* h, const double* b, int32_t kmax,
+                     int32_t* k_best, int32_t* its, void* stream);
+
 /* Release every resource of the handle.  NULL is accepted.  The handle must
  * not be used afterwards. */
 void gmresir_free(gmresir_ctx* h);

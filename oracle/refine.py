@@ -42,7 +42,7 @@ from .krylov import KrylovOptions, RecycleState, gcrodr
 from .lu import fp16_scale_exponent, lu_blocked, lu_chop, unpack
 
 __all__ = ["Options", "Factors", "Info", "factor", "solve", "gmresir",
-           "minv_t", "atilde_t", "residual_t", "solve_transposed", "gradient",
+           "minv_t", "atilde_t", "residual_t", "solve_transposed", "gradient", "choose_k",
            "STATUS_OK", "STATUS_SINGULAR", "STATUS_RANGE", "STATUS_NOCONV"]
 
 STATUS_OK = 0
@@ -366,3 +366,30 @@ def gmresir(a: np.ndarray, b: np.ndarray, opts: Options):
     f = factor(a, opts)
     x, info = solve(f, b)
     return x, info, f
+
+
+def choose_k(f: Factors, b: np.ndarray, kmax: int):
+    """Automatic recycle dimension, "finding the knee" (Section 3, total
+    iterations against k): one solve per k = 0 .. kmax with the same factors
+    and no recycle space carried between them; the chosen k is the smallest
+    with the fewest total Arnoldi steps among the converged solves, limited to
+    k <= (Arnoldi steps of the first refinement step at k = 0) - 1.
+    Returns (k_best, its per k with -1 for not converged / beyond the limit)."""
+    import dataclasses
+    its = []
+    best, best_its = 0, None
+    limit = kmax
+    for k in range(kmax + 1):
+        if k > limit:
+            its.append(-1)
+            continue
+        fk = dataclasses.replace(f, opts=dataclasses.replace(f.opts, k=k, keep_recycle=False))
+        _, info = solve(fk, b)
+        total = info.total_its if info.status == STATUS_OK else -1
+        its.append(total)
+        if k == 0:
+            limit = max(0, info.its[0] - 1) if info.steps > 0 else 0
+        if total >= 0 and (best_its is None or total < best_its):
+            best, best_its = k, total
+    return best, its
+

@@ -44,7 +44,7 @@ EXPORTED = (
     "gmresir_default_opts", "gmresir_factor", "gmresir_solve", "gmresir_free",
     "gmresir_strerror", "gmresir_last_error", "gmresir_import_factors",
     "gmresir_export_factors", "gmresir_apply", "gmresir_kernel_stats", "gmresir_query",
-    "gmresir_solve_transposed", "gmresir_rank1",
+    "gmresir_solve_transposed", "gmresir_rank1", "gmresir_choose_k",
 )
 
 
@@ -141,6 +141,8 @@ def load_library() -> ctypes.CDLL:
     lib.gmresir_solve_transposed.restype = ctypes.c_int
     lib.gmresir_rank1.argtypes = [ctypes.c_double, vp, vp, i64, vp, i64, vp]
     lib.gmresir_rank1.restype = ctypes.c_int
+    lib.gmresir_choose_k.argtypes = [vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
+    lib.gmresir_choose_k.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -226,6 +228,23 @@ class Handle:
         """Solve the adjoint system A^T lambda = g with the transposed factors
         and a recycle space of its own (same conventions as ``solve``)."""
         return self._solve(self._lib.gmresir_solve_transposed, g, stream)
+
+    def choose_k(self, b, kmax: int, stream=None):
+        """Automatic recycle dimension ("finding the knee"): one solve per
+        k = 0 .. kmax; returns (k_best, its per k (-1: not converged or beyond
+        the first-step limit), status)."""
+        import torch
+        ptr = self._live()
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64
+                and b.shape == (self.n,) and b.is_contiguous()):
+            raise ValueError("b must be a contiguous float64 CUDA vector of length n")
+        kb = ctypes.c_int32(0)
+        its = (ctypes.c_int32 * (kmax + 1))()
+        rc = self._lib.gmresir_choose_k(ptr, ctypes.c_void_p(b.data_ptr()), int(kmax),
+                                        ctypes.byref(kb), its, _stream(stream))
+        if rc < 0:
+            raise _err(self._lib, rc)
+        return int(kb.value), [int(v) for v in its], int(rc)
 
     def _solve(self, fn, b, stream):
         import torch

@@ -1375,6 +1375,45 @@ int gmresir_solve_transposed(gmresir_ctx* h, const double* g, double* lambda, in
   return rc;
 }
 
+int gmresir_choose_k(gmresir_ctx* h, const double* b, int32_t kmax, int32_t* k_best,
+                     int32_t* its, void* stream) {
+  if (!h || !b || !k_best || kmax < 0 || kmax > h->k) {
+    set_error("invalid arguments (need 0 <= kmax <= the handle's k)");
+    return GMRESIR_EINVAL;
+  }
+  if (stream) h->stream = reinterpret_cast<hipStream_t>(stream);
+  const int k_saved = h->k, keep_saved = h->o.keep_recycle, kc_saved = h->kc_keep;
+  h->o.keep_recycle = 0;
+  int best = 0, best_its = -1, limit = kmax, rc = 0, first_status = 0;
+  for (int k = 0; k <= kmax && k <= limit; ++k) {
+    h->k = k;
+    h->kc_keep = 0;
+    gmresir_info inf{};
+    rc = solve_one(h, b, h->z64, &inf);
+    if (rc < 0) break;
+    const int total = inf.status == GMRESIR_OK ? inf.total_its : -1;
+    if (its) its[k] = total;
+    if (k == 0) {
+      first_status = rc;
+      // k recycled vectors need at least k + 1 Arnoldi steps in the first
+      // refinement step, which runs without recycling
+      limit = inf.steps > 0 ? std::max(0, inf.its[0] - 1) : 0;
+    }
+    if (total >= 0 && (best_its < 0 || total < best_its)) {
+      best_its = total;
+      best = k;
+    }
+  }
+  if (its)
+    for (int k = limit + 1; k <= kmax; ++k) its[k] = -1;
+  h->k = k_saved;
+  h->o.keep_recycle = keep_saved;
+  h->kc_keep = kc_saved;
+  if (rc < 0) return rc;
+  *k_best = best;
+  return best_its < 0 ? (first_status ? first_status : GMRESIR_ENOCONV) : GMRESIR_OK;
+}
+
 int gmresir_rank1(double alpha, const double* x, const double* y, int64_t n, double* out,
                   int64_t ldo, void* stream) {
   if (!x || !y || !out || n <= 0 || ldo < n || n > (1 << 30)) {

@@ -168,3 +168,33 @@ def test_gradient_dense_reference_n1024(lib):
     kappa = np.linalg.cond(p.a, np.inf)
     log(f"[grad] n=1024 rel err dA {ea:.2e} db {eb:.2e} (kappa_inf {kappa:.1e})")
     assert ea <= 10 * kappa * n * U64 and eb <= 10 * kappa * n * U64
+
+
+# moderately conditioned systems: at kappa ~ 1e5 the counts of a sweep
+# change by tens of steps with the summation order of the CPU's own BLAS
+@pytest.mark.parametrize("n,kappa,seed,m,kmax", [(100, 1e4, 3, 20, 8), (300, 1e4, 4, 10, 6),
+                                                 (256, 1e4, 1, 8, 6)])
+def test_choose_k_shared_factors(lib, n, kappa, seed, m, kmax):
+    """Automatic k on the oracle's factors: the iteration count of every k
+    within +-2 of the oracle's, the same limit, and a chosen k whose count is
+    within 2 of the oracle's minimum (the same k when the oracle's minimum is
+    unique by more than 4 steps)."""
+    p = randsvd_problem(n, kappa, seed)
+    o = oracle_options(m=m, k=kmax)
+    f = refine.factor(p.a, o)
+    kb_ref, its_ref = refine.choose_k(f, p.b, kmax)
+    log(f"[choose-k] n={n} oracle k={kb_ref} its={its_ref}")
+    h = _import(lib, p, f, o)
+    kb, its, status = h.choose_k(_dev(p.b), kmax)
+    h.free()
+    log(f"[choose-k] n={n} gpu    k={kb} its={its} status={status}")
+    assert status == 0
+    for a, b in zip(its, its_ref):
+        assert (a < 0) == (b < 0)
+        assert a < 0 or abs(a - b) <= 2
+    best = min(t for t in its_ref if t >= 0)
+    assert its[kb] == min(t for t in its if t >= 0)
+    assert its_ref[kb] >= 0 and its_ref[kb] - best <= 2
+    others = [t for k, t in enumerate(its_ref) if t >= 0 and k != kb_ref]
+    if not others or min(others) > best + 4:
+        assert kb == kb_ref

@@ -116,3 +116,25 @@ def test_transposed_solve_rejects_other_triples():
     f = factor(p.a, _opts(uf="fp32", u="fp64", ur="dd"))
     with pytest.raises(ValueError):
         refine.solve_transposed(f, p.b)
+
+
+def test_choose_k_matches_brute_force_runs():
+    """The sweep's iteration counts are those of independent runs with each
+    k (the factorisation does not depend on k), and the chosen k is the
+    smallest one attaining the minimum below the first-step limit."""
+    from oracle import gmresir
+    p = randsvd_problem(100, 1e4, 3)
+    o = _opts(m=20, k=8)
+    f = factor(p.a, o)
+    kb, its = refine.choose_k(f, p.b, 8)
+    x0, info0, _ = gmresir(p.a, p.b, _opts(m=20, k=0))
+    limit = info0.its[0] - 1
+    for k in range(9):
+        if k > limit:
+            assert its[k] == -1
+            continue
+        _, info, _ = gmresir(p.a, p.b, _opts(m=20, k=k))
+        assert its[k] == (info.total_its if info.status == refine.STATUS_OK else -1)
+    valid = [(t, k) for k, t in enumerate(its) if t >= 0]
+    assert kb == min(valid)[1]
+    assert kb <= limit
