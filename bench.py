@@ -237,6 +237,30 @@ def main():
                  "berr": ip["berr"][-1]}
         log(f"plain k=0: {dtp / args.steps * 1e3:.2f} ms/step its={ip['its']}")
 
+    # the reuse variant: the recycled pair of the previous refinement step is
+    # kept instead of recomputing QR(A-tilde U_k) (same matrix)
+    reuse = None
+    if not args.no_plain and args.k > 0:
+        opts_reuse = dict(opts, reuse_recycle=1)
+
+        def reuse_step():
+            h = g.factor(a, k=args.k, **opts_reuse)
+            x1, i1 = h.solve(b)
+            h.free()
+            return i1
+
+        reuse_step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            ir = reuse_step()
+        torch.cuda.synchronize()
+        dtr = (time.perf_counter() - t) / args.steps
+        reuse = {"ms_per_step": dtr * 1e3, "status": ir["status_name"], "its": ir["its"],
+                 "berr": ir["berr"][-1], "t_solve_ms": ir["t_solve_s"] * 1e3}
+        log(f"recycled k={args.k}, recycled pair reused: {dtr * 1e3:.2f} ms/step its={ir['its']} "
+            f"solve={ir['t_solve_s'] * 1e3:.2f} ms")
+
     # roofline of the dominant class, from its launches in the timed steps
     r = kstats[dom]
     achieved = r["work"] / (r["total_ms"] * 1e-3) / 1e9
@@ -369,6 +393,7 @@ def main():
             "outcomes": outcomes,
             "outcomes_prolate16k": prolate or None,
             "gradient": adjoint,
+            "reuse_recycle": reuse,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

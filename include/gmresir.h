@@ -85,7 +85,13 @@ typedef struct {
   int32_t timing;         /* bit c set: bracket every launch of kernel class c
                              (the order listed at gmresir_kernel_stats) with
                              HIP events on the stream it runs on; 0: off     */
-  int32_t reserved[3];    /* must be zero                                    */
+  int32_t matvec_u;       /* 1: the correction solve applies M^-1 and A-tilde in
+                             u instead of u^2 (SGMRES-IR / RSGMRES-IR, Section 3;
+                             u = FP64 only); x0 keeps u^2.  Default 0.          */
+  int32_t reuse_recycle;  /* 1: keep C_k and U_k of the previous correction solve
+                             (same A: A-tilde U_k = C_k still holds) instead of
+                             recomputing QR(A-tilde U_k).  Default 0.           */
+  int32_t reserved[1];    /* must be zero                                    */
 } gmresir_opts;
 
 /* Per-solve record, filled by gmresir_solve (host struct). */

@@ -67,6 +67,7 @@ class KrylovOptions:
     maxit: int = 0          # 0 -> 10 * m
     u: str = "fp32"         # storage precision of Krylov vectors and d, r
     ortho: str = "cgs2"     # "cgs2" or "mgs"
+    reuse: bool = False     # keep (U_k, C_k) of the previous solve (same A) as they are
 
     def cap(self) -> int:
         return self.maxit if self.maxit > 0 else 10 * self.m
@@ -75,8 +76,11 @@ class KrylovOptions:
 @dataclass
 class RecycleState:
     """U_k carried between correction solves (Ytilde_k = U_k, Alg. GCRO-DR
-    last line)."""
+    last line), and C_k with it: at the end of every cycle A-tilde U_k = C_k
+    with C_k orthonormal, so for an unchanged matrix the pair can be kept
+    instead of recomputing QR(A-tilde U_k) (the reuse variant)."""
     U: np.ndarray | None = None
+    C: np.ndarray | None = None
 
     @property
     def dim(self) -> int:
@@ -310,11 +314,14 @@ def gcrodr(apply_u, apply64, z, opts: KrylovOptions, state: RecycleState,
 
     # --- a recycled space from the previous system: QR of A-tilde Ytilde
     if k > 0 and state.U is not None and state.U.shape[1] > 0:
-        yt = state.U
-        zq = apply64(yt)
-        q, rr = qr_positive(zq)
-        C = q
-        U = sla.solve_triangular(rr, yt.T, lower=False, trans="T").T  # Yt R^-1
+        if opts.reuse and state.C is not None:
+            C, U = state.C, state.U
+        else:
+            yt = state.U
+            zq = apply64(yt)
+            q, rr = qr_positive(zq)
+            C = q
+            U = sla.solve_triangular(rr, yt.T, lower=False, trans="T").T  # Yt R^-1
         c = C.T @ r
         d = fl(U @ c, u)
         r = fl(r - C @ c, u)
@@ -376,4 +383,5 @@ def gcrodr(apply_u, apply64, z, opts: KrylovOptions, state: RecycleState,
                     U = sla.solve_triangular(rr, ytil.T, lower=False, trans="T").T
     if k > 0:
         state.U = None if U is None else U.copy()
+        state.C = None if C is None else C.copy()
     return d, rec

@@ -69,6 +69,8 @@ class Options:
     ortho: str = "cgs2"
     keep_recycle: bool = False
     mode: str = "build"       # "build" or "paper" (chop-style LU, x in u)
+    matvec: str = "u2"        # "u2": A-tilde v in u^2 (Algorithms 2, 3); "u": uniform u
+    reuse_recycle: bool = False  # keep (U_k, C_k) between refinement steps
 
     def validate(self):
         if self.uf not in ("fp16", "bf16", "fp32", "fp64"):
@@ -83,6 +85,10 @@ class Options:
             raise ValueError("need m > k >= 0")
         if not (self.tau > 0):
             raise ValueError("tau")
+        if self.matvec not in ("u2", "u"):
+            raise ValueError("matvec")
+        if self.matvec == "u" and self.u != "fp64":
+            raise ValueError("uniform-precision products are defined for u = fp64")
 
     def scaled(self) -> bool:
         return (self.uf == "fp16") if self.scale_pow2 is None else bool(self.scale_pow2)
@@ -299,17 +305,34 @@ def gradient(f: Factors, x: np.ndarray, gx: np.ndarray, state: RecycleState | No
     return -np.outer(lam, x), lam, info
 
 
+def atilde_uniform(f: Factors, v: np.ndarray) -> np.ndarray:
+    """A-tilde v with every operation in the working precision u = fp64
+    (SGMRES-IR / RSGMRES-IR: uniform precision within GMRES, Section 3)."""
+    return minv_hi(f, f.au @ v, "fp64")
+
+
 def solve(f: Factors, b: np.ndarray, state: RecycleState | None = None,
           x0: np.ndarray | None = None):
-    """Refinement loop of Algorithm 3 (k = 0: Algorithm 2).  Returns (x, Info)."""
+    """Refinement loop of Algorithm 3 (k = 0: Algorithm 2).  Returns (x, Info).
+    With matvec = "u" the correction solve applies M^-1 (to r-hat and inside
+    GMRES) in u instead of u^2; x0 keeps u^2."""
     wide = fp.square_precision(f.opts.u)
+    if f.opts.matvec == "u":
+        return _refine(f, b, state, x0,
+                       lambda v: minv_hi(f, v, wide), lambda v: atilde_uniform(f, v),
+                       lambda y: np.column_stack([atilde_uniform(f, y[:, c])
+                                                  for c in range(y.shape[1])]),
+                       lambda bb, x: residual(f, bb, x), None,
+                       minv_z=lambda v: minv_hi(f, v, "fp64"))
     return _refine(f, b, state, x0,
                    lambda v: minv_hi(f, v, wide), lambda v: atilde(f, v),
                    lambda y: atilde64(f, y), lambda bb, x: residual(f, bb, x), None)
 
 
-def _refine(f: Factors, b: np.ndarray, state, x0, minv, apply_u, apply64, resid, norm_a):
+def _refine(f: Factors, b: np.ndarray, state, x0, minv, apply_u, apply64, resid, norm_a,
+            minv_z=None):
     o = f.opts
+    minv_z = minv if minv_z is None else minv_z
     info = Info()
     if f.status != STATUS_OK:
         info.status = f.status
@@ -335,7 +358,7 @@ def _refine(f: Factors, b: np.ndarray, state, x0, minv, apply_u, apply64, resid,
     else:
         x = minv(b)
     kopts = KrylovOptions(m=o.m, k=o.k, tau=o.tau, maxit=o.maxit, u=o.u,
-                          ortho=o.ortho)
+                          ortho=o.ortho, reuse=o.reuse_recycle)
     for i in range(o.imax + 1):
         r = resid(b, x)
         eta = backward_error(f, b, x, r, norm_a)
@@ -348,7 +371,7 @@ def _refine(f: Factors, b: np.ndarray, state, x0, minv, apply_u, apply64, resid,
             break
         s = float(np.max(np.abs(r)))
         rhat = fl(r / s, o.u)
-        z = fl(minv(rhat), o.u)
+        z = fl(minv_z(rhat), o.u)
         d, rec = gcrodr(apply_u, apply64, z, kopts, state, info.resid_log)
         info.its.append(rec.its)
         info.cycles.append(rec.cycles)

@@ -63,7 +63,9 @@ class Opts(ctypes.Structure):
         ("scale_pow2", ctypes.c_int32),
         ("keep_recycle", ctypes.c_int32),
         ("timing", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("matvec_u", ctypes.c_int32),
+        ("reuse_recycle", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -158,7 +160,7 @@ def _opts(**kw) -> Opts:
     for key, val in kw.items():
         if key in ("uf", "u", "ur") and isinstance(val, str):
             val = PREC[val]
-        if key in ("keep_recycle", "scale_pow2", "timing"):
+        if key in ("keep_recycle", "scale_pow2", "timing", "matvec_u", "reuse_recycle"):
             val = int(val)
         if not hasattr(o, key):
             raise TypeError(f"unknown option {key!r}")

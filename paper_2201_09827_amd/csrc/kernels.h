@@ -65,6 +65,9 @@ void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* 
 void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const float* v32,
                     const double* v64, double* t, const CycleState* gate, int step,
                     hipStream_t s);
+// t[i] = sum_c A[permA[i]][c] v[c] with fp64 A and v, fp64 accumulation
+void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const double* v,
+                     double* t, const CycleState* gate, int step, hipStream_t s);
 // r = b - A x (fp64); norms[0] = max|r| bits, norms[1] = max|x| bits (zeroed here)
 void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
                      double* r, unsigned long long* norms, hipStream_t s);

@@ -59,6 +59,43 @@ __global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, i
   if (lane == 0) t[row] = s;
 }
 
+// t[i] = sum_c A[permA[i]][c] v[c] with fp64 A and v (the uniform-precision
+// product for u = fp64): one wave per row, double2 loads
+__global__ __launch_bounds__(256) void k_gemv_a64(const double* __restrict__ A, int64_t ld,
+                                                  const int* __restrict__ permA, int n,
+                                                  const double* __restrict__ v,
+                                                  double* __restrict__ t, const CycleState* gate,
+                                                  int step) {
+  if (gated_off(gate, step)) return;
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= n) return;
+  const int prow = permA ? permA[row] : row;
+  const double* a = A + (int64_t)prow * ld;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  const int n2 = n & ~1;
+  int c = lane * 2;
+  for (; c + 128 < n2; c += 256) {
+    const double2 a0 = *reinterpret_cast<const double2*>(a + c);
+    const double2 a1 = *reinterpret_cast<const double2*>(a + c + 128);
+    const double2 x0 = *reinterpret_cast<const double2*>(v + c);
+    const double2 x1 = *reinterpret_cast<const double2*>(v + c + 128);
+    acc0 = fma(a0.x, x0.x, acc0);
+    acc1 = fma(a0.y, x0.y, acc1);
+    acc2 = fma(a1.x, x1.x, acc2);
+    acc3 = fma(a1.y, x1.y, acc3);
+  }
+  for (; c < n2; c += 128) {
+    const double2 a0 = *reinterpret_cast<const double2*>(a + c);
+    const double2 x0 = *reinterpret_cast<const double2*>(v + c);
+    acc0 = fma(a0.x, x0.x, acc0);
+    acc1 = fma(a0.y, x0.y, acc1);
+  }
+  for (int cc = n2 + lane; cc < n; cc += kWave) acc0 = fma(a[cc], v[cc], acc0);
+  const double s = wave_sum((acc0 + acc1) + (acc2 + acc3));
+  if (lane == 0) t[row] = s;
+}
+
 // ---------------------------------------------------------------------------
 // residual r = b - A x (fp64), norms[0] = max |r_i|, norms[1] = max |x_i|
 // ---------------------------------------------------------------------------
@@ -1070,6 +1107,12 @@ void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const 
   else
     hipLaunchKernelGGL(k_gemv_au<double>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, v64, t,
                        gate, step);
+}
+
+void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const double* v,
+                     double* t, const CycleState* gate, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_a64, dim3(nblocks(n, 4)), dim3(256), 0, s, A, ld, permA, n, v, t,
+                     gate, step);
 }
 
 void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,

@@ -165,6 +165,7 @@ struct gmresir_ctx {
   double t_factor = 0.0;
   int m = 0, k = 0;
   int u64 = 0;    // working precision fp64: vectors in fp64, A-tilde in double-double
+  int uni = 0;    // u = fp64 with the correction solve's products in u (uniform)
   int rdd = 0;    // residual in double-double
   size_t ue = 4;  // bytes per element of a vector in u
 
@@ -326,11 +327,18 @@ int validate_opts(const gmresir_opts* o) {
     set_error("timing must be a bit mask of the kernel classes");
     return GMRESIR_EINVAL;
   }
-  for (int i = 0; i < 3; ++i)
-    if (o->reserved[i] != 0) {
-      set_error("reserved fields must be zero");
-      return GMRESIR_EINVAL;
-    }
+  if (o->reserved[0] != 0) {
+    set_error("reserved fields must be zero");
+    return GMRESIR_EINVAL;
+  }
+  if ((o->matvec_u != 0 && o->matvec_u != 1) || (o->reuse_recycle != 0 && o->reuse_recycle != 1)) {
+    set_error("matvec_u and reuse_recycle must be 0 or 1");
+    return GMRESIR_EINVAL;
+  }
+  if (o->matvec_u && o->u != GMRESIR_FP64) {
+    set_error("uniform-precision products (matvec_u) are supported for u = FP64");
+    return GMRESIR_EINVAL;
+  }
   return 0;
 }
 
@@ -432,7 +440,7 @@ int alloc_common(gmresir_ctx* h) {
   GIR_TRY(dalloc(h->arena, reinterpret_cast<char**>(&h->S), n * ld * store_bytes(h->store)));
   GIR_TRY(dalloc(h->arena, &h->perm, n));
   GIR_TRY(dalloc(h->arena, &h->ipiv, n));
-  if (!h->u64) {
+  if (!h->u64 || h->uni) {
     // fp64 inverses of the diagonal blocks (the double-double solves
     // substitute within the block instead)
     const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
@@ -590,7 +598,7 @@ int run_lu(gmresir_ctx* h) {
   int* flag = reinterpret_cast<int*>(h->counter + 2);
   GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
   gir::launch_check_factors(h->S, n, h->ld, h->store, flag, h->stream);
-  if (!h->u64)
+  if (!h->u64 || h->uni)
     gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->dtmp,
                               h->stream);
   gir::CycleState hs{};
@@ -635,6 +643,7 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
   h->k = opts->k;
   h->store = store_of(opts->uf);
   h->u64 = opts->u == GMRESIR_FP64 ? 1 : 0;
+  h->uni = (h->u64 && opts->matvec_u) ? 1 : 0;
   h->rdd = opts->ur == GMRESIR_DD ? 1 : 0;
   h->ue = h->u64 ? 8 : 4;
   h->stream = reinterpret_cast<hipStream_t>(stream);
@@ -678,9 +687,27 @@ int precond_t(gmresir_ctx* h, const double* in, double* out64, void* outu,
 }
 
 int precond(gmresir_ctx* h, const double* in, const double* inl, const int* permIn, double* out64,
-            void* outu, const gir::CycleState* gate, int step) {
+            void* outu, const gir::CycleState* gate, int step, bool correction = false) {
   const int n = (int)h->n;
   if (h->trans) return precond_t(h, in, out64, outu, gate, step);
+  if (h->uni && correction) {
+    // uniform precision: the fp64 solves (u = fp64)
+    const double bytes = 0.5 * (double)n * (double)(n + 1) * (double)store_bytes(h->store) +
+                         24.0 * (double)n;
+    double* out = out64 ? out64 : static_cast<double*>(outu);
+    const int eL = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvL, bytes, h->stream, gate, step, [&] {
+      gir::launch_trsv_lower(h->S, h->ld, h->permS, h->store, n, in, permIn, h->Linv, h->y64,
+                             h->xwL, eL, gate, step, &h->st->abort, h->stream);
+    }));
+    const int eU = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvU, bytes, h->stream, gate, step, [&] {
+      gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->Uinv, h->z64,
+                             h->scale, out, nullptr, h->xwU, eU, gate, step, &h->st->abort,
+                             h->stream);
+    }));
+    return 0;
+  }
   // the stored triangle and the vectors read and written
   const double tri = 0.5 * (double)n * (double)(n + 1) * (double)store_bytes(h->store);
   if (h->u64) {
@@ -727,6 +754,14 @@ int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, voi
                          h->stream);
     }));
     return precond_t(h, h->t64, out64, outu, gate, step);
+  }
+  if (h->uni) {
+    const double* v = vu ? static_cast<const double*>(vu) : v64;
+    GIR_TRY(timed(h, kKcGemv, 8.0 * nn * nn + 24.0 * nn, h->stream, gate, step, [&] {
+      gir::launch_gemv_a64(h->A64, h->ld, h->permP, (int)h->n, v, h->t64, gate, step,
+                           h->stream);
+    }));
+    return precond(h, h->t64, nullptr, nullptr, out64, outu, gate, step, true);
   }
   if (h->u64) {
     const double* v = vu ? static_cast<const double*>(vu) : v64;
@@ -840,6 +875,39 @@ int combine(gmresir_ctx* h, const gir::Basis& X, const std::vector<double>& M, i
   return 0;
 }
 
+// C = QR(A-tilde U) by CholeskyQR2 in fp64, U <- U R^-1 (the recycled space
+// at the start of a correction solve); *ok = false when a Cholesky factor
+// breaks down (the space is then dropped)
+int recompute_recycle(gmresir_ctx* h, int kk, bool* ok) {
+  const int64_t ld = h->ld;
+  GIR_TRY(atilde_block(h, h->U, kk, h->C));
+  GIR_HIP(hipGetLastError());
+  std::vector<double> G1, G2, R1(kk * kk), R2(kk * kk), Ri(kk * kk), Rt(kk * kk);
+  GIR_TRY(gram(h, basis(h, h->C, kk, ld, nullptr, 0, ld), h->C, kk, G1));
+  *ok = gir::la::cholesky_upper(G1.data(), kk, R1.data());
+  if (*ok) {
+    gir::la::inv_upper(R1.data(), kk, Ri.data());
+    GIR_TRY(combine(h, basis(h, h->C, kk, ld, nullptr, 0, ld), Ri, kk, h->Cn));
+    GIR_TRY(gram(h, basis(h, h->Cn, kk, ld, nullptr, 0, ld), h->Cn, kk, G2));
+    *ok = gir::la::cholesky_upper(G2.data(), kk, R2.data());
+  }
+  if (*ok) {
+    gir::la::inv_upper(R2.data(), kk, Ri.data());
+    GIR_TRY(combine(h, basis(h, h->Cn, kk, ld, nullptr, 0, ld), Ri, kk, h->C));
+    // R = R2 R1, U = Y R^-1
+    for (int j = 0; j < kk; ++j)
+      for (int i = 0; i < kk; ++i) {
+        double sum = 0.0;
+        for (int t = 0; t < kk; ++t) sum += R2[(size_t)t * kk + i] * R1[(size_t)j * kk + t];
+        Rt[(size_t)j * kk + i] = sum;
+      }
+    gir::la::inv_upper(Rt.data(), kk, Ri.data());
+    GIR_TRY(combine(h, basis(h, h->U, kk, ld, nullptr, 0, ld), Ri, kk, h->Un));
+    std::swap(h->U, h->Un);
+  }
+  return 0;
+}
+
 struct SolveStats {
   int its = 0;
 };
@@ -869,33 +937,16 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   // recycled space from the previous system: C = QR(A-tilde Y), U = Y R^-1
   if (k > 0 && h->kc_keep > 0) {
     const int kk = h->kc_keep;
-    GIR_TRY(atilde_block(h, h->U, kk, h->C));
-    GIR_HIP(hipGetLastError());
-    // CholeskyQR2 in fp64
-    std::vector<double> G1, G2, R1(kk * kk), R2(kk * kk), Ri(kk * kk), Rt(kk * kk);
     bool ok = true;
-    GIR_TRY(gram(h, basis(h, h->C, kk, ld, nullptr, 0, ld), h->C, kk, G1));
-    ok = gir::la::cholesky_upper(G1.data(), kk, R1.data());
-    if (ok) {
-      gir::la::inv_upper(R1.data(), kk, Ri.data());
-      GIR_TRY(combine(h, basis(h, h->C, kk, ld, nullptr, 0, ld), Ri, kk, h->Cn));
-      GIR_TRY(gram(h, basis(h, h->Cn, kk, ld, nullptr, 0, ld), h->Cn, kk, G2));
-      ok = gir::la::cholesky_upper(G2.data(), kk, R2.data());
+    if (h->o.reuse_recycle) {
+      // the matrix is unchanged: C and U of the previous solve still satisfy
+      // A-tilde U = C with C orthonormal (the reuse variant)
+      kc = kk;
+    } else {
+      GIR_TRY(recompute_recycle(h, kk, &ok));
+      if (ok) kc = kk;
     }
     if (ok) {
-      gir::la::inv_upper(R2.data(), kk, Ri.data());
-      GIR_TRY(combine(h, basis(h, h->Cn, kk, ld, nullptr, 0, ld), Ri, kk, h->C));
-      // R = R2 R1, U = Y R^-1
-      for (int j = 0; j < kk; ++j)
-        for (int i = 0; i < kk; ++i) {
-          double sum = 0.0;
-          for (int t = 0; t < kk; ++t) sum += R2[(size_t)t * kk + i] * R1[(size_t)j * kk + t];
-          Rt[(size_t)j * kk + i] = sum;
-        }
-      gir::la::inv_upper(Rt.data(), kk, Ri.data());
-      GIR_TRY(combine(h, basis(h, h->U, kk, ld, nullptr, 0, ld), Ri, kk, h->Un));
-      std::swap(h->U, h->Un);
-      kc = kk;
       // d = U (C^T r), r = r - C (C^T r)
       std::vector<double> ctr(kc);
       double n2;
@@ -1167,7 +1218,7 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     }
     if (i >= imax) break;
     gir::launch_scale_round(h->r64, rmax, h->t64, n, h->u64, s);  // r-hat = fl_u(r / s)
-    GIR_TRY(precond(h, h->t64, nullptr, h->permP, nullptr, h->zu, nullptr, 0));
+    GIR_TRY(precond(h, h->t64, nullptr, h->permP, nullptr, h->zu, nullptr, 0, true));
     SolveStats ss;
     GIR_TRY(gcrodr(h, ss));
     inf.its[i] = ss.its;
@@ -1312,7 +1363,7 @@ int gmresir_import_factors(const double* A, int64_t n, int64_t lda, const void* 
     if (rc == 0) rc = upload(h, h->ipiv, ipiv, sizeof(int) * n);
     h->permP = h->perm;
     h->permS = nullptr;
-    if (rc == 0 && !h->u64) {
+    if (rc == 0 && (!h->u64 || h->uni)) {
       gir::launch_diag_inverses(h->S, h->ld, nullptr, h->store, (int)n, h->Linv, h->Uinv,
                                 h->dtmp, h->stream);
       if (hipGetLastError() != hipSuccess) rc = GMRESIR_EHIP;

@@ -19,14 +19,15 @@ def log(*args):
 
 
 def oracle_options(uf="fp16", m=20, k=5, tau=1e-4, imax=10, maxit=0, berr=1e-14, u="fp32",
-                   ur="fp64"):
+                   ur="fp64", matvec="u2", reuse=False):
     return Options(uf=uf, u=u, ur=ur, m=m, k=k, tau=tau, imax=imax, maxit=maxit,
-                   berr_target=berr, nb=NB)
+                   berr_target=berr, nb=NB, matvec=matvec, reuse_recycle=reuse)
 
 
 def lib_options(o: Options) -> dict:
     return dict(uf=o.uf, u=o.u, ur=o.ur, m=o.m, k=o.k, tau=o.tau, imax=o.imax,
-                maxit=o.maxit, berr_target=o.berr_target)
+                maxit=o.maxit, berr_target=o.berr_target,
+                matvec_u=1 if o.matvec == "u" else 0, reuse_recycle=int(o.reuse_recycle))
 
 
 def decode_factors(raw: np.ndarray, uf: str) -> np.ndarray:
