@@ -149,6 +149,17 @@ struct KStat {
 
 }  // namespace
 
+// The host part of a recycle-space refresh at the end of a GCRO-DR cycle (the
+// harmonic Ritz problem G^T G z = theta G^T M z, the QR of G P_k) and the
+// data it needs; after the last cycle of a correction solve it is deferred
+// until the space is next needed, so that it overlaps the device work in
+// between (x update, residual, preconditioned right-hand side).
+struct Refresh {
+  bool active = false;
+  int kc = 0, J = 0, rows = 0, cols = 0;
+  std::vector<double> Gm, Mm, dk;  // rows x cols each (column-major); D of U
+};
+
 struct gmresir_ctx {
   Arena arena;  // declared first: destroyed last
   int64_t n = 0, ld = 0;
@@ -193,6 +204,7 @@ struct gmresir_ctx {
   double *tl = nullptr, *yl = nullptr;  // low parts of the double-double products (u64)
   double *C = nullptr, *U = nullptr, *Cn = nullptr, *Un = nullptr;
   int kc_keep = 0;  // columns of U carried to the next correction solve
+  Refresh pend;     // deferred refresh of the last cycle (V, C, U untouched meanwhile)
   // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
   // it runs) and the partial sums of the products with A^T
   double *Ct = nullptr, *Ut = nullptr;
@@ -875,6 +887,67 @@ int combine(gmresir_ctx* h, const gir::Basis& X, const std::vector<double>& M, i
   return 0;
 }
 
+// Harmonic Ritz vectors P_k of the refresh problem, QR of G P_k = Q R, then
+// C <- [C V_{J+1}] Q and U <- [U D, V_J] P_k R^-1 on the device; *kc_new is
+// the new dimension (unchanged when no vector was found)
+int apply_refresh(gmresir_ctx* h, Refresh& rf, int* kc_new) {
+  rf.active = false;
+  const int64_t ld = h->ld;
+  const int rows = rf.rows, cols = rf.cols, kc = rf.kc, J = rf.J, k = h->k;
+  *kc_new = kc;
+  std::vector<double> Pk((size_t)cols * k);
+  const int kn = gir::la::harmonic_ritz(rf.Gm.data(), rf.Mm.data(), rows, cols, k, Pk.data());
+  if (kn <= 0) return 0;
+  std::vector<double> GP((size_t)rows * kn, 0.0), Q((size_t)rows * kn), R((size_t)kn * kn),
+      Ri((size_t)kn * kn), PR((size_t)cols * kn, 0.0);
+  for (int o = 0; o < kn; ++o)
+    for (int i = 0; i < rows; ++i) {
+      double sum = 0.0;
+      for (int c = 0; c < cols; ++c) sum += rf.Gm[(size_t)c * rows + i] * Pk[(size_t)o * cols + c];
+      GP[(size_t)o * rows + i] = sum;
+    }
+  if (!gir::la::qr_thin(GP.data(), rows, rows, kn, Q.data(), R.data())) return 0;
+  gir::la::inv_upper(R.data(), kn, Ri.data());
+  for (int o = 0; o < kn; ++o)
+    for (int c = 0; c < cols; ++c) {
+      double sum = 0.0;
+      for (int t = 0; t < kn; ++t) sum += Pk[(size_t)t * cols + c] * Ri[(size_t)o * kn + t];
+      // U-tilde = U D: fold D into the coefficients of the U columns
+      PR[(size_t)o * cols + c] = (c < kc) ? sum * rf.dk[c] : sum;
+    }
+  GIR_TRY(combine(h, basis(h, h->C, kc, ld, h->V, J + 1, ld), Q, kn, h->Cn));
+  GIR_TRY(combine(h, basis(h, h->U, kc, ld, h->V, J, ld), PR, kn, h->Un));
+  std::swap(h->C, h->Cn);
+  std::swap(h->U, h->Un);
+  *kc_new = kn;
+  return 0;
+}
+
+// after a cycle: the refresh now, or, when the cycle is likely the last of
+// the correction solve, deferred (*kc stays until it is applied)
+int schedule_refresh(gmresir_ctx* h, Refresh& rf, bool likely_last, int* kc) {
+  if (likely_last) {
+    h->pend = std::move(rf);
+    h->pend.active = true;
+    return 0;
+  }
+  return apply_refresh(h, rf, kc);
+}
+
+// the deferred refresh (if any) of the previous correction solve
+int resolve_pending(gmresir_ctx* h, bool keep) {
+  if (!h->pend.active) return 0;
+  if (!keep) {
+    h->pend.active = false;
+    h->kc_keep = 0;
+    return 0;
+  }
+  int kcn = 0;
+  GIR_TRY(apply_refresh(h, h->pend, &kcn));
+  h->kc_keep = h->k > 0 ? kcn : 0;
+  return 0;
+}
+
 // C = QR(A-tilde U) by CholeskyQR2 in fp64, U <- U R^-1 (the recycled space
 // at the start of a correction solve); *ok = false when a Cholesky factor
 // breaks down (the space is then dropped)
@@ -919,6 +992,9 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   const int m = h->m, k = h->k;
   const int cap = h->o.maxit > 0 ? h->o.maxit : 10 * m;
   hipStream_t s = h->stream;
+  // the previous solve's last refresh runs on the host while the device
+  // finishes the preconditioned right-hand side
+  GIR_TRY(resolve_pending(h, true));
   double beta0 = 0.0;
   {
     double n2 = 0.0;
@@ -964,9 +1040,17 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     double n2 = 0.0;
     GIR_TRY(dots_norm(h, basis(h, h->C, kc, ld, nullptr, 0, ld), h->ru, kc ? ctr.data() : nullptr,
                       &n2));
-    const double rn = std::sqrt(n2);
+    double rn = std::sqrt(n2);
     if (rn <= tol) break;
     if (stats.its >= cap) break;
+    if (h->pend.active) {
+      // the estimate said converged but the residual did not: refresh now
+      GIR_TRY(apply_refresh(h, h->pend, &kc));
+      ctr.assign(std::max(kc, 1), 0.0);
+      GIR_TRY(dots_norm(h, basis(h, h->C, kc, ld, nullptr, 0, ld), h->ru,
+                        kc ? ctr.data() : nullptr, &n2));
+      rn = std::sqrt(n2);
+    }
     const int nsteps = std::min(m - kc, cap - stats.its);
     // v1 = r / ||r||; device cycle state and Givens right-hand side
     gir::launch_div_u(h->ru, rn, h->V, h->u64, n, s);
@@ -1056,37 +1140,19 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       GIR_HIP(hipGetLastError());
       if (k > 0 && J > 0) {
         // first-cycle harmonic Ritz: Hbar^T Hbar z = theta H^T z
-        std::vector<double> Gm((size_t)(J + 1) * J), Mm((size_t)(J + 1) * J, 0.0);
+        Refresh rf;
+        rf.kc = 0;
+        rf.J = J;
+        rf.rows = J + 1;
+        rf.cols = J;
+        rf.Gm.assign((size_t)(J + 1) * J, 0.0);
+        rf.Mm.assign((size_t)(J + 1) * J, 0.0);
         for (int c = 0; c < J; ++c) {
-          for (int i = 0; i <= J; ++i) Gm[(size_t)c * (J + 1) + i] = (i <= c + 1) ? Hh[(size_t)c * ldh + i] : 0.0;
-          Mm[(size_t)c * (J + 1) + c] = 1.0;
+          for (int i = 0; i <= J; ++i)
+            rf.Gm[(size_t)c * (J + 1) + i] = (i <= c + 1) ? Hh[(size_t)c * ldh + i] : 0.0;
+          rf.Mm[(size_t)c * (J + 1) + c] = 1.0;
         }
-        std::vector<double> Pk((size_t)J * k);
-        const int kn = gir::la::harmonic_ritz(Gm.data(), Mm.data(), J + 1, J, k, Pk.data());
-        if (kn > 0) {
-          std::vector<double> GP((size_t)(J + 1) * kn, 0.0), Q((size_t)(J + 1) * kn), R((size_t)kn * kn),
-              Ri((size_t)kn * kn), PR((size_t)J * kn, 0.0);
-          for (int o = 0; o < kn; ++o)
-            for (int i = 0; i <= J; ++i) {
-              double sum = 0.0;
-              for (int c = 0; c < J; ++c) sum += Gm[(size_t)c * (J + 1) + i] * Pk[(size_t)o * J + c];
-              GP[(size_t)o * (J + 1) + i] = sum;
-            }
-          if (gir::la::qr_thin(GP.data(), J + 1, J + 1, kn, Q.data(), R.data())) {
-            gir::la::inv_upper(R.data(), kn, Ri.data());
-            for (int o = 0; o < kn; ++o)
-              for (int c = 0; c < J; ++c) {
-                double sum = 0.0;
-                for (int t = 0; t < kn; ++t) sum += Pk[(size_t)t * J + c] * Ri[(size_t)o * kn + t];
-                PR[(size_t)o * J + c] = sum;
-              }
-            GIR_TRY(combine(h, basis(h, nullptr, 0, ld, h->V, J + 1, ld), Q, kn, h->Cn));
-            GIR_TRY(combine(h, basis(h, nullptr, 0, ld, h->V, J, ld), PR, kn, h->Un));
-            std::swap(h->C, h->Cn);
-            std::swap(h->U, h->Un);
-            kc = kn;
-          }
-        }
+        GIR_TRY(schedule_refresh(h, rf, fin.done || stats.its >= cap, &kc));
       }
     } else {
       // D = diag(1 / ||U e_i||)
@@ -1125,38 +1191,21 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
         }
         for (int c = 0; c < kc; ++c)
           for (int i = 0; i < rows; ++i) Mm[(size_t)c * rows + i] = W[(size_t)c * rows + i] * dk[c];
-        std::vector<double> Pk((size_t)cols * k);
-        const int kn = gir::la::harmonic_ritz(Gm.data(), Mm.data(), rows, cols, k, Pk.data());
-        if (kn > 0) {
-          std::vector<double> GP((size_t)rows * kn, 0.0), Q((size_t)rows * kn), R((size_t)kn * kn),
-              Ri((size_t)kn * kn), PR((size_t)cols * kn, 0.0);
-          for (int o = 0; o < kn; ++o)
-            for (int i = 0; i < rows; ++i) {
-              double sum = 0.0;
-              for (int c = 0; c < cols; ++c) sum += Gm[(size_t)c * rows + i] * Pk[(size_t)o * cols + c];
-              GP[(size_t)o * rows + i] = sum;
-            }
-          if (gir::la::qr_thin(GP.data(), rows, rows, kn, Q.data(), R.data())) {
-            gir::la::inv_upper(R.data(), kn, Ri.data());
-            for (int o = 0; o < kn; ++o)
-              for (int c = 0; c < cols; ++c) {
-                double sum = 0.0;
-                for (int t = 0; t < kn; ++t) sum += Pk[(size_t)t * cols + c] * Ri[(size_t)o * kn + t];
-                // U-tilde = U D: fold D into the coefficients of the U columns
-                PR[(size_t)o * cols + c] = (c < kc) ? sum * dk[c] : sum;
-              }
-            GIR_TRY(combine(h, basis(h, h->C, kc, ld, h->V, J + 1, ld), Q, kn, h->Cn));
-            GIR_TRY(combine(h, basis(h, h->U, kc, ld, h->V, J, ld), PR, kn, h->Un));
-            std::swap(h->C, h->Cn);
-            std::swap(h->U, h->Un);
-            kc = kn;
-          }
-        }
+        Refresh rf;
+        rf.kc = kc;
+        rf.J = J;
+        rf.rows = rows;
+        rf.cols = cols;
+        rf.Gm = std::move(Gm);
+        rf.Mm = std::move(Mm);
+        rf.dk = dk;
+        GIR_TRY(schedule_refresh(h, rf, fin.done || stats.its >= cap, &kc));
       }
     }
     GIR_HIP(hipStreamSynchronize(s));
   }
-  h->kc_keep = (k > 0) ? kc : 0;
+  // with a deferred refresh the dimension is set when it is applied
+  if (!h->pend.active) h->kc_keep = (k > 0) ? kc : 0;
   return 0;
 }
 
@@ -1171,7 +1220,10 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     if (info) *info = inf;
     return h->status;
   }
-  if (!h->o.keep_recycle) h->kc_keep = 0;
+  if (!h->o.keep_recycle) {
+    h->kc_keep = 0;
+    h->pend.active = false;
+  }
   gir::launch_copy_i32(reinterpret_cast<int*>(h->b), reinterpret_cast<const int*>(bcol), 2 * n, s);
   gir::launch_maxabs(h->b, n, h->norms + 2, s);
   unsigned long long bbits = 0;
@@ -1226,6 +1278,8 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     gir::launch_x_update(h->x, h->du, h->u64, rmax, n, s);
     GIR_HIP(hipGetLastError());
   }
+  // the last refresh is needed only when the space is kept for the next call
+  GIR_TRY(resolve_pending(h, h->o.keep_recycle != 0));
   inf.steps = i;
   inf.status = status;
   inf.recycle_dim = h->kc_keep;
