@@ -65,6 +65,10 @@ void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* 
 void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const float* v32,
                     const double* v64, double* t, const CycleState* gate, int step,
                     hipStream_t s);
+// T[:, r] = A_u[permA rows] Y[:, r], r < nr <= 8 (fp64 Y and T, leading
+// dimensions ldy, ldt; Y's columns 16-byte aligned), fp64 accumulation
+void launch_gemv_au_multi(const float* Au, int64_t ld, const int* permA, int n, const double* Y,
+                          int64_t ldy, int nr, double* T, int64_t ldt, hipStream_t s);
 // t[i] = sum_c A[permA[i]][c] v[c] with fp64 A and v, fp64 accumulation
 void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const double* v,
                      double* t, const CycleState* gate, int step, hipStream_t s);

@@ -59,6 +59,48 @@ __global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, i
   if (lane == 0) t[row] = s;
 }
 
+// T[:, r] = A_u[permA] Y[:, r] for NR fp64 columns of Y (ld ldy) at once:
+// one wave per row, the row read once for all of them (the recycle set-up)
+template <int NR>
+__global__ __launch_bounds__(256) void k_gemv_au_multi(const float* __restrict__ Au, int64_t ld,
+                                                       const int* __restrict__ permA, int n,
+                                                       const double* __restrict__ Y,
+                                                       int64_t ldy, int nr,
+                                                       double* __restrict__ T, int64_t ldt) {
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= n) return;
+  const int prow = permA ? permA[row] : row;
+  const float* a = Au + (int64_t)prow * ld;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  const int n4 = n & ~3;
+  for (int c = lane * 4; c < n4; c += 256) {
+    const float4 x = *reinterpret_cast<const float4*>(a + c);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double* y = Y + (int64_t)min(r, nr - 1) * ldy + c;
+      const double2 y0 = *reinterpret_cast<const double2*>(y);
+      const double2 y1 = *reinterpret_cast<const double2*>(y + 2);
+      acc[r] = fma((double)x.x, y0.x, acc[r]);
+      acc[r] = fma((double)x.y, y0.y, acc[r]);
+      acc[r] = fma((double)x.z, y1.x, acc[r]);
+      acc[r] = fma((double)x.w, y1.y, acc[r]);
+    }
+  }
+  for (int cc = n4 + lane; cc < n; cc += kWave) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      acc[r] = fma((double)a[cc], Y[(int64_t)min(r, nr - 1) * ldy + cc], acc[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double sres = wave_sum(acc[r]);
+    if (lane == 0 && r < nr) T[(int64_t)r * ldt + row] = sres;
+  }
+}
+
 // t[i] = sum_c A[permA[i]][c] v[c] with fp64 A and v (the uniform-precision
 // product for u = fp64): one wave per row, double2 loads
 __global__ __launch_bounds__(256) void k_gemv_a64(const double* __restrict__ A, int64_t ld,
@@ -365,13 +407,12 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
 // row.  in / out are column-major (ldi / ldo); right-hand side r exchanges its
 // words in xw + r * xstride.
 
-template <class F, bool kUpper>
+template <class F, bool kUpper, int NR>
 __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
     const typename F::T* __restrict__ S, int64_t ld, const int* __restrict__ permS, int n,
     const double* __restrict__ in, int64_t ldi, const int* __restrict__ permIn, int nr,
     const double* __restrict__ Dinv, double* __restrict__ out, int64_t ldo, double scale,
     uint64_t* xw, int64_t xstride, uint32_t epoch, int* abortp) {
-  constexpr int NR = kTrsvMaxRhs;
   __shared__ double ysh[8][NR][kTB];
   __shared__ double zsh[NR][kTS];
   __shared__ double part[4][NR][kTS];
@@ -1109,6 +1150,20 @@ void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const 
                        gate, step);
 }
 
+void launch_gemv_au_multi(const float* Au, int64_t ld, const int* permA, int n, const double* Y,
+                          int64_t ldy, int nr, double* T, int64_t ldt, hipStream_t s) {
+  const unsigned grid = nblocks(n, 4);
+  if (nr <= 2)
+    hipLaunchKernelGGL(k_gemv_au_multi<2>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, Y, ldy,
+                       nr, T, ldt);
+  else if (nr <= 4)
+    hipLaunchKernelGGL(k_gemv_au_multi<4>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, Y, ldy,
+                       nr, T, ldt);
+  else
+    hipLaunchKernelGGL(k_gemv_au_multi<8>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, Y, ldy,
+                       nr, T, ldt);
+}
+
 void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const double* v,
                      double* t, const CycleState* gate, int step, hipStream_t s) {
   hipLaunchKernelGGL(k_gemv_a64, dim3(nblocks(n, 4)), dim3(256), 0, s, A, ld, permA, n, v, t,
@@ -1174,17 +1229,24 @@ void launch_trsv_multi(const void* S, int64_t ld, const int* permS, int store, i
                        const double* Dinv, double* out, int64_t ldo, double scale, uint64_t* xw,
                        int64_t xstride, int epoch, int* abortp, hipStream_t s) {
   const unsigned grid = nblocks(n, kTS);
-#define GIR_TM(F, U)                                                                          \
-  hipLaunchKernelGGL((k_trsv_multi<F, U>), dim3(grid), dim3(kTSThreads), 0, s,                \
+  // the kernel's cost per block grows with the number of right-hand sides it
+  // is compiled for: the smallest of 2, 4, 8 that holds nr
+#define GIR_TM(F, U, R)                                                                        \
+  hipLaunchKernelGGL((k_trsv_multi<F, U, R>), dim3(grid), dim3(kTSThreads), 0, s,              \
                      reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, ldi, permIn, \
                      nr, Dinv, out, ldo, scale, xw, xstride, (uint32_t)epoch, abortp)
+#define GIR_TMR(F, U) \
+  do {                \
+    if (nr <= 2) GIR_TM(F, U, 2); else if (nr <= 4) GIR_TM(F, U, 4); else GIR_TM(F, U, 8); \
+  } while (0)
   if (store == kStoreF16) {
-    if (upper) GIR_TM(Fp16, true); else GIR_TM(Fp16, false);
+    if (upper) GIR_TMR(Fp16, true); else GIR_TMR(Fp16, false);
   } else if (store == kStoreBF16) {
-    if (upper) GIR_TM(Bf16, true); else GIR_TM(Bf16, false);
+    if (upper) GIR_TMR(Bf16, true); else GIR_TMR(Bf16, false);
   } else {
-    if (upper) GIR_TM(Fp32, true); else GIR_TM(Fp32, false);
+    if (upper) GIR_TMR(Fp32, true); else GIR_TMR(Fp32, false);
   }
+#undef GIR_TMR
 #undef GIR_TM
 }
 

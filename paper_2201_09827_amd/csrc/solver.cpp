@@ -808,11 +808,11 @@ int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
   const double tbytes = 0.5 * nn * (nn + 1.0) * (double)store_bytes(h->store);
   for (int c0 = 0; c0 < kk; c0 += gir::kTrsvMaxRhs) {
     const int nr = std::min(gir::kTrsvMaxRhs, kk - c0);
-    for (int r = 0; r < nr; ++r)
-      GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + 16.0 * nn, h->stream, nullptr, 0, [&] {
-        gir::launch_gemv_au(h->Au, ld, h->permP, n, nullptr, Y + (size_t)(c0 + r) * ld,
-                            h->Tb + (size_t)r * ld, nullptr, 0, h->stream);
-      }));
+    // A_u read once for the chunk's columns
+    GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + 16.0 * nn * nr, h->stream, nullptr, 0, [&] {
+      gir::launch_gemv_au_multi(h->Au, ld, h->permP, n, Y + (size_t)c0 * ld, ld, nr, h->Tb, ld,
+                                h->stream);
+    }));
     const int eL = next_epoch(h);
     GIR_TRY(timed(h, kKcTrsvL, tbytes + 16.0 * nr * nn, h->stream, nullptr, 0, [&] {
       gir::launch_trsv_multi(h->S, ld, h->permS, h->store, n, false, h->Tb, ld, nullptr, nr,
