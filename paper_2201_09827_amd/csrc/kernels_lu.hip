@@ -497,6 +497,13 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict
   const int64_t c = (int64_t)c_begin + (int64_t)blockIdx.x * kTrsmThreads + tid;
   prow[tid] = perm[k0 + tid];
   __syncthreads();
+  // this thread's column of the block row: its loads are issued together with
+  // those of the L11 row below (one memory round trip for both); a thread
+  // beyond c_end reads a valid column and discards it
+  const int64_t cc = c < c_end ? c : (int64_t)c_begin;
+  typename F::T yraw[kMaxNb];
+#pragma unroll
+  for (int t = 0; t < kMaxNb; ++t) yraw[t] = S[(int64_t)prow[t] * ld + cc];
   {
     // row r = tid of L11 in 16-byte pieces (all loads in flight at once),
     // written transposed; entries on and above the diagonal are zero
@@ -509,7 +516,7 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict
   if (c >= c_end) return;
   float y[kMaxNb];
 #pragma unroll
-  for (int t = 0; t < kMaxNb; ++t) y[t] = F::to_f(S[(int64_t)prow[t] * ld + c]);
+  for (int t = 0; t < kMaxNb; ++t) y[t] = F::to_f(yraw[t]);
 #pragma unroll
   for (int t = 0; t < kMaxNb; ++t) asm volatile("" : "+v"(y[t]));
 #pragma unroll
