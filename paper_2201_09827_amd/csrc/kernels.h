@@ -76,7 +76,7 @@ void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const
 void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
                      double* r, unsigned long long* norms, hipStream_t s);
 // y = L^-1 (in gathered by permIn), fp64; L unit lower in S rows permS;
-// Linv holds the fp64 inverses of the 64 x 64 diagonal blocks
+// Linv as written by launch_diag_inverses
 // xw: [2 * ceil(n/128) * 128] tagged words, zeroed once; epoch: a new
 // nonzero value per launch
 void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
@@ -96,8 +96,11 @@ void launch_trsv_multi(const void* S, int64_t ld, const int* permS, int store, i
                        const double* in, int64_t ldi, const int* permIn, int nr,
                        const double* Dinv, double* out, int64_t ldo, double scale, uint64_t* xw,
                        int64_t xstride, int epoch, int* abortp, hipStream_t s);
-// fp64 inverses of the 128 x 128 diagonal blocks of L and U (ceil(n/128)
-// blocks of 128 x 128 each, row-major); tmp: ceil(n/64) * 64 * 64 doubles
+// Linv / Uinv: 2 * ceil(n/128) blocks of 128 x 128 fp64, row-major: the
+// inverses of the diagonal blocks of L and U, then the products of each
+// inverse with the neighbouring off-diagonal block the single right-hand side
+// solves read (lower: Linv_I L_{I,I-1}; upper: Uinv_I U_{I,I+1});
+// tmp: ceil(n/64) * 64 * 64 doubles
 constexpr int kTrsvBlock = 128;
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,
                           double* Linv, double* Uinv, double* tmp, hipStream_t s);

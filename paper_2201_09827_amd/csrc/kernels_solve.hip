@@ -274,11 +274,11 @@ __device__ __forceinline__ void put_tagged(uint64_t* xw, int row, double v, uint
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// wave-uniform: every lane reads row (c0 + lane)'s value; false on abort
-__device__ __forceinline__ bool get_tagged64(const uint64_t* xw, int c0, uint32_t tag, double& v,
-                                             int* abortp) {
-  const int lane = threadIdx.x % kWave;
-  const uint64_t* p = xw + 2 * (c0 + lane);
+// every lane reads the value of row `row` (wave-uniform result: the wave
+// waits until all its lanes see this epoch's tags); false on abort
+__device__ __forceinline__ bool get_tagged_row(const uint64_t* xw, int row, uint32_t tag,
+                                               double& v, int* abortp) {
+  const uint64_t* p = xw + 2 * row;
   long long spins = 0;
   for (;;) {
     const uint64_t lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -297,6 +297,20 @@ __device__ __forceinline__ bool get_tagged64(const uint64_t* xw, int c0, uint32_
       }
     }
   }
+}
+
+// wave-uniform: every lane reads row (c0 + lane)'s value; false on abort
+__device__ __forceinline__ bool get_tagged64(const uint64_t* xw, int c0, uint32_t tag, double& v,
+                                             int* abortp) {
+  return get_tagged_row(xw, c0 + (int)(threadIdx.x % kWave), tag, v, abortp);
+}
+
+// lane c's fp64 value, read into scalar registers (c a compile-time constant)
+__device__ __forceinline__ double lane_value(double v, int c) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), c);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), c);
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 template <class F, bool kUpper>
@@ -328,17 +342,29 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   const bool valid = row < n;
   const int prow = valid ? (permS ? permS[row] : row) : 0;
   const typename F::T* srow = S + (int64_t)prow * ld;
-  // this thread's quarter of its row of the inverse diagonal block
+  // the neighbouring block (the last one this block waits for) enters
+  // through its precomputed product with the inverse diagonal block
+  const bool hasAdj = kUpper ? blk < nb - 1 : blk > 0;
+  const int adj = kUpper ? blk + 1 : blk - 1;
+  // this thread's quarter of its row of the inverse diagonal block, and of
+  // the same row of the adjacent product
   const int di = tid % kTS;
   const int dq4 = tid / kTS;
-  double dq[kTS / 4];
+  double dq[kTS / 4], mq[kTS / 4];
   {
     const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
+    const double* mrow = drow + (int64_t)nb * kTS * kTS;
 #pragma unroll
     for (int c = 0; c < kTS / 4; c += 2) {
       const double2 v = *reinterpret_cast<const double2*>(drow + c);
       dq[c] = v.x;
       dq[c + 1] = v.y;
+    }
+#pragma unroll
+    for (int c = 0; c < kTS / 4; c += 2) {
+      const double2 v = hasAdj ? *reinterpret_cast<const double2*>(mrow + c) : double2{0.0, 0.0};
+      mq[c] = v.x;
+      mq[c + 1] = v.y;
     }
   }
   double rhs = 0.0;
@@ -348,8 +374,9 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   }
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   bool ok = true;
-  const int t0 = kUpper ? 2 * blk + 2 : 0;  // first off-diagonal tile (upper: first to the right)
-  const int t1 = kUpper ? nt : 2 * blk;     // one past the last
+  // off-diagonal tiles other than the neighbouring block's two
+  const int t0 = kUpper ? 2 * blk + 4 : 0;
+  const int t1 = kUpper ? nt : (blk > 0 ? 2 * blk - 2 : 0);
   // lower: ascending from tile wq; upper: descending from the last tile
   for (int i = wq;; i += 4) {
     const int J = kUpper ? t1 - 1 - i : t0 + i;
@@ -385,11 +412,30 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
     zsh[tid] = (r0 + tid < n) ? rhs - sum : 0.0;
   }
   __syncthreads();
+  // Dinv (in - sum over the far blocks) - P (neighbour's values), this
+  // thread's quarter of its row
   double p = 0.0;
 #pragma unroll
   for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[dq4 * (kTS / 4) + c], p);
+  if (hasAdj) {
+    // the 32 neighbouring values this quarter multiplies: lanes c and c + 32
+    // both read row dq4 * 32 + c of the neighbour
+    double ya;
+    const bool got = get_tagged_row(xw, adj * kTS + dq4 * (kTS / 4) + (lane & 31), epoch, ya,
+                                    abortp);
+    if (got) {
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) p = fma(-mq[c], lane_value(ya, c), p);
+    }
+    if (lane == 0) wok[wave] = got ? 1 : 0;
+  }
   part[dq4][di] = p;
   __syncthreads();
+  if (hasAdj) {
+#pragma unroll
+    for (int w = 0; w < 8; ++w) allok &= wok[w];
+    if (!allok) return;
+  }
   if (tid >= kTS) return;
   const int rr = r0 + tid;
   const double v = (rr < n) ? (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]) : 0.0;
@@ -406,6 +452,40 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
 // for all of them, and one round trip fetches the nr published values of a
 // row.  in / out are column-major (ldi / ldo); right-hand side r exchanges its
 // words in xw + r * xstride.
+
+// the nr published values of row `row` (each lane its own row), all loads
+// issued before any is checked (one memory round trip; slots beyond nr
+// repeat the last one); false on abort
+template <int NR>
+__device__ __forceinline__ bool get_tagged_rows(const uint64_t* xw, int64_t xstride, int nr,
+                                                int row, uint32_t epoch, double (&v)[NR],
+                                                int* abortp) {
+  long long spins = 0;
+  for (;;) {
+    uint64_t lo[NR], hi[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint64_t* p = xw + (int64_t)min(r, nr - 1) * xstride + 2 * row;
+      lo[r] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hi[r] = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    bool got = true;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      got = got && (uint32_t)(lo[r] >> 32) == epoch && (uint32_t)(hi[r] >> 32) == epoch;
+      v[r] = __longlong_as_double((long long)((hi[r] << 32) | (lo[r] & 0xFFFFFFFFull)));
+    }
+    if (__all(got)) return true;
+    __builtin_amdgcn_s_sleep(1);
+    if (((++spins) & 1023) == 0) {
+      if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+          spins > (1ll << 22)) {
+        __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+  }
+}
 
 template <class F, bool kUpper, int NR>
 __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
@@ -430,16 +510,31 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
   const bool valid = row < n;
   const int prow = valid ? (permS ? permS[row] : row) : 0;
   const typename F::T* srow = S + (int64_t)prow * ld;
+  // the neighbouring block enters through its precomputed product with the
+  // inverse diagonal block where the registers allow it (up to 8 right-hand
+  // sides with 16-bit factors, 4 with fp32 ones); otherwise through its tiles
+  constexpr bool kAdj = NR <= (sizeof(typename F::T) == 2 ? 8 : 4);
+  const bool hasAdj = kAdj && (kUpper ? blk < nb - 1 : blk > 0);
+  const int adj = kUpper ? blk + 1 : blk - 1;
   const int di = tid % kTS;
   const int dq4 = tid / kTS;
-  double dq[kTS / 4];
-  {
-    const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
+  // this thread's quarter of its row of the inverse diagonal block and of the
+  // neighbour's product
+  const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
+  const double* mrow = drow + (int64_t)nb * kTS * kTS;
+  double dq[kTS / 4], mq[kTS / 4];
+#pragma unroll
+  for (int c = 0; c < kTS / 4; c += 2) {
+    const double2 v = *reinterpret_cast<const double2*>(drow + c);
+    dq[c] = v.x;
+    dq[c + 1] = v.y;
+  }
+  if (kAdj) {
 #pragma unroll
     for (int c = 0; c < kTS / 4; c += 2) {
-      const double2 v = *reinterpret_cast<const double2*>(drow + c);
-      dq[c] = v.x;
-      dq[c + 1] = v.y;
+      const double2 v = hasAdj ? *reinterpret_cast<const double2*>(mrow + c) : double2{0.0, 0.0};
+      mq[c] = v.x;
+      mq[c + 1] = v.y;
     }
   }
   double rhs[NR];
@@ -455,8 +550,10 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
 #pragma unroll
   for (int r = 0; r < NR; ++r) acc[r] = 0.0;
   bool ok = true;
-  const int t0 = kUpper ? 2 * blk + 2 : 0;
-  const int t1 = kUpper ? nt : 2 * blk;
+  // off-diagonal tiles (without the neighbouring block's two when its
+  // product is used)
+  const int t0 = kUpper ? 2 * blk + (kAdj ? 4 : 2) : 0;
+  const int t1 = kUpper ? nt : (kAdj ? (blk > 0 ? 2 * blk - 2 : 0) : 2 * blk);
   for (int i = wq;; i += 4) {
     const int J = kUpper ? t1 - 1 - i : t0 + i;
     if (kUpper ? (J < t0) : (J >= t1)) break;
@@ -528,6 +625,8 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
     }
   }
   __syncthreads();
+  // Dinv (in - sum over the far blocks) - P (neighbour's values), this
+  // thread's quarter of its row, for each right-hand side
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     double p = 0.0;
@@ -535,7 +634,31 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
     for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[r][dq4 * (kTS / 4) + c], p);
     part[dq4][r][di] = p;
   }
+  if (hasAdj) {
+    // lanes c and c + 32 both fetch row dq4 * 32 + c of the neighbour
+    double v[NR];
+    const bool got = get_tagged_rows<NR>(xw, xstride, nr, adj * kTS + dq4 * (kTS / 4) + (lane & 31),
+                                         epoch, v, abortp);
+    if (got) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) ysh[wave][r][lane] = v[r];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double p = part[dq4][r][di];
+#pragma unroll
+        for (int c = 0; c < kTS / 4; ++c) p = fma(-mq[c], ysh[wave][r][c], p);
+        part[dq4][r][di] = p;
+      }
+    }
+    if (lane == 0) wok[wave] = got ? 1 : 0;
+  }
   __syncthreads();
+  if (hasAdj) {
+#pragma unroll
+    for (int w = 0; w < 8; ++w) allok &= wok[w];
+    if (!allok) return;
+  }
   if (tid >= kTS) return;
   const int rr = r0 + tid;
 #pragma unroll
@@ -606,6 +729,53 @@ __global__ __launch_bounds__(256) void k_diag_combine(const typename F::T* __res
     }
     out[idx] = v;
   }
+}
+
+// Products of each 128 x 128 inverse diagonal block with the neighbouring
+// off-diagonal block of the same triangle, in fp64 with the u_f entries
+// taken exactly:
+//   lower: P_I = Dinv_I L_{I,I-1}  (I >= 1)
+//   upper: P_I = Dinv_I U_{I,I+1}  (I <= nb - 2)
+// so that the blocked solve needs one 128 x 128 product once the neighbour's
+// values arrive.  Grid (nb - 1, 4): blockIdx.y picks 32 columns of P_I.
+// Rows or columns beyond n enter as zeros.
+template <class F, bool kUpper>
+__global__ __launch_bounds__(256) void k_adjacent_product(const typename F::T* __restrict__ S,
+                                                          int64_t ld,
+                                                          const int* __restrict__ permS, int n,
+                                                          const double* __restrict__ Dinv,
+                                                          double* __restrict__ P) {
+  constexpr int kC = kTS / 4;
+  __shared__ double B[kTS][kC + 1];
+  const int blk = kUpper ? (int)blockIdx.x : (int)blockIdx.x + 1;
+  const int adj = kUpper ? blk + 1 : blk - 1;
+  const int c0 = adj * kTS + (int)blockIdx.y * kC;  // first global column
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kTS * kC; idx += 256) {
+    const int t = idx / kC, c = idx % kC;
+    const int gr = blk * kTS + t, gc = c0 + c;
+    double v = 0.0;
+    if (gr < n && gc < n) v = (double)F::to_f(S[(int64_t)(permS ? permS[gr] : gr) * ld + gc]);
+    B[t][c] = v;
+  }
+  __syncthreads();
+  const int r = tid / 2;
+  const int cb = (tid % 2) * (kC / 2);
+  const double* drow = Dinv + ((int64_t)blk * kTS + r) * kTS;
+  double acc[kC / 2];
+#pragma unroll
+  for (int j = 0; j < kC / 2; ++j) acc[j] = 0.0;
+  for (int t = 0; t < kTS; t += 2) {
+    const double2 d = *reinterpret_cast<const double2*>(drow + t);
+#pragma unroll
+    for (int j = 0; j < kC / 2; ++j) {
+      acc[j] = fma(d.x, B[t][cb + j], acc[j]);
+      acc[j] = fma(d.y, B[t + 1][cb + j], acc[j]);
+    }
+  }
+  double* out = P + ((int64_t)blk * kTS + r) * kTS + (int)blockIdx.y * kC + cb;
+#pragma unroll
+  for (int j = 0; j < kC / 2; ++j) out[j] = acc[j];
 }
 
 // Inverse of each 64 x 64 diagonal block of L (unit lower) or U (upper) in
@@ -1265,6 +1435,12 @@ void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store
                        n, tmp);                                                              \
     hipLaunchKernelGGL((k_diag_combine<F, true>), dim3(g128), dim3(256), 0, s, Sp, ld, permS, \
                        n, tmp, Uinv);                                                        \
+    if (g128 > 1) {                                                                          \
+      hipLaunchKernelGGL((k_adjacent_product<F, false>), dim3(g128 - 1, 4), dim3(256), 0, s,  \
+                         Sp, ld, permS, n, Linv, Linv + (int64_t)g128 * kTS * kTS);          \
+      hipLaunchKernelGGL((k_adjacent_product<F, true>), dim3(g128 - 1, 4), dim3(256), 0, s,   \
+                         Sp, ld, permS, n, Uinv, Uinv + (int64_t)g128 * kTS * kTS);          \
+    }                                                                                        \
   } while (0)
   if (store == kStoreF16) {
     GIR_DINV(Fp16);

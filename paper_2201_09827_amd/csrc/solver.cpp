@@ -456,8 +456,8 @@ int alloc_common(gmresir_ctx* h) {
     // fp64 inverses of the diagonal blocks (the double-double solves
     // substitute within the block instead)
     const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
-    GIR_TRY(dalloc(h->arena, &h->Linv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
-    GIR_TRY(dalloc(h->arena, &h->Uinv, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    GIR_TRY(dalloc(h->arena, &h->Linv, 2 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    GIR_TRY(dalloc(h->arena, &h->Uinv, 2 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
     GIR_TRY(dalloc(h->arena, &h->dtmp, ((n + 63) / 64) * 64 * 64));
   }
   GIR_TRY(dalloc(h->arena, &h->st, 1));

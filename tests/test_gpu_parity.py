@@ -5,8 +5,8 @@ Bars:
 * LU: pivots identical; u_f entries identical except rare one-ulp splits of
   the fp32-accumulated trailing update; componentwise backward error within
   the blocked-GEPP bound.
-* preconditioned products with identical factors: fp64 results agree to
-  rounding level (they differ only in summation order).
+* preconditioned products with identical factors: fp64 results within the
+  LU-solve backward error bound; rounded to u, nearly all entries identical.
 * end-to-end: identical refinement-step counts, GMRES iterations within +-2
   per step, normwise backward error <= 8 n u, forward error within 10x the
   oracle's.
@@ -92,8 +92,30 @@ def test_lu_factors_match_oracle(lib, n, uf):
     assert np.all(np.abs(np.tril(L, -1)) <= 1.0)      # partial pivoting
 
 
+def _lu_backward_error(f, rhs, z, extra=None):
+    """max |rhs - M z| / max(|M| |z| (+ extra)) with M = 2^-e P^T L U, the
+    residual in extended precision (LU-solve backward error, normwise)."""
+    ld = np.longdouble
+    zs = np.ldexp(z, -f.e)
+    lu = f.L.astype(ld) @ (f.U.astype(ld) @ zs.astype(ld))
+    mz = np.empty_like(lu)
+    mz[f.perm] = lu
+    r = (np.asarray(rhs, dtype=ld) - mz).astype(np.float64)
+    a = np.abs(f.L) @ (np.abs(f.U) @ np.abs(zs))
+    den = np.empty_like(a)
+    den[f.perm] = a
+    if extra is not None:
+        den = den + extra
+    return np.max(np.abs(r)) / np.max(den)
+
+
 @pytest.mark.parametrize("n", [100, 333, 1024])
 def test_preconditioned_products_with_shared_factors(lib, n):
+    """M^-1 v and A-tilde v with the oracle's factors, in fp64 (precision u^2):
+    each within the backward error bound of a solve with the LU factors,
+    |r| <= 3 n u^2 (|L||U||z| (+ |A_u||v|)); the forward difference from the
+    oracle's substitution is rounding-order noise amplified by the condition
+    of U, logged; once rounded to u nearly every entry is identical."""
     p = randsvd_problem(n, 1e5, 5)
     o = oracle_options()
     f = refine.factor(p.a, o)
@@ -109,8 +131,13 @@ def test_preconditioned_products_with_shared_factors(lib, n):
     r1 = refine.minv_hi(f, f.au @ v, "fp64")
     e0 = np.linalg.norm(y0 - r0) / np.linalg.norm(r0)
     e1 = np.linalg.norm(y1 - r1) / np.linalg.norm(r1)
-    log(f"[apply] n={n} rel err M^-1 v {e0:.2e}  A~v {e1:.2e}")
-    assert e0 < 1e-11 and e1 < 1e-11
+    # A_u v exactly (fp32 products are exact in fp64; the sum in extended precision)
+    w = f.au.astype(np.longdouble) @ v.astype(np.longdouble)
+    b0 = _lu_backward_error(f, v, y0)
+    b1 = _lu_backward_error(f, w, y1, extra=np.abs(f.au) @ np.abs(v))
+    log(f"[apply] n={n} rel diff from oracle M^-1 v {e0:.2e}  A~v {e1:.2e}; "
+        f"backward error / u^2 {b0 / U64:.2f} {b1 / U64:.2f}")
+    assert b0 <= 3 * n * U64 and b1 <= 3 * n * U64
     # once rounded to u (fp32) nearly every entry is identical
     same = np.mean(fp.fl32(y1) == fp.fl32(r1))
     assert same > 0.99
