@@ -197,13 +197,20 @@ void launch_colsum(const void* A, int a64, int64_t ld, int n, const void* v, int
 // receives the column sums
 void launch_colsum_abs(const double* A, int64_t ld, int n, double* partial, double* t,
                        unsigned long long* out, hipStream_t s);
+// the products the transposed solves read, one 128 x 128 fp64 block per
+// block row (ceil(n/128) blocks each, row-major): Uq_I = U_{I-1,I} Uinv_I,
+// Lq_I = L_{I+1,I} Linv_I (Linv / Uinv as written by launch_diag_inverses)
+void launch_adjacent_products_t(const void* S, int64_t ld, const int* permS, int store, int n,
+                                const double* Linv, const double* Uinv, double* Lq, double* Uq,
+                                hipStream_t s);
 // U^T y = in (upperT = false) or L^T z = in (upperT = true) with the stored
-// factor (rows permS of S) and the fp64 inverses of its 128 x 128 diagonal
-// blocks (transposed on use); y (may be null) receives the solution,
-// out64 / out32 (either may be null) scale * solution scattered through
-// permOut (null: identity); xw / epoch as for launch_trsv_lower
+// factor (rows permS of S), the fp64 inverses of its 128 x 128 diagonal
+// blocks (transposed on use) and the products Q (Uq, Lq) above; y (may be
+// null) receives the solution, out64 / out32 (either may be null) scale *
+// solution scattered through permOut (null: identity); xw / epoch as for
+// launch_trsv_lower
 void launch_trsv_t(const void* S, int64_t ld, const int* permS, int store, int n, bool upperT,
-                   const double* in, const double* Dinv, double* y, double scale,
+                   const double* in, const double* Dinv, const double* Q, double* y, double scale,
                    const int* permOut, double* out64, float* out32, uint64_t* xw, int epoch,
                    const CycleState* gate, int step, int* abortp, hipStream_t s);
 // out = alpha x y^T (n x n row-major, leading dimension ld)

@@ -778,6 +778,60 @@ __global__ __launch_bounds__(256) void k_adjacent_product(const typename F::T* _
   for (int j = 0; j < kC / 2; ++j) out[j] = acc[j];
 }
 
+// The products the transposed solves need, the neighbouring off-diagonal
+// block times the inverse diagonal block (fp64, u_f entries exact):
+//   U^T solve (block I >= 1):      Q_I = U_{I-1,I} Uinv_I
+//   L^T solve (block I <= nb - 2): Q_I = L_{I+1,I} Linv_I
+// Q_I^T is the block of the transposed system's product.  Grid (nb - 1, 4):
+// blockIdx.y picks 32 columns of Q_I; B and the inverse are staged through
+// LDS 32 contraction columns at a time.  Rows or columns beyond n enter as
+// zeros.
+template <class F, bool kUpperSrc>
+__global__ __launch_bounds__(256) void k_adjacent_product_t(const typename F::T* __restrict__ S,
+                                                            int64_t ld,
+                                                            const int* __restrict__ permS, int n,
+                                                            const double* __restrict__ Dinv,
+                                                            double* __restrict__ Q) {
+  constexpr int kC = kTS / 4;
+  __shared__ double B[kTS][kC + 1];
+  __shared__ double D[kC][kC + 1];
+  const int blk = kUpperSrc ? (int)blockIdx.x + 1 : (int)blockIdx.x;
+  const int brow0 = kUpperSrc ? (blk - 1) * kTS : (blk + 1) * kTS;  // rows of B
+  const int bcol0 = blk * kTS;                                        // columns of B
+  const int c0 = (int)blockIdx.y * kC;
+  const int tid = threadIdx.x;
+  const int r = tid / 2;
+  const int cb = (tid % 2) * (kC / 2);
+  const double* Db = Dinv + (int64_t)blk * kTS * kTS;
+  double acc[kC / 2];
+#pragma unroll
+  for (int j = 0; j < kC / 2; ++j) acc[j] = 0.0;
+  for (int t0 = 0; t0 < kTS; t0 += kC) {
+    __syncthreads();
+    for (int idx = tid; idx < kTS * kC; idx += 256) {
+      const int rr = idx / kC, t = idx % kC;
+      const int gr = brow0 + rr, gc = bcol0 + t0 + t;
+      double v = 0.0;
+      if (gr < n && gc < n) v = (double)F::to_f(S[(int64_t)(permS ? permS[gr] : gr) * ld + gc]);
+      B[rr][t] = v;
+    }
+    for (int idx = tid; idx < kC * kC; idx += 256) {
+      const int t = idx / kC, c = idx % kC;
+      D[t][c] = Db[(int64_t)(t0 + t) * kTS + c0 + c];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int t = 0; t < kC; ++t) {
+      const double b = B[r][t];
+#pragma unroll
+      for (int j = 0; j < kC / 2; ++j) acc[j] = fma(b, D[t][cb + j], acc[j]);
+    }
+  }
+  double* out = Q + ((int64_t)blk * kTS + r) * kTS + c0 + cb;
+#pragma unroll
+  for (int j = 0; j < kC / 2; ++j) out[j] = acc[j];
+}
+
 // Inverse of each 64 x 64 diagonal block of L (unit lower) or U (upper) in
 // fp64, row-major per block; rows/columns beyond n get the identity.
 template <class F, bool kUpper>
@@ -1192,7 +1246,8 @@ __global__ __launch_bounds__(256) void k_colsum_finish(const double* __restrict_
 template <class F, bool kUpperT>
 __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
     const typename F::T* __restrict__ S, int64_t ld, const int* __restrict__ permS, int n,
-    const double* __restrict__ in, const double* __restrict__ Dinv, double* __restrict__ y,
+    const double* __restrict__ in, const double* __restrict__ Dinv,
+    const double* __restrict__ Q, double* __restrict__ y,
     double scale, const int* __restrict__ permOut, double* __restrict__ out64,
     float* __restrict__ out32, uint64_t* xw, uint32_t epoch, const CycleState* gate, int step,
     int* abortp) {
@@ -1213,21 +1268,28 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
   const int half = wave >> 2;
   const int wq = wave & 3;
   const int col = r0 + half * kTB + lane;  // this thread's row of the transposed system
-  // this thread's quarter of its row of (D^-1)^T, i.e. of column di of D^-1
+  // the neighbouring block (the last one waited for) enters through Q^T
+  const bool hasAdj = kUpperT ? blk < nb - 1 : blk > 0;
+  const int adj = kUpperT ? blk + 1 : blk - 1;
+  // this thread's quarter of its row of (D^-1)^T and of Q^T, i.e. of column
+  // di of D^-1 and of Q
   const int di = tid % kTS;
   const int dq4 = tid / kTS;
-  double dq[kTS / 4];
+  double dq[kTS / 4], mq[kTS / 4];
   {
-    const double* dcol = Dinv + (int64_t)blk * kTS * kTS + (int64_t)(dq4 * (kTS / 4)) * kTS + di;
+    const int64_t off = (int64_t)blk * kTS * kTS + (int64_t)(dq4 * (kTS / 4)) * kTS + di;
 #pragma unroll
-    for (int c = 0; c < kTS / 4; ++c) dq[c] = dcol[(int64_t)c * kTS];
+    for (int c = 0; c < kTS / 4; ++c) dq[c] = Dinv[off + (int64_t)c * kTS];
+#pragma unroll
+    for (int c = 0; c < kTS / 4; ++c) mq[c] = hasAdj ? Q[off + (int64_t)c * kTS] : 0.0;
   }
   double rhs = 0.0;
   if (tid < kTS && r0 + tid < n) rhs = in[r0 + tid];
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   bool ok = true;
-  const int t0 = kUpperT ? 2 * blk + 2 : 0;
-  const int t1 = kUpperT ? nt : 2 * blk;
+  // off-diagonal tiles other than the neighbouring block's two
+  const int t0 = kUpperT ? 2 * blk + 4 : 0;
+  const int t1 = kUpperT ? nt : (blk > 0 ? 2 * blk - 2 : 0);
   for (int i = wq;; i += 4) {
     const int J = kUpperT ? t1 - 1 - i : t0 + i;
     if (kUpperT ? (J < t0) : (J >= t1)) break;
@@ -1274,8 +1336,24 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
   double p = 0.0;
 #pragma unroll
   for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[dq4 * (kTS / 4) + c], p);
+  if (hasAdj) {
+    // lanes c and c + 32 both read row dq4 * 32 + c of the neighbour
+    double ya;
+    const bool got = get_tagged_row(xw, adj * kTS + dq4 * (kTS / 4) + (lane & 31), epoch, ya,
+                                    abortp);
+    if (got) {
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) p = fma(-mq[c], lane_value(ya, c), p);
+    }
+    if (lane == 0) wok[wave] = got ? 1 : 0;
+  }
   part[dq4][di] = p;
   __syncthreads();
+  if (hasAdj) {
+#pragma unroll
+    for (int w = 0; w < 8; ++w) allok &= wok[w];
+    if (!allok) return;
+  }
   if (tid >= kTS) return;
   const int rr = r0 + tid;
   const double v = (rr < n) ? (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]) : 0.0;
@@ -1452,6 +1530,29 @@ void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store
 #undef GIR_DINV
 }
 
+void launch_adjacent_products_t(const void* S, int64_t ld, const int* permS, int store, int n,
+                                const double* Linv, const double* Uinv, double* Lq, double* Uq,
+                                hipStream_t s) {
+  const unsigned g128 = nblocks(n, kTS);
+  if (g128 < 2) return;
+#define GIR_QT(F)                                                                              \
+  do {                                                                                         \
+    const typename F::T* Sp = reinterpret_cast<const typename F::T*>(S);                       \
+    hipLaunchKernelGGL((k_adjacent_product_t<F, true>), dim3(g128 - 1, 4), dim3(256), 0, s, Sp, \
+                       ld, permS, n, Uinv, Uq);                                                \
+    hipLaunchKernelGGL((k_adjacent_product_t<F, false>), dim3(g128 - 1, 4), dim3(256), 0, s,    \
+                       Sp, ld, permS, n, Linv, Lq);                                            \
+  } while (0)
+  if (store == kStoreF16) {
+    GIR_QT(Fp16);
+  } else if (store == kStoreBF16) {
+    GIR_QT(Bf16);
+  } else {
+    GIR_QT(Fp32);
+  }
+#undef GIR_QT
+}
+
 void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s) {
   if (a.X.v64)
     hipLaunchKernelGGL(k_ortho<double>, dim3(nblocks(a.n, kRowsPerBlock)), dim3(256), 0, s, a,
@@ -1570,14 +1671,14 @@ void launch_colsum_abs(const double* A, int64_t ld, int n, double* partial, doub
 }
 
 void launch_trsv_t(const void* S, int64_t ld, const int* permS, int store, int n, bool upperT,
-                   const double* in, const double* Dinv, double* y, double scale,
+                   const double* in, const double* Dinv, const double* Q, double* y, double scale,
                    const int* permOut, double* out64, float* out32, uint64_t* xw, int epoch,
                    const CycleState* gate, int step, int* abortp, hipStream_t s) {
   const unsigned grid = nblocks(n, kTS);
 #define GIR_TT(F, U)                                                                        \
   hipLaunchKernelGGL((k_trsv_t<F, U>), dim3(grid), dim3(kTSThreads), 0, s,                  \
-                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, Dinv, y,   \
-                     scale, permOut, out64, out32, xw, (uint32_t)epoch, gate, step, abortp)
+                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, Dinv, Q,   \
+                     y, scale, permOut, out64, out32, xw, (uint32_t)epoch, gate, step, abortp)
   if (store == kStoreF16) {
     if (upperT) GIR_TT(Fp16, true); else GIR_TT(Fp16, false);
   } else if (store == kStoreBF16) {

@@ -189,6 +189,7 @@ struct gmresir_ctx {
   int* permS = nullptr;   // equals perm after gmresir_factor, null after import
   int* ipiv = nullptr;
   double *Linv = nullptr, *Uinv = nullptr;  // inverses of the diagonal blocks
+  double *Lq = nullptr, *Uq = nullptr;      // the transposed solves' block products
   double* dtmp = nullptr;                    // 64 x 64 inverses (factor time)
   // LU scratch
   uint64_t* xch = nullptr;  // pivot exchange of the block-column kernel (LU only)
@@ -685,13 +686,13 @@ int precond_t(gmresir_ctx* h, const double* in, double* out64, void* outu,
                        24.0 * (double)n;
   const int eL = next_epoch(h);
   GIR_TRY(timed(h, kKcTrsvL, bytes, h->stream, gate, step, [&] {
-    gir::launch_trsv_t(h->S, h->ld, h->permS, h->store, n, false, in, h->Uinv, h->y64, 1.0,
+    gir::launch_trsv_t(h->S, h->ld, h->permS, h->store, n, false, in, h->Uinv, h->Uq, h->y64, 1.0,
                        nullptr, nullptr, nullptr, h->xwL, eL, gate, step, &h->st->abort,
                        h->stream);
   }));
   const int eU = next_epoch(h);
   GIR_TRY(timed(h, kKcTrsvU, bytes, h->stream, gate, step, [&] {
-    gir::launch_trsv_t(h->S, h->ld, h->permS, h->store, n, true, h->y64, h->Linv, nullptr,
+    gir::launch_trsv_t(h->S, h->ld, h->permS, h->store, n, true, h->y64, h->Linv, h->Lq, nullptr,
                        h->scale, h->permP, out64, static_cast<float*>(outu), h->xwU, eU, gate,
                        step, &h->st->abort, h->stream);
   }));
@@ -1305,6 +1306,14 @@ int adjoint_setup(gmresir_ctx* h) {
   if (h->k > 0 && !h->Ut) {
     GIR_TRY(dalloc(h->arena, &h->Ut, ld * h->k));
     GIR_TRY(dalloc(h->arena, &h->Ct, ld * h->k));
+  }
+  if (!h->Lq) {
+    const size_t nb2 = ((size_t)n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
+    GIR_TRY(dalloc(h->arena, &h->Lq, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    GIR_TRY(dalloc(h->arena, &h->Uq, nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    gir::launch_adjacent_products_t(h->S, h->ld, h->permS, h->store, n, h->Linv, h->Uinv, h->Lq,
+                                    h->Uq, h->stream);
+    GIR_HIP(hipGetLastError());
   }
   if (h->norm_a1 < 0.0) {
     gir::launch_colsum_abs(h->A64, h->ld, n, h->colpart, h->t64, h->norms + 2, h->stream);

@@ -2,7 +2,8 @@
 factors (gmresir_solve_transposed), its preconditioned products, and the
 gradient of L = 0.5 ||x - y||^2 through x = A^-1 b (the autograd Function).
 
-Bars: products with shared factors agree with the oracle to rounding level;
+Bars: products with shared factors within the LU-solve backward error
+bound (M^-T v) and a first-order forward bound (M^-T A_u^T v);
 solves: identical refinement-step counts, Arnoldi iterations within +-2
 (identical with shared factors), backward error <= 8 n u, forward error
 within 10x the oracle's; gradients: central finite differences of the fp64
@@ -38,8 +39,22 @@ def _import(lib, p, f, o):
                               f.ipiv.astype(np.int32), f.e, **lib_options(o))
 
 
+def _lu_t_backward_error(f, rhs, z):
+    """max |rhs - M^T z| / max(|M|^T |z|) with M^T = 2^-e U^T L^T P, the
+    residual in extended precision (transposed LU-solve backward error)."""
+    ld = np.longdouble
+    zp = z[f.perm]
+    mz = f.U.T.astype(ld) @ (f.L.T.astype(ld) @ zp.astype(ld))
+    r = (np.asarray(rhs, dtype=ld) - np.ldexp(mz, -f.e)).astype(np.float64)
+    den = np.ldexp(np.abs(f.U).T @ (np.abs(f.L).T @ np.abs(zp)), -f.e)
+    return np.max(np.abs(r)) / np.max(den)
+
+
 @pytest.mark.parametrize("n", [100, 333, 1024])
 def test_transposed_products_with_shared_factors(lib, n):
+    """M^-T v within the transposed LU-solve backward error bound 3 n u^2;
+    M^-T A_u^T v within its first-order forward bound from the summation
+    order of the product with A_u^T."""
     p = randsvd_problem(n, 1e5, 7)
     o = oracle_options()
     f = refine.factor(p.a, o)
@@ -54,12 +69,14 @@ def test_transposed_products_with_shared_factors(lib, n):
     r3 = refine.minv_t(f, f.au.T @ v)
     e2 = np.linalg.norm(y2 - r2) / np.linalg.norm(r2)
     e3 = np.linalg.norm(y3 - r3) / np.linalg.norm(r3)
+    b2 = _lu_t_backward_error(f, v, y2)
     # the products with A_u^T differ in summation order only: bounded by
     # n u |M^-T| (|A_u|^T |v|), relative to the result
     mt = np.abs(refine.minv_t(f, np.eye(n)))
     b3 = n * U64 * np.linalg.norm(mt @ (np.abs(f.au).T @ np.abs(v))) / np.linalg.norm(r3)
-    log(f"[apply-t] n={n} rel err M^-T v {e2:.2e}  M^-T A_u^T v {e3:.2e} (bound {b3:.2e})")
-    assert e2 < 1e-11 and e3 <= b3
+    log(f"[apply-t] n={n} rel diff M^-T v {e2:.2e} (backward error / u^2 {b2 / U64:.2f})  "
+        f"M^-T A_u^T v {e3:.2e} (bound {b3:.2e})")
+    assert b2 <= 3 * n * U64 and e3 <= b3
 
 
 def _check(p, g, lam, info, lam_ref, info_ref, n, shared):
