@@ -313,6 +313,52 @@ __device__ __forceinline__ double lane_value(double v, int c) {
   return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// v summed over the lanes of each aligned group of four, as
+// ((v0 + v1) + (v2 + v3)), through DPP quad permutations (no LDS)
+__device__ __forceinline__ double quad_sum(double v) {
+  const long long b = __double_as_longlong(v);
+  // quad_perm [1,0,3,2]: the partner lane l ^ 1
+  const int lo1 = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), 0xB1, 0xf, 0xf, false);
+  const int hi1 = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xf, 0xf, false);
+  v += __longlong_as_double(((long long)(unsigned)hi1 << 32) | (unsigned)lo1);
+  const long long c = __double_as_longlong(v);
+  // quad_perm [2,3,0,1]: the partner lane l ^ 2
+  const int lo2 = __builtin_amdgcn_update_dpp(0, (int)(c & 0xFFFFFFFFll), 0x4E, 0xf, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, (int)(c >> 32), 0x4E, 0xf, 0xf, false);
+  return v + __longlong_as_double(((long long)(unsigned)hi2 << 32) | (unsigned)lo2);
+}
+
+// One wave fetches the 128 published values of rows base .. base + 127
+// (lane l: rows base + l and base + 64 + l).  Wave-uniform; false on abort.
+__device__ __forceinline__ bool get_tagged_block(const uint64_t* xw, int base, uint32_t tag,
+                                                 double& v0, double& v1, int* abortp) {
+  const int lane = threadIdx.x % kWave;
+  const uint64_t* p0 = xw + 2 * (base + lane);
+  const uint64_t* p1 = xw + 2 * (base + kWave + lane);
+  long long spins = 0;
+  for (;;) {
+    const uint64_t a0 = __hip_atomic_load(p0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t a1 = __hip_atomic_load(p0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t a2 = __hip_atomic_load(p1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t a3 = __hip_atomic_load(p1 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool ok = (uint32_t)(a0 >> 32) == tag && (uint32_t)(a1 >> 32) == tag &&
+                    (uint32_t)(a2 >> 32) == tag && (uint32_t)(a3 >> 32) == tag;
+    if (__all(ok)) {
+      v0 = __longlong_as_double((long long)((a1 << 32) | (a0 & 0xFFFFFFFFull)));
+      v1 = __longlong_as_double((long long)((a3 << 32) | (a2 & 0xFFFFFFFFull)));
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if (((++spins) & 1023) == 0) {
+      if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if (spins > (1ll << 22)) {
+        __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+  }
+}
+
 template <class F, bool kUpper>
 __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __restrict__ S,
                                                      int64_t ld, const int* __restrict__ permS,
@@ -326,8 +372,11 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   if (gated_off(gate, step)) return;
   __shared__ double red[8][kTB];
   __shared__ double ysh[8][kTB];
-  __shared__ double zsh[kTS];
-  __shared__ double part[4][kTS];
+  // vectors read by quarters: quarter q at q * kQS (padded so that the four
+  // quarters a lane quad reads fall in different LDS banks)
+  constexpr int kQS = kTS / 4 + 2;
+  __shared__ double zsh[4 * kQS];
+  __shared__ double yadj[4 * kQS];
   __shared__ int wok[8];
   const int nb = (n + kTS - 1) / kTS;
   const int nt = (n + kTB - 1) / kTB;  // 64-column tiles
@@ -346,10 +395,11 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   // through its precomputed product with the inverse diagonal block
   const bool hasAdj = kUpper ? blk < nb - 1 : blk > 0;
   const int adj = kUpper ? blk + 1 : blk - 1;
-  // this thread's quarter of its row of the inverse diagonal block, and of
-  // the same row of the adjacent product
-  const int di = tid % kTS;
-  const int dq4 = tid / kTS;
+  // the products with the inverse diagonal block and the neighbour's
+  // product: wave w takes rows 16 w .. 16 w + 15, lane l the quarter l % 4
+  // of row 16 w + l / 4, so a row's four partial sums sit in one lane quad
+  const int di = wave * 16 + lane / 4;
+  const int dq4 = lane % 4;
   double dq[kTS / 4], mq[kTS / 4];
   {
     const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
@@ -409,36 +459,47 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   if (tid < kTS) {
     const int h = tid / kTB, l = tid % kTB;
     const double sum = (red[4 * h][l] + red[4 * h + 1][l]) + (red[4 * h + 2][l] + red[4 * h + 3][l]);
-    zsh[tid] = (r0 + tid < n) ? rhs - sum : 0.0;
+    zsh[(tid / (kTS / 4)) * kQS + tid % (kTS / 4)] = (r0 + tid < n) ? rhs - sum : 0.0;
   }
   __syncthreads();
   // Dinv (in - sum over the far blocks) - P (neighbour's values), this
-  // thread's quarter of its row
-  double p = 0.0;
+  // thread's quarter of its row, in four interleaved partial sums
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+  {
+    const double* z = zsh + dq4 * kQS;
 #pragma unroll
-  for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[dq4 * (kTS / 4) + c], p);
-  if (hasAdj) {
-    // the 32 neighbouring values this quarter multiplies: lanes c and c + 32
-    // both read row dq4 * 32 + c of the neighbour
-    double ya;
-    const bool got = get_tagged_row(xw, adj * kTS + dq4 * (kTS / 4) + (lane & 31), epoch, ya,
-                                    abortp);
-    if (got) {
-#pragma unroll
-      for (int c = 0; c < kTS / 4; ++c) p = fma(-mq[c], lane_value(ya, c), p);
+    for (int c = 0; c < kTS / 4; c += 4) {
+      p0 = fma(dq[c], z[c], p0);
+      p1 = fma(dq[c + 1], z[c + 1], p1);
+      p2 = fma(dq[c + 2], z[c + 2], p2);
+      p3 = fma(dq[c + 3], z[c + 3], p3);
     }
-    if (lane == 0) wok[wave] = got ? 1 : 0;
   }
-  part[dq4][di] = p;
-  __syncthreads();
   if (hasAdj) {
+    // wave 0 fetches the neighbour's 128 values for all
+    if (wave == 0) {
+      double ya0 = 0.0, ya1 = 0.0;
+      const bool got = get_tagged_block(xw, adj * kTS, epoch, ya0, ya1, abortp);
+      // rows lane and 64 + lane: quarters lane / 32 and 2 + lane / 32
+      yadj[(lane / 32) * kQS + lane % 32] = ya0;
+      yadj[(2 + lane / 32) * kQS + lane % 32] = ya1;
+      if (lane == 0) wok[0] = got ? 1 : 0;
+    }
+    __syncthreads();
+    if (!wok[0]) return;
+    const double* ya = yadj + dq4 * kQS;
 #pragma unroll
-    for (int w = 0; w < 8; ++w) allok &= wok[w];
-    if (!allok) return;
+    for (int c = 0; c < kTS / 4; c += 4) {
+      p0 = fma(-mq[c], ya[c], p0);
+      p1 = fma(-mq[c + 1], ya[c + 1], p1);
+      p2 = fma(-mq[c + 2], ya[c + 2], p2);
+      p3 = fma(-mq[c + 3], ya[c + 3], p3);
+    }
   }
-  if (tid >= kTS) return;
-  const int rr = r0 + tid;
-  const double v = (rr < n) ? (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]) : 0.0;
+  const double p = quad_sum((p0 + p1) + (p2 + p3));
+  if (dq4 != 0) return;
+  const int rr = r0 + di;
+  const double v = (rr < n) ? p : 0.0;
   if (rr < n) {
     y[rr] = v;
     if (out64) out64[rr] = v * scale;
