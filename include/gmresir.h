@@ -284,6 +284,44 @@ typedef struct {
 int gmresir_kernel_stats(gmresir_ctx* h, gmresir_kernel_stat* out, int32_t cap,
                          int32_t* count);
 
+/* One system of a batch (host struct; A, b, x are device pointers).
+ *   A     n x n row-major fp64, leading dimension lda >= n.
+ *   b, x  nrhs right-hand sides and solutions, column j at b + j * ldb and
+ *         x + j * ldb (ldb >= n); x is written.
+ *   info  host array of nrhs records, one per right-hand side (as
+ *         gmresir_solve fills them), or NULL.
+ *   status  out: the system's outcome -- the first nonzero gmresir_status
+ *         of its factorisation and its right-hand sides in order (a negative
+ *         one stops the system), else 0. */
+typedef struct {
+  const double* A;
+  int64_t n;
+  int64_t lda;
+  const double* b;
+  double* x;
+  int64_t nrhs;
+  int64_t ldb;
+  gmresir_info* info;
+  int32_t status;
+  int32_t reserved;
+} gmresir_batch_item;
+
+/* Batched solves (the batching extension of the method: many independent
+ * systems of uneven n, each with its own right-hand sides).  Every system is
+ * factored and solved exactly as by gmresir_factor + gmresir_solve with
+ * `opts` (Algorithm 3; Algorithm 2 for k = 0), so its result does not depend
+ * on the batch.  `workers` host threads (<= 0: 8; at most 64), each with a
+ * HIP stream of its own, take the systems largest first and keep several in
+ * flight on the current device.
+ *   stream  hipStream_t or NULL: work queued on it (producing A and b) is
+ *           finished before any system is read.
+ * Blocks until every system is done and its device memory released.
+ * Returns 0 when no system reports a negative status; otherwise the first
+ * negative status in item order (EINVAL also for invalid items: null
+ * pointers, n <= 0, lda < n, nrhs <= 0, ldb < n -- then nothing runs). */
+int gmresir_solve_batched(gmresir_batch_item* items, int64_t count,
+                          const gmresir_opts* opts, int32_t workers, void* stream);
+
 /* Size n and ABI version of a handle (either pointer may be NULL). */
 int gmresir_query(gmresir_ctx* h, int64_t* n, int32_t* abi_version);
 

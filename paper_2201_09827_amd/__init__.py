@@ -27,6 +27,7 @@ __all__ = [
     "EXPORTED",
     "KERNEL_CLASSES",
     "rank1",
+    "solve_batched",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,7 +45,7 @@ EXPORTED = (
     "gmresir_default_opts", "gmresir_factor", "gmresir_solve", "gmresir_free",
     "gmresir_strerror", "gmresir_last_error", "gmresir_import_factors",
     "gmresir_export_factors", "gmresir_apply", "gmresir_kernel_stats", "gmresir_query",
-    "gmresir_solve_transposed", "gmresir_rank1", "gmresir_choose_k",
+    "gmresir_solve_transposed", "gmresir_rank1", "gmresir_choose_k", "gmresir_solve_batched",
 )
 
 
@@ -99,6 +100,21 @@ class GmresirError(RuntimeError):
         self.status = status
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("A", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("lda", ctypes.c_int64),
+        ("b", ctypes.c_void_p),
+        ("x", ctypes.c_void_p),
+        ("nrhs", ctypes.c_int64),
+        ("ldb", ctypes.c_int64),
+        ("info", ctypes.c_void_p),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 _LIB = None
 
 
@@ -145,6 +161,9 @@ def load_library() -> ctypes.CDLL:
     lib.gmresir_rank1.restype = ctypes.c_int
     lib.gmresir_choose_k.argtypes = [vp, vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp]
     lib.gmresir_choose_k.restype = ctypes.c_int
+    lib.gmresir_solve_batched.argtypes = [ctypes.POINTER(BatchItem), i64, ctypes.POINTER(Opts),
+                                          i32, vp]
+    lib.gmresir_solve_batched.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -393,3 +412,44 @@ def rank1(alpha: float, x, y, out=None, stream=None):
     if rc != 0:
         raise _err(lib, rc)
     return out
+
+
+def solve_batched(systems, workers: int = 8, stream=None, **opts):
+    """Factor and solve many independent systems (uneven n, each with its own
+    right-hand sides) with the same options, several at once on worker
+    streams.  ``systems``: sequence of (A, B) with A a square row-major float64
+    CUDA tensor and B its right-hand sides, (n,) or the transpose of a
+    contiguous (nrhs, n) tensor.  Returns a list of (X, infos, status) in the
+    order given: X shaped like B, infos one dict per right-hand side, status
+    the system's gmresir_status (ESINGULAR / ERANGE / ENOCONV are outcomes, not
+    errors).  Raises GmresirError on a negative return."""
+    import torch
+    lib = load_library()
+    o = _opts(**opts)
+    items = (BatchItem * len(systems))()
+    keep = []
+    for i, (a, b) in enumerate(systems):
+        _check_matrix(a)
+        n = a.shape[0]
+        if not (isinstance(b, torch.Tensor) and b.is_cuda and b.dtype == torch.float64):
+            raise ValueError("b must be a float64 CUDA tensor")
+        if b.dim() == 1:
+            if b.shape[0] != n or b.stride(0) != 1:
+                raise ValueError("b has the wrong length or stride")
+            nrhs = 1
+            x = torch.empty_like(b)
+        else:
+            if b.shape[0] != n or not b.t().is_contiguous():
+                raise ValueError("2-D b must be the transpose of a contiguous (nrhs, n) tensor")
+            nrhs = b.shape[1]
+            x = torch.empty((nrhs, n), dtype=torch.float64, device=b.device).t()
+        infos = (Info * nrhs)()
+        keep.append((x, infos, nrhs))
+        items[i] = BatchItem(a.data_ptr(), n, a.stride(0), b.data_ptr(), x.data_ptr(), nrhs, n,
+                             ctypes.cast(infos, ctypes.c_void_p), 0, 0)
+    rc = lib.gmresir_solve_batched(items, len(systems), ctypes.byref(o), int(workers),
+                                   _stream(stream))
+    if rc < 0:
+        raise _err(lib, rc)
+    return [(x, [_info_dict(infos[j]) for j in range(nrhs)], int(items[i].status))
+            for i, (x, infos, nrhs) in enumerate(keep)]

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgmresir.so")
 
-SOURCES = ["kernels_lu.hip", "kernels_solve.hip", "kernels_dd.hip", "host_la.cpp", "solver.cpp"]
+SOURCES = ["kernels_lu.hip", "kernels_solve.hip", "kernels_dd.hip", "host_la.cpp", "solver.cpp",
+           "batch.cpp"]
 
 ARCH = os.environ.get("GMRESIR_OFFLOAD_ARCH", "gfx950")
 
@@ -56,7 +57,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

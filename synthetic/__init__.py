@@ -190,3 +190,35 @@ def prolate_problem_torch(n: int, w: float, seed: int, device="cuda"):
     x = torch.from_numpy(normal_vector(n, generator(seed))).to(device)
     b = a @ x
     return a, x, b
+
+
+def batch_specs(count: int, seed: int, n_range=(128, 2048), log10_kappa=(1.0, 8.0),
+                nrhs_range=(1, 8)):
+    """Specifications of a batch of independent randsvd systems of uneven
+    size: n uniform on the integers of ``n_range``, log10 kappa_2 uniform on
+    ``log10_kappa``, the number of right-hand sides uniform on the integers of
+    ``nrhs_range``.  Returns a list of dicts (n, kappa, nrhs, seed) with one
+    derived seed per system."""
+    g = generator(seed)
+    out = []
+    for i in range(count):
+        n = int(g.integers(n_range[0], n_range[1] + 1))
+        kappa = float(10.0 ** g.uniform(*log10_kappa))
+        nrhs = int(g.integers(nrhs_range[0], nrhs_range[1] + 1))
+        out.append({"n": n, "kappa": kappa, "nrhs": nrhs, "seed": int(seed) * 100003 + i})
+    return out
+
+
+def batch_system_torch(spec: dict, device="cuda"):
+    """One system of :func:`batch_specs` on ``device``: A from
+    :func:`randsvd_problem_torch`, then ``nrhs`` solutions X ~ U(-1, 1) and
+    B = A X in float64.  Returns (a, x_true, b) with x_true and b shaped
+    (n, nrhs) as transposes of contiguous (nrhs, n) tensors."""
+    import torch
+    n, nrhs = spec["n"], spec["nrhs"]
+    a, _, _ = randsvd_problem_torch(n, spec["kappa"], spec["seed"], device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(spec["seed"]) + 1)
+    x = torch.rand((nrhs, n), generator=gen, dtype=torch.float64, device=device) * 2.0 - 1.0
+    b = (x @ a.T).contiguous()
+    return a, x.t(), b.t()

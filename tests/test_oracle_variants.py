@@ -78,3 +78,19 @@ def test_uniform_refinement_converges():
 def test_uniform_rejected_for_fp32_working_precision():
     with pytest.raises(ValueError):
         Options(uf="fp16", u="fp32", ur="fp64", matvec="u").validate()
+
+
+def test_batch_specs_follow_the_stated_distribution():
+    """The uneven batch's specifications: sizes, conditioning and right-hand
+    side counts inside their ranges, reproducible from the seed, and spread
+    over the ranges (512 draws)."""
+    from synthetic import batch_specs
+    sp = batch_specs(512, 1)
+    assert sp == batch_specs(512, 1)
+    ns = np.array([d["n"] for d in sp])
+    ks = np.log10([d["kappa"] for d in sp])
+    rs = np.array([d["nrhs"] for d in sp])
+    assert ns.min() >= 128 and ns.max() <= 2048 and ks.min() >= 1 and ks.max() <= 8
+    assert rs.min() >= 1 and rs.max() <= 8 and set(rs) == set(range(1, 9))
+    assert abs(np.mean(ns) - 1088) < 60 and abs(np.mean(ks) - 4.5) < 0.25
+    assert len({d["seed"] for d in sp}) == 512
