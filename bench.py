@@ -79,6 +79,11 @@ def parse():
                     help="also report the outcome of the ill-conditioned Toeplitz system "
                          "(prolate w = 0.48, n = 16384, m = 50, k = 20 and 0) at "
                          "(bf16, fp32, fp64) and (fp32, fp64, double-double); about 2 minutes")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="also time this many systems of the uneven batch (n ~ U[128, 2048], "
+                         "kappa2 log-uniform in [1e1, 1e8], 1-8 right-hand sides; 512 take "
+                         "about 3 minutes) through gmresir_solve_batched")
+    ap.add_argument("--batched-workers", type=int, default=8)
     ap.add_argument("--cpu-n", type=int, default=6144, help="order of the oracle sample")
     ap.add_argument("--gen", choices=("gpu", "cpu"), default="gpu",
                     help="draw the system on the GPU (torch) or on the CPU (numpy, slower)")
@@ -142,6 +147,74 @@ def cpu_baseline(n_sample: int, n_target: int, kappa: float, seed: int, m: int, 
                    f"scaled to n={n_target} by (n/{n_sample})^3 for the factor and "
                    f"(n/{n_sample})^2 for the solve"),
     }
+
+
+def batched_bench(g, count: int, workers: int, oracle: bool):
+    """The uneven batch through gmresir_solve_batched (m = 30, k = 10, at most
+    300 Arnoldi steps per correction), the first 16 systems also one at a
+    time, and the oracle on the batch's first systems (about 20 s)."""
+    import torch
+    from synthetic import batch_specs, batch_system_torch
+    specs = batch_specs(count, 1)
+    systems = []
+    for sp in specs:
+        a, _, b = batch_system_torch(sp)
+        systems.append((a, b))
+    torch.cuda.synchronize()
+    log(f"batched: {count} systems generated on the GPU")
+    opts = dict(m=30, k=10, maxit=300)
+    t = time.perf_counter()
+    out = g.solve_batched(systems, workers=workers, **opts)
+    dt = time.perf_counter() - t
+    nrhs = sum(len(o[1]) for o in out)
+    conv = sum(1 for o in out for i in o[1] if i["status"] == 0)
+    st = [o[2] for o in out]
+    first = systems[:16]
+    t = time.perf_counter()
+    g.solve_batched(first, workers=1, **opts)
+    d1 = time.perf_counter() - t
+    t = time.perf_counter()
+    g.solve_batched(first, workers=workers, **opts)
+    dw = time.perf_counter() - t
+    rec = {"systems": count, "rhs": nrhs, "workers": workers, "seconds": dt,
+           "systems_per_s": count / dt, "rhs_per_s": nrhs / dt, "converged_rhs": conv,
+           "status_counts": {name: st.count(c) for c, name in
+                             ((0, "OK"), (1, "ESINGULAR"), (2, "ERANGE"), (3, "ENOCONV"))},
+           "first16_one_at_a_time_s": d1, "first16_batched_s": dw,
+           "sum_n3_flop": float(sum(2.0 * sp["n"] ** 3 / 3.0 for sp in specs)),
+           "sum_a_bytes": float(sum(8.0 * sp["n"] ** 2 for sp in specs))}
+    log(f"batched: {count} systems ({nrhs} right-hand sides) in {dt:.1f} s = "
+        f"{count / dt:.2f} systems/s, {conv} right-hand sides converged; first 16: "
+        f"{d1:.1f} s one at a time, {dw:.1f} s batched")
+    del systems
+    if oracle:
+        from oracle import refine
+        from synthetic import randsvd_problem
+        import numpy as np
+        o = refine.Options(uf="fp16", u="fp32", ur="fp64", m=30, k=10, tau=1e-4, imax=10,
+                           maxit=300, berr_target=1e-14, nb=64)
+        # factorisations and right-hand sides in batch order until 20 s have
+        # passed; compared per right-hand side (a system's factorisation is
+        # charged to its first one)
+        t = time.perf_counter()
+        rhs = 0
+        for sp in specs:
+            p = randsvd_problem(sp["n"], sp["kappa"], sp["seed"])
+            f = refine.factor(p.a, o)
+            gen = np.random.default_rng(sp["seed"])
+            for _ in range(sp["nrhs"]):
+                refine.solve(f, p.a @ gen.uniform(-1, 1, sp["n"]))
+                rhs += 1
+                if time.perf_counter() - t > 20.0:
+                    break
+            if time.perf_counter() - t > 20.0:
+                break
+        el = time.perf_counter() - t
+        rec["cpu_oracle"] = {"value": rhs / el, "unit": "rhs/s", "kind": "oracle",
+                             "sample": f"the batch's first {rhs} right-hand sides in order "
+                                       f"(systems drawn with numpy), {el:.1f} s"}
+        log(f"batched oracle: {rhs} right-hand sides in {el:.1f} s")
+    return rec
 
 
 def main():
@@ -356,6 +429,10 @@ def main():
                     f"in {rec['seconds']:.1f} s")
         del a3, xt3, b3
 
+    batched = None
+    if args.batched > 0:
+        batched = batched_bench(g, args.batched, args.batched_workers, not args.no_cpu_baseline)
+
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()
@@ -394,6 +471,7 @@ def main():
             "outcomes_prolate16k": prolate or None,
             "gradient": adjoint,
             "reuse_recycle": reuse,
+            "batched": batched,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
