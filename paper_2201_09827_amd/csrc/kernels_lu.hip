@@ -481,61 +481,87 @@ __global__ __launch_bounds__(kRowThreads) void k_panel(typename F::T* __restrict
 
 // U12 = L11^-1 A12 in fp32 with the stored (u_f) unit lower triangle L11
 // (the block column is always 64 wide here: a narrower one is the last and
-// has nothing to its right).  One thread per column keeps the column's 64
-// values in registers; L11 is staged transposed in LDS and read as broadcast
-// vectors.  Step t updates rows r > t with one fused multiply-add each, so
-// every entry receives its terms in the order t = 0, 1, ... of forward
-// substitution.
+// has nothing to its right).  Four lanes share a column: lane p of a quad
+// keeps rows 4 i + p (i < 16) in registers, and at step t the quad's owner of
+// row t hands y_t to the other three by a DPP quad broadcast.  L11 is staged
+// in LDS by row class (Lq[t][p][i] = L11[4 i + p][t]) and read as 16-byte
+// broadcast vectors.  Step t updates rows r > t with one fused multiply-add
+// each, so every entry receives its terms in the order t = 0, 1, ... of
+// forward substitution.
 constexpr int kTrsmThreads = 64;
+constexpr int kTrsmCols = kTrsmThreads / 4;  // columns per workgroup
+constexpr int kTrsmLq = 20;                   // padded row class (floats): no bank conflicts
+
+template <int P>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), P * 0x55, 0xf, 0xf, false));
+}
+
 template <class F>
 __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict__ S, int64_t ld,
                                                        const int* __restrict__ perm, int k0,
                                                        int c_begin, int c_end) {
-  __shared__ __align__(16) float Lt[kMaxNb][kMaxNb];  // Lt[t][r] = L11[r][t]
+  __shared__ __align__(16) float Lq[kMaxNb][4][kTrsmLq];
   __shared__ int prow[kMaxNb];
   const int tid = threadIdx.x;
-  const int64_t c = (int64_t)c_begin + (int64_t)blockIdx.x * kTrsmThreads + tid;
+  const int p = tid & 3;
+  const int64_t c = (int64_t)c_begin + (int64_t)blockIdx.x * kTrsmCols + (tid >> 2);
   prow[tid] = perm[k0 + tid];
   __syncthreads();
-  // this thread's column of the block row: its loads are issued together with
-  // those of the L11 row below (one memory round trip for both); a thread
-  // beyond c_end reads a valid column and discards it
+  // this lane's rows of its column, loaded together with the L11 row below
+  // (one memory round trip for both); a lane beyond c_end reads a valid
+  // column and discards it
   const int64_t cc = c < c_end ? c : (int64_t)c_begin;
-  typename F::T yraw[kMaxNb];
+  typename F::T yraw[kMaxNb / 4];
 #pragma unroll
-  for (int t = 0; t < kMaxNb; ++t) yraw[t] = S[(int64_t)prow[t] * ld + cc];
+  for (int i = 0; i < kMaxNb / 4; ++i) yraw[i] = S[(int64_t)prow[4 * i + p] * ld + cc];
   {
-    // row r = tid of L11 in 16-byte pieces (all loads in flight at once),
-    // written transposed; entries on and above the diagonal are zero
+    // row r = tid of L11 in 16-byte pieces, written by row class; entries on
+    // and above the diagonal are never read
     float lrow[kMaxNb];
     load_panel_row<F>(S + (int64_t)prow[tid] * ld + k0, kMaxNb, true, lrow);
 #pragma unroll
-    for (int t = 0; t < kMaxNb; ++t) Lt[t][tid] = (tid > t) ? lrow[t] : 0.0f;
+    for (int t = 0; t < kMaxNb; ++t) Lq[t][tid & 3][tid >> 2] = lrow[t];
   }
   __syncthreads();
-  if (c >= c_end) return;
-  float y[kMaxNb];
+  if (c >= c_end) return;  // whole quads: the four lanes of a column leave together
+  float y[kMaxNb / 4];
 #pragma unroll
-  for (int t = 0; t < kMaxNb; ++t) y[t] = F::to_f(yraw[t]);
+  for (int i = 0; i < kMaxNb / 4; ++i) y[i] = F::to_f(yraw[i]);
 #pragma unroll
-  for (int t = 0; t < kMaxNb; ++t) asm volatile("" : "+v"(y[t]));
-#pragma unroll
-  for (int t = 0; t < kMaxNb - 1; ++t) {
-#pragma unroll
-    for (int r = ((t + 1) & ~3); r < kMaxNb; r += 4) {
-      const float4 lv = *reinterpret_cast<const float4*>(&Lt[t][r]);
-      if (r > t) y[r] = __builtin_fmaf(-lv.x, y[t], y[r]);
-      if (r + 1 > t) y[r + 1] = __builtin_fmaf(-lv.y, y[t], y[r + 1]);
-      if (r + 2 > t) y[r + 2] = __builtin_fmaf(-lv.z, y[t], y[r + 2]);
-      if (r + 3 > t) y[r + 3] = __builtin_fmaf(-lv.w, y[t], y[r + 3]);
-    }
+  for (int i = 0; i < kMaxNb / 4; ++i) asm volatile("" : "+v"(y[i]));
+#define GIR_TRSM_STEP(T)                                                                  \
+  {                                                                                       \
+    constexpr int ti = (T) >> 2, tp = (T) & 3;                                            \
+    const float yt = quad_bcast<tp>(y[ti]);                                               \
+    const float* lq = &Lq[T][p][0];                                                       \
+    _Pragma("unroll") for (int j = ti & ~3; j < kMaxNb / 4; j += 4) {                     \
+      const float4 lv = *reinterpret_cast<const float4*>(lq + j);                         \
+      const float l4[4] = {lv.x, lv.y, lv.z, lv.w};                                       \
+      _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                     \
+        const int i = j + e;                                                              \
+        if (i > ti)                                                                       \
+          y[i] = __builtin_fmaf(-l4[e], yt, y[i]);                                        \
+        else if (i == ti)                                                                 \
+          y[i] = (p > tp) ? __builtin_fmaf(-l4[e], yt, y[i]) : y[i];                      \
+      }                                                                                   \
+    }                                                                                     \
   }
+#define GIR_TRSM_STEP4(T) GIR_TRSM_STEP(T) GIR_TRSM_STEP(T + 1) GIR_TRSM_STEP(T + 2) GIR_TRSM_STEP(T + 3)
+  GIR_TRSM_STEP4(0) GIR_TRSM_STEP4(4) GIR_TRSM_STEP4(8) GIR_TRSM_STEP4(12)
+  GIR_TRSM_STEP4(16) GIR_TRSM_STEP4(20) GIR_TRSM_STEP4(24) GIR_TRSM_STEP4(28)
+  GIR_TRSM_STEP4(32) GIR_TRSM_STEP4(36) GIR_TRSM_STEP4(40) GIR_TRSM_STEP4(44)
+  GIR_TRSM_STEP4(48) GIR_TRSM_STEP4(52) GIR_TRSM_STEP4(56) GIR_TRSM_STEP(60)
+  GIR_TRSM_STEP(61) GIR_TRSM_STEP(62)
+#undef GIR_TRSM_STEP4
+#undef GIR_TRSM_STEP
   // the fp32 result is rounded to u_f in a separate step (an fma fused with
   // the narrowing conversion would round only once)
 #pragma unroll
-  for (int t = 0; t < kMaxNb; ++t) asm volatile("" : "+v"(y[t]));
+  for (int i = 0; i < kMaxNb / 4; ++i) asm volatile("" : "+v"(y[i]));
 #pragma unroll
-  for (int t = 0; t < kMaxNb; ++t) S[(int64_t)prow[t] * ld + c] = F::from_f(y[t]);
+  for (int i = 0; i < kMaxNb / 4; ++i) S[(int64_t)prow[4 * i + p] * ld + c] = F::from_f(y[i]);
 }
 
 // ---- trailing update on the matrix cores ----------------------------------
@@ -809,7 +835,7 @@ template <class F>
 void trsm_t(const PanelArgs& a, int c_begin, int c_end, hipStream_t s) {
   using T = typename F::T;
   if (c_end <= c_begin) return;  // kb == 64 whenever a column lies right of the panel
-  hipLaunchKernelGGL(k_trsm<F>, dim3((c_end - c_begin + kTrsmThreads - 1) / kTrsmThreads),
+  hipLaunchKernelGGL(k_trsm<F>, dim3((c_end - c_begin + kTrsmCols - 1) / kTrsmCols),
                      dim3(kTrsmThreads), 0, s, reinterpret_cast<T*>(a.S), a.ld, a.perm, a.k0,
                      c_begin, c_end);
 }
