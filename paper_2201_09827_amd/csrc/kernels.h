@@ -150,7 +150,8 @@ void launch_combine(const Basis& X, int n, const double* M, int nout, double* ou
 // part skipped when its vector is null
 void launch_cycle_update(const Basis& Xd, const double* cd, void* d, const Basis& Xr,
                          const double* cr, void* r, int n, int v64, hipStream_t s);
-// G (nx x ny, col-major) = X^T Y for fp64 Y (n x ny, ld ldy)
+// G (nx x ny, col-major) = X^T Y for fp64 Y (n x ny, ld ldy); nx <= 192,
+// ny <= 96 (m <= 95, k < m)
 void launch_gram(const Basis& X, const double* Y, int ny, int64_t ldy, int n, double* G,
                  double* partial, unsigned int* counter, hipStream_t s);
 // out = fl_u(r / s), held in fp64 (u = fp32, or fp64 when v64)

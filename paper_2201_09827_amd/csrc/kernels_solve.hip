@@ -934,6 +934,26 @@ __global__ __launch_bounds__(64) void k_diag_inverse(const typename F::T* __rest
   }
 }
 
+// fp64 sum over the 64 lanes of a wave by DPP row shifts and row broadcasts
+// (no LDS); the total lands in lane 63 (other lanes hold partial sums).  The
+// tree is fixed, so the result does not depend on timing.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), Ctrl, RowMask, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, RowMask, 0xf, false);
+  return v + __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_to63(double v) {
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8: lane 15 of each row holds the row's sum
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // orthogonalisation passes (CGS2) with last-block reduction
 // ---------------------------------------------------------------------------
@@ -958,6 +978,7 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   __shared__ double wsh[kRowsPerBlock];
   __shared__ double red[4][kWave + 1];
   __shared__ double coef_sh[256];
+  __shared__ double colsum[4][256];
   __shared__ unsigned int s_ticket;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
@@ -983,22 +1004,27 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   const int nout = ncol + 1;  // dots then the squared norm
   double* part = a.partial + (int64_t)blockIdx.x * nout;
   if (mode & kOrthoDots) {
-    for (int cg = 0; cg < ncol; cg += kWave) {
-      const int c = cg + lane;
-      double acc = 0.0;
-      if (c < ncol) {
-        const int r0 = wave * kWave;
-#pragma unroll 8
-        for (int r = 0; r < kWave; ++r) {
-          const int rr = rbase + r0 + r;
-          if (rr < a.n) acc = fma(basis_at<VT>(a.X, c, rr), wsh[r0 + r], acc);
-        }
+    // lane = row: each column is read coalesced, multiplied by this row's w
+    // and summed over the wave's 64 rows by DPP, four columns at a time; the
+    // four waves' sums are added through LDS
+    for (int c0 = 0; c0 < ncol; c0 += 4) {
+      double pr[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = c0 + e;
+        pr[e] = (valid && c < ncol) ? basis_at<VT>(a.X, c, row) * wv : 0.0;
       }
-      red[wave][lane] = acc;
-      __syncthreads();
-      if (wave == 0 && c < ncol) part[c] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pr[e] = wave_sum_to63(pr[e]);
+      if (lane == kWave - 1) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (c0 + e < ncol) colsum[wave][c0 + e] = pr[e];
+      }
     }
+    __syncthreads();
+    for (int c = tid; c < ncol; c += 256)
+      part[c] = (colsum[0][c] + colsum[1][c]) + (colsum[2][c] + colsum[3][c]);
   }
   if (mode & kOrthoNorm) {
     double sq = wave_sum(wv * wv);
@@ -1117,40 +1143,60 @@ __global__ __launch_bounds__(256) void k_cycle_update(Basis Xd, const double* __
 }
 
 // G[o * nx + c] = sum_rows X[row, c] Y[row, o]
+// G = X^T Y (nx x ny, column o of Y against column c of X at G[o * nx + c])
+// in fp64 (nx <= 192, ny <= 96: m <= 95 and k < m).  Each workgroup takes
+// 256 rows in chunks of 32, staged in LDS with coalesced loads; thread t
+// accumulates outputs t, t + 256, ... over its rows; the last workgroup adds
+// the per-workgroup sums in order.
+constexpr int kGramRows = 32;
+constexpr int kGramQ = 8;
+constexpr int kGramMaxX = 192;
+constexpr int kGramMaxY = 96;
 template <typename VT>
 __global__ __launch_bounds__(256) void k_gram(Basis X, const double* __restrict__ Y, int ny,
                                               int64_t ldy, int n, double* __restrict__ G,
                                               double* __restrict__ partial,
                                               unsigned int* counter) {
-  __shared__ double ysh[kRowsPerBlock];
-  __shared__ double red[4][kWave + 1];
+  __shared__ double xs[kGramRows][kGramMaxX + 1];
+  __shared__ double ys[kGramRows][kGramMaxY + 1];
   __shared__ unsigned int s_ticket;
   const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
   const int nx = X.kc + X.nv;
   const int rbase = blockIdx.x * kRowsPerBlock;
   const int nout = nx * ny;
   double* part = partial + (int64_t)blockIdx.x * nout;
-  for (int o = 0; o < ny; ++o) {
-    const int row = rbase + tid;
-    ysh[tid] = (row < n) ? Y[(int64_t)o * ldy + row] : 0.0;
-    __syncthreads();
-    for (int cg = 0; cg < nx; cg += kWave) {
-      const int c = cg + lane;
-      double acc = 0.0;
-      if (c < nx) {
-        const int r0 = wave * kWave;
-        for (int r = 0; r < kWave; ++r) {
-          const int rr = rbase + r0 + r;
-          if (rr < n) acc = fma(basis_at<VT>(X, c, rr), ysh[r0 + r], acc);
+  // outputs in groups of 256 kGramQ (one group for the usual sizes)
+  for (int g0 = 0; g0 < nout; g0 += 256 * kGramQ) {
+    double acc[kGramQ];
+#pragma unroll
+    for (int q = 0; q < kGramQ; ++q) acc[q] = 0.0;
+    for (int r0 = rbase; r0 < rbase + kRowsPerBlock; r0 += kGramRows) {
+      for (int idx = tid; idx < kGramRows * nx; idx += 256) {
+        const int r = idx % kGramRows, c = idx / kGramRows;
+        xs[r][c] = (r0 + r < n) ? basis_at<VT>(X, c, r0 + r) : 0.0;
+      }
+      for (int idx = tid; idx < kGramRows * ny; idx += 256) {
+        const int r = idx % kGramRows, o = idx / kGramRows;
+        ys[r][o] = (r0 + r < n) ? Y[(int64_t)o * ldy + r0 + r] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kGramQ; ++q) {
+        const int idx = g0 + tid + 256 * q;
+        if (idx < nout) {
+          const int c = idx % nx, o = idx / nx;
+          double sacc = acc[q];
+#pragma unroll 8
+          for (int r = 0; r < kGramRows; ++r) sacc = fma(xs[r][c], ys[r][o], sacc);
+          acc[q] = sacc;
         }
       }
-      red[wave][lane] = acc;
       __syncthreads();
-      if (wave == 0 && c < nx)
-        part[o * nx + c] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kGramQ; ++q) {
+      const int idx = g0 + tid + 256 * q;
+      if (idx < nout) part[idx] = acc[q];
     }
   }
   __threadfence();
@@ -1160,9 +1206,9 @@ __global__ __launch_bounds__(256) void k_gram(Basis X, const double* __restrict_
   if (s_ticket != gridDim.x - 1) return;
   __threadfence();
   for (int c = tid; c < nout; c += 256) {
-    double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += partial[(int64_t)b * nout + c];
-    G[c] = s;
+    double sum = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) sum += partial[(int64_t)b * nout + c];
+    G[c] = sum;
   }
   if (tid == 0) *counter = 0u;
 }

@@ -405,10 +405,13 @@ int alloc_solve(gmresir_ctx* h) {
   GIR_TRY(dalloc(h->arena, &h->nrm, 4));
   GIR_TRY(dalloc(h->arena, &h->coefA, 256));
   GIR_TRY(dalloc(h->arena, &h->coefB, 256));
-  GIR_TRY(dalloc(h->arena, &h->Mdev, 4096));
-  GIR_TRY(dalloc(h->arena, &h->Gdev, 4096));
+  // the small products of the recycle space: [C_k V] (k + m + 1 columns)
+  // against at most k + 1 columns
+  const size_t small = std::max<size_t>(4096, (size_t)(h->m + h->k + 2) * (size_t)(h->k + 2));
+  GIR_TRY(dalloc(h->arena, &h->Mdev, small));
+  GIR_TRY(dalloc(h->arena, &h->Gdev, small));
   const size_t grid = (ld + 255) / 256;
-  GIR_TRY(dalloc(h->arena, &h->partial, grid * 4096));
+  GIR_TRY(dalloc(h->arena, &h->partial, grid * small));
   // tagged words of the two solves: 2 per row in 128-row blocks (fp64), 4 per
   // row in 64-row blocks (double-double)
   const int64_t nxw =
