@@ -406,3 +406,19 @@ def test_keep_recycle_across_right_hand_sides(lib):
             assert abs(a_ - b_) <= 2
         assert info["recycle_dim"] == st.dim
     h.free()
+
+
+def test_solve_largest_recycle_dimensions_shared_factors(lib):
+    """m = 95, k = 42 (the largest m with (m + 1) k <= 4096): the small
+    products of the recycle space then have (k + m + 1) k = 5796 outputs."""
+    # first correction 179 Arnoldi steps (full cycles of 95 with the recycle
+    # refresh); counts identical with 1 and 8 BLAS threads in the oracle
+    p = randsvd_problem(300, 1e6, 1)
+    o = oracle_options(m=95, k=42)
+    x_ref, info_ref, f = _run_oracle(p, o)
+    log("[solve-shared] n=300 m=95 k=42")
+    h = lib.import_factors(_dev(p.a), _dev(encode_factors(f.lu, "fp16").view(np.int16)),
+                           f.ipiv.astype(np.int32), f.e, **lib_options(o))
+    x, info = h.solve(_dev(p.b))
+    h.free()
+    _compare(p, x_ref, info_ref, x.cpu().numpy(), info, 300)
