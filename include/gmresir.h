@@ -82,9 +82,11 @@ typedef struct {
                              preconditioner)                                  */
   int32_t keep_recycle;   /* 1: the recycled pair survives between
                              gmresir_solve calls on the same handle          */
-  int32_t timing;         /* bit c set: bracket every launch of kernel class c
-                             (the order listed at gmresir_kernel_stats) with
-                             HIP events on the stream it runs on; 0: off     */
+  int32_t timing;         /* bit c (0-7) set: bracket every launch of kernel
+                             class c (the order listed at gmresir_kernel_stats)
+                             with HIP events on the stream it runs on; bits
+                             8-15 = s > 1: only every s-th launch of each
+                             timed class (fewer events in the stream); 0: off */
   int32_t matvec_u;       /* 1: the correction solve applies M^-1 and A-tilde in
                              u instead of u^2 (SGMRES-IR / RSGMRES-IR, Section 3;
                              u = FP64 only); x0 keeps u^2.  Default 0.          */
@@ -268,7 +270,7 @@ int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y,
  * "lu_panel", "lu_trsm", "lu_gemm" (factorisation), "trsv_lower",
  * "trsv_upper", "gemv_au", "residual", "ortho" (solve phase).  Each event
  * pair costs a few microseconds of stream time, so time only the classes of
- * interest.
+ * interest, or a sample of their launches (opts.timing bits 8-15).
  *
  *   out    host array of cap records; count receives the number written.
  * Waits for the recorded events.  Returns EINVAL when timing is off.

@@ -15,8 +15,11 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gmresir.h"
@@ -88,15 +91,72 @@ int scale_exponent(double amax, int64_t n) {
   return e;
 }
 
+// Device memory released by handles is kept by the process (up to
+// kCacheBytes in all) and handed out again for requests of the same size on
+// the same device, so repeated factorisations of systems of one order call
+// neither hipMalloc nor hipFree (which waits for the whole device) after the
+// first.  Every entry point is blocking, so a released chunk has no work
+// pending on it.  The cache is never torn down: its memory returns to the
+// system when the process ends.
+constexpr size_t kCacheBytes = size_t(16) << 30;
+
+struct ChunkCache {
+  std::mutex mu;
+  std::multimap<std::pair<int, size_t>, void*> free_chunks;  // (device, bytes) -> chunk
+  size_t cached = 0;
+};
+
+ChunkCache& chunk_cache() {
+  static ChunkCache* c = new ChunkCache();  // never destroyed (see above)
+  return *c;
+}
+
+hipError_t chunk_alloc(void** p, size_t bytes, int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  *dev_out = dev;
+  {
+    ChunkCache& c = chunk_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    auto it = c.free_chunks.find({dev, bytes});
+    if (it != c.free_chunks.end()) {
+      *p = it->second;
+      c.free_chunks.erase(it);
+      c.cached -= bytes;
+      return hipSuccess;
+    }
+  }
+  return hipMalloc(p, bytes);
+}
+
+void chunk_release(void* p, size_t bytes, int dev) {
+  ChunkCache& c = chunk_cache();
+  {
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (c.cached + bytes <= kCacheBytes) {
+      c.free_chunks.emplace(std::make_pair(dev, bytes), p);
+      c.cached += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
 // Device memory of a handle: buffers above 4 MiB get their own allocation,
 // smaller ones are carved from 32 MiB chunks (256-byte aligned), so that a
-// handle costs a handful of hipMalloc / hipFree calls.
+// handle costs a handful of chunk allocations.
 struct Arena {
-  std::vector<void*> chunks;
+  struct Chunk {
+    void* p;
+    size_t bytes;
+    int dev;
+  };
+  std::vector<Chunk> chunks;
   char* cur = nullptr;
   size_t left = 0;
   ~Arena() {
-    for (void* c : chunks) (void)hipFree(c);
+    for (const Chunk& c : chunks) chunk_release(c.p, c.bytes, c.dev);
   }
 };
 
@@ -111,12 +171,13 @@ int dalloc(Arena& a, T** p, size_t count) {
   if (bytes > kOwnAllocation || bytes > a.left) {
     void* q = nullptr;
     const size_t want = bytes > kOwnAllocation ? bytes : kChunk;
-    hipError_t e = hipMalloc(&q, want);
+    int dev = 0;
+    hipError_t e = chunk_alloc(&q, want, &dev);
     if (e != hipSuccess) {
       set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
       return GMRESIR_ENOMEM;
     }
-    a.chunks.push_back(q);
+    a.chunks.push_back({q, want, dev});
     if (bytes > kOwnAllocation) {
       *p = reinterpret_cast<T*>(q);
       return 0;
@@ -233,6 +294,7 @@ struct gmresir_ctx {
   size_t tnext = 0;
   std::vector<TimedRec> trec;
   KStat kstat[kKcCount];
+  int64_t tcount[kKcCount] = {};  // launches per class (the timing stride)
 
   ~gmresir_ctx() {
     // device buffers belong to `arena` (freed by its destructor)
@@ -265,6 +327,12 @@ template <class Fn>
 int timed(gmresir_ctx* h, int cls, double work, hipStream_t s, const void* gate, int step,
           Fn&& launch) {
   if (!((h->o.timing >> cls) & 1)) {
+    launch();
+    return 0;
+  }
+  // bits 8-15: bracket only every s-th launch of the class
+  const int stride = (h->o.timing >> 8) & 0xFF;
+  if (stride > 1 && (h->tcount[cls]++ % stride) != 0) {
     launch();
     return 0;
   }
@@ -336,8 +404,9 @@ int validate_opts(const gmresir_opts* o) {
     set_error("invalid tau, imax or maxit");
     return GMRESIR_EINVAL;
   }
-  if (o->timing < 0 || o->timing >= (1 << kKcCount)) {
-    set_error("timing must be a bit mask of the kernel classes");
+  if (o->timing < 0 || o->timing >= (1 << 16)) {
+    set_error("timing must be a bit mask of the kernel classes (bits 0-7) and a stride "
+              "(bits 8-15)");
     return GMRESIR_EINVAL;
   }
   if (o->reserved[0] != 0) {
