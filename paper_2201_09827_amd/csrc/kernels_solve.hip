@@ -210,54 +210,23 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, 
 // ---------------------------------------------------------------------------
 // Triangular solves with the u_f factors in fp64 arithmetic.
 //
-// One workgroup (4 waves) per block of 64 rows.  The off-diagonal tiles of a
+// One workgroup (8 waves) per block of 128 rows.  The off-diagonal tiles of a
 // block row are consumed as soon as the producing block has published its
-// part of the solution (flag == epoch): wave w handles the tiles J = w mod 4,
-// each lane one row, with the tile prefetched before the wait.  The diagonal
-// block is applied through its fp64 inverse (formed once per factorisation),
-// so no dependent chain of 64 substitution steps sits on the critical path;
-// all four waves share that 64 x 64 product.
+// part of the solution (tags == epoch), each lane one row of a 64-column
+// tile, with the tile loaded before the wait.  The diagonal block is applied
+// through its fp64 inverse and the neighbouring block through its product
+// with that inverse (both formed once per factorisation), so no dependent
+// chain of substitution steps sits on the critical path.
 // ---------------------------------------------------------------------------
-// 64 consecutive u_f values (16-byte aligned) widened to fp64
-template <class F>
-__device__ __forceinline__ void load_row64(const typename F::T* p, double (&out)[kTB]) {
-  using T = typename F::T;
-  if constexpr (sizeof(T) == 2) {
-    const uint4* q = reinterpret_cast<const uint4*>(p);
-#pragma unroll
-    for (int v = 0; v < kTB / 8; ++v) {
-      const uint4 w = q[v];
-      const uint32_t parts[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        T lo, hi;
-        const uint16_t a = (uint16_t)(parts[h] & 0xFFFFu), b = (uint16_t)(parts[h] >> 16);
-        __builtin_memcpy(&lo, &a, 2);
-        __builtin_memcpy(&hi, &b, 2);
-        out[8 * v + 2 * h] = (double)F::to_f(lo);
-        out[8 * v + 2 * h + 1] = (double)F::to_f(hi);
-      }
-    }
-  } else {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int v = 0; v < kTB / 4; ++v) {
-      const float4 w = q[v];
-      out[4 * v] = w.x;
-      out[4 * v + 1] = w.y;
-      out[4 * v + 2] = w.z;
-      out[4 * v + 3] = w.w;
-    }
-  }
-}
-
 // Blocked triangular solve, one workgroup per 128-row block (two 64-row
 // tiles), fp64 arithmetic with the u_f factor entries taken exactly:
-//   lower: y_I = Dinv_I (in_I - sum_{J < I} L_IJ y_J)
-//   upper: z_I = Dinv_I (y_I  - sum_{J > I} U_IJ z_J)
-// Dinv_I is the fp64 inverse of the 128 x 128 diagonal block.  Waves 0-3 own
-// the first 64 rows, waves 4-7 the second; wave w takes the 64-column tiles
-// J = w mod 4, stepping by 4, and widens each tile row from raw u_f bits.
+//   lower: y_I = Dinv_I (in_I - sum_{J < I-1} L_IJ y_J) - P_I y_{I-1}
+//   upper: z_I = Dinv_I (y_I  - sum_{J > I+1} U_IJ z_J) - P_I z_{I+1}
+// Dinv_I is the fp64 inverse of the 128 x 128 diagonal block and P_I its
+// product with the neighbouring off-diagonal block.  For the far tiles waves
+// 0-3 own the first 64 rows, waves 4-7 the second; wave w takes the 64-column
+// tiles J = w mod 4, stepping by 4, and widens each tile row from raw u_f
+// bits.
 // Finished blocks are published as tagged words: row i's fp64 value is split
 // into two 64-bit words (tag << 32 | half) in xw[2i], xw[2i+1], written with
 // relaxed device-scope atomic stores; a reader polls until both tags equal

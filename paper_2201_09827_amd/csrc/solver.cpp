@@ -249,14 +249,12 @@ struct gmresir_ctx {
   int* permP = nullptr;   // logical -> row of A (P)
   int* permS = nullptr;   // equals perm after gmresir_factor, null after import
   int* ipiv = nullptr;
-  double *Linv = nullptr, *Uinv = nullptr;  // inverses of the diagonal blocks
+  double *Linv = nullptr, *Uinv = nullptr;  // diagonal-block inverses, then neighbour products
   double *Lq = nullptr, *Uq = nullptr;      // the transposed solves' block products
   double* dtmp = nullptr;                    // 64 x 64 inverses (factor time)
   // LU scratch
   uint64_t* xch = nullptr;  // pivot exchange of the block-column kernel (LU only)
   int* perm_rest = nullptr;  // permutation copy read by the lookahead remainder (LU only)
-  hipStream_t s_aux = nullptr;
-  hipEvent_t ev_panel = nullptr, ev_rest = nullptr;
   // solve buffers (length ld, zero padded)
   double *x = nullptr, *b = nullptr, *r64 = nullptr, *t64 = nullptr, *y64 = nullptr,
          *z64 = nullptr;
@@ -301,9 +299,6 @@ struct gmresir_ctx {
     if (st_host) (void)hipHostFree(st_host);
     for (auto& e2 : ev) (void)hipEventDestroy(e2);
     for (auto& e2 : tpool) (void)hipEventDestroy(e2);
-    if (ev_panel) (void)hipEventDestroy(ev_panel);
-    if (ev_rest) (void)hipEventDestroy(ev_rest);
-    if (s_aux) (void)hipStreamDestroy(s_aux);
   }};
 
 namespace {
