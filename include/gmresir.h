@@ -214,7 +214,11 @@ int gmresir_choose_k(gmresir_ctx* h, const double* b, int32_t kmax,
                      int32_t* k_best, int32_t* its, void* stream);
 
 /* Release every resource of the handle.  NULL is accepted.  The handle must
- * not be used afterwards. */
+ * not be used afterwards.  Its device memory goes to a process-wide cache
+ * (at most 16 GiB in all, beyond that it is freed) from which later handles
+ * of the same sizes take their buffers, so repeated factorisations do not
+ * call hipMalloc / hipFree; cached memory is returned when the process
+ * ends. */
 void gmresir_free(gmresir_ctx* h);
 
 /* Static description of a status code. */
