@@ -34,8 +34,8 @@ struct Worker {
   int rc = 0;  // a failure of the worker itself (stream creation)
 };
 
-void run_worker(int device, gmresir_batch_item* items, const std::vector<int64_t>* order,
-                std::atomic<int64_t>* next, const gmresir_opts* opts, Worker* w) {
+void work(int device, gmresir_batch_item* items, const std::vector<int64_t>* order,
+          std::atomic<int64_t>* next, const gmresir_opts* opts, Worker* w) {
   if (hipSetDevice(device) != hipSuccess) {
     w->rc = GMRESIR_EHIP;
     return;
@@ -73,6 +73,16 @@ void run_worker(int device, gmresir_batch_item* items, const std::vector<int64_t
   }
   (void)hipStreamSynchronize(s);
   (void)hipStreamDestroy(s);
+}
+
+// no exception may leave a thread (it would end the process)
+void run_worker(int device, gmresir_batch_item* items, const std::vector<int64_t>* order,
+                std::atomic<int64_t>* next, const gmresir_opts* opts, Worker* w) {
+  try {
+    work(device, items, order, next, opts, w);
+  } catch (...) {
+    w->rc = GMRESIR_ENOMEM;
+  }
 }
 
 }  // namespace
