@@ -422,3 +422,24 @@ def test_solve_largest_recycle_dimensions_shared_factors(lib):
     x, info = h.solve(_dev(p.b))
     h.free()
     _compare(p, x_ref, info_ref, x.cpu().numpy(), info, 300)
+
+
+def test_kernel_timing_records_and_sampling(lib):
+    """Launch timing (opts.timing): every launch of a timed class, or every
+    s-th with bits 8-15; 16 block columns at n = 1024."""
+    p = randsvd_problem(1024, 1e2, 1)
+    a, b = _dev(p.a), _dev(p.b)
+    full = lib.factor(a, timing=1)
+    x1, _ = full.solve(b)
+    s1 = {r["name"]: r for r in full.kernel_stats()}
+    full.free()
+    samp = lib.factor(a, timing=1 | (8 << 8))
+    x2, _ = samp.solve(b)
+    s2 = {r["name"]: r for r in samp.kernel_stats()}
+    samp.free()
+    log(f"[timing] every launch {s1['lu_panel']['launches']}, every 8th {s2['lu_panel']['launches']}")
+    assert s1["lu_panel"]["launches"] == 16 and s2["lu_panel"]["launches"] == 2
+    assert s1["lu_panel"]["total_ms"] > 0 and s2["lu_panel"]["total_ms"] > 0
+    assert torch.equal(x1, x2)
+    with pytest.raises(lib.GmresirError):
+        lib.factor(a, timing=1 << 16)
