@@ -326,23 +326,27 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
       bool ok = true;
       uint64_t v[kMaxPanelWgs * kMaxNb / kRowThreads];
       uint64_t kk = 0;  // wave 0, lane < G: the key word of record `lane`
-      const bool kneed = wave == 0 && lane < G;
       {
         long long spins = 0;
         for (;;) {
+          // every load is issued, unconditionally and in bounds (slots of
+          // records >= G lie inside the exchange buffer and are ignored),
+          // before any is checked: one memory round trip per poll, where
+          // loads under per-record branches were each waited for in turn
+#pragma unroll
+          for (int i = 0; i < kMaxPanelWgs * kMaxNb / kRowThreads; ++i) {
+            const int f = tid + kRowThreads * i;
+            v[i] = xch_load(base + (size_t)(f >> 6) * kRecWords + (f & 63));
+          }
+          if (wave == 0)
+            kk = xch_load(base + (size_t)(lane & (kMaxPanelWgs - 1)) * kRecWords + kMaxNb);
           bool got = true;
 #pragma unroll
           for (int i = 0; i < kMaxPanelWgs * kMaxNb / kRowThreads; ++i) {
             const int f = tid + kRowThreads * i;
-            if ((f >> 6) < G) {
-              v[i] = xch_load(base + (size_t)(f >> 6) * kRecWords + (f & 63));
-              got = got && (uint32_t)(v[i] >> 32) == tag;
-            }
+            got = got && ((f >> 6) >= G || (uint32_t)(v[i] >> 32) == tag);
           }
-          if (kneed) {
-            kk = xch_load(base + (size_t)lane * kRecWords + kMaxNb);
-            got = got && (uint32_t)(kk >> 48) == tag;
-          }
+          if (wave == 0) got = got && (lane >= G || (uint32_t)(kk >> 48) == tag);
           if (__all(got)) break;
           __builtin_amdgcn_s_sleep(1);
           if (((++spins) & 1023) == 0) {
