@@ -257,6 +257,18 @@ __global__ __launch_bounds__(256) void k_trsv_dd(const typename F::T* __restrict
   const bool valid = row < n;
   const int prow = valid ? (permS ? permS[row] : row) : 0;
   const typename F::T* srow = S + (int64_t)prow * ld;
+  // wave 0's inputs of the substitution (the right-hand side and the row of
+  // the diagonal block) are loaded before the waits, off the critical path;
+  // the loads are unconditional and in bounds, their values used only for
+  // valid rows
+  DD tin{0.0, 0.0};
+  RawRow<F> dv;
+  if (wave == 0) {
+    dv.load(srow, r0, n, valid);
+    const int src = valid ? (permIn ? permIn[row] : row) : 0;
+    tin.h = inh[src];
+    tin.l = inl ? inl[src] : 0.0;
+  }
   Acc acc;
   bool ok = true;
   const int t0 = kUpper ? blk + 1 : 0;  // off-diagonal tiles [t0, t1)
@@ -297,15 +309,10 @@ __global__ __launch_bounds__(256) void k_trsv_dd(const typename F::T* __restrict
   }
   DD t{0.0, 0.0};
   if (valid) {
-    const int src = permIn ? permIn[row] : row;
-    t.h = inh[src];
-    t.l = inl ? inl[src] : 0.0;
     const DD sum = tot.value();
-    t = dd_add(t, DD{-sum.h, -sum.l});
+    t = dd_add(tin, DD{-sum.h, -sum.l});
   }
   // substitution with the diagonal block (rows r0 .. r0 + nv - 1)
-  RawRow<F> dv;
-  dv.load(srow, r0, n, valid);
   const int nv = min(kDB, n - r0);
   if (!kUpper) {
 #pragma unroll
