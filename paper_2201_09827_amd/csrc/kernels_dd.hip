@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_trsv_dd(const typename F::T* __restrict
     tin.h = inh[src];
     tin.l = inl ? inl[src] : 0.0;
   }
-  Acc acc;
+  Acc acc, acc1, acc2, acc3;
   bool ok = true;
   const int t0 = kUpper ? blk + 1 : 0;  // off-diagonal tiles [t0, t1)
   const int t1 = kUpper ? nt : blk;
@@ -287,10 +287,20 @@ __global__ __launch_bounds__(256) void k_trsv_dd(const typename F::T* __restrict
     ysh[wave][lane] = yv.h;
     ysl[wave][lane] = yv.l;
     __builtin_amdgcn_wave_barrier();
+    // four interleaved compensated sums: the dependent chain through the
+    // running sum is a quarter as long
 #pragma unroll
-    for (int c = 0; c < kDB; ++c) acc.add_prod(lv.at(c), ysh[wave][c], ysl[wave][c]);
+    for (int c = 0; c < kDB; c += 4) {
+      acc.add_prod(lv.at(c), ysh[wave][c], ysl[wave][c]);
+      acc1.add_prod(lv.at(c + 1), ysh[wave][c + 1], ysl[wave][c + 1]);
+      acc2.add_prod(lv.at(c + 2), ysh[wave][c + 2], ysl[wave][c + 2]);
+      acc3.add_prod(lv.at(c + 3), ysh[wave][c + 3], ysl[wave][c + 3]);
+    }
     __builtin_amdgcn_wave_barrier();
   }
+  acc1.add(acc3);
+  acc.add(acc2);
+  acc.add(acc1);
   ps[wave][lane] = acc.s;
   pc[wave][lane] = acc.c;
   if (lane == 0) wok[wave] = ok ? 1 : 0;
