@@ -54,12 +54,11 @@ __device__ __forceinline__ DD dd_sub_mul(DD x, double a, DD y) {
   return dd_add(x, DD{-p.h, -p.l});
 }
 
-// double-double divided by fp64 with one correction of the quotient
-__device__ __forceinline__ DD dd_div_d(DD a, double b) {
-  const double q1 = a.h / b;
-  const DD p = two_prod(q1, b);
-  const double r = ((a.h - p.h) - p.l) + a.l;
-  return fast_two_sum(q1, r / b);
+// double-double product a * b (b a double-double reciprocal below)
+__device__ __forceinline__ DD dd_mul(DD a, DD b) {
+  DD p = two_prod(a.h, b.h);
+  p.l = __builtin_fma(a.h, b.l, __builtin_fma(a.l, b.h, p.l));
+  return fast_two_sum(p.h, p.l);
 }
 
 // compensated accumulator: the sum is s + c, c collects the exact errors
@@ -262,12 +261,18 @@ __global__ __launch_bounds__(256) void k_trsv_dd(const typename F::T* __restrict
   // the loads are unconditional and in bounds, their values used only for
   // valid rows
   DD tin{0.0, 0.0};
+  DD rdiag{0.0, 0.0};  // upper: the double-double reciprocal of this row's pivot
   RawRow<F> dv;
   if (wave == 0) {
     dv.load(srow, r0, n, valid);
     const int src = valid ? (permIn ? permIn[row] : row) : 0;
     tin.h = inh[src];
     tin.l = inl ? inl[src] : 0.0;
+    if (kUpper) {
+      const double d = (double)F::to_f(srow[valid ? row : 0]);
+      rdiag.h = 1.0 / d;
+      rdiag.l = __builtin_fma(-d, rdiag.h, 1.0) * rdiag.h;
+    }
   }
   Acc acc, acc1, acc2, acc3;
   bool ok = true;
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(256) void k_trsv_dd(const typename F::T* __restrict
 #pragma unroll
     for (int j = kDB - 1; j >= 0; --j) {
       if (j >= nv) continue;
-      if (lane == j) t = dd_div_d(t, dv.at(j));
+      if (lane == j) t = dd_mul(t, rdiag);
       if (j == 0) break;
       DD yj;
       yj.h = readlane_d(t.h, j);
