@@ -15,6 +15,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
@@ -574,6 +575,35 @@ int download(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
   return 0;
 }
 
+// Several device-to-host copies with one synchronisation: each piece goes
+// through the pinned download staging (hipMemcpyAsync when it does not fit),
+// then the stream is synchronised once.
+struct Piece {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+int download_many(gmresir_ctx* h, std::initializer_list<Piece> pieces) {
+  GIR_TRY(stage_init(h));
+  size_t off = 0;
+  std::vector<std::pair<const Piece*, size_t>> staged;
+  for (const Piece& p : pieces) {
+    if (p.bytes == 0) continue;
+    if (p.bytes % 4 == 0 && off + p.bytes <= kStageBytes) {
+      gir::launch_copy_words(h->dl_stage + off, p.src, (int64_t)(p.bytes / 4), h->stream);
+      staged.push_back({&p, off});
+      off += (p.bytes + 255) & ~size_t(255);
+    } else {
+      GIR_HIP(hipMemcpyAsync(p.dst, p.src, p.bytes, hipMemcpyDeviceToHost, h->stream));
+    }
+  }
+  GIR_HIP(hipGetLastError());
+  GIR_HIP(hipStreamSynchronize(h->stream));
+  for (const auto& st : staged) std::memcpy(st.first->dst, h->dl_stage + st.second, st.first->bytes);
+  h->up_off = 0;
+  return 0;
+}
+
 // Copies of A (fp64 and fp32, zero padded), ||A||_inf, max |a|, the
 // non-finite check and, with make_lu_copy, A_f = fl_uf(2^e A) with the scale
 // exponent chosen on the device: no host round trip.  ingest_finish reads the
@@ -600,8 +630,7 @@ int ingest(gmresir_ctx* h, const double* A, int64_t lda, bool make_lu_copy) {
 int ingest_finish(gmresir_ctx* h, bool has_e) {
   unsigned long long hv[2];
   int hi[2];
-  GIR_TRY(download(h, hv, h->norms, sizeof(hv)));
-  GIR_TRY(download(h, hi, h->counter + 4, sizeof(hi)));
+  GIR_TRY(download_many(h, {{hv, h->norms, sizeof(hv)}, {hi, h->counter + 4, sizeof(hi)}}));
   double rowsum;
   std::memcpy(&rowsum, &hv[1], 8);
   h->norm_a = rowsum;
@@ -683,8 +712,7 @@ int run_lu(gmresir_ctx* h) {
                               h->stream);
   gir::CycleState hs{};
   int hflag = 0;
-  GIR_TRY(download(h, &hs, h->st, sizeof(hs)));
-  GIR_TRY(download(h, &hflag, flag, sizeof(int)));
+  GIR_TRY(download_many(h, {{&hs, h->st, sizeof(hs)}, {&hflag, flag, sizeof(int)}}));
   GIR_TRY(ingest_finish(h, true));
   if (hs.abort) {
     set_error("LU: a device-side wait exceeded its bound");
@@ -930,8 +958,8 @@ int dots_norm(gmresir_ctx* h, const gir::Basis& X, const void* w, double* dots, 
   gir::launch_ortho(a, mode, h->stream);
   GIR_HIP(hipGetLastError());
   const int nc = X.kc + X.nv;
-  if (nc > 0 && dots) GIR_TRY(download(h, dots, h->h1, sizeof(double) * nc));
-  GIR_TRY(download(h, nrm2, h->nrm, sizeof(double)));
+  const size_t db = (nc > 0 && dots) ? sizeof(double) * nc : 0;
+  GIR_TRY(download_many(h, {{dots, h->h1, db}, {nrm2, h->nrm, sizeof(double)}}));
   return 0;
 }
 
@@ -1180,17 +1208,17 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       }
     }
     (void)queued;
-    GIR_HIP(hipStreamSynchronize(s));
     gir::CycleState fin{};
-    GIR_TRY(download(h, &fin, h->st, sizeof(fin)));
+    GIR_TRY(download_many(
+        h, {{&fin, h->st, sizeof(fin)},
+            {Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m},
+            {Bh.data(), h->Bd, kc > 0 ? sizeof(double) * (size_t)std::max(k, 1) * m : 0}}));
     if (fin.abort) {
       set_error("triangular solve: a device-side wait exceeded its bound");
       return GMRESIR_EINTERNAL;
     }
     const int J = fin.jdone;
     drop_skipped(h, trec0, J);
-    GIR_TRY(download(h, Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m));
-    if (kc > 0) GIR_TRY(download(h, Bh.data(), h->Bd, sizeof(double) * (size_t)std::max(k, 1) * m));
     const int ldh = m + 1, ldb = std::max(k, 1);
     std::fill(y.begin(), y.end(), 0.0);
     gir::la::givens_lsq(Hh.data(), ldh, J, rn, y.data());
