@@ -61,43 +61,64 @@ __global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, i
 
 // T[:, r] = A_u[permA] Y[:, r] for NR fp64 columns of Y (ld ldy) at once:
 // one wave per row, the row read once for all of them (the recycle set-up)
+// T[:, r] = A_u Y[:, r] for nr <= NR right-hand sides: one wave takes
+// kMultiRows rows, so each 4-column chunk of Y (NR fp64 values per column)
+// is read once for all of them; fp64 accumulation per row and column.
+constexpr int kMultiRows = 4;
 template <int NR>
 __global__ __launch_bounds__(256) void k_gemv_au_multi(const float* __restrict__ Au, int64_t ld,
                                                        const int* __restrict__ permA, int n,
                                                        const double* __restrict__ Y,
                                                        int64_t ldy, int nr,
                                                        double* __restrict__ T, int64_t ldt) {
-  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int row0 = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kMultiRows;
   const int lane = threadIdx.x % kWave;
-  if (row >= n) return;
-  const int prow = permA ? permA[row] : row;
-  const float* a = Au + (int64_t)prow * ld;
-  double acc[NR];
+  if (row0 >= n) return;
+  const float* a[kMultiRows];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+  for (int q = 0; q < kMultiRows; ++q) {
+    const int rw = min(row0 + q, n - 1);  // rows beyond n repeat the last one (not stored)
+    a[q] = Au + (int64_t)(permA ? permA[rw] : rw) * ld;
+  }
+  double acc[kMultiRows][NR];
+#pragma unroll
+  for (int q = 0; q < kMultiRows; ++q)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[q][r] = 0.0;
   const int n4 = n & ~3;
   for (int c = lane * 4; c < n4; c += 256) {
-    const float4 x = *reinterpret_cast<const float4*>(a + c);
+    float4 x[kMultiRows];
+#pragma unroll
+    for (int q = 0; q < kMultiRows; ++q) x[q] = *reinterpret_cast<const float4*>(a[q] + c);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const double* y = Y + (int64_t)min(r, nr - 1) * ldy + c;
       const double2 y0 = *reinterpret_cast<const double2*>(y);
       const double2 y1 = *reinterpret_cast<const double2*>(y + 2);
-      acc[r] = fma((double)x.x, y0.x, acc[r]);
-      acc[r] = fma((double)x.y, y0.y, acc[r]);
-      acc[r] = fma((double)x.z, y1.x, acc[r]);
-      acc[r] = fma((double)x.w, y1.y, acc[r]);
+#pragma unroll
+      for (int q = 0; q < kMultiRows; ++q) {
+        acc[q][r] = fma((double)x[q].x, y0.x, acc[q][r]);
+        acc[q][r] = fma((double)x[q].y, y0.y, acc[q][r]);
+        acc[q][r] = fma((double)x[q].z, y1.x, acc[q][r]);
+        acc[q][r] = fma((double)x[q].w, y1.y, acc[q][r]);
+      }
     }
   }
   for (int cc = n4 + lane; cc < n; cc += kWave) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-      acc[r] = fma((double)a[cc], Y[(int64_t)min(r, nr - 1) * ldy + cc], acc[r]);
+    for (int r = 0; r < NR; ++r) {
+      const double yv = Y[(int64_t)min(r, nr - 1) * ldy + cc];
+#pragma unroll
+      for (int q = 0; q < kMultiRows; ++q) acc[q][r] = fma((double)a[q][cc], yv, acc[q][r]);
+    }
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const double sres = wave_sum(acc[r]);
-    if (lane == 0 && r < nr) T[(int64_t)r * ldt + row] = sres;
+  for (int q = 0; q < kMultiRows; ++q) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double sres = wave_sum(acc[q][r]);
+      if (lane == 0 && r < nr && row0 + q < n) T[(int64_t)r * ldt + row0 + q] = sres;
+    }
   }
 }
 
@@ -1476,7 +1497,7 @@ void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const 
 
 void launch_gemv_au_multi(const float* Au, int64_t ld, const int* permA, int n, const double* Y,
                           int64_t ldy, int nr, double* T, int64_t ldt, hipStream_t s) {
-  const unsigned grid = nblocks(n, 4);
+  const unsigned grid = nblocks(n, 4 * kMultiRows);
   if (nr <= 2)
     hipLaunchKernelGGL(k_gemv_au_multi<2>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, Y, ldy,
                        nr, T, ldt);
