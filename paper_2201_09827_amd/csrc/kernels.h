@@ -164,6 +164,15 @@ void launch_div_u(const void* w, double s, void* out, int v64, int n, hipStream_
 void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t st);
 void launch_copy_f32_to_f64(const float* a, double* b, int n, hipStream_t s);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
+// zeroes count (<= kMaxZeroSpans) spans of 4-byte words, p[j][0 .. n[j]), in
+// one launch; the spans must not overlap
+constexpr int kMaxZeroSpans = 16;
+struct ZeroSpans {
+  int* p[kMaxZeroSpans];
+  int64_t n[kMaxZeroSpans];
+  int count;
+};
+void launch_zero_spans(const ZeroSpans& z, hipStream_t s);
 
 // ---- double-double (u = fp64, u^2 = double-double; u_r = double-double) -----
 

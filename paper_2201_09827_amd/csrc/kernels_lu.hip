@@ -144,6 +144,16 @@ __global__ void k_fill_i32(int* p, int v, int64_t n) {
     p[i] = v;
 }
 
+// span blockIdx.y of the list, grid-strided over blockIdx.x
+__global__ void k_zero_spans(ZeroSpans z) {
+  const int j = blockIdx.y;
+  int* p = z.p[j];
+  const int64_t n = z.n[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 // ---- block column: one pivot search per column across workgroups -----------
 //
 // G = ceil(h / 512) workgroups; thread t of workgroup g owns logical row
@@ -885,6 +895,14 @@ void launch_iota(int* p, int64_t n, hipStream_t s) {
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)),
                      dim3(256), 0, s, p, v, n);
+}
+
+void launch_zero_spans(const ZeroSpans& z, hipStream_t s) {
+  if (z.count <= 0) return;
+  int64_t most = 0;
+  for (int j = 0; j < z.count; ++j) most = std::max(most, z.n[j]);
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((most + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_zero_spans, dim3(gx, (unsigned)z.count), dim3(256), 0, s, z);
 }
 
 void launch_panel_step(const PanelArgs& a, int store, hipStream_t s) {

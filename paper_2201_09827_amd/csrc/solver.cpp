@@ -131,6 +131,45 @@ hipError_t chunk_alloc(void** p, size_t bytes, int* dev_out) {
   return hipMalloc(p, bytes);
 }
 
+// the pinned host staging of a handle, kept the same way (a handful of
+// small blocks; hipHostMalloc and hipHostFree cost hundreds of microseconds)
+struct PinnedCache {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;
+};
+
+PinnedCache& pinned_cache() {
+  static PinnedCache* c = new PinnedCache();  // never destroyed
+  return *c;
+}
+
+hipError_t pinned_alloc(void** p, size_t bytes) {
+  {
+    PinnedCache& c = pinned_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    auto it = c.free_blocks.find(bytes);
+    if (it != c.free_blocks.end()) {
+      *p = it->second;
+      c.free_blocks.erase(it);
+      return hipSuccess;
+    }
+  }
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+void pinned_release(void* p, size_t bytes) {
+  constexpr size_t kMaxPinnedBlocks = 64;
+  PinnedCache& c = pinned_cache();
+  {
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (c.free_blocks.size() < kMaxPinnedBlocks) {
+      c.free_blocks.emplace(bytes, p);
+      return;
+    }
+  }
+  (void)hipHostFree(p);
+}
+
 void chunk_release(void* p, size_t bytes, int dev) {
   ChunkCache& c = chunk_cache();
   {
@@ -283,6 +322,7 @@ struct gmresir_ctx {
   int epoch = 0;
   // pinned host staging
   gir::CycleState* st_host = nullptr;  // one slot per queued step
+  size_t pinned_bytes = 0;             // the pinned block st_host starts
   double* hbuf = nullptr;              // general small transfers
   size_t hbuf_len = 0;
   char *up_stage = nullptr, *dl_stage = nullptr;  // pinned staging of small transfers
@@ -297,7 +337,7 @@ struct gmresir_ctx {
 
   ~gmresir_ctx() {
     // device buffers belong to `arena` (freed by its destructor)
-    if (st_host) (void)hipHostFree(st_host);
+    if (st_host) pinned_release(st_host, pinned_bytes);
     for (auto& e2 : ev) (void)hipEventDestroy(e2);
     for (auto& e2 : tpool) (void)hipEventDestroy(e2);
   }};
@@ -434,7 +474,8 @@ int pinned_init(gmresir_ctx* h) {
   h->hbuf_len = 8192;
   const size_t total = st_bytes + sizeof(double) * h->hbuf_len + 2 * kStageBytes;
   char* p = nullptr;
-  GIR_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), total, hipHostMallocDefault));
+  GIR_HIP(pinned_alloc(reinterpret_cast<void**>(&p), total));
+  h->pinned_bytes = total;
   h->st_host = reinterpret_cast<gir::CycleState*>(p);
   h->hbuf = reinterpret_cast<double*>(p + st_bytes);
   h->up_stage = p + st_bytes + sizeof(double) * h->hbuf_len;
@@ -443,6 +484,25 @@ int pinned_init(gmresir_ctx* h) {
 }
 
 int stage_init(gmresir_ctx* h) { return pinned_init(h); }
+
+// Buffers zeroed at set-up, collected and cleared by one kernel per 16 spans
+// (a memset call, or a launch per buffer, costs microseconds of latency each).
+struct ZeroList {
+  std::vector<std::pair<void*, size_t>> spans;  // (pointer, bytes: a multiple of 4)
+  void add(void* p, size_t bytes) { spans.emplace_back(p, bytes); }
+  void launch(hipStream_t s) {
+    for (size_t i = 0; i < spans.size(); i += gir::kMaxZeroSpans) {
+      gir::ZeroSpans z{};
+      z.count = (int)std::min<size_t>(gir::kMaxZeroSpans, spans.size() - i);
+      for (int j = 0; j < z.count; ++j) {
+        z.p[j] = static_cast<int*>(spans[i + (size_t)j].first);
+        z.n[j] = (int64_t)(spans[i + (size_t)j].second / 4);
+      }
+      gir::launch_zero_spans(z, s);
+    }
+    spans.clear();
+  }
+};
 
 int alloc_solve(gmresir_ctx* h) {
   const size_t ld = (size_t)h->ld;
@@ -484,8 +544,9 @@ int alloc_solve(gmresir_ctx* h) {
              : 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
   GIR_TRY(dalloc(h->arena, &h->xwL, (size_t)nxw));
   GIR_TRY(dalloc(h->arena, &h->xwU, (size_t)nxw));
-  gir::launch_fill_i32(reinterpret_cast<int*>(h->xwL), 0, 2 * nxw, h->stream);
-  gir::launch_fill_i32(reinterpret_cast<int*>(h->xwU), 0, 2 * nxw, h->stream);
+  ZeroList zl;
+  zl.add(h->xwL, sizeof(uint64_t) * (size_t)nxw);
+  zl.add(h->xwU, sizeof(uint64_t) * (size_t)nxw);
   if (h->u64) {
     GIR_TRY(dalloc(h->arena, &h->tl, ld));
     GIR_TRY(dalloc(h->arena, &h->yl, ld));
@@ -493,21 +554,22 @@ int alloc_solve(gmresir_ctx* h) {
     const int64_t nm = nxw * gir::kTrsvMaxRhs;
     GIR_TRY(dalloc(h->arena, &h->xwLm, (size_t)nm));
     GIR_TRY(dalloc(h->arena, &h->xwUm, (size_t)nm));
-    gir::launch_fill_i32(reinterpret_cast<int*>(h->xwLm), 0, 2 * nm, h->stream);
-    gir::launch_fill_i32(reinterpret_cast<int*>(h->xwUm), 0, 2 * nm, h->stream);
+    zl.add(h->xwLm, sizeof(uint64_t) * (size_t)nm);
+    zl.add(h->xwUm, sizeof(uint64_t) * (size_t)nm);
     GIR_TRY(dalloc(h->arena, &h->Tb, (size_t)h->ld * gir::kTrsvMaxRhs));
     GIR_TRY(dalloc(h->arena, &h->Yb, (size_t)h->ld * gir::kTrsvMaxRhs));
   }
   // zero padding of every vector
   double* dv[] = {h->x, h->b, h->r64, h->t64, h->y64, h->z64};
-  for (double* p : dv) GIR_HIP(hipMemsetAsync(p, 0, sizeof(double) * ld, h->stream));
+  for (double* p : dv) zl.add(p, sizeof(double) * ld);
   void* fv[] = {h->zu, h->wu, h->du, h->ru};
-  for (void* p : fv) GIR_HIP(hipMemsetAsync(p, 0, h->ue * ld, h->stream));
-  GIR_HIP(hipMemsetAsync(h->V, 0, h->ue * ld * (m + 1), h->stream));
+  for (void* p : fv) zl.add(p, h->ue * ld);
+  zl.add(h->V, h->ue * ld * (m + 1));
   if (h->u64) {
-    GIR_HIP(hipMemsetAsync(h->tl, 0, sizeof(double) * ld, h->stream));
-    GIR_HIP(hipMemsetAsync(h->yl, 0, sizeof(double) * ld, h->stream));
+    zl.add(h->tl, sizeof(double) * ld);
+    zl.add(h->yl, sizeof(double) * ld);
   }
+  zl.launch(h->stream);
   GIR_TRY(pinned_init(h));
   h->ev.resize(kEventRing);
   for (auto& e2 : h->ev) GIR_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
@@ -532,8 +594,10 @@ int alloc_common(gmresir_ctx* h) {
   GIR_TRY(dalloc(h->arena, &h->st, 1));
   GIR_TRY(dalloc(h->arena, &h->counter, 8));
   GIR_TRY(dalloc(h->arena, &h->norms, 4));
-  GIR_HIP(hipMemsetAsync(h->st, 0, sizeof(gir::CycleState), h->stream));
-  GIR_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned) * 8, h->stream));
+  ZeroList zl;
+  zl.add(h->st, sizeof(gir::CycleState));
+  zl.add(h->counter, sizeof(unsigned) * 8);
+  zl.launch(h->stream);
   return 0;
 }
 
@@ -705,7 +769,7 @@ int run_lu(gmresir_ctx* h) {
   }
   GIR_HIP(hipGetLastError());
   int* flag = reinterpret_cast<int*>(h->counter + 2);
-  GIR_HIP(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+  gir::launch_fill_i32(flag, 0, 1, h->stream);
   gir::launch_check_factors(h->S, n, h->ld, h->store, flag, h->stream);
   if (!h->u64 || h->uni)
     gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->dtmp,
