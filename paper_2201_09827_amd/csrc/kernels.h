@@ -55,7 +55,8 @@ void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, cons
 void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s);
 // copy of `words` 4-byte words; either side may be mapped pinned host memory
 void launch_copy_words(void* dst, const void* src, int64_t words, hipStream_t s);
-// after the last panel: non-finite check of the factors
+// after the last panel: non-finite check of the factors (S 16-byte aligned,
+// ld a multiple of 8 elements: rows are read as 16-byte vectors)
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,
                           hipStream_t s);
 
@@ -100,7 +101,7 @@ void launch_trsv_multi(const void* S, int64_t ld, const int* permS, int store, i
 // inverses of the diagonal blocks of L and U, then the products of each
 // inverse with the neighbouring off-diagonal block the single right-hand side
 // solves read (lower: Linv_I L_{I,I-1}; upper: Uinv_I U_{I,I+1});
-// tmp: ceil(n/64) * 64 * 64 doubles
+// tmp: 2 * ceil(n/64) * 64 * 64 doubles (the 64 x 64 inverses of L, then of U)
 constexpr int kTrsvBlock = 128;
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,
                           double* Linv, double* Uinv, double* tmp, hipStream_t s);

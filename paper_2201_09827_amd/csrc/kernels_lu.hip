@@ -812,13 +812,33 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_update(
   }
 }
 
+// Non-finite entries of the n x n factor.  Each thread tests one 16-byte
+// vector of a row (rows start on 128-byte boundaries: ld is a multiple of 64
+// elements); the thread just past the last whole vector tests the row's tail
+// element by element.
 template <class F>
 __global__ void k_check(const typename F::T* __restrict__ S, int64_t n, int64_t ld, int* flag) {
+  using T = typename F::T;
+  constexpr int kV = 16 / (int)sizeof(T);
+  const int64_t nv = n / kV;  // whole vectors per row
   int bad = 0;
-  for (int64_t r = blockIdx.y; r < n; r += gridDim.y)
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-         c += (int64_t)gridDim.x * blockDim.x)
-      if (!F::finite(S[r * ld + c])) bad = 1;
+  for (int64_t r = blockIdx.y; r < n; r += gridDim.y) {
+    const T* row = S + r * ld;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= nv;
+         v += (int64_t)gridDim.x * blockDim.x) {
+      if (v < nv) {
+        const uint4 w = *reinterpret_cast<const uint4*>(row + v * kV);
+        T e[kV];
+        __builtin_memcpy(e, &w, sizeof(w));
+#pragma unroll
+        for (int i = 0; i < kV; ++i)
+          if (!F::finite(e[i])) bad = 1;
+      } else {
+        for (int64_t c = nv * kV; c < n; ++c)
+          if (!F::finite(row[c])) bad = 1;
+      }
+    }
+  }
   if (__any(bad) && (threadIdx.x % kWave) == 0) atomicOr(flag, 1);
 }
 
@@ -951,7 +971,9 @@ void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s) {
 
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,
                           hipStream_t s) {
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)std::min<int64_t>(n, 65535));
+  // one thread per 16-byte vector of a row, plus one for the tail
+  const int64_t nvec = n * (store == kStoreF32 ? 4 : 2) / 16 + 1;
+  dim3 grid((unsigned)((nvec + 255) / 256), (unsigned)std::min<int64_t>(n, 65535));
   if (store == kStoreF16)
     hipLaunchKernelGGL(k_check<Fp16>, grid, dim3(256), 0, s,
                        reinterpret_cast<const _Float16*>(S), n, ld, flag);

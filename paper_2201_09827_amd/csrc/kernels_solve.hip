@@ -728,14 +728,13 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
 // (fp64, B taken exactly from the u_f factor; a missing second 64-block or
 // rows beyond n act as the identity).
 template <class F, bool kUpper>
-__global__ __launch_bounds__(256) void k_diag_combine(const typename F::T* __restrict__ S,
-                                                      int64_t ld, const int* __restrict__ permS,
-                                                      int n, const double* __restrict__ D64,
-                                                      double* __restrict__ D128) {
-  __shared__ double Ai[kTB][kTB + 1];
-  __shared__ double Ci[kTB][kTB + 1];
-  __shared__ double Bm[kTB][kTB + 1];
-  __shared__ double T[kTB][kTB + 1];
+__device__ __forceinline__ void diag_combine(const typename F::T* __restrict__ S, int64_t ld,
+                                             const int* __restrict__ permS, int n,
+                                             const double* __restrict__ D64,
+                                             double* __restrict__ D128, double (&Ai)[kTB][kTB + 1],
+                                             double (&Ci)[kTB][kTB + 1],
+                                             double (&Bm)[kTB][kTB + 1],
+                                             double (&T)[kTB][kTB + 1]) {
   const int blk = blockIdx.x;
   const int tid = threadIdx.x;
   const int nt = (n + kTB - 1) / kTB;
@@ -782,22 +781,40 @@ __global__ __launch_bounds__(256) void k_diag_combine(const typename F::T* __res
   }
 }
 
+// both triangles in one launch: blockIdx.y = 0 for L, 1 for U
+template <class F>
+__global__ __launch_bounds__(256) void k_diag_combine(const typename F::T* __restrict__ S,
+                                                      int64_t ld, const int* __restrict__ permS,
+                                                      int n, const double* __restrict__ D64L,
+                                                      const double* __restrict__ D64U,
+                                                      double* __restrict__ Linv,
+                                                      double* __restrict__ Uinv) {
+  __shared__ double Ai[kTB][kTB + 1];
+  __shared__ double Ci[kTB][kTB + 1];
+  __shared__ double Bm[kTB][kTB + 1];
+  __shared__ double T[kTB][kTB + 1];
+  if (blockIdx.y == 0)
+    diag_combine<F, false>(S, ld, permS, n, D64L, Linv, Ai, Ci, Bm, T);
+  else
+    diag_combine<F, true>(S, ld, permS, n, D64U, Uinv, Ai, Ci, Bm, T);
+}
+
 // Products of each 128 x 128 inverse diagonal block with the neighbouring
 // off-diagonal block of the same triangle, in fp64 with the u_f entries
 // taken exactly:
 //   lower: P_I = Dinv_I L_{I,I-1}  (I >= 1)
 //   upper: P_I = Dinv_I U_{I,I+1}  (I <= nb - 2)
 // so that the blocked solve needs one 128 x 128 product once the neighbour's
-// values arrive.  Grid (nb - 1, 4): blockIdx.y picks 32 columns of P_I.
-// Rows or columns beyond n enter as zeros.
+// values arrive.  Grid (nb - 1, 4, 2): blockIdx.y picks 32 columns of P_I,
+// blockIdx.z the triangle (0: L, 1: U).  Rows or columns beyond n enter as
+// zeros.
 template <class F, bool kUpper>
-__global__ __launch_bounds__(256) void k_adjacent_product(const typename F::T* __restrict__ S,
-                                                          int64_t ld,
-                                                          const int* __restrict__ permS, int n,
-                                                          const double* __restrict__ Dinv,
-                                                          double* __restrict__ P) {
+__device__ __forceinline__ void adjacent_product(const typename F::T* __restrict__ S, int64_t ld,
+                                                 const int* __restrict__ permS, int n,
+                                                 const double* __restrict__ Dinv,
+                                                 double* __restrict__ P,
+                                                 double (&B)[kTS][kTS / 4 + 1]) {
   constexpr int kC = kTS / 4;
-  __shared__ double B[kTS][kC + 1];
   const int blk = kUpper ? (int)blockIdx.x : (int)blockIdx.x + 1;
   const int adj = kUpper ? blk + 1 : blk - 1;
   const int c0 = adj * kTS + (int)blockIdx.y * kC;  // first global column
@@ -827,6 +844,21 @@ __global__ __launch_bounds__(256) void k_adjacent_product(const typename F::T* _
   double* out = P + ((int64_t)blk * kTS + r) * kTS + (int)blockIdx.y * kC + cb;
 #pragma unroll
   for (int j = 0; j < kC / 2; ++j) out[j] = acc[j];
+}
+
+template <class F>
+__global__ __launch_bounds__(256) void k_adjacent_product(const typename F::T* __restrict__ S,
+                                                          int64_t ld,
+                                                          const int* __restrict__ permS, int n,
+                                                          const double* __restrict__ Linv,
+                                                          double* __restrict__ PL,
+                                                          const double* __restrict__ Uinv,
+                                                          double* __restrict__ PU) {
+  __shared__ double B[kTS][kTS / 4 + 1];
+  if (blockIdx.z == 0)
+    adjacent_product<F, false>(S, ld, permS, n, Linv, PL, B);
+  else
+    adjacent_product<F, true>(S, ld, permS, n, Uinv, PU, B);
 }
 
 // The products the transposed solves need, the neighbouring off-diagonal
@@ -886,11 +918,10 @@ __global__ __launch_bounds__(256) void k_adjacent_product_t(const typename F::T*
 // Inverse of each 64 x 64 diagonal block of L (unit lower) or U (upper) in
 // fp64, row-major per block; rows/columns beyond n get the identity.
 template <class F, bool kUpper>
-__global__ __launch_bounds__(64) void k_diag_inverse(const typename F::T* __restrict__ S, int64_t ld,
-                                                     const int* __restrict__ permS, int n,
-                                                     double* __restrict__ Dinv) {
-  __shared__ double B[kTB][kTB + 1];
-  __shared__ double X[kTB][kTB + 1];
+__device__ __forceinline__ void diag_inverse(const typename F::T* __restrict__ S, int64_t ld,
+                                             const int* __restrict__ permS, int n,
+                                             double* __restrict__ Dinv, double (&B)[kTB][kTB + 1],
+                                             double (&X)[kTB][kTB + 1]) {
   const int blk = blockIdx.x;
   const int r0 = blk * kTB;
   const int j = threadIdx.x;  // column of the inverse
@@ -922,6 +953,20 @@ __global__ __launch_bounds__(64) void k_diag_inverse(const typename F::T* __rest
     const bool lowerpart = kUpper ? (j >= r) : (j <= r);
     Dinv[((int64_t)blk * kTB + r) * kTB + j] = lowerpart ? X[r][j] : 0.0;
   }
+}
+
+// both triangles in one launch: blockIdx.y = 0 for L, 1 for U
+template <class F>
+__global__ __launch_bounds__(64) void k_diag_inverse(const typename F::T* __restrict__ S, int64_t ld,
+                                                     const int* __restrict__ permS, int n,
+                                                     double* __restrict__ DinvL,
+                                                     double* __restrict__ DinvU) {
+  __shared__ double B[kTB][kTB + 1];
+  __shared__ double X[kTB][kTB + 1];
+  if (blockIdx.y == 0)
+    diag_inverse<F, false>(S, ld, permS, n, DinvL, B, X);
+  else
+    diag_inverse<F, true>(S, ld, permS, n, DinvU, B, X);
 }
 
 // fp64 sum over the 64 lanes of a wave by DPP row shifts and row broadcasts
@@ -1602,19 +1647,15 @@ void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store
 #define GIR_DINV(F)                                                                          \
   do {                                                                                       \
     const typename F::T* Sp = reinterpret_cast<const typename F::T*>(S);                     \
-    hipLaunchKernelGGL((k_diag_inverse<F, false>), dim3(g64), dim3(kTB), 0, s, Sp, ld, permS, \
-                       n, tmp);                                                              \
-    hipLaunchKernelGGL((k_diag_combine<F, false>), dim3(g128), dim3(256), 0, s, Sp, ld, permS, \
-                       n, tmp, Linv);                                                        \
-    hipLaunchKernelGGL((k_diag_inverse<F, true>), dim3(g64), dim3(kTB), 0, s, Sp, ld, permS,  \
-                       n, tmp);                                                              \
-    hipLaunchKernelGGL((k_diag_combine<F, true>), dim3(g128), dim3(256), 0, s, Sp, ld, permS, \
-                       n, tmp, Uinv);                                                        \
+    double* tmpU = tmp + (int64_t)g64 * kTB * kTB;                                           \
+    hipLaunchKernelGGL((k_diag_inverse<F>), dim3(g64, 2), dim3(kTB), 0, s, Sp, ld, permS, n,  \
+                       tmp, tmpU);                                                           \
+    hipLaunchKernelGGL((k_diag_combine<F>), dim3(g128, 2), dim3(256), 0, s, Sp, ld, permS, n, \
+                       tmp, tmpU, Linv, Uinv);                                               \
     if (g128 > 1) {                                                                          \
-      hipLaunchKernelGGL((k_adjacent_product<F, false>), dim3(g128 - 1, 4), dim3(256), 0, s,  \
-                         Sp, ld, permS, n, Linv, Linv + (int64_t)g128 * kTS * kTS);          \
-      hipLaunchKernelGGL((k_adjacent_product<F, true>), dim3(g128 - 1, 4), dim3(256), 0, s,   \
-                         Sp, ld, permS, n, Uinv, Uinv + (int64_t)g128 * kTS * kTS);          \
+      hipLaunchKernelGGL((k_adjacent_product<F>), dim3(g128 - 1, 4, 2), dim3(256), 0, s, Sp,  \
+                         ld, permS, n, Linv, Linv + (int64_t)g128 * kTS * kTS, Uinv,          \
+                         Uinv + (int64_t)g128 * kTS * kTS);                                   \
     }                                                                                        \
   } while (0)
   if (store == kStoreF16) {

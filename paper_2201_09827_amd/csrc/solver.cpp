@@ -291,7 +291,7 @@ struct gmresir_ctx {
   int* ipiv = nullptr;
   double *Linv = nullptr, *Uinv = nullptr;  // diagonal-block inverses, then neighbour products
   double *Lq = nullptr, *Uq = nullptr;      // the transposed solves' block products
-  double* dtmp = nullptr;                    // 64 x 64 inverses (factor time)
+  double* dtmp = nullptr;                    // 64 x 64 inverses of L and U (factor time)
   // LU scratch
   uint64_t* xch = nullptr;  // pivot exchange of the block-column kernel (LU only)
   int* perm_rest = nullptr;  // permutation copy read by the lookahead remainder (LU only)
@@ -589,7 +589,7 @@ int alloc_common(gmresir_ctx* h) {
     const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
     GIR_TRY(dalloc(h->arena, &h->Linv, 2 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
     GIR_TRY(dalloc(h->arena, &h->Uinv, 2 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
-    GIR_TRY(dalloc(h->arena, &h->dtmp, ((n + 63) / 64) * 64 * 64));
+    GIR_TRY(dalloc(h->arena, &h->dtmp, 2 * ((n + 63) / 64) * 64 * 64));
   }
   GIR_TRY(dalloc(h->arena, &h->st, 1));
   GIR_TRY(dalloc(h->arena, &h->counter, 8));
