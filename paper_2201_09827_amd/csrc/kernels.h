@@ -89,14 +89,15 @@ void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, i
                        const double* y, const double* Uinv, double* z, double scale,
                        double* out64, float* out32, uint64_t* xw, int epoch,
                        const CycleState* gate, int step, int* abort, hipStream_t s);
-// the lower (upper = false) or upper solve for nr <= 8 right-hand sides at
-// once: in / out column-major (ldi / ldo), out = scale * solution; xw holds
-// nr slots of xstride >= 2 * ceil(n/128) * 128 tagged words
+// the lower (upper = false) or upper solve for nr <= 8 right-hand sides as
+// nr independent solves in one launch (one grid row each): in / out
+// column-major (ldi / ldo), out = scale * solution (the lower solve: scale 1);
+// xw holds nr slots of xstride >= 2 * ceil(n/128) * 128 tagged words
 constexpr int kTrsvMaxRhs = 8;
-void launch_trsv_multi(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
-                       const double* in, int64_t ldi, const int* permIn, int nr,
-                       const double* Dinv, double* out, int64_t ldo, double scale, uint64_t* xw,
-                       int64_t xstride, int epoch, int* abortp, hipStream_t s);
+void launch_trsv_cols(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
+                      const double* in, int64_t ldi, int nr, const double* Dinv, double* out,
+                      int64_t ldo, double scale, uint64_t* xw, int64_t xstride, int epoch,
+                      int* abortp, hipStream_t s);
 // Linv / Uinv: 2 * ceil(n/128) blocks of 128 x 128 fp64, row-major: the
 // inverses of the diagonal blocks of L and U, then the products of each
 // inverse with the neighbouring off-diagonal block the single right-hand side

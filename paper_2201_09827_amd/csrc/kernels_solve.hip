@@ -349,6 +349,15 @@ __device__ __forceinline__ bool get_tagged_block(const uint64_t* xw, int base, u
   }
 }
 
+// Several right-hand sides are independent solves, one per grid row
+// (blockIdx.y = column): column c reads in + c * cs.in and writes y + c * cs.y,
+// out64 + c * cs.out, exchanging its values through xw + c * cs.xw.  A block
+// waits only for blocks of its own column with a smaller blockIdx.x, which
+// were dispatched before it.
+struct ColStrides {
+  int64_t in, y, out, xw;
+};
+
 template <class F, bool kUpper>
 __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __restrict__ S,
                                                      int64_t ld, const int* __restrict__ permS,
@@ -358,8 +367,15 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
                                                      double scale, double* __restrict__ out64,
                                                      float* __restrict__ out32, uint64_t* xw,
                                                      uint32_t epoch, const CycleState* gate,
-                                                     int step, int* abortp) {
+                                                     int step, int* abortp, ColStrides cs) {
   if (gated_off(gate, step)) return;
+  {
+    const int64_t col = blockIdx.y;
+    in += col * cs.in;
+    if (y) y += col * cs.y;
+    if (out64) out64 += col * cs.out;
+    xw += col * cs.xw;
+  }
   __shared__ double red[8][kTB];
   __shared__ double ysh[8][kTB];
   // vectors read by quarters: quarter q at q * kQS (padded so that the four
@@ -491,235 +507,11 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   const int rr = r0 + di;
   const double v = (rr < n) ? p : 0.0;
   if (rr < n) {
-    y[rr] = v;
+    if (y) y[rr] = v;
     if (out64) out64[rr] = v * scale;
     if (out32) out32[rr] = (float)(v * scale);
   }
   put_tagged(xw, rr, v, epoch);
-}
-
-// The same blocked solve for nr <= 8 right-hand sides at once (the recycle
-// set-up applies M^-1 to k vectors): each tile row of the factor is read once
-// for all of them, and one round trip fetches the nr published values of a
-// row.  in / out are column-major (ldi / ldo); right-hand side r exchanges its
-// words in xw + r * xstride.
-
-// the nr published values of row `row` (each lane its own row), all loads
-// issued before any is checked (one memory round trip; slots beyond nr
-// repeat the last one); false on abort
-template <int NR>
-__device__ __forceinline__ bool get_tagged_rows(const uint64_t* xw, int64_t xstride, int nr,
-                                                int row, uint32_t epoch, double (&v)[NR],
-                                                int* abortp) {
-  long long spins = 0;
-  for (;;) {
-    uint64_t lo[NR], hi[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const uint64_t* p = xw + (int64_t)min(r, nr - 1) * xstride + 2 * row;
-      lo[r] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      hi[r] = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    bool got = true;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      got = got && (uint32_t)(lo[r] >> 32) == epoch && (uint32_t)(hi[r] >> 32) == epoch;
-      v[r] = __longlong_as_double((long long)((hi[r] << 32) | (lo[r] & 0xFFFFFFFFull)));
-    }
-    if (__all(got)) return true;
-    __builtin_amdgcn_s_sleep(1);
-    if (((++spins) & 1023) == 0) {
-      if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-          spins > (1ll << 22)) {
-        __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return false;
-      }
-    }
-  }
-}
-
-template <class F, bool kUpper, int NR>
-__global__ __launch_bounds__(kTSThreads) void k_trsv_multi(
-    const typename F::T* __restrict__ S, int64_t ld, const int* __restrict__ permS, int n,
-    const double* __restrict__ in, int64_t ldi, const int* __restrict__ permIn, int nr,
-    const double* __restrict__ Dinv, double* __restrict__ out, int64_t ldo, double scale,
-    uint64_t* xw, int64_t xstride, uint32_t epoch, int* abortp) {
-  __shared__ double ysh[8][NR][kTB];
-  __shared__ double zsh[NR][kTS];
-  __shared__ double part[4][NR][kTS];
-  __shared__ int wok[8];
-  const int nb = (n + kTS - 1) / kTS;
-  const int nt = (n + kTB - 1) / kTB;
-  const int blk = kUpper ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x;
-  const int r0 = blk * kTS;
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
-  const int half = wave >> 2;
-  const int wq = wave & 3;
-  const int row = r0 + half * kTB + lane;
-  const bool valid = row < n;
-  const int prow = valid ? (permS ? permS[row] : row) : 0;
-  const typename F::T* srow = S + (int64_t)prow * ld;
-  // the neighbouring block enters through its precomputed product with the
-  // inverse diagonal block where the registers allow it (up to 8 right-hand
-  // sides with 16-bit factors, 4 with fp32 ones); otherwise through its tiles
-  constexpr bool kAdj = NR <= (sizeof(typename F::T) == 2 ? 8 : 4);
-  const bool hasAdj = kAdj && (kUpper ? blk < nb - 1 : blk > 0);
-  const int adj = kUpper ? blk + 1 : blk - 1;
-  const int di = tid % kTS;
-  const int dq4 = tid / kTS;
-  // this thread's quarter of its row of the inverse diagonal block and of the
-  // neighbour's product
-  const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
-  const double* mrow = drow + (int64_t)nb * kTS * kTS;
-  double dq[kTS / 4], mq[kTS / 4];
-#pragma unroll
-  for (int c = 0; c < kTS / 4; c += 2) {
-    const double2 v = *reinterpret_cast<const double2*>(drow + c);
-    dq[c] = v.x;
-    dq[c + 1] = v.y;
-  }
-  if (kAdj) {
-#pragma unroll
-    for (int c = 0; c < kTS / 4; c += 2) {
-      const double2 v = hasAdj ? *reinterpret_cast<const double2*>(mrow + c) : double2{0.0, 0.0};
-      mq[c] = v.x;
-      mq[c + 1] = v.y;
-    }
-  }
-  double rhs[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    rhs[r] = 0.0;
-    if (r < nr && tid < kTS && r0 + tid < n) {
-      const int rr = r0 + tid;
-      rhs[r] = in[(int64_t)r * ldi + (permIn ? permIn[rr] : rr)];
-    }
-  }
-  double acc[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-  bool ok = true;
-  // off-diagonal tiles (without the neighbouring block's two when its
-  // product is used)
-  const int t0 = kUpper ? 2 * blk + (kAdj ? 4 : 2) : 0;
-  const int t1 = kUpper ? nt : (kAdj ? (blk > 0 ? 2 * blk - 2 : 0) : 2 * blk);
-  for (int i = wq;; i += 4) {
-    const int J = kUpper ? t1 - 1 - i : t0 + i;
-    if (kUpper ? (J < t0) : (J >= t1)) break;
-    RawRow<F> lv;
-    lv.load(srow, J * kTB, n, valid);
-    // the nr published values of row J * 64 + lane, fetched together
-    {
-      const int c = J * kTB + lane;
-      long long spins = 0;
-      for (;;) {
-        // every load is issued before any is checked (one memory round trip;
-        // slots beyond nr repeat the last one)
-        uint64_t lo[NR], hi[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const uint64_t* p = xw + (int64_t)min(r, nr - 1) * xstride + 2 * c;
-          lo[r] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          hi[r] = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        bool got = true;
-        double v[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          got = got && (uint32_t)(lo[r] >> 32) == epoch && (uint32_t)(hi[r] >> 32) == epoch;
-          v[r] = __longlong_as_double((long long)((hi[r] << 32) | (lo[r] & 0xFFFFFFFFull)));
-        }
-        if (__all(got)) {
-#pragma unroll
-          for (int r = 0; r < NR; ++r) ysh[wave][r][lane] = v[r];
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        if (((++spins) & 1023) == 0) {
-          if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-              spins > (1ll << 22)) {
-            __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-            break;
-          }
-        }
-      }
-    }
-    if (!ok) break;
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int c = 0; c < kTB; ++c) {
-      const double a = lv.at(c);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) acc[r] = fma(a, ysh[wave][r][c], acc[r]);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int r = 0; r < NR; ++r) ysh[wave][r][lane] = acc[r];
-  if (lane == 0) wok[wave] = ok ? 1 : 0;
-  __syncthreads();
-  int allok = 1;
-#pragma unroll
-  for (int w = 0; w < 8; ++w) allok &= wok[w];
-  if (!allok) return;
-  if (tid < kTS) {
-    const int h = tid / kTB, l = tid % kTB;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double sum = (ysh[4 * h][r][l] + ysh[4 * h + 1][r][l]) +
-                         (ysh[4 * h + 2][r][l] + ysh[4 * h + 3][r][l]);
-      zsh[r][tid] = (r0 + tid < n) ? rhs[r] - sum : 0.0;
-    }
-  }
-  __syncthreads();
-  // Dinv (in - sum over the far blocks) - P (neighbour's values), this
-  // thread's quarter of its row, for each right-hand side
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    double p = 0.0;
-#pragma unroll
-    for (int c = 0; c < kTS / 4; ++c) p = fma(dq[c], zsh[r][dq4 * (kTS / 4) + c], p);
-    part[dq4][r][di] = p;
-  }
-  if (hasAdj) {
-    // lanes c and c + 32 both fetch row dq4 * 32 + c of the neighbour
-    double v[NR];
-    const bool got = get_tagged_rows<NR>(xw, xstride, nr, adj * kTS + dq4 * (kTS / 4) + (lane & 31),
-                                         epoch, v, abortp);
-    if (got) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) ysh[wave][r][lane] = v[r];
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        double p = part[dq4][r][di];
-#pragma unroll
-        for (int c = 0; c < kTS / 4; ++c) p = fma(-mq[c], ysh[wave][r][c], p);
-        part[dq4][r][di] = p;
-      }
-    }
-    if (lane == 0) wok[wave] = got ? 1 : 0;
-  }
-  __syncthreads();
-  if (hasAdj) {
-#pragma unroll
-    for (int w = 0; w < 8; ++w) allok &= wok[w];
-    if (!allok) return;
-  }
-  if (tid >= kTS) return;
-  const int rr = r0 + tid;
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (r >= nr) break;
-    const double v =
-        (rr < n) ? (part[0][r][tid] + part[1][r][tid]) + (part[2][r][tid] + part[3][r][tid]) : 0.0;
-    if (rr < n) out[(int64_t)r * ldo + rr] = v * scale;
-    put_tagged(xw + (int64_t)r * xstride, rr, v, epoch);
-  }
 }
 
 // 128 x 128 inverses of the diagonal blocks from the 64 x 64 ones (D64):
@@ -1570,18 +1362,47 @@ template <class F>
 void trsv_pair(const void* S, int64_t ld, const int* permS, int n, bool upper, const double* in,
                const int* permIn, const double* Dinv, double* y, double scale, double* out64,
                float* out32, uint64_t* xw, int epoch, const CycleState* gate, int step,
-               int* abortp, hipStream_t s) {
+               int* abortp, hipStream_t s, int ncols = 1, ColStrides cs = ColStrides{0, 0, 0, 0}) {
   using T = typename F::T;
-  const unsigned grid = nblocks(n, kTS);
+  const dim3 grid(nblocks(n, kTS), (unsigned)ncols);
   const T* Sp = reinterpret_cast<const T*>(S);
   if (upper)
-    hipLaunchKernelGGL((k_trsv<F, true>), dim3(grid), dim3(kTSThreads), 0, s, Sp, ld, permS, n,
-                       in, permIn, Dinv, y, scale, out64, out32, xw, (uint32_t)epoch, gate, step,
-                       abortp);
+    hipLaunchKernelGGL((k_trsv<F, true>), grid, dim3(kTSThreads), 0, s, Sp, ld, permS, n, in,
+                       permIn, Dinv, y, scale, out64, out32, xw, (uint32_t)epoch, gate, step,
+                       abortp, cs);
   else
-    hipLaunchKernelGGL((k_trsv<F, false>), dim3(grid), dim3(kTSThreads), 0, s, Sp, ld, permS, n,
-                       in, permIn, Dinv, y, 1.0, nullptr, nullptr, xw, (uint32_t)epoch, gate,
-                       step, abortp);
+    hipLaunchKernelGGL((k_trsv<F, false>), grid, dim3(kTSThreads), 0, s, Sp, ld, permS, n, in,
+                       permIn, Dinv, y, 1.0, nullptr, nullptr, xw, (uint32_t)epoch, gate, step,
+                       abortp, cs);
+}
+
+template <class F>
+void trsv_cols_t(const void* S, int64_t ld, const int* permS, int n, bool upper,
+                 const double* in, int64_t ldi, int nr, const double* Dinv, double* out,
+                 int64_t ldo, double scale, uint64_t* xw, int64_t xstride, int epoch,
+                 int* abortp, hipStream_t s) {
+  if (upper)
+    trsv_pair<F>(S, ld, permS, n, true, in, nullptr, Dinv, nullptr, scale, out, nullptr, xw,
+                 epoch, nullptr, 0, abortp, s, nr, ColStrides{ldi, 0, ldo, xstride});
+  else  // the lower solve writes its (unscaled) result through y
+    trsv_pair<F>(S, ld, permS, n, false, in, nullptr, Dinv, out, 1.0, nullptr, nullptr, xw,
+                 epoch, nullptr, 0, abortp, s, nr, ColStrides{ldi, ldo, 0, xstride});
+}
+
+void launch_trsv_cols(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
+                      const double* in, int64_t ldi, int nr, const double* Dinv, double* out,
+                      int64_t ldo, double scale, uint64_t* xw, int64_t xstride, int epoch,
+                      int* abortp, hipStream_t s) {
+  if (nr <= 0) return;
+  if (store == kStoreF16)
+    trsv_cols_t<Fp16>(S, ld, permS, n, upper, in, ldi, nr, Dinv, out, ldo, scale, xw, xstride,
+                      epoch, abortp, s);
+  else if (store == kStoreBF16)
+    trsv_cols_t<Bf16>(S, ld, permS, n, upper, in, ldi, nr, Dinv, out, ldo, scale, xw, xstride,
+                      epoch, abortp, s);
+  else
+    trsv_cols_t<Fp32>(S, ld, permS, n, upper, in, ldi, nr, Dinv, out, ldo, scale, xw, xstride,
+                      epoch, abortp, s);
 }
 
 void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, int n,
@@ -1612,32 +1433,6 @@ void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, i
   else
     trsv_pair<Fp32>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, xw,
                     epoch, gate, step, abortp, s);
-}
-
-void launch_trsv_multi(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
-                       const double* in, int64_t ldi, const int* permIn, int nr,
-                       const double* Dinv, double* out, int64_t ldo, double scale, uint64_t* xw,
-                       int64_t xstride, int epoch, int* abortp, hipStream_t s) {
-  const unsigned grid = nblocks(n, kTS);
-  // the kernel's cost per block grows with the number of right-hand sides it
-  // is compiled for: the smallest of 2, 4, 8 that holds nr
-#define GIR_TM(F, U, R)                                                                        \
-  hipLaunchKernelGGL((k_trsv_multi<F, U, R>), dim3(grid), dim3(kTSThreads), 0, s,              \
-                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, ldi, permIn, \
-                     nr, Dinv, out, ldo, scale, xw, xstride, (uint32_t)epoch, abortp)
-#define GIR_TMR(F, U) \
-  do {                \
-    if (nr <= 2) GIR_TM(F, U, 2); else if (nr <= 4) GIR_TM(F, U, 4); else GIR_TM(F, U, 8); \
-  } while (0)
-  if (store == kStoreF16) {
-    if (upper) GIR_TMR(Fp16, true); else GIR_TMR(Fp16, false);
-  } else if (store == kStoreBF16) {
-    if (upper) GIR_TMR(Bf16, true); else GIR_TMR(Bf16, false);
-  } else {
-    if (upper) GIR_TMR(Fp32, true); else GIR_TMR(Fp32, false);
-  }
-#undef GIR_TMR
-#undef GIR_TM
 }
 
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,

@@ -975,15 +975,14 @@ int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
     }));
     const int eL = next_epoch(h);
     GIR_TRY(timed(h, kKcTrsvL, tbytes + 16.0 * nr * nn, h->stream, nullptr, 0, [&] {
-      gir::launch_trsv_multi(h->S, ld, h->permS, h->store, n, false, h->Tb, ld, nullptr, nr,
-                             h->Linv, h->Yb, ld, 1.0, h->xwLm, xstride, eL, &h->st->abort,
-                             h->stream);
+      gir::launch_trsv_cols(h->S, ld, h->permS, h->store, n, false, h->Tb, ld, nr, h->Linv,
+                            h->Yb, ld, 1.0, h->xwLm, xstride, eL, &h->st->abort, h->stream);
     }));
     const int eU = next_epoch(h);
     GIR_TRY(timed(h, kKcTrsvU, tbytes + 16.0 * nr * nn, h->stream, nullptr, 0, [&] {
-      gir::launch_trsv_multi(h->S, ld, h->permS, h->store, n, true, h->Yb, ld, nullptr, nr,
-                             h->Uinv, C + (size_t)c0 * ld, ld, h->scale, h->xwUm, xstride, eU,
-                             &h->st->abort, h->stream);
+      gir::launch_trsv_cols(h->S, ld, h->permS, h->store, n, true, h->Yb, ld, nr, h->Uinv,
+                            C + (size_t)c0 * ld, ld, h->scale, h->xwUm, xstride, eU,
+                            &h->st->abort, h->stream);
     }));
   }
   return 0;
