@@ -225,6 +225,15 @@ void launch_trsv_t(const void* S, int64_t ld, const int* permS, int store, int n
                    const double* in, const double* Dinv, const double* Q, double* y, double scale,
                    const int* permOut, double* out64, float* out32, uint64_t* xw, int epoch,
                    const CycleState* gate, int step, int* abortp, hipStream_t s);
+// the same for nr <= 8 right-hand sides as independent solves in one launch
+// (one grid row each): column c reads in + c * ldi, writes y + c * ldy (y may
+// be null) and out64 + c * ldo (scattered through permOut), and exchanges
+// through xw + c * xstride
+void launch_trsv_t_cols(const void* S, int64_t ld, const int* permS, int store, int n,
+                        bool upperT, const double* in, int64_t ldi, int nr, const double* Dinv,
+                        const double* Q, double* y, int64_t ldy, double scale,
+                        const int* permOut, double* out64, int64_t ldo, uint64_t* xw,
+                        int64_t xstride, int epoch, int* abortp, hipStream_t s);
 // out = alpha x y^T (n x n row-major, leading dimension ld)
 void launch_rank1(double alpha, const double* x, const double* y, int n, int64_t ld, double* out,
                   hipStream_t s);

@@ -1184,8 +1184,15 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
     const double* __restrict__ Q, double* __restrict__ y,
     double scale, const int* __restrict__ permOut, double* __restrict__ out64,
     float* __restrict__ out32, uint64_t* xw, uint32_t epoch, const CycleState* gate, int step,
-    int* abortp) {
+    int* abortp, ColStrides cs) {
   if (gated_off(gate, step)) return;
+  {
+    const int64_t col = blockIdx.y;
+    in += col * cs.in;
+    if (y) y += col * cs.y;
+    if (out64) out64 += col * cs.out;
+    xw += col * cs.xw;
+  }
   __shared__ double red[8][kTB];
   __shared__ double ysh[8][kTB];
   __shared__ double zsh[kTS];
@@ -1603,15 +1610,39 @@ void launch_colsum_abs(const double* A, int64_t ld, int n, double* partial, doub
                      nullptr, nullptr, t, out, nullptr, 0);
 }
 
+void launch_trsv_t_cols(const void* S, int64_t ld, const int* permS, int store, int n,
+                        bool upperT, const double* in, int64_t ldi, int nr, const double* Dinv,
+                        const double* Q, double* y, int64_t ldy, double scale,
+                        const int* permOut, double* out64, int64_t ldo, uint64_t* xw,
+                        int64_t xstride, int epoch, int* abortp, hipStream_t s) {
+  if (nr <= 0) return;
+  const dim3 grid(nblocks(n, kTS), (unsigned)nr);
+  const ColStrides cs{ldi, ldy, ldo, xstride};
+#define GIR_TT(F, U)                                                                          \
+  hipLaunchKernelGGL((k_trsv_t<F, U>), grid, dim3(kTSThreads), 0, s,                          \
+                     reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, Dinv, Q, y,  \
+                     scale, permOut, out64, nullptr, xw, (uint32_t)epoch, nullptr, 0, abortp, cs)
+  if (store == kStoreF16) {
+    if (upperT) GIR_TT(Fp16, true); else GIR_TT(Fp16, false);
+  } else if (store == kStoreBF16) {
+    if (upperT) GIR_TT(Bf16, true); else GIR_TT(Bf16, false);
+  } else {
+    if (upperT) GIR_TT(Fp32, true); else GIR_TT(Fp32, false);
+  }
+#undef GIR_TT
+}
+
 void launch_trsv_t(const void* S, int64_t ld, const int* permS, int store, int n, bool upperT,
                    const double* in, const double* Dinv, const double* Q, double* y, double scale,
                    const int* permOut, double* out64, float* out32, uint64_t* xw, int epoch,
                    const CycleState* gate, int step, int* abortp, hipStream_t s) {
   const unsigned grid = nblocks(n, kTS);
+  const ColStrides cs{0, 0, 0, 0};
 #define GIR_TT(F, U)                                                                        \
   hipLaunchKernelGGL((k_trsv_t<F, U>), dim3(grid), dim3(kTSThreads), 0, s,                  \
                      reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, Dinv, Q,   \
-                     y, scale, permOut, out64, out32, xw, (uint32_t)epoch, gate, step, abortp)
+                     y, scale, permOut, out64, out32, xw, (uint32_t)epoch, gate, step, abortp, \
+                     cs)
   if (store == kStoreF16) {
     if (upperT) GIR_TT(Fp16, true); else GIR_TT(Fp16, false);
   } else if (store == kStoreBF16) {

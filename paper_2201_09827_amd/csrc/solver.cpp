@@ -953,19 +953,43 @@ int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, voi
 }
 
 // C(:, 0:kk) = A-tilde Y(:, 0:kk) for fp64 columns (ld apart): the products
-// with A_u one column at a time, the two triangular solves for up to eight
-// columns at once (double-double: one column at a time)
+// with A_u (or A_u^T) for up to eight columns, then the two triangular solves
+// for those columns in one launch each (double-double: one column at a time)
 int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
   const int n = (int)h->n;
   const int64_t ld = h->ld;
-  if (h->u64 || h->trans) {
+  const int64_t xstride = 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
+  const double nn = (double)n;
+  const double tbytes = 0.5 * nn * (nn + 1.0) * (double)store_bytes(h->store);
+  if (h->trans && !h->u64) {
+    // A_u^T one column at a time, then M^-T for up to eight columns at once
+    for (int c0 = 0; c0 < kk; c0 += gir::kTrsvMaxRhs) {
+      const int nr = std::min(gir::kTrsvMaxRhs, kk - c0);
+      for (int c = 0; c < nr; ++c)
+        GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + 12.0 * nn, h->stream, nullptr, 0, [&] {
+          gir::launch_colsum(h->Au, 0, ld, n, Y + (size_t)(c0 + c) * ld, 1, h->colpart, nullptr,
+                             nullptr, h->Tb + (size_t)c * ld, nullptr, nullptr, 0, h->stream);
+        }));
+      const int eL = next_epoch(h);
+      GIR_TRY(timed(h, kKcTrsvL, tbytes + 16.0 * nr * nn, h->stream, nullptr, 0, [&] {
+        gir::launch_trsv_t_cols(h->S, ld, h->permS, h->store, n, false, h->Tb, ld, nr, h->Uinv,
+                                h->Uq, h->Yb, ld, 1.0, nullptr, nullptr, 0, h->xwLm, xstride, eL,
+                                &h->st->abort, h->stream);
+      }));
+      const int eU = next_epoch(h);
+      GIR_TRY(timed(h, kKcTrsvU, tbytes + 16.0 * nr * nn, h->stream, nullptr, 0, [&] {
+        gir::launch_trsv_t_cols(h->S, ld, h->permS, h->store, n, true, h->Yb, ld, nr, h->Linv,
+                                h->Lq, nullptr, 0, h->scale, h->permP, C + (size_t)c0 * ld, ld,
+                                h->xwUm, xstride, eU, &h->st->abort, h->stream);
+      }));
+    }
+    return 0;
+  }
+  if (h->u64) {
     for (int c = 0; c < kk; ++c)
       GIR_TRY(atilde(h, nullptr, Y + (size_t)c * ld, C + (size_t)c * ld, nullptr, nullptr, 0));
     return 0;
   }
-  const int64_t xstride = 2 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock) * gir::kTrsvBlock;
-  const double nn = (double)n;
-  const double tbytes = 0.5 * nn * (nn + 1.0) * (double)store_bytes(h->store);
   for (int c0 = 0; c0 < kk; c0 += gir::kTrsvMaxRhs) {
     const int nr = std::min(gir::kTrsvMaxRhs, kk - c0);
     // A_u read once for the chunk's columns
