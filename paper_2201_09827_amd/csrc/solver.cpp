@@ -691,18 +691,35 @@ int ingest(gmresir_ctx* h, const double* A, int64_t lda, bool make_lu_copy) {
   return 0;
 }
 
-int ingest_finish(gmresir_ctx* h, bool has_e) {
+// the scalars the ingest leaves on the device: ||A||_inf (bits), the
+// non-finite flag and the scale exponent
+struct IngestScalars {
   unsigned long long hv[2];
   int hi[2];
-  GIR_TRY(download_many(h, {{hv, h->norms, sizeof(hv)}, {hi, h->counter + 4, sizeof(hi)}}));
+};
+
+Piece ingest_piece_norms(gmresir_ctx* h, IngestScalars& r) {
+  return Piece{r.hv, h->norms, sizeof(r.hv)};
+}
+Piece ingest_piece_flags(gmresir_ctx* h, IngestScalars& r) {
+  return Piece{r.hi, h->counter + 4, sizeof(r.hi)};
+}
+
+void ingest_apply(gmresir_ctx* h, const IngestScalars& r, bool has_e) {
   double rowsum;
-  std::memcpy(&rowsum, &hv[1], 8);
+  std::memcpy(&rowsum, &r.hv[1], 8);
   h->norm_a = rowsum;
   if (has_e) {
-    h->e = hi[1];
+    h->e = r.hi[1];
     h->scale = std::ldexp(1.0, h->e);
   }
-  if (hi[0]) h->status = GMRESIR_ERANGE;
+  if (r.hi[0]) h->status = GMRESIR_ERANGE;
+}
+
+int ingest_finish(gmresir_ctx* h, bool has_e) {
+  IngestScalars r{};
+  GIR_TRY(download_many(h, {ingest_piece_norms(h, r), ingest_piece_flags(h, r)}));
+  ingest_apply(h, r, has_e);
   return 0;
 }
 
@@ -774,10 +791,15 @@ int run_lu(gmresir_ctx* h) {
   if (!h->u64 || h->uni)
     gir::launch_diag_inverses(h->S, h->ld, h->perm, h->store, n, h->Linv, h->Uinv, h->dtmp,
                               h->stream);
+  // the factorisation's state and the ingest's scalars in one round trip
   gir::CycleState hs{};
   int hflag = 0;
-  GIR_TRY(download_many(h, {{&hs, h->st, sizeof(hs)}, {&hflag, flag, sizeof(int)}}));
-  GIR_TRY(ingest_finish(h, true));
+  IngestScalars ir{};
+  GIR_TRY(download_many(h, {{&hs, h->st, sizeof(hs)},
+                            {&hflag, flag, sizeof(int)},
+                            ingest_piece_norms(h, ir),
+                            ingest_piece_flags(h, ir)}));
+  ingest_apply(h, ir, true);
   if (hs.abort) {
     set_error("LU: a device-side wait exceeded its bound");
     return GMRESIR_EINTERNAL;
@@ -1544,13 +1566,16 @@ int gmresir_factor(const double* A, int64_t n, int64_t lda, const gmresir_opts* 
   const double t0 = now_s();
   GIR_TRY(make_ctx(A, n, lda, opts, stream, out, &h));
   int rc = alloc_common(h);
+  // the solve's buffers first: their zeroing is then complete by the time
+  // the factorisation's results are read back, and the final
+  // synchronisation finds an idle stream
+  if (rc == 0) rc = alloc_solve(h);
   if (rc == 0) rc = ingest(h, A, lda, true);
   if (rc == 0) {
     h->permP = h->perm;
     h->permS = h->perm;
     rc = run_lu(h);
   }
-  if (rc == 0) rc = alloc_solve(h);
   if (rc == 0) {
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
