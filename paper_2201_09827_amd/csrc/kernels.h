@@ -91,7 +91,8 @@ void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, i
                        const CycleState* gate, int step, int* abort, hipStream_t s);
 // the lower (upper = false) or upper solve for nr <= 8 right-hand sides as
 // nr independent solves in one launch (one grid row each): in / out
-// column-major (ldi / ldo), out = scale * solution (the lower solve: scale 1);
+// column-major (ldi / ldo); the upper solve writes scale * solution, the
+// lower solve its unscaled solution (scale is ignored);
 // xw holds nr slots of xstride >= 2 * ceil(n/128) * 128 tagged words
 constexpr int kTrsvMaxRhs = 8;
 void launch_trsv_cols(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
