@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define GMRESIR_ABI_VERSION 1
+#define GMRESIR_ABI_VERSION 2
 
 typedef enum {
   GMRESIR_OK = 0,
@@ -82,11 +82,12 @@ typedef struct {
                              preconditioner)                                  */
   int32_t keep_recycle;   /* 1: the recycled pair survives between
                              gmresir_solve calls on the same handle          */
-  int32_t timing;         /* bit c (0-7) set: bracket every launch of kernel
-                             class c (the order listed at gmresir_kernel_stats)
-                             with HIP events on the stream it runs on; bits
-                             8-15 = s > 1: only every s-th launch of each
-                             timed class (fewer events in the stream); 0: off */
+  int32_t timing;         /* bit c (classes 0-7) or bit c + 8 (classes 8-15)
+                             set: bracket every launch of kernel class c (the
+                             order listed at gmresir_kernel_stats) with HIP
+                             events on the stream it runs on; bits 8-15 =
+                             s > 1: only every s-th launch of each timed
+                             class (fewer events in the stream); 0: off     */
   int32_t matvec_u;       /* 1: the correction solve applies M^-1 and A-tilde in
                              u instead of u^2 (SGMRES-IR / RSGMRES-IR, Section 3;
                              u = FP64 only); x0 keeps u^2.  Default 0.          */
@@ -105,11 +106,29 @@ typedef struct {
   int32_t its[GMRESIR_MAX_STEPS];      /* Arnoldi steps per correction, the
                                           paper's "total (i1, i2, ...)"     */
   double berr[GMRESIR_MAX_STEPS + 1];  /* normwise backward error before
-                                          each correction and at the end    */
+                                          each correction and at the end:
+                                          ||r||_inf / (||A||_inf ||x||_inf +
+                                          ||b||_inf), r from the u_r residual */
   int32_t singular_col;                /* 1-based column of the zero pivot  */
   int32_t recycle_dim;                 /* dimension of U_k at the end       */
   double t_factor_s;                   /* wall time of gmresir_factor       */
   double t_solve_s;                    /* wall time of this gmresir_solve   */
+  double berr_cw[GMRESIR_MAX_STEPS + 1];  /* componentwise backward error at
+                                          the same points, max_i |r_i| /
+                                          (|A| |x| + |b|)_i with 0/0 = 0 (the
+                                          error measures of Table 2); NaN for
+                                          gmresir_solve_transposed            */
+  /* Stream time of the solve's phases (seconds; HIP events at the phase
+   * boundaries, so host decisions between launches count in the phase they
+   * interrupt).  They add up to the solve's device span.                   */
+  double t_x0_s;                       /* x0 = M^-1 b                        */
+  double t_residual_s;                 /* residuals, backward errors, test  */
+  double t_precond_s;                  /* r-hat and z = M^-1 r-hat           */
+  double t_recycle_s;                  /* QR(A-tilde U_k), projection of z,
+                                          deferred recycle refreshes         */
+  double t_arnoldi_s;                  /* Arnoldi cycles, least squares,
+                                          cycle updates and refreshes, x
+                                          update                             */
 } gmresir_info;
 
 typedef struct gmresir_ctx gmresir_ctx;
@@ -127,7 +146,9 @@ void gmresir_default_opts(gmresir_opts* opts);
  *
  *   A      device pointer, n x n float64, row-major, leading dimension lda.
  *          Read only; the library copies what it needs.
- *   n      order of A (n >= 1); lda >= n.
+ *   n      order of A, 1 <= n <= 16384 (EINVAL beyond: the pivot search
+ *          of a block column runs in at most 32 workgroups of 512 rows);
+ *          lda >= n.
  *   opts   host pointer to options (copied).
  *   stream hipStream_t or NULL.
  *   out    host pointer receiving a new handle (set to NULL on failure).
@@ -207,8 +228,10 @@ int gmresir_rank1(double alpha, const double* x, const double* y, int64_t n,
  *   stream hipStream_t or NULL.
  *
  * Returns 0, ENOCONV (no k converged; *k_best = 0), ESINGULAR / ERANGE as
- * gmresir_solve, or a negative error.  The handle's k and recycle state are
- * left as they were.
+ * gmresir_solve, or a negative error.  The handle's k is left as it was; a
+ * recycle space kept from earlier solves (opts.keep_recycle = 1) is dropped,
+ * because the trial solves reuse its buffers, so the next gmresir_solve starts
+ * without one (as on a new handle).
  */
 int gmresir_choose_k(gmresir_ctx* h, const double* b, int32_t kmax,
                      int32_t* k_best, int32_t* its, void* stream);
@@ -263,6 +286,24 @@ int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y,
                   void* stream);
 
 /*
+ * gmresir_errors -- the error measures of a computed solution (Table 2's
+ * columns), from a residual r = b - A x formed in double-double and rounded
+ * to fp64 (independent of the handle's u_r):
+ *   out[0]  normwise backward error ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf)
+ *   out[1]  componentwise backward error max_i |r_i| / (|A| |x| + |b|)_i
+ *           (0/0 = 0)
+ *   out[2]  forward error ||x - x_true||_inf / ||x_true||_inf, or NaN when
+ *           x_true is NULL
+ * b, x, x_true: device pointers of n float64 values (read only); out: host
+ * pointer to 3 doubles.  Uses the handle's fp64 copy of A and its scratch
+ * vectors (not re-entrant with a solve on the same handle).  Returns 0,
+ * EINVAL (null handle, b, x or out), ERANGE (handle from a non-finite A),
+ * or EHIP.
+ */
+int gmresir_errors(gmresir_ctx* h, const double* b, const double* x,
+                   const double* x_true, double* out, void* stream);
+
+/*
  * Per-kernel-class launch timing (handles created with opts.timing != 0).
  * One record per timed class that ran since the handle was created: the
  * number of
@@ -270,9 +311,12 @@ int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y,
  * the stream the kernels were launched on (launches an Arnoldi step skipped
  * on the device after convergence are not counted), and the algorithmic work
  * of those launches: bytes that must cross HBM (bound = 0) or floating-point
- * operations on the matrix cores (bound = 1).  Classes, bit 0 first:
- * "lu_panel", "lu_trsm", "lu_gemm" (factorisation), "trsv_lower",
- * "trsv_upper", "gemv_au", "residual", "ortho" (solve phase).  Each event
+ * operations (bound = 1).  Classes, in order: "lu_panel" (a block column's
+ * GEPP fused with the previous step's trailing update), "lu_trsm", "lu_gemm"
+ * (factorisation; flops), "trsv_lower", "trsv_upper", "gemv_au", "residual",
+ * "ortho" (solve-phase launches; bytes) and "arnoldi_step" (class 8, timing
+ * bit 16: one whole Arnoldi step, A-tilde v_j through the normalisation,
+ * with n^2 (s_A + s_f) plus one read of the basis as its bytes).  Each event
  * pair costs a few microseconds of stream time, so time only the classes of
  * interest, or a sample of their launches (opts.timing bits 8-15).
  *

@@ -26,6 +26,7 @@ __all__ = [
     "Handle",
     "EXPORTED",
     "KERNEL_CLASSES",
+    "timing_mask",
     "rank1",
     "solve_batched",
 ]
@@ -38,7 +39,17 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EINTERNAL",
 MAX_STEPS = 64
 # kernel classes of gmresir_kernel_stats, bit 0 first
 KERNEL_CLASSES = ("lu_panel", "lu_trsm", "lu_gemm", "trsv_lower", "trsv_upper", "gemv_au",
-                  "residual", "ortho")
+                  "residual", "ortho", "arnoldi_step")
+
+
+def timing_mask(classes, stride: int = 0) -> int:
+    """opts.timing for the named kernel classes (bits 0-7 for classes 0-7,
+    16-23 for classes 8-15) with every stride-th launch bracketed."""
+    m = 0
+    for c in classes:
+        i = KERNEL_CLASSES.index(c)
+        m |= 1 << (i if i < 8 else i + 8)
+    return m | ((stride & 0xFF) << 8 if stride > 1 else 0)
 
 # every symbol declared in include/gmresir.h
 EXPORTED = (
@@ -46,6 +57,7 @@ EXPORTED = (
     "gmresir_strerror", "gmresir_last_error", "gmresir_import_factors",
     "gmresir_export_factors", "gmresir_apply", "gmresir_kernel_stats", "gmresir_query",
     "gmresir_solve_transposed", "gmresir_rank1", "gmresir_choose_k", "gmresir_solve_batched",
+    "gmresir_errors",
 )
 
 
@@ -91,6 +103,12 @@ class Info(ctypes.Structure):
         ("recycle_dim", ctypes.c_int32),
         ("t_factor_s", ctypes.c_double),
         ("t_solve_s", ctypes.c_double),
+        ("berr_cw", ctypes.c_double * (MAX_STEPS + 1)),
+        ("t_x0_s", ctypes.c_double),
+        ("t_residual_s", ctypes.c_double),
+        ("t_precond_s", ctypes.c_double),
+        ("t_recycle_s", ctypes.c_double),
+        ("t_arnoldi_s", ctypes.c_double),
     ]
 
 
@@ -151,6 +169,8 @@ def load_library() -> ctypes.CDLL:
     lib.gmresir_export_factors.restype = ctypes.c_int
     lib.gmresir_apply.argtypes = [vp, i32, vp, vp, vp]
     lib.gmresir_apply.restype = ctypes.c_int
+    lib.gmresir_errors.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.gmresir_errors.restype = ctypes.c_int
     lib.gmresir_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
     lib.gmresir_kernel_stats.restype = ctypes.c_int
     lib.gmresir_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
@@ -220,6 +240,12 @@ def _info_dict(info: Info) -> dict:
         "recycle_dim": int(info.recycle_dim),
         "t_factor_s": float(info.t_factor_s),
         "t_solve_s": float(info.t_solve_s),
+        "berr_cw": [float(info.berr_cw[i]) for i in range(min(steps, MAX_STEPS) + 1)],
+        "t_x0_s": float(info.t_x0_s),
+        "t_residual_s": float(info.t_residual_s),
+        "t_precond_s": float(info.t_precond_s),
+        "t_recycle_s": float(info.t_recycle_s),
+        "t_arnoldi_s": float(info.t_arnoldi_s),
     }
 
 
@@ -289,6 +315,28 @@ class Handle:
         if rc < 0:
             raise _err(self._lib, rc)
         return x, _info_dict(info)
+
+    def errors(self, b, x, x_true=None, stream=None):
+        """Error measures of a solution from a double-double residual:
+        returns (normwise backward error, componentwise backward error,
+        forward error or nan without x_true)."""
+        import torch
+        ptr = self._live()
+        for name, t in (("b", b), ("x", x), ("x_true", x_true)):
+            if t is None and name == "x_true":
+                continue
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                    and t.shape == (self.n,) and t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 CUDA vector of length n")
+        out = (ctypes.c_double * 3)()
+        rc = self._lib.gmresir_errors(ptr, ctypes.c_void_p(b.data_ptr()),
+                                      ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(x_true.data_ptr() if x_true is not None
+                                                      else None),
+                                      out, _stream(stream))
+        if rc != 0:
+            raise _err(self._lib, rc)
+        return float(out[0]), float(out[1]), float(out[2])
 
     def apply(self, op: int, v, stream=None):
         """op 0: M^-1 v; op 1: A-tilde v; op 2: M^-T v; op 3: M^-T A_u^T v

@@ -111,6 +111,16 @@ __device__ __forceinline__ void atomic_max_nonneg(unsigned long long* p, double 
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
+// slot of a handle's norms array (as bits) that the residual kernels raise to
+// the componentwise backward error max_i |r_i| / (|A| |x| + |b|)_i
+constexpr int kNormCw = 4;
+
+// one term of that maximum: 0/0 = 0, r/0 = inf
+__device__ __forceinline__ double cw_ratio(double r, double den) {
+  if (r == 0.0) return 0.0;
+  return den > 0.0 ? r / den : __builtin_inf();
+}
+
 // Bounded waits on a device-scope flag.  The flag is polled with relaxed
 // loads (an acquire load would invalidate the caches on every poll) and a
 // single acquire fence follows the successful poll.  Returns false on

@@ -73,7 +73,8 @@ void launch_gemv_au_multi(const float* Au, int64_t ld, const int* permA, int n, 
 // t[i] = sum_c A[permA[i]][c] v[c] with fp64 A and v, fp64 accumulation
 void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const double* v,
                      double* t, const CycleState* gate, int step, hipStream_t s);
-// r = b - A x (fp64); norms[0] = max|r| bits, norms[1] = max|x| bits (zeroed here)
+// r = b - A x (fp64); norms[0] = max|r| bits, norms[1] = max|x| bits,
+// norms[kNormCw] = componentwise backward error bits (all three zeroed here)
 void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
                      double* r, unsigned long long* norms, hipStream_t s);
 // y = L^-1 (in gathered by permIn), fp64; L unit lower in S rows permS;
@@ -165,6 +166,20 @@ void launch_x_update(double* x, const void* d, int v64, double s, int n, hipStre
 void launch_div_u(const void* w, double s, void* out, int v64, int n, hipStream_t st);
 // out[0] = max |v_i| (as bits)
 void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t st);
+// out[0] = max_i sum_j |A[i][j]| (bits; zeroed here), the rows summed in the
+// order of launch_ingest's row sums (bit-identical ||A||_inf)
+void launch_rowsum_max(const double* A, int64_t n, int64_t lda, unsigned long long* out,
+                       hipStream_t s);
+// out[0..2] (device) = normwise backward error, componentwise backward error
+// and forward error (NaN without has_xt) from the reduction words w:
+// w[0] max |r|, w[1] max |x|, w[2] max |b|, w[3] ||A||_inf, w[kNormCw] the
+// componentwise error, w[5] max |x - x_true|, w[6] max |x_true| (as bits)
+void launch_errors_finish(const unsigned long long* w, int has_xt, double* out, hipStream_t s);
+// sets the text gmresir_last_error returns (defined with the C ABI)
+void set_last_error(const char* s);
+// out[0] = max |x - x_true|, out[1] = max |x_true| (as bits)
+void launch_ferr(const double* x, const double* xt, int n, unsigned long long* out,
+                 hipStream_t s);
 void launch_copy_f32_to_f64(const float* a, double* b, int n, hipStream_t s);
 void launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 // zeroes count (<= kMaxZeroSpans) spans of 4-byte words, p[j][0 .. n[j]), in

@@ -94,9 +94,14 @@ __device__ __forceinline__ Acc wave_sum_acc(Acc a) {
 // ---------------------------------------------------------------------------
 // row dot products of an fp64 matrix: one wave per row, 16-byte loads
 // ---------------------------------------------------------------------------
+// (with kAbs, *abs_sum receives sum |a_c| |v_c| in fp64 on every lane: the
+// denominator of the componentwise backward error)
+template <bool kAbs = false>
 __device__ __forceinline__ Acc row_dot_dd(const double* __restrict__ a,
-                                          const double* __restrict__ v, int n, int lane) {
+                                          const double* __restrict__ v, int n, int lane,
+                                          double* abs_sum = nullptr) {
   Acc acc0, acc1;
+  double s0 = 0.0, s1 = 0.0;
   const int n2 = n & ~1;
   int c = lane * 2;
   for (; c + 128 < n2; c += 256) {
@@ -108,15 +113,29 @@ __device__ __forceinline__ Acc row_dot_dd(const double* __restrict__ a,
     acc1.add_prod(a0.y, x0.y, 0.0);
     acc0.add_prod(a1.x, x1.x, 0.0);
     acc1.add_prod(a1.y, x1.y, 0.0);
+    if (kAbs) {
+      s0 = fma(fabs(a0.x), fabs(x0.x), s0);
+      s1 = fma(fabs(a0.y), fabs(x0.y), s1);
+      s0 = fma(fabs(a1.x), fabs(x1.x), s0);
+      s1 = fma(fabs(a1.y), fabs(x1.y), s1);
+    }
   }
   for (; c < n2; c += 128) {
     const double2 a0 = *reinterpret_cast<const double2*>(a + c);
     const double2 x0 = *reinterpret_cast<const double2*>(v + c);
     acc0.add_prod(a0.x, x0.x, 0.0);
     acc1.add_prod(a0.y, x0.y, 0.0);
+    if (kAbs) {
+      s0 = fma(fabs(a0.x), fabs(x0.x), s0);
+      s1 = fma(fabs(a0.y), fabs(x0.y), s1);
+    }
   }
-  for (int cc = n2 + lane; cc < n; cc += kWave) acc0.add_prod(a[cc], v[cc], 0.0);
+  for (int cc = n2 + lane; cc < n; cc += kWave) {
+    acc0.add_prod(a[cc], v[cc], 0.0);
+    if (kAbs) s0 = fma(fabs(a[cc]), fabs(v[cc]), s0);
+  }
   acc0.add(acc1);
+  if (kAbs) *abs_sum = wave_sum(s0 + s1);
   return wave_sum_acc(acc0);
 }
 
@@ -138,8 +157,10 @@ __global__ __launch_bounds__(256) void k_gemv_dd(const double* __restrict__ A, i
   }
 }
 
+// norms[0], norms[1] and norms[kNormCw] cleared
 __global__ void k_zero_norms(unsigned long long* p) {
   if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+  if (threadIdx.x == 2) p[kNormCw] = 0ull;
 }
 
 __global__ __launch_bounds__(256) void k_residual_dd(const double* __restrict__ A, int64_t ld,
@@ -151,8 +172,9 @@ __global__ __launch_bounds__(256) void k_residual_dd(const double* __restrict__ 
   const int lane = threadIdx.x % kWave;
   const bool rvalid = row0 < n;
   const int row = rvalid ? row0 : n - 1;  // out-of-range waves recompute a valid row
-  const DD ax = row_dot_dd(A + (int64_t)row * ld, x, n, lane).value();
-  __shared__ double mr[4], mx[4];
+  double axabs;
+  const DD ax = row_dot_dd<true>(A + (int64_t)row * ld, x, n, lane, &axabs).value();
+  __shared__ double mr[4], mx[4], mc[4];
   const int wave = threadIdx.x / kWave;
   if (lane == 0) {
     // b - (ax.h + ax.l), rounded once to fp64
@@ -161,15 +183,18 @@ __global__ __launch_bounds__(256) void k_residual_dd(const double* __restrict__ 
     if (rvalid) r[row] = ri;
     mr[wave] = fabs(ri);
     mx[wave] = fabs(x[row]);
+    mc[wave] = cw_ratio(fabs(ri), axabs + fabs(b[row]));
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, c = 0.0;
+    double a = 0.0, c = 0.0, e = 0.0;
     const int nw = min(4, (n - (int)blockIdx.x * 4));
     for (int w = 0; w < nw; ++w) {
       a = fmax(a, mr[w]);
       c = fmax(c, mx[w]);
+      e = fmax(e, mc[w]);
     }
+    atomic_max_nonneg(norms + kNormCw, e);
     atomic_max_nonneg(norms + 0, a);
     atomic_max_nonneg(norms + 1, c);
   }

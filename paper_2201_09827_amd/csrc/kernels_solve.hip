@@ -166,6 +166,12 @@ __global__ void k_zero_u64(unsigned long long* p, int k) {
   if (threadIdx.x < k) p[threadIdx.x] = 0ull;
 }
 
+// norms[0], norms[1] and norms[kNormCw] cleared
+__global__ void k_zero_resid_norms(unsigned long long* p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0ull;
+  if (threadIdx.x == 2) p[kNormCw] = 0ull;
+}
+
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, int64_t ld, int n,
                                                   const double* __restrict__ b,
                                                   const double* __restrict__ x,
@@ -177,6 +183,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, 
   const int row = rvalid ? row0 : n - 1;  // out-of-range waves recompute a valid row
   const double* a = A + (int64_t)row * ld;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  double ab0 = 0.0, ab1 = 0.0;  // sum |a| |x| (componentwise backward error)
   const int n2 = n & ~1;
   int c = lane * 2;
   for (; c + 384 < n2; c += 512) {
@@ -196,33 +203,50 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, 
     acc1 = fma(a2.y, x2.y, acc1);
     acc2 = fma(a3.x, x3.x, acc2);
     acc3 = fma(a3.y, x3.y, acc3);
+    ab0 = fma(fabs(a0.x), fabs(x0.x), ab0);
+    ab1 = fma(fabs(a0.y), fabs(x0.y), ab1);
+    ab0 = fma(fabs(a1.x), fabs(x1.x), ab0);
+    ab1 = fma(fabs(a1.y), fabs(x1.y), ab1);
+    ab0 = fma(fabs(a2.x), fabs(x2.x), ab0);
+    ab1 = fma(fabs(a2.y), fabs(x2.y), ab1);
+    ab0 = fma(fabs(a3.x), fabs(x3.x), ab0);
+    ab1 = fma(fabs(a3.y), fabs(x3.y), ab1);
   }
   for (; c < n2; c += 128) {
     const double2 a0 = *reinterpret_cast<const double2*>(a + c);
     const double2 x0 = *reinterpret_cast<const double2*>(x + c);
     acc0 = fma(a0.x, x0.x, acc0);
     acc1 = fma(a0.y, x0.y, acc1);
+    ab0 = fma(fabs(a0.x), fabs(x0.x), ab0);
+    ab1 = fma(fabs(a0.y), fabs(x0.y), ab1);
   }
-  for (int cc = n2 + lane; cc < n; cc += kWave) acc0 = fma(a[cc], x[cc], acc0);
+  for (int cc = n2 + lane; cc < n; cc += kWave) {
+    acc0 = fma(a[cc], x[cc], acc0);
+    ab0 = fma(fabs(a[cc]), fabs(x[cc]), ab0);
+  }
   acc0 += acc2;
   acc1 += acc3;
   const double s = wave_sum(acc0 + acc1);
-  __shared__ double mr[4], mx[4];
+  const double sabs = wave_sum(ab0 + ab1);
+  __shared__ double mr[4], mx[4], mc[4];
   const int wave = threadIdx.x / kWave;
   if (lane == 0) {
     const double ri = b[row] - s;
     if (rvalid) r[row] = ri;
     mr[wave] = fabs(ri);
     mx[wave] = fabs(x[row]);
+    mc[wave] = cw_ratio(fabs(ri), sabs + fabs(b[row]));
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, c = 0.0;
+    double a = 0.0, c = 0.0, e = 0.0;
     const int nw = min(4, (n - blockIdx.x * 4));
     for (int w = 0; w < nw; ++w) {
       a = fmax(a, mr[w]);
       c = fmax(c, mx[w]);
+      e = fmax(e, mc[w]);
     }
+    atomic_max_nonneg(norms + kNormCw, e);
     atomic_max_nonneg(norms + 0, a);
     atomic_max_nonneg(norms + 1, c);
   }
@@ -1361,7 +1385,7 @@ void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const
 
 void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
                      double* r, unsigned long long* norms, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, norms, 2);
+  hipLaunchKernelGGL(k_zero_resid_norms, dim3(1), dim3(64), 0, s, norms);
   hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 4)), dim3(256), 0, s, A, ld, n, b, x, r, norms);
 }
 
@@ -1569,6 +1593,85 @@ void launch_div_u(const void* w, double sc, void* out, int v64, int n, hipStream
   else
     hipLaunchKernelGGL(k_div_u<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
                        static_cast<const float*>(w), sc, static_cast<float*>(out), n);
+}
+
+// out[0] = max |x - x_true|, out[1] = max |x_true| (bits; zeroed here)
+__global__ void k_ferr(const double* __restrict__ x, const double* __restrict__ xt, int n,
+                       unsigned long long* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0, t = 0.0;
+  if (i < n) {
+    d = fabs(x[i] - xt[i]);
+    t = fabs(xt[i]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d = fmax(d, __shfl_xor(d, o, kWave));
+    t = fmax(t, __shfl_xor(t, o, kWave));
+  }
+  if ((threadIdx.x % kWave) == 0) {
+    atomic_max_nonneg(out, d);
+    atomic_max_nonneg(out + 1, t);
+  }
+}
+
+// one wave per row, lanes strided over the columns as in k_ingest, then the
+// same wave reduction: the same sums bit for bit
+__global__ __launch_bounds__(256) void k_rowsum_max(const double* __restrict__ A, int64_t n,
+                                                    int64_t lda, unsigned long long* out) {
+  __shared__ double ssum[4];
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  double s = 0.0;
+  if (row < n) {
+    const double* a = A + row * lda;
+    for (int64_t c = lane; c < n; c += kWave) s += fabs(a[c]);
+  }
+  s = wave_sum(s);
+  if (lane == 0) ssum[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < 4; ++w) r = fmax(r, ssum[w]);
+    atomic_max_nonneg(out, r);
+  }
+}
+
+void launch_rowsum_max(const double* A, int64_t n, int64_t lda, unsigned long long* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out, 1);
+  hipLaunchKernelGGL(k_rowsum_max, dim3(nblocks(n, 4)), dim3(256), 0, s, A, n, lda, out);
+}
+
+// out[0..2] from the reduction words of an error report (layout of
+// launch_errors_finish); one thread
+__global__ void k_errors_finish(const unsigned long long* __restrict__ w, int has_xt,
+                                double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double rmax = __longlong_as_double((long long)w[0]);
+  const double xmax = __longlong_as_double((long long)w[1]);
+  const double bmax = __longlong_as_double((long long)w[2]);
+  const double na = __longlong_as_double((long long)w[3]);
+  const double den = na * xmax + bmax;
+  out[0] = (rmax == 0.0) ? 0.0 : (den > 0.0 ? rmax / den : __builtin_inf());
+  out[1] = __longlong_as_double((long long)w[kNormCw]);
+  out[2] = __builtin_nan("");
+  if (has_xt) {
+    const double dmax = __longlong_as_double((long long)w[5]);
+    const double tmax = __longlong_as_double((long long)w[6]);
+    out[2] = (dmax == 0.0) ? 0.0 : (tmax > 0.0 ? dmax / tmax : __builtin_inf());
+  }
+}
+
+void launch_errors_finish(const unsigned long long* w, int has_xt, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_errors_finish, dim3(1), dim3(64), 0, s, w, has_xt, out);
+}
+
+void launch_ferr(const double* x, const double* xt, int n, unsigned long long* out,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, out, 2);
+  hipLaunchKernelGGL(k_ferr, dim3(nblocks(n, 256)), dim3(256), 0, s, x, xt, n, out);
 }
 
 void launch_maxabs(const double* v, int n, unsigned long long* out, hipStream_t s) {

@@ -14,12 +14,14 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -32,6 +34,15 @@ namespace {
 thread_local std::string g_last_error;
 
 void set_error(const std::string& s) { g_last_error = s; }
+
+}  // namespace
+
+namespace gir {
+// the text gmresir_last_error returns, for the entry points of other files
+void set_last_error(const char* s) { set_error(s); }
+}  // namespace gir
+
+namespace {
 
 #define GIR_HIP(call)                                                                 \
   do {                                                                                \
@@ -233,9 +244,15 @@ int dalloc(Arena& a, T** p, size_t count) {
 
 // kernel classes of gmresir_kernel_stats
 enum KClass { kKcPanel, kKcTrsm, kKcGemm, kKcTrsvL, kKcTrsvU, kKcGemv, kKcResid, kKcOrtho,
-              kKcCount };
+              kKcStep, kKcCount };
 const char* const kKcName[kKcCount] = {"lu_panel", "lu_trsm",  "lu_gemm",  "trsv_lower",
-                                       "trsv_upper", "gemv_au", "residual", "ortho"};
+                                       "trsv_upper", "gemv_au", "residual", "ortho",
+                                       "arnoldi_step"};
+// the factorisation's classes count matrix-core flops, the others HBM bytes
+constexpr bool kKcFlops[kKcCount] = {true, true, true, false, false, false, false, false, false};
+// bit of opts.timing that selects class c: bits 0-7 for classes 0-7, bits
+// 16-23 for classes 8-15 (bits 8-15 hold the sampling stride)
+constexpr int timing_bit(int c) { return c < 8 ? c : c + 8; }
 struct TimedRec {
   int cls;
   double work;
@@ -304,6 +321,10 @@ struct gmresir_ctx {
   double *tl = nullptr, *yl = nullptr;  // low parts of the double-double products (u64)
   double *C = nullptr, *U = nullptr, *Cn = nullptr, *Un = nullptr;
   int kc_keep = 0;  // columns of U carried to the next correction solve
+  // recycle set-up by Householder QR only (environment variable
+  // GMRESIR_RECYCLE_QR=householder at handle creation; a test hook for the
+  // branch that CholeskyQR2 breakdowns take)
+  bool force_hqr = false;
   Refresh pend;     // deferred refresh of the last cycle (V, C, U untouched meanwhile)
   // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
   // it runs) and the partial sums of the products with A^T
@@ -334,12 +355,18 @@ struct gmresir_ctx {
   std::vector<TimedRec> trec;
   KStat kstat[kKcCount];
   int64_t tcount[kKcCount] = {};  // launches per class (the timing stride)
+  // phase clock of a solve: an event on the stream at each phase boundary,
+  // tagged with the phase that ends there
+  std::vector<hipEvent_t> pev;
+  std::vector<int> pphase;
+  size_t pnext = 0;
 
   ~gmresir_ctx() {
     // device buffers belong to `arena` (freed by its destructor)
     if (st_host) pinned_release(st_host, pinned_bytes);
     for (auto& e2 : ev) (void)hipEventDestroy(e2);
     for (auto& e2 : tpool) (void)hipEventDestroy(e2);
+    for (auto& e2 : pev) (void)hipEventDestroy(e2);
   }};
 
 namespace {
@@ -347,6 +374,17 @@ namespace {
 // ---------------------------------------------------------------------------
 // launch timing
 // ---------------------------------------------------------------------------
+
+// bytes per element of the matrix the preconditioned product reads (A_u)
+double a_bytes(const gmresir_ctx* h) { return h->u64 ? 8.0 : 4.0; }
+
+// flops of GEPP on an h x kb block column (division and rank-1 update of the
+// rows below each pivot)
+double panel_flops(double hr, int kb) {
+  double f = 0.0;
+  for (int c = 0; c < kb; ++c) f += (hr - c - 1.0) * (1.0 + 2.0 * (kb - c - 1.0));
+  return f;
+}
 
 int pool_event(gmresir_ctx* h, hipEvent_t* e) {
   if (h->tnext == h->tpool.size()) {
@@ -358,25 +396,30 @@ int pool_event(gmresir_ctx* h, hipEvent_t* e) {
   return 0;
 }
 
+// launch() may return nothing or a status (nonzero is passed on)
+template <class Fn>
+int run_launch(Fn&& launch) {
+  if constexpr (std::is_same_v<decltype(launch()), int>) {
+    return launch();
+  } else {
+    launch();
+    return 0;
+  }
+}
+
 // Runs launch() bracketed by two events on s when timing is on.
 template <class Fn>
 int timed(gmresir_ctx* h, int cls, double work, hipStream_t s, const void* gate, int step,
           Fn&& launch) {
-  if (!((h->o.timing >> cls) & 1)) {
-    launch();
-    return 0;
-  }
+  if (!((h->o.timing >> timing_bit(cls)) & 1)) return run_launch(launch);
   // bits 8-15: bracket only every s-th launch of the class
   const int stride = (h->o.timing >> 8) & 0xFF;
-  if (stride > 1 && (h->tcount[cls]++ % stride) != 0) {
-    launch();
-    return 0;
-  }
+  if (stride > 1 && (h->tcount[cls]++ % stride) != 0) return run_launch(launch);
   TimedRec r{cls, work, gate != nullptr, step, nullptr, nullptr};
   GIR_TRY(pool_event(h, &r.a));
   GIR_TRY(pool_event(h, &r.b));
   GIR_HIP(hipEventRecord(r.a, s));
-  launch();
+  GIR_TRY(run_launch(launch));
   GIR_HIP(hipEventRecord(r.b, s));
   h->trec.push_back(r);
   return 0;
@@ -402,6 +445,36 @@ int flush_timing(gmresir_ctx* h) {
   }
   h->trec.clear();
   h->tnext = 0;
+  return 0;
+}
+
+// phases of a solve (gmresir_info's timers)
+enum { kPhStart = 0, kPhX0, kPhResidual, kPhPrecond, kPhRecycle, kPhArnoldi, kPhCount };
+
+// records the end of phase ph on the handle's stream
+int phase_mark(gmresir_ctx* h, int ph) {
+  if (h->pnext == h->pev.size()) {
+    hipEvent_t e = nullptr;
+    GIR_HIP(hipEventCreate(&e));
+    h->pev.push_back(e);
+    h->pphase.push_back(0);
+  }
+  h->pphase[h->pnext] = ph;
+  GIR_HIP(hipEventRecord(h->pev[h->pnext], h->stream));
+  ++h->pnext;
+  return 0;
+}
+
+// stream time between consecutive marks, summed per phase (seconds); the
+// stream must have passed the last mark
+int phase_times(gmresir_ctx* h, double* t) {
+  for (int p = 0; p < kPhCount; ++p) t[p] = 0.0;
+  for (size_t i = 1; i < h->pnext; ++i) {
+    float ms = 0.0f;
+    GIR_HIP(hipEventElapsedTime(&ms, h->pev[i - 1], h->pev[i]));
+    t[h->pphase[i]] += 1e-3 * (double)ms;
+  }
+  h->pnext = 0;
   return 0;
 }
 
@@ -440,9 +513,9 @@ int validate_opts(const gmresir_opts* o) {
     set_error("invalid tau, imax or maxit");
     return GMRESIR_EINVAL;
   }
-  if (o->timing < 0 || o->timing >= (1 << 16)) {
-    set_error("timing must be a bit mask of the kernel classes (bits 0-7) and a stride "
-              "(bits 8-15)");
+  if (o->timing < 0 || o->timing >= (1 << timing_bit(kKcCount))) {
+    set_error("timing must be a bit mask of the kernel classes (bits 0-7 and 16-23) and a "
+              "stride (bits 8-15)");
     return GMRESIR_EINVAL;
   }
   if (o->reserved[0] != 0) {
@@ -593,7 +666,7 @@ int alloc_common(gmresir_ctx* h) {
   }
   GIR_TRY(dalloc(h->arena, &h->st, 1));
   GIR_TRY(dalloc(h->arena, &h->counter, 8));
-  GIR_TRY(dalloc(h->arena, &h->norms, 4));
+  GIR_TRY(dalloc(h->arena, &h->norms, 8));
   ZeroList zl;
   zl.add(h->st, sizeof(gir::CycleState));
   zl.add(h->counter, sizeof(unsigned) * 8);
@@ -749,7 +822,8 @@ int run_lu(gmresir_ctx* h) {
   int* prow = nullptr;
   GIR_TRY(dalloc(h->arena, &prow, 2 * (size_t)n));
   h->perm_rest = prow;
-  const double es = (double)store_bytes(h->store);
+  // work of each launch for the timing records: flops (panel GEPP, the
+  // block-row solve, the rank-kb trailing products)
   int step = 0;
   for (int k0 = 0; k0 < n; k0 += kNb, ++step) {
     a.k0 = k0;
@@ -758,29 +832,29 @@ int run_lu(gmresir_ctx* h) {
     int* pcopy = prow + (size_t)(step & 1) * n;  // written by block column `step`
     if (k0 == 0) {
       a.perm_copy = pcopy;
-      GIR_TRY(timed(h, kKcPanel, 2.0 * hr * kb * es, s0, nullptr, 0,
+      GIR_TRY(timed(h, kKcPanel, panel_flops(hr, a.kb), s0, nullptr, 0,
                     [&] { gir::launch_panel_step(a, h->store, s0); }));
     }
     if (M <= 0) break;
     const int c1 = k0 + a.kb;                // next block column
     const int c2 = std::min(n, c1 + kNb);    // ... and the columns beyond it
-    GIR_TRY(timed(h, kKcTrsm, (0.5 * kb * kb + 2.0 * kb * (n - c1)) * es, s0, nullptr, 0,
+    GIR_TRY(timed(h, kKcTrsm, kb * (kb - 1.0) * (n - c1), s0, nullptr, 0,
                   [&] { gir::launch_trsm(a, h->store, c1, n, s0); }));
-    GIR_TRY(timed(h, kKcGemm, (2.0 * M * (c2 - c1) + M * kb + kb * (c2 - c1)) * es, s0, nullptr,
+    GIR_TRY(timed(h, kKcGemm, 2.0 * M * (c2 - c1) * kb, s0, nullptr,
                   0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
     gir::PanelArgs an = a;
     an.k0 = c1;
     an.kb = std::min(kNb, n - c1);
     an.perm_copy = prow + (size_t)((step + 1) & 1) * n;
     const double hn = (double)(n - c1);
-    const double pbytes = 2.0 * hn * an.kb * es;
+    const double pflops = panel_flops(hn, an.kb);
     if (c2 < n) {
-      const double gbytes = (2.0 * M * (n - c2) + M * kb + kb * (n - c2)) * es;
-      GIR_TRY(timed(h, kKcPanel, pbytes + gbytes, s0, nullptr, 0, [&] {
+      const double gflops = 2.0 * M * (n - c2) * kb;
+      GIR_TRY(timed(h, kKcPanel, pflops + gflops, s0, nullptr, 0, [&] {
         gir::launch_panel_update(an, a, h->store, pcopy, c2, n, s0);
       }));
     } else {
-      GIR_TRY(timed(h, kKcPanel, pbytes, s0, nullptr, 0,
+      GIR_TRY(timed(h, kKcPanel, pflops, s0, nullptr, 0,
                     [&] { gir::launch_panel_step(an, h->store, s0); }));
     }
   }
@@ -832,6 +906,10 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
   if (!h) return GMRESIR_ENOMEM;
   h->n = n;
   h->ld = (n + 63) / 64 * 64;
+  {
+    const char* q = std::getenv("GMRESIR_RECYCLE_QR");
+    h->force_hqr = q && std::strcmp(q, "householder") == 0;
+  }
   h->o = *opts;
   h->m = opts->m;
   h->k = opts->k;
@@ -1156,10 +1234,32 @@ int resolve_pending(gmresir_ctx* h, bool keep) {
 // C = QR(A-tilde U) by CholeskyQR2 in fp64, U <- U R^-1 (the recycled space
 // at the start of a correction solve); *ok = false when a Cholesky factor
 // breaks down (the space is then dropped)
+// C R = Z (Z = A-tilde U in h->C, n x kk) by Householder QR on the host,
+// then U = U R^-1 on the device
+int householder_recycle(gmresir_ctx* h, int kk, bool* ok) {
+  const int64_t ld = h->ld;
+  const int n = (int)h->n;
+  std::vector<double> Z((size_t)ld * kk), Q((size_t)n * kk), R((size_t)kk * kk),
+      Ri((size_t)kk * kk);
+  GIR_TRY(download(h, Z.data(), h->C, sizeof(double) * (size_t)ld * kk));
+  *ok = gir::la::qr_thin(Z.data(), (int)ld, n, kk, Q.data(), R.data());
+  if (!*ok) return 0;
+  std::fill(Z.begin(), Z.end(), 0.0);  // Q in the padded column layout
+  for (int j = 0; j < kk; ++j)
+    std::copy(Q.begin() + (size_t)j * n, Q.begin() + (size_t)(j + 1) * n,
+              Z.begin() + (size_t)j * ld);
+  GIR_TRY(upload(h, h->C, Z.data(), sizeof(double) * (size_t)ld * kk));
+  gir::la::inv_upper(R.data(), kk, Ri.data());
+  GIR_TRY(combine(h, basis(h, h->U, kk, ld, nullptr, 0, ld), Ri, kk, h->Un));
+  std::swap(h->U, h->Un);
+  return 0;
+}
+
 int recompute_recycle(gmresir_ctx* h, int kk, bool* ok) {
   const int64_t ld = h->ld;
   GIR_TRY(atilde_block(h, h->U, kk, h->C));
   GIR_HIP(hipGetLastError());
+  if (h->force_hqr) return householder_recycle(h, kk, ok);
   std::vector<double> G1, G2, R1(kk * kk), R2(kk * kk), Ri(kk * kk), Rt(kk * kk);
   GIR_TRY(gram(h, basis(h, h->C, kk, ld, nullptr, 0, ld), h->C, kk, G1));
   *ok = gir::la::cholesky_upper(G1.data(), kk, R1.data());
@@ -1182,6 +1282,13 @@ int recompute_recycle(gmresir_ctx* h, int kk, bool* ok) {
     gir::la::inv_upper(Rt.data(), kk, Ri.data());
     GIR_TRY(combine(h, basis(h, h->U, kk, ld, nullptr, 0, ld), Ri, kk, h->Un));
     std::swap(h->U, h->Un);
+  }
+  if (!*ok) {
+    // CholeskyQR2 broke down (the Gram matrix of Z = A-tilde U is not
+    // numerically positive definite): Householder QR of Z on the host, the
+    // factorisation the method states.  h->C still holds Z.  Only an exactly
+    // rank-deficient Z (no R^-1) drops the space.
+    GIR_TRY(householder_recycle(h, kk, ok));
   }
   return 0;
 }
@@ -1238,6 +1345,7 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       GIR_HIP(hipGetLastError());
     }
   }
+  GIR_TRY(phase_mark(h, kPhRecycle));
 
   std::vector<double> Hh((size_t)(m + 1) * m), Bh((size_t)std::max(k, 1) * m), y((size_t)m + 1);
   while (true) {
@@ -1272,6 +1380,12 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     int queued = 0;
     const size_t trec0 = h->trec.size();
     for (int j = 0; j < nsteps; ++j) {
+      // one Arnoldi step, timed as a whole under its own class: A_u v_j and
+      // the factors once each (the HBM model of the step) plus one read of
+      // the basis [C_k V_j]
+      const double step_bytes = (double)n * (double)n * (double)(a_bytes(h) + store_bytes(h->store)) +
+                                (8.0 * kc + (double)h->ue * (j + 1)) * n + 4.0 * h->ue * n;
+      GIR_TRY(timed(h, kKcStep, step_bytes, s, h->st, j, [&]() -> int {
       GIR_TRY(atilde(h, vcol(h, j), nullptr, nullptr, h->wu, h->st, j));
       gir::OrthoArgs a{};
       a.X = basis(h, h->C, kc, ld, h->V, j + 1, ld);
@@ -1306,6 +1420,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
         gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
       }));
       gir::launch_normalize(h->wu, vcol(h, j + 1), h->u64, h->Hd, m + 1, j, n, h->st, s);
+      return 0;
+      }));
       static_assert(sizeof(gir::CycleState) % 4 == 0, "CycleState is copied as words");
       gir::launch_copy_words(&h->st_host[j], h->st, sizeof(gir::CycleState) / 4, s);
       GIR_HIP(hipEventRecord(h->ev[j % kEventRing], s));
@@ -1429,6 +1545,8 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     h->kc_keep = 0;
     h->pend.active = false;
   }
+  h->pnext = 0;
+  GIR_TRY(phase_mark(h, kPhStart));
   gir::launch_copy_i32(reinterpret_cast<int*>(h->b), reinterpret_cast<const int*>(bcol), 2 * n, s);
   gir::launch_maxabs(h->b, n, h->norms + 2, s);
   unsigned long long bbits = 0;
@@ -1442,6 +1560,7 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   }
   // x0 = M^-1 b in u^2, kept in fp64
   GIR_TRY(precond(h, h->b, nullptr, h->permP, h->x, nullptr, nullptr, 0));
+  GIR_TRY(phase_mark(h, kPhX0));
   int status = GMRESIR_ENOCONV;
   const int imax = h->o.imax;
   int i = 0;
@@ -1457,14 +1576,20 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
                       gir::launch_residual(h->A64, h->ld, n, h->b, h->x, h->r64, h->norms, s);
                   }));
     GIR_HIP(hipGetLastError());
-    unsigned long long nb[2];
+    unsigned long long nb[gir::kNormCw + 1];
     GIR_TRY(download(h, nb, h->norms, sizeof(nb)));
-    double rmax, xmax;
+    GIR_TRY(phase_mark(h, kPhResidual));
+    double rmax, xmax, etac;
     std::memcpy(&rmax, &nb[0], 8);
     std::memcpy(&xmax, &nb[1], 8);
+    std::memcpy(&etac, &nb[gir::kNormCw], 8);
     const double den = (h->trans ? h->norm_a1 : h->norm_a) * xmax + bmax;
     const double eta = (rmax == 0.0) ? 0.0 : (den > 0.0 ? rmax / den : INFINITY);
-    if (i <= GMRESIR_MAX_STEPS) inf.berr[i] = eta;
+    if (i <= GMRESIR_MAX_STEPS) {
+      inf.berr[i] = eta;
+      // the products with A^T do not form |A^T| |lambda|
+      inf.berr_cw[i] = h->trans ? NAN : etac;
+    }
     if (!std::isfinite(eta)) {
       status = GMRESIR_ERANGE;
       break;
@@ -1476,15 +1601,18 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
     if (i >= imax) break;
     gir::launch_scale_round(h->r64, rmax, h->t64, n, h->u64, s);  // r-hat = fl_u(r / s)
     GIR_TRY(precond(h, h->t64, nullptr, h->permP, nullptr, h->zu, nullptr, 0, true));
+    GIR_TRY(phase_mark(h, kPhPrecond));
     SolveStats ss;
     GIR_TRY(gcrodr(h, ss));
     inf.its[i] = ss.its;
     inf.total_its += ss.its;
     gir::launch_x_update(h->x, h->du, h->u64, rmax, n, s);
     GIR_HIP(hipGetLastError());
+    GIR_TRY(phase_mark(h, kPhArnoldi));
   }
   // the last refresh is needed only when the space is kept for the next call
   GIR_TRY(resolve_pending(h, h->o.keep_recycle != 0));
+  GIR_TRY(phase_mark(h, kPhRecycle));
   inf.steps = i;
   inf.status = status;
   inf.recycle_dim = h->kc_keep;
@@ -1492,6 +1620,15 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   GIR_HIP(hipStreamSynchronize(s));
   inf.t_factor_s = h->t_factor;
   inf.t_solve_s = now_s() - t0;
+  {
+    double tp[kPhCount];
+    GIR_TRY(phase_times(h, tp));
+    inf.t_x0_s = tp[kPhX0];
+    inf.t_residual_s = tp[kPhResidual];
+    inf.t_precond_s = tp[kPhPrecond];
+    inf.t_recycle_s = tp[kPhRecycle];
+    inf.t_arnoldi_s = tp[kPhArnoldi];
+  }
   if (info) *info = inf;
   return status;
 }
@@ -1703,7 +1840,7 @@ int gmresir_choose_k(gmresir_ctx* h, const double* b, int32_t kmax, int32_t* k_b
     return GMRESIR_EINVAL;
   }
   if (stream) h->stream = reinterpret_cast<hipStream_t>(stream);
-  const int k_saved = h->k, keep_saved = h->o.keep_recycle, kc_saved = h->kc_keep;
+  const int k_saved = h->k, keep_saved = h->o.keep_recycle;
   h->o.keep_recycle = 0;
   int best = 0, best_its = -1, limit = kmax, rc = 0, first_status = 0;
   for (int k = 0; k <= kmax && k <= limit; ++k) {
@@ -1729,7 +1866,11 @@ int gmresir_choose_k(gmresir_ctx* h, const double* b, int32_t kmax, int32_t* k_b
     for (int k = limit + 1; k <= kmax; ++k) its[k] = -1;
   h->k = k_saved;
   h->o.keep_recycle = keep_saved;
-  h->kc_keep = kc_saved;
+  // the trial solves overwrote (and may have swapped) the buffers of the
+  // kept pair, so a space kept from an earlier solve no longer satisfies
+  // A-tilde U_k = C_k: it is dropped, and the next solve starts without one
+  h->kc_keep = 0;
+  h->pend.active = false;
   if (rc < 0) return rc;
   *k_best = best;
   return best_its < 0 ? (first_status ? first_status : GMRESIR_ENOCONV) : GMRESIR_OK;
@@ -1832,6 +1973,48 @@ int gmresir_apply(gmresir_ctx* h, int32_t op, const double* v, double* y, void* 
   return 0;
 }
 
+int gmresir_errors(gmresir_ctx* h, const double* b, const double* x, const double* x_true,
+                   double* out, void* stream) {
+  if (!h || !b || !x || !out) {
+    set_error("invalid errors arguments");
+    return GMRESIR_EINVAL;
+  }
+  if (h->status == GMRESIR_ERANGE) return GMRESIR_ERANGE;
+  if (stream) h->stream = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = h->stream;
+  const int n = (int)h->n;
+  // the caller's vectors are copied into the handle's aligned scratch first
+  gir::launch_copy_i32(reinterpret_cast<int*>(h->y64), reinterpret_cast<const int*>(b), 2 * n, s);
+  gir::launch_copy_i32(reinterpret_cast<int*>(h->t64), reinterpret_cast<const int*>(x), 2 * n, s);
+  gir::launch_maxabs(h->y64, n, h->norms + 2, s);
+  gir::launch_residual_dd(h->A64, h->ld, n, h->y64, h->t64, h->r64, h->norms, s);
+  GIR_HIP(hipGetLastError());
+  unsigned long long nb[gir::kNormCw + 1];
+  GIR_TRY(download(h, nb, h->norms, sizeof(nb)));
+  double rmax, xmax, bmax, etac;
+  std::memcpy(&rmax, &nb[0], 8);
+  std::memcpy(&xmax, &nb[1], 8);
+  std::memcpy(&bmax, &nb[2], 8);
+  std::memcpy(&etac, &nb[gir::kNormCw], 8);
+  const double den = h->norm_a * xmax + bmax;
+  out[0] = (rmax == 0.0) ? 0.0 : (den > 0.0 ? rmax / den : INFINITY);
+  out[1] = etac;
+  out[2] = NAN;
+  if (x_true) {
+    gir::launch_copy_i32(reinterpret_cast<int*>(h->y64), reinterpret_cast<const int*>(x_true),
+                         2 * n, s);
+    gir::launch_ferr(h->t64, h->y64, n, h->norms + 2, s);
+    GIR_HIP(hipGetLastError());
+    unsigned long long fb[2];
+    GIR_TRY(download(h, fb, h->norms + 2, sizeof(fb)));
+    double dmax, tmax;
+    std::memcpy(&dmax, &fb[0], 8);
+    std::memcpy(&tmax, &fb[1], 8);
+    out[2] = (dmax == 0.0) ? 0.0 : (tmax > 0.0 ? dmax / tmax : INFINITY);
+  }
+  return 0;
+}
+
 int gmresir_kernel_stats(gmresir_ctx* h, gmresir_kernel_stat* out, int32_t cap,
                          int32_t* count) {
   if (!h || !count || cap < 0 || (cap > 0 && !out)) {
@@ -1851,7 +2034,7 @@ int gmresir_kernel_stats(gmresir_ctx* h, gmresir_kernel_stat* out, int32_t cap,
       std::memset(&r, 0, sizeof(r));
       std::strncpy(r.name, kKcName[k], sizeof(r.name) - 1);
       r.launches = (int32_t)h->kstat[k].launches;
-      r.bound = 0;
+      r.bound = kKcFlops[k] ? 1 : 0;
       r.total_ms = h->kstat[k].ms;
       r.work = h->kstat[k].work;
     }

@@ -170,6 +170,19 @@ def test_preconditioner_full_size_properties(lib, n, uf, u):
     for i, j in enumerate(ipiv):
         perm[[i, j]] = perm[[j, i]]
     pt = torch.from_numpy(perm).to("cuda")
+    # the library's own factors at this size: partial pivoting (|L| <= 1) and
+    # the blocked-GEPP componentwise backward error of P A_f = L U, in fp64
+    af = a * 2.0 ** e
+    af = af.half().double() if uf == "fp16" else af.float().double()
+    lmax = torch.max(torch.abs(torch.tril(L, -1))).item()
+    lhs = torch.abs(af[pt] - L @ U)
+    rhs = torch.abs(L) @ torch.abs(U)
+    c = 2 * (n // NB + 3) * fp.unit_roundoff(uf)
+    worst = torch.max(lhs / (c * rhs + 1e-300)).item()
+    log(f"[apply-full] n={n} max|L| {lmax:.3f}; backward error of P A_f = L U / bound {worst:.3f}")
+    assert lmax <= 1.0
+    assert worst <= 1.0
+    del af, lhs, rhs
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
     v = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
@@ -442,4 +455,4 @@ def test_kernel_timing_records_and_sampling(lib):
     assert s1["lu_panel"]["total_ms"] > 0 and s2["lu_panel"]["total_ms"] > 0
     assert torch.equal(x1, x2)
     with pytest.raises(lib.GmresirError):
-        lib.factor(a, timing=1 << 16)
+        lib.factor(a, timing=1 << 24)
