@@ -14,15 +14,24 @@ and 1e10 systems of the same size is reported for both.
 
 Live kernel timing: the library brackets every launch of its kernel classes
 with HIP events on the stream they run on (opts.timing); the class with the
-largest share of the timed steps gives the roofline object (algorithmic
-bytes of its launches / their summed duration, against 8 TB/s).  HBM
-traffic measured with rocprofv3 counters is read from profiles/traffic.json
-when that file was taken on the current source of the kernel.
+largest share of the timed steps gives the roofline object: the
+factorisation's classes against the fp16 matrix-core peak (algorithmic flops
+of their launches over their summed duration), the solve's against 8 TB/s
+(algorithmic bytes).  The object also carries the whole factorisation's
+matrix-core fraction (2 n^3 / 3 flops over its wall time), the GEMM-only
+update launches, and one whole Arnoldi step against HBM (n^2 (s_A + s_f)
+bytes plus one read of the basis, per step).  HBM traffic measured with
+rocprofv3 counters is read from profiles/traffic.json when that file was
+taken on the current source of the kernel.
 
-cpu_baseline: the CPU oracle (test infrastructure, numpy) on a bounded
-sample of the same workload -- factor and solve of one randsvd system of
-order 6144 -- scaled to n = 8192 by the cost orders of its parts (n^3 for the
-factorisation, n^2 per Arnoldi step for the solve).
+Also reported: M2, the factorisation amortised over 16 right-hand sides
+solved in sequence with the recycle space kept between them (recycled and
+plain), and a comparator, plain fp64 LU-based refinement on the same GPU (the
+vendor LU through torch.linalg.lu_factor, fp64 corrections with its factors).
+
+cpu_baseline: the CPU oracle (test infrastructure, numpy) on the benchmark's
+own system at full order (factor and one solve, about 30 s on 16 cores), and
+a native fp64 LAPACK LU solve of it as context.
 
 Other configurations (precision triple, order, kappa, m, k) are selected by
 flags; --prolate16k adds the outcome of the ill-conditioned Toeplitz system of
@@ -44,6 +53,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP16_MFMA_PEAK_TFLOPS = 2500.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 # source files whose text determines each kernel class (traffic validity)
@@ -84,7 +94,10 @@ def parse():
                          "kappa2 log-uniform in [1e1, 1e8], 1-8 right-hand sides; 512 take "
                          "about 3 minutes) through gmresir_solve_batched")
     ap.add_argument("--batched-workers", type=int, default=8)
-    ap.add_argument("--cpu-n", type=int, default=6144, help="order of the oracle sample")
+    ap.add_argument("--m2-rhs", type=int, default=16,
+                    help="right-hand sides of the amortised variant (factor once, keep_recycle=1)")
+    ap.add_argument("--no-comparator", action="store_true",
+                    help="skip the vendor fp64 LU comparator")
     ap.add_argument("--gen", choices=("gpu", "cpu"), default="gpu",
                     help="draw the system on the GPU (torch) or on the CPU (numpy, slower)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -117,35 +130,43 @@ def traffic_for(kernel: str, launches_per_step: float):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(n_sample: int, n_target: int, kappa: float, seed: int, m: int, k: int):
-    """The oracle (as it stands) on one system of order n_sample."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(a_np, b_np, kappa: float, seed: int, m: int, k: int):
+    """The oracle (as it stands) on the benchmark's own system (factor and one
+    solve at the full order), plus a native fp64 LAPACK LU solve on the same
+    cores as context."""
+    import numpy as np
+    import scipy.linalg as sla
     from oracle import refine
-    from synthetic import randsvd_problem
     try:
         from threadpoolctl import threadpool_info
         threads = max([int(i.get("num_threads", 1)) for i in threadpool_info()] + [1])
     except Exception:
         threads = 1
-    prob = randsvd_problem(n_sample, kappa, seed)
+    n = a_np.shape[0]
     o = refine.Options(uf="fp16", u="fp32", ur="fp64", m=m, k=k, tau=1e-4, imax=10,
                        berr_target=1e-14, nb=64)
     t0 = time.perf_counter()
-    f = refine.factor(prob.a, o)
+    f = refine.factor(a_np, o)
     t1 = time.perf_counter()
-    x, info = refine.solve(f, prob.b)
+    x, info = refine.solve(f, b_np)
     t2 = time.perf_counter()
-    r = n_target / n_sample
-    t_scaled = (t1 - t0) * r ** 3 + (t2 - t1) * r ** 2
+    t3 = time.perf_counter()
+    lu = sla.lu_factor(a_np, check_finite=False)
+    xs = sla.lu_solve(lu, b_np, check_finite=False)
+    t4 = time.perf_counter()
+    rs = b_np - a_np @ xs
+    eta_s = float(np.max(np.abs(rs)) / (np.max(np.sum(np.abs(a_np), axis=1)) * np.max(np.abs(xs))
+                                        + np.max(np.abs(b_np))))
     return {
-        "value": 1.0 / t_scaled,
+        "value": 1.0 / (t2 - t0),
         "unit": "solves/s",
         "cores": threads,
         "kind": "oracle",
         "sample": (f"oracle factor ({t1 - t0:.1f} s) + solve ({t2 - t1:.1f} s, its {info.its}, "
-                   f"status {info.status}) of randsvd n={n_sample} kappa={kappa:g} seed={seed}, "
-                   f"scaled to n={n_target} by (n/{n_sample})^3 for the factor and "
-                   f"(n/{n_sample})^2 for the solve"),
+                   f"status {info.status}) of the benchmark's own randsvd system, n={n} "
+                   f"kappa={kappa:g} seed={seed}, one run"),
+        "context_lapack_fp64_lu_solve_s": t4 - t3,
+        "context_lapack_fp64_berr": eta_s,
     }
 
 
@@ -283,27 +304,39 @@ def main():
         return dt, infos, x
 
     # one untimed-region step with every kernel class timed picks the class
-    # with the largest share; the timed steps then bracket only that class
+    # with the largest share (the composite Arnoldi-step class aside); the
+    # timed steps then bracket only that class
     survey = {}
-    one_step(args.k, a, b, survey, (1 << len(g.KERNEL_CLASSES)) - 1)
+    one_step(args.k, a, b, survey, g.timing_mask(g.KERNEL_CLASSES[:8]))
     dom = max(survey, key=lambda kk: survey[kk]["total_ms"])
+
+    def rate(r):
+        if r["total_ms"] <= 0:
+            return 0.0
+        return r["work"] / (r["total_ms"] * 1e-3) / (1e12 if r["bound"] else 1e9)
+
     kernels = {name: {"launches_per_step": r["launches"], "ms_per_step": r["total_ms"],
                       "avg_us": r["total_ms"] / max(r["launches"], 1) * 1e3,
-                      "GBps": r["work"] / (r["total_ms"] * 1e-3) / 1e9 if r["total_ms"] > 0 else 0.0}
+                      ("TFLOPs" if r["bound"] else "GBps"): rate(r)}
                for name, r in survey.items()}
+    # whole Arnoldi steps, timed alone (no nested events)
+    steps_stat = {}
+    one_step(args.k, a, b, steps_stat, g.timing_mask(["arnoldi_step"]))
     # every 8th launch of that class is bracketed (the events' own stream
     # time stays out of most of the timed region)
     kstats = {}
     sample_stride = 8
     dt, infos, x = timed(args.k, args.steps, args.warmup, kstats,
-                         (1 << g.KERNEL_CLASSES.index(dom)) | (sample_stride << 8))
+                         g.timing_mask([dom], sample_stride))
     info = infos[-1]
     converged = all(i["status"] == 0 for i in infos)
     ferr = float(torch.max(torch.abs(x - xt_dev)) / torch.max(torch.abs(xt_dev)))
     value = args.steps / dt if converged else 0.0
     log(f"recycled k={args.k}: {dt / args.steps * 1e3:.2f} ms/step status={info['status']} "
         f"its={info['its']} berr={info['berr'][-1]:.2e} factor={info['t_factor_s'] * 1e3:.2f} ms "
-        f"solve={info['t_solve_s'] * 1e3:.2f} ms")
+        f"solve={info['t_solve_s'] * 1e3:.2f} ms; phases (ms) x0 {info['t_x0_s'] * 1e3:.2f} "
+        f"residual {info['t_residual_s'] * 1e3:.2f} precond {info['t_precond_s'] * 1e3:.2f} "
+        f"recycle {info['t_recycle_s'] * 1e3:.2f} arnoldi {info['t_arnoldi_s'] * 1e3:.2f}")
     plain = None
     if not args.no_plain:
         dtp, infp, _ = timed(0, args.steps, args.warmup)
@@ -339,18 +372,125 @@ def main():
 
     # roofline of the dominant class, from its launches in the timed steps
     r = kstats[dom]
-    achieved = r["work"] / (r["total_ms"] * 1e-3) / 1e9
+    achieved = rate(r)
+    mfma = bool(r["bound"])
+    peak = FP16_MFMA_PEAK_TFLOPS if mfma else HBM_PEAK_GBS
     # the counter summary was taken on the default workload only
     default_workload = (args.uf, args.u, args.ur, args.n) == ("fp16", "fp32", "fp64", 8192)
     traffic = traffic_for(dom, r["launches"] / args.steps) if default_workload else None
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+    # the whole factorisation against the fp16 matrix cores (2 n^3 / 3 flops
+    # over the factor's wall time), its GEMM-only launches, and one Arnoldi
+    # step against HBM (n^2 (s_A + s_f) bytes plus one read of the basis)
+    t_lu = sum(i["t_factor_s"] for i in infos) / len(infos)
+    lu_flops = 2.0 * args.n ** 3 / 3.0
+    lu_peak = FP16_MFMA_PEAK_TFLOPS if args.uf in ("fp16", "bf16") else FP64_MFMA_PEAK_TFLOPS
+    gemm = survey.get("lu_gemm")
+    st = steps_stat.get("arnoldi_step")
+    arn = None
+    if st and st["launches"]:
+        gbps = st["work"] / (st["total_ms"] * 1e-3) / 1e9
+        arn = {"launches": st["launches"], "avg_us": st["total_ms"] / st["launches"] * 1e3,
+               "bytes_per_step": st["work"] / st["launches"], "GBps": gbps,
+               "frac_hbm": gbps / HBM_PEAK_GBS,
+               "ideal_us": st["work"] / st["launches"] / (HBM_PEAK_GBS * 1e9) * 1e6}
+    roofline = {"bound": "mfma" if mfma else "hbm", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s" if mfma else "GB/s", "frac": achieved / peak,
+                "traffic": traffic, "kernel": dom,
                 "launches": r["launches"], "avg_us": r["total_ms"] / r["launches"] * 1e3,
                 "sampled": f"every {sample_stride}th launch of the class in the timed steps",
-                "algorithmic_bytes_per_launch": r["work"] / r["launches"],
+                ("algorithmic_flops_per_launch" if mfma else "algorithmic_bytes_per_launch"):
+                    r["work"] / r["launches"],
+                "lu_whole": {"flops": lu_flops, "t_factor_ms": t_lu * 1e3,
+                             "TFLOPs": lu_flops / t_lu / 1e12, "peak": lu_peak,
+                             "frac": lu_flops / t_lu / 1e12 / lu_peak},
+                "lu_gemm_only": None if not gemm else {
+                    "launches_per_step": gemm["launches"], "avg_us": gemm["total_ms"] /
+                    max(gemm["launches"], 1) * 1e3, "TFLOPs": rate(gemm),
+                    "frac": rate(gemm) / lu_peak},
+                "arnoldi_step": arn,
                 "kernels_one_step": kernels}
     log(f"dominant kernel class {dom}: {r['launches']} launches, avg "
-        f"{r['total_ms'] / r['launches'] * 1e3:.1f} us, {achieved:.1f} GB/s")
+        f"{r['total_ms'] / r['launches'] * 1e3:.1f} us, {achieved:.2f} "
+        f"{'TFLOP/s' if mfma else 'GB/s'} ({achieved / peak * 100:.2f} % of peak); whole LU "
+        f"{lu_flops / t_lu / 1e12:.2f} TFLOP/s"
+        + (f"; Arnoldi step {arn['avg_us']:.1f} us = {arn['GBps']:.0f} GB/s" if arn else ""))
+
+    # M2: the factorisation amortised over several right-hand sides solved in
+    # sequence with the recycle space kept between them (keep_recycle = 1)
+    m2 = None
+    if args.m2_rhs > 0:
+        gx = torch.Generator(device=dev)
+        gx.manual_seed(args.seed + 11)
+        xs = torch.rand((args.m2_rhs, args.n), generator=gx, dtype=torch.float64,
+                        device=dev) * 2.0 - 1.0
+        bs = torch.matmul(xs, a.t())                 # row j: A x_j
+        m2 = {"rhs": args.m2_rhs}
+        for kk in (args.k, 0):
+            def m2_step():
+                h = g.factor(a, k=kk, keep_recycle=1, **opts)
+                xm, im = h.solve(bs.t())
+                h.free()
+                return xm, im
+            m2_step()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            m2_reps = max(1, min(args.steps, 3))
+            for _ in range(m2_reps):
+                xm, im = m2_step()
+            torch.cuda.synchronize()
+            dtm = (time.perf_counter() - t) / m2_reps
+            rr = bs.t() - torch.matmul(a, xm)
+            den = (torch.max(torch.sum(torch.abs(a), dim=1)) * torch.max(torch.abs(xm), dim=0).values
+                   + torch.max(torch.abs(bs.t()), dim=0).values)
+            eta = (torch.max(torch.abs(rr), dim=0).values / den).max().item()
+            key = "recycled" if kk else "plain"
+            m2[key] = {"k": kk, "ms_per_factor_and_rhs_set": dtm * 1e3,
+                       "solves_per_s": args.m2_rhs / dtm if eta <= 1e-14 else 0.0,
+                       "max_berr_fp64": eta, "last_rhs_its": im["its"],
+                       "last_rhs_recycle_dim": im["recycle_dim"]}
+            log(f"M2 k={kk}: {args.m2_rhs} right-hand sides in {dtm * 1e3:.1f} ms "
+                f"({args.m2_rhs / dtm:.1f} solves/s), max berr {eta:.2e}, last its {im['its']}")
+        if m2.get("plain", {}).get("solves_per_s"):
+            m2["recycled_over_plain"] = m2["recycled"]["solves_per_s"] / m2["plain"]["solves_per_s"]
+        del xs, bs
+
+    # comparator: plain fp64 LU-based refinement on the same GPU (the vendor
+    # LU, rocSOLVER getrf through torch, then fp64 residuals and corrections
+    # with the fp64 factors until the same backward-error target)
+    comparator = None
+    if not args.no_comparator:
+        def fp64_ir():
+            lu, piv = torch.linalg.lu_factor(a)
+            xv = torch.linalg.lu_solve(lu, piv, b.unsqueeze(1))[:, 0]
+            na = torch.max(torch.sum(torch.abs(a), dim=1))
+            steps_c = 0
+            while True:
+                rv = b - torch.mv(a, xv)
+                eta_c = (torch.max(torch.abs(rv)) / (na * torch.max(torch.abs(xv))
+                                                      + torch.max(torch.abs(b)))).item()
+                if eta_c <= 1e-14 or steps_c >= 10:
+                    return eta_c, steps_c
+                xv = xv + torch.linalg.lu_solve(lu, piv, rv.unsqueeze(1))[:, 0]
+                steps_c += 1
+        try:
+            fp64_ir()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            creps = max(1, min(args.steps, 5))
+            for _ in range(creps):
+                eta_c, steps_c = fp64_ir()
+            torch.cuda.synchronize()
+            dtc = (time.perf_counter() - t) / creps
+            comparator = {"what": "fp64 LU (torch.linalg.lu_factor, vendor getrf) + fp64 "
+                                  "refinement with lu_solve to backward error 1e-14",
+                          "ms_per_solve": dtc * 1e3, "refinement_steps": steps_c,
+                          "berr": eta_c,
+                          "ours_speedup": (dtc / (dt / args.steps)) if value else None}
+            log(f"comparator fp64 LU + refinement: {dtc * 1e3:.2f} ms/solve ({steps_c} steps, "
+                f"berr {eta_c:.2e}); ours {dt / args.steps * 1e3:.2f} ms")
+        except Exception as exc:  # the comparator is context only
+            comparator = {"error": repr(exc)}
+            log(f"comparator failed: {exc!r}")
 
     # the differentiated solve: forward solve, the adjoint A^T lambda = x - y
     # with its own recycle space, dL/dA = -lambda x^T (L = 0.5 ||x - y||^2)
@@ -440,8 +580,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         t = time.time()
-        cpu = cpu_baseline(args.cpu_n, args.n, args.kappa, args.seed, args.m, args.k)
-        log(f"cpu baseline ({time.time() - t:.1f} s): {cpu['value']:.3g} solves/s; {cpu['sample']}")
+        cpu = cpu_baseline(a.cpu().numpy(), b.cpu().numpy(), args.kappa, args.seed, args.m,
+                           args.k)
+        log(f"cpu baseline ({time.time() - t:.1f} s): {cpu['value']:.3g} solves/s; "
+            f"{cpu['sample']}; LAPACK fp64 LU solve {cpu['context_lapack_fp64_lu_solve_s']:.2f} s")
 
     out = {
         "metric": "refined solves/s to backward err 1e-14, recycled vs plain GMRES-IR, n=8192",
@@ -475,6 +617,11 @@ def main():
             "outcomes_prolate16k": prolate or None,
             "gradient": adjoint,
             "reuse_recycle": reuse,
+            "m2_amortised": m2,
+            "comparator_fp64_lu": comparator,
+            "phases_ms": {kk: info[kk] * 1e3 for kk in ("t_x0_s", "t_residual_s", "t_precond_s",
+                                                         "t_recycle_s", "t_arnoldi_s")},
+            "berr_cw": info["berr_cw"][-1],
             "batched": batched,
         },
         "roofline": roofline,
