@@ -304,6 +304,36 @@ int gmresir_errors(gmresir_ctx* h, const double* b, const double* x,
                    const double* x_true, double* out, void* stream);
 
 /*
+ * gmresir_errors_noalloc -- gmresir_errors for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc): the same three measures, computed by the same
+ * kernels, without a handle and without allocating anything.  Its scratch
+ * vectors and reduction words live in one static device array per GPU
+ * (about 384 KiB, held until the process ends; its device address is taken
+ * once per device on the first call).  Results go to device memory in stream
+ * order: the call enqueues its kernels and returns without synchronising.
+ *
+ *   A       device pointer, n x n float64 row-major, leading dimension lda;
+ *           16-byte aligned with lda even (its rows are read as 16-byte
+ *           pairs).  ||A||_inf is computed here, summed in the same order as
+ *           gmresir_factor sums it.
+ *   n       1 <= n <= 16384 (EINVAL beyond: the static scratch limit).
+ *   b, x    device pointers of n float64 values; x_true as well, or NULL.
+ *   out     DEVICE pointer to 3 doubles: normwise backward error,
+ *           componentwise backward error, forward error (NaN without
+ *           x_true), as gmresir_errors defines them.
+ *   stream  hipStream_t or NULL.
+ *
+ * Every call on one GPU uses that GPU's one scratch array: calls that
+ * overlap on the same device (other streams or threads) race and must be
+ * serialised by the caller.  Returns 0, EINVAL (null pointer, n out of range,
+ * lda < n, misaligned A or odd lda) or EHIP.
+ */
+int gmresir_errors_noalloc(const double* A, int64_t n, int64_t lda,
+                           const double* b, const double* x,
+                           const double* x_true, double* out, void* stream);
+
+/*
  * Per-kernel-class launch timing (handles created with opts.timing != 0).
  * One record per timed class that ran since the handle was created: the
  * number of

@@ -29,6 +29,7 @@ __all__ = [
     "timing_mask",
     "rank1",
     "solve_batched",
+    "errors_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -57,7 +58,7 @@ EXPORTED = (
     "gmresir_strerror", "gmresir_last_error", "gmresir_import_factors",
     "gmresir_export_factors", "gmresir_apply", "gmresir_kernel_stats", "gmresir_query",
     "gmresir_solve_transposed", "gmresir_rank1", "gmresir_choose_k", "gmresir_solve_batched",
-    "gmresir_errors",
+    "gmresir_errors", "gmresir_errors_noalloc",
 )
 
 
@@ -171,6 +172,8 @@ def load_library() -> ctypes.CDLL:
     lib.gmresir_apply.restype = ctypes.c_int
     lib.gmresir_errors.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.gmresir_errors.restype = ctypes.c_int
+    lib.gmresir_errors_noalloc.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+    lib.gmresir_errors_noalloc.restype = ctypes.c_int
     lib.gmresir_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
     lib.gmresir_kernel_stats.restype = ctypes.c_int
     lib.gmresir_query.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
@@ -439,6 +442,33 @@ def import_factors(a, lu, ipiv, e: int, stream=None, **opts) -> Handle:
     if rc < 0:
         raise _err(lib, rc)
     return Handle(lib, out, a.shape[0], o, rc)
+
+
+def errors_noalloc(a, b, x, out, x_true=None, stream=None) -> None:
+    """gmresir_errors_noalloc: the three error measures of x written to the
+    device tensor out (3 float64) in stream order, without a handle and
+    without allocating (A: row-major float64 CUDA, 16-byte aligned, even
+    leading dimension)."""
+    import torch
+    lib = load_library()
+    _check_matrix(a)
+    n = a.shape[0]
+    for name, t in (("b", b), ("x", x), ("x_true", x_true)):
+        if t is None and name == "x_true":
+            continue
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.shape == (n,) and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA vector of length n")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+            and out.numel() >= 3 and out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 CUDA tensor of 3 values")
+    rc = lib.gmresir_errors_noalloc(ctypes.c_void_p(a.data_ptr()), n, a.stride(0),
+                                    ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(x_true.data_ptr() if x_true is not None
+                                                    else None),
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream))
+    if rc != 0:
+        raise _err(lib, rc)
 
 
 def rank1(alpha: float, x, y, out=None, stream=None):

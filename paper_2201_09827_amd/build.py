@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgmresir.so")
 
 SOURCES = ["kernels_lu.hip", "kernels_solve.hip", "kernels_dd.hip", "host_la.cpp", "solver.cpp",
-           "batch.cpp"]
+           "batch.cpp", "noalloc.hip"]
 
 ARCH = os.environ.get("GMRESIR_OFFLOAD_ARCH", "gfx950")
 
