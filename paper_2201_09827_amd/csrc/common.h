@@ -94,6 +94,24 @@ __device__ __forceinline__ uint64_t dpp_max_step(uint64_t v, int lo_nb, int hi_n
     v = dpp_max_step(v, lo_, hi_);                                                       \
   } while (0)
 
+// Wave-wide maximum of a 32-bit unsigned value by the same DPP pattern;
+// every lane receives the maximum.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#define GIR_DPP_MAX32(ctrl, rmask)                                                          \
+  do {                                                                                   \
+    const uint32_t o_ = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, rmask, 0xf, false); \
+    v = v > o_ ? v : o_;                                                                 \
+  } while (0)
+  GIR_DPP_MAX32(0x111, 0xf);  // row_shr:1
+  GIR_DPP_MAX32(0x112, 0xf);  // row_shr:2
+  GIR_DPP_MAX32(0x114, 0xf);  // row_shr:4
+  GIR_DPP_MAX32(0x118, 0xf);  // row_shr:8
+  GIR_DPP_MAX32(0x142, 0xa);  // row_bcast:15
+  GIR_DPP_MAX32(0x143, 0xc);  // row_bcast:31
+#undef GIR_DPP_MAX32
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   GIR_DPP_MAX(v, 0x111, 0xf);  // row_shr:1
   GIR_DPP_MAX(v, 0x112, 0xf);  // row_shr:2

@@ -310,7 +310,18 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
     const uint32_t ab = (ac == ac) ? __float_as_uint(ac) : 0u;  // NaN ranks as zero
     const uint64_t mykey =
         pv ? 0ull : (((uint64_t)ab << 17) | (uint64_t)(0x1FFFFu - (uint32_t)lid));
-    const uint64_t wmax = wave_max_u64(mykey);
+    // the wave's largest key by two 32-bit reductions: the largest magnitude
+    // (+1, so that an unpivoted zero still outranks the pivoted rows), then,
+    // only when several rows attain it, the first of them in logical order
+    const uint32_t am = pv ? 0u : ab + 1u;
+    const uint32_t mw = wave_max_u32(am);
+    const bool cand = mw != 0u && am == mw;
+    const uint32_t il = cand ? (0x1FFFFu - (uint32_t)lid) : 0u;
+    const unsigned long long bal = __ballot(cand);
+    const uint32_t ilw = (__builtin_popcountll(bal) == 1)
+                             ? (uint32_t)__builtin_amdgcn_readlane((int)il, __builtin_ctzll(bal))
+                             : wave_max_u32(il);
+    const uint64_t wmax = mw ? (((uint64_t)(mw - 1u) << 17) | ilw) : 0ull;
     if (lane == 0) kw[wave] = wmax;
     __syncthreads();
     uint64_t K = kw[0];
