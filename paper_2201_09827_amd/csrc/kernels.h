@@ -85,6 +85,14 @@ void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, i
                        const double* in, const int* permIn, const double* Linv, double* y,
                        uint64_t* xw, int epoch, const CycleState* gate, int step, int* abort,
                        hipStream_t s);
+// y = L^-1 (A_u[permA] v) in fp64 in one launch: the lower solve's blocks
+// plus workgroups that form the product (eight rows each, fp64 sums as
+// launch_gemv_au) and publish its rows as tagged words in xt (2 words per
+// row, sized as xw, zeroed once); epoch tags both xw and xt
+void launch_atilde_lower(const void* S, int64_t ld, const int* permS, int store, int n,
+                         const float* Au, int64_t lda, const int* permA, const float* v,
+                         const double* Linv, double* y, uint64_t* xw, uint64_t* xt, int epoch,
+                         const CycleState* gate, int step, int* abort, hipStream_t s);
 // z = U^-1 y; out64 = 2^e z, out32 = fl32(2^e z) (either may be null)
 void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
                        const double* y, const double* Uinv, double* z, double scale,

@@ -21,20 +21,38 @@ constexpr int kTB = 64;  // triangular-solve block (rows per workgroup)
 // ---------------------------------------------------------------------------
 // GEMV: t[i] = sum_c Au[permA[i]][c] v[c], one wave per row, fp64 accumulate
 // ---------------------------------------------------------------------------
-template <typename VT>
-__global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, int64_t ld,
-                                                 const int* __restrict__ permA, int n,
-                                                 const VT* __restrict__ v, double* __restrict__ t,
-                                                 const CycleState* gate, int step) {
-  if (gated_off(gate, step)) return;
-  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (row >= n) return;
-  const int prow = permA ? permA[row] : row;
-  const float* a = Au + (int64_t)prow * ld;
+// one row of the product, summed over the wave (every lane gets the sum);
+// with kAhead > 1 the loads of kAhead loop iterations are issued before
+// their products are taken, in the same order (the same sums bit for bit),
+// for waves that run at low occupancy
+template <typename VT, int kAhead = 1>
+__device__ __forceinline__ double gemv_au_row(const float* __restrict__ a,
+                                              const VT* __restrict__ v, int n, int lane) {
   double acc0 = 0.0, acc1 = 0.0;
   const int n4 = n & ~3;
   int c = lane * 4;
+  if (kAhead > 1) {
+    for (; c + 512 * (kAhead - 1) + 256 < n4; c += 512 * kAhead) {
+      float4 x0[kAhead], x1[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        x0[u] = *reinterpret_cast<const float4*>(a + c + 512 * u);
+        x1[u] = *reinterpret_cast<const float4*>(a + c + 512 * u + 256);
+      }
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int cu = c + 512 * u;
+        acc0 = fma((double)x0[u].x, (double)v[cu + 0], acc0);
+        acc1 = fma((double)x0[u].y, (double)v[cu + 1], acc1);
+        acc0 = fma((double)x0[u].z, (double)v[cu + 2], acc0);
+        acc1 = fma((double)x0[u].w, (double)v[cu + 3], acc1);
+        acc0 = fma((double)x1[u].x, (double)v[cu + 256], acc0);
+        acc1 = fma((double)x1[u].y, (double)v[cu + 257], acc1);
+        acc0 = fma((double)x1[u].z, (double)v[cu + 258], acc0);
+        acc1 = fma((double)x1[u].w, (double)v[cu + 259], acc1);
+      }
+    }
+  }
   for (; c + 256 < n4; c += 512) {
     const float4 x0 = *reinterpret_cast<const float4*>(a + c);
     const float4 x1 = *reinterpret_cast<const float4*>(a + c + 256);
@@ -55,7 +73,20 @@ __global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, i
     acc1 = fma((double)x0.w, (double)v[c + 3], acc1);
   }
   for (int cc = n4 + lane; cc < n; cc += kWave) acc0 = fma((double)a[cc], (double)v[cc], acc0);
-  const double s = wave_sum(acc0 + acc1);
+  return wave_sum(acc0 + acc1);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, int64_t ld,
+                                                 const int* __restrict__ permA, int n,
+                                                 const VT* __restrict__ v, double* __restrict__ t,
+                                                 const CycleState* gate, int step) {
+  if (gated_off(gate, step)) return;
+  const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= n) return;
+  const int prow = permA ? permA[row] : row;
+  const double s = gemv_au_row(Au + (int64_t)prow * ld, v, n, lane);
   if (lane == 0) t[row] = s;
 }
 
@@ -382,7 +413,21 @@ struct ColStrides {
   int64_t in, y, out, xw;
 };
 
-template <class F, bool kUpper>
+// The A-tilde product fused into the lower solve (u = fp32): the launch's
+// workgroups beyond the solve's blocks compute t = A_u[permA] v, eight rows
+// each (one wave per row, the sums of k_gemv_au), and publish every row as
+// two tagged words in xt; a solve block takes its right-hand side from there
+// as soon as its rows are published, so the product streams from HBM while
+// the chain of blocks is running.
+struct FusedGemv {
+  const float* Au;
+  int64_t ld;
+  const int* permA;
+  const float* v;
+  uint64_t* xt;
+};
+
+template <class F, bool kUpper, bool kFused = false>
 __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __restrict__ S,
                                                      int64_t ld, const int* __restrict__ permS,
                                                      int n, const double* __restrict__ in,
@@ -391,8 +436,20 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
                                                      double scale, double* __restrict__ out64,
                                                      float* __restrict__ out32, uint64_t* xw,
                                                      uint32_t epoch, const CycleState* gate,
-                                                     int step, int* abortp, ColStrides cs) {
+                                                     int step, int* abortp, ColStrides cs,
+                                                     FusedGemv fg = FusedGemv{}) {
   if (gated_off(gate, step)) return;
+  if (kFused && (int)blockIdx.x >= (n + kTS - 1) / kTS) {
+    // a product workgroup: rows 8 (b - nb) + wave
+    const int row = ((int)blockIdx.x - (n + kTS - 1) / kTS) * (kTSThreads / kWave) +
+                    (int)(threadIdx.x / kWave);
+    if (row >= n) return;
+    const int prow = fg.permA ? fg.permA[row] : row;
+    const double t = gemv_au_row<float, 8>(fg.Au + (int64_t)prow * fg.ld, fg.v, n,
+                                           (int)(threadIdx.x % kWave));
+    if ((threadIdx.x % kWave) == 0) put_tagged(fg.xt, row, t, epoch);
+    return;
+  }
   {
     const int64_t col = blockIdx.y;
     in += col * cs.in;
@@ -448,7 +505,7 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
     }
   }
   double rhs = 0.0;
-  if (tid < kTS && r0 + tid < n) {
+  if (!kFused && tid < kTS && r0 + tid < n) {
     const int rr = r0 + tid;
     rhs = in[permIn ? permIn[rr] : rr];
   }
@@ -478,6 +535,13 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
       acc3 = fma(lv.at(c + 3), ysh[wave][c + 3], acc3);
     }
     __builtin_amdgcn_wave_barrier();
+  }
+  if (kFused && ok && tid < kTS) {
+    // waves 0 and 1: this block's right-hand side from the product rows
+    // (rows beyond n were never published and stay zero)
+    double tv = 0.0;
+    if (!get_tagged_row(fg.xt, r0 + tid < n ? r0 + tid : r0, epoch, tv, abortp)) ok = false;
+    rhs = (r0 + tid < n) ? tv : 0.0;
   }
   red[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
   if (lane == 0) wok[wave] = ok ? 1 : 0;
@@ -1405,6 +1469,36 @@ void trsv_pair(const void* S, int64_t ld, const int* permS, int n, bool upper, c
     hipLaunchKernelGGL((k_trsv<F, false>), grid, dim3(kTSThreads), 0, s, Sp, ld, permS, n, in,
                        permIn, Dinv, y, 1.0, nullptr, nullptr, xw, (uint32_t)epoch, gate, step,
                        abortp, cs);
+}
+
+template <class F>
+void atilde_lower_t(const void* S, int64_t ld, const int* permS, int n, const float* Au,
+                    int64_t lda, const int* permA, const float* v, const double* Linv, double* y,
+                    uint64_t* xw, uint64_t* xt, int epoch, const CycleState* gate, int step,
+                    int* abortp, hipStream_t s) {
+  using T = typename F::T;
+  const unsigned nb = nblocks(n, kTS);
+  const unsigned ng = nblocks(n, kTSThreads / kWave);
+  const T* Sp = reinterpret_cast<const T*>(S);
+  hipLaunchKernelGGL((k_trsv<F, false, true>), dim3(nb + ng), dim3(kTSThreads), 0, s, Sp, ld,
+                     permS, n, nullptr, nullptr, Linv, y, 1.0, nullptr, nullptr, xw,
+                     (uint32_t)epoch, gate, step, abortp, ColStrides{0, 0, 0, 0},
+                     FusedGemv{Au, lda, permA, v, xt});
+}
+
+void launch_atilde_lower(const void* S, int64_t ld, const int* permS, int store, int n,
+                         const float* Au, int64_t lda, const int* permA, const float* v,
+                         const double* Linv, double* y, uint64_t* xw, uint64_t* xt, int epoch,
+                         const CycleState* gate, int step, int* abort, hipStream_t s) {
+  if (store == kStoreF16)
+    atilde_lower_t<Fp16>(S, ld, permS, n, Au, lda, permA, v, Linv, y, xw, xt, epoch, gate, step,
+                         abort, s);
+  else if (store == kStoreBF16)
+    atilde_lower_t<Bf16>(S, ld, permS, n, Au, lda, permA, v, Linv, y, xw, xt, epoch, gate, step,
+                         abort, s);
+  else
+    atilde_lower_t<Fp32>(S, ld, permS, n, Au, lda, permA, v, Linv, y, xw, xt, epoch, gate, step,
+                         abort, s);
 }
 
 template <class F>

@@ -325,6 +325,10 @@ struct gmresir_ctx {
   // GMRESIR_RECYCLE_QR=householder at handle creation; a test hook for the
   // branch that CholeskyQR2 breakdowns take)
   bool force_hqr = false;
+  // Arnoldi steps (u = fp32) run the A_u product inside the lower solve's
+  // launch; GMRESIR_FUSED_ATILDE=0 at handle creation selects the separate
+  // launches (the same arithmetic)
+  bool fuse_atilde = true;
   Refresh pend;     // deferred refresh of the last cycle (V, C, U untouched meanwhile)
   // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
   // it runs) and the partial sums of the products with A^T
@@ -338,6 +342,7 @@ struct gmresir_ctx {
   unsigned long long* norms = nullptr;
   gir::CycleState* st = nullptr;
   uint64_t *xwL = nullptr, *xwU = nullptr;  // tagged partial solutions of the two solves
+  uint64_t* xt = nullptr;  // tagged rows of A_u v for the fused lower solve (u = fp32)
   uint64_t *xwLm = nullptr, *xwUm = nullptr;  // the same for the multi-vector solves
   double *Tb = nullptr, *Yb = nullptr;        // ld x 8 blocks for the multi-vector product
   int epoch = 0;
@@ -623,7 +628,12 @@ int alloc_solve(gmresir_ctx* h) {
   if (h->u64) {
     GIR_TRY(dalloc(h->arena, &h->tl, ld));
     GIR_TRY(dalloc(h->arena, &h->yl, ld));
-  } else if (h->k > 0) {
+  } else {
+    // the A_u product's rows, published to the fused lower solve
+    GIR_TRY(dalloc(h->arena, &h->xt, (size_t)nxw));
+    zl.add(h->xt, sizeof(uint64_t) * (size_t)nxw);
+  }
+  if (!h->u64 && h->k > 0) {
     const int64_t nm = nxw * gir::kTrsvMaxRhs;
     GIR_TRY(dalloc(h->arena, &h->xwLm, (size_t)nm));
     GIR_TRY(dalloc(h->arena, &h->xwUm, (size_t)nm));
@@ -909,6 +919,8 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
   {
     const char* q = std::getenv("GMRESIR_RECYCLE_QR");
     h->force_hqr = q && std::strcmp(q, "householder") == 0;
+    const char* f = std::getenv("GMRESIR_FUSED_ATILDE");
+    h->fuse_atilde = !(f && std::strcmp(f, "0") == 0);
   }
   h->o = *opts;
   h->m = opts->m;
@@ -1044,6 +1056,24 @@ int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, voi
     return precond(h, h->t64, h->tl, nullptr, out64, outu, gate, step);
   }
   const float* v32 = static_cast<const float*>(vu);
+  if (v32 && h->fuse_atilde) {
+    // the product and the lower solve in one launch, then the upper solve
+    const double tri = 0.5 * nn * (nn + 1.0) * (double)store_bytes(h->store);
+    const int eL = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvL, 4.0 * nn * nn + 4.0 * nn + tri + 16.0 * nn, h->stream, gate, step,
+                  [&] {
+                    gir::launch_atilde_lower(h->S, h->ld, h->permS, h->store, (int)h->n, h->Au,
+                                             h->ld, h->permP, v32, h->Linv, h->y64, h->xwL, h->xt,
+                                             eL, gate, step, &h->st->abort, h->stream);
+                  }));
+    const int eU = next_epoch(h);
+    GIR_TRY(timed(h, kKcTrsvU, tri + 24.0 * nn, h->stream, gate, step, [&] {
+      gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, (int)h->n, h->y64, h->Uinv, h->z64,
+                             h->scale, out64, static_cast<float*>(outu), h->xwU, eU, gate, step,
+                             &h->st->abort, h->stream);
+    }));
+    return 0;
+  }
   GIR_TRY(timed(h, kKcGemv, 4.0 * nn * nn + (v32 ? 4.0 : 8.0) * nn + 8.0 * nn, h->stream, gate,
                 step, [&] {
                   gir::launch_gemv_au(h->Au, h->ld, h->permP, (int)h->n, v32, v64, h->t64, gate,

@@ -150,3 +150,25 @@ def test_recycle_setup_by_householder_qr(lib, monkeypatch, seed):
     fe = np.max(np.abs(x.cpu().numpy() - p.x_true)) / np.max(np.abs(p.x_true))
     fo = np.max(np.abs(x_ref - p.x_true)) / np.max(np.abs(p.x_true))
     assert fe <= 10 * fo + 1000 * U64
+
+
+@pytest.mark.parametrize("n,k", [(1000, 10), (4097, 5), (300, 0)])
+def test_fused_product_and_lower_solve_match_separate_launches(lib, monkeypatch, n, k):
+    """The Arnoldi step's A_u product fused into the lower solve's launch
+    (the default) against the separate launches (GMRESIR_FUSED_ATILDE=0):
+    the same sums in the same order, so every count and every bit of x must
+    agree."""
+    p = randsvd_problem(n, 1e3, 7)
+    a, b = _dev(p.a), _dev(p.b)
+    log(f"[fused] n={n} k={k}")
+    h = lib.factor(a, m=20, k=k)
+    x1, i1 = h.solve(b)
+    h.free()
+    monkeypatch.setenv("GMRESIR_FUSED_ATILDE", "0")
+    h = lib.factor(a, m=20, k=k)
+    x0, i0 = h.solve(b)
+    h.free()
+    log(f"[fused] its fused {i1['its']} separate {i0['its']}")
+    assert i1["status"] == i0["status"] == 0
+    assert i1["its"] == i0["its"] and i1["berr"] == i0["berr"]
+    assert torch.equal(x1, x0)
