@@ -94,7 +94,23 @@ typedef struct {
   int32_t reuse_recycle;  /* 1: keep C_k and U_k of the previous correction solve
                              (same A: A-tilde U_k = C_k still holds) instead of
                              recomputing QR(A-tilde U_k).  Default 0.           */
-  int32_t reserved[1];    /* must be zero                                    */
+  int32_t ortho;          /* orthogonalisation of each Arnoldi vector against
+                             [C_k V_j]: 0 classical Gram-Schmidt applied
+                             twice (CGS2, default), 1 modified Gram-Schmidt
+                             (one column at a time; slower, two launches per
+                             basis column)                                   */
+  /* Optional device allocator (both or neither): when alloc is not NULL,
+   * every device buffer of a handle is carved from memory obtained with
+   * alloc(bytes, alloc_user) -- which must return device memory on the
+   * current device, 256-byte aligned, or NULL (then the call fails with
+   * ENOMEM) -- and handed back with free_(ptr, alloc_user) by gmresir_free.
+   * This routes the library's memory through a caller's pool (for example
+   * torch's caching allocator).  With gmresir_solve_batched the callbacks
+   * are called from the worker threads and must be thread-safe.  NULL: the
+   * library's own allocation and its process-wide cache.                    */
+  void* (*alloc)(size_t bytes, void* alloc_user);
+  void (*free_)(void* ptr, void* alloc_user);
+  void* alloc_user;
 } gmresir_opts;
 
 /* Per-solve record, filled by gmresir_solve (host struct). */
@@ -135,7 +151,7 @@ typedef struct gmresir_ctx gmresir_ctx;
 
 /* Fill *opts with defaults: (FP16, FP32, FP64), m = 30, k = 10, tau = 1e-4,
  * imax = 10, maxit = 0, berr_target = 1e-14, scale_pow2 = -1,
- * keep_recycle = 0, timing = 0. */
+ * keep_recycle = 0, timing = 0, ortho = 0 (CGS2). */
 void gmresir_default_opts(gmresir_opts* opts);
 
 /*

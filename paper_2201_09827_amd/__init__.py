@@ -30,6 +30,7 @@ __all__ = [
     "rank1",
     "solve_batched",
     "errors_noalloc",
+    "TorchAllocator",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -79,7 +80,10 @@ class Opts(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("matvec_u", ctypes.c_int32),
         ("reuse_recycle", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("ortho", ctypes.c_int32),
+        ("alloc", ctypes.c_void_p),
+        ("free_", ctypes.c_void_p),
+        ("alloc_user", ctypes.c_void_p),
     ]
 
 
@@ -202,6 +206,8 @@ def _opts(**kw) -> Opts:
     for key, val in kw.items():
         if key in ("uf", "u", "ur") and isinstance(val, str):
             val = PREC[val]
+        if key == "ortho" and isinstance(val, str):
+            val = {"cgs2": 0, "mgs": 1}[val]
         if key in ("keep_recycle", "scale_pow2", "timing", "matvec_u", "reuse_recycle"):
             val = int(val)
         if not hasattr(o, key):
@@ -410,7 +416,9 @@ class Handle:
 def factor(a, stream=None, **opts) -> Handle:
     """LU-factorise A (the factorisation step of Algorithm 3).  ``a``: square row-major float64
     CUDA tensor.  Options: uf, u, ur ('fp16', 'bf16', 'fp32', 'fp64', 'dd'),
-    m, k, tau, imax, maxit, berr_target, scale_pow2, keep_recycle, timing.  Raises
+    m, k, tau, imax, maxit, berr_target, scale_pow2, keep_recycle, timing,
+    matvec_u, reuse_recycle, ortho ('cgs2' or 'mgs'), alloc / free_ (see
+    TorchAllocator).  Raises
     GmresirError on a negative status; ESINGULAR/ERANGE return a handle whose
     ``status`` says so."""
     lib = load_library()
@@ -442,6 +450,42 @@ def import_factors(a, lu, ipiv, e: int, stream=None, **opts) -> Handle:
     if rc < 0:
         raise _err(lib, rc)
     return Handle(lib, out, a.shape[0], o, rc)
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """The library's device buffers from torch's caching allocator (the
+    opts.alloc / opts.free_ hooks): ``g.factor(A, **TorchAllocator().opts())``.
+    Keep the object alive as long as handles created with it exist."""
+
+    def __init__(self):
+        import torch
+        self.live = {}
+        self.calls = 0
+
+        def _alloc(nbytes, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes))
+            except Exception:
+                return None
+            self.live[int(p)] = int(nbytes)
+            self.calls += 1
+            return int(p)
+
+        def _free(ptr, user):
+            if ptr is not None and int(ptr) in self.live:
+                del self.live[int(ptr)]
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._alloc = _ALLOC_FN(_alloc)
+        self._free = _FREE_FN(_free)
+
+    def opts(self) -> dict:
+        return {"alloc": ctypes.cast(self._alloc, ctypes.c_void_p).value,
+                "free_": ctypes.cast(self._free, ctypes.c_void_p).value}
 
 
 def errors_noalloc(a, b, x, out, x_true=None, stream=None) -> None:

@@ -197,17 +197,28 @@ void chunk_release(void* p, size_t bytes, int dev) {
 // Device memory of a handle: buffers above 4 MiB get their own allocation,
 // smaller ones are carved from 32 MiB chunks (256-byte aligned), so that a
 // handle costs a handful of chunk allocations.
+// With a caller's allocator (opts.alloc / opts.free_) the chunks come from it
+// instead and go back to it when the handle is freed.
 struct Arena {
   struct Chunk {
     void* p;
     size_t bytes;
     int dev;
+    bool user;
   };
   std::vector<Chunk> chunks;
   char* cur = nullptr;
   size_t left = 0;
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free_)(void*, void*) = nullptr;
+  void* user = nullptr;
   ~Arena() {
-    for (const Chunk& c : chunks) chunk_release(c.p, c.bytes, c.dev);
+    for (const Chunk& c : chunks) {
+      if (c.user)
+        free_(c.p, user);
+      else
+        chunk_release(c.p, c.bytes, c.dev);
+    }
   }
 };
 
@@ -223,12 +234,26 @@ int dalloc(Arena& a, T** p, size_t count) {
     void* q = nullptr;
     const size_t want = bytes > kOwnAllocation ? bytes : kChunk;
     int dev = 0;
-    hipError_t e = chunk_alloc(&q, want, &dev);
-    if (e != hipSuccess) {
-      set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
-      return GMRESIR_ENOMEM;
+    if (a.alloc) {
+      q = a.alloc(want, a.user);
+      if (!q) {
+        set_error("the caller's allocator returned NULL");
+        return GMRESIR_ENOMEM;
+      }
+      if ((reinterpret_cast<uintptr_t>(q) & 255) != 0) {
+        a.free_(q, a.user);
+        set_error("the caller's allocator returned memory not 256-byte aligned");
+        return GMRESIR_ENOMEM;
+      }
+      a.chunks.push_back({q, want, 0, true});
+    } else {
+      hipError_t e = chunk_alloc(&q, want, &dev);
+      if (e != hipSuccess) {
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return GMRESIR_ENOMEM;
+      }
+      a.chunks.push_back({q, want, dev, false});
     }
-    a.chunks.push_back({q, want, dev});
     if (bytes > kOwnAllocation) {
       *p = reinterpret_cast<T*>(q);
       return 0;
@@ -523,8 +548,12 @@ int validate_opts(const gmresir_opts* o) {
               "stride (bits 8-15)");
     return GMRESIR_EINVAL;
   }
-  if (o->reserved[0] != 0) {
-    set_error("reserved fields must be zero");
+  if ((o->alloc == nullptr) != (o->free_ == nullptr)) {
+    set_error("alloc and free_ must be given together");
+    return GMRESIR_EINVAL;
+  }
+  if (o->ortho != 0 && o->ortho != 1) {
+    set_error("ortho must be 0 (CGS2) or 1 (MGS)");
     return GMRESIR_EINVAL;
   }
   if ((o->matvec_u != 0 && o->matvec_u != 1) || (o->reuse_recycle != 0 && o->reuse_recycle != 1)) {
@@ -923,6 +952,9 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
     h->fuse_atilde = !(f && std::strcmp(f, "0") == 0);
   }
   h->o = *opts;
+  h->arena.alloc = opts->alloc;
+  h->arena.free_ = opts->free_;
+  h->arena.user = opts->alloc_user;
   h->m = opts->m;
   h->k = opts->k;
   h->store = store_of(opts->uf);
@@ -1409,6 +1441,9 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     GIR_TRY(upload(h, &h->st->tol, &st0.tol, 2 * sizeof(double)));
     int queued = 0;
     const size_t trec0 = h->trec.size();
+    // modified Gram-Schmidt's finish pass applies zero coefficients
+    if (h->o.ortho == 1)
+      gir::launch_fill_i32(reinterpret_cast<int*>(h->h2), 0, 2 * 256, s);
     for (int j = 0; j < nsteps; ++j) {
       // one Arnoldi step, timed as a whole under its own class: A_u v_j and
       // the factors once each (the HBM model of the step) plus one read of
@@ -1429,12 +1464,31 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       a.dots_out = h->h1;
       // basis read once per pass; the update pass also reads and writes w
       const double xb = (8.0 * kc + (double)h->ue * (j + 1)) * n;
-      GIR_TRY(timed(h, kKcOrtho, xb + (double)h->ue * n, s, h->st, j,
-                    [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
-      a.coef = h->h1;
-      a.dots_out = h->h2;
-      GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 2.0 * h->ue * n, s, h->st, j,
-                    [&] { gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s); }));
+      if (h->o.ortho == 1) {
+        // modified Gram-Schmidt: one basis column at a time ([C_k V_j] in
+        // order), its inner product with the current w, then its update;
+        // the coefficients gather in h1 and the finish pass below applies
+        // none (h2 is zero) but forms the norm and the Givens update
+        for (int i = 0; i < kc + j + 1; ++i) {
+          gir::OrthoArgs ai = a;
+          ai.X = i < kc ? basis(h, h->C + (size_t)i * ld, 1, ld, nullptr, 0, ld)
+                        : basis(h, nullptr, 0, ld, vcol(h, i - kc), 1, ld);
+          ai.dots_out = h->h1 + i;
+          ai.coef = h->h1 + i;
+          const double cb = (double)(i < kc ? 8 : h->ue) * n;
+          GIR_TRY(timed(h, kKcOrtho, cb + (double)h->ue * n, s, h->st, j,
+                        [&] { gir::launch_ortho(ai, gir::kOrthoDots, s); }));
+          GIR_TRY(timed(h, kKcOrtho, cb + 2.0 * h->ue * n, s, h->st, j,
+                        [&] { gir::launch_ortho(ai, gir::kOrthoUpdate, s); }));
+        }
+      } else {
+        GIR_TRY(timed(h, kKcOrtho, xb + (double)h->ue * n, s, h->st, j,
+                      [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
+        a.coef = h->h1;
+        a.dots_out = h->h2;
+        GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 2.0 * h->ue * n, s, h->st, j,
+                      [&] { gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s); }));
+      }
       a.coef = h->h2;
       a.h_prev = h->h1;
       a.norm_out = h->nrm;

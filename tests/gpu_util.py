@@ -19,15 +19,16 @@ def log(*args):
 
 
 def oracle_options(uf="fp16", m=20, k=5, tau=1e-4, imax=10, maxit=0, berr=1e-14, u="fp32",
-                   ur="fp64", matvec="u2", reuse=False):
+                   ur="fp64", matvec="u2", reuse=False, ortho="cgs2"):
     return Options(uf=uf, u=u, ur=ur, m=m, k=k, tau=tau, imax=imax, maxit=maxit,
-                   berr_target=berr, nb=NB, matvec=matvec, reuse_recycle=reuse)
+                   berr_target=berr, nb=NB, matvec=matvec, reuse_recycle=reuse, ortho=ortho)
 
 
 def lib_options(o: Options) -> dict:
     return dict(uf=o.uf, u=o.u, ur=o.ur, m=o.m, k=o.k, tau=o.tau, imax=o.imax,
                 maxit=o.maxit, berr_target=o.berr_target,
-                matvec_u=1 if o.matvec == "u" else 0, reuse_recycle=int(o.reuse_recycle))
+                matvec_u=1 if o.matvec == "u" else 0, reuse_recycle=int(o.reuse_recycle),
+                ortho=o.ortho)
 
 
 def decode_factors(raw: np.ndarray, uf: str) -> np.ndarray:

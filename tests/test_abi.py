@@ -43,7 +43,7 @@ int main(void) {
   printf("opts %zu %zu %zu %zu %zu %zu %zu\n", sizeof(gmresir_opts),
          offsetof(gmresir_opts, tau), offsetof(gmresir_opts, imax),
          offsetof(gmresir_opts, berr_target), offsetof(gmresir_opts, scale_pow2),
-         offsetof(gmresir_opts, keep_recycle), offsetof(gmresir_opts, reserved));
+         offsetof(gmresir_opts, keep_recycle), offsetof(gmresir_opts, ortho));
   printf("timing %zu\n", offsetof(gmresir_opts, timing));
   printf("kstat %zu %zu %zu %zu %zu\n", sizeof(gmresir_kernel_stat),
          offsetof(gmresir_kernel_stat, launches), offsetof(gmresir_kernel_stat, bound),
@@ -69,7 +69,7 @@ def test_struct_layout_matches_header():
     o = [int(v) for v in lines["opts"].split()]
     assert o == [ctypes.sizeof(g.Opts), g.Opts.tau.offset, g.Opts.imax.offset,
                  g.Opts.berr_target.offset, g.Opts.scale_pow2.offset,
-                 g.Opts.keep_recycle.offset, g.Opts.reserved.offset]
+                 g.Opts.keep_recycle.offset, g.Opts.ortho.offset]
     assert int(lines["timing"]) == g.Opts.timing.offset
     ks = [int(v) for v in lines["kstat"].split()]
     assert ks == [ctypes.sizeof(g.KernelStat), g.KernelStat.launches.offset,

@@ -172,3 +172,37 @@ def test_fused_product_and_lower_solve_match_separate_launches(lib, monkeypatch,
     assert i1["status"] == i0["status"] == 0
     assert i1["its"] == i0["its"] and i1["berr"] == i0["berr"]
     assert torch.equal(x1, x0)
+
+
+def test_caller_allocator_hooks(lib):
+    """opts.alloc / opts.free_ route every device buffer of a handle through
+    the caller's allocator (here torch's caching allocator): the solve is
+    bit-identical to the one on the library's own memory, and gmresir_free
+    hands every block back.  An allocator that fails gives ENOMEM."""
+    p = randsvd_problem(700, 1e3, 9)
+    a, b = _dev(p.a), _dev(p.b)
+    log("[alloc-hooks] n=700")
+    h = lib.factor(a, m=20, k=5)
+    x0, i0 = h.solve(b)
+    h.free()
+    al = lib.TorchAllocator()
+    h = lib.factor(a, m=20, k=5, **al.opts())
+    x1, i1 = h.solve(b)
+    assert al.calls > 0 and len(al.live) > 0
+    h.free()
+    assert len(al.live) == 0
+    assert i1["its"] == i0["its"] and torch.equal(x1, x0)
+
+    def refuse(nbytes, user):
+        return None
+
+    def nothing(ptr, user):
+        pass
+
+    ra = lib._ALLOC_FN(refuse)
+    rf = lib._FREE_FN(nothing)
+    import ctypes
+    with pytest.raises(lib.GmresirError) as ei:
+        lib.factor(a, m=20, k=5, alloc=ctypes.cast(ra, ctypes.c_void_p).value,
+                   free_=ctypes.cast(rf, ctypes.c_void_p).value)
+    assert ei.value.status == -2

@@ -97,3 +97,31 @@ def test_reuse_recycle_full_path(lib, n, kappa, m, k):
     x, info = h.solve(_dev(p.b))
     h.free()
     _compare(p, x_ref, info_ref, x.cpu().numpy(), info, n, False)
+
+
+@pytest.mark.parametrize("k,seed", [(5, 1), (0, 2), (5, 3)])
+def test_mgs_shared_factors(lib, k, seed):
+    """opts.ortho = 1 (modified Gram-Schmidt, one basis column at a time) on
+    the oracle's factors against the oracle's ortho = "mgs": counts within
+    +-2 per step (the inner products are fp64 sums in another order)."""
+    p = randsvd_problem(200, 1e4, seed)
+    o = oracle_options(m=20, k=k, ortho="mgs")
+    f = refine.factor(p.a, o)
+    x_ref, info_ref = refine.solve(f, p.b)
+    log(f"[mgs-shared] n=200 k={k} seed={seed}")
+    h = lib.import_factors(_dev(p.a), _dev(encode_factors(f.lu, "fp16").view(np.int16)),
+                           f.ipiv.astype(np.int32), f.e, **lib_options(o))
+    x, info = h.solve(_dev(p.b))
+    h.free()
+    _compare(p, x_ref, info_ref, x.cpu().numpy(), info, 200, False)
+
+
+def test_mgs_full_path_ragged(lib):
+    p = randsvd_problem(513, 1e4, 2)
+    o = oracle_options(m=30, k=10, ortho="mgs")
+    x_ref, info_ref, _ = refine.gmresir(p.a, p.b, o)
+    log("[mgs-full] n=513")
+    h = lib.factor(_dev(p.a), **lib_options(o))
+    x, info = h.solve(_dev(p.b))
+    h.free()
+    _compare(p, x_ref, info_ref, x.cpu().numpy(), info, 513, False)

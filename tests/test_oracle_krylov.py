@@ -240,3 +240,42 @@ def test_recycled_second_system_needs_fewer_iterations():
     o0 = KrylovOptions(m=30, k=0, tau=1e-8, u="fp64")
     _, p2 = gcrodr(ap, a64, g.standard_normal(n), o0, st0)
     assert r2.its < p2.its
+
+
+def test_mgs_is_the_sequential_recurrence_exactly():
+    """Modified Gram-Schmidt (the oracle's ortho="mgs"): on dyadic inputs every
+    fp64 operation is exact, so the oracle must reproduce the recurrence
+    h_i = q_i . w_i, w_{i+1} = w_i - h_i q_i in exact rational arithmetic;
+    on a non-orthogonal basis that differs from classical Gram-Schmidt, so a
+    swap of the schemes is seen."""
+    from fractions import Fraction
+    from oracle.krylov import _orthogonalise
+    g = np.random.default_rng(3)
+    basis = g.integers(-2, 3, (6, 3)) / 4.0
+    w = g.integers(-4, 5, 6) / 8.0
+    wo, h = _orthogonalise(w.copy(), basis, "fp64", "mgs")
+    wf = [Fraction(x) for x in w]
+    hf = []
+    for i in range(3):
+        q = [Fraction(x) for x in basis[:, i]]
+        hi = sum(a * b for a, b in zip(q, wf))
+        hf.append(hi)
+        wf = [a - hi * b for a, b in zip(wf, q)]
+    assert [Fraction(x) for x in h] == hf
+    assert [Fraction(x) for x in wo] == wf
+    wc, hc = _orthogonalise(w.copy(), basis, "fp64", "cgs2")
+    assert not np.array_equal(hc, h)
+
+
+def test_mgs_arnoldi_relation_and_gmres_counts():
+    """GMRES with modified Gram-Schmidt on the diagonal operator with d
+    distinct eigenvalues: d iterations in fp64, as with CGS2."""
+    from oracle.krylov import KrylovOptions, RecycleState, gcrodr
+    d = 7
+    lam = np.repeat(np.arange(1.0, d + 1.0), 5)
+    n = lam.size
+    z = np.random.default_rng(1).standard_normal(n)
+    opts = KrylovOptions(m=20, k=0, tau=1e-12, maxit=0, u="fp64", ortho="mgs")
+    dsol, rec = gcrodr(lambda v: lam * v, lambda y: lam[:, None] * y, z, opts, RecycleState())
+    assert rec.its == d
+    assert np.max(np.abs(lam * dsol - z)) <= 1e-10 * np.max(np.abs(z))
