@@ -89,10 +89,11 @@ def parse():
                     help="also report the outcome of the ill-conditioned Toeplitz system "
                          "(prolate w = 0.48, n = 16384, m = 50, k = 20 and 0) at "
                          "(bf16, fp32, fp64) and (fp32, fp64, double-double); about 2 minutes")
-    ap.add_argument("--batched", type=int, default=0,
+    ap.add_argument("--batched", type=int, default=128,
                     help="also time this many systems of the uneven batch (n ~ U[128, 2048], "
-                         "kappa2 log-uniform in [1e1, 1e8], 1-8 right-hand sides; 512 take "
-                         "about 3 minutes) through gmresir_solve_batched")
+                         "kappa2 log-uniform in [1e1, 1e8], 1-8 right-hand sides; 128 take "
+                         "about 45 s, 512 about 3 minutes) through gmresir_solve_batched "
+                         "(0 to skip)")
     ap.add_argument("--batched-workers", type=int, default=8)
     ap.add_argument("--m2-rhs", type=int, default=16,
                     help="right-hand sides of the amortised variant (factor once, keep_recycle=1)")
@@ -197,7 +198,25 @@ def batched_bench(g, count: int, workers: int, oracle: bool):
     t = time.perf_counter()
     g.solve_batched(first, workers=workers, **opts)
     dw = time.perf_counter() - t
+    # the HBM model of one Arnoldi step at order n (the one the library's
+    # arnoldi_step class counts): A in fp32 and the fp16 factors once each,
+    # plus one read of the basis [C_k V_j] at the cycle's mean j
+    steps = 0
+    step_bytes = 0.0
+    for sp, o in zip(specs, out):
+        nn = float(sp["n"])
+        for i in o[1]:
+            s_ = float(sum(i["its"]))
+            steps += s_
+            step_bytes += s_ * (6.0 * nn * nn + (8.0 * opts["k"] + 4.0 * (opts["m"] / 2 + 1)
+                                                 + 16.0) * nn)
     rec = {"systems": count, "rhs": nrhs, "workers": workers, "seconds": dt,
+           "arnoldi_steps": int(steps),
+           "roofline": {"bound": "hbm", "achieved": step_bytes / dt / 1e9, "peak": 8000.0,
+                        "unit": "GB/s", "frac": step_bytes / dt / 1e9 / 8000.0,
+                        "what": "Arnoldi-step HBM model summed over every step of the batch, "
+                                "over the batch's whole wall time (factorisations, residuals "
+                                "and host work included)"},
            "systems_per_s": count / dt, "rhs_per_s": nrhs / dt, "converged_rhs": conv,
            "status_counts": {name: st.count(c) for c, name in
                              ((0, "OK"), (1, "ESINGULAR"), (2, "ERANGE"), (3, "ENOCONV"))},

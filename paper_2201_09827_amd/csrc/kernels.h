@@ -151,6 +151,12 @@ struct OrthoArgs {
   const CycleState* gate;
 };
 void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s);
+// the CGS2 step, the finish and the normalisation in one single-workgroup
+// launch (n <= kOrthoSmallMax, kc + nv <= 192): a.dots_out = h1, a.coef =
+// h2 (written), a.norm_out, a.w_out; vout = v_{j+1}.  Bit-identical to the
+// three k_ortho passes and k_normalize.
+constexpr int kOrthoSmallMax = 4096;
+void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s);
 // v_out = fl_u(w / H[j+1][j]) (u = fp32, or fp64 when v64)
 void launch_normalize(const void* w, void* vout, int v64, const double* H, int ldh, int step,
                       int n, const CycleState* gate, hipStream_t s);

@@ -887,6 +887,111 @@ __device__ __forceinline__ double round_u(double x) {
   return (double)(VT)x;
 }
 
+// s <- fma(X[row, c], coef[c], s) for c = 0 .. kc + nv - 1 in order: the C_k
+// columns, then the V columns.  The values of eight columns are loaded before
+// any of their products is taken, so a row waits for one memory round trip
+// per eight columns instead of one per column.
+constexpr int kBatchCols = 8;
+template <typename VT>
+__device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
+                                                const double* __restrict__ coef, double s) {
+  for (int c = 0; c < X.kc; c += kBatchCols) {
+    double v[kBatchCols];
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      v[e] = (c + e < X.kc) ? X.c64[(int64_t)(c + e) * X.ldc + row] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      if (c + e < X.kc) s = fma(v[e], coef[c + e], s);
+  }
+  const VT* V = static_cast<const VT*>(X.v);
+  const double* cv = coef + X.kc;
+  for (int c = 0; c < X.nv; c += kBatchCols) {
+    double v[kBatchCols];
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      v[e] = (c + e < X.nv) ? (double)V[(int64_t)(c + e) * X.ldv + row] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      if (c + e < X.nv) s = fma(v[e], cv[c + e], s);
+  }
+  return s;
+}
+
+// products X[row, c] * w for the columns c0 .. c0 + kDotGroup - 1 (zero for
+// columns >= ncol or an invalid row), all loads issued before any is used
+constexpr int kDotGroup = 16;
+template <typename VT>
+__device__ __forceinline__ void basis_products(const Basis& X, int c0, int ncol, int row,
+                                               bool valid, double w,
+                                               double (&pr)[kDotGroup]) {
+#pragma unroll
+  for (int e = 0; e < kDotGroup; ++e) {
+    const int c = c0 + e;
+    pr[e] = (valid && c < ncol) ? basis_at<VT>(X, c, row) : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < kDotGroup; ++e) pr[e] *= w;
+}
+
+// lane i's value of a per-index vector held as two registers (indices i and
+// 64 + i); i is the same for the whole wave
+__device__ __forceinline__ double lane_pick(double lo, double hi, int i) {
+  return i < kWave ? readlane_d(lo, i) : readlane_d(hi, i - kWave);
+}
+
+// The finish of Arnoldi step j by one whole wave (every lane calls it): the
+// Hessenberg column h = h1 + h2 (and the B column of the recycle part) is
+// stored, the j earlier Givens rotations are applied to it, the new rotation
+// annihilating beta = sqrt(norm2) is formed, and g, the residual estimate and
+// the cycle state are updated.  The lanes load the coefficients in parallel;
+// the rotations then run as one chain in registers (of the rotated column
+// only the running entry matters: the entries above it are not used again).
+__device__ __forceinline__ void arnoldi_finish(const OrthoArgs& a, const double* __restrict__ h1,
+                                               const double* __restrict__ h2, double norm2) {
+  const int lane = threadIdx.x % kWave;
+  const int j = a.step;
+  const int kc = a.X.kc;
+  for (int i = lane; i < kc; i += kWave) a.B[(int64_t)j * a.ldb + i] = h1[i] + h2[i];
+  double hc0 = 0.0, hc1 = 0.0, cs0 = 0.0, cs1 = 0.0, sn0 = 0.0, sn1 = 0.0;
+  if (lane <= j) hc0 = h1[kc + lane] + h2[kc + lane];
+  if (kWave + lane <= j) hc1 = h1[kc + kWave + lane] + h2[kc + kWave + lane];
+  if (lane < j) {
+    cs0 = a.cs[lane];
+    sn0 = a.sn[lane];
+  }
+  if (kWave + lane < j) {
+    cs1 = a.cs[kWave + lane];
+    sn1 = a.sn[kWave + lane];
+  }
+  if (lane <= j) a.H[(int64_t)j * a.ldh + lane] = hc0;
+  if (kWave + lane <= j) a.H[(int64_t)j * a.ldh + kWave + lane] = hc1;
+  const double beta = sqrt(norm2);
+  double carry = lane_pick(hc0, hc1, 0);
+  for (int i = 0; i < j; ++i) {
+    const double nxt = lane_pick(hc0, hc1, i + 1);
+    carry = -lane_pick(sn0, sn1, i) * carry + lane_pick(cs0, cs1, i) * nxt;
+  }
+  if (lane != 0) return;
+  a.H[(int64_t)j * a.ldh + j + 1] = beta;
+  const double aa = carry, bb = beta;
+  const double rr = hypot(aa, bb);
+  double c = 1.0, s = 0.0;
+  if (rr != 0.0) {
+    c = aa / rr;
+    s = bb / rr;
+  }
+  a.cs[j] = c;
+  a.sn[j] = s;
+  const double gj = a.g[j];
+  a.g[j + 1] = -s * gj;
+  a.g[j] = c * gj;
+  const double est = fabs(a.g[j + 1]);
+  a.st->est = est;
+  a.st->jdone = j + 1;
+  if (est <= a.st->tol || beta == 0.0) a.st->done = 1;
+}
+
 template <typename VT>
 __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   if (gated_off(a.gate, a.step)) return;
@@ -909,8 +1014,7 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   const VT* w_in = static_cast<const VT*>(a.w_in);
   double wv = valid ? (double)w_in[row] : 0.0;
   if ((mode & kOrthoUpdate) && valid) {
-    double s = 0.0;
-    for (int c = 0; c < ncol; ++c) s = fma(basis_at<VT>(a.X, c, row), coef_sh[c], s);
+    const double s = basis_row_fma<VT>(a.X, row, coef_sh, 0.0);
     wv = round_u<VT>(wv - s);
     static_cast<VT*>(a.w_out)[row] = (VT)wv;
   }
@@ -922,18 +1026,14 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
     // lane = row: each column is read coalesced, multiplied by this row's w
     // and summed over the wave's 64 rows by DPP, four columns at a time; the
     // four waves' sums are added through LDS
-    for (int c0 = 0; c0 < ncol; c0 += 4) {
-      double pr[4];
+    for (int c0 = 0; c0 < ncol; c0 += kDotGroup) {
+      double pr[kDotGroup];
+      basis_products<VT>(a.X, c0, ncol, row, valid, wv, pr);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = c0 + e;
-        pr[e] = (valid && c < ncol) ? basis_at<VT>(a.X, c, row) * wv : 0.0;
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) pr[e] = wave_sum_to63(pr[e]);
+      for (int e = 0; e < kDotGroup; ++e) pr[e] = wave_sum_to63(pr[e]);
       if (lane == kWave - 1) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < kDotGroup; ++e)
           if (c0 + e < ncol) colsum[wave][c0 + e] = pr[e];
       }
     }
@@ -969,40 +1069,141 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   if (tid == 0) *a.counter = 0u;
   if (!(mode & kOrthoFinish)) return;
   __syncthreads();
-  if (tid != 0) return;
-  // Arnoldi step j: h = h1 + h2, beta = ||w||, Givens update of column j
-  const int j = a.step;
-  const int kc = a.X.kc;
-  double col[129];
-  for (int i = 0; i < kc; ++i) a.B[(int64_t)j * a.ldb + i] = a.h_prev[i] + a.coef[i];
-  for (int i = 0; i <= j; ++i) {
-    col[i] = a.h_prev[kc + i] + a.coef[kc + i];
-    a.H[(int64_t)j * a.ldh + i] = col[i];
+  if (wave != 0) return;
+  arnoldi_finish(a, a.h_prev, a.coef, a.norm_out[0]);
+}
+
+
+// The whole classical Gram-Schmidt step (CGS2: dots, update and dots,
+// update and norm), the Arnoldi finish (Hessenberg column, Givens rotation,
+// residual estimate) and the normalisation of v_{j+1} in one launch of one
+// workgroup, for orders up to kOrthoSmallMax.  Every sum is formed as the
+// multi-workgroup passes form it -- per 256-row chunk the DPP sum over each
+// wave's 64 rows, the chunk's four waves added pairwise, the chunks then
+// added in order -- so the results are bit-identical to k_ortho followed by
+// k_normalize; what goes away is three launches and three cross-workgroup
+// reductions, which dominate the step at these orders.
+constexpr int kOrthoSmallThreads = 1024;
+constexpr int kOrthoSmallWaves = kOrthoSmallThreads / kWave;          // 16
+constexpr int kOrthoSmallChunks = kOrthoSmallMax / kRowsPerBlock;     // 16 chunks of 256 rows
+constexpr int kOrthoSmallIters = kOrthoSmallMax / kOrthoSmallThreads;  // rows per thread
+constexpr int kOrthoSmallCols = 192;                                  // kc + nv (k + m <= 189)
+
+template <typename VT>
+__device__ __forceinline__ void ortho_small_dots(const Basis& X, int ncol, int n, int nbk,
+                                                 const double (&wv)[kOrthoSmallIters],
+                                                 double (&colsum)[kOrthoSmallWaves][kOrthoSmallCols],
+                                                 double (&part)[kOrthoSmallChunks][kOrthoSmallCols],
+                                                 double* __restrict__ out_lds,
+                                                 double* __restrict__ out_global) {
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+#pragma unroll
+  for (int it = 0; it < kOrthoSmallIters; ++it) {
+    if (4 * it >= nbk) break;
+    const int row = it * kOrthoSmallThreads + tid;
+    const bool valid = row < n;
+    for (int c0 = 0; c0 < ncol; c0 += kDotGroup) {
+      double pr[kDotGroup];
+      basis_products<VT>(X, c0, ncol, row, valid, wv[it], pr);
+#pragma unroll
+      for (int e = 0; e < kDotGroup; ++e) pr[e] = wave_sum_to63(pr[e]);
+      if (lane == kWave - 1) {
+#pragma unroll
+        for (int e = 0; e < kDotGroup; ++e)
+          if (c0 + e < ncol) colsum[wave][c0 + e] = pr[e];
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 4 * ncol; idx += kOrthoSmallThreads) {
+      const int q = idx / ncol, c = idx % ncol;
+      if (4 * it + q < nbk)
+        part[4 * it + q][c] =
+            (colsum[4 * q][c] + colsum[4 * q + 1][c]) + (colsum[4 * q + 2][c] + colsum[4 * q + 3][c]);
+    }
+    __syncthreads();
   }
-  const double beta = sqrt(a.norm_out[0]);
-  a.H[(int64_t)j * a.ldh + j + 1] = beta;
-  col[j + 1] = beta;
-  for (int i = 0; i < j; ++i) {
-    const double t = a.cs[i] * col[i] + a.sn[i] * col[i + 1];
-    col[i + 1] = -a.sn[i] * col[i] + a.cs[i] * col[i + 1];
-    col[i] = t;
+  for (int c = tid; c < ncol; c += kOrthoSmallThreads) {
+    double s = 0.0;
+    for (int b = 0; b < nbk; ++b) s += part[b][c];
+    out_lds[c] = s;
+    out_global[c] = s;
   }
-  const double aa = col[j], bb = col[j + 1];
-  const double rr = hypot(aa, bb);
-  double c = 1.0, s = 0.0;
-  if (rr != 0.0) {
-    c = aa / rr;
-    s = bb / rr;
+  __syncthreads();
+}
+
+// a.dots_out: the first pass's coefficients (h1); a.coef: the second's (h2);
+// a.norm_out: the squared norm; a.w_out: w after both updates; vout: v_{j+1}
+template <typename VT>
+__global__ __launch_bounds__(kOrthoSmallThreads) void k_ortho_small(OrthoArgs a, VT* vout) {
+  if (gated_off(a.gate, a.step)) return;
+  __shared__ double colsum[kOrthoSmallWaves][kOrthoSmallCols];
+  __shared__ double part[kOrthoSmallChunks][kOrthoSmallCols];
+  __shared__ double c1[kOrthoSmallCols];
+  __shared__ double c2[kOrthoSmallCols];
+  __shared__ double red[kOrthoSmallWaves];
+  __shared__ double npart[kOrthoSmallChunks];
+  __shared__ double s_beta;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int n = a.n;
+  const int ncol = a.X.kc + a.X.nv;
+  const int nbk = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+  const VT* w_in = static_cast<const VT*>(a.w_in);
+  double wv[kOrthoSmallIters];
+#pragma unroll
+  for (int it = 0; it < kOrthoSmallIters; ++it) {
+    const int row = it * kOrthoSmallThreads + tid;
+    wv[it] = row < n ? (double)w_in[row] : 0.0;
   }
-  a.cs[j] = c;
-  a.sn[j] = s;
-  const double gj = a.g[j];
-  a.g[j + 1] = -s * gj;
-  a.g[j] = c * gj;
-  const double est = fabs(a.g[j + 1]);
-  a.st->est = est;
-  a.st->jdone = j + 1;
-  if (est <= a.st->tol || beta == 0.0) a.st->done = 1;
+  // pass 1: h1 = X^T w
+  ortho_small_dots<VT>(a.X, ncol, n, nbk, wv, colsum, part, c1, a.dots_out);
+  // pass 2: w <- fl_u(w - X h1), h2 = X^T w
+#pragma unroll
+  for (int it = 0; it < kOrthoSmallIters; ++it) {
+    const int row = it * kOrthoSmallThreads + tid;
+    if (row < n) wv[it] = round_u<VT>(wv[it] - basis_row_fma<VT>(a.X, row, c1, 0.0));
+  }
+  double* h2 = const_cast<double*>(a.coef);
+  ortho_small_dots<VT>(a.X, ncol, n, nbk, wv, colsum, part, c2, h2);
+  // pass 3: w <- fl_u(w - X h2) and its squared norm
+#pragma unroll
+  for (int it = 0; it < kOrthoSmallIters; ++it) {
+    const int row = it * kOrthoSmallThreads + tid;
+    if (row < n) {
+      wv[it] = round_u<VT>(wv[it] - basis_row_fma<VT>(a.X, row, c2, 0.0));
+      static_cast<VT*>(a.w_out)[row] = (VT)wv[it];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < kOrthoSmallIters; ++it) {
+    if (4 * it >= nbk) break;
+    const double sq = wave_sum(wv[it] * wv[it]);
+    if (lane == 0) red[wave] = sq;
+    __syncthreads();
+    if (tid < 4 && 4 * it + tid < nbk)
+      npart[4 * it + tid] = (red[4 * tid] + red[4 * tid + 1]) + (red[4 * tid + 2] + red[4 * tid + 3]);
+    __syncthreads();
+  }
+  if (wave == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nbk; ++b) s += npart[b];
+    if (lane == 0) {
+      a.norm_out[0] = s;
+      s_beta = sqrt(s);
+    }
+    arnoldi_finish(a, c1, c2, s);
+  }
+  __syncthreads();
+  // v_{j+1} = fl_u(w / beta)
+  const double beta = s_beta;
+#pragma unroll
+  for (int it = 0; it < kOrthoSmallIters; ++it) {
+    const int row = it * kOrthoSmallThreads + tid;
+    if (row < n) vout[row] = (beta > 0.0) ? (VT)(wv[it] / beta) : (VT)0;
+  }
 }
 
 template <typename VT>
@@ -1043,18 +1244,8 @@ __global__ __launch_bounds__(256) void k_cycle_update(Basis Xd, const double* __
                                                       VT* __restrict__ r, int n) {
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
-  if (d) {
-    const int nc = Xd.kc + Xd.nv;
-    double s = 0.0;
-    for (int c = 0; c < nc; ++c) s = fma(basis_at<VT>(Xd, c, row), cd[c], s);
-    d[row] = (VT)((double)d[row] + s);
-  }
-  if (r) {
-    const int nc = Xr.kc + Xr.nv;
-    double s = 0.0;
-    for (int c = 0; c < nc; ++c) s = fma(basis_at<VT>(Xr, c, row), cr[c], s);
-    r[row] = (VT)((double)r[row] - s);
-  }
+  if (d) d[row] = (VT)((double)d[row] + basis_row_fma<VT>(Xd, row, cd, 0.0));
+  if (r) r[row] = (VT)((double)r[row] - basis_row_fma<VT>(Xr, row, cr, 0.0));
 }
 
 // G[o * nx + c] = sum_rows X[row, c] Y[row, o]
@@ -1618,6 +1809,15 @@ void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_ortho<float>, dim3(nblocks(a.n, kRowsPerBlock)), dim3(256), 0, s, a,
                        mode);
+}
+
+void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s) {
+  if (a.X.v64)
+    hipLaunchKernelGGL(k_ortho_small<double>, dim3(1), dim3(kOrthoSmallThreads), 0, s, a,
+                       static_cast<double*>(vout));
+  else
+    hipLaunchKernelGGL(k_ortho_small<float>, dim3(1), dim3(kOrthoSmallThreads), 0, s, a,
+                       static_cast<float*>(vout));
 }
 
 void launch_normalize(const void* w, void* vout, int v64, const double* H, int ldh, int step,

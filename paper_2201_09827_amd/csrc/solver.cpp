@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -354,6 +355,12 @@ struct gmresir_ctx {
   // launch; GMRESIR_FUSED_ATILDE=0 at handle creation selects the separate
   // launches (the same arithmetic)
   bool fuse_atilde = true;
+  // the Arnoldi step's Gram-Schmidt passes, finish and normalisation in one
+  // single-workgroup launch (1) or as three multi-workgroup passes and a
+  // normalisation (0): bit-identical, chosen by timing both on this device
+  // for the handle's shape (GMRESIR_ORTHO_SMALL=0/1 at handle creation
+  // forces one; -1 until decided)
+  int ortho_small = -1;
   Refresh pend;     // deferred refresh of the last cycle (V, C, U untouched meanwhile)
   // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
   // it runs) and the partial sums of the products with A^T
@@ -611,6 +618,8 @@ struct ZeroList {
   }
 };
 
+int tune_ortho(gmresir_ctx* h);
+
 int alloc_solve(gmresir_ctx* h) {
   const size_t ld = (size_t)h->ld;
   const int m = h->m, k = std::max(h->k, 1);
@@ -685,7 +694,7 @@ int alloc_solve(gmresir_ctx* h) {
   GIR_TRY(pinned_init(h));
   h->ev.resize(kEventRing);
   for (auto& e2 : h->ev) GIR_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
-  return 0;
+  return tune_ortho(h);
 }
 
 int alloc_common(gmresir_ctx* h) {
@@ -950,6 +959,9 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
     h->force_hqr = q && std::strcmp(q, "householder") == 0;
     const char* f = std::getenv("GMRESIR_FUSED_ATILDE");
     h->fuse_atilde = !(f && std::strcmp(f, "0") == 0);
+    const char* os = std::getenv("GMRESIR_ORTHO_SMALL");
+    if (os && (std::strcmp(os, "0") == 0 || std::strcmp(os, "1") == 0))
+      h->ortho_small = os[0] - '0';
   }
   h->o = *opts;
   h->arena.alloc = opts->alloc;
@@ -1190,6 +1202,119 @@ gir::Basis basis(const gmresir_ctx* h, const double* c, int kc, int64_t ldc, con
 
 // column j of V
 void* vcol(gmresir_ctx* h, int j) { return static_cast<char*>(h->V) + (size_t)j * h->ld * h->ue; }
+
+// ---------------------------------------------------------------------------
+// Autotuning by measurement.  Where two kernel variants give bit-identical
+// results, the faster one on this device for a shape is found by timing both
+// once, on the handle's own (scratch) buffers, and the choice is kept for the
+// process, per device and shape; results never depend on it.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::array<int, 6>, int> g_tune;
+
+// milliseconds for `reps` runs of `run` on stream s (after one untimed run)
+template <class Fn>
+int time_runs(hipStream_t s, int reps, Fn&& run, float* ms) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GIR_HIP(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error(hipGetErrorString(e));
+    return GMRESIR_EHIP;
+  }
+  run();
+  e = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) run();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  if (e == hipSuccess) e = hipGetLastError();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) {
+    set_error(hipGetErrorString(e));
+    return GMRESIR_EHIP;
+  }
+  return 0;
+}
+
+// The Arnoldi step's orthogonalisation: the single-workgroup launch against
+// the three multi-workgroup passes and the normalisation, timed at step 0
+// with half a cycle's basis ([C_k V_{m/2+1}]) and a scratch cycle state (in
+// Mdev), so that nothing the solve keeps is touched.
+int tune_ortho(gmresir_ctx* h) {
+  if (h->ortho_small >= 0) return 0;
+  if (h->o.ortho == 1 || h->n > gir::kOrthoSmallMax || h->k + h->m + 1 > 192) {
+    h->ortho_small = 0;
+    return 0;
+  }
+  int dev = 0;
+  GIR_HIP(hipGetDevice(&dev));
+  const std::array<int, 6> key{dev, 0, h->u64 ? 1 : 0, (int)((h->n + 255) / 256), h->k, h->m};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      h->ortho_small = it->second;
+      return 0;
+    }
+  }
+  hipStream_t s = h->stream;
+  const int m = h->m, k = h->k, n = (int)h->n;
+  const int64_t ld = h->ld;
+  double* sc = h->Mdev;  // >= 4096 doubles of scratch
+  gir::CycleState* st = reinterpret_cast<gir::CycleState*>(sc);
+  gir::OrthoArgs a{};
+  a.X = basis(h, h->C, k, ld, h->V, m / 2 + 1, ld);
+  a.n = n;
+  a.w_in = h->wu;
+  a.w_out = h->wu;
+  a.partial = h->partial;
+  a.counter = h->counter;
+  a.gate = st;
+  a.step = 0;
+  a.h_prev = h->h1;
+  a.norm_out = h->nrm;
+  a.H = sc + 32;
+  a.B = sc + 64;
+  a.ldh = m + 1;
+  a.ldb = std::max(k, 1);
+  a.cs = sc + 160;
+  a.sn = sc + 170;
+  a.g = sc + 200;
+  a.st = st;
+  void* vout = vcol(h, m);
+  auto multi = [&] {
+    gir::OrthoArgs b = a;
+    b.dots_out = h->h1;
+    gir::launch_ortho(b, gir::kOrthoDots, s);
+    b.coef = h->h1;
+    b.dots_out = h->h2;
+    gir::launch_ortho(b, gir::kOrthoUpdate | gir::kOrthoDots, s);
+    b.coef = h->h2;
+    gir::launch_ortho(b, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
+    gir::launch_normalize(h->wu, vout, h->u64, b.H, m + 1, 0, n, st, s);
+  };
+  auto single = [&] {
+    gir::OrthoArgs b = a;
+    b.dots_out = h->h1;
+    b.coef = h->h2;
+    gir::launch_ortho_small(b, vout, s);
+  };
+  // a zero state: done stays 0 or, with jdone = 1 > step 0, gates nothing
+  gir::launch_fill_i32(reinterpret_cast<int*>(sc), 0, 2 * 256, s);
+  constexpr int kReps = 10;
+  float t_multi = 0.0f, t_single = 0.0f, t_multi2 = 0.0f;
+  GIR_TRY(time_runs(s, kReps, multi, &t_multi));
+  GIR_TRY(time_runs(s, kReps, single, &t_single));
+  GIR_TRY(time_runs(s, kReps, multi, &t_multi2));
+  const int choice = t_single < std::min(t_multi, t_multi2) ? 1 : 0;
+  h->ortho_small = choice;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[key] = choice;
+  return 0;
+}
 
 // dots (X^T w) and/or squared norm of a vector in u, synchronous result
 int dots_norm(gmresir_ctx* h, const gir::Basis& X, const void* w, double* dots, double* nrm2) {
@@ -1464,6 +1589,23 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       a.dots_out = h->h1;
       // basis read once per pass; the update pass also reads and writes w
       const double xb = (8.0 * kc + (double)h->ue * (j + 1)) * n;
+      if (h->o.ortho != 1 && h->ortho_small == 1) {
+        // the three passes, the finish and the normalisation in one launch
+        // of one workgroup (the same sums; the basis read four times)
+        a.coef = h->h2;
+        a.norm_out = h->nrm;
+        a.H = h->Hd;
+        a.B = h->Bd;
+        a.ldh = m + 1;
+        a.ldb = std::max(k, 1);
+        a.cs = h->cs;
+        a.sn = h->sn;
+        a.g = h->g;
+        a.st = h->st;
+        GIR_TRY(timed(h, kKcOrtho, 4.0 * xb + 4.0 * h->ue * n, s, h->st, j,
+                      [&] { gir::launch_ortho_small(a, vcol(h, j + 1), s); }));
+        return 0;
+      }
       if (h->o.ortho == 1) {
         // modified Gram-Schmidt: one basis column at a time ([C_k V_j] in
         // order), its inner product with the current w, then its update;
