@@ -108,10 +108,11 @@ void launch_trsv_cols(const void* S, int64_t ld, const int* permS, int store, in
                       const double* in, int64_t ldi, int nr, const double* Dinv, double* out,
                       int64_t ldo, double scale, uint64_t* xw, int64_t xstride, int epoch,
                       int* abortp, hipStream_t s);
-// Linv / Uinv: 2 * ceil(n/128) blocks of 128 x 128 fp64, row-major: the
+// Linv / Uinv: 3 * ceil(n/128) blocks of 128 x 128 fp64, row-major: the
 // inverses of the diagonal blocks of L and U, then the products of each
-// inverse with the neighbouring off-diagonal block the single right-hand side
-// solves read (lower: Linv_I L_{I,I-1}; upper: Uinv_I U_{I,I+1});
+// inverse with the nearest and with the second-nearest off-diagonal block
+// the solves read (lower: Linv_I L_{I,I-1}, then Linv_I L_{I,I-2}; upper:
+// Uinv_I U_{I,I+1}, then Uinv_I U_{I,I+2});
 // tmp: 2 * ceil(n/64) * 64 * 64 doubles (the 64 x 64 inverses of L, then of U)
 constexpr int kTrsvBlock = 128;
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,

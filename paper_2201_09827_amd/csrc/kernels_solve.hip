@@ -457,6 +457,10 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
     if (out64) out64 += col * cs.out;
     xw += col * cs.xw;
   }
+  // this thread's quarter row of the inverse diagonal block, kept in LDS in
+  // the order it is read (its product is formed two chain steps ahead of
+  // need, so it does not have to occupy registers)
+  __shared__ double dsh[kTS / 4][kTSThreads + 2];
   __shared__ double red[8][kTB];
   __shared__ double ysh[8][kTB];
   // vectors read by quarters: quarter q at q * kQS (padded so that the four
@@ -464,6 +468,7 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   constexpr int kQS = kTS / 4 + 2;
   __shared__ double zsh[4 * kQS];
   __shared__ double yadj[4 * kQS];
+  __shared__ double yadj2[4 * kQS];
   __shared__ int wok[8];
   const int nb = (n + kTS - 1) / kTS;
   const int nt = (n + kTB - 1) / kTB;  // 64-column tiles
@@ -478,31 +483,53 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   const bool valid = row < n;
   const int prow = valid ? (permS ? permS[row] : row) : 0;
   const typename F::T* srow = S + (int64_t)prow * ld;
-  // the neighbouring block (the last one this block waits for) enters
-  // through its precomputed product with the inverse diagonal block
+  // the two nearest blocks (the last ones this block waits for) enter
+  // through their precomputed products with the inverse diagonal block
   const bool hasAdj = kUpper ? blk < nb - 1 : blk > 0;
   const int adj = kUpper ? blk + 1 : blk - 1;
-  // the products with the inverse diagonal block and the neighbour's
-  // product: wave w takes rows 16 w .. 16 w + 15, lane l the quarter l % 4
+  const bool hasAdj2 = kUpper ? blk < nb - 2 : blk > 1;
+  const int adj2 = kUpper ? blk + 2 : blk - 2;
+  // the products with the inverse diagonal block and the neighbours'
+  // products: wave w takes rows 16 w .. 16 w + 15, lane l the quarter l % 4
   // of row 16 w + l / 4, so a row's four partial sums sit in one lane quad
   const int di = wave * 16 + lane / 4;
   const int dq4 = lane % 4;
-  double dq[kTS / 4], mq[kTS / 4];
+  double mq[kTS / 4], qq[kTS / 4];
   {
-    const double* drow = Dinv + ((int64_t)blk * kTS + di) * kTS + dq4 * (kTS / 4);
-    const double* mrow = drow + (int64_t)nb * kTS * kTS;
+    // each 128 x 128 block is read whole rows at a time (a wave reads one
+    // row per load) into dsh in the per-thread order: thread 64 (r / 16) +
+    // 4 (r % 16) + (col / 32) holds row r's columns col / 32 * 32 .. + 31
+    const double* dblk = Dinv + (int64_t)blk * kTS * kTS;
+    auto stage = [&](const double* M) {
+      __syncthreads();
+#pragma unroll 4
+      for (int k = 0; k < kTS * kTS / 2 / kTSThreads; ++k) {
+        const int idx = k * kTSThreads + tid;
+        const int r = idx >> 6, col = 2 * (idx & 63);
+        const double2 v = *reinterpret_cast<const double2*>(M + (int64_t)r * kTS + col);
+        const int t2 = 64 * (r >> 4) + 4 * (r & 15) + (col >> 5);
+        dsh[col & 31][t2] = v.x;
+        dsh[(col & 31) + 1][t2] = v.y;
+      }
+      __syncthreads();
+    };
+    if (hasAdj) {
+      stage(dblk + (int64_t)nb * kTS * kTS);
 #pragma unroll
-    for (int c = 0; c < kTS / 4; c += 2) {
-      const double2 v = *reinterpret_cast<const double2*>(drow + c);
-      dq[c] = v.x;
-      dq[c + 1] = v.y;
-    }
+      for (int c = 0; c < kTS / 4; ++c) mq[c] = dsh[c][tid];
+    } else {
 #pragma unroll
-    for (int c = 0; c < kTS / 4; c += 2) {
-      const double2 v = hasAdj ? *reinterpret_cast<const double2*>(mrow + c) : double2{0.0, 0.0};
-      mq[c] = v.x;
-      mq[c + 1] = v.y;
+      for (int c = 0; c < kTS / 4; ++c) mq[c] = 0.0;
     }
+    if (hasAdj2) {
+      stage(dblk + 2 * (int64_t)nb * kTS * kTS);
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) qq[c] = dsh[c][tid];
+    } else {
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) qq[c] = 0.0;
+    }
+    stage(dblk);
   }
   double rhs = 0.0;
   if (!kFused && tid < kTS && r0 + tid < n) {
@@ -511,9 +538,9 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
   }
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   bool ok = true;
-  // off-diagonal tiles other than the neighbouring block's two
-  const int t0 = kUpper ? 2 * blk + 4 : 0;
-  const int t1 = kUpper ? nt : (blk > 0 ? 2 * blk - 2 : 0);
+  // off-diagonal tiles other than the two nearest blocks' four
+  const int t0 = kUpper ? 2 * blk + 6 : 0;
+  const int t1 = kUpper ? nt : (blk > 2 ? 2 * blk - 4 : 0);
   // lower: ascending from tile wq; upper: descending from the last tile
   for (int i = wq;; i += 4) {
     const int J = kUpper ? t1 - 1 - i : t0 + i;
@@ -563,10 +590,30 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
     const double* z = zsh + dq4 * kQS;
 #pragma unroll
     for (int c = 0; c < kTS / 4; c += 4) {
-      p0 = fma(dq[c], z[c], p0);
-      p1 = fma(dq[c + 1], z[c + 1], p1);
-      p2 = fma(dq[c + 2], z[c + 2], p2);
-      p3 = fma(dq[c + 3], z[c + 3], p3);
+      p0 = fma(dsh[c][tid], z[c], p0);
+      p1 = fma(dsh[c + 1][tid], z[c + 1], p1);
+      p2 = fma(dsh[c + 2][tid], z[c + 2], p2);
+      p3 = fma(dsh[c + 3][tid], z[c + 3], p3);
+    }
+  }
+  if (hasAdj2) {
+    // the second-nearest block's values, one chain step ahead of need
+    if (wave == 0) {
+      double ya0 = 0.0, ya1 = 0.0;
+      const bool got = get_tagged_block(xw, adj2 * kTS, epoch, ya0, ya1, abortp);
+      yadj2[(lane / 32) * kQS + lane % 32] = ya0;
+      yadj2[(2 + lane / 32) * kQS + lane % 32] = ya1;
+      if (lane == 0) wok[1] = got ? 1 : 0;
+    }
+    __syncthreads();
+    if (!wok[1]) return;
+    const double* ya = yadj2 + dq4 * kQS;
+#pragma unroll
+    for (int c = 0; c < kTS / 4; c += 4) {
+      p0 = fma(-qq[c], ya[c], p0);
+      p1 = fma(-qq[c + 1], ya[c + 1], p1);
+      p2 = fma(-qq[c + 2], ya[c + 2], p2);
+      p3 = fma(-qq[c + 3], ya[c + 3], p3);
     }
   }
   if (hasAdj) {
@@ -692,11 +739,11 @@ template <class F, bool kUpper>
 __device__ __forceinline__ void adjacent_product(const typename F::T* __restrict__ S, int64_t ld,
                                                  const int* __restrict__ permS, int n,
                                                  const double* __restrict__ Dinv,
-                                                 double* __restrict__ P,
+                                                 double* __restrict__ P, int dist,
                                                  double (&B)[kTS][kTS / 4 + 1]) {
   constexpr int kC = kTS / 4;
-  const int blk = kUpper ? (int)blockIdx.x : (int)blockIdx.x + 1;
-  const int adj = kUpper ? blk + 1 : blk - 1;
+  const int blk = kUpper ? (int)blockIdx.x : (int)blockIdx.x + dist;
+  const int adj = kUpper ? blk + dist : blk - dist;
   const int c0 = adj * kTS + (int)blockIdx.y * kC;  // first global column
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kTS * kC; idx += 256) {
@@ -733,12 +780,12 @@ __global__ __launch_bounds__(256) void k_adjacent_product(const typename F::T* _
                                                           const double* __restrict__ Linv,
                                                           double* __restrict__ PL,
                                                           const double* __restrict__ Uinv,
-                                                          double* __restrict__ PU) {
+                                                          double* __restrict__ PU, int dist) {
   __shared__ double B[kTS][kTS / 4 + 1];
   if (blockIdx.z == 0)
-    adjacent_product<F, false>(S, ld, permS, n, Linv, PL, B);
+    adjacent_product<F, false>(S, ld, permS, n, Linv, PL, dist, B);
   else
-    adjacent_product<F, true>(S, ld, permS, n, Uinv, PU, B);
+    adjacent_product<F, true>(S, ld, permS, n, Uinv, PU, dist, B);
 }
 
 // The products the transposed solves need, the neighbouring off-diagonal
@@ -1763,11 +1810,10 @@ void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store
                        tmp, tmpU);                                                           \
     hipLaunchKernelGGL((k_diag_combine<F>), dim3(g128, 2), dim3(256), 0, s, Sp, ld, permS, n, \
                        tmp, tmpU, Linv, Uinv);                                               \
-    if (g128 > 1) {                                                                          \
-      hipLaunchKernelGGL((k_adjacent_product<F>), dim3(g128 - 1, 4, 2), dim3(256), 0, s, Sp,  \
-                         ld, permS, n, Linv, Linv + (int64_t)g128 * kTS * kTS, Uinv,          \
-                         Uinv + (int64_t)g128 * kTS * kTS);                                   \
-    }                                                                                        \
+    for (int d = 1; d <= 2 && (unsigned)d < g128; ++d)                                      \
+      hipLaunchKernelGGL((k_adjacent_product<F>), dim3(g128 - d, 4, 2), dim3(256), 0, s, Sp,  \
+                         ld, permS, n, Linv, Linv + (int64_t)d * g128 * kTS * kTS, Uinv,      \
+                         Uinv + (int64_t)d * g128 * kTS * kTS, d);                            \
   } while (0)
   if (store == kStoreF16) {
     GIR_DINV(Fp16);

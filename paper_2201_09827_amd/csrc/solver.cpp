@@ -332,7 +332,9 @@ struct gmresir_ctx {
   int* permP = nullptr;   // logical -> row of A (P)
   int* permS = nullptr;   // equals perm after gmresir_factor, null after import
   int* ipiv = nullptr;
-  double *Linv = nullptr, *Uinv = nullptr;  // diagonal-block inverses, then neighbour products
+  // diagonal-block inverses, then the products with the nearest and the
+  // second-nearest off-diagonal blocks (three nb x 128 x 128 sets)
+  double *Linv = nullptr, *Uinv = nullptr;
   double *Lq = nullptr, *Uq = nullptr;      // the transposed solves' block products
   double* dtmp = nullptr;                    // 64 x 64 inverses of L and U (factor time)
   // LU scratch
@@ -708,8 +710,8 @@ int alloc_common(gmresir_ctx* h) {
     // fp64 inverses of the diagonal blocks (the double-double solves
     // substitute within the block instead)
     const size_t nb2 = (n + gir::kTrsvBlock - 1) / gir::kTrsvBlock;
-    GIR_TRY(dalloc(h->arena, &h->Linv, 2 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
-    GIR_TRY(dalloc(h->arena, &h->Uinv, 2 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    GIR_TRY(dalloc(h->arena, &h->Linv, 3 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
+    GIR_TRY(dalloc(h->arena, &h->Uinv, 3 * nb2 * gir::kTrsvBlock * gir::kTrsvBlock));
     GIR_TRY(dalloc(h->arena, &h->dtmp, 2 * ((n + 63) / 64) * 64 * 64));
   }
   GIR_TRY(dalloc(h->arena, &h->st, 1));
