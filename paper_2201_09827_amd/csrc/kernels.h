@@ -150,6 +150,9 @@ struct OrthoArgs {
   double* g;
   CycleState* st;
   const CycleState* gate;
+  // when set (kOrthoFinish), the finish also writes the step's whole cycle
+  // state there (host-mapped pinned memory the host polls); null: not written
+  CycleState* st_out;
 };
 void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s);
 // the CGS2 step, the finish and the normalisation in one single-workgroup

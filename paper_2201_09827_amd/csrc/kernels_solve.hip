@@ -1037,6 +1037,18 @@ __device__ __forceinline__ void arnoldi_finish(const OrthoArgs& a, const double*
   a.st->est = est;
   a.st->jdone = j + 1;
   if (est <= a.st->tol || beta == 0.0) a.st->done = 1;
+  if (a.st_out) {
+    // the state after this step (the abort and singular flags were set by
+    // earlier kernels, if at all) for the host's poll
+    CycleState o;
+    o.done = a.st->done;
+    o.jdone = j + 1;
+    o.abort = a.st->abort;
+    o.singular = a.st->singular;
+    o.tol = a.st->tol;
+    o.est = est;
+    *a.st_out = o;
+  }
 }
 
 template <typename VT>

@@ -1604,6 +1604,7 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
         a.sn = h->sn;
         a.g = h->g;
         a.st = h->st;
+        a.st_out = &h->st_host[j];
         GIR_TRY(timed(h, kKcOrtho, 4.0 * xb + 4.0 * h->ue * n, s, h->st, j,
                       [&] { gir::launch_ortho_small(a, vcol(h, j + 1), s); }));
         return 0;
@@ -1644,14 +1645,16 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       a.sn = h->sn;
       a.g = h->g;
       a.st = h->st;
+      a.st_out = &h->st_host[j];
       GIR_TRY(timed(h, kKcOrtho, xb + 2.0 * h->ue * n, s, h->st, j, [&] {
         gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
       }));
       gir::launch_normalize(h->wu, vcol(h, j + 1), h->u64, h->Hd, m + 1, j, n, h->st, s);
       return 0;
       }));
-      static_assert(sizeof(gir::CycleState) % 4 == 0, "CycleState is copied as words");
-      gir::launch_copy_words(&h->st_host[j], h->st, sizeof(gir::CycleState) / 4, s);
+      // the step's finish wrote its cycle state to st_host[j]; a step skipped
+      // on the device (converged earlier) writes nothing, and its slot is
+      // never read: the loop stops at the converged step's own slot
       GIR_HIP(hipEventRecord(h->ev[j % kEventRing], s));
       queued = j + 1;
       if (j >= kLaunchAhead) {
