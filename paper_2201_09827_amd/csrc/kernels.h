@@ -93,11 +93,37 @@ void launch_atilde_lower(const void* S, int64_t ld, const int* permS, int store,
                          const float* Au, int64_t lda, const int* permA, const float* v,
                          const double* Linv, double* y, uint64_t* xw, uint64_t* xt, int epoch,
                          const CycleState* gate, int step, int* abort, hipStream_t s);
-// z = U^-1 y; out64 = 2^e z, out32 = fl32(2^e z) (either may be null)
+
+// a basis [C_k, V]: kc fp64 columns, then nv columns in u
+struct Basis {
+  const double* c64;  // kc columns, column-major, ld ldc
+  int kc;
+  int64_t ldc;
+  const void* v;      // nv columns in u (fp32, or fp64 when v64), column-major, ld ldv
+  int nv;
+  int64_t ldv;
+  int v64;
+};
+
+// The first classical Gram-Schmidt pass of an Arnoldi step fused into its
+// upper solve: h1 = X^T w, w = fl32(2^e z), over the basis X = [C_k, V_j]
+// (fp32 V, kc + nv <= kDotsMaxCols); partial holds ceil(n/128) x (kc + nv)
+// per-block sums; counter is zero on entry and reset by the last block.
+// The sums are those of launch_ortho's kOrthoDots pass, bit for bit.
+constexpr int kDotsMaxCols = 192;
+struct TrsvDots {
+  Basis X;
+  double* partial;
+  unsigned int* counter;
+  double* h1;
+};
+// z = U^-1 y; out64 = 2^e z, out32 = fl32(2^e z) (either may be null); with
+// dots (out32 required), also the first Gram-Schmidt pass on out32
 void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
                        const double* y, const double* Uinv, double* z, double scale,
                        double* out64, float* out32, uint64_t* xw, int epoch,
-                       const CycleState* gate, int step, int* abort, hipStream_t s);
+                       const CycleState* gate, int step, int* abort, hipStream_t s,
+                       const TrsvDots* dots = nullptr);
 // the lower (upper = false) or upper solve for nr <= 8 right-hand sides as
 // nr independent solves in one launch (one grid row each): in / out
 // column-major (ldi / ldo); the upper solve writes scale * solution, the
@@ -118,15 +144,6 @@ constexpr int kTrsvBlock = 128;
 void launch_diag_inverses(const void* S, int64_t ld, const int* permS, int store, int n,
                           double* Linv, double* Uinv, double* tmp, hipStream_t s);
 
-struct Basis {
-  const double* c64;  // kc columns, column-major, ld ldc
-  int kc;
-  int64_t ldc;
-  const void* v;      // nv columns in u (fp32, or fp64 when v64), column-major, ld ldv
-  int nv;
-  int64_t ldv;
-  int v64;
-};
 
 enum OrthoMode { kOrthoDots = 1, kOrthoUpdate = 2, kOrthoNorm = 4, kOrthoFinish = 8 };
 struct OrthoArgs {

@@ -283,6 +283,109 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, 
   }
 }
 
+// Basis-column products shared by the orthogonalisation passes and the
+// first pass fused into the upper triangular solve.
+// fp64 sum over the 64 lanes of a wave by DPP row shifts and row broadcasts
+// (no LDS); the total lands in lane 63 (other lanes hold partial sums).  The
+// tree is fixed, so the result does not depend on timing.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), Ctrl, RowMask, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, RowMask, 0xf, false);
+  return v + __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_to63(double v) {
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8: lane 15 of each row holds the row's sum
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// rows per workgroup of the orthogonalisation passes (their 256-row chunks)
+constexpr int kRowsPerBlock = 256;
+
+// vectors in the working precision u: VT = float (u = fp32) or double (fp64)
+template <typename VT>
+__device__ __forceinline__ double basis_at(const Basis& X, int c, int row) {
+  return (c < X.kc) ? X.c64[(int64_t)c * X.ldc + row]
+                    : (double)static_cast<const VT*>(X.v)[(int64_t)(c - X.kc) * X.ldv + row];
+}
+
+// fl_u(x) held in fp64
+template <typename VT>
+__device__ __forceinline__ double round_u(double x) {
+  return (double)(VT)x;
+}
+
+// s <- fma(X[row, c], coef[c], s) for c = 0 .. kc + nv - 1 in order: the C_k
+// columns, then the V columns.  The values of eight columns are loaded before
+// any of their products is taken, so a row waits for one memory round trip
+// per eight columns instead of one per column.
+constexpr int kBatchCols = 8;
+template <typename VT>
+__device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
+                                                const double* __restrict__ coef, double s) {
+  for (int c = 0; c < X.kc; c += kBatchCols) {
+    double v[kBatchCols];
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      v[e] = (c + e < X.kc) ? X.c64[(int64_t)(c + e) * X.ldc + row] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      if (c + e < X.kc) s = fma(v[e], coef[c + e], s);
+  }
+  const VT* V = static_cast<const VT*>(X.v);
+  const double* cv = coef + X.kc;
+  for (int c = 0; c < X.nv; c += kBatchCols) {
+    double v[kBatchCols];
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      v[e] = (c + e < X.nv) ? (double)V[(int64_t)(c + e) * X.ldv + row] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kBatchCols; ++e)
+      if (c + e < X.nv) s = fma(v[e], cv[c + e], s);
+  }
+  return s;
+}
+
+// products X[row, c] * w for the columns c0 .. c0 + kDotGroup - 1 (zero for
+// columns >= ncol or an invalid row), all loads issued before any is used
+constexpr int kDotGroup = 16;
+template <typename VT>
+__device__ __forceinline__ void basis_products(const Basis& X, int c0, int ncol, int row,
+                                               bool valid, double w,
+                                               double (&pr)[kDotGroup]) {
+#pragma unroll
+  for (int e = 0; e < kDotGroup; ++e) {
+    const int c = c0 + e;
+    pr[e] = (valid && c < ncol) ? basis_at<VT>(X, c, row) : 0.0;
+  }
+#pragma unroll
+  for (int e = 0; e < kDotGroup; ++e) pr[e] *= w;
+}
+
+// s = ((0 + p[0]) + p[stride]) + ... over count values in order, the values
+// of eight at a time loaded before any is added (one memory round trip per
+// eight instead of per value)
+__device__ __forceinline__ double ordered_sum(const double* __restrict__ p, int count,
+                                              int64_t stride) {
+  double s = 0.0;
+  for (int b = 0; b < count; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (b + e < count) ? p[(int64_t)(b + e) * stride] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (b + e < count) s += v[e];
+  }
+  return s;
+}
+
+
 // ---------------------------------------------------------------------------
 // Triangular solves with the u_f factors in fp64 arithmetic.
 //
@@ -427,7 +530,7 @@ struct FusedGemv {
   uint64_t* xt;
 };
 
-template <class F, bool kUpper, bool kFused = false>
+template <class F, bool kUpper, bool kFused = false, bool kDots = false>
 __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __restrict__ S,
                                                      int64_t ld, const int* __restrict__ permS,
                                                      int n, const double* __restrict__ in,
@@ -437,7 +540,8 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
                                                      float* __restrict__ out32, uint64_t* xw,
                                                      uint32_t epoch, const CycleState* gate,
                                                      int step, int* abortp, ColStrides cs,
-                                                     FusedGemv fg = FusedGemv{}) {
+                                                     FusedGemv fg = FusedGemv{},
+                                                     TrsvDots td = TrsvDots{}) {
   if (gated_off(gate, step)) return;
   if (kFused && (int)blockIdx.x >= (n + kTS - 1) / kTS) {
     // a product workgroup: rows 8 (b - nb) + wave
@@ -638,15 +742,72 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
     }
   }
   const double p = quad_sum((p0 + p1) + (p2 + p3));
-  if (dq4 != 0) return;
+  if constexpr (!kDots) {
+    if (dq4 != 0) return;
+  }
   const int rr = r0 + di;
   const double v = (rr < n) ? p : 0.0;
-  if (rr < n) {
-    if (y) y[rr] = v;
-    if (out64) out64[rr] = v * scale;
-    if (out32) out32[rr] = (float)(v * scale);
+  if (dq4 == 0) {
+    if (rr < n) {
+      if (y) y[rr] = v;
+      if (out64) out64[rr] = v * scale;
+      if (out32) out32[rr] = (float)(v * scale);
+    }
+    put_tagged(xw, rr, v, epoch);
   }
-  put_tagged(xw, rr, v, epoch);
+  if constexpr (kDots) {
+    // the first classical Gram-Schmidt pass of the Arnoldi step on this
+    // block's rows of w = fl_u(2^e z): lane = row, each basis column summed
+    // over a wave's 64 rows by the orthogonalisation's DPP tree, the two
+    // waves added as the passes add a chunk's first (or second) pair of
+    // waves; the last block adds the pairs of each 256-row chunk and then
+    // the chunks in order, so h1 is bit-identical to the separate pass
+    __shared__ double wsh[kTS];
+    __shared__ double hsum[2][kDotsMaxCols];
+    __shared__ unsigned int s_ticket;
+    if (dq4 == 0) wsh[di] = (rr < n) ? (double)(float)(v * scale) : 0.0;
+    __syncthreads();
+    const int ncol = td.X.kc + td.X.nv;
+    if (wave < 2) {
+      const int lrow = wave * kWave + lane;
+      const int grow = r0 + lrow;
+      const double wv = wsh[lrow];
+      for (int c0 = 0; c0 < ncol; c0 += kDotGroup) {
+        double pr[kDotGroup];
+        basis_products<float>(td.X, c0, ncol, grow, grow < n, wv, pr);
+#pragma unroll
+        for (int e = 0; e < kDotGroup; ++e) pr[e] = wave_sum_to63(pr[e]);
+        if (lane == kWave - 1) {
+#pragma unroll
+          for (int e = 0; e < kDotGroup; ++e)
+            if (c0 + e < ncol) hsum[wave][c0 + e] = pr[e];
+        }
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < ncol; c += kTSThreads)
+      td.partial[(int64_t)blk * ncol + c] = hsum[0][c] + hsum[1][c];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_ticket = atomicAdd(td.counter, 1u);
+    __syncthreads();
+    if (s_ticket != (unsigned)nb - 1) return;
+    __threadfence();
+    for (int c = tid; c < ncol; c += kTSThreads) {
+      double sum = 0.0;
+      for (int b = 0; b < nb; b += 16) {
+        double v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          v[e] = (b + e < nb) ? td.partial[(int64_t)(b + e) * ncol + c] : 0.0;
+#pragma unroll
+        for (int e = 0; e < 16; e += 2)
+          if (b + e < nb) sum += v[e] + v[e + 1];
+      }
+      td.h1[c] = sum;
+    }
+    if (tid == 0) *td.counter = 0u;
+  }
 }
 
 // 128 x 128 inverses of the diagonal blocks from the 64 x 64 ones (D64):
@@ -896,91 +1057,9 @@ __global__ __launch_bounds__(64) void k_diag_inverse(const typename F::T* __rest
     diag_inverse<F, true>(S, ld, permS, n, DinvU, B, X);
 }
 
-// fp64 sum over the 64 lanes of a wave by DPP row shifts and row broadcasts
-// (no LDS); the total lands in lane 63 (other lanes hold partial sums).  The
-// tree is fixed, so the result does not depend on timing.
-template <int Ctrl, int RowMask>
-__device__ __forceinline__ double dpp_add(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), Ctrl, RowMask, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), Ctrl, RowMask, 0xf, false);
-  return v + __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double wave_sum_to63(double v) {
-  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
-  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
-  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
-  v = dpp_add<0x118, 0xf>(v);  // row_shr:8: lane 15 of each row holds the row's sum
-  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  return v;
-}
-
 // ---------------------------------------------------------------------------
 // orthogonalisation passes (CGS2) with last-block reduction
 // ---------------------------------------------------------------------------
-constexpr int kRowsPerBlock = 256;
-
-// vectors in the working precision u: VT = float (u = fp32) or double (fp64)
-template <typename VT>
-__device__ __forceinline__ double basis_at(const Basis& X, int c, int row) {
-  return (c < X.kc) ? X.c64[(int64_t)c * X.ldc + row]
-                    : (double)static_cast<const VT*>(X.v)[(int64_t)(c - X.kc) * X.ldv + row];
-}
-
-// fl_u(x) held in fp64
-template <typename VT>
-__device__ __forceinline__ double round_u(double x) {
-  return (double)(VT)x;
-}
-
-// s <- fma(X[row, c], coef[c], s) for c = 0 .. kc + nv - 1 in order: the C_k
-// columns, then the V columns.  The values of eight columns are loaded before
-// any of their products is taken, so a row waits for one memory round trip
-// per eight columns instead of one per column.
-constexpr int kBatchCols = 8;
-template <typename VT>
-__device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
-                                                const double* __restrict__ coef, double s) {
-  for (int c = 0; c < X.kc; c += kBatchCols) {
-    double v[kBatchCols];
-#pragma unroll
-    for (int e = 0; e < kBatchCols; ++e)
-      v[e] = (c + e < X.kc) ? X.c64[(int64_t)(c + e) * X.ldc + row] : 0.0;
-#pragma unroll
-    for (int e = 0; e < kBatchCols; ++e)
-      if (c + e < X.kc) s = fma(v[e], coef[c + e], s);
-  }
-  const VT* V = static_cast<const VT*>(X.v);
-  const double* cv = coef + X.kc;
-  for (int c = 0; c < X.nv; c += kBatchCols) {
-    double v[kBatchCols];
-#pragma unroll
-    for (int e = 0; e < kBatchCols; ++e)
-      v[e] = (c + e < X.nv) ? (double)V[(int64_t)(c + e) * X.ldv + row] : 0.0;
-#pragma unroll
-    for (int e = 0; e < kBatchCols; ++e)
-      if (c + e < X.nv) s = fma(v[e], cv[c + e], s);
-  }
-  return s;
-}
-
-// products X[row, c] * w for the columns c0 .. c0 + kDotGroup - 1 (zero for
-// columns >= ncol or an invalid row), all loads issued before any is used
-constexpr int kDotGroup = 16;
-template <typename VT>
-__device__ __forceinline__ void basis_products(const Basis& X, int c0, int ncol, int row,
-                                               bool valid, double w,
-                                               double (&pr)[kDotGroup]) {
-#pragma unroll
-  for (int e = 0; e < kDotGroup; ++e) {
-    const int c = c0 + e;
-    pr[e] = (valid && c < ncol) ? basis_at<VT>(X, c, row) : 0.0;
-  }
-#pragma unroll
-  for (int e = 0; e < kDotGroup; ++e) pr[e] *= w;
-}
-
 // lane i's value of a per-index vector held as two registers (indices i and
 // 64 + i); i is the same for the whole wave
 __device__ __forceinline__ double lane_pick(double lo, double hi, int i) {
@@ -1115,15 +1194,11 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   __threadfence();
   if (mode & kOrthoDots) {
     for (int c = tid; c < ncol; c += 256) {
-      double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += a.partial[(int64_t)b * nout + c];
-      a.dots_out[c] = s;
+      a.dots_out[c] = ordered_sum(a.partial + c, (int)gridDim.x, nout);
     }
   }
   if ((mode & kOrthoNorm) && tid == 0) {
-    double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += a.partial[(int64_t)b * nout + ncol];
-    a.norm_out[0] = s;
+    a.norm_out[0] = ordered_sum(a.partial + ncol, (int)gridDim.x, nout);
   }
   if (tid == 0) *a.counter = 0u;
   if (!(mode & kOrthoFinish)) return;
@@ -1370,11 +1445,7 @@ __global__ __launch_bounds__(256) void k_gram(Basis X, const double* __restrict_
   __syncthreads();
   if (s_ticket != gridDim.x - 1) return;
   __threadfence();
-  for (int c = tid; c < nout; c += 256) {
-    double sum = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) sum += partial[(int64_t)b * nout + c];
-    G[c] = sum;
-  }
+  for (int c = tid; c < nout; c += 256) G[c] = ordered_sum(partial + c, (int)gridDim.x, nout);
   if (tid == 0) *counter = 0u;
 }
 
@@ -1795,10 +1866,38 @@ void launch_trsv_lower(const void* S, int64_t ld, const int* permS, int store, i
                     epoch, gate, step, abortp, s);
 }
 
+template <class F>
+using T_of = typename F::T;
+
+template <class F>
+void trsv_upper_dots_t(const void* S, int64_t ld, const int* permS, int n, const double* yin,
+                       const double* Uinv, double* z, double scale, double* out64, float* out32,
+                       uint64_t* xw, int epoch, const CycleState* gate, int step, int* abortp,
+                       const TrsvDots& td, hipStream_t s) {
+  const T_of<F>* Sp = reinterpret_cast<const T_of<F>*>(S);
+  hipLaunchKernelGGL((k_trsv<F, true, false, true>), dim3(nblocks(n, kTS)), dim3(kTSThreads), 0,
+                     s, Sp, ld, permS, n, yin, nullptr, Uinv, z, scale, out64, out32, xw,
+                     (uint32_t)epoch, gate, step, abortp, ColStrides{0, 0, 0, 0}, FusedGemv{},
+                     td);
+}
+
 void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, int n,
                        const double* yin, const double* Uinv, double* z, double scale,
                        double* out64, float* out32, uint64_t* xw, int epoch,
-                       const CycleState* gate, int step, int* abortp, hipStream_t s) {
+                       const CycleState* gate, int step, int* abortp, hipStream_t s,
+                       const TrsvDots* dots) {
+  if (dots) {
+    if (store == kStoreF16)
+      trsv_upper_dots_t<Fp16>(S, ld, permS, n, yin, Uinv, z, scale, out64, out32, xw, epoch,
+                              gate, step, abortp, *dots, s);
+    else if (store == kStoreBF16)
+      trsv_upper_dots_t<Bf16>(S, ld, permS, n, yin, Uinv, z, scale, out64, out32, xw, epoch,
+                              gate, step, abortp, *dots, s);
+    else
+      trsv_upper_dots_t<Fp32>(S, ld, permS, n, yin, Uinv, z, scale, out64, out32, xw, epoch,
+                              gate, step, abortp, *dots, s);
+    return;
+  }
   if (store == kStoreF16)
     trsv_pair<Fp16>(S, ld, permS, n, true, yin, nullptr, Uinv, z, scale, out64, out32, xw,
                     epoch, gate, step, abortp, s);

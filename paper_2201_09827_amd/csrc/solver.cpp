@@ -363,6 +363,9 @@ struct gmresir_ctx {
   // for the handle's shape (GMRESIR_ORTHO_SMALL=0/1 at handle creation
   // forces one; -1 until decided)
   int ortho_small = -1;
+  // the first Gram-Schmidt pass inside the upper solve (GMRESIR_FUSED_DOTS=0
+  // at handle creation: the separate pass; the same sums either way)
+  bool fuse_dots = true;
   Refresh pend;     // deferred refresh of the last cycle (V, C, U untouched meanwhile)
   // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
   // it runs) and the partial sums of the products with A^T
@@ -961,6 +964,8 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
     h->force_hqr = q && std::strcmp(q, "householder") == 0;
     const char* f = std::getenv("GMRESIR_FUSED_ATILDE");
     h->fuse_atilde = !(f && std::strcmp(f, "0") == 0);
+    const char* fd = std::getenv("GMRESIR_FUSED_DOTS");
+    h->fuse_dots = !(fd && std::strcmp(fd, "0") == 0);
     const char* os = std::getenv("GMRESIR_ORTHO_SMALL");
     if (os && (std::strcmp(os, "0") == 0 || std::strcmp(os, "1") == 0))
       h->ortho_small = os[0] - '0';
@@ -1017,7 +1022,8 @@ int precond_t(gmresir_ctx* h, const double* in, double* out64, void* outu,
 }
 
 int precond(gmresir_ctx* h, const double* in, const double* inl, const int* permIn, double* out64,
-            void* outu, const gir::CycleState* gate, int step, bool correction = false) {
+            void* outu, const gir::CycleState* gate, int step, bool correction = false,
+            const gir::TrsvDots* dots = nullptr) {
   const int n = (int)h->n;
   if (h->trans) return precond_t(h, in, out64, outu, gate, step);
   if (h->uni && correction) {
@@ -1066,15 +1072,26 @@ int precond(gmresir_ctx* h, const double* in, const double* inl, const int* perm
   GIR_TRY(timed(h, kKcTrsvU, bytes, h->stream, gate, step, [&] {
     gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, n, h->y64, h->Uinv, h->z64,
                            h->scale, out64, out32, h->xwU, eU, gate, step, &h->st->abort,
-                           h->stream);
+                           h->stream, dots);
   }));
   return 0;
 }
 
 // A-tilde v for v in u (vu) or in fp64 (v64): the product with A_u in u^2
 // (fp64, or double-double from A itself for u = fp64), then M^-1
+// the Arnoldi step's first Gram-Schmidt pass runs inside the upper solve
+// (fp32 basis, classical Gram-Schmidt in its multi-workgroup form, the
+// forward operator; GMRESIR_FUSED_DOTS=0 at handle creation keeps the
+// separate pass)
+bool fuse_first_dots(const gmresir_ctx* h) {
+  return h->fuse_dots && !h->trans && !h->u64 && !h->uni && h->o.ortho == 0 &&
+         h->ortho_small == 0;
+}
+
+// dots (u = fp32 only): the Arnoldi step's first Gram-Schmidt pass on the
+// result, fused into the upper solve
 int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, void* outu,
-           const gir::CycleState* gate, int step) {
+           const gir::CycleState* gate, int step, const gir::TrsvDots* dots = nullptr) {
   const double nn = (double)h->n;
   if (h->trans) {
     // A_u^T v (column sums in fp64), then M^-T
@@ -1116,7 +1133,7 @@ int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, voi
     GIR_TRY(timed(h, kKcTrsvU, tri + 24.0 * nn, h->stream, gate, step, [&] {
       gir::launch_trsv_upper(h->S, h->ld, h->permS, h->store, (int)h->n, h->y64, h->Uinv, h->z64,
                              h->scale, out64, static_cast<float*>(outu), h->xwU, eU, gate, step,
-                             &h->st->abort, h->stream);
+                             &h->st->abort, h->stream, dots);
     }));
     return 0;
   }
@@ -1125,7 +1142,7 @@ int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, voi
                   gir::launch_gemv_au(h->Au, h->ld, h->permP, (int)h->n, v32, v64, h->t64, gate,
                                       step, h->stream);
                 }));
-  return precond(h, h->t64, nullptr, nullptr, out64, outu, gate, step);
+  return precond(h, h->t64, nullptr, nullptr, out64, outu, gate, step, false, dots);
 }
 
 // C(:, 0:kk) = A-tilde Y(:, 0:kk) for fp64 columns (ld apart): the products
@@ -1565,6 +1582,9 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     GIR_TRY(upload(h, h->g, hb, sizeof(double) * (m + 2)));
     // keep the abort and singular fields of the state
     GIR_TRY(upload(h, h->st, &st0, offsetof(gir::CycleState, abort)));
+    // the orthogonalisation's reduction ticket starts at zero (a launch
+    // that gave up on a bounded wait may have left it counted)
+    gir::launch_fill_i32(reinterpret_cast<int*>(h->counter), 0, 1, s);
     GIR_TRY(upload(h, &h->st->tol, &st0.tol, 2 * sizeof(double)));
     int queued = 0;
     const size_t trec0 = h->trec.size();
@@ -1578,9 +1598,14 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       const double step_bytes = (double)n * (double)n * (double)(a_bytes(h) + store_bytes(h->store)) +
                                 (8.0 * kc + (double)h->ue * (j + 1)) * n + 4.0 * h->ue * n;
       GIR_TRY(timed(h, kKcStep, step_bytes, s, h->st, j, [&]() -> int {
-      GIR_TRY(atilde(h, vcol(h, j), nullptr, nullptr, h->wu, h->st, j));
+      const gir::Basis Xj = basis(h, h->C, kc, ld, h->V, j + 1, ld);
+      // classical Gram-Schmidt in its multi-workgroup form: the first pass
+      // (h1 = X^T w) runs inside the upper solve that produces w
+      const bool dots1 = fuse_first_dots(h) && kc + j + 1 <= gir::kDotsMaxCols;
+      const gir::TrsvDots td{Xj, h->partial, h->counter, h->h1};
+      GIR_TRY(atilde(h, vcol(h, j), nullptr, nullptr, h->wu, h->st, j, dots1 ? &td : nullptr));
       gir::OrthoArgs a{};
-      a.X = basis(h, h->C, kc, ld, h->V, j + 1, ld);
+      a.X = Xj;
       a.n = n;
       a.w_in = h->wu;
       a.w_out = h->wu;
@@ -1627,8 +1652,9 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
                         [&] { gir::launch_ortho(ai, gir::kOrthoUpdate, s); }));
         }
       } else {
-        GIR_TRY(timed(h, kKcOrtho, xb + (double)h->ue * n, s, h->st, j,
-                      [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
+        if (!dots1)
+          GIR_TRY(timed(h, kKcOrtho, xb + (double)h->ue * n, s, h->st, j,
+                        [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
         a.coef = h->h1;
         a.dots_out = h->h2;
         GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 2.0 * h->ue * n, s, h->st, j,

@@ -81,3 +81,25 @@ def test_single_launch_with_kept_recycle_space(lib, monkeypatch):
     for (x0, i0), (x1, i1) in zip(res["0"], res["1"]):
         assert i0["its"] == i1["its"] and i0["recycle_dim"] == i1["recycle_dim"]
         assert torch.equal(x0, x1)
+
+
+@pytest.mark.parametrize("n,k", [(257, 5), (384, 0), (1000, 10), (4097, 8)])
+def test_first_pass_inside_the_upper_solve_is_bit_identical(lib, monkeypatch, n, k):
+    """The Arnoldi step's first Gram-Schmidt pass formed inside the upper
+    triangular solve (the default with the multi-workgroup passes) against
+    the separate pass (GMRESIR_FUSED_DOTS=0): the per-block sums are paired
+    and the 256-row chunks added in the separate pass's order, so every
+    count and every bit of x must agree (odd and even block counts)."""
+    p = randsvd_problem(n, 1e4, 17)
+    a, b = _dev(p.a), _dev(p.b)
+    kw = dict(m=25, k=k)
+    monkeypatch.setenv("GMRESIR_ORTHO_SMALL", "0")
+    log(f"[dots-fused] n={n} k={k}")
+    x1, i1 = _solve(lib, monkeypatch, a, b, "0", **kw)
+    monkeypatch.setenv("GMRESIR_FUSED_DOTS", "0")
+    x0, i0 = _solve(lib, monkeypatch, a, b, "0", **kw)
+    monkeypatch.delenv("GMRESIR_FUSED_DOTS")
+    log(f"[dots-fused] its fused {i1['its']} separate {i0['its']}")
+    assert i1["status"] == i0["status"]
+    assert i1["its"] == i0["its"] and i1["berr"] == i0["berr"]
+    assert torch.equal(x1, x0)
