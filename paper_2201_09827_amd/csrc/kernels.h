@@ -170,6 +170,9 @@ struct OrthoArgs {
   // when set (kOrthoFinish), the finish also writes the step's whole cycle
   // state there (host-mapped pinned memory the host polls); null: not written
   CycleState* st_out;
+  // when set (kOrthoFinish), the finishing workgroup also writes
+  // v_{j+1} = fl_u(w_out / beta) there (16-byte aligned; zero when beta is not positive)
+  void* vout;
 };
 void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s);
 // the CGS2 step, the finish and the normalisation in one single-workgroup
@@ -178,9 +181,6 @@ void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s);
 // three k_ortho passes and k_normalize.
 constexpr int kOrthoSmallMax = 4096;
 void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s);
-// v_out = fl_u(w / H[j+1][j]) (u = fp32, or fp64 when v64)
-void launch_normalize(const void* w, void* vout, int v64, const double* H, int ldh, int step,
-                      int n, const CycleState* gate, hipStream_t s);
 
 // out (n x nout, col-major fp64, ld ldo) = X M, M (ncol x nout col-major) on device
 void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,

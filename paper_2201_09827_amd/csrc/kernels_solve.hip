@@ -10,6 +10,8 @@
 //    Hessenberg column, its Givens rotation and the residual estimate are
 //    updated on the device so that no host round trip sits inside a cycle;
 //  * skinny products with the recycle space (combine, gram, updates).
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace gir {
@@ -1130,6 +1132,38 @@ __device__ __forceinline__ void arnoldi_finish(const OrthoArgs& a, const double*
   }
 }
 
+// v = fl_u(w / beta) (zero when beta is not positive) over n rows by one
+// workgroup: 16-byte pieces, eight of them loaded per thread before any is
+// used, then the scalar tail
+template <typename VT>
+__device__ __forceinline__ void normalize_by_block(const VT* __restrict__ w, VT* __restrict__ v,
+                                                   int n, double beta) {
+  constexpr int kPer = 16 / (int)sizeof(VT);
+  using Vec = typename std::conditional<sizeof(VT) == 4, float4, double2>::type;
+  const int nchunk = n / kPer;
+  const int nt = (int)blockDim.x;
+  const int tid = (int)threadIdx.x;
+  for (int c0 = tid; c0 < nchunk; c0 += 8 * nt) {
+    Vec x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (c0 + e * nt < nchunk) x[e] = reinterpret_cast<const Vec*>(w)[c0 + e * nt];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (c0 + e * nt >= nchunk) continue;
+      VT in[kPer], out[kPer];
+      __builtin_memcpy(in, &x[e], 16);
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) out[q] = (beta > 0.0) ? (VT)((double)in[q] / beta) : (VT)0;
+      Vec y;
+      __builtin_memcpy(&y, out, 16);
+      reinterpret_cast<Vec*>(v)[c0 + e * nt] = y;
+    }
+  }
+  for (int i = nchunk * kPer + tid; i < n; i += nt)
+    v[i] = (beta > 0.0) ? (VT)((double)w[i] / beta) : (VT)0;
+}
+
 template <typename VT>
 __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   if (gated_off(a.gate, a.step)) return;
@@ -1203,8 +1237,12 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
   if (tid == 0) *a.counter = 0u;
   if (!(mode & kOrthoFinish)) return;
   __syncthreads();
-  if (wave != 0) return;
-  arnoldi_finish(a, a.h_prev, a.coef, a.norm_out[0]);
+  if (wave == 0) arnoldi_finish(a, a.h_prev, a.coef, a.norm_out[0]);
+  // v_{j+1} = fl_u(w / beta) by this (the last) workgroup: every other one
+  // wrote its rows of w before taking its ticket
+  if (a.vout)
+    normalize_by_block<VT>(static_cast<const VT*>(a.w_out), static_cast<VT*>(a.vout), a.n,
+                           sqrt(a.norm_out[0]));
 }
 
 
@@ -1338,17 +1376,6 @@ __global__ __launch_bounds__(kOrthoSmallThreads) void k_ortho_small(OrthoArgs a,
     const int row = it * kOrthoSmallThreads + tid;
     if (row < n) vout[row] = (beta > 0.0) ? (VT)(wv[it] / beta) : (VT)0;
   }
-}
-
-template <typename VT>
-__global__ void k_normalize(const VT* __restrict__ w, VT* __restrict__ vout,
-                            const double* __restrict__ H, int ldh, int step, int n,
-                            const CycleState* gate) {
-  if (gated_off(gate, step)) return;
-  const double beta = H[(int64_t)step * ldh + step + 1];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  vout[i] = (beta > 0.0) ? (VT)((double)w[i] / beta) : (VT)0;
 }
 
 // out[:, o] = sum_c X[:, c] M[c, o]
@@ -1975,18 +2002,6 @@ void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_ortho_small<float>, dim3(1), dim3(kOrthoSmallThreads), 0, s, a,
                        static_cast<float*>(vout));
-}
-
-void launch_normalize(const void* w, void* vout, int v64, const double* H, int ldh, int step,
-                      int n, const CycleState* gate, hipStream_t s) {
-  if (v64)
-    hipLaunchKernelGGL(k_normalize<double>, dim3(nblocks(n, 256)), dim3(256), 0, s,
-                       static_cast<const double*>(w), static_cast<double*>(vout), H, ldh, step,
-                       n, gate);
-  else
-    hipLaunchKernelGGL(k_normalize<float>, dim3(nblocks(n, 256)), dim3(256), 0, s,
-                       static_cast<const float*>(w), static_cast<float*>(vout), H, ldh, step, n,
-                       gate);
 }
 
 void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,

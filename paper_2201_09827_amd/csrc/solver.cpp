@@ -1259,7 +1259,9 @@ int time_runs(hipStream_t s, int reps, Fn&& run, float* ms) {
 }
 
 // The Arnoldi step's orthogonalisation: the single-workgroup launch against
-// the three multi-workgroup passes and the normalisation, timed at step 0
+// the three multi-workgroup passes (the last one normalising; the first is
+// timed as its own launch although a solve runs it inside the upper
+// triangular solve), timed at step 0
 // with half a cycle's basis ([C_k V_{m/2+1}]) and a scratch cycle state (in
 // Mdev), so that nothing the solve keeps is touched.
 int tune_ortho(gmresir_ctx* h) {
@@ -1312,8 +1314,8 @@ int tune_ortho(gmresir_ctx* h) {
     b.dots_out = h->h2;
     gir::launch_ortho(b, gir::kOrthoUpdate | gir::kOrthoDots, s);
     b.coef = h->h2;
+    b.vout = vout;
     gir::launch_ortho(b, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
-    gir::launch_normalize(h->wu, vout, h->u64, b.H, m + 1, 0, n, st, s);
   };
   auto single = [&] {
     gir::OrthoArgs b = a;
@@ -1672,10 +1674,10 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       a.g = h->g;
       a.st = h->st;
       a.st_out = &h->st_host[j];
-      GIR_TRY(timed(h, kKcOrtho, xb + 2.0 * h->ue * n, s, h->st, j, [&] {
+      a.vout = vcol(h, j + 1);  // the normalisation in the finishing workgroup
+      GIR_TRY(timed(h, kKcOrtho, xb + 4.0 * h->ue * n, s, h->st, j, [&] {
         gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
       }));
-      gir::launch_normalize(h->wu, vcol(h, j + 1), h->u64, h->Hd, m + 1, j, n, h->st, s);
       return 0;
       }));
       // the step's finish wrote its cycle state to st_host[j]; a step skipped
