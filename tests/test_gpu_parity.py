@@ -144,6 +144,7 @@ def test_preconditioned_products_with_shared_factors(lib, n):
 
 
 @pytest.mark.parametrize("n,uf,u", [(4097, "fp16", "fp32"), (8192, "fp16", "fp32"),
+                                    (8192, "bf16", "fp32"), (16384, "fp16", "fp32"),
                                     (16384, "fp32", "fp64")])
 def test_preconditioner_full_size_properties(lib, n, uf, u):
     """At the full sizes (oracle too slow): y = M^-1 v must satisfy
@@ -160,6 +161,8 @@ def test_preconditioner_full_size_properties(lib, n, uf, u):
     raw, ipiv, e = h.export_factors()
     if uf == "fp16":
         lu = torch.from_numpy(raw.view(np.float16)).to("cuda").to(torch.float64)
+    elif uf == "bf16":
+        lu = torch.from_numpy(raw.view(np.int16)).to("cuda").view(torch.bfloat16).to(torch.float64)
     else:
         lu = torch.from_numpy(raw).to("cuda").to(torch.float64)
     del raw
@@ -173,7 +176,7 @@ def test_preconditioner_full_size_properties(lib, n, uf, u):
     # the library's own factors at this size: partial pivoting (|L| <= 1) and
     # the blocked-GEPP componentwise backward error of P A_f = L U, in fp64
     af = a * 2.0 ** e
-    af = af.half().double() if uf == "fp16" else af.float().double()
+    af = {"fp16": af.half(), "bf16": af.bfloat16()}.get(uf, af.float()).double()
     lmax = torch.max(torch.abs(torch.tril(L, -1))).item()
     lhs = torch.abs(af[pt] - L @ U)
     rhs = torch.abs(L) @ torch.abs(U)
