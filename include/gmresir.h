@@ -360,9 +360,13 @@ int gmresir_errors_noalloc(const double* A, int64_t n, int64_t lda,
  * operations (bound = 1).  Classes, in order: "lu_panel" (a block column's
  * GEPP fused with the previous step's trailing update), "lu_trsm", "lu_gemm"
  * (factorisation; flops), "trsv_lower", "trsv_upper", "gemv_au", "residual",
- * "ortho" (solve-phase launches; bytes) and "arnoldi_step" (class 8, timing
+ * "ortho" (solve-phase launches; bytes), "arnoldi_step" (class 8, timing
  * bit 16: one whole Arnoldi step, A-tilde v_j through the normalisation,
- * with n^2 (s_A + s_f) plus one read of the basis as its bytes).  Each event
+ * with n^2 (s_A + s_f) plus one read of the basis as its bytes) and
+ * "arnoldi_cycle" (class 9, timing bit 17: a cycle's steps in one persistent
+ * launch, used for u = FP32 with classical Gram-Schmidt when n <= 2048; its
+ * work is that of the steps it took; GMRESIR_PERSISTENT=0 in the
+ * environment at handle creation keeps the separate launches).  Each event
  * pair costs a few microseconds of stream time, so time only the classes of
  * interest, or a sample of their launches (opts.timing bits 8-15).
  *

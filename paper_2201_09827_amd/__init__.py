@@ -41,7 +41,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EINTERNAL",
 MAX_STEPS = 64
 # kernel classes of gmresir_kernel_stats, bit 0 first
 KERNEL_CLASSES = ("lu_panel", "lu_trsm", "lu_gemm", "trsv_lower", "trsv_upper", "gemv_au",
-                  "residual", "ortho", "arnoldi_step")
+                  "residual", "ortho", "arnoldi_step", "arnoldi_cycle")
 
 
 def timing_mask(classes, stride: int = 0) -> int:

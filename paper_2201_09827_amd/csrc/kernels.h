@@ -182,6 +182,66 @@ void launch_ortho(const OrthoArgs& a, int mode, hipStream_t s);
 constexpr int kOrthoSmallMax = 4096;
 void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s);
 
+// A whole GMRES cycle of Arnoldi steps (u = fp32, classical Gram-Schmidt
+// twice, the forward operator) in one persistent launch of 2 ceil(n/128)
+// workgroups that stay resident for the cycle: the product with A_u, the two
+// triangular solves, the three passes, the finish and v_{j+1} per step,
+// every cross-workgroup hand-over through tagged words (the step's tag is
+// epoch0 + j).  Bit-identical to the step's separate launches.  Needs
+// n <= kCycleMaxN, m <= kCycleMaxM and all its workgroups resident at once
+// (one per compute unit: at most 32 of them): each first arrives on the
+// zeroed word *arrive; when not all have arrived within kCycleArriveUs, the
+// launch gives up before touching any result (kCycleGaveUp set in *arrive)
+// and the caller runs the steps as separate launches instead.
+constexpr int kCycleMaxN = 2048;
+constexpr unsigned kCycleGaveUp = 1u << 31;
+constexpr int kCycleArriveUs = 500;
+constexpr int kCycleMaxM = 96;
+struct CycleArgs {
+  // the u_f factors (rows permS), the fp64 diagonal-block inverses and
+  // products (three sets each, as the triangular solves take them)
+  const void* S;
+  int64_t ld;
+  const int* permS;
+  const double* Linv;
+  const double* Uinv;
+  double scale;  // 2^e of the preconditioner
+  // A_u (rows permA), ld lda
+  const float* Au;
+  int64_t lda;
+  const int* permA;
+  int n, kc, m, nsteps;
+  // the basis: C_k (fp64, ld ldc) and V (fp32, ld ldv; column 0 = v_1 on
+  // entry, columns 1 .. J written)
+  const double* C;
+  int64_t ldc;
+  float* V;
+  int64_t ldv;
+  // the Hessenberg and B columns of the steps, the rotations, the Givens
+  // right-hand side and the cycle state (as the finish writes them)
+  double* H;
+  double* B;
+  int ldh, ldb;
+  double* cs;
+  double* sn;
+  double* g;
+  CycleState* st;
+  // tagged exchange words, zeroed once: xt, xwL, xwU 2 ceil(n/128) 128 each
+  // (the product, the lower and the upper solve), vw ceil(n/128) 128 (v_{j+1}
+  // in fp32), px kCycleExchange (the passes' per-block sums), ctrl 2
+  uint64_t* xt;
+  uint64_t* xwL;
+  uint64_t* xwU;
+  uint64_t* vw;
+  uint64_t* px;
+  uint64_t* ctrl;
+  unsigned* arrive;
+  uint32_t epoch0;
+  int* abortp;
+};
+constexpr int kCycleExchange = 3 * (kCycleMaxN / kTrsvBlock) * kDotsMaxCols * 2;
+void launch_cycle(const CycleArgs& a, int store, hipStream_t s);
+
 // out (n x nout, col-major fp64, ld ldo) = X M, M (ncol x nout col-major) on device
 void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,
                     hipStream_t s);

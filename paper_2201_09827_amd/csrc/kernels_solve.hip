@@ -354,20 +354,21 @@ __device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
   return s;
 }
 
-// products X[row, c] * w for the columns c0 .. c0 + kDotGroup - 1 (zero for
+// products X[row, c] * w for the columns c0 .. c0 + G - 1 (zero for
 // columns >= ncol or an invalid row), all loads issued before any is used
+// (G = kDotGroup, or fewer where registers are short: each column's product
+// is the same whatever the group)
 constexpr int kDotGroup = 16;
-template <typename VT>
+template <typename VT, int G>
 __device__ __forceinline__ void basis_products(const Basis& X, int c0, int ncol, int row,
-                                               bool valid, double w,
-                                               double (&pr)[kDotGroup]) {
+                                               bool valid, double w, double (&pr)[G]) {
 #pragma unroll
-  for (int e = 0; e < kDotGroup; ++e) {
+  for (int e = 0; e < G; ++e) {
     const int c = c0 + e;
     pr[e] = (valid && c < ncol) ? basis_at<VT>(X, c, row) : 0.0;
   }
 #pragma unroll
-  for (int e = 0; e < kDotGroup; ++e) pr[e] *= w;
+  for (int e = 0; e < G; ++e) pr[e] *= w;
 }
 
 // s = ((0 + p[0]) + p[stride]) + ... over count values in order, the values
@@ -532,6 +533,223 @@ struct FusedGemv {
   uint64_t* xt;
 };
 
+// vectors read by quarters: quarter q at q * kQS (padded so that the four
+// quarters a lane quad reads fall in different LDS banks)
+constexpr int kQS = kTS / 4 + 2;
+
+// LDS of one triangular-solve block
+struct TrsvShared {
+  // this thread's quarter row of the inverse diagonal block, kept in the
+  // order it is read (its product is formed two chain steps ahead of need,
+  // so it does not have to occupy registers)
+  double dsh[kTS / 4][kTSThreads + 2];
+  double red[8][kTB];
+  double ysh[8][kTB];
+  double zsh[4 * kQS];
+  double yadj[4 * kQS];
+  double yadj2[4 * kQS];
+  int wok[8];
+};
+
+// One 128-row block of a blocked triangular solve (lower: block blk of L y =
+// t; upper: block blk of U z = y), run by a 512-thread workgroup: init()
+// stages the block's three fp64 matrices once, solve() runs one solve and
+// may be called again (a persistent workgroup keeps its matrices).
+template <class F, bool kUpper>
+struct TrsvBlock {
+  using T = typename F::T;
+  int n, nb, nt, blk, r0, tid, wave, lane, wq, di, dq4, adj, adj2;
+  bool valid, hasAdj, hasAdj2;
+  const T* srow;
+  double mq[kTS / 4], qq[kTS / 4];
+
+  __device__ __forceinline__ void init(TrsvShared& sm, const T* S, int64_t ld,
+                                       const int* __restrict__ permS, int n_, int blk_,
+                                       const double* __restrict__ Dinv) {
+    n = n_;
+    nb = (n + kTS - 1) / kTS;
+    nt = (n + kTB - 1) / kTB;  // 64-column tiles
+    blk = blk_;
+    r0 = blk * kTS;
+    tid = threadIdx.x;
+    wave = tid / kWave;
+    lane = tid % kWave;
+    const int half = wave >> 2;
+    wq = wave & 3;
+    const int row = r0 + half * kTB + lane;
+    valid = row < n;
+    const int prow = valid ? (permS ? permS[row] : row) : 0;
+    srow = S + (int64_t)prow * ld;
+    // the two nearest blocks (the last ones this block waits for) enter
+    // through their precomputed products with the inverse diagonal block
+    hasAdj = kUpper ? blk < nb - 1 : blk > 0;
+    adj = kUpper ? blk + 1 : blk - 1;
+    hasAdj2 = kUpper ? blk < nb - 2 : blk > 1;
+    adj2 = kUpper ? blk + 2 : blk - 2;
+    // the products with the inverse diagonal block and the neighbours'
+    // products: wave w takes rows 16 w .. 16 w + 15, lane l the quarter l % 4
+    // of row 16 w + l / 4, so a row's four partial sums sit in one lane quad
+    di = wave * 16 + lane / 4;
+    dq4 = lane % 4;
+    // each 128 x 128 block is read whole rows at a time (a wave reads one
+    // row per load) into dsh in the per-thread order: thread 64 (r / 16) +
+    // 4 (r % 16) + (col / 32) holds row r's columns col / 32 * 32 .. + 31
+    const double* dblk = Dinv + (int64_t)blk * kTS * kTS;
+    auto stage = [&](const double* M) {
+      __syncthreads();
+#pragma unroll 4
+      for (int k = 0; k < kTS * kTS / 2 / kTSThreads; ++k) {
+        const int idx = k * kTSThreads + tid;
+        const int r = idx >> 6, col = 2 * (idx & 63);
+        const double2 v = *reinterpret_cast<const double2*>(M + (int64_t)r * kTS + col);
+        const int t2 = 64 * (r >> 4) + 4 * (r & 15) + (col >> 5);
+        sm.dsh[col & 31][t2] = v.x;
+        sm.dsh[(col & 31) + 1][t2] = v.y;
+      }
+      __syncthreads();
+    };
+    if (hasAdj) {
+      stage(dblk + (int64_t)nb * kTS * kTS);
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) mq[c] = sm.dsh[c][tid];
+    } else {
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) mq[c] = 0.0;
+    }
+    if (hasAdj2) {
+      stage(dblk + 2 * (int64_t)nb * kTS * kTS);
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) qq[c] = sm.dsh[c][tid];
+    } else {
+#pragma unroll
+      for (int c = 0; c < kTS / 4; ++c) qq[c] = 0.0;
+    }
+    stage(dblk);
+  }
+
+  // One solve: the right-hand side of row r0 + tid (tid < kTS) is in[permIn
+  // (row)] (rhs_words null; loaded before the far tiles) or the value
+  // published as tagged words in rhs_words (polled after them; rows beyond n
+  // read as zero).  The block's results are published in xw with epoch.
+  // Returns false on abort; p is the value of row r0 + di (every lane of
+  // the row's quad).
+  __device__ __forceinline__ bool solve(TrsvShared& sm, uint64_t* xw, uint32_t epoch, int* abortp,
+                                        const double* __restrict__ in,
+                                        const int* __restrict__ permIn,
+                                        const uint64_t* rhs_words, double& p) {
+    double rhs = 0.0;
+    if (!rhs_words && tid < kTS && r0 + tid < n) {
+      const int rr = r0 + tid;
+      rhs = in[permIn ? permIn[rr] : rr];
+    }
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    bool ok = true;
+    // off-diagonal tiles other than the two nearest blocks' four
+    const int t0 = kUpper ? 2 * blk + 6 : 0;
+    const int t1 = kUpper ? nt : (blk > 2 ? 2 * blk - 4 : 0);
+    // lower: ascending from tile wq; upper: descending from the last tile
+    for (int i = wq;; i += 4) {
+      const int J = kUpper ? t1 - 1 - i : t0 + i;
+      if (kUpper ? (J < t0) : (J >= t1)) break;
+      RawRow<F> lv;
+      lv.load(srow, J * kTB, n, valid);
+      double yv;
+      if (!get_tagged64(xw, J * kTB, epoch, yv, abortp)) {
+        ok = false;
+        break;
+      }
+      sm.ysh[wave][lane] = yv;
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int c = 0; c < kTB; c += 4) {
+        acc0 = fma(lv.at(c), sm.ysh[wave][c], acc0);
+        acc1 = fma(lv.at(c + 1), sm.ysh[wave][c + 1], acc1);
+        acc2 = fma(lv.at(c + 2), sm.ysh[wave][c + 2], acc2);
+        acc3 = fma(lv.at(c + 3), sm.ysh[wave][c + 3], acc3);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (rhs_words && ok && tid < kTS) {
+      // waves 0 and 1: this block's right-hand side from the published rows
+      // (rows beyond n were never published and stay zero)
+      double tv = 0.0;
+      if (!get_tagged_row(rhs_words, r0 + tid < n ? r0 + tid : r0, epoch, tv, abortp)) ok = false;
+      rhs = (r0 + tid < n) ? tv : 0.0;
+    }
+    sm.red[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
+    if (lane == 0) sm.wok[wave] = ok ? 1 : 0;
+    __syncthreads();
+    int allok = 1;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) allok &= sm.wok[w];
+    if (!allok) return false;
+    if (tid < kTS) {
+      const int h = tid / kTB, l = tid % kTB;
+      const double sum =
+          (sm.red[4 * h][l] + sm.red[4 * h + 1][l]) + (sm.red[4 * h + 2][l] + sm.red[4 * h + 3][l]);
+      sm.zsh[(tid / (kTS / 4)) * kQS + tid % (kTS / 4)] = (r0 + tid < n) ? rhs - sum : 0.0;
+    }
+    __syncthreads();
+    // Dinv (in - sum over the far blocks) - Q (second neighbour's values) -
+    // P (neighbour's values), this thread's quarter of its row, in four
+    // interleaved partial sums
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    {
+      const double* z = sm.zsh + dq4 * kQS;
+#pragma unroll
+      for (int c = 0; c < kTS / 4; c += 4) {
+        p0 = fma(sm.dsh[c][tid], z[c], p0);
+        p1 = fma(sm.dsh[c + 1][tid], z[c + 1], p1);
+        p2 = fma(sm.dsh[c + 2][tid], z[c + 2], p2);
+        p3 = fma(sm.dsh[c + 3][tid], z[c + 3], p3);
+      }
+    }
+    if (hasAdj2) {
+      // the second-nearest block's values, one chain step ahead of need
+      if (wave == 0) {
+        double ya0 = 0.0, ya1 = 0.0;
+        const bool got = get_tagged_block(xw, adj2 * kTS, epoch, ya0, ya1, abortp);
+        sm.yadj2[(lane / 32) * kQS + lane % 32] = ya0;
+        sm.yadj2[(2 + lane / 32) * kQS + lane % 32] = ya1;
+        if (lane == 0) sm.wok[1] = got ? 1 : 0;
+      }
+      __syncthreads();
+      if (!sm.wok[1]) return false;
+      const double* ya = sm.yadj2 + dq4 * kQS;
+#pragma unroll
+      for (int c = 0; c < kTS / 4; c += 4) {
+        p0 = fma(-qq[c], ya[c], p0);
+        p1 = fma(-qq[c + 1], ya[c + 1], p1);
+        p2 = fma(-qq[c + 2], ya[c + 2], p2);
+        p3 = fma(-qq[c + 3], ya[c + 3], p3);
+      }
+    }
+    if (hasAdj) {
+      // wave 0 fetches the neighbour's 128 values for all
+      if (wave == 0) {
+        double ya0 = 0.0, ya1 = 0.0;
+        const bool got = get_tagged_block(xw, adj * kTS, epoch, ya0, ya1, abortp);
+        // rows lane and 64 + lane: quarters lane / 32 and 2 + lane / 32
+        sm.yadj[(lane / 32) * kQS + lane % 32] = ya0;
+        sm.yadj[(2 + lane / 32) * kQS + lane % 32] = ya1;
+        if (lane == 0) sm.wok[0] = got ? 1 : 0;
+      }
+      __syncthreads();
+      if (!sm.wok[0]) return false;
+      const double* ya = sm.yadj + dq4 * kQS;
+#pragma unroll
+      for (int c = 0; c < kTS / 4; c += 4) {
+        p0 = fma(-mq[c], ya[c], p0);
+        p1 = fma(-mq[c + 1], ya[c + 1], p1);
+        p2 = fma(-mq[c + 2], ya[c + 2], p2);
+        p3 = fma(-mq[c + 3], ya[c + 3], p3);
+      }
+    }
+    p = quad_sum((p0 + p1) + (p2 + p3));
+    return true;
+  }
+};
+
 template <class F, bool kUpper, bool kFused = false, bool kDots = false>
 __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __restrict__ S,
                                                      int64_t ld, const int* __restrict__ permS,
@@ -563,187 +781,15 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
     if (out64) out64 += col * cs.out;
     xw += col * cs.xw;
   }
-  // this thread's quarter row of the inverse diagonal block, kept in LDS in
-  // the order it is read (its product is formed two chain steps ahead of
-  // need, so it does not have to occupy registers)
-  __shared__ double dsh[kTS / 4][kTSThreads + 2];
-  __shared__ double red[8][kTB];
-  __shared__ double ysh[8][kTB];
-  // vectors read by quarters: quarter q at q * kQS (padded so that the four
-  // quarters a lane quad reads fall in different LDS banks)
-  constexpr int kQS = kTS / 4 + 2;
-  __shared__ double zsh[4 * kQS];
-  __shared__ double yadj[4 * kQS];
-  __shared__ double yadj2[4 * kQS];
-  __shared__ int wok[8];
+  __shared__ TrsvShared sm;
   const int nb = (n + kTS - 1) / kTS;
-  const int nt = (n + kTB - 1) / kTB;  // 64-column tiles
   const int blk = kUpper ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x;
-  const int r0 = blk * kTS;
-  const int tid = threadIdx.x;
-  const int wave = tid / kWave;
-  const int lane = tid % kWave;
-  const int half = wave >> 2;
-  const int wq = wave & 3;
-  const int row = r0 + half * kTB + lane;
-  const bool valid = row < n;
-  const int prow = valid ? (permS ? permS[row] : row) : 0;
-  const typename F::T* srow = S + (int64_t)prow * ld;
-  // the two nearest blocks (the last ones this block waits for) enter
-  // through their precomputed products with the inverse diagonal block
-  const bool hasAdj = kUpper ? blk < nb - 1 : blk > 0;
-  const int adj = kUpper ? blk + 1 : blk - 1;
-  const bool hasAdj2 = kUpper ? blk < nb - 2 : blk > 1;
-  const int adj2 = kUpper ? blk + 2 : blk - 2;
-  // the products with the inverse diagonal block and the neighbours'
-  // products: wave w takes rows 16 w .. 16 w + 15, lane l the quarter l % 4
-  // of row 16 w + l / 4, so a row's four partial sums sit in one lane quad
-  const int di = wave * 16 + lane / 4;
-  const int dq4 = lane % 4;
-  double mq[kTS / 4], qq[kTS / 4];
-  {
-    // each 128 x 128 block is read whole rows at a time (a wave reads one
-    // row per load) into dsh in the per-thread order: thread 64 (r / 16) +
-    // 4 (r % 16) + (col / 32) holds row r's columns col / 32 * 32 .. + 31
-    const double* dblk = Dinv + (int64_t)blk * kTS * kTS;
-    auto stage = [&](const double* M) {
-      __syncthreads();
-#pragma unroll 4
-      for (int k = 0; k < kTS * kTS / 2 / kTSThreads; ++k) {
-        const int idx = k * kTSThreads + tid;
-        const int r = idx >> 6, col = 2 * (idx & 63);
-        const double2 v = *reinterpret_cast<const double2*>(M + (int64_t)r * kTS + col);
-        const int t2 = 64 * (r >> 4) + 4 * (r & 15) + (col >> 5);
-        dsh[col & 31][t2] = v.x;
-        dsh[(col & 31) + 1][t2] = v.y;
-      }
-      __syncthreads();
-    };
-    if (hasAdj) {
-      stage(dblk + (int64_t)nb * kTS * kTS);
-#pragma unroll
-      for (int c = 0; c < kTS / 4; ++c) mq[c] = dsh[c][tid];
-    } else {
-#pragma unroll
-      for (int c = 0; c < kTS / 4; ++c) mq[c] = 0.0;
-    }
-    if (hasAdj2) {
-      stage(dblk + 2 * (int64_t)nb * kTS * kTS);
-#pragma unroll
-      for (int c = 0; c < kTS / 4; ++c) qq[c] = dsh[c][tid];
-    } else {
-#pragma unroll
-      for (int c = 0; c < kTS / 4; ++c) qq[c] = 0.0;
-    }
-    stage(dblk);
-  }
-  double rhs = 0.0;
-  if (!kFused && tid < kTS && r0 + tid < n) {
-    const int rr = r0 + tid;
-    rhs = in[permIn ? permIn[rr] : rr];
-  }
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  bool ok = true;
-  // off-diagonal tiles other than the two nearest blocks' four
-  const int t0 = kUpper ? 2 * blk + 6 : 0;
-  const int t1 = kUpper ? nt : (blk > 2 ? 2 * blk - 4 : 0);
-  // lower: ascending from tile wq; upper: descending from the last tile
-  for (int i = wq;; i += 4) {
-    const int J = kUpper ? t1 - 1 - i : t0 + i;
-    if (kUpper ? (J < t0) : (J >= t1)) break;
-    RawRow<F> lv;
-    lv.load(srow, J * kTB, n, valid);
-    double yv;
-    if (!get_tagged64(xw, J * kTB, epoch, yv, abortp)) {
-      ok = false;
-      break;
-    }
-    ysh[wave][lane] = yv;
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int c = 0; c < kTB; c += 4) {
-      acc0 = fma(lv.at(c), ysh[wave][c], acc0);
-      acc1 = fma(lv.at(c + 1), ysh[wave][c + 1], acc1);
-      acc2 = fma(lv.at(c + 2), ysh[wave][c + 2], acc2);
-      acc3 = fma(lv.at(c + 3), ysh[wave][c + 3], acc3);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-  if (kFused && ok && tid < kTS) {
-    // waves 0 and 1: this block's right-hand side from the product rows
-    // (rows beyond n were never published and stay zero)
-    double tv = 0.0;
-    if (!get_tagged_row(fg.xt, r0 + tid < n ? r0 + tid : r0, epoch, tv, abortp)) ok = false;
-    rhs = (r0 + tid < n) ? tv : 0.0;
-  }
-  red[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
-  if (lane == 0) wok[wave] = ok ? 1 : 0;
-  __syncthreads();
-  int allok = 1;
-#pragma unroll
-  for (int w = 0; w < 8; ++w) allok &= wok[w];
-  if (!allok) return;
-  if (tid < kTS) {
-    const int h = tid / kTB, l = tid % kTB;
-    const double sum = (red[4 * h][l] + red[4 * h + 1][l]) + (red[4 * h + 2][l] + red[4 * h + 3][l]);
-    zsh[(tid / (kTS / 4)) * kQS + tid % (kTS / 4)] = (r0 + tid < n) ? rhs - sum : 0.0;
-  }
-  __syncthreads();
-  // Dinv (in - sum over the far blocks) - P (neighbour's values), this
-  // thread's quarter of its row, in four interleaved partial sums
-  double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-  {
-    const double* z = zsh + dq4 * kQS;
-#pragma unroll
-    for (int c = 0; c < kTS / 4; c += 4) {
-      p0 = fma(dsh[c][tid], z[c], p0);
-      p1 = fma(dsh[c + 1][tid], z[c + 1], p1);
-      p2 = fma(dsh[c + 2][tid], z[c + 2], p2);
-      p3 = fma(dsh[c + 3][tid], z[c + 3], p3);
-    }
-  }
-  if (hasAdj2) {
-    // the second-nearest block's values, one chain step ahead of need
-    if (wave == 0) {
-      double ya0 = 0.0, ya1 = 0.0;
-      const bool got = get_tagged_block(xw, adj2 * kTS, epoch, ya0, ya1, abortp);
-      yadj2[(lane / 32) * kQS + lane % 32] = ya0;
-      yadj2[(2 + lane / 32) * kQS + lane % 32] = ya1;
-      if (lane == 0) wok[1] = got ? 1 : 0;
-    }
-    __syncthreads();
-    if (!wok[1]) return;
-    const double* ya = yadj2 + dq4 * kQS;
-#pragma unroll
-    for (int c = 0; c < kTS / 4; c += 4) {
-      p0 = fma(-qq[c], ya[c], p0);
-      p1 = fma(-qq[c + 1], ya[c + 1], p1);
-      p2 = fma(-qq[c + 2], ya[c + 2], p2);
-      p3 = fma(-qq[c + 3], ya[c + 3], p3);
-    }
-  }
-  if (hasAdj) {
-    // wave 0 fetches the neighbour's 128 values for all
-    if (wave == 0) {
-      double ya0 = 0.0, ya1 = 0.0;
-      const bool got = get_tagged_block(xw, adj * kTS, epoch, ya0, ya1, abortp);
-      // rows lane and 64 + lane: quarters lane / 32 and 2 + lane / 32
-      yadj[(lane / 32) * kQS + lane % 32] = ya0;
-      yadj[(2 + lane / 32) * kQS + lane % 32] = ya1;
-      if (lane == 0) wok[0] = got ? 1 : 0;
-    }
-    __syncthreads();
-    if (!wok[0]) return;
-    const double* ya = yadj + dq4 * kQS;
-#pragma unroll
-    for (int c = 0; c < kTS / 4; c += 4) {
-      p0 = fma(-mq[c], ya[c], p0);
-      p1 = fma(-mq[c + 1], ya[c + 1], p1);
-      p2 = fma(-mq[c + 2], ya[c + 2], p2);
-      p3 = fma(-mq[c + 3], ya[c + 3], p3);
-    }
-  }
-  const double p = quad_sum((p0 + p1) + (p2 + p3));
+  TrsvBlock<F, kUpper> tb;
+  tb.init(sm, S, ld, permS, n, blk, Dinv);
+  double p = 0.0;
+  if (!tb.solve(sm, xw, epoch, abortp, in, permIn, kFused ? fg.xt : nullptr, p)) return;
+  const int tid = tb.tid, wave = tb.wave, lane = tb.lane, di = tb.di, dq4 = tb.dq4;
+  const int r0 = tb.r0;
   if constexpr (!kDots) {
     if (dq4 != 0) return;
   }
@@ -1080,7 +1126,8 @@ __device__ __forceinline__ void arnoldi_finish(const OrthoArgs& a, const double*
   const int lane = threadIdx.x % kWave;
   const int j = a.step;
   const int kc = a.X.kc;
-  for (int i = lane; i < kc; i += kWave) a.B[(int64_t)j * a.ldb + i] = h1[i] + h2[i];
+  if (a.B)
+    for (int i = lane; i < kc; i += kWave) a.B[(int64_t)j * a.ldb + i] = h1[i] + h2[i];
   double hc0 = 0.0, hc1 = 0.0, cs0 = 0.0, cs1 = 0.0, sn0 = 0.0, sn1 = 0.0;
   if (lane <= j) hc0 = h1[kc + lane] + h2[kc + lane];
   if (kWave + lane <= j) hc1 = h1[kc + kWave + lane] + h2[kc + kWave + lane];
@@ -1092,8 +1139,8 @@ __device__ __forceinline__ void arnoldi_finish(const OrthoArgs& a, const double*
     cs1 = a.cs[kWave + lane];
     sn1 = a.sn[kWave + lane];
   }
-  if (lane <= j) a.H[(int64_t)j * a.ldh + lane] = hc0;
-  if (kWave + lane <= j) a.H[(int64_t)j * a.ldh + kWave + lane] = hc1;
+  if (a.H && lane <= j) a.H[(int64_t)j * a.ldh + lane] = hc0;
+  if (a.H && kWave + lane <= j) a.H[(int64_t)j * a.ldh + kWave + lane] = hc1;
   const double beta = sqrt(norm2);
   double carry = lane_pick(hc0, hc1, 0);
   for (int i = 0; i < j; ++i) {
@@ -1101,7 +1148,7 @@ __device__ __forceinline__ void arnoldi_finish(const OrthoArgs& a, const double*
     carry = -lane_pick(sn0, sn1, i) * carry + lane_pick(cs0, cs1, i) * nxt;
   }
   if (lane != 0) return;
-  a.H[(int64_t)j * a.ldh + j + 1] = beta;
+  if (a.H) a.H[(int64_t)j * a.ldh + j + 1] = beta;
   const double aa = carry, bb = beta;
   const double rr = hypot(aa, bb);
   double c = 1.0, s = 0.0;
@@ -1754,6 +1801,386 @@ __global__ __launch_bounds__(256) void k_rank1(double alpha, const double* __res
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+
+// ---------------------------------------------------------------------------
+// One GMRES cycle of a small system in one persistent launch
+// ---------------------------------------------------------------------------
+// 2 nb workgroups (nb = ceil(n / 128) <= 16) stay resident for the whole
+// cycle: the first nb run the upper solve's blocks (workgroup u takes block
+// nb - 1 - u, the order of that chain), the others the lower solve's; each
+// stages its block's fp64 matrices once.  Per Arnoldi step j, with the tag
+// epoch0 + j on every word the step publishes:
+//   1. every workgroup copies v_j to LDS (step 0: from V; later: from the
+//      words the previous step published) and forms its share of the rows
+//      of A_u[permA] v_j, eight at a time, published as tagged words;
+//   2. the lower blocks run their chain on those rows, the upper blocks
+//      theirs on the lower chain's published values;
+//   3. each upper block runs the three classical Gram-Schmidt passes on its
+//      128 rows, publishing its per-block sums and reading every block's,
+//      added in the order of the multi-workgroup passes;
+//   4. every upper block runs the finish on its own copy of the rotations
+//      (the same arithmetic, so the same values; block 0 also writes H and
+//      B), normalises its rows of v_{j+1} and publishes them; block 0
+//      publishes the step's verdict, which the lower blocks wait for.
+// Every sum is formed as in the separate launches of a step, so the results
+// are bit-identical to them.  Every wait is bounded and watches the abort
+// flag; a workgroup that gives up leaves the flag set and the others follow.
+constexpr int kCycleBlocks = kCycleMaxN / kTS;
+constexpr int kCycleDotGroup = 8;  // the upper blocks keep two 128-entry products in registers
+
+struct CycleShared {
+  TrsvShared t;
+  float vsh[kCycleMaxN];
+  double wsh[kTS];
+  double hsum[2][kDotsMaxCols];
+  double c1[kDotsMaxCols];
+  double c2[kDotsMaxCols];
+  double nrm[2];
+  double cs[kCycleMaxM], sn[kCycleMaxM], g[kCycleMaxM + 1];
+  CycleState st;
+};
+
+// one lane's value of entry idx of a tagged double array (two words per
+// entry); per lane, no wave vote; false on abort
+__device__ __forceinline__ bool get_tagged_lane(const uint64_t* xw, int idx, uint32_t tag,
+                                                double& v, int* abortp) {
+  const uint64_t* p = xw + 2 * idx;
+  long long spins = 0;
+  for (;;) {
+    const uint64_t lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t hi = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(lo >> 32) == tag && (uint32_t)(hi >> 32) == tag) {
+      v = __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
+      return true;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if (((++spins) & 1023) == 0) {
+      if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+      if (spins > (1ll << 22)) {
+        __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+      }
+    }
+  }
+}
+
+// v_j in LDS from the fp32 words the previous step published (one word per
+// row: tag << 32 | bits); false (for the whole workgroup) on abort
+__device__ __forceinline__ bool cycle_fetch_v(const uint64_t* vw, int n, uint32_t tag, float* vsh,
+                                              int* abortp) {
+  bool ok = true;
+  for (int i0 = 0; i0 < n && ok; i0 += 4 * kTSThreads) {
+    // four words per thread in flight, then poll the ones not yet there
+    uint64_t x[4];
+    long long spins = 0;
+    for (;;) {
+      bool all = true;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + e * kTSThreads + (int)threadIdx.x;
+        x[e] = (i < n) ? __hip_atomic_load(vw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : ((uint64_t)tag << 32);
+        all = all && (uint32_t)(x[e] >> 32) == tag;
+      }
+      if (all) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (((++spins) & 1023) == 0) {
+        if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = false;
+          break;
+        }
+        if (spins > (1ll << 22)) {
+          __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = false;
+          break;
+        }
+      }
+    }
+    if (ok) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + e * kTSThreads + (int)threadIdx.x;
+        if (i < n) vsh[i] = __uint_as_float((uint32_t)x[e]);
+      }
+    }
+  }
+  return !__syncthreads_or(!ok);
+}
+
+// step 1 of a step: v_j to LDS, then this workgroup's rows of the product
+__device__ __forceinline__ bool cycle_product(const CycleArgs& a, CycleShared& sm, int j,
+                                              uint32_t tag) {
+  const int n = a.n;
+  if (j == 0) {
+    for (int i = threadIdx.x; i < n; i += kTSThreads) sm.vsh[i] = a.V[i];
+    __syncthreads();
+  } else if (!cycle_fetch_v(a.vw, n, tag, sm.vsh, a.abortp)) {
+    return false;
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  for (int grp = (int)blockIdx.x; grp * 8 < n; grp += (int)gridDim.x) {
+    const int row = grp * 8 + wave;
+    if (row < n) {
+      const int prow = a.permA ? a.permA[row] : row;
+      const double t = gemv_au_row<float, 4>(a.Au + (int64_t)prow * a.lda, sm.vsh, n, lane);
+      if (lane == 0) put_tagged(a.xt, row, t, tag);
+    }
+  }
+  return true;
+}
+
+// the per-block sums of one exchange (cnt values per block; block b's pair
+// sum of column c at entry b cnt + c of x): per 256-row chunk the two
+// blocks' sums added, then the chunks in order from zero, for the columns
+// c = threadIdx.x, ... < cnt, into out; false (for the whole workgroup) on
+// abort
+__device__ __forceinline__ bool cycle_reduce(const uint64_t* x, int nb, int cnt, uint32_t tag,
+                                             double* out, int* abortp) {
+  bool ok = true;
+  for (int c = threadIdx.x; c < cnt && ok; c += kTSThreads) {
+    double sum = 0.0;
+    for (int b = 0; b < nb && ok; b += 8) {
+      // eight blocks' values in flight before any is waited for
+      double v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = 0.0;
+      long long spins = 0;
+      for (;;) {
+        bool all = true;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (b + e < nb) {
+            const uint64_t* p = x + 2 * ((b + e) * cnt + c);
+            const uint64_t lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t hi =
+                __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            all = all && (uint32_t)(lo >> 32) == tag && (uint32_t)(hi >> 32) == tag;
+            v[e] = __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
+          }
+        }
+        if (all) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (((++spins) & 1023) == 0) {
+          if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = false;
+            break;
+          }
+          if (spins > (1ll << 22)) {
+            __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+          }
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 8; e += 2)
+        if (b + e < nb) sum += v[e] + v[e + 1];
+    }
+    out[c] = sum;
+  }
+  return !__syncthreads_or(!ok);
+}
+
+template <class F>
+__device__ __forceinline__ void cycle_lower(const CycleArgs& a, CycleShared& sm, int nb) {
+  const int n = a.n;
+  TrsvBlock<F, false> tb;
+  tb.init(sm.t, static_cast<const typename F::T*>(a.S), a.ld, a.permS, n, (int)blockIdx.x - nb,
+          a.Linv);
+  for (int j = 0; j < a.nsteps; ++j) {
+    const uint32_t tag = a.epoch0 + (uint32_t)j;
+    if (!cycle_product(a, sm, j, tag)) return;
+    double p = 0.0;
+    if (!tb.solve(sm.t, a.xwL, tag, a.abortp, nullptr, nullptr, a.xt, p)) return;
+    const int rr = tb.r0 + tb.di;
+    if (tb.dq4 == 0) put_tagged(a.xwL, rr, rr < n ? p : 0.0, tag);
+    // the step's verdict: 0 go on, 1 converged (every upper block ends too)
+    bool ok = true;
+    double verdict = 0.0;
+    if (threadIdx.x == 0) ok = get_tagged_lane(a.ctrl, 0, tag, verdict, a.abortp);
+    if (__syncthreads_or(!ok || verdict != 0.0)) return;
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void cycle_upper(const CycleArgs& a, CycleShared& sm, int nb) {
+  const int n = a.n;
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave, lane = tid % kWave;
+  const bool lead = blockIdx.x == 0;
+  TrsvBlock<F, true> tb;
+  tb.init(sm.t, static_cast<const typename F::T*>(a.S), a.ld, a.permS, n,
+          nb - 1 - (int)blockIdx.x, a.Uinv);
+  // this workgroup's copy of the rotations and the cycle state
+  for (int i = tid; i <= a.m; i += kTSThreads) {
+    if (i < a.m) {
+      sm.cs[i] = a.cs[i];
+      sm.sn[i] = a.sn[i];
+    }
+    sm.g[i] = a.g[i];
+  }
+  if (tid == 0) sm.st = *a.st;
+  __syncthreads();
+  const int ub = tb.blk, r0 = tb.r0;
+  const int lrow = wave * kWave + lane;  // waves 0 and 1: lane = row
+  const int grow = r0 + lrow;
+  const bool vrow = wave < 2 && grow < n;
+  for (int j = 0; j < a.nsteps; ++j) {
+    const uint32_t tag = a.epoch0 + (uint32_t)j;
+    if (!cycle_product(a, sm, j, tag)) return;
+    // the upper chain on the lower chain's published values
+    double p = 0.0;
+    if (!tb.solve(sm.t, a.xwU, tag, a.abortp, nullptr, nullptr, a.xwL, p)) return;
+    {
+      const int rr = r0 + tb.di;
+      const double v = rr < n ? p : 0.0;
+      if (tb.dq4 == 0) {
+        put_tagged(a.xwU, rr, v, tag);
+        sm.wsh[tb.di] = (rr < n) ? (double)(float)(v * a.scale) : 0.0;
+      }
+    }
+    __syncthreads();
+    // w = fl32(2^e z) on this block's rows; three passes: dots, update and
+    // dots, update and norm
+    const int ncol = a.kc + j + 1;
+    const Basis X{a.C, a.kc, a.ldc, a.V, j + 1, a.ldv, 0};
+    double wv = (wave < 2) ? sm.wsh[lrow] : 0.0;
+    for (int pass = 0; pass < 3; ++pass) {
+      uint64_t* px = a.px + (int64_t)pass * kCycleBlocks * kDotsMaxCols * 2;
+      if (pass > 0 && vrow)
+        wv = round_u<float>(wv - basis_row_fma<float>(X, grow, pass == 1 ? sm.c1 : sm.c2, 0.0));
+      if (pass < 2) {
+        if (wave < 2) {
+          for (int c0 = 0; c0 < ncol; c0 += kCycleDotGroup) {
+            double pr[kCycleDotGroup];
+            basis_products<float>(X, c0, ncol, grow, grow < n, wv, pr);
+#pragma unroll
+            for (int e = 0; e < kCycleDotGroup; ++e) pr[e] = wave_sum_to63(pr[e]);
+            if (lane == kWave - 1) {
+#pragma unroll
+              for (int e = 0; e < kCycleDotGroup; ++e)
+                if (c0 + e < ncol) sm.hsum[wave][c0 + e] = pr[e];
+            }
+          }
+        }
+        __syncthreads();
+        for (int c = tid; c < ncol; c += kTSThreads)
+          put_tagged(px, ub * ncol + c, sm.hsum[0][c] + sm.hsum[1][c], tag);
+        if (!cycle_reduce(px, nb, ncol, tag, pass == 0 ? sm.c1 : sm.c2, a.abortp)) return;
+      } else {
+        const double sq = wave_sum(wv * wv);
+        if (wave < 2 && lane == 0) sm.nrm[wave] = sq;
+        __syncthreads();
+        if (tid == 0) put_tagged(px, ub, sm.nrm[0] + sm.nrm[1], tag);
+        if (!cycle_reduce(px, nb, 1, tag, sm.nrm, a.abortp)) return;
+      }
+    }
+    // the finish on this workgroup's copy (block 0 also writes H and B)
+    const double norm2 = sm.nrm[0];
+    if (wave == 0) {
+      OrthoArgs fa{};
+      fa.X = X;
+      fa.step = j;
+      fa.H = lead ? a.H : nullptr;
+      fa.B = lead ? a.B : nullptr;
+      fa.ldh = a.ldh;
+      fa.ldb = a.ldb;
+      fa.cs = sm.cs;
+      fa.sn = sm.sn;
+      fa.g = sm.g;
+      fa.st = &sm.st;
+      arnoldi_finish(fa, sm.c1, sm.c2, norm2);
+    }
+    __syncthreads();
+    // v_{j+1} = fl32(w / beta) on this block's rows, published for the next
+    // step; then the verdict
+    const double beta = sqrt(norm2);
+    const int done = sm.st.done;
+    if (vrow) {
+      const float vv = (beta > 0.0) ? (float)(wv / beta) : 0.0f;
+      a.V[(int64_t)(j + 1) * a.ldv + grow] = vv;
+      if (!done && j + 1 < a.nsteps)
+        __hip_atomic_store(a.vw + grow, ((uint64_t)(tag + 1) << 32) | __float_as_uint(vv),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lead && tid == 0) put_tagged(a.ctrl, 0, done ? 1.0 : 0.0, tag);
+    if (done) break;
+  }
+  // the cycle's state for the host (block 0's copy; every copy is the same)
+  if (lead) {
+    __syncthreads();
+    for (int i = tid; i <= a.m; i += kTSThreads) {
+      if (i < a.m) {
+        a.cs[i] = sm.cs[i];
+        a.sn[i] = sm.sn[i];
+      }
+      a.g[i] = sm.g[i];
+    }
+    if (tid == 0) {
+      a.st->done = sm.st.done;
+      a.st->jdone = sm.st.jdone;
+      a.st->est = sm.st.est;
+    }
+  }
+}
+
+// The launch goes on only if all its total workgroups are resident at once
+// (they wait for one another at every step).  Each arrives on the state word
+// (the count in the low bits) unless the launch has already given up; one
+// that has waited kCycleArriveUs without seeing all arrive gives up for the
+// launch, unless the last one arrived meanwhile (both are decided by
+// compare-and-swap on the one word, so every workgroup takes the same
+// verdict).  Returns the verdict (workgroup-uniform).
+__device__ __forceinline__ bool cycle_arrive(unsigned* state, unsigned total, int& verdict) {
+  if (threadIdx.x == 0) {
+    int go = 0;
+    unsigned old = __hip_atomic_load(state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool in = false;
+    while (!(old & kCycleGaveUp)) {
+      if (__hip_atomic_compare_exchange_strong(state, &old, old + 1, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        old += 1;
+        in = true;
+        break;
+      }
+    }
+    if (in) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz
+      for (;;) {
+        if ((old & ~kCycleGaveUp) == total && !(old & kCycleGaveUp)) {
+          go = 1;
+          break;
+        }
+        if (old & kCycleGaveUp) break;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)kCycleArriveUs * 100) {
+          if (__hip_atomic_compare_exchange_strong(state, &old, old | kCycleGaveUp,
+                                                   __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT))
+            break;
+          continue;  // old holds the word's current value
+        }
+        __builtin_amdgcn_s_sleep(2);
+        old = __hip_atomic_load(state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    verdict = go;
+  }
+  __syncthreads();
+  return verdict != 0;
+}
+
+template <class F>
+__global__ __launch_bounds__(kTSThreads) void k_cycle(CycleArgs a) {
+  __shared__ CycleShared sm;
+  __shared__ int s_verdict;
+  const int nb = (a.n + kTS - 1) / kTS;
+  if (!cycle_arrive(a.arrive, 2u * (unsigned)nb, s_verdict)) return;
+  if ((int)blockIdx.x < nb)
+    cycle_upper<F>(a, sm, nb);
+  else
+    cycle_lower<F>(a, sm, nb);
+}
+
 }  // namespace
 
 void launch_copy_words(void* dst, const void* src, int64_t words, hipStream_t s) {
@@ -2002,6 +2429,17 @@ void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_ortho_small<float>, dim3(1), dim3(kOrthoSmallThreads), 0, s, a,
                        static_cast<float*>(vout));
+}
+
+void launch_cycle(const CycleArgs& a, int store, hipStream_t s) {
+  const int nb = (a.n + kTS - 1) / kTS;
+  const dim3 grid(2 * nb), block(kTSThreads);
+  if (store == kStoreF16)
+    hipLaunchKernelGGL(k_cycle<Fp16>, grid, block, 0, s, a);
+  else if (store == kStoreBF16)
+    hipLaunchKernelGGL(k_cycle<Bf16>, grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_cycle<Fp32>, grid, block, 0, s, a);
 }
 
 void launch_combine(const Basis& X, int n, const double* M, int nout, double* out, int64_t ldo,

@@ -270,12 +270,13 @@ int dalloc(Arena& a, T** p, size_t count) {
 
 // kernel classes of gmresir_kernel_stats
 enum KClass { kKcPanel, kKcTrsm, kKcGemm, kKcTrsvL, kKcTrsvU, kKcGemv, kKcResid, kKcOrtho,
-              kKcStep, kKcCount };
+              kKcStep, kKcCycle, kKcCount };
 const char* const kKcName[kKcCount] = {"lu_panel", "lu_trsm",  "lu_gemm",  "trsv_lower",
                                        "trsv_upper", "gemv_au", "residual", "ortho",
-                                       "arnoldi_step"};
+                                       "arnoldi_step", "arnoldi_cycle"};
 // the factorisation's classes count matrix-core flops, the others HBM bytes
-constexpr bool kKcFlops[kKcCount] = {true, true, true, false, false, false, false, false, false};
+constexpr bool kKcFlops[kKcCount] = {true,  true,  true,  false, false,
+                                     false, false, false, false, false};
 // bit of opts.timing that selects class c: bits 0-7 for classes 0-7, bits
 // 16-23 for classes 8-15 (bits 8-15 hold the sampling stride)
 constexpr int timing_bit(int c) { return c < 8 ? c : c + 8; }
@@ -366,6 +367,12 @@ struct gmresir_ctx {
   // the first Gram-Schmidt pass inside the upper solve (GMRESIR_FUSED_DOTS=0
   // at handle creation: the separate pass; the same sums either way)
   bool fuse_dots = true;
+  // a cycle's Arnoldi steps in one persistent launch where the shape allows
+  // it (the same sums as the separate launches); GMRESIR_PERSISTENT=0 at
+  // handle creation keeps the separate launches
+  bool persistent = true;
+  uint64_t *cvw = nullptr, *cpx = nullptr, *cctrl = nullptr;  // its exchange words
+  int64_t cycle_fallbacks = 0;  // persistent launches that gave up (device shared)
   Refresh pend;     // deferred refresh of the last cycle (V, C, U untouched meanwhile)
   // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
   // it runs) and the partial sums of the products with A^T
@@ -675,6 +682,15 @@ int alloc_solve(gmresir_ctx* h) {
     // the A_u product's rows, published to the fused lower solve
     GIR_TRY(dalloc(h->arena, &h->xt, (size_t)nxw));
     zl.add(h->xt, sizeof(uint64_t) * (size_t)nxw);
+    if (h->n <= gir::kCycleMaxN && h->m <= gir::kCycleMaxM) {
+      // the persistent cycle's own words: v_{j+1}, the passes' sums, the verdict
+      GIR_TRY(dalloc(h->arena, &h->cvw, (size_t)nxw / 2));
+      GIR_TRY(dalloc(h->arena, &h->cpx, (size_t)gir::kCycleExchange));
+      GIR_TRY(dalloc(h->arena, &h->cctrl, 4));
+      zl.add(h->cvw, sizeof(uint64_t) * (size_t)nxw / 2);
+      zl.add(h->cpx, sizeof(uint64_t) * (size_t)gir::kCycleExchange);
+      zl.add(h->cctrl, sizeof(uint64_t) * 4);
+    }
   }
   if (!h->u64 && h->k > 0) {
     const int64_t nm = nxw * gir::kTrsvMaxRhs;
@@ -966,6 +982,8 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
     h->fuse_atilde = !(f && std::strcmp(f, "0") == 0);
     const char* fd = std::getenv("GMRESIR_FUSED_DOTS");
     h->fuse_dots = !(fd && std::strcmp(fd, "0") == 0);
+    const char* pe = std::getenv("GMRESIR_PERSISTENT");
+    h->persistent = !(pe && std::strcmp(pe, "0") == 0);
     const char* os = std::getenv("GMRESIR_ORTHO_SMALL");
     if (os && (std::strcmp(os, "0") == 0 || std::strcmp(os, "1") == 0))
       h->ortho_small = os[0] - '0';
@@ -993,6 +1011,14 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
 int next_epoch(gmresir_ctx* h) {
   if (++h->epoch >= 0x3fffffff) h->epoch = 1;
   return h->epoch;
+}
+
+// count consecutive epochs; the first is returned
+int reserve_epochs(gmresir_ctx* h, int count) {
+  if (h->epoch + count + 1 >= 0x3fffffff) h->epoch = 0;
+  const int e0 = h->epoch + 1;
+  h->epoch += count;
+  return e0;
 }
 
 // M^-1 in = 2^e U^-1 L^-1 P in (P applied by gather through permIn) in u^2:
@@ -1505,6 +1531,71 @@ struct SolveStats {
   int its = 0;
 };
 
+// a cycle's Arnoldi steps in one persistent launch: u = fp32, classical
+// Gram-Schmidt twice, the forward operator, n and m within the kernel's
+// limits (its exchange words allocated)
+bool cycle_eligible(const gmresir_ctx* h) {
+  return h->persistent && h->cvw && !h->trans && !h->u64 && !h->uni && h->o.ortho == 0 &&
+         h->fuse_atilde;
+}
+
+// up to nsteps Arnoldi steps of the cycle with kc recycled columns, one
+// launch; the results (V, H, B, the rotations and the cycle state) are where
+// the separate launches leave them.  *ran is false when the launch gave up
+// (its workgroups were not all resident together) and wrote nothing.
+int run_cycle(gmresir_ctx* h, int kc, int nsteps, bool* ran) {
+  gir::CycleArgs a{};
+  a.S = h->S;
+  a.ld = h->ld;
+  a.permS = h->permS;
+  a.Linv = h->Linv;
+  a.Uinv = h->Uinv;
+  a.scale = h->scale;
+  a.Au = h->Au;
+  a.lda = h->ld;
+  a.permA = h->permP;
+  a.n = (int)h->n;
+  a.kc = kc;
+  a.m = h->m;
+  a.nsteps = nsteps;
+  a.C = h->C;
+  a.ldc = h->ld;
+  a.V = static_cast<float*>(h->V);
+  a.ldv = h->ld;
+  a.H = h->Hd;
+  a.B = h->Bd;
+  a.ldh = h->m + 1;
+  a.ldb = std::max(h->k, 1);
+  a.cs = h->cs;
+  a.sn = h->sn;
+  a.g = h->g;
+  a.st = h->st;
+  a.xt = h->xt;
+  a.xwL = h->xwL;
+  a.xwU = h->xwU;
+  a.vw = h->cvw;
+  a.px = h->cpx;
+  a.ctrl = h->cctrl;
+  a.arrive = reinterpret_cast<unsigned*>(h->cctrl + 2);
+  a.epoch0 = (uint32_t)reserve_epochs(h, nsteps);
+  a.abortp = &h->st->abort;
+  gir::launch_fill_i32(reinterpret_cast<int*>(a.arrive), 0, 1, h->stream);
+  // the work is set once the number of steps taken is known
+  const size_t r0 = h->trec.size();
+  GIR_TRY(timed(h, kKcCycle, 0.0, h->stream, nullptr, 0,
+                [&] { gir::launch_cycle(a, h->store, h->stream); }));
+  unsigned word = 0;
+  GIR_TRY(download_many(h, {{&word, a.arrive, sizeof(word)}}));
+  *ran = !(word & gir::kCycleGaveUp);
+  if (!*ran) {
+    // not all workgroups were resident together (the device is shared):
+    // nothing was written, the caller runs the separate launches
+    h->trec.resize(r0);
+    ++h->cycle_fallbacks;
+  }
+  return 0;
+}
+
 // GCRO-DR(m, k) for A-tilde d = z (z in h->zu); result in h->du.
 int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   const int n = (int)h->n;
@@ -1593,12 +1684,17 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     // modified Gram-Schmidt's finish pass applies zero coefficients
     if (h->o.ortho == 1)
       gir::launch_fill_i32(reinterpret_cast<int*>(h->h2), 0, 2 * 256, s);
-    for (int j = 0; j < nsteps; ++j) {
-      // one Arnoldi step, timed as a whole under its own class: A_u v_j and
-      // the factors once each (the HBM model of the step) plus one read of
-      // the basis [C_k V_j]
-      const double step_bytes = (double)n * (double)n * (double)(a_bytes(h) + store_bytes(h->store)) +
-                                (8.0 * kc + (double)h->ue * (j + 1)) * n + 4.0 * h->ue * n;
+    // one Arnoldi step's work: A_u v_j and the factors once each (the HBM
+    // model of the step) plus one read of the basis [C_k V_j]
+    auto step_work = [&](int j) {
+      return (double)n * (double)n * (double)(a_bytes(h) + store_bytes(h->store)) +
+             (8.0 * kc + (double)h->ue * (j + 1)) * n + 4.0 * h->ue * n;
+    };
+    bool one_launch = false;
+    if (cycle_eligible(h)) GIR_TRY(run_cycle(h, kc, nsteps, &one_launch));
+    for (int j = 0; !one_launch && j < nsteps; ++j) {
+      // one Arnoldi step, timed as a whole under its own class
+      const double step_bytes = step_work(j);
       GIR_TRY(timed(h, kKcStep, step_bytes, s, h->st, j, [&]() -> int {
       const gir::Basis Xj = basis(h, h->C, kc, ld, h->V, j + 1, ld);
       // classical Gram-Schmidt in its multi-workgroup form: the first pass
@@ -1703,6 +1799,11 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     }
     const int J = fin.jdone;
     drop_skipped(h, trec0, J);
+    if (one_launch && h->trec.size() > trec0 && h->trec.back().cls == kKcCycle) {
+      double w = 0.0;
+      for (int j = 0; j < J; ++j) w += step_work(j);
+      h->trec.back().work = w;
+    }
     const int ldh = m + 1, ldb = std::max(k, 1);
     std::fill(y.begin(), y.end(), 0.0);
     gir::la::givens_lsq(Hh.data(), ldh, J, rn, y.data());

@@ -5,7 +5,9 @@ multi-workgroup passes and the separate normalisation: both form every sum
 in the same order, so every count and every bit of x must agree.  The
 library picks one of the two by timing them (the autotuner); the variant is
 forced here with GMRESIR_ORTHO_SMALL at handle creation, and the default
-(tuned) handle must agree with both.
+(tuned) handle must agree with both.  The cycle's persistent single launch
+(the default where the shape allows it) is switched off here
+(GMRESIR_PERSISTENT=0), so that these are the separate launches.
 """
 import numpy as np
 import pytest
@@ -16,6 +18,11 @@ from synthetic import randsvd_problem
 torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _separate_launches(monkeypatch):
+    monkeypatch.setenv("GMRESIR_PERSISTENT", "0")
 
 
 @pytest.fixture(scope="module")
