@@ -183,13 +183,14 @@ constexpr int kOrthoSmallMax = 4096;
 void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s);
 
 // A whole GMRES cycle of Arnoldi steps (u = fp32, classical Gram-Schmidt
-// twice, the forward operator) in one persistent launch of 2 ceil(n/128)
-// workgroups that stay resident for the cycle: the product with A_u, the two
-// triangular solves, the three passes, the finish and v_{j+1} per step,
-// every cross-workgroup hand-over through tagged words (the step's tag is
-// epoch0 + j).  Bit-identical to the step's separate launches.  Needs
-// n <= kCycleMaxN, m <= kCycleMaxM and all its workgroups resident at once
-// (one per compute unit: at most 32 of them): each first arrives on the
+// twice, the forward operator) in one persistent launch of 3 ceil(n/128)
+// workgroups that stay resident for the cycle (the upper and the lower
+// solve's blocks, and one per 128 rows for the product, the three passes,
+// the finish and v_{j+1}), every cross-workgroup hand-over through tagged
+// words (the step's tag is epoch0 + j).  Bit-identical to the step's
+// separate launches.  Needs n <= kCycleMaxN, m <= kCycleMaxM and all its
+// workgroups resident at once (one per compute unit: at most 48 of them):
+// each first arrives on the
 // zeroed word *arrive; when not all have arrived within kCycleArriveUs, the
 // launch gives up before touching any result (kCycleGaveUp set in *arrive)
 // and the caller runs the steps as separate launches instead.

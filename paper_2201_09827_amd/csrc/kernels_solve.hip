@@ -1805,39 +1805,55 @@ inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); 
 // ---------------------------------------------------------------------------
 // One GMRES cycle of a small system in one persistent launch
 // ---------------------------------------------------------------------------
-// 2 nb workgroups (nb = ceil(n / 128) <= 16) stay resident for the whole
-// cycle: the first nb run the upper solve's blocks (workgroup u takes block
-// nb - 1 - u, the order of that chain), the others the lower solve's; each
-// stages its block's fp64 matrices once.  Per Arnoldi step j, with the tag
-// epoch0 + j on every word the step publishes:
-//   1. every workgroup copies v_j to LDS (step 0: from V; later: from the
-//      words the previous step published) and forms its share of the rows
-//      of A_u[permA] v_j, eight at a time, published as tagged words;
-//   2. the lower blocks run their chain on those rows, the upper blocks
-//      theirs on the lower chain's published values;
-//   3. each upper block runs the three classical Gram-Schmidt passes on its
-//      128 rows, publishing its per-block sums and reading every block's,
-//      added in the order of the multi-workgroup passes;
-//   4. every upper block runs the finish on its own copy of the rotations
-//      (the same arithmetic, so the same values; block 0 also writes H and
-//      B), normalises its rows of v_{j+1} and publishes them; block 0
-//      publishes the step's verdict, which the lower blocks wait for.
+// 3 nb workgroups (nb = ceil(n / 128) <= 16) stay resident for the whole
+// cycle, in three roles of nb each:
+//   upper solve: workgroup u takes block nb - 1 - u (the chain's order);
+//   lower solve: workgroup nb + l takes block l;
+//   rows: workgroup 2 nb + b takes the 128 rows of block b for the
+//         Gram-Schmidt passes and a share of the product's rows.
+// The solve blocks stage their fp64 matrices once and keep them (in LDS and
+// registers) for the cycle; a rows workgroup keeps its rows of the basis
+// [C_k V] in LDS.  Per Arnoldi step j, with the tag epoch0 + j on every word
+// the step publishes:
+//   1. the rows workgroups take v_j (step 0: from V; later: from the words
+//      they published) and form the rows of A_u[permA] v_j in row order,
+//      published as tagged words;
+//   2. the lower chain runs on those rows, the upper chain on the lower
+//      chain's published values;
+//   3. rows workgroup b takes its block's values of z, forms w = fl32(2^e z)
+//      and runs the three classical Gram-Schmidt passes on its rows,
+//      publishing its per-block sums and reading every block's, added in
+//      the order of the multi-workgroup passes;
+//   4. every rows workgroup runs the finish on its own copy of the rotations
+//      (the same arithmetic, so the same values; workgroup 2 nb also writes H
+//      and B and publishes the step's verdict, which the solve blocks wait
+//      for), normalises its rows of v_{j+1} and publishes them.
 // Every sum is formed as in the separate launches of a step, so the results
 // are bit-identical to them.  Every wait is bounded and watches the abort
 // flag; a workgroup that gives up leaves the flag set and the others follow.
 constexpr int kCycleBlocks = kCycleMaxN / kTS;
-constexpr int kCycleDotGroup = 8;  // the upper blocks keep two 128-entry products in registers
+constexpr int kCycleRowPieces = 16;  // 16-byte pieces a lane of the product loads per round
 
-struct CycleShared {
-  TrsvShared t;
+// LDS of a rows workgroup: its block's rows of the basis, column after
+// column (kc fp64 columns of C_k, then the fp32 columns of V; at most
+// kCycleMaxM columns of 128 doubles in all, since kc + steps + 1 <= m + 1
+// and an fp32 column takes half the room), v_j, w, the passes' sums, the
+// rotations and the cycle state
+struct CycleRowsShared {
+  double basis[kCycleMaxM * kTS];
   float vsh[kCycleMaxN];
   double wsh[kTS];
   double hsum[2][kDotsMaxCols];
   double c1[kDotsMaxCols];
   double c2[kDotsMaxCols];
+  double scr[4 * kDotsMaxCols];
   double nrm[2];
   double cs[kCycleMaxM], sn[kCycleMaxM], g[kCycleMaxM + 1];
   CycleState st;
+};
+union CycleShared {
+  TrsvShared t;
+  CycleRowsShared r;
 };
 
 // one lane's value of entry idx of a tagged double array (two words per
@@ -1878,9 +1894,12 @@ __device__ __forceinline__ bool cycle_fetch_v(const uint64_t* vw, int n, uint32_
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = i0 + e * kTSThreads + (int)threadIdx.x;
-        x[e] = (i < n) ? __hip_atomic_load(vw + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                       : ((uint64_t)tag << 32);
-        all = all && (uint32_t)(x[e] >> 32) == tag;
+        x[e] = __hip_atomic_load(vw + (i < n ? i : 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + e * kTSThreads + (int)threadIdx.x;
+        all = all && (i >= n || (uint32_t)(x[e] >> 32) == tag);
       }
       if (all) break;
       __builtin_amdgcn_s_sleep(1);
@@ -1907,111 +1926,238 @@ __device__ __forceinline__ bool cycle_fetch_v(const uint64_t* vw, int n, uint32_
   return !__syncthreads_or(!ok);
 }
 
-// step 1 of a step: v_j to LDS, then this workgroup's rows of the product
-__device__ __forceinline__ bool cycle_product(const CycleArgs& a, CycleShared& sm, int j,
-                                              uint32_t tag) {
-  const int n = a.n;
-  if (j == 0) {
-    for (int i = threadIdx.x; i < n; i += kTSThreads) sm.vsh[i] = a.V[i];
-    __syncthreads();
-  } else if (!cycle_fetch_v(a.vw, n, tag, sm.vsh, a.abortp)) {
-    return false;
-  }
+// The product's rows, formed by the rows workgroups in row order, so that
+// the lower chain's blocks find their rows ahead of need.  A row's 256-column
+// pieces number P = ceil(n4 / 256) <= 8 (n4 = n rounded down to a multiple
+// of 4); a wave takes R = kCycleRowPieces / P rows at a time and issues
+// every load of them before any product, and its rows' indices in A_u sit
+// in one register (lane e: the e-th row it takes), so no permutation load
+// waits in the step.  Rows workgroup u's wave w takes, in its k-th round,
+// rows ((k nb + u) 8 + w) R .. + R - 1.
+__device__ __forceinline__ int cycle_product_pieces(int n) {
+  const int p = ((n & ~3) + 255) / 256;
+  return p < 1 ? 1 : p;
+}
+
+// lane e of the result: the row of A_u for the e-th row this wave takes
+// (-1 past n)
+__device__ __forceinline__ int cycle_product_rowlist(const CycleArgs& a, int nb, int u) {
+  const int R = kCycleRowPieces / cycle_product_pieces(a.n);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int k = lane / R, r = lane % R;
+  const int row = ((k * nb + u) * 8 + wave) * R + r;
+  if (row >= a.n) return -1;
+  return a.permA ? a.permA[row] : row;
+}
+
+// one step's rows of A_u[permA] v (v in LDS), each row's sum formed as
+// gemv_au_row forms it: the pieces in increasing order, their elements
+// alternately into two accumulators, the tail element into the first, then
+// the wave sum of the two
+template <int P>
+__device__ __forceinline__ void cycle_product_rows(const CycleArgs& a, const float* v, int rowlist,
+                                                   int nb, int u, uint32_t tag) {
+  constexpr int R = kCycleRowPieces / P;
+  const int n = a.n, n4 = n & ~3;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  for (int grp = (int)blockIdx.x; grp * 8 < n; grp += (int)gridDim.x) {
-    const int row = grp * 8 + wave;
-    if (row < n) {
-      const int prow = a.permA ? a.permA[row] : row;
-      const double t = gemv_au_row<float, 4>(a.Au + (int64_t)prow * a.lda, sm.vsh, n, lane);
-      if (lane == 0) put_tagged(a.xt, row, t, tag);
+  const int cc = n4 + lane;  // this lane's tail column (n - n4 < 4)
+  for (int k = 0;; ++k) {
+    const int base = ((k * nb + u) * 8 + wave) * R;
+    if (base >= n) break;
+    // every load is issued unconditionally (an index outside the row reads
+    // its first piece, a row past n reads row 0 of A_u; neither is used), so
+    // that no branch splits the loads and they all wait together
+    const float* rp[R];
+    bool ok[R];
+    float4 x[R][P];
+    float tl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pr = __builtin_amdgcn_readlane(rowlist, k * R + r);
+      ok[r] = pr >= 0;
+      rp[r] = a.Au + (int64_t)(pr >= 0 ? pr : 0) * a.lda;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int c = lane * 4 + 256 * i;
+        x[r][i] = *reinterpret_cast<const float4*>(rp[r] + (c < n4 ? c : 0));
+      }
+      tl[r] = rp[r][cc < n ? cc : 0];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!ok[r]) continue;
+      double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int c = lane * 4 + 256 * i;
+        if (c < n4) {
+          acc0 = fma((double)x[r][i].x, (double)v[c + 0], acc0);
+          acc1 = fma((double)x[r][i].y, (double)v[c + 1], acc1);
+          acc0 = fma((double)x[r][i].z, (double)v[c + 2], acc0);
+          acc1 = fma((double)x[r][i].w, (double)v[c + 3], acc1);
+        }
+      }
+      if (cc < n) acc0 = fma((double)tl[r], (double)v[cc], acc0);
+      const double t = wave_sum(acc0 + acc1);
+      if (lane == 0) put_tagged(a.xt, base + r, t, tag);
     }
   }
+}
+
+__device__ __forceinline__ void cycle_product(const CycleArgs& a, const float* v, int rowlist,
+                                              int nb, int u, uint32_t tag) {
+  switch (cycle_product_pieces(a.n)) {
+    case 1: cycle_product_rows<1>(a, v, rowlist, nb, u, tag); break;
+    case 2: cycle_product_rows<2>(a, v, rowlist, nb, u, tag); break;
+    case 3: cycle_product_rows<3>(a, v, rowlist, nb, u, tag); break;
+    case 4: cycle_product_rows<4>(a, v, rowlist, nb, u, tag); break;
+    case 5: cycle_product_rows<5>(a, v, rowlist, nb, u, tag); break;
+    case 6: cycle_product_rows<6>(a, v, rowlist, nb, u, tag); break;
+    case 7: cycle_product_rows<7>(a, v, rowlist, nb, u, tag); break;
+    default: cycle_product_rows<8>(a, v, rowlist, nb, u, tag); break;
+  }
+}
+
+// The per-block sums of one exchange (cnt values per block; block b's pair
+// sum of column c at entry b cnt + c of x): per 256-row chunk the two
+// blocks' sums added, then the chunks in order from zero, into out[c].  Two
+// threads per column, each polling its eight blocks' words at once (blocks
+// 0-7 and 8-15): the second hands its chunk sums over through scr (4 cnt
+// doubles), the first adds them after its own.  False (for the whole
+// workgroup) on abort.
+__device__ __forceinline__ bool cycle_reduce(const uint64_t* x, int nb, int cnt, uint32_t tag,
+                                             double* out, double* scr, int* abortp) {
+  bool ok = true;
+  const int t = threadIdx.x;
+  const int c = t >> 1, g = t & 1;
+  double ch[4] = {0.0, 0.0, 0.0, 0.0};
+  if (c < cnt) {
+    const int b0 = 8 * g;
+    double v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = 0.0;
+    long long spins = 0;
+    for (;;) {
+      bool all = true;
+      // all sixteen words loaded unconditionally (a block past nb reads
+      // block 0's, unused), so that the loads wait together
+      uint64_t lo[8], hi[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint64_t* p = x + 2 * ((b0 + e < nb ? b0 + e : 0) * cnt + c);
+        lo[e] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        hi[e] = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool in = b0 + e < nb;
+        all = all && (!in || ((uint32_t)(lo[e] >> 32) == tag && (uint32_t)(hi[e] >> 32) == tag));
+        v[e] = in ? __longlong_as_double((long long)((hi[e] << 32) | (lo[e] & 0xFFFFFFFFull)))
+                  : 0.0;
+      }
+      if (all) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (((++spins) & 1023) == 0) {
+        if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = false;
+          break;
+        }
+        if (spins > (1ll << 22)) {
+          __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = false;
+          break;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ch[q] = v[2 * q] + v[2 * q + 1];
+    if (g == 1) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) scr[4 * c + q] = ch[q];
+    }
+  }
+  if (__syncthreads_or(!ok)) return false;
+  if (c < cnt && g == 0) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (2 * q < nb) sum += ch[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (8 + 2 * q < nb) sum += scr[4 * c + q];
+    out[c] = sum;
+  }
+  __syncthreads();
   return true;
 }
 
-// the per-block sums of one exchange (cnt values per block; block b's pair
-// sum of column c at entry b cnt + c of x): per 256-row chunk the two
-// blocks' sums added, then the chunks in order from zero, for the columns
-// c = threadIdx.x, ... < cnt, into out; false (for the whole workgroup) on
-// abort
-__device__ __forceinline__ bool cycle_reduce(const uint64_t* x, int nb, int cnt, uint32_t tag,
-                                             double* out, int* abortp) {
+// the solve blocks: after each solve, the step's verdict (0: go on; 1: the
+// cycle ended); false when the cycle ended or on abort
+__device__ __forceinline__ bool cycle_verdict(const CycleArgs& a, uint32_t tag) {
   bool ok = true;
-  for (int c = threadIdx.x; c < cnt && ok; c += kTSThreads) {
-    double sum = 0.0;
-    for (int b = 0; b < nb && ok; b += 8) {
-      // eight blocks' values in flight before any is waited for
-      double v[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0.0;
-      long long spins = 0;
-      for (;;) {
-        bool all = true;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (b + e < nb) {
-            const uint64_t* p = x + 2 * ((b + e) * cnt + c);
-            const uint64_t lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t hi =
-                __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            all = all && (uint32_t)(lo >> 32) == tag && (uint32_t)(hi >> 32) == tag;
-            v[e] = __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
-          }
-        }
-        if (all) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (((++spins) & 1023) == 0) {
-          if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            ok = false;
-            break;
-          }
-          if (spins > (1ll << 22)) {
-            __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = false;
-            break;
-          }
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 8; e += 2)
-        if (b + e < nb) sum += v[e] + v[e + 1];
-    }
-    out[c] = sum;
-  }
-  return !__syncthreads_or(!ok);
+  double verdict = 0.0;
+  if (threadIdx.x == 0) ok = get_tagged_lane(a.ctrl, 0, tag, verdict, a.abortp);
+  return !__syncthreads_or(!ok || verdict != 0.0);
 }
 
-template <class F>
-__device__ __forceinline__ void cycle_lower(const CycleArgs& a, CycleShared& sm, int nb) {
+template <class F, bool kUpper>
+__device__ __forceinline__ void cycle_solve(const CycleArgs& a, TrsvShared& sm, int blk) {
   const int n = a.n;
-  TrsvBlock<F, false> tb;
-  tb.init(sm.t, static_cast<const typename F::T*>(a.S), a.ld, a.permS, n, (int)blockIdx.x - nb,
-          a.Linv);
+  TrsvBlock<F, kUpper> tb;
+  tb.init(sm, static_cast<const typename F::T*>(a.S), a.ld, a.permS, n, blk,
+          kUpper ? a.Uinv : a.Linv);
+  uint64_t* xw = kUpper ? a.xwU : a.xwL;
+  // right-hand sides: the product's rows (lower), the lower chain's values
+  // (upper), both published as tagged words
+  const uint64_t* rhs = kUpper ? a.xwL : a.xt;
   for (int j = 0; j < a.nsteps; ++j) {
     const uint32_t tag = a.epoch0 + (uint32_t)j;
-    if (!cycle_product(a, sm, j, tag)) return;
     double p = 0.0;
-    if (!tb.solve(sm.t, a.xwL, tag, a.abortp, nullptr, nullptr, a.xt, p)) return;
+    if (!tb.solve(sm, xw, tag, a.abortp, nullptr, nullptr, rhs, p)) return;
     const int rr = tb.r0 + tb.di;
-    if (tb.dq4 == 0) put_tagged(a.xwL, rr, rr < n ? p : 0.0, tag);
-    // the step's verdict: 0 go on, 1 converged (every upper block ends too)
-    bool ok = true;
-    double verdict = 0.0;
-    if (threadIdx.x == 0) ok = get_tagged_lane(a.ctrl, 0, tag, verdict, a.abortp);
-    if (__syncthreads_or(!ok || verdict != 0.0)) return;
+    if (tb.dq4 == 0) put_tagged(xw, rr, rr < n ? p : 0.0, tag);
+    if (!cycle_verdict(a, tag)) return;
   }
 }
 
-template <class F>
-__device__ __forceinline__ void cycle_upper(const CycleArgs& a, CycleShared& sm, int nb) {
+// the block's rows of the basis in LDS: column c < kc is C_k's (fp64), the
+// others V's (fp32); the products and sums are those of basis_products and
+// basis_row_fma (the same values, the same order)
+struct CycleBasis {
+  const double* c;
+  const float* v;
+  int kc;
+  __device__ __forceinline__ double at(int col, int lr) const {
+    return col < kc ? c[col * kTS + lr] : (double)v[(col - kc) * kTS + lr];
+  }
+};
+
+__device__ __forceinline__ double cycle_row_fma(const CycleBasis& X, int nv, int lr,
+                                                const double* __restrict__ coef) {
+  double s = 0.0;
+  for (int c = 0; c < X.kc; ++c) s = fma(X.c[c * kTS + lr], coef[c], s);
+  for (int c = 0; c < nv; ++c) s = fma((double)X.v[c * kTS + lr], coef[X.kc + c], s);
+  return s;
+}
+
+__device__ __forceinline__ void cycle_rows(const CycleArgs& a, CycleRowsShared& sm, int nb) {
   const int n = a.n;
   const int tid = threadIdx.x;
   const int wave = tid / kWave, lane = tid % kWave;
-  const bool lead = blockIdx.x == 0;
-  TrsvBlock<F, true> tb;
-  tb.init(sm.t, static_cast<const typename F::T*>(a.S), a.ld, a.permS, n,
-          nb - 1 - (int)blockIdx.x, a.Uinv);
-  // this workgroup's copy of the rotations and the cycle state
+  const int u = (int)blockIdx.x - 2 * nb;  // this workgroup's block of rows
+  const bool lead = u == 0;
+  const int kc = a.kc;
+  const int r0 = u * kTS;
+  // the block's rows of C_k and of v_1, the rotations, the cycle state
+  for (int i = tid; i < kc * kTS; i += kTSThreads) {
+    const int c = i / kTS, lr = i % kTS;
+    sm.basis[i] = (r0 + lr < n) ? a.C[(int64_t)c * a.ldc + r0 + lr] : 0.0;
+  }
+  float* vb = reinterpret_cast<float*>(sm.basis + (int64_t)kc * kTS);
+  for (int lr = tid; lr < kTS; lr += kTSThreads) vb[lr] = (r0 + lr < n) ? a.V[r0 + lr] : 0.0f;
   for (int i = tid; i <= a.m; i += kTSThreads) {
     if (i < a.m) {
       sm.cs[i] = a.cs[i];
@@ -2020,66 +2166,73 @@ __device__ __forceinline__ void cycle_upper(const CycleArgs& a, CycleShared& sm,
     sm.g[i] = a.g[i];
   }
   if (tid == 0) sm.st = *a.st;
-  __syncthreads();
-  const int ub = tb.blk, r0 = tb.r0;
+  const CycleBasis X{sm.basis, vb, kc};
+  const int rowlist = cycle_product_rowlist(a, nb, u);
   const int lrow = wave * kWave + lane;  // waves 0 and 1: lane = row
   const int grow = r0 + lrow;
   const bool vrow = wave < 2 && grow < n;
+  // the dot products: wave w takes the rows of half w % 2 and the columns
+  // c = 4 i + w / 2 (the sums of every column are the same whoever forms them)
+  const int dh = wave & 1, dq = wave >> 1;
+  const int dlr = dh * kWave + lane;
+  const bool dvalid = r0 + dlr < n;
+  __syncthreads();
   for (int j = 0; j < a.nsteps; ++j) {
     const uint32_t tag = a.epoch0 + (uint32_t)j;
-    if (!cycle_product(a, sm, j, tag)) return;
-    // the upper chain on the lower chain's published values
-    double p = 0.0;
-    if (!tb.solve(sm.t, a.xwU, tag, a.abortp, nullptr, nullptr, a.xwL, p)) return;
-    {
-      const int rr = r0 + tb.di;
-      const double v = rr < n ? p : 0.0;
-      if (tb.dq4 == 0) {
-        put_tagged(a.xwU, rr, v, tag);
-        sm.wsh[tb.di] = (rr < n) ? (double)(float)(v * a.scale) : 0.0;
-      }
+    // 1. v_j, then this workgroup's rows of the product
+    if (j == 0) {
+      for (int i = tid; i < n; i += kTSThreads) sm.vsh[i] = a.V[i];
+      __syncthreads();
+    } else if (!cycle_fetch_v(a.vw, n, tag, sm.vsh, a.abortp)) {
+      return;
     }
-    __syncthreads();
-    // w = fl32(2^e z) on this block's rows; three passes: dots, update and
-    // dots, update and norm
-    const int ncol = a.kc + j + 1;
-    const Basis X{a.C, a.kc, a.ldc, a.V, j + 1, a.ldv, 0};
-    double wv = (wave < 2) ? sm.wsh[lrow] : 0.0;
+    cycle_product(a, sm.vsh, rowlist, nb, u, tag);
+    // 2. this block's z from the upper chain; w = fl32(2^e z)
+    double wv = 0.0;
+    {
+      bool ok = true;
+      if (wave < 2) {
+        double z = 0.0;
+        ok = get_tagged_row(a.xwU, grow, tag, z, a.abortp);
+        wv = (grow < n) ? (double)(float)(z * a.scale) : 0.0;
+        sm.wsh[lrow] = wv;
+      }
+      if (__syncthreads_or(!ok)) return;
+    }
+    // 3. the passes: dots; update and dots; update and norm
+    const int ncol = kc + j + 1;
     for (int pass = 0; pass < 3; ++pass) {
       uint64_t* px = a.px + (int64_t)pass * kCycleBlocks * kDotsMaxCols * 2;
-      if (pass > 0 && vrow)
-        wv = round_u<float>(wv - basis_row_fma<float>(X, grow, pass == 1 ? sm.c1 : sm.c2, 0.0));
+      if (pass > 0 && vrow) wv = round_u<float>(wv - cycle_row_fma(X, j + 1, lrow, pass == 1 ? sm.c1 : sm.c2));
       if (pass < 2) {
-        if (wave < 2) {
-          for (int c0 = 0; c0 < ncol; c0 += kCycleDotGroup) {
-            double pr[kCycleDotGroup];
-            basis_products<float>(X, c0, ncol, grow, grow < n, wv, pr);
-#pragma unroll
-            for (int e = 0; e < kCycleDotGroup; ++e) pr[e] = wave_sum_to63(pr[e]);
-            if (lane == kWave - 1) {
-#pragma unroll
-              for (int e = 0; e < kCycleDotGroup; ++e)
-                if (c0 + e < ncol) sm.hsum[wave][c0 + e] = pr[e];
-            }
-          }
+        if (pass > 0) {
+          if (wave < 2) sm.wsh[lrow] = wv;
+          __syncthreads();
+        }
+        const double wd = sm.wsh[dlr];
+        for (int c = dq; c < ncol; c += 4) {
+          double pr = dvalid ? X.at(c, dlr) : 0.0;
+          pr *= wd;
+          pr = wave_sum_to63(pr);
+          if (lane == kWave - 1) sm.hsum[dh][c] = pr;
         }
         __syncthreads();
         for (int c = tid; c < ncol; c += kTSThreads)
-          put_tagged(px, ub * ncol + c, sm.hsum[0][c] + sm.hsum[1][c], tag);
-        if (!cycle_reduce(px, nb, ncol, tag, pass == 0 ? sm.c1 : sm.c2, a.abortp)) return;
+          put_tagged(px, u * ncol + c, sm.hsum[0][c] + sm.hsum[1][c], tag);
+        if (!cycle_reduce(px, nb, ncol, tag, pass == 0 ? sm.c1 : sm.c2, sm.scr, a.abortp)) return;
       } else {
         const double sq = wave_sum(wv * wv);
         if (wave < 2 && lane == 0) sm.nrm[wave] = sq;
         __syncthreads();
-        if (tid == 0) put_tagged(px, ub, sm.nrm[0] + sm.nrm[1], tag);
-        if (!cycle_reduce(px, nb, 1, tag, sm.nrm, a.abortp)) return;
+        if (tid == 0) put_tagged(px, u, sm.nrm[0] + sm.nrm[1], tag);
+        if (!cycle_reduce(px, nb, 1, tag, sm.nrm, sm.scr, a.abortp)) return;
       }
     }
-    // the finish on this workgroup's copy (block 0 also writes H and B)
+    // 4. the finish on this workgroup's copy (the lead also writes H and B)
     const double norm2 = sm.nrm[0];
     if (wave == 0) {
       OrthoArgs fa{};
-      fa.X = X;
+      fa.X.kc = kc;
       fa.step = j;
       fa.H = lead ? a.H : nullptr;
       fa.B = lead ? a.B : nullptr;
@@ -2092,21 +2245,24 @@ __device__ __forceinline__ void cycle_upper(const CycleArgs& a, CycleShared& sm,
       arnoldi_finish(fa, sm.c1, sm.c2, norm2);
     }
     __syncthreads();
-    // v_{j+1} = fl32(w / beta) on this block's rows, published for the next
-    // step; then the verdict
+    // v_{j+1} = fl32(w / beta) on this block's rows (LDS, V and the words
+    // of the next step); then the verdict
     const double beta = sqrt(norm2);
     const int done = sm.st.done;
-    if (vrow) {
-      const float vv = (beta > 0.0) ? (float)(wv / beta) : 0.0f;
-      a.V[(int64_t)(j + 1) * a.ldv + grow] = vv;
-      if (!done && j + 1 < a.nsteps)
-        __hip_atomic_store(a.vw + grow, ((uint64_t)(tag + 1) << 32) | __float_as_uint(vv),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (wave < 2) {
+      const float vv = (vrow && beta > 0.0) ? (float)(wv / beta) : 0.0f;
+      vb[(j + 1) * kTS + lrow] = vv;
+      if (vrow) {
+        a.V[(int64_t)(j + 1) * a.ldv + grow] = vv;
+        if (!done && j + 1 < a.nsteps)
+          __hip_atomic_store(a.vw + grow, ((uint64_t)(tag + 1) << 32) | __float_as_uint(vv),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     if (lead && tid == 0) put_tagged(a.ctrl, 0, done ? 1.0 : 0.0, tag);
     if (done) break;
   }
-  // the cycle's state for the host (block 0's copy; every copy is the same)
+  // the cycle's state for the host (the lead's copy; every copy is the same)
   if (lead) {
     __syncthreads();
     for (int i = tid; i <= a.m; i += kTSThreads) {
@@ -2174,11 +2330,14 @@ __global__ __launch_bounds__(kTSThreads) void k_cycle(CycleArgs a) {
   __shared__ CycleShared sm;
   __shared__ int s_verdict;
   const int nb = (a.n + kTS - 1) / kTS;
-  if (!cycle_arrive(a.arrive, 2u * (unsigned)nb, s_verdict)) return;
-  if ((int)blockIdx.x < nb)
-    cycle_upper<F>(a, sm, nb);
+  if (!cycle_arrive(a.arrive, 3u * (unsigned)nb, s_verdict)) return;
+  const int role = (int)blockIdx.x / nb, i = (int)blockIdx.x % nb;
+  if (role == 0)
+    cycle_solve<F, true>(a, sm.t, nb - 1 - i);
+  else if (role == 1)
+    cycle_solve<F, false>(a, sm.t, i);
   else
-    cycle_lower<F>(a, sm, nb);
+    cycle_rows(a, sm.r, nb);
 }
 
 }  // namespace
@@ -2433,7 +2592,7 @@ void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s) {
 
 void launch_cycle(const CycleArgs& a, int store, hipStream_t s) {
   const int nb = (a.n + kTS - 1) / kTS;
-  const dim3 grid(2 * nb), block(kTSThreads);
+  const dim3 grid(3 * nb), block(kTSThreads);
   if (store == kStoreF16)
     hipLaunchKernelGGL(k_cycle<Fp16>, grid, block, 0, s, a);
   else if (store == kStoreBF16)

@@ -1544,6 +1544,8 @@ bool cycle_eligible(const gmresir_ctx* h) {
 // the separate launches leave them.  *ran is false when the launch gave up
 // (its workgroups were not all resident together) and wrote nothing.
 int run_cycle(gmresir_ctx* h, int kc, int nsteps, bool* ran) {
+  *ran = false;
+  if (nsteps <= 0) return 0;
   gir::CycleArgs a{};
   a.S = h->S;
   a.ld = h->ld;
