@@ -307,6 +307,16 @@ __device__ __forceinline__ double wave_sum_to63(double v) {
   return v;
 }
 
+// A term of the passes' reductions (a basis entry times w, or w squared),
+// rounded on its own: with contraction off here the compiler cannot fuse the
+// product into the reduction's first addition, so every pass and every
+// variant that forms these sums gets the same bits however its code is
+// arranged.
+__device__ __forceinline__ double sum_term(double x, double w) {
+#pragma clang fp contract(off)
+  return x * w;
+}
+
 // rows per workgroup of the orthogonalisation passes (their 256-row chunks)
 constexpr int kRowsPerBlock = 256;
 
@@ -326,7 +336,9 @@ __device__ __forceinline__ double round_u(double x) {
 // s <- fma(X[row, c], coef[c], s) for c = 0 .. kc + nv - 1 in order: the C_k
 // columns, then the V columns.  The values of eight columns are loaded before
 // any of their products is taken, so a row waits for one memory round trip
-// per eight columns instead of one per column.
+// per eight columns instead of one per column; the loads are unconditional
+// (a column past the end reads the last one, unused), so that no branch
+// separates them.
 constexpr int kBatchCols = 8;
 template <typename VT>
 __device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
@@ -334,8 +346,10 @@ __device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
   for (int c = 0; c < X.kc; c += kBatchCols) {
     double v[kBatchCols];
 #pragma unroll
-    for (int e = 0; e < kBatchCols; ++e)
-      v[e] = (c + e < X.kc) ? X.c64[(int64_t)(c + e) * X.ldc + row] : 0.0;
+    for (int e = 0; e < kBatchCols; ++e) {
+      const int cc = (c + e < X.kc) ? c + e : X.kc - 1;
+      v[e] = X.c64[(int64_t)cc * X.ldc + row];
+    }
 #pragma unroll
     for (int e = 0; e < kBatchCols; ++e)
       if (c + e < X.kc) s = fma(v[e], coef[c + e], s);
@@ -345,8 +359,10 @@ __device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
   for (int c = 0; c < X.nv; c += kBatchCols) {
     double v[kBatchCols];
 #pragma unroll
-    for (int e = 0; e < kBatchCols; ++e)
-      v[e] = (c + e < X.nv) ? (double)V[(int64_t)(c + e) * X.ldv + row] : 0.0;
+    for (int e = 0; e < kBatchCols; ++e) {
+      const int cc = (c + e < X.nv) ? c + e : X.nv - 1;
+      v[e] = (double)V[(int64_t)cc * X.ldv + row];
+    }
 #pragma unroll
     for (int e = 0; e < kBatchCols; ++e)
       if (c + e < X.nv) s = fma(v[e], cv[c + e], s);
@@ -357,18 +373,40 @@ __device__ __forceinline__ double basis_row_fma(const Basis& X, int row,
 // products X[row, c] * w for the columns c0 .. c0 + G - 1 (zero for
 // columns >= ncol or an invalid row), all loads issued before any is used
 // (G = kDotGroup, or fewer where registers are short: each column's product
-// is the same whatever the group)
+// is the same whatever the group).  The loads are unconditional: an invalid
+// row reads row 0 and a column past ncol the last one, neither used; a group
+// that lies wholly in C_k or wholly in V loads one kind only.
 constexpr int kDotGroup = 16;
 template <typename VT, int G>
 __device__ __forceinline__ void basis_products(const Basis& X, int c0, int ncol, int row,
                                                bool valid, double w, double (&pr)[G]) {
+  const int r = valid ? row : 0;
+  const VT* V = static_cast<const VT*>(X.v);
+  if (c0 + G <= X.kc) {
 #pragma unroll
-  for (int e = 0; e < G; ++e) {
-    const int c = c0 + e;
-    pr[e] = (valid && c < ncol) ? basis_at<VT>(X, c, row) : 0.0;
+    for (int e = 0; e < G; ++e) pr[e] = X.c64[(int64_t)(c0 + e) * X.ldc + r];
+  } else if (c0 >= X.kc) {
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const int cc = (c0 + e < ncol ? c0 + e : ncol - 1) - X.kc;
+      pr[e] = (double)V[(int64_t)cc * X.ldv + r];
+    }
+  } else if (X.nv == 0) {
+#pragma unroll
+    for (int e = 0; e < G; ++e)
+      pr[e] = X.c64[(int64_t)(c0 + e < X.kc ? c0 + e : X.kc - 1) * X.ldc + r];
+  } else {
+    // the group straddles C_k and V: both loaded for every column, one kept
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const int c = c0 + e < ncol ? c0 + e : ncol - 1;
+      const double xc = X.c64[(int64_t)(c < X.kc ? c : X.kc - 1) * X.ldc + r];
+      const double xv = (double)V[(int64_t)(c >= X.kc ? c - X.kc : 0) * X.ldv + r];
+      pr[e] = c < X.kc ? xc : xv;
+    }
   }
 #pragma unroll
-  for (int e = 0; e < G; ++e) pr[e] *= w;
+  for (int e = 0; e < G; ++e) pr[e] = (valid && c0 + e < ncol) ? sum_term(pr[e], w) : 0.0;
 }
 
 // s = ((0 + p[0]) + p[stride]) + ... over count values in order, the values
@@ -380,7 +418,7 @@ __device__ __forceinline__ double ordered_sum(const double* __restrict__ p, int 
   for (int b = 0; b < count; b += 8) {
     double v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = (b + e < count) ? p[(int64_t)(b + e) * stride] : 0.0;
+    for (int e = 0; e < 8; ++e) v[e] = p[(int64_t)(b + e < count ? b + e : count - 1) * stride];
 #pragma unroll
     for (int e = 0; e < 8; ++e)
       if (b + e < count) s += v[e];
@@ -1261,7 +1299,7 @@ __global__ __launch_bounds__(256) void k_ortho(OrthoArgs a, int mode) {
       part[c] = (colsum[0][c] + colsum[1][c]) + (colsum[2][c] + colsum[3][c]);
   }
   if (mode & kOrthoNorm) {
-    double sq = wave_sum(wv * wv);
+    double sq = wave_sum(sum_term(wv, wv));
     if (lane == 0) red[wave][0] = sq;
     __syncthreads();
     if (tid == 0) part[ncol] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
@@ -1399,7 +1437,7 @@ __global__ __launch_bounds__(kOrthoSmallThreads) void k_ortho_small(OrthoArgs a,
 #pragma unroll
   for (int it = 0; it < kOrthoSmallIters; ++it) {
     if (4 * it >= nbk) break;
-    const double sq = wave_sum(wv[it] * wv[it]);
+    const double sq = wave_sum(sum_term(wv[it], wv[it]));
     if (lane == 0) red[wave] = sq;
     __syncthreads();
     if (tid < 4 && 4 * it + tid < nbk)
@@ -2211,9 +2249,7 @@ __device__ __forceinline__ void cycle_rows(const CycleArgs& a, CycleRowsShared& 
         }
         const double wd = sm.wsh[dlr];
         for (int c = dq; c < ncol; c += 4) {
-          double pr = dvalid ? X.at(c, dlr) : 0.0;
-          pr *= wd;
-          pr = wave_sum_to63(pr);
+          const double pr = wave_sum_to63(dvalid ? sum_term(X.at(c, dlr), wd) : 0.0);
           if (lane == kWave - 1) sm.hsum[dh][c] = pr;
         }
         __syncthreads();
@@ -2221,7 +2257,7 @@ __device__ __forceinline__ void cycle_rows(const CycleArgs& a, CycleRowsShared& 
           put_tagged(px, u * ncol + c, sm.hsum[0][c] + sm.hsum[1][c], tag);
         if (!cycle_reduce(px, nb, ncol, tag, pass == 0 ? sm.c1 : sm.c2, sm.scr, a.abortp)) return;
       } else {
-        const double sq = wave_sum(wv * wv);
+        const double sq = wave_sum(sum_term(wv, wv));
         if (wave < 2 && lane == 0) sm.nrm[wave] = sq;
         __syncthreads();
         if (tid == 0) put_tagged(px, u, sm.nrm[0] + sm.nrm[1], tag);
