@@ -191,7 +191,7 @@ void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s);
 // separate launches.  Needs n <= kCycleMaxN, m <= kCycleMaxM and all its
 // workgroups resident at once (one per compute unit: at most 48 of them):
 // each first arrives on the
-// zeroed word *arrive; when not all have arrived within kCycleArriveUs, the
+// zeroed word *arrive; when not all have arrived within arrive_us, the
 // launch gives up before touching any result (kCycleGaveUp set in *arrive)
 // and the caller runs the steps as separate launches instead.
 constexpr int kCycleMaxN = 2048;
@@ -237,6 +237,7 @@ struct CycleArgs {
   uint64_t* px;
   uint64_t* ctrl;
   unsigned* arrive;
+  int arrive_us;  // the arrival wait's bound (kCycleArriveUs unless a test sets it)
   uint32_t epoch0;
   int* abortp;
 };

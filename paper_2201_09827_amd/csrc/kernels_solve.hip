@@ -2319,16 +2319,21 @@ __device__ __forceinline__ void cycle_rows(const CycleArgs& a, CycleRowsShared& 
 // The launch goes on only if all its total workgroups are resident at once
 // (they wait for one another at every step).  Each arrives on the state word
 // (the count in the low bits) unless the launch has already given up; one
-// that has waited kCycleArriveUs without seeing all arrive gives up for the
+// that has waited bound_us without seeing all arrive gives up for the
 // launch, unless the last one arrived meanwhile (both are decided by
 // compare-and-swap on the one word, so every workgroup takes the same
-// verdict).  Returns the verdict (workgroup-uniform).
-__device__ __forceinline__ bool cycle_arrive(unsigned* state, unsigned total, int& verdict) {
+// verdict; a bound of zero gives up at once).  Returns the verdict
+// (workgroup-uniform).
+__device__ __forceinline__ bool cycle_arrive(unsigned* state, unsigned total, int bound_us,
+                                             int& verdict) {
   if (threadIdx.x == 0) {
     int go = 0;
     unsigned old = __hip_atomic_load(state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool in = false;
-    while (!(old & kCycleGaveUp)) {
+    // a bound of zero gives up at once (the fall-back path, forced)
+    if (bound_us <= 0)
+      __hip_atomic_fetch_or(state, kCycleGaveUp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (bound_us > 0 && !(old & kCycleGaveUp)) {
       if (__hip_atomic_compare_exchange_strong(state, &old, old + 1, __ATOMIC_RELAXED,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         old += 1;
@@ -2344,7 +2349,7 @@ __device__ __forceinline__ bool cycle_arrive(unsigned* state, unsigned total, in
           break;
         }
         if (old & kCycleGaveUp) break;
-        if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)kCycleArriveUs * 100) {
+        if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)bound_us * 100) {
           if (__hip_atomic_compare_exchange_strong(state, &old, old | kCycleGaveUp,
                                                    __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT))
@@ -2366,7 +2371,7 @@ __global__ __launch_bounds__(kTSThreads) void k_cycle(CycleArgs a) {
   __shared__ CycleShared sm;
   __shared__ int s_verdict;
   const int nb = (a.n + kTS - 1) / kTS;
-  if (!cycle_arrive(a.arrive, 3u * (unsigned)nb, s_verdict)) return;
+  if (!cycle_arrive(a.arrive, 3u * (unsigned)nb, a.arrive_us, s_verdict)) return;
   const int role = (int)blockIdx.x / nb, i = (int)blockIdx.x % nb;
   if (role == 0)
     cycle_solve<F, true>(a, sm.t, nb - 1 - i);

@@ -373,6 +373,9 @@ struct gmresir_ctx {
   bool persistent = true;
   uint64_t *cvw = nullptr, *cpx = nullptr, *cctrl = nullptr;  // its exchange words
   int64_t cycle_fallbacks = 0;  // persistent launches that gave up (device shared)
+  // the persistent launch's arrival bound (GMRESIR_CYCLE_ARRIVE_US at handle
+  // creation: a test hook; 0 makes every launch give up and fall back)
+  int cycle_arrive_us = gir::kCycleArriveUs;
   Refresh pend;     // deferred refresh of the last cycle (V, C, U untouched meanwhile)
   // the adjoint solve's own recycle space (swapped with C, U, kc_keep while
   // it runs) and the partial sums of the products with A^T
@@ -984,6 +987,8 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
     h->fuse_dots = !(fd && std::strcmp(fd, "0") == 0);
     const char* pe = std::getenv("GMRESIR_PERSISTENT");
     h->persistent = !(pe && std::strcmp(pe, "0") == 0);
+    const char* au = std::getenv("GMRESIR_CYCLE_ARRIVE_US");
+    if (au && *au) h->cycle_arrive_us = std::max(0, std::min(1000000, std::atoi(au)));
     const char* os = std::getenv("GMRESIR_ORTHO_SMALL");
     if (os && (std::strcmp(os, "0") == 0 || std::strcmp(os, "1") == 0))
       h->ortho_small = os[0] - '0';
@@ -1541,11 +1546,10 @@ bool cycle_eligible(const gmresir_ctx* h) {
 
 // up to nsteps Arnoldi steps of the cycle with kc recycled columns, one
 // launch; the results (V, H, B, the rotations and the cycle state) are where
-// the separate launches leave them.  *ran is false when the launch gave up
-// (its workgroups were not all resident together) and wrote nothing.
-int run_cycle(gmresir_ctx* h, int kc, int nsteps, bool* ran) {
-  *ran = false;
-  if (nsteps <= 0) return 0;
+// the separate launches leave them, unless the launch gave up (its
+// workgroups were not all resident together: kCycleGaveUp in the word at
+// cctrl + 2), in which case it wrote nothing.
+int run_cycle(gmresir_ctx* h, int kc, int nsteps) {
   gir::CycleArgs a{};
   a.S = h->S;
   a.ld = h->ld;
@@ -1579,23 +1583,13 @@ int run_cycle(gmresir_ctx* h, int kc, int nsteps, bool* ran) {
   a.px = h->cpx;
   a.ctrl = h->cctrl;
   a.arrive = reinterpret_cast<unsigned*>(h->cctrl + 2);
+  a.arrive_us = h->cycle_arrive_us;
   a.epoch0 = (uint32_t)reserve_epochs(h, nsteps);
   a.abortp = &h->st->abort;
   gir::launch_fill_i32(reinterpret_cast<int*>(a.arrive), 0, 1, h->stream);
   // the work is set once the number of steps taken is known
-  const size_t r0 = h->trec.size();
-  GIR_TRY(timed(h, kKcCycle, 0.0, h->stream, nullptr, 0,
-                [&] { gir::launch_cycle(a, h->store, h->stream); }));
-  unsigned word = 0;
-  GIR_TRY(download_many(h, {{&word, a.arrive, sizeof(word)}}));
-  *ran = !(word & gir::kCycleGaveUp);
-  if (!*ran) {
-    // not all workgroups were resident together (the device is shared):
-    // nothing was written, the caller runs the separate launches
-    h->trec.resize(r0);
-    ++h->cycle_fallbacks;
-  }
-  return 0;
+  return timed(h, kKcCycle, 0.0, h->stream, nullptr, 0,
+               [&] { gir::launch_cycle(a, h->store, h->stream); });
 }
 
 // GCRO-DR(m, k) for A-tilde d = z (z in h->zu); result in h->du.
@@ -1692,34 +1686,77 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       return (double)n * (double)n * (double)(a_bytes(h) + store_bytes(h->store)) +
              (8.0 * kc + (double)h->ue * (j + 1)) * n + 4.0 * h->ue * n;
     };
-    bool one_launch = false;
-    if (cycle_eligible(h)) GIR_TRY(run_cycle(h, kc, nsteps, &one_launch));
-    for (int j = 0; !one_launch && j < nsteps; ++j) {
-      // one Arnoldi step, timed as a whole under its own class
-      const double step_bytes = step_work(j);
-      GIR_TRY(timed(h, kKcStep, step_bytes, s, h->st, j, [&]() -> int {
-      const gir::Basis Xj = basis(h, h->C, kc, ld, h->V, j + 1, ld);
-      // classical Gram-Schmidt in its multi-workgroup form: the first pass
-      // (h1 = X^T w) runs inside the upper solve that produces w
-      const bool dots1 = fuse_first_dots(h) && kc + j + 1 <= gir::kDotsMaxCols;
-      const gir::TrsvDots td{Xj, h->partial, h->counter, h->h1};
-      GIR_TRY(atilde(h, vcol(h, j), nullptr, nullptr, h->wu, h->st, j, dots1 ? &td : nullptr));
-      gir::OrthoArgs a{};
-      a.X = Xj;
-      a.n = n;
-      a.w_in = h->wu;
-      a.w_out = h->wu;
-      a.partial = h->partial;
-      a.counter = h->counter;
-      a.gate = h->st;
-      a.step = j;
-      a.dots_out = h->h1;
-      // basis read once per pass; the update pass also reads and writes w
-      const double xb = (8.0 * kc + (double)h->ue * (j + 1)) * n;
-      if (h->o.ortho != 1 && h->ortho_small == 1) {
-        // the three passes, the finish and the normalisation in one launch
-        // of one workgroup (the same sums; the basis read four times)
+    // the cycle's steps as separate launches, the host polling each step's
+    // state (it stops the loop once the cycle has converged)
+    auto run_steps = [&]() -> int {
+      for (int j = 0; j < nsteps; ++j) {
+        // one Arnoldi step, timed as a whole under its own class
+        const double step_bytes = step_work(j);
+        GIR_TRY(timed(h, kKcStep, step_bytes, s, h->st, j, [&]() -> int {
+        const gir::Basis Xj = basis(h, h->C, kc, ld, h->V, j + 1, ld);
+        // classical Gram-Schmidt in its multi-workgroup form: the first pass
+        // (h1 = X^T w) runs inside the upper solve that produces w
+        const bool dots1 = fuse_first_dots(h) && kc + j + 1 <= gir::kDotsMaxCols;
+        const gir::TrsvDots td{Xj, h->partial, h->counter, h->h1};
+        GIR_TRY(atilde(h, vcol(h, j), nullptr, nullptr, h->wu, h->st, j, dots1 ? &td : nullptr));
+        gir::OrthoArgs a{};
+        a.X = Xj;
+        a.n = n;
+        a.w_in = h->wu;
+        a.w_out = h->wu;
+        a.partial = h->partial;
+        a.counter = h->counter;
+        a.gate = h->st;
+        a.step = j;
+        a.dots_out = h->h1;
+        // basis read once per pass; the update pass also reads and writes w
+        const double xb = (8.0 * kc + (double)h->ue * (j + 1)) * n;
+        if (h->o.ortho != 1 && h->ortho_small == 1) {
+          // the three passes, the finish and the normalisation in one launch
+          // of one workgroup (the same sums; the basis read four times)
+          a.coef = h->h2;
+          a.norm_out = h->nrm;
+          a.H = h->Hd;
+          a.B = h->Bd;
+          a.ldh = m + 1;
+          a.ldb = std::max(k, 1);
+          a.cs = h->cs;
+          a.sn = h->sn;
+          a.g = h->g;
+          a.st = h->st;
+          a.st_out = &h->st_host[j];
+          GIR_TRY(timed(h, kKcOrtho, 4.0 * xb + 4.0 * h->ue * n, s, h->st, j,
+                        [&] { gir::launch_ortho_small(a, vcol(h, j + 1), s); }));
+          return 0;
+        }
+        if (h->o.ortho == 1) {
+          // modified Gram-Schmidt: one basis column at a time ([C_k V_j] in
+          // order), its inner product with the current w, then its update;
+          // the coefficients gather in h1 and the finish pass below applies
+          // none (h2 is zero) but forms the norm and the Givens update
+          for (int i = 0; i < kc + j + 1; ++i) {
+            gir::OrthoArgs ai = a;
+            ai.X = i < kc ? basis(h, h->C + (size_t)i * ld, 1, ld, nullptr, 0, ld)
+                          : basis(h, nullptr, 0, ld, vcol(h, i - kc), 1, ld);
+            ai.dots_out = h->h1 + i;
+            ai.coef = h->h1 + i;
+            const double cb = (double)(i < kc ? 8 : h->ue) * n;
+            GIR_TRY(timed(h, kKcOrtho, cb + (double)h->ue * n, s, h->st, j,
+                          [&] { gir::launch_ortho(ai, gir::kOrthoDots, s); }));
+            GIR_TRY(timed(h, kKcOrtho, cb + 2.0 * h->ue * n, s, h->st, j,
+                          [&] { gir::launch_ortho(ai, gir::kOrthoUpdate, s); }));
+          }
+        } else {
+          if (!dots1)
+            GIR_TRY(timed(h, kKcOrtho, xb + (double)h->ue * n, s, h->st, j,
+                          [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
+          a.coef = h->h1;
+          a.dots_out = h->h2;
+          GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 2.0 * h->ue * n, s, h->st, j,
+                        [&] { gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s); }));
+        }
         a.coef = h->h2;
+        a.h_prev = h->h1;
         a.norm_out = h->nrm;
         a.H = h->Hd;
         a.B = h->Bd;
@@ -1730,71 +1767,52 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
         a.g = h->g;
         a.st = h->st;
         a.st_out = &h->st_host[j];
-        GIR_TRY(timed(h, kKcOrtho, 4.0 * xb + 4.0 * h->ue * n, s, h->st, j,
-                      [&] { gir::launch_ortho_small(a, vcol(h, j + 1), s); }));
+        a.vout = vcol(h, j + 1);  // the normalisation in the finishing workgroup
+        GIR_TRY(timed(h, kKcOrtho, xb + 4.0 * h->ue * n, s, h->st, j, [&] {
+          gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
+        }));
         return 0;
-      }
-      if (h->o.ortho == 1) {
-        // modified Gram-Schmidt: one basis column at a time ([C_k V_j] in
-        // order), its inner product with the current w, then its update;
-        // the coefficients gather in h1 and the finish pass below applies
-        // none (h2 is zero) but forms the norm and the Givens update
-        for (int i = 0; i < kc + j + 1; ++i) {
-          gir::OrthoArgs ai = a;
-          ai.X = i < kc ? basis(h, h->C + (size_t)i * ld, 1, ld, nullptr, 0, ld)
-                        : basis(h, nullptr, 0, ld, vcol(h, i - kc), 1, ld);
-          ai.dots_out = h->h1 + i;
-          ai.coef = h->h1 + i;
-          const double cb = (double)(i < kc ? 8 : h->ue) * n;
-          GIR_TRY(timed(h, kKcOrtho, cb + (double)h->ue * n, s, h->st, j,
-                        [&] { gir::launch_ortho(ai, gir::kOrthoDots, s); }));
-          GIR_TRY(timed(h, kKcOrtho, cb + 2.0 * h->ue * n, s, h->st, j,
-                        [&] { gir::launch_ortho(ai, gir::kOrthoUpdate, s); }));
+        }));
+        // the step's finish wrote its cycle state to st_host[j]; a step skipped
+        // on the device (converged earlier) writes nothing, and its slot is
+        // never read: the loop stops at the converged step's own slot
+        GIR_HIP(hipEventRecord(h->ev[j % kEventRing], s));
+        queued = j + 1;
+        if (j >= kLaunchAhead) {
+          GIR_HIP(hipEventSynchronize(h->ev[(j - kLaunchAhead) % kEventRing]));
+          const gir::CycleState& sj = h->st_host[j - kLaunchAhead];
+          if (sj.done || sj.abort) break;
         }
-      } else {
-        if (!dots1)
-          GIR_TRY(timed(h, kKcOrtho, xb + (double)h->ue * n, s, h->st, j,
-                        [&] { gir::launch_ortho(a, gir::kOrthoDots, s); }));
-        a.coef = h->h1;
-        a.dots_out = h->h2;
-        GIR_TRY(timed(h, kKcOrtho, 2.0 * xb + 2.0 * h->ue * n, s, h->st, j,
-                      [&] { gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoDots, s); }));
       }
-      a.coef = h->h2;
-      a.h_prev = h->h1;
-      a.norm_out = h->nrm;
-      a.H = h->Hd;
-      a.B = h->Bd;
-      a.ldh = m + 1;
-      a.ldb = std::max(k, 1);
-      a.cs = h->cs;
-      a.sn = h->sn;
-      a.g = h->g;
-      a.st = h->st;
-      a.st_out = &h->st_host[j];
-      a.vout = vcol(h, j + 1);  // the normalisation in the finishing workgroup
-      GIR_TRY(timed(h, kKcOrtho, xb + 4.0 * h->ue * n, s, h->st, j, [&] {
-        gir::launch_ortho(a, gir::kOrthoUpdate | gir::kOrthoNorm | gir::kOrthoFinish, s);
-      }));
       return 0;
-      }));
-      // the step's finish wrote its cycle state to st_host[j]; a step skipped
-      // on the device (converged earlier) writes nothing, and its slot is
-      // never read: the loop stops at the converged step's own slot
-      GIR_HIP(hipEventRecord(h->ev[j % kEventRing], s));
-      queued = j + 1;
-      if (j >= kLaunchAhead) {
-        GIR_HIP(hipEventSynchronize(h->ev[(j - kLaunchAhead) % kEventRing]));
-        const gir::CycleState& sj = h->st_host[j - kLaunchAhead];
-        if (sj.done || sj.abort) break;
-      }
-    }
+    };
+    // one persistent launch for the steps where it applies; its residency
+    // word comes back with the cycle's state, and a launch that gave up (not
+    // all its workgroups resident together: the device is shared) wrote
+    // nothing, so the steps then run as separate launches
+    bool one_launch = cycle_eligible(h);
+    if (one_launch)
+      GIR_TRY(run_cycle(h, kc, nsteps));
+    else
+      GIR_TRY(run_steps());
     (void)queued;
     gir::CycleState fin{};
-    GIR_TRY(download_many(
-        h, {{&fin, h->st, sizeof(fin)},
-            {Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m},
-            {Bh.data(), h->Bd, kc > 0 ? sizeof(double) * (size_t)std::max(k, 1) * m : 0}}));
+    unsigned gate = 0;
+    auto fetch_state = [&]() -> int {
+      return download_many(
+          h, {{&fin, h->st, sizeof(fin)},
+              {Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m},
+              {Bh.data(), h->Bd, kc > 0 ? sizeof(double) * (size_t)std::max(k, 1) * m : 0},
+              {&gate, h->cctrl + 2, one_launch ? sizeof(gate) : 0}});
+    };
+    GIR_TRY(fetch_state());
+    if (one_launch && (gate & gir::kCycleGaveUp)) {
+      h->trec.resize(trec0);
+      ++h->cycle_fallbacks;
+      one_launch = false;
+      GIR_TRY(run_steps());
+      GIR_TRY(fetch_state());
+    }
     if (fin.abort) {
       set_error("triangular solve: a device-side wait exceeded its bound");
       return GMRESIR_EINTERNAL;

@@ -99,3 +99,25 @@ def test_persistent_cycle_outside_its_limits(lib, monkeypatch, n, u, extra):
     log(f"[cycle-limits] n={n} u={u} {extra}")
     (r,), c = _solve(lib, monkeypatch, _dev(p.a), [_dev(p.b)], True, **kw)
     assert c == 0 and r[1]["status"] == 0
+
+
+def test_persistent_cycle_that_gives_up_falls_back(lib, monkeypatch):
+    """A persistent launch whose workgroups are not all resident together
+    gives up before writing anything and the cycle runs as separate
+    launches.  Forced from the host with a zero arrival bound
+    (GMRESIR_CYCLE_ARRIVE_US=0: the first workgroup to arrive gives up, and
+    every kernel still ends normally): the results must equal those of the
+    separate launches, and no persistent launch is counted."""
+    p = randsvd_problem(700, 1e4, 37)
+    a, b = _dev(p.a), _dev(p.b)
+    kw = dict(m=20, k=5, maxit=100)
+    log("[cycle-fallback] n=700 arrival bound 0")
+    monkeypatch.setenv("GMRESIR_CYCLE_ARRIVE_US", "0")
+    (r1,), c1 = _solve(lib, monkeypatch, a, [b], True, **kw)
+    monkeypatch.delenv("GMRESIR_CYCLE_ARRIVE_US")
+    (r0,), c0 = _solve(lib, monkeypatch, a, [b], False, **kw)
+    (x1, i1), (x0, i0) = r1, r0
+    log(f"[cycle-fallback] its {i1['its']} / {i0['its']} launches {c1} / {c0}")
+    assert c1 == 0 and c0 == 0
+    assert i1["status"] == i0["status"] and i1["its"] == i0["its"]
+    assert i1["berr"] == i0["berr"] and torch.equal(x1, x0)
