@@ -212,6 +212,9 @@ def batched_bench(g, count: int, workers: int, oracle: bool):
                                                  + 16.0) * nn)
     rec = {"systems": count, "rhs": nrhs, "workers": workers, "seconds": dt,
            "arnoldi_steps": int(steps),
+           "persistent_cycles": int(sum(i.get("cycles_persistent", 0) for o in out for i in o[1])),
+           "persistent_fallbacks": int(sum(i.get("cycles_fallback", 0)
+                                           for o in out for i in o[1])),
            "roofline": {"bound": "hbm", "achieved": step_bytes / dt / 1e9, "peak": 8000.0,
                         "unit": "GB/s", "frac": step_bytes / dt / 1e9 / 8000.0,
                         "what": "Arnoldi-step HBM model summed over every step of the batch, "

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define GMRESIR_ABI_VERSION 2
+#define GMRESIR_ABI_VERSION 3
 
 typedef enum {
   GMRESIR_OK = 0,
@@ -145,6 +145,13 @@ typedef struct {
   double t_arnoldi_s;                  /* Arnoldi cycles, least squares,
                                           cycle updates and refreshes, x
                                           update                             */
+  int32_t cycles_persistent;           /* GMRES cycles whose Arnoldi steps ran
+                                          in one persistent launch (u = FP32,
+                                          CGS2, n <= 2048)                   */
+  int32_t cycles_fallback;             /* persistent launches that gave up
+                                          (not all their workgroups resident
+                                          together: the device was shared)
+                                          and ran as separate launches       */
 } gmresir_info;
 
 typedef struct gmresir_ctx gmresir_ctx;

@@ -114,6 +114,8 @@ class Info(ctypes.Structure):
         ("t_precond_s", ctypes.c_double),
         ("t_recycle_s", ctypes.c_double),
         ("t_arnoldi_s", ctypes.c_double),
+        ("cycles_persistent", ctypes.c_int32),
+        ("cycles_fallback", ctypes.c_int32),
     ]
 
 
@@ -255,6 +257,8 @@ def _info_dict(info: Info) -> dict:
         "t_precond_s": float(info.t_precond_s),
         "t_recycle_s": float(info.t_recycle_s),
         "t_arnoldi_s": float(info.t_arnoldi_s),
+        "cycles_persistent": int(info.cycles_persistent),
+        "cycles_fallback": int(info.cycles_fallback),
     }
 
 

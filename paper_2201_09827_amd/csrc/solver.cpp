@@ -372,6 +372,7 @@ struct gmresir_ctx {
   // handle creation keeps the separate launches
   bool persistent = true;
   uint64_t *cvw = nullptr, *cpx = nullptr, *cctrl = nullptr;  // its exchange words
+  int64_t cycles_run = 0;        // cycles run as one persistent launch
   int64_t cycle_fallbacks = 0;  // persistent launches that gave up (device shared)
   // the persistent launch's arrival bound (GMRESIR_CYCLE_ARRIVE_US at handle
   // creation: a test hook; 0 makes every launch give up and fall back)
@@ -1812,6 +1813,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       one_launch = false;
       GIR_TRY(run_steps());
       GIR_TRY(fetch_state());
+    } else if (one_launch) {
+      ++h->cycles_run;
     }
     if (fin.abort) {
       set_error("triangular solve: a device-side wait exceeded its bound");
@@ -1916,6 +1919,7 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   const double t0 = now_s();
   gmresir_info inf{};
   inf.singular_col = h->singular_col;
+  const int64_t cyc0 = h->cycles_run, fb0 = h->cycle_fallbacks;
   if (h->status == GMRESIR_ESINGULAR || h->status == GMRESIR_ERANGE) {
     inf.status = h->status;
     if (info) *info = inf;
@@ -2000,6 +2004,8 @@ int solve_one(gmresir_ctx* h, const double* bcol, double* xcol, gmresir_info* in
   GIR_HIP(hipStreamSynchronize(s));
   inf.t_factor_s = h->t_factor;
   inf.t_solve_s = now_s() - t0;
+  inf.cycles_persistent = (int32_t)(h->cycles_run - cyc0);
+  inf.cycles_fallback = (int32_t)(h->cycle_fallbacks - fb0);
   {
     double tp[kPhCount];
     GIR_TRY(phase_times(h, tp));

@@ -48,10 +48,11 @@ int main(void) {
   printf("kstat %zu %zu %zu %zu %zu\n", sizeof(gmresir_kernel_stat),
          offsetof(gmresir_kernel_stat, launches), offsetof(gmresir_kernel_stat, bound),
          offsetof(gmresir_kernel_stat, total_ms), offsetof(gmresir_kernel_stat, work));
-  printf("info %zu %zu %zu %zu %zu %zu %zu\n", sizeof(gmresir_info), offsetof(gmresir_info, its),
-         offsetof(gmresir_info, berr), offsetof(gmresir_info, singular_col),
-         offsetof(gmresir_info, t_solve_s), offsetof(gmresir_info, berr_cw),
-         offsetof(gmresir_info, t_arnoldi_s));
+  printf("info %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(gmresir_info),
+         offsetof(gmresir_info, its), offsetof(gmresir_info, berr),
+         offsetof(gmresir_info, singular_col), offsetof(gmresir_info, t_solve_s),
+         offsetof(gmresir_info, berr_cw), offsetof(gmresir_info, t_arnoldi_s),
+         offsetof(gmresir_info, cycles_persistent), offsetof(gmresir_info, cycles_fallback));
   return 0;
 }
 """
@@ -78,7 +79,8 @@ def test_struct_layout_matches_header():
     i = [int(v) for v in lines["info"].split()]
     assert i == [ctypes.sizeof(g.Info), g.Info.its.offset, g.Info.berr.offset,
                  g.Info.singular_col.offset, g.Info.t_solve_s.offset, g.Info.berr_cw.offset,
-                 g.Info.t_arnoldi_s.offset]
+                 g.Info.t_arnoldi_s.offset, g.Info.cycles_persistent.offset,
+                 g.Info.cycles_fallback.offset]
 
 
 def test_host_only_entry_points():
@@ -92,7 +94,7 @@ def test_host_only_entry_points():
     n = ctypes.c_int64(-1)
     abi = ctypes.c_int32(0)
     assert lib.gmresir_query(None, ctypes.byref(n), ctypes.byref(abi)) == -1
-    assert abi.value == 2
+    assert abi.value == 3
     lib.gmresir_free(None)          # NULL-safe
 
 

@@ -65,6 +65,8 @@ def test_persistent_cycle_is_bit_identical(lib, monkeypatch, n, k, m, kappa, uf)
     (x1, i1), (x0, i0) = r1, r0
     log(f"[cycle] its persistent {i1['its']} separate {i0['its']} launches {c1} / {c0}")
     assert c1 > 0 and c0 == 0
+    assert i1["cycles_persistent"] > 0 and i1["cycles_fallback"] == 0
+    assert i0["cycles_persistent"] == 0 and i0["cycles_fallback"] == 0
     assert i1["status"] == i0["status"]
     assert i1["its"] == i0["its"] and i1["berr"] == i0["berr"]
     assert i1["recycle_dim"] == i0["recycle_dim"]
@@ -119,5 +121,6 @@ def test_persistent_cycle_that_gives_up_falls_back(lib, monkeypatch):
     (x1, i1), (x0, i0) = r1, r0
     log(f"[cycle-fallback] its {i1['its']} / {i0['its']} launches {c1} / {c0}")
     assert c1 == 0 and c0 == 0
+    assert i1["cycles_fallback"] > 0 and i1["cycles_persistent"] == 0
     assert i1["status"] == i0["status"] and i1["its"] == i0["its"]
     assert i1["berr"] == i0["berr"] and torch.equal(x1, x0)
