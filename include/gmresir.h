@@ -147,7 +147,8 @@ typedef struct {
                                           update                             */
   int32_t cycles_persistent;           /* GMRES cycles whose Arnoldi steps ran
                                           in one persistent launch (u = FP32,
-                                          CGS2, n <= 2048)                   */
+                                          CGS2, n <= 8192 and 3 ceil(n/128)
+                                          compute units on the device)       */
   int32_t cycles_fallback;             /* persistent launches that gave up
                                           (not all their workgroups resident
                                           together: the device was shared)
@@ -371,7 +372,7 @@ int gmresir_errors_noalloc(const double* A, int64_t n, int64_t lda,
  * bit 16: one whole Arnoldi step, A-tilde v_j through the normalisation,
  * with n^2 (s_A + s_f) plus one read of the basis as its bytes) and
  * "arnoldi_cycle" (class 9, timing bit 17: a cycle's steps in one persistent
- * launch, used for u = FP32 with classical Gram-Schmidt when n <= 2048; its
+ * launch, used for u = FP32 with classical Gram-Schmidt when n <= 8192; its
  * work is that of the steps it took; GMRESIR_PERSISTENT=0 in the
  * environment at handle creation keeps the separate launches).  Each event
  * pair costs a few microseconds of stream time, so time only the classes of

@@ -189,13 +189,16 @@ void launch_ortho_small(const OrthoArgs& a, void* vout, hipStream_t s);
 // the finish and v_{j+1}), every cross-workgroup hand-over through tagged
 // words (the step's tag is epoch0 + j).  Bit-identical to the step's
 // separate launches.  Needs n <= kCycleMaxN, m <= kCycleMaxM and all its
-// workgroups resident at once (one per compute unit: at most 48 of them):
+// workgroups resident at once (one per compute unit: at most 192 of them;
+// the caller checks the device has that many):
 // each first arrives on the
-// zeroed word *arrive; when not all have arrived within arrive_us, the
-// launch gives up before touching any result (kCycleGaveUp set in *arrive)
-// and the caller runs the steps as separate launches instead.
-constexpr int kCycleMaxN = 2048;
-constexpr unsigned kCycleGaveUp = 1u << 31;
+// zeroed words arrive[0] (the arrival count) and arrive[1] (the decision);
+// when not all have arrived within arrive_us, the launch gives up before
+// touching any result (arrive[1] = kCycleGaveUp; kCycleGo when it ran) and
+// the caller runs the steps as separate launches instead.
+constexpr int kCycleMaxN = 8192;
+constexpr unsigned kCycleGo = 1;
+constexpr unsigned kCycleGaveUp = 2;
 constexpr int kCycleArriveUs = 500;
 constexpr int kCycleMaxM = 96;
 struct CycleArgs {
@@ -229,19 +232,20 @@ struct CycleArgs {
   CycleState* st;
   // tagged exchange words, zeroed once: xt, xwL, xwU 2 ceil(n/128) 128 each
   // (the product, the lower and the upper solve), vw ceil(n/128) 128 (v_{j+1}
-  // in fp32), px kCycleExchange (the passes' per-block sums), ctrl 2
+  // in fp32), px kCycleExchange (the passes' per-block sums), ctrl 4 (the
+// verdict, then the arrival word)
   uint64_t* xt;
   uint64_t* xwL;
   uint64_t* xwU;
   uint64_t* vw;
   uint64_t* px;
   uint64_t* ctrl;
-  unsigned* arrive;
+  unsigned* arrive;  // two zeroed words: the arrival count, the decision
   int arrive_us;  // the arrival wait's bound (kCycleArriveUs unless a test sets it)
   uint32_t epoch0;
   int* abortp;
 };
-constexpr int kCycleExchange = 3 * (kCycleMaxN / kTrsvBlock) * kDotsMaxCols * 2;
+constexpr int kCycleExchange = 3 * (kCycleMaxN / kTrsvBlock) * kCycleMaxM * 2;
 void launch_cycle(const CycleArgs& a, int store, hipStream_t s);
 
 // out (n x nout, col-major fp64, ld ldo) = X M, M (ncol x nout col-major) on device

@@ -1870,6 +1870,8 @@ inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); 
 // are bit-identical to them.  Every wait is bounded and watches the abort
 // flag; a workgroup that gives up leaves the flag set and the others follow.
 constexpr int kCycleBlocks = kCycleMaxN / kTS;
+// the exchanges' reduction: blocks polled per thread
+constexpr int kCycleReduceBlocks = 8;
 constexpr int kCycleRowPieces = 16;  // 16-byte pieces a lane of the product loads per round
 
 // LDS of a rows workgroup: its block's rows of the basis, column after
@@ -1881,10 +1883,10 @@ struct CycleRowsShared {
   double basis[kCycleMaxM * kTS];
   float vsh[kCycleMaxN];
   double wsh[kTS];
-  double hsum[2][kDotsMaxCols];
-  double c1[kDotsMaxCols];
-  double c2[kDotsMaxCols];
-  double scr[4 * kDotsMaxCols];
+  double hsum[2][kCycleMaxM];
+  double c1[kCycleMaxM];
+  double c2[kCycleMaxM];
+  double scr[kCycleMaxM * (kCycleBlocks / 2)];  // the exchanges' chunk sums
   double nrm[2];
   double cs[kCycleMaxM], sn[kCycleMaxM], g[kCycleMaxM + 1];
   CycleState st;
@@ -1922,20 +1924,21 @@ __device__ __forceinline__ bool get_tagged_lane(const uint64_t* xw, int idx, uin
 // row: tag << 32 | bits); false (for the whole workgroup) on abort
 __device__ __forceinline__ bool cycle_fetch_v(const uint64_t* vw, int n, uint32_t tag, float* vsh,
                                               int* abortp) {
+  constexpr int kPer = kCycleMaxN / kTSThreads;  // words per thread in flight
   bool ok = true;
-  for (int i0 = 0; i0 < n && ok; i0 += 4 * kTSThreads) {
-    // four words per thread in flight, then poll the ones not yet there
-    uint64_t x[4];
+  for (int i0 = 0; i0 < n && ok; i0 += kPer * kTSThreads) {
+    // every word of the round in flight, then poll until all carry the tag
+    uint64_t x[kPer];
     long long spins = 0;
     for (;;) {
       bool all = true;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < kPer; ++e) {
         const int i = i0 + e * kTSThreads + (int)threadIdx.x;
         x[e] = __hip_atomic_load(vw + (i < n ? i : 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < kPer; ++e) {
         const int i = i0 + e * kTSThreads + (int)threadIdx.x;
         all = all && (i >= n || (uint32_t)(x[e] >> 32) == tag);
       }
@@ -1955,7 +1958,7 @@ __device__ __forceinline__ bool cycle_fetch_v(const uint64_t* vw, int n, uint32_
     }
     if (ok) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < kPer; ++e) {
         const int i = i0 + e * kTSThreads + (int)threadIdx.x;
         if (i < n) vsh[i] = __uint_as_float((uint32_t)x[e]);
       }
@@ -1966,21 +1969,28 @@ __device__ __forceinline__ bool cycle_fetch_v(const uint64_t* vw, int n, uint32_
 
 // The product's rows, formed by the rows workgroups in row order, so that
 // the lower chain's blocks find their rows ahead of need.  A row's 256-column
-// pieces number P = ceil(n4 / 256) <= 8 (n4 = n rounded down to a multiple
-// of 4); a wave takes R = kCycleRowPieces / P rows at a time and issues
-// every load of them before any product, and its rows' indices in A_u sit
-// in one register (lane e: the e-th row it takes), so no permutation load
-// waits in the step.  Rows workgroup u's wave w takes, in its k-th round,
-// rows ((k nb + u) 8 + w) R .. + R - 1.
+// pieces number P = ceil(n4 / 256) <= 32 (n4 = n rounded down to a multiple
+// of 4); a wave takes R = kCycleRowPieces / P rows at a time (one row, in
+// batches of kCycleRowPieces pieces, when P is larger) and issues every load
+// of a batch before any product, and its rows' indices in A_u sit in one
+// register (lane e: the e-th row it takes), so no permutation load waits in
+// the step.  Rows workgroup u's wave w takes, in its k-th round, rows
+// ((k nb + u) 8 + w) R .. + R - 1.
 __device__ __forceinline__ int cycle_product_pieces(int n) {
   const int p = ((n & ~3) + 255) / 256;
   return p < 1 ? 1 : p;
 }
 
+__device__ __forceinline__ int cycle_product_rows_per_wave(int n) {
+  const int p = cycle_product_pieces(n);
+  return p < kCycleRowPieces ? kCycleRowPieces / p : 1;
+}
+
 // lane e of the result: the row of A_u for the e-th row this wave takes
-// (-1 past n)
+// (-1 past n; at most 64 rows, since k R < 16 for every round k that starts
+// below n)
 __device__ __forceinline__ int cycle_product_rowlist(const CycleArgs& a, int nb, int u) {
-  const int R = kCycleRowPieces / cycle_product_pieces(a.n);
+  const int R = cycle_product_rows_per_wave(a.n);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int k = lane / R, r = lane % R;
   const int row = ((k * nb + u) * 8 + wave) * R + r;
@@ -2045,8 +2055,50 @@ __device__ __forceinline__ void cycle_product_rows(const CycleArgs& a, const flo
   }
 }
 
+// rows of more than kCycleRowPieces pieces: one row per wave at a time, its
+// pieces in batches of kCycleRowPieces (the same order of sums)
+__device__ __forceinline__ void cycle_product_long_rows(const CycleArgs& a, const float* v,
+                                                        int rowlist, int nb, int u, uint32_t tag) {
+  constexpr int B = kCycleRowPieces;
+  const int n = a.n, n4 = n & ~3, P = cycle_product_pieces(n);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int cc = n4 + lane;
+  for (int k = 0;; ++k) {
+    const int row = (k * nb + u) * 8 + wave;
+    if (row >= n) break;
+    const int pr = __builtin_amdgcn_readlane(rowlist, k);
+    const float* rp = a.Au + (int64_t)(pr >= 0 ? pr : 0) * a.lda;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int i0 = 0; i0 < P; i0 += B) {
+      float4 x[B];
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const int c = lane * 4 + 256 * (i0 + i);
+        x[i] = *reinterpret_cast<const float4*>(rp + (c < n4 ? c : 0));
+      }
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const int c = lane * 4 + 256 * (i0 + i);
+        if (c < n4) {
+          acc0 = fma((double)x[i].x, (double)v[c + 0], acc0);
+          acc1 = fma((double)x[i].y, (double)v[c + 1], acc1);
+          acc0 = fma((double)x[i].z, (double)v[c + 2], acc0);
+          acc1 = fma((double)x[i].w, (double)v[c + 3], acc1);
+        }
+      }
+    }
+    if (cc < n) acc0 = fma((double)rp[cc], (double)v[cc], acc0);
+    const double t = wave_sum(acc0 + acc1);
+    if (lane == 0) put_tagged(a.xt, row, t, tag);
+  }
+}
+
 __device__ __forceinline__ void cycle_product(const CycleArgs& a, const float* v, int rowlist,
                                               int nb, int u, uint32_t tag) {
+  if (cycle_product_pieces(a.n) > 8) {
+    cycle_product_long_rows(a, v, rowlist, nb, u, tag);
+    return;
+  }
   switch (cycle_product_pieces(a.n)) {
     case 1: cycle_product_rows<1>(a, v, rowlist, nb, u, tag); break;
     case 2: cycle_product_rows<2>(a, v, rowlist, nb, u, tag); break;
@@ -2061,71 +2113,63 @@ __device__ __forceinline__ void cycle_product(const CycleArgs& a, const float* v
 
 // The per-block sums of one exchange (cnt values per block; block b's pair
 // sum of column c at entry b cnt + c of x): per 256-row chunk the two
-// blocks' sums added, then the chunks in order from zero, into out[c].  Two
-// threads per column, each polling its eight blocks' words at once (blocks
-// 0-7 and 8-15): the second hands its chunk sums over through scr (4 cnt
-// doubles), the first adds them after its own.  False (for the whole
-// workgroup) on abort.
+// blocks' sums added, then the chunks in order from zero, into out[c].
+// ceil(nb / kCycleReduceBlocks) threads per column (in rounds of the
+// workgroup's threads), each polling its kCycleReduceBlocks blocks' words
+// at once (every load unconditional: a block past nb reads block 0's,
+// unused) and leaving its chunk sums in scr; then one thread per column adds
+// the chunks in order.  False (for the whole workgroup) on abort.
 __device__ __forceinline__ bool cycle_reduce(const uint64_t* x, int nb, int cnt, uint32_t tag,
                                              double* out, double* scr, int* abortp) {
+  constexpr int B = kCycleReduceBlocks, Q = B / 2;
+  const int T = (nb + B - 1) / B;
   bool ok = true;
-  const int t = threadIdx.x;
-  const int c = t >> 1, g = t & 1;
-  double ch[4] = {0.0, 0.0, 0.0, 0.0};
-  if (c < cnt) {
-    const int b0 = 8 * g;
-    double v[8];
+  for (int p0 = 0; p0 < cnt * T; p0 += kTSThreads) {
+    const int pidx = p0 + (int)threadIdx.x;
+    if (pidx < cnt * T && ok) {
+      const int c = pidx / T, g = pidx % T, b0 = B * g;
+      double v[B];
+      long long spins = 0;
+      for (;;) {
+        bool all = true;
+        uint64_t lo[B], hi[B];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = 0.0;
-    long long spins = 0;
-    for (;;) {
-      bool all = true;
-      // all sixteen words loaded unconditionally (a block past nb reads
-      // block 0's, unused), so that the loads wait together
-      uint64_t lo[8], hi[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint64_t* p = x + 2 * ((b0 + e < nb ? b0 + e : 0) * cnt + c);
-        lo[e] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        hi[e] = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const bool in = b0 + e < nb;
-        all = all && (!in || ((uint32_t)(lo[e] >> 32) == tag && (uint32_t)(hi[e] >> 32) == tag));
-        v[e] = in ? __longlong_as_double((long long)((hi[e] << 32) | (lo[e] & 0xFFFFFFFFull)))
-                  : 0.0;
-      }
-      if (all) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (((++spins) & 1023) == 0) {
-        if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          ok = false;
-          break;
+        for (int e = 0; e < B; ++e) {
+          const uint64_t* p = x + 2 * ((b0 + e < nb ? b0 + e : 0) * cnt + c);
+          lo[e] = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          hi[e] = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (spins > (1ll << 22)) {
-          __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = false;
-          break;
+#pragma unroll
+        for (int e = 0; e < B; ++e) {
+          const bool in = b0 + e < nb;
+          all = all &&
+                (!in || ((uint32_t)(lo[e] >> 32) == tag && (uint32_t)(hi[e] >> 32) == tag));
+          v[e] = in ? __longlong_as_double((long long)((hi[e] << 32) | (lo[e] & 0xFFFFFFFFull)))
+                    : 0.0;
+        }
+        if (all) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (((++spins) & 1023) == 0) {
+          if (__hip_atomic_load(abortp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = false;
+            break;
+          }
+          if (spins > (1ll << 22)) {
+            __hip_atomic_store(abortp, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+          }
         }
       }
-    }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ch[q] = v[2 * q] + v[2 * q + 1];
-    if (g == 1) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) scr[4 * c + q] = ch[q];
+      for (int q = 0; q < Q; ++q) scr[c * (kCycleBlocks / 2) + g * Q + q] = v[2 * q] + v[2 * q + 1];
     }
   }
   if (__syncthreads_or(!ok)) return false;
-  if (c < cnt && g == 0) {
+  if ((int)threadIdx.x < cnt) {
+    const int c = threadIdx.x;
     double sum = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (2 * q < nb) sum += ch[q];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (8 + 2 * q < nb) sum += scr[4 * c + q];
+    for (int k = 0; 2 * k < nb; ++k) sum += scr[c * (kCycleBlocks / 2) + k];
     out[c] = sum;
   }
   __syncthreads();
@@ -2240,7 +2284,7 @@ __device__ __forceinline__ void cycle_rows(const CycleArgs& a, CycleRowsShared& 
     // 3. the passes: dots; update and dots; update and norm
     const int ncol = kc + j + 1;
     for (int pass = 0; pass < 3; ++pass) {
-      uint64_t* px = a.px + (int64_t)pass * kCycleBlocks * kDotsMaxCols * 2;
+      uint64_t* px = a.px + (int64_t)pass * kCycleBlocks * kCycleMaxM * 2;
       if (pass > 0 && vrow) wv = round_u<float>(wv - cycle_row_fma(X, j + 1, lrow, pass == 1 ? sm.c1 : sm.c2));
       if (pass < 2) {
         if (pass > 0) {
@@ -2317,50 +2361,42 @@ __device__ __forceinline__ void cycle_rows(const CycleArgs& a, CycleRowsShared& 
 }
 
 // The launch goes on only if all its total workgroups are resident at once
-// (they wait for one another at every step).  Each arrives on the state word
-// (the count in the low bits) unless the launch has already given up; one
-// that has waited bound_us without seeing all arrive gives up for the
-// launch, unless the last one arrived meanwhile (both are decided by
-// compare-and-swap on the one word, so every workgroup takes the same
-// verdict; a bound of zero gives up at once).  Returns the verdict
-// (workgroup-uniform).
+// (they wait for one another at every step).  state[0] counts arrivals (one
+// fetch-and-add per workgroup); state[1] holds the decision, taken once by
+// compare-and-swap from zero: kCycleGo by the arrival that completes the
+// count, kCycleGaveUp by a workgroup that has waited bound_us without seeing
+// a decision (a bound of zero gives up at once).  Every workgroup then reads
+// the decision, so all take the same one.  Returns it (workgroup-uniform).
 __device__ __forceinline__ bool cycle_arrive(unsigned* state, unsigned total, int bound_us,
                                              int& verdict) {
   if (threadIdx.x == 0) {
-    int go = 0;
-    unsigned old = __hip_atomic_load(state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool in = false;
-    // a bound of zero gives up at once (the fall-back path, forced)
-    if (bound_us <= 0)
-      __hip_atomic_fetch_or(state, kCycleGaveUp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (bound_us > 0 && !(old & kCycleGaveUp)) {
-      if (__hip_atomic_compare_exchange_strong(state, &old, old + 1, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        old += 1;
-        in = true;
-        break;
-      }
+    unsigned* count = state;
+    unsigned* decision = state + 1;
+    unsigned expect = 0;
+    if (bound_us <= 0) {
+      __hip_atomic_compare_exchange_strong(decision, &expect, kCycleGaveUp, __ATOMIC_RELAXED,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned before =
+          __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (before + 1 == total)
+        __hip_atomic_compare_exchange_strong(decision, &expect, kCycleGo, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (in) {
-      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz
-      for (;;) {
-        if ((old & ~kCycleGaveUp) == total && !(old & kCycleGaveUp)) {
-          go = 1;
-          break;
-        }
-        if (old & kCycleGaveUp) break;
-        if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)bound_us * 100) {
-          if (__hip_atomic_compare_exchange_strong(state, &old, old | kCycleGaveUp,
-                                                   __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT))
-            break;
-          continue;  // old holds the word's current value
-        }
-        __builtin_amdgcn_s_sleep(2);
-        old = __hip_atomic_load(state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();  // 100 MHz
+    unsigned d;
+    for (;;) {
+      d = __hip_atomic_load(decision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (d != 0) break;
+      if (__builtin_amdgcn_s_memrealtime() - t0 > (uint64_t)bound_us * 100) {
+        expect = 0;
+        __hip_atomic_compare_exchange_strong(decision, &expect, kCycleGaveUp, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        continue;  // read the decision taken
       }
+      __builtin_amdgcn_s_sleep(2);
     }
-    verdict = go;
+    verdict = (d == kCycleGo) ? 1 : 0;
   }
   __syncthreads();
   return verdict != 0;

@@ -686,7 +686,13 @@ int alloc_solve(gmresir_ctx* h) {
     // the A_u product's rows, published to the fused lower solve
     GIR_TRY(dalloc(h->arena, &h->xt, (size_t)nxw));
     zl.add(h->xt, sizeof(uint64_t) * (size_t)nxw);
-    if (h->n <= gir::kCycleMaxN && h->m <= gir::kCycleMaxM) {
+    // the persistent cycle's 3 ceil(n/128) workgroups must all be resident
+    // at once, one per compute unit
+    int dev = 0, cus = 0;
+    GIR_HIP(hipGetDevice(&dev));
+    GIR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t cycle_wgs = 3 * ((h->n + gir::kTrsvBlock - 1) / gir::kTrsvBlock);
+    if (h->n <= gir::kCycleMaxN && h->m <= gir::kCycleMaxM && cycle_wgs <= cus) {
       // the persistent cycle's own words: v_{j+1}, the passes' sums, the verdict
       GIR_TRY(dalloc(h->arena, &h->cvw, (size_t)nxw / 2));
       GIR_TRY(dalloc(h->arena, &h->cpx, (size_t)gir::kCycleExchange));
@@ -1539,7 +1545,8 @@ struct SolveStats {
 
 // a cycle's Arnoldi steps in one persistent launch: u = fp32, classical
 // Gram-Schmidt twice, the forward operator, n and m within the kernel's
-// limits (its exchange words allocated)
+// limits and 3 ceil(n/128) compute units on the device (its exchange words
+// allocated)
 bool cycle_eligible(const gmresir_ctx* h) {
   return h->persistent && h->cvw && !h->trans && !h->u64 && !h->uni && h->o.ortho == 0 &&
          h->fuse_atilde;
@@ -1548,8 +1555,9 @@ bool cycle_eligible(const gmresir_ctx* h) {
 // up to nsteps Arnoldi steps of the cycle with kc recycled columns, one
 // launch; the results (V, H, B, the rotations and the cycle state) are where
 // the separate launches leave them, unless the launch gave up (its
-// workgroups were not all resident together: kCycleGaveUp in the word at
-// cctrl + 2), in which case it wrote nothing.
+// workgroups were not all resident together: the decision word after the
+// arrival count at cctrl + 2 is then kCycleGaveUp, not kCycleGo), in which
+// case it wrote nothing.
 int run_cycle(gmresir_ctx* h, int kc, int nsteps) {
   gir::CycleArgs a{};
   a.S = h->S;
@@ -1587,7 +1595,7 @@ int run_cycle(gmresir_ctx* h, int kc, int nsteps) {
   a.arrive_us = h->cycle_arrive_us;
   a.epoch0 = (uint32_t)reserve_epochs(h, nsteps);
   a.abortp = &h->st->abort;
-  gir::launch_fill_i32(reinterpret_cast<int*>(a.arrive), 0, 1, h->stream);
+  gir::launch_fill_i32(reinterpret_cast<int*>(a.arrive), 0, 2, h->stream);
   // the work is set once the number of steps taken is known
   return timed(h, kKcCycle, 0.0, h->stream, nullptr, 0,
                [&] { gir::launch_cycle(a, h->store, h->stream); });
@@ -1804,10 +1812,10 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
           h, {{&fin, h->st, sizeof(fin)},
               {Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m},
               {Bh.data(), h->Bd, kc > 0 ? sizeof(double) * (size_t)std::max(k, 1) * m : 0},
-              {&gate, h->cctrl + 2, one_launch ? sizeof(gate) : 0}});
+              {&gate, reinterpret_cast<unsigned*>(h->cctrl + 2) + 1, one_launch ? sizeof(gate) : 0}});
     };
     GIR_TRY(fetch_state());
-    if (one_launch && (gate & gir::kCycleGaveUp)) {
+    if (one_launch && gate != gir::kCycleGo) {
       h->trec.resize(trec0);
       ++h->cycle_fallbacks;
       one_launch = false;

@@ -1,5 +1,5 @@
 """A GMRES cycle's Arnoldi steps in one persistent launch (u = fp32,
-classical Gram-Schmidt twice, n <= 2048) against the separate launches of
+classical Gram-Schmidt twice, n <= 8192) against the separate launches of
 each step (GMRESIR_PERSISTENT=0 at handle creation).  The persistent kernel
 forms every sum of the step -- the product with A_u, the two blocked
 triangular solves, the three Gram-Schmidt passes with their per-block sums
@@ -73,6 +73,25 @@ def test_persistent_cycle_is_bit_identical(lib, monkeypatch, n, k, m, kappa, uf)
     assert torch.equal(x1, x0)
 
 
+@pytest.mark.parametrize("n,k", [(4097, 10), (8192, 10)])
+def test_persistent_cycle_at_large_orders(lib, monkeypatch, n, k):
+    """Orders beyond 4096 (up to 64 blocks per chain, rows of more than eight
+    256-column pieces, exchanges over more than 16 blocks), among them the
+    benchmark's n = 8192: the same bits as the separate launches."""
+    from synthetic import randsvd_problem_torch
+    a, _, b = randsvd_problem_torch(n, 1e2, 3)
+    kw = dict(m=30, k=k, maxit=60)
+    log(f"[cycle-large] n={n} k={k}")
+    (r1,), c1 = _solve(lib, monkeypatch, a, [b], True, **kw)
+    (r0,), c0 = _solve(lib, monkeypatch, a, [b], False, **kw)
+    (x1, i1), (x0, i0) = r1, r0
+    log(f"[cycle-large] its persistent {i1['its']} separate {i0['its']} launches {c1} / {c0}")
+    assert c1 > 0 and c0 == 0 and i1["cycles_persistent"] > 0
+    assert i1["status"] == i0["status"] == 0
+    assert i1["its"] == i0["its"] and i1["berr"] == i0["berr"]
+    assert torch.equal(x1, x0)
+
+
 def test_persistent_cycle_with_kept_recycle_space(lib, monkeypatch):
     """Several right-hand sides with the recycle space carried over: every
     cycle's basis starts with C_k."""
@@ -89,17 +108,22 @@ def test_persistent_cycle_with_kept_recycle_space(lib, monkeypatch):
         assert torch.equal(x1, x0)
 
 
-@pytest.mark.parametrize("n,u,extra", [(2049, "fp32", {}), (600, "fp64", {}),
+@pytest.mark.parametrize("n,u,extra", [(8193, "fp32", {}), (600, "fp64", {}),
                                         (600, "fp32", {"ortho": "mgs"})])
 def test_persistent_cycle_outside_its_limits(lib, monkeypatch, n, u, extra):
-    """Beyond n = 2048, for u = fp64 and with modified Gram-Schmidt the cycle
+    """Beyond n = 8192, for u = fp64 and with modified Gram-Schmidt the cycle
     runs as separate launches (no persistent launch is made)."""
-    p = randsvd_problem(n, 1e3, 35)
+    if n > 4096:
+        from synthetic import randsvd_problem_torch
+        a, _, b = randsvd_problem_torch(n, 1e2, 35)
+    else:
+        p = randsvd_problem(n, 1e3, 35)
+        a, b = _dev(p.a), _dev(p.b)
     uf = "fp16" if u == "fp32" else "fp32"
     kw = dict(uf=uf, u=u, ur="dd" if u == "fp64" else "fp64", m=20, k=4,
               tau=1e-4 if u == "fp32" else 1e-8, **extra)
     log(f"[cycle-limits] n={n} u={u} {extra}")
-    (r,), c = _solve(lib, monkeypatch, _dev(p.a), [_dev(p.b)], True, **kw)
+    (r,), c = _solve(lib, monkeypatch, a, [b], True, **kw)
     assert c == 0 and r[1]["status"] == 0
 
 
