@@ -1376,7 +1376,10 @@ int tune_ortho(gmresir_ctx* h) {
 }
 
 // dots (X^T w) and/or squared norm of a vector in u, synchronous result
-int dots_norm(gmresir_ctx* h, const gir::Basis& X, const void* w, double* dots, double* nrm2) {
+// extra: one more device-to-host piece fetched in the same synchronisation
+// (null: none)
+int dots_norm(gmresir_ctx* h, const gir::Basis& X, const void* w, double* dots, double* nrm2,
+              const struct Piece* extra = nullptr) {
   gir::OrthoArgs a{};
   a.X = X;
   a.n = (int)h->n;
@@ -1392,7 +1395,9 @@ int dots_norm(gmresir_ctx* h, const gir::Basis& X, const void* w, double* dots, 
   GIR_HIP(hipGetLastError());
   const int nc = X.kc + X.nv;
   const size_t db = (nc > 0 && dots) ? sizeof(double) * nc : 0;
-  GIR_TRY(download_many(h, {{dots, h->h1, db}, {nrm2, h->nrm, sizeof(double)}}));
+  GIR_TRY(download_many(h, {{dots, h->h1, db},
+                            {nrm2, h->nrm, sizeof(double)},
+                            extra ? *extra : Piece{nullptr, nullptr, 0}}));
   return 0;
 }
 
@@ -1655,8 +1660,22 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
   while (true) {
     std::vector<double> ctr(std::max(kc, 1));
     double n2 = 0.0;
-    GIR_TRY(dots_norm(h, basis(h, h->C, kc, ld, nullptr, 0, ld), h->ru, kc ? ctr.data() : nullptr,
-                      &n2));
+    // C^T r and ||r||, and with them U^T U (its diagonal scales the recycled
+    // columns after the cycle; U does not change before then), all in one
+    // synchronisation
+    std::vector<double> UU((size_t)std::max(kc, 1) * std::max(kc, 1));
+    auto start_cycle = [&]() -> int {
+      Piece uu{UU.data(), h->Gdev, 0};
+      if (kc > 0) {
+        gir::launch_gram(basis(h, h->U, kc, ld, nullptr, 0, ld), h->U, kc, ld, n, h->Gdev,
+                         h->partial, h->counter, s);
+        GIR_HIP(hipGetLastError());
+        uu.bytes = sizeof(double) * (size_t)kc * kc;
+      }
+      return dots_norm(h, basis(h, h->C, kc, ld, nullptr, 0, ld), h->ru,
+                       kc ? ctr.data() : nullptr, &n2, &uu);
+    };
+    GIR_TRY(start_cycle());
     double rn = std::sqrt(n2);
     if (rn <= tol) break;
     if (stats.its >= cap) break;
@@ -1664,8 +1683,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       // the estimate said converged but the residual did not: refresh now
       GIR_TRY(apply_refresh(h, h->pend, &kc));
       ctr.assign(std::max(kc, 1), 0.0);
-      GIR_TRY(dots_norm(h, basis(h, h->C, kc, ld, nullptr, 0, ld), h->ru,
-                        kc ? ctr.data() : nullptr, &n2));
+      UU.assign((size_t)std::max(kc, 1) * std::max(kc, 1), 0.0);
+      GIR_TRY(start_cycle());
       rn = std::sqrt(n2);
     }
     const int nsteps = std::min(m - kc, cap - stats.its);
@@ -1807,12 +1826,23 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     (void)queued;
     gir::CycleState fin{};
     unsigned gate = 0;
+    // W = [C V_{nsteps+1}]^T U for the recycle refresh, formed over every
+    // column the cycle may have written (rows past kc + J + 1 are not used)
+    // and fetched with the cycle's state
+    const int wrows = kc + nsteps + 1;
+    std::vector<double> Wall((size_t)wrows * std::max(kc, 1));
     auto fetch_state = [&]() -> int {
+      if (kc > 0) {
+        gir::launch_gram(basis(h, h->C, kc, ld, h->V, nsteps + 1, ld), h->U, kc, ld, n, h->Gdev,
+                         h->partial, h->counter, s);
+        GIR_HIP(hipGetLastError());
+      }
       return download_many(
           h, {{&fin, h->st, sizeof(fin)},
               {Hh.data(), h->Hd, sizeof(double) * (size_t)(m + 1) * m},
               {Bh.data(), h->Bd, kc > 0 ? sizeof(double) * (size_t)std::max(k, 1) * m : 0},
-              {&gate, reinterpret_cast<unsigned*>(h->cctrl + 2) + 1, one_launch ? sizeof(gate) : 0}});
+              {&gate, reinterpret_cast<unsigned*>(h->cctrl + 2) + 1, one_launch ? sizeof(gate) : 0},
+              {Wall.data(), h->Gdev, kc > 0 ? sizeof(double) * (size_t)wrows * kc : 0}});
     };
     GIR_TRY(fetch_state());
     if (one_launch && gate != gir::kCycleGo) {
@@ -1867,9 +1897,7 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
         GIR_TRY(schedule_refresh(h, rf, fin.done || stats.its >= cap, &kc));
       }
     } else {
-      // D = diag(1 / ||U e_i||)
-      std::vector<double> UU;
-      GIR_TRY(gram(h, basis(h, h->U, kc, ld, nullptr, 0, ld), h->U, kc, UU));
+      // D = diag(1 / ||U e_i||), U^T U fetched at the cycle's start
       std::vector<double> dk(kc);
       for (int i = 0; i < kc; ++i) dk[i] = 1.0 / std::sqrt(UU[(size_t)i * kc + i]);
       std::vector<double> y1(kc), by2(kc, 0.0);
@@ -1891,8 +1919,10 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       GIR_HIP(hipGetLastError());
       if (J > 0) {
         const int rows = kc + J + 1, cols = kc + J;
-        std::vector<double> W;  // [C V_{J+1}]^T U  (rows x kc)
-        GIR_TRY(gram(h, basis(h, h->C, kc, ld, h->V, J + 1, ld), h->U, kc, W));
+        std::vector<double> W((size_t)rows * kc);  // [C V_{J+1}]^T U  (rows x kc)
+        for (int c = 0; c < kc; ++c)
+          std::copy(Wall.begin() + (size_t)c * wrows, Wall.begin() + (size_t)c * wrows + rows,
+                    W.begin() + (size_t)c * rows);
         std::vector<double> Gm((size_t)rows * cols, 0.0), Mm((size_t)rows * cols, 0.0);
         for (int i = 0; i < kc; ++i) Gm[(size_t)i * rows + i] = dk[i];
         for (int c = 0; c < J; ++c) {
@@ -1914,7 +1944,6 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
         GIR_TRY(schedule_refresh(h, rf, fin.done || stats.its >= cap, &kc));
       }
     }
-    GIR_HIP(hipStreamSynchronize(s));
   }
   // with a deferred refresh the dimension is set when it is applied
   if (!h->pend.active) h->kc_keep = (k > 0) ? kc : 0;
