@@ -159,146 +159,185 @@ inline void givens_c(cd x, cd y, double& c, cd& s) {
 
 }  // namespace
 
+namespace {
+
+// Complex Schur form T = Z^H A Z of a real matrix: Householder reduction to
+// upper Hessenberg form (real arithmetic), then single-shift QR with
+// Wilkinson shifts (an
+// exceptional shift every 11th iteration).  Z is not accumulated: its
+// factors (the reflectors and every sweep's rotations) are kept, and
+// vector(e) forms only the eigenvectors asked for (back substitution on T,
+// then Z applied factor by factor), which costs far less than carrying Z
+// through every sweep when a few vectors are wanted.
+struct SchurC {
+  struct Rot {
+    int k;
+    double c;
+    cd s;
+  };
+  int N = 0;
+  std::vector<cd> T;          // column-major
+  std::vector<double> hv;     // reflector c: hv[c * N + i] for i > c (real: A is real)
+  std::vector<double> hb;     // its beta (0: no reflection)
+  std::vector<Rot> rots;      // in the order they were applied
+  double small = 0.0;
+
+  cd& t(int i, int j) { return T[(size_t)j * N + i]; }
+  const cd& t(int i, int j) const { return T[(size_t)j * N + i]; }
+
+  bool factor(const double* A, int n) {
+    N = n;
+    // Householder reduction to upper Hessenberg form in real arithmetic
+    std::vector<double> H(A, A + (size_t)N * N);
+    auto h = [&](int i, int j) -> double& { return H[(size_t)j * N + i]; };
+    hv.assign((size_t)N * N, 0.0);
+    hb.assign(N, 0.0);
+    rots.clear();
+    for (int c = 0; c + 2 < N; ++c) {
+      double nrm = 0.0;
+      for (int i = c + 1; i < N; ++i) nrm += h(i, c) * h(i, c);
+      nrm = std::sqrt(nrm);
+      if (nrm == 0.0) continue;
+      const double x0 = h(c + 1, c);
+      const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+      double* v = &hv[(size_t)c * N];
+      for (int i = c + 1; i < N; ++i) v[i] = h(i, c);
+      v[c + 1] -= alpha;
+      double vn = 0.0;
+      for (int i = c + 1; i < N; ++i) vn += v[i] * v[i];
+      if (vn == 0.0) continue;
+      const double beta = 2.0 / vn;
+      hb[c] = beta;
+      // H = (I - beta v v^T) H (I - beta v v^T)
+      for (int j = 0; j < N; ++j) {
+        double d = 0.0;
+        for (int i = c + 1; i < N; ++i) d += v[i] * h(i, j);
+        d *= beta;
+        for (int i = c + 1; i < N; ++i) h(i, j) -= d * v[i];
+      }
+      for (int i = 0; i < N; ++i) {
+        double d = 0.0;
+        for (int j = c + 1; j < N; ++j) d += h(i, j) * v[j];
+        d *= beta;
+        for (int j = c + 1; j < N; ++j) h(i, j) -= d * v[j];
+      }
+      for (int i = c + 2; i < N; ++i) h(i, c) = 0.0;
+    }
+    T.assign((size_t)N * N, cd(0.0));
+    for (size_t i = 0; i < (size_t)N * N; ++i) T[i] = H[i];
+    const double eps = std::numeric_limits<double>::epsilon();
+    int hi = N - 1;
+    int iter = 0, total = 0;
+    while (hi > 0) {
+      int l = hi;
+      while (l > 0) {
+        const double sub = std::abs(t(l, l - 1));
+        const double dsum = std::abs(t(l - 1, l - 1)) + std::abs(t(l, l));
+        if (sub <= eps * (dsum > 0.0 ? dsum : 1.0)) {
+          t(l, l - 1) = 0.0;
+          break;
+        }
+        --l;
+      }
+      if (l == hi) {
+        --hi;
+        iter = 0;
+        continue;
+      }
+      if (++total > 100 * N) return false;
+      ++iter;
+      const cd a = t(hi - 1, hi - 1), b = t(hi - 1, hi), c = t(hi, hi - 1), d = t(hi, hi);
+      cd mu;
+      if (iter % 11 == 10) {
+        mu = d + std::abs(t(hi, hi - 1));  // exceptional shift
+      } else {
+        const cd tr = a + d;
+        const cd det = a * d - b * c;
+        const cd disc = std::sqrt(tr * tr * 0.25 - det);
+        const cd m1 = tr * 0.5 + disc, m2 = tr * 0.5 - disc;
+        mu = (std::abs(m1 - d) < std::abs(m2 - d)) ? m1 : m2;
+      }
+      cd x = t(l, l) - mu;
+      cd y = t(l + 1, l);
+      for (int k = l; k < hi; ++k) {
+        double cc;
+        cd s;
+        givens_c(x, y, cc, s);
+        // rows k, k+1, then columns k, k+1
+        for (int j = std::max(l, k - 1); j < N; ++j) {
+          const cd t1 = t(k, j), t2 = t(k + 1, j);
+          t(k, j) = cc * t1 + s * t2;
+          t(k + 1, j) = -std::conj(s) * t1 + cc * t2;
+        }
+        const int rmax = std::min(k + 2, hi);
+        for (int i = 0; i <= rmax; ++i) {
+          const cd t1 = t(i, k), t2 = t(i, k + 1);
+          t(i, k) = cc * t1 + std::conj(s) * t2;
+          t(i, k + 1) = -s * t1 + cc * t2;
+        }
+        rots.push_back({k, cc, s});
+        if (k + 1 < hi) {
+          x = t(k + 1, k);
+          y = t(k + 2, k);
+        }
+      }
+    }
+    double tn = 0.0;
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i <= j; ++i) tn = std::max(tn, std::abs(t(i, j)));
+    small = std::max(tn, 1e-300) * eps;
+    return true;
+  }
+
+  cd value(int e) const { return t(e, e); }
+
+  // the unit eigenvector of eigenvalue e: T x = lambda x by back
+  // substitution (x_e = 1), then Z x
+  void vector(int e, cd* out) const {
+    std::vector<cd> x(N, cd(0.0));
+    x[e] = 1.0;
+    const cd lam = t(e, e);
+    for (int r = e - 1; r >= 0; --r) {
+      cd s = 0.0;
+      for (int q = r + 1; q <= e; ++q) s += t(r, q) * x[q];
+      cd den = t(r, r) - lam;
+      if (std::abs(den) < small) den = small;
+      x[r] = -s / den;
+    }
+    // Z = P_0 .. P_{N-3} G_1 .. G_R: the rotations last to first, then the
+    // reflectors last to first
+    for (size_t q = rots.size(); q-- > 0;) {
+      const Rot& g = rots[q];
+      const cd x1 = x[g.k], x2 = x[g.k + 1];
+      x[g.k] = g.c * x1 - g.s * x2;
+      x[g.k + 1] = std::conj(g.s) * x1 + g.c * x2;
+    }
+    for (int c = N - 3; c >= 0; --c) {
+      if (hb[c] == 0.0) continue;
+      const double* v = &hv[(size_t)c * N];
+      cd d = 0.0;
+      for (int i = c + 1; i < N; ++i) d += v[i] * x[i];
+      d *= hb[c];
+      for (int i = c + 1; i < N; ++i) x[i] -= d * v[i];
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < N; ++i) nrm += std::norm(x[i]);
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < N; ++i) out[i] = (nrm > 0.0) ? x[i] / nrm : x[i];
+  }
+};
+
+}  // namespace
+
 bool eig_real(const double* A, int N, std::vector<cd>& w, std::vector<cd>& V) {
   w.assign(N, cd(0.0));
   V.assign((size_t)N * N, cd(0.0));
   if (N == 0) return true;
-  auto H = [&](std::vector<cd>& M, int i, int j) -> cd& { return M[(size_t)j * N + i]; };
-  std::vector<cd> T((size_t)N * N), Z((size_t)N * N, cd(0.0));
-  for (int j = 0; j < N; ++j)
-    for (int i = 0; i < N; ++i) T[(size_t)j * N + i] = A[(size_t)j * N + i];
-  for (int i = 0; i < N; ++i) H(Z, i, i) = 1.0;
-  // Householder reduction to upper Hessenberg form
-  for (int c = 0; c < N - 2; ++c) {
-    double nrm = 0.0;
-    for (int i = c + 1; i < N; ++i) nrm += std::norm(H(T, i, c));
-    nrm = std::sqrt(nrm);
-    if (nrm == 0.0) continue;
-    const cd x0 = H(T, c + 1, c);
-    const cd phase = (std::abs(x0) > 0.0) ? x0 / std::abs(x0) : cd(1.0);
-    const cd alpha = -phase * nrm;
-    std::vector<cd> v(N, cd(0.0));
-    for (int i = c + 1; i < N; ++i) v[i] = H(T, i, c);
-    v[c + 1] -= alpha;
-    double vn = 0.0;
-    for (int i = c + 1; i < N; ++i) vn += std::norm(v[i]);
-    if (vn == 0.0) continue;
-    const double beta = 2.0 / vn;
-    // T = (I - beta v v^H) T
-    for (int j = 0; j < N; ++j) {
-      cd d = 0.0;
-      for (int i = c + 1; i < N; ++i) d += std::conj(v[i]) * H(T, i, j);
-      d *= beta;
-      for (int i = c + 1; i < N; ++i) H(T, i, j) -= d * v[i];
-    }
-    // T = T (I - beta v v^H), Z = Z (I - beta v v^H)
-    for (int i = 0; i < N; ++i) {
-      cd d = 0.0, e = 0.0;
-      for (int j = c + 1; j < N; ++j) {
-        d += H(T, i, j) * v[j];
-        e += H(Z, i, j) * v[j];
-      }
-      d *= beta;
-      e *= beta;
-      for (int j = c + 1; j < N; ++j) {
-        H(T, i, j) -= d * std::conj(v[j]);
-        H(Z, i, j) -= e * std::conj(v[j]);
-      }
-    }
-    for (int i = c + 2; i < N; ++i) H(T, i, c) = 0.0;
-  }
-  // shifted QR to upper triangular (Schur) form
-  const double eps = std::numeric_limits<double>::epsilon();
-  int hi = N - 1;
-  int iter = 0, total = 0;
-  while (hi > 0) {
-    int l = hi;
-    while (l > 0) {
-      const double sub = std::abs(H(T, l, l - 1));
-      const double dsum = std::abs(H(T, l - 1, l - 1)) + std::abs(H(T, l, l));
-      if (sub <= eps * (dsum > 0.0 ? dsum : 1.0)) {
-        H(T, l, l - 1) = 0.0;
-        break;
-      }
-      --l;
-    }
-    if (l == hi) {
-      --hi;
-      iter = 0;
-      continue;
-    }
-    if (++total > 100 * N) return false;
-    ++iter;
-    const cd a = H(T, hi - 1, hi - 1), b = H(T, hi - 1, hi), c = H(T, hi, hi - 1),
-             d = H(T, hi, hi);
-    cd mu;
-    if (iter % 11 == 10) {
-      mu = d + std::abs(H(T, hi, hi - 1));  // exceptional shift
-    } else {
-      const cd tr = a + d;
-      const cd det = a * d - b * c;
-      const cd disc = std::sqrt(tr * tr * 0.25 - det);
-      const cd m1 = tr * 0.5 + disc, m2 = tr * 0.5 - disc;
-      mu = (std::abs(m1 - d) < std::abs(m2 - d)) ? m1 : m2;
-    }
-    cd x = H(T, l, l) - mu;
-    cd y = H(T, l + 1, l);
-    for (int k = l; k < hi; ++k) {
-      double cc;
-      cd s;
-      givens_c(x, y, cc, s);
-      // rows k, k+1
-      for (int j = std::max(l, k - 1); j < N; ++j) {
-        const cd t1 = H(T, k, j), t2 = H(T, k + 1, j);
-        H(T, k, j) = cc * t1 + s * t2;
-        H(T, k + 1, j) = -std::conj(s) * t1 + cc * t2;
-      }
-      // columns k, k+1 of T and Z
-      const int rmax = std::min(k + 2, hi);
-      for (int i = 0; i <= rmax; ++i) {
-        const cd t1 = H(T, i, k), t2 = H(T, i, k + 1);
-        H(T, i, k) = cc * t1 + std::conj(s) * t2;
-        H(T, i, k + 1) = -s * t1 + cc * t2;
-      }
-      for (int i = 0; i < N; ++i) {
-        const cd t1 = H(Z, i, k), t2 = H(Z, i, k + 1);
-        H(Z, i, k) = cc * t1 + std::conj(s) * t2;
-        H(Z, i, k + 1) = -s * t1 + cc * t2;
-      }
-      if (k + 1 < hi) {
-        x = H(T, k + 1, k);
-        y = H(T, k + 2, k);
-      }
-    }
-  }
-  for (int i = 0; i < N; ++i) w[i] = H(T, i, i);
-  // eigenvectors of the triangular factor, then back-transform
-  double tn = 0.0;
-  for (int j = 0; j < N; ++j)
-    for (int i = 0; i <= j; ++i) tn = std::max(tn, std::abs(H(T, i, j)));
-  const double small = std::max(tn, 1e-300) * eps;
-  std::vector<cd> x(N);
+  SchurC sc;
+  if (!sc.factor(A, N)) return false;
   for (int e = 0; e < N; ++e) {
-    std::fill(x.begin(), x.end(), cd(0.0));
-    x[e] = 1.0;
-    const cd lam = H(T, e, e);
-    for (int r = e - 1; r >= 0; --r) {
-      cd s = 0.0;
-      for (int t = r + 1; t <= e; ++t) s += H(T, r, t) * x[t];
-      cd den = H(T, r, r) - lam;
-      if (std::abs(den) < small) den = small;
-      x[r] = -s / den;
-    }
-    double nrm = 0.0;
-    for (int i = 0; i < N; ++i) {
-      cd s = 0.0;
-      for (int t = 0; t <= e; ++t) s += H(Z, i, t) * x[t];
-      V[(size_t)e * N + i] = s;
-      nrm += std::norm(s);
-    }
-    nrm = std::sqrt(nrm);
-    if (nrm > 0.0)
-      for (int i = 0; i < N; ++i) V[(size_t)e * N + i] /= nrm;
+    w[e] = sc.value(e);
+    sc.vector(e, &V[(size_t)e * N]);
   }
   return true;
 }
@@ -333,8 +372,10 @@ int harmonic_ritz(const double* G, const double* M, int rows, int cols, int k, d
       Tm[(size_t)j * cols + i] = s / R[(size_t)i * cols + i];
     }
   }
-  std::vector<cd> mu, W;
-  if (!eig_real(Tm.data(), cols, mu, W)) return 0;
+  SchurC sc;
+  if (!sc.factor(Tm.data(), cols)) return 0;
+  std::vector<cd> mu(cols), wv(cols);
+  for (int e = 0; e < cols; ++e) mu[e] = sc.value(e);
   // order: largest |mu| first (smallest |theta|), stable in index
   std::vector<int> ord(cols);
   std::iota(ord.begin(), ord.end(), 0);
@@ -359,7 +400,8 @@ int harmonic_ritz(const double* G, const double* M, int rows, int cols, int k, d
     const double am = std::abs(m);
     const bool is_complex = std::abs(m.imag()) > 1e3 * 2.220446049250313e-16 * am && am > 0.0;
     used[idx] = true;
-    back(&W[(size_t)idx * cols], z);
+    sc.vector(idx, wv.data());
+    back(wv.data(), z);
     if (is_complex) {
       if (kout + 2 > k) break;
       int partner = -1;
