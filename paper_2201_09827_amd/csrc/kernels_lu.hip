@@ -591,8 +591,8 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict
 
 // ---- trailing update on the matrix cores ----------------------------------
 
-typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -602,14 +602,17 @@ constexpr int kKP = kMaxNb + 8;  // padded LDS row of -L21 and U12^T (elements, 
 template <class F>
 struct Mfma;
 
+// gfx950's 16-deep fp16 / bf16 products: A rows i = lane % 32 with k =
+// 8 (lane / 32) + e, B columns j = lane % 32 with the same k, e = 0 .. 7 (one
+// 16-byte LDS read per operand); the 32 x 32 fp32 result as with the 8-deep
+// form
 template <>
 struct Mfma<Fp16> {
-  // 8-deep k chunk: A rows i = lane%32, k = 4*(lane/32)+e; B cols j = lane%32
   static __device__ __forceinline__ float16_t step(const _Float16* a, const _Float16* b,
                                                    float16_t acc) {
-    const half4_t av = *reinterpret_cast<const half4_t*>(a);
-    const half4_t bv = *reinterpret_cast<const half4_t*>(b);
-    return __builtin_amdgcn_mfma_f32_32x32x8f16(av, bv, acc, 0, 0, 0);
+    const half8_t av = *reinterpret_cast<const half8_t*>(a);
+    const half8_t bv = *reinterpret_cast<const half8_t*>(b);
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc, 0, 0, 0);
   }
 };
 
@@ -617,9 +620,10 @@ template <>
 struct Mfma<Bf16> {
   static __device__ __forceinline__ float16_t step(const uint16_t* a, const uint16_t* b,
                                                    float16_t acc) {
-    const short4_t av = *reinterpret_cast<const short4_t*>(a);
-    const short4_t bv = *reinterpret_cast<const short4_t*>(b);
-    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+    bf16x8_t av, bv;
+    __builtin_memcpy(&av, a, 16);
+    __builtin_memcpy(&bv, b, 16);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
   }
 };
 
@@ -755,8 +759,8 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
 #pragma unroll
-    for (int kk = 0; kk < kMaxNb / 8; ++kk) {
-      const int ko = kk * 8 + 4 * hi;
+    for (int kk = 0; kk < kMaxNb / 16; ++kk) {
+      const int ko = kk * 16 + 8 * hi;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         acc[i] = Mfma<F>::step(&As[wr + i * 32 + l32][ko], &Bt[wc + l32][ko], acc[i]);
