@@ -374,6 +374,10 @@ struct gmresir_ctx {
   uint64_t *cvw = nullptr, *cpx = nullptr, *cctrl = nullptr;  // its exchange words
   int64_t cycles_run = 0;        // cycles run as one persistent launch
   int64_t cycle_fallbacks = 0;  // persistent launches that gave up (device shared)
+  // after a launch gave up, the next cycles run as separate launches
+  // without trying (cycle_wait of them), the wait doubling with every
+  // further give-up and reset by a launch that runs
+  int cycle_backoff = 0, cycle_wait = 0;
   // the persistent launch's arrival bound (GMRESIR_CYCLE_ARRIVE_US at handle
   // creation: a test hook; 0 makes every launch give up and fall back)
   int cycle_arrive_us = gir::kCycleArriveUs;
@@ -1819,6 +1823,10 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     // all its workgroups resident together: the device is shared) wrote
     // nothing, so the steps then run as separate launches
     bool one_launch = cycle_eligible(h);
+    if (one_launch && h->cycle_wait > 0) {
+      --h->cycle_wait;
+      one_launch = false;
+    }
     if (one_launch)
       GIR_TRY(run_cycle(h, kc, nsteps));
     else
@@ -1848,11 +1856,14 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     if (one_launch && gate != gir::kCycleGo) {
       h->trec.resize(trec0);
       ++h->cycle_fallbacks;
+      h->cycle_backoff = std::min(64, std::max(1, 2 * h->cycle_backoff));
+      h->cycle_wait = h->cycle_backoff;
       one_launch = false;
       GIR_TRY(run_steps());
       GIR_TRY(fetch_state());
     } else if (one_launch) {
       ++h->cycles_run;
+      h->cycle_backoff = 0;
     }
     if (fin.abort) {
       set_error("triangular solve: a device-side wait exceeded its bound");
