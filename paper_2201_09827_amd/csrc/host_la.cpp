@@ -161,156 +161,261 @@ inline void givens_c(cd x, cd y, double& c, cd& s) {
 
 namespace {
 
-// Complex Schur form T = Z^H A Z of a real matrix: Householder reduction to
-// upper Hessenberg form (real arithmetic), then single-shift QR with
-// Wilkinson shifts (an
-// exceptional shift every 11th iteration).  Z is not accumulated: its
-// factors (the reflectors and every sweep's rotations) are kept, and
-// vector(e) forms only the eigenvectors asked for (back substitution on T,
-// then Z applied factor by factor), which costs far less than carrying Z
-// through every sweep when a few vectors are wanted.
-struct SchurC {
-  struct Rot {
-    int k;
-    double c;
-    cd s;
+// Real Schur form T = Z^T A Z of a real matrix (T quasi upper triangular:
+// 1 x 1 blocks for the real eigenvalues, 2 x 2 blocks for the complex
+// conjugate pairs): Householder reduction to upper Hessenberg form, then
+// Francis double-shift QR sweeps (3-element reflectors chasing the bulge,
+// a 2-element reflector at the end of the window; an ad hoc shift on the
+// 10th and 20th iteration without deflation), every 2 x 2 block with real
+// eigenvalues split into two 1 x 1 blocks.  Z is not accumulated: its
+// factors (the reflectors, in the order applied) are kept, and vector(e)
+// forms only the eigenvectors asked for: back substitution on T (2 x 2
+// blocks solved directly), then Z applied factor by factor.
+struct SchurR {
+  struct Refl {
+    int k;       // first row / column
+    int len;     // 2 or 3
+    double v[3];
+    double beta;  // P = I - beta v v^T (0: identity)
   };
   int N = 0;
-  std::vector<cd> T;          // column-major
-  std::vector<double> hv;     // reflector c: hv[c * N + i] for i > c (real: A is real)
-  std::vector<double> hb;     // its beta (0: no reflection)
-  std::vector<Rot> rots;      // in the order they were applied
+  std::vector<double> T;   // column-major
+  std::vector<double> hv;  // Hessenberg reflector c: hv[c * N + i] for i > c
+  std::vector<double> hb;
+  std::vector<Refl> refl;
+  std::vector<cd> w;       // eigenvalues, in the order of T's diagonal
   double small = 0.0;
 
-  cd& t(int i, int j) { return T[(size_t)j * N + i]; }
-  const cd& t(int i, int j) const { return T[(size_t)j * N + i]; }
+  double& t(int i, int j) { return T[(size_t)j * N + i]; }
+  double t(int i, int j) const { return T[(size_t)j * N + i]; }
+
+  // P u = alpha e_1 for u of length len (beta = 0 when u = 0)
+  static Refl house(int k, int len, const double* u) {
+    Refl r{k, len, {0.0, 0.0, 0.0}, 0.0};
+    double nrm = 0.0;
+    for (int i = 0; i < len; ++i) nrm += u[i] * u[i];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) return r;
+    const double alpha = (u[0] >= 0.0) ? -nrm : nrm;
+    for (int i = 0; i < len; ++i) r.v[i] = u[i];
+    r.v[0] -= alpha;
+    double vn = 0.0;
+    for (int i = 0; i < len; ++i) vn += r.v[i] * r.v[i];
+    r.beta = (vn > 0.0) ? 2.0 / vn : 0.0;
+    return r;
+  }
+
+  // T <- P T P on rows k .. k+len-1 (columns c0 .. N-1) and columns
+  // k .. k+len-1 (rows 0 .. r1); the transformation is recorded
+  void apply(const Refl& p, int c0, int r1) {
+    if (p.beta == 0.0) return;
+    for (int j = c0; j < N; ++j) {
+      double d = 0.0;
+      for (int i = 0; i < p.len; ++i) d += p.v[i] * t(p.k + i, j);
+      d *= p.beta;
+      for (int i = 0; i < p.len; ++i) t(p.k + i, j) -= d * p.v[i];
+    }
+    for (int i = 0; i <= r1; ++i) {
+      double d = 0.0;
+      for (int q = 0; q < p.len; ++q) d += t(i, p.k + q) * p.v[q];
+      d *= p.beta;
+      for (int q = 0; q < p.len; ++q) t(i, p.k + q) -= d * p.v[q];
+    }
+    refl.push_back(p);
+  }
 
   bool factor(const double* A, int n) {
     N = n;
-    // Householder reduction to upper Hessenberg form in real arithmetic
-    std::vector<double> H(A, A + (size_t)N * N);
-    auto h = [&](int i, int j) -> double& { return H[(size_t)j * N + i]; };
+    T.assign(A, A + (size_t)N * N);
     hv.assign((size_t)N * N, 0.0);
     hb.assign(N, 0.0);
-    rots.clear();
+    refl.clear();
+    w.assign(N, cd(0.0));
+    // Householder reduction to upper Hessenberg form
     for (int c = 0; c + 2 < N; ++c) {
       double nrm = 0.0;
-      for (int i = c + 1; i < N; ++i) nrm += h(i, c) * h(i, c);
+      for (int i = c + 1; i < N; ++i) nrm += t(i, c) * t(i, c);
       nrm = std::sqrt(nrm);
       if (nrm == 0.0) continue;
-      const double x0 = h(c + 1, c);
+      const double x0 = t(c + 1, c);
       const double alpha = (x0 >= 0.0) ? -nrm : nrm;
       double* v = &hv[(size_t)c * N];
-      for (int i = c + 1; i < N; ++i) v[i] = h(i, c);
+      for (int i = c + 1; i < N; ++i) v[i] = t(i, c);
       v[c + 1] -= alpha;
       double vn = 0.0;
       for (int i = c + 1; i < N; ++i) vn += v[i] * v[i];
       if (vn == 0.0) continue;
       const double beta = 2.0 / vn;
       hb[c] = beta;
-      // H = (I - beta v v^T) H (I - beta v v^T)
       for (int j = 0; j < N; ++j) {
         double d = 0.0;
-        for (int i = c + 1; i < N; ++i) d += v[i] * h(i, j);
+        for (int i = c + 1; i < N; ++i) d += v[i] * t(i, j);
         d *= beta;
-        for (int i = c + 1; i < N; ++i) h(i, j) -= d * v[i];
+        for (int i = c + 1; i < N; ++i) t(i, j) -= d * v[i];
       }
       for (int i = 0; i < N; ++i) {
         double d = 0.0;
-        for (int j = c + 1; j < N; ++j) d += h(i, j) * v[j];
+        for (int j = c + 1; j < N; ++j) d += t(i, j) * v[j];
         d *= beta;
-        for (int j = c + 1; j < N; ++j) h(i, j) -= d * v[j];
+        for (int j = c + 1; j < N; ++j) t(i, j) -= d * v[j];
       }
-      for (int i = c + 2; i < N; ++i) h(i, c) = 0.0;
+      for (int i = c + 2; i < N; ++i) t(i, c) = 0.0;
     }
-    T.assign((size_t)N * N, cd(0.0));
-    for (size_t i = 0; i < (size_t)N * N; ++i) T[i] = H[i];
+    double tn = 0.0;
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) tn = std::max(tn, std::fabs(t(i, j)));
     const double eps = std::numeric_limits<double>::epsilon();
+    small = std::max(tn, 1e-300) * eps;
     int hi = N - 1;
     int iter = 0, total = 0;
-    while (hi > 0) {
+    while (hi >= 0) {
+      // deflation: the active window is l .. hi
       int l = hi;
       while (l > 0) {
-        const double sub = std::abs(t(l, l - 1));
-        const double dsum = std::abs(t(l - 1, l - 1)) + std::abs(t(l, l));
-        if (sub <= eps * (dsum > 0.0 ? dsum : 1.0)) {
+        const double sub = std::fabs(t(l, l - 1));
+        double dsum = std::fabs(t(l - 1, l - 1)) + std::fabs(t(l, l));
+        if (dsum == 0.0) dsum = tn;
+        if (sub <= eps * dsum) {
           t(l, l - 1) = 0.0;
           break;
         }
         --l;
       }
       if (l == hi) {
+        w[hi] = t(hi, hi);
         --hi;
+        iter = 0;
+        continue;
+      }
+      if (l == hi - 1) {
+        // a 2 x 2 block: a complex pair stays, real eigenvalues are split
+        const double a = t(hi - 1, hi - 1), b = t(hi - 1, hi), c = t(hi, hi - 1),
+                     d = t(hi, hi);
+        const double p = 0.5 * (a - d);
+        const double disc = p * p + b * c;
+        if (disc >= 0.0) {
+          const double sq = std::sqrt(disc);
+          const double l1 = 0.5 * (a + d) + (p >= 0.0 ? sq : -sq);
+          // an eigenvector of the block for l1, the larger of two forms
+          double u[2] = {b, l1 - a};
+          const double u2[2] = {l1 - d, c};
+          if (std::hypot(u2[0], u2[1]) > std::hypot(u[0], u[1])) {
+            u[0] = u2[0];
+            u[1] = u2[1];
+          }
+          apply(house(hi - 1, 2, u), hi - 1, hi);
+          t(hi, hi - 1) = 0.0;
+          w[hi - 1] = t(hi - 1, hi - 1);
+          w[hi] = t(hi, hi);
+        } else {
+          const double re = 0.5 * (a + d), im = std::sqrt(-disc);
+          w[hi - 1] = cd(re, im);
+          w[hi] = cd(re, -im);
+        }
+        hi -= 2;
         iter = 0;
         continue;
       }
       if (++total > 100 * N) return false;
       ++iter;
-      const cd a = t(hi - 1, hi - 1), b = t(hi - 1, hi), c = t(hi, hi - 1), d = t(hi, hi);
-      cd mu;
-      if (iter % 11 == 10) {
-        mu = d + std::abs(t(hi, hi - 1));  // exceptional shift
+      double s, q;
+      if (iter == 10 || iter == 20) {
+        const double ex = std::fabs(t(hi, hi - 1)) + std::fabs(t(hi - 1, hi - 2));
+        s = 1.5 * ex;
+        q = ex * ex;
       } else {
-        const cd tr = a + d;
-        const cd det = a * d - b * c;
-        const cd disc = std::sqrt(tr * tr * 0.25 - det);
-        const cd m1 = tr * 0.5 + disc, m2 = tr * 0.5 - disc;
-        mu = (std::abs(m1 - d) < std::abs(m2 - d)) ? m1 : m2;
+        s = t(hi - 1, hi - 1) + t(hi, hi);
+        q = t(hi - 1, hi - 1) * t(hi, hi) - t(hi - 1, hi) * t(hi, hi - 1);
       }
-      cd x = t(l, l) - mu;
-      cd y = t(l + 1, l);
-      for (int k = l; k < hi; ++k) {
-        double cc;
-        cd s;
-        givens_c(x, y, cc, s);
-        // rows k, k+1, then columns k, k+1
-        for (int j = std::max(l, k - 1); j < N; ++j) {
-          const cd t1 = t(k, j), t2 = t(k + 1, j);
-          t(k, j) = cc * t1 + s * t2;
-          t(k + 1, j) = -std::conj(s) * t1 + cc * t2;
+      // the first column of (T - r1)(T - r2) on the window
+      double x = t(l, l) * t(l, l) + t(l, l + 1) * t(l + 1, l) - s * t(l, l) + q;
+      double y = t(l + 1, l) * (t(l, l) + t(l + 1, l + 1) - s);
+      double z = t(l + 1, l) * t(l + 2, l + 1);
+      for (int k = l; k <= hi - 2; ++k) {
+        const double u[3] = {x, y, z};
+        apply(house(k, 3, u), std::max(l, k - 1), std::min(k + 3, hi));
+        if (k > l) {
+          t(k + 1, k - 1) = 0.0;
+          t(k + 2, k - 1) = 0.0;
         }
-        const int rmax = std::min(k + 2, hi);
-        for (int i = 0; i <= rmax; ++i) {
-          const cd t1 = t(i, k), t2 = t(i, k + 1);
-          t(i, k) = cc * t1 + std::conj(s) * t2;
-          t(i, k + 1) = -s * t1 + cc * t2;
-        }
-        rots.push_back({k, cc, s});
-        if (k + 1 < hi) {
-          x = t(k + 1, k);
-          y = t(k + 2, k);
-        }
+        x = t(k + 1, k);
+        y = t(k + 2, k);
+        if (k < hi - 2) z = t(k + 3, k);
       }
+      const double u[2] = {x, y};
+      apply(house(hi - 1, 2, u), hi - 2, hi);
+      t(hi, hi - 2) = 0.0;
     }
-    double tn = 0.0;
-    for (int j = 0; j < N; ++j)
-      for (int i = 0; i <= j; ++i) tn = std::max(tn, std::abs(t(i, j)));
-    small = std::max(tn, 1e-300) * eps;
     return true;
   }
 
-  cd value(int e) const { return t(e, e); }
+  cd value(int e) const { return w[e]; }
 
-  // the unit eigenvector of eigenvalue e: T x = lambda x by back
-  // substitution (x_e = 1), then Z x
+  // the unit eigenvector of eigenvalue e
   void vector(int e, cd* out) const {
     std::vector<cd> x(N, cd(0.0));
-    x[e] = 1.0;
-    const cd lam = t(e, e);
-    for (int r = e - 1; r >= 0; --r) {
-      cd s = 0.0;
-      for (int q = r + 1; q <= e; ++q) s += t(r, q) * x[q];
-      cd den = t(r, r) - lam;
-      if (std::abs(den) < small) den = small;
-      x[r] = -s / den;
+    const cd lam = w[e];
+    int top;  // the last row already set
+    if (e > 0 && t(e, e - 1) != 0.0) {
+      // second row of a complex 2 x 2 block
+      top = e - 1;
+    } else if (e + 1 < N && t(e + 1, e) != 0.0) {
+      top = e;
+    } else {
+      top = -1;
     }
-    // Z = P_0 .. P_{N-3} G_1 .. G_R: the rotations last to first, then the
-    // reflectors last to first
-    for (size_t q = rots.size(); q-- > 0;) {
-      const Rot& g = rots[q];
-      const cd x1 = x[g.k], x2 = x[g.k + 1];
-      x[g.k] = g.c * x1 - g.s * x2;
-      x[g.k + 1] = std::conj(g.s) * x1 + g.c * x2;
+    int r;
+    if (top >= 0) {
+      // the block's own eigenvector, the larger of two forms
+      const double a = t(top, top), b = t(top, top + 1), c = t(top + 1, top),
+                   d = t(top + 1, top + 1);
+      cd u0 = b, u1 = lam - a;
+      const cd v0 = lam - d, v1 = c;
+      if (std::norm(v0) + std::norm(v1) > std::norm(u0) + std::norm(u1)) {
+        u0 = v0;
+        u1 = v1;
+      }
+      x[top] = u0;
+      x[top + 1] = u1;
+      r = top - 1;
+    } else {
+      x[e] = 1.0;
+      r = e - 1;
+    }
+    const int last = (top >= 0) ? top + 1 : e;
+    while (r >= 0) {
+      if (r > 0 && t(r, r - 1) != 0.0) {
+        // rows r-1, r form a 2 x 2 block: solve it for both
+        cd s1 = 0.0, s2 = 0.0;
+        for (int q = r + 1; q <= last; ++q) {
+          s1 += t(r - 1, q) * x[q];
+          s2 += t(r, q) * x[q];
+        }
+        const cd m11 = t(r - 1, r - 1) - lam, m12 = t(r - 1, r), m21 = t(r, r - 1),
+                 m22 = t(r, r) - lam;
+        cd det = m11 * m22 - m12 * m21;
+        if (std::abs(det) < small * small) det = small * small;
+        x[r - 1] = (-s1 * m22 + m12 * s2) / det;
+        x[r] = (-m11 * s2 + m21 * s1) / det;
+        r -= 2;
+      } else {
+        cd s = 0.0;
+        for (int q = r + 1; q <= last; ++q) s += t(r, q) * x[q];
+        cd den = t(r, r) - lam;
+        if (std::abs(den) < small) den = small;
+        x[r] = -s / den;
+        r -= 1;
+      }
+    }
+    // Z = H_0 .. H_{N-3} P_1 .. P_R: the sweep reflectors last to first,
+    // then the Hessenberg reflectors last to first
+    for (size_t q = refl.size(); q-- > 0;) {
+      const Refl& p = refl[q];
+      if (p.beta == 0.0) continue;
+      cd d = 0.0;
+      for (int i = 0; i < p.len; ++i) d += p.v[i] * x[p.k + i];
+      d *= p.beta;
+      for (int i = 0; i < p.len; ++i) x[p.k + i] -= d * p.v[i];
     }
     for (int c = N - 3; c >= 0; --c) {
       if (hb[c] == 0.0) continue;
@@ -333,7 +438,7 @@ bool eig_real(const double* A, int N, std::vector<cd>& w, std::vector<cd>& V) {
   w.assign(N, cd(0.0));
   V.assign((size_t)N * N, cd(0.0));
   if (N == 0) return true;
-  SchurC sc;
+  SchurR sc;
   if (!sc.factor(A, N)) return false;
   for (int e = 0; e < N; ++e) {
     w[e] = sc.value(e);
@@ -372,7 +477,7 @@ int harmonic_ritz(const double* G, const double* M, int rows, int cols, int k, d
       Tm[(size_t)j * cols + i] = s / R[(size_t)i * cols + i];
     }
   }
-  SchurC sc;
+  SchurR sc;
   if (!sc.factor(Tm.data(), cols)) return 0;
   std::vector<cd> mu(cols), wv(cols);
   for (int e = 0; e < cols; ++e) mu[e] = sc.value(e);

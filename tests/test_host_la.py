@@ -147,6 +147,20 @@ def test_real_eigenproblem(driver):
         A = g.standard_normal((N, N))
         cases.append(_fmt("eig", N, A))
         mats.append(A)
+    # structured cases reaching every branch of the real Schur solver: all
+    # eigenvalues real (symmetric), already triangular, a repeated
+    # eigenvalue, a companion matrix with complex roots, the zero matrix
+    S = g.standard_normal((12, 12))
+    extra = [S + S.T, np.triu(g.standard_normal((7, 7)))]
+    Qr, _ = np.linalg.qr(g.standard_normal((5, 5)))
+    extra.append(Qr @ np.diag([2.0, 2.0, 3.0, -1.0, 2.0]) @ Qr.T)
+    C = np.zeros((6, 6))
+    C[1:, :-1] = np.eye(5)
+    C[:, -1] = -np.array([1.0, 0.0, 2.0, 0.0, 3.0, 1.0])
+    extra += [C, np.zeros((3, 3))]
+    for A in extra:
+        cases.append(_fmt("eig", A.shape[0], A))
+        mats.append(A)
     # a matrix with a known spectrum: block diagonal rotation-scalings
     B = np.zeros((4, 4))
     B[:2, :2] = [[1.0, -2.0], [2.0, 1.0]]
