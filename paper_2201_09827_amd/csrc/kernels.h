@@ -66,7 +66,7 @@ void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* 
 void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const float* v32,
                     const double* v64, double* t, const CycleState* gate, int step,
                     hipStream_t s);
-// T[:, r] = A_u[permA rows] Y[:, r], r < nr <= 8 (fp64 Y and T, leading
+// T[:, r] = A_u[permA rows] Y[:, r], r < nr <= 16 (fp64 Y and T, leading
 // dimensions ldy, ldt; Y's columns 16-byte aligned), fp64 accumulation
 void launch_gemv_au_multi(const float* Au, int64_t ld, const int* permA, int n, const double* Y,
                           int64_t ldy, int nr, double* T, int64_t ldt, hipStream_t s);
@@ -124,12 +124,12 @@ void launch_trsv_upper(const void* S, int64_t ld, const int* permS, int store, i
                        double* out64, float* out32, uint64_t* xw, int epoch,
                        const CycleState* gate, int step, int* abort, hipStream_t s,
                        const TrsvDots* dots = nullptr);
-// the lower (upper = false) or upper solve for nr <= 8 right-hand sides as
-// nr independent solves in one launch (one grid row each): in / out
+// the lower (upper = false) or upper solve for nr <= 16 right-hand sides as
+// nr independent solves in one launch (block-major grid): in / out
 // column-major (ldi / ldo); the upper solve writes scale * solution, the
 // lower solve its unscaled solution (scale is ignored);
 // xw holds nr slots of xstride >= 2 * ceil(n/128) * 128 tagged words
-constexpr int kTrsvMaxRhs = 8;
+constexpr int kTrsvMaxRhs = 16;
 void launch_trsv_cols(const void* S, int64_t ld, const int* permS, int store, int n, bool upper,
                       const double* in, int64_t ldi, int nr, const double* Dinv, double* out,
                       int64_t ldo, double scale, uint64_t* xw, int64_t xstride, int epoch,

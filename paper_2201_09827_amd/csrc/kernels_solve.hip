@@ -92,25 +92,36 @@ __global__ __launch_bounds__(256) void k_gemv_au(const float* __restrict__ Au, i
   if (lane == 0) t[row] = s;
 }
 
-// T[:, r] = A_u[permA] Y[:, r] for NR fp64 columns of Y (ld ldy) at once:
-// one wave per row, the row read once for all of them (the recycle set-up)
-// T[:, r] = A_u Y[:, r] for nr <= NR right-hand sides: one wave takes
-// kMultiRows rows, so each 4-column chunk of Y (NR fp64 values per column)
-// is read once for all of them; fp64 accumulation per row and column.
-constexpr int kMultiRows = 4;
-template <int NR>
-__global__ __launch_bounds__(256) void k_gemv_au_multi(const float* __restrict__ Au, int64_t ld,
-                                                       const int* __restrict__ permA, int n,
-                                                       const double* __restrict__ Y,
-                                                       int64_t ldy, int nr,
-                                                       double* __restrict__ T, int64_t ldt) {
-  const int row0 = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kMultiRows;
-  const int lane = threadIdx.x % kWave;
-  if (row0 >= n) return;
+// T[:, r] = A_u[permA] Y[:, r] for nr <= NR fp64 columns of Y (ld ldy) at
+// once (the recycle set-up): one wave takes kMultiRows rows and each lane the
+// columns 4 lane + 256 i, summed per row and column in fp64 in that order and
+// then over the wave, as k_gemv_au sums one column.  Each chunk of kChunk
+// columns of Y is staged once per workgroup in LDS (two buffers, one barrier
+// per chunk) instead of being read by every wave from the cache: with eight
+// or more columns those reads, four times the bytes of A_u, had set the pace.
+// The next chunk's rows of A_u and of Y are loaded before the current chunk's
+// multiply-adds; what remains exposed is one memory latency per chunk, so
+// wider chunks pay where the registers allow them.
+constexpr int kMultiThreads = 512;
+template <int NR, int kMultiRows, int kChunk>
+__global__ __launch_bounds__(kMultiThreads) void k_gemv_au_multi(
+    const float* __restrict__ Au, int64_t ld, const int* __restrict__ permA, int n,
+    const double* __restrict__ Y, int64_t ldy, int nr, double* __restrict__ T, int64_t ldt) {
+  constexpr int kRowThreads = kChunk / 2;               // threads staging one row of a chunk
+  constexpr int kPass = kMultiThreads / kRowThreads;    // chunk rows staged per pass
+  static_assert(NR % kPass == 0, "the staging covers whole passes of rows");
+  constexpr int kStage = NR / kPass;                    // double2 per thread and chunk
+  constexpr int kSub = kChunk / 256;                    // float4 per lane, row and chunk
+  __shared__ double ysh[2][NR][kChunk];
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave;
+  const int row0 = (blockIdx.x * (kMultiThreads / kWave) + tid / kWave) * kMultiRows;
   const float* a[kMultiRows];
 #pragma unroll
   for (int q = 0; q < kMultiRows; ++q) {
-    const int rw = min(row0 + q, n - 1);  // rows beyond n repeat the last one (not stored)
+    // rows beyond n repeat the last one (not stored); a wave wholly beyond n
+    // still takes part in the staging and the barriers
+    const int rw = min(row0 + q, n - 1);
     a[q] = Au + (int64_t)(permA ? permA[rw] : rw) * ld;
   }
   double acc[kMultiRows][NR];
@@ -119,24 +130,78 @@ __global__ __launch_bounds__(256) void k_gemv_au_multi(const float* __restrict__
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[q][r] = 0.0;
   const int n4 = n & ~3;
-  for (int c = lane * 4; c < n4; c += 256) {
-    float4 x[kMultiRows];
+  const int nchunk = (n4 + kChunk - 1) / kChunk;
+  // staging: thread t moves the double2 at column 2 (t % kRowThreads) of rows
+  // t / kRowThreads + kPass e of the chunk (columns at or past n4 enter as zero)
+  double2 st[kStage];
+  auto load_stage = [&](int c0) {
 #pragma unroll
-    for (int q = 0; q < kMultiRows; ++q) x[q] = *reinterpret_cast<const float4*>(a[q] + c);
+    for (int e = 0; e < kStage; ++e) {
+      const int r = tid / kRowThreads + kPass * e;
+      const int c = c0 + 2 * (tid % kRowThreads);
+      const double* src = Y + (int64_t)min(r, nr - 1) * ldy + min(c, max(n4 - 2, 0));
+      const double2 v = *reinterpret_cast<const double2*>(src);
+      st[e] = (c < n4) ? v : make_double2(0.0, 0.0);
+    }
+  };
+  auto store_stage = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const double* y = Y + (int64_t)min(r, nr - 1) * ldy + c;
-      const double2 y0 = *reinterpret_cast<const double2*>(y);
-      const double2 y1 = *reinterpret_cast<const double2*>(y + 2);
+    for (int e = 0; e < kStage; ++e)
+      *reinterpret_cast<double2*>(
+          &ysh[buf][tid / kRowThreads + kPass * e][2 * (tid % kRowThreads)]) = st[e];
+  };
+  auto load_a = [&](int c0, float4 (&x)[kSub][kMultiRows]) {
 #pragma unroll
-      for (int q = 0; q < kMultiRows; ++q) {
-        acc[q][r] = fma((double)x[q].x, y0.x, acc[q][r]);
-        acc[q][r] = fma((double)x[q].y, y0.y, acc[q][r]);
-        acc[q][r] = fma((double)x[q].z, y1.x, acc[q][r]);
-        acc[q][r] = fma((double)x[q].w, y1.y, acc[q][r]);
+    for (int u = 0; u < kSub; ++u) {
+      const int c = min(c0 + 256 * u + lane * 4, max(n4 - 4, 0));
+#pragma unroll
+      for (int q = 0; q < kMultiRows; ++q) x[u][q] = *reinterpret_cast<const float4*>(a[q] + c);
+    }
+  };
+  if (nchunk > 0) {
+    float4 x[kSub][kMultiRows];
+    load_stage(0);
+    load_a(0, x);
+    store_stage(0);
+    __syncthreads();
+    for (int i = 0; i < nchunk; ++i) {
+      const int c0 = i * kChunk;
+      const bool more = i + 1 < nchunk;
+      float4 xn[kSub][kMultiRows];
+      if (more) {
+        load_stage(c0 + kChunk);
+        load_a(c0 + kChunk, xn);
       }
+      const double(*yb)[kChunk] = ysh[i & 1];
+#pragma unroll
+      for (int u = 0; u < kSub; ++u) {
+        if (c0 + 256 * u + lane * 4 < n4) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double2 y0 = *reinterpret_cast<const double2*>(&yb[r][256 * u + lane * 4]);
+            const double2 y1 =
+                *reinterpret_cast<const double2*>(&yb[r][256 * u + lane * 4 + 2]);
+#pragma unroll
+            for (int q = 0; q < kMultiRows; ++q) {
+              acc[q][r] = fma((double)x[u][q].x, y0.x, acc[q][r]);
+              acc[q][r] = fma((double)x[u][q].y, y0.y, acc[q][r]);
+              acc[q][r] = fma((double)x[u][q].z, y1.x, acc[q][r]);
+              acc[q][r] = fma((double)x[u][q].w, y1.y, acc[q][r]);
+            }
+          }
+        }
+      }
+      if (more) {
+        store_stage((i + 1) & 1);
+#pragma unroll
+        for (int u = 0; u < kSub; ++u)
+#pragma unroll
+          for (int q = 0; q < kMultiRows; ++q) x[u][q] = xn[u][q];
+      }
+      __syncthreads();
     }
   }
+  if (row0 >= n) return;
   for (int cc = n4 + lane; cc < n; cc += kWave) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -548,14 +613,40 @@ __device__ __forceinline__ bool get_tagged_block(const uint64_t* xw, int base, u
   }
 }
 
-// Several right-hand sides are independent solves, one per grid row
-// (blockIdx.y = column): column c reads in + c * cs.in and writes y + c * cs.y,
-// out64 + c * cs.out, exchanging its values through xw + c * cs.xw.  A block
-// waits only for blocks of its own column with a smaller blockIdx.x, which
-// were dispatched before it.
+// Several right-hand sides are independent solves in one launch: column c
+// reads in + c * cs.in and writes y + c * cs.y, out64 + c * cs.out, exchanging
+// its values through xw + c * cs.xw.  The grid runs over groups of eight
+// block positions: workgroup 8 ncols g + 8 c + e is position 8 g + e of
+// column c (workgroups past the last position return at once).  Two
+// properties follow.  The chains of all columns advance together when the
+// launch holds more workgroups than can be resident (a column-major order
+// started the later columns only as the earlier ones drained: 231 us for
+// eight columns at n = 8192, against 115 us for one).  And since workgroup w
+// runs on XCD w mod 8, every column's block at one position runs on the same
+// XCD and reads that block row of the factor through one L2 (ten columns:
+// 165 us, against 185 us in plain position-major order).  A block waits only
+// for blocks of its own column at earlier positions, which have smaller
+// workgroup indices and were dispatched before it.  With one column the
+// order is the identity.
 struct ColStrides {
   int64_t in, y, out, xw;
+  int ncols = 1;
 };
+
+// (position in the chain, column) of this workgroup; false past the last
+// position
+__device__ __forceinline__ bool col_block(const ColStrides& cs, int nb, int& bx, int& col) {
+  const int g8 = 8 * cs.ncols;
+  const int grp = (int)blockIdx.x / g8, rem = (int)blockIdx.x - grp * g8;
+  col = rem >> 3;
+  bx = grp * 8 + (rem & 7);
+  return bx < nb;
+}
+
+inline unsigned col_grid(int n, int ncols) {
+  const unsigned nb = (unsigned)((n + kTS - 1) / kTS);
+  return ncols == 1 ? nb : ((nb + 7) / 8) * 8 * (unsigned)ncols;
+}
 
 // The A-tilde product fused into the lower solve (u = fp32): the launch's
 // workgroups beyond the solve's blocks compute t = A_u[permA] v, eight rows
@@ -812,16 +903,15 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv(const typename F::T* __rest
     if ((threadIdx.x % kWave) == 0) put_tagged(fg.xt, row, t, epoch);
     return;
   }
-  {
-    const int64_t col = blockIdx.y;
-    in += col * cs.in;
-    if (y) y += col * cs.y;
-    if (out64) out64 += col * cs.out;
-    xw += col * cs.xw;
-  }
-  __shared__ TrsvShared sm;
   const int nb = (n + kTS - 1) / kTS;
-  const int blk = kUpper ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  int bx, col;
+  if (!col_block(cs, nb, bx, col)) return;
+  in += (int64_t)col * cs.in;
+  if (y) y += (int64_t)col * cs.y;
+  if (out64) out64 += (int64_t)col * cs.out;
+  xw += (int64_t)col * cs.xw;
+  __shared__ TrsvShared sm;
+  const int blk = kUpper ? nb - 1 - bx : bx;
   TrsvBlock<F, kUpper> tb;
   tb.init(sm, S, ld, permS, n, blk, Dinv);
   double p = 0.0;
@@ -1707,13 +1797,12 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
     float* __restrict__ out32, uint64_t* xw, uint32_t epoch, const CycleState* gate, int step,
     int* abortp, ColStrides cs) {
   if (gated_off(gate, step)) return;
-  {
-    const int64_t col = blockIdx.y;
-    in += col * cs.in;
-    if (y) y += col * cs.y;
-    if (out64) out64 += col * cs.out;
-    xw += col * cs.xw;
-  }
+  int bx, cidx;  // the launch order of k_trsv
+  if (!col_block(cs, (n + kTS - 1) / kTS, bx, cidx)) return;
+  in += (int64_t)cidx * cs.in;
+  if (y) y += (int64_t)cidx * cs.y;
+  if (out64) out64 += (int64_t)cidx * cs.out;
+  xw += (int64_t)cidx * cs.xw;
   __shared__ double red[8][kTB];
   __shared__ double ysh[8][kTB];
   __shared__ double zsh[kTS];
@@ -1722,7 +1811,7 @@ __global__ __launch_bounds__(kTSThreads) void k_trsv_t(
   using T = typename F::T;
   const int nb = (n + kTS - 1) / kTS;
   const int nt = (n + kTB - 1) / kTB;
-  const int blk = kUpperT ? nb - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int blk = kUpperT ? nb - 1 - bx : bx;
   const int r0 = blk * kTS;
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
@@ -2440,16 +2529,25 @@ void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const 
 
 void launch_gemv_au_multi(const float* Au, int64_t ld, const int* permA, int n, const double* Y,
                           int64_t ldy, int nr, double* T, int64_t ldt, hipStream_t s) {
-  const unsigned grid = nblocks(n, 4 * kMultiRows);
-  if (nr <= 2)
-    hipLaunchKernelGGL(k_gemv_au_multi<2>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, Y, ldy,
+  // four rows per wave (each staged entry of Y serves four rows: the LDS
+  // reads keep pace with the fp64 multiply-adds); 512-column chunks where
+  // the registers allow (up to eight columns).  Measured at n = 8192: eight
+  // columns 72 us (87 with 256-column chunks), ten columns in the twelve-
+  // column form 101 us (150 with two rows per wave and sixteen columns)
+  constexpr int kWaves = kMultiThreads / kWave;
+  const dim3 grid(nblocks(n, kWaves * 4)), block(kMultiThreads);
+  if (nr <= 4)
+    hipLaunchKernelGGL((k_gemv_au_multi<4, 4, 256>), grid, block, 0, s, Au, ld, permA, n, Y, ldy,
                        nr, T, ldt);
-  else if (nr <= 4)
-    hipLaunchKernelGGL(k_gemv_au_multi<4>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, Y, ldy,
+  else if (nr <= 8)
+    hipLaunchKernelGGL((k_gemv_au_multi<8, 4, 512>), grid, block, 0, s, Au, ld, permA, n, Y, ldy,
                        nr, T, ldt);
+  else if (nr <= 12)
+    hipLaunchKernelGGL((k_gemv_au_multi<12, 4, 256>), grid, block, 0, s, Au, ld, permA, n, Y,
+                       ldy, nr, T, ldt);
   else
-    hipLaunchKernelGGL(k_gemv_au_multi<8>, dim3(grid), dim3(256), 0, s, Au, ld, permA, n, Y, ldy,
-                       nr, T, ldt);
+    hipLaunchKernelGGL((k_gemv_au_multi<16, 4, 256>), grid, block, 0, s, Au, ld, permA, n, Y,
+                       ldy, nr, T, ldt);
 }
 
 void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const double* v,
@@ -2470,7 +2568,8 @@ void trsv_pair(const void* S, int64_t ld, const int* permS, int n, bool upper, c
                float* out32, uint64_t* xw, int epoch, const CycleState* gate, int step,
                int* abortp, hipStream_t s, int ncols = 1, ColStrides cs = ColStrides{0, 0, 0, 0}) {
   using T = typename F::T;
-  const dim3 grid(nblocks(n, kTS), (unsigned)ncols);
+  const dim3 grid(col_grid(n, ncols));
+  cs.ncols = ncols;
   const T* Sp = reinterpret_cast<const T*>(S);
   if (upper)
     hipLaunchKernelGGL((k_trsv<F, true>), grid, dim3(kTSThreads), 0, s, Sp, ld, permS, n, in,
@@ -2859,8 +2958,8 @@ void launch_trsv_t_cols(const void* S, int64_t ld, const int* permS, int store, 
                         const int* permOut, double* out64, int64_t ldo, uint64_t* xw,
                         int64_t xstride, int epoch, int* abortp, hipStream_t s) {
   if (nr <= 0) return;
-  const dim3 grid(nblocks(n, kTS), (unsigned)nr);
-  const ColStrides cs{ldi, ldy, ldo, xstride};
+  const dim3 grid(col_grid(n, nr));
+  const ColStrides cs{ldi, ldy, ldo, xstride, nr};
 #define GIR_TT(F, U)                                                                          \
   hipLaunchKernelGGL((k_trsv_t<F, U>), grid, dim3(kTSThreads), 0, s,                          \
                      reinterpret_cast<const typename F::T*>(S), ld, permS, n, in, Dinv, Q, y,  \

@@ -1188,7 +1188,7 @@ int atilde(gmresir_ctx* h, const void* vu, const double* v64, double* out64, voi
 }
 
 // C(:, 0:kk) = A-tilde Y(:, 0:kk) for fp64 columns (ld apart): the products
-// with A_u (or A_u^T) for up to eight columns, then the two triangular solves
+// with A_u (or A_u^T) for up to sixteen columns, then the two triangular solves
 // for those columns in one launch each (double-double: one column at a time)
 int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
   const int n = (int)h->n;
@@ -1197,7 +1197,7 @@ int atilde_block(gmresir_ctx* h, const double* Y, int kk, double* C) {
   const double nn = (double)n;
   const double tbytes = 0.5 * nn * (nn + 1.0) * (double)store_bytes(h->store);
   if (h->trans && !h->u64) {
-    // A_u^T one column at a time, then M^-T for up to eight columns at once
+    // A_u^T one column at a time, then M^-T for up to sixteen columns at once
     for (int c0 = 0; c0 < kk; c0 += gir::kTrsvMaxRhs) {
       const int nr = std::min(gir::kTrsvMaxRhs, kk - c0);
       for (int c = 0; c < nr; ++c)
