@@ -270,83 +270,108 @@ __global__ void k_zero_resid_norms(unsigned long long* p) {
   if (threadIdx.x == 2) p[kNormCw] = 0ull;
 }
 
+// One wave takes R rows: each lane's loads of x serve all of them (one wave
+// per row had read x from the cache once per row, as many bytes as A).
+// Every row keeps its own four accumulators, summed in the order of the
+// one-row form, so r does not depend on R.
+constexpr int kResidRows = 4;
+template <int R>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ A, int64_t ld, int n,
                                                   const double* __restrict__ b,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ r,
                                                   unsigned long long* norms) {
-  const int row0 = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
-  const bool rvalid = row0 < n;
-  const int row = rvalid ? row0 : n - 1;  // out-of-range waves recompute a valid row
-  const double* a = A + (int64_t)row * ld;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  double ab0 = 0.0, ab1 = 0.0;  // sum |a| |x| (componentwise backward error)
+  const int row0 = (blockIdx.x * (blockDim.x / kWave) + wave) * R;
+  const double* a[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q)  // rows beyond n recompute the last row (not stored)
+    a[q] = A + (int64_t)min(row0 + q, n - 1) * ld;
+  double acc[R][4], ab[R][2];  // ab: sum |a| |x| (componentwise backward error)
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
+    ab[q][0] = ab[q][1] = 0.0;
+  }
   const int n2 = n & ~1;
   int c = lane * 2;
   for (; c + 384 < n2; c += 512) {
-    const double2 a0 = *reinterpret_cast<const double2*>(a + c);
-    const double2 a1 = *reinterpret_cast<const double2*>(a + c + 128);
-    const double2 a2 = *reinterpret_cast<const double2*>(a + c + 256);
-    const double2 a3 = *reinterpret_cast<const double2*>(a + c + 384);
-    const double2 x0 = *reinterpret_cast<const double2*>(x + c);
-    const double2 x1 = *reinterpret_cast<const double2*>(x + c + 128);
-    const double2 x2 = *reinterpret_cast<const double2*>(x + c + 256);
-    const double2 x3 = *reinterpret_cast<const double2*>(x + c + 384);
-    acc0 = fma(a0.x, x0.x, acc0);
-    acc1 = fma(a0.y, x0.y, acc1);
-    acc2 = fma(a1.x, x1.x, acc2);
-    acc3 = fma(a1.y, x1.y, acc3);
-    acc0 = fma(a2.x, x2.x, acc0);
-    acc1 = fma(a2.y, x2.y, acc1);
-    acc2 = fma(a3.x, x3.x, acc2);
-    acc3 = fma(a3.y, x3.y, acc3);
-    ab0 = fma(fabs(a0.x), fabs(x0.x), ab0);
-    ab1 = fma(fabs(a0.y), fabs(x0.y), ab1);
-    ab0 = fma(fabs(a1.x), fabs(x1.x), ab0);
-    ab1 = fma(fabs(a1.y), fabs(x1.y), ab1);
-    ab0 = fma(fabs(a2.x), fabs(x2.x), ab0);
-    ab1 = fma(fabs(a2.y), fabs(x2.y), ab1);
-    ab0 = fma(fabs(a3.x), fabs(x3.x), ab0);
-    ab1 = fma(fabs(a3.y), fabs(x3.y), ab1);
+    double2 av[R][4];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) av[q][e] = *reinterpret_cast<const double2*>(a[q] + c + 128 * e);
+    double2 xv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xv[e] = *reinterpret_cast<const double2*>(x + c + 128 * e);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      acc[q][0] = fma(av[q][0].x, xv[0].x, acc[q][0]);
+      acc[q][1] = fma(av[q][0].y, xv[0].y, acc[q][1]);
+      acc[q][2] = fma(av[q][1].x, xv[1].x, acc[q][2]);
+      acc[q][3] = fma(av[q][1].y, xv[1].y, acc[q][3]);
+      acc[q][0] = fma(av[q][2].x, xv[2].x, acc[q][0]);
+      acc[q][1] = fma(av[q][2].y, xv[2].y, acc[q][1]);
+      acc[q][2] = fma(av[q][3].x, xv[3].x, acc[q][2]);
+      acc[q][3] = fma(av[q][3].y, xv[3].y, acc[q][3]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        ab[q][0] = fma(fabs(av[q][e].x), fabs(xv[e].x), ab[q][0]);
+        ab[q][1] = fma(fabs(av[q][e].y), fabs(xv[e].y), ab[q][1]);
+      }
+    }
   }
   for (; c < n2; c += 128) {
-    const double2 a0 = *reinterpret_cast<const double2*>(a + c);
     const double2 x0 = *reinterpret_cast<const double2*>(x + c);
-    acc0 = fma(a0.x, x0.x, acc0);
-    acc1 = fma(a0.y, x0.y, acc1);
-    ab0 = fma(fabs(a0.x), fabs(x0.x), ab0);
-    ab1 = fma(fabs(a0.y), fabs(x0.y), ab1);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double2 a0 = *reinterpret_cast<const double2*>(a[q] + c);
+      acc[q][0] = fma(a0.x, x0.x, acc[q][0]);
+      acc[q][1] = fma(a0.y, x0.y, acc[q][1]);
+      ab[q][0] = fma(fabs(a0.x), fabs(x0.x), ab[q][0]);
+      ab[q][1] = fma(fabs(a0.y), fabs(x0.y), ab[q][1]);
+    }
   }
   for (int cc = n2 + lane; cc < n; cc += kWave) {
-    acc0 = fma(a[cc], x[cc], acc0);
-    ab0 = fma(fabs(a[cc]), fabs(x[cc]), ab0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      acc[q][0] = fma(a[q][cc], x[cc], acc[q][0]);
+      ab[q][0] = fma(fabs(a[q][cc]), fabs(x[cc]), ab[q][0]);
+    }
   }
-  acc0 += acc2;
-  acc1 += acc3;
-  const double s = wave_sum(acc0 + acc1);
-  const double sabs = wave_sum(ab0 + ab1);
+  // the maxima of |r_i|, |x_i| and the componentwise ratio over the valid rows
+  double mrw = 0.0, mxw = 0.0, mcw = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const double s = wave_sum((acc[q][0] + acc[q][2]) + (acc[q][1] + acc[q][3]));
+    const double sabs = wave_sum(ab[q][0] + ab[q][1]);
+    const int row = row0 + q;
+    if (lane == 0 && row < n) {
+      const double ri = b[row] - s;
+      r[row] = ri;
+      mrw = fmax(mrw, fabs(ri));
+      mxw = fmax(mxw, fabs(x[row]));
+      mcw = fmax(mcw, cw_ratio(fabs(ri), sabs + fabs(b[row])));
+    }
+  }
   __shared__ double mr[4], mx[4], mc[4];
-  const int wave = threadIdx.x / kWave;
   if (lane == 0) {
-    const double ri = b[row] - s;
-    if (rvalid) r[row] = ri;
-    mr[wave] = fabs(ri);
-    mx[wave] = fabs(x[row]);
-    mc[wave] = cw_ratio(fabs(ri), sabs + fabs(b[row]));
+    mr[wave] = mrw;
+    mx[wave] = mxw;
+    mc[wave] = mcw;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, c = 0.0, e = 0.0;
-    const int nw = min(4, (n - blockIdx.x * 4));
-    for (int w = 0; w < nw; ++w) {
-      a = fmax(a, mr[w]);
-      c = fmax(c, mx[w]);
-      e = fmax(e, mc[w]);
+    double am = 0.0, cm = 0.0, em = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      am = fmax(am, mr[w]);
+      cm = fmax(cm, mx[w]);
+      em = fmax(em, mc[w]);
     }
-    atomic_max_nonneg(norms + kNormCw, e);
-    atomic_max_nonneg(norms + 0, a);
-    atomic_max_nonneg(norms + 1, c);
+    atomic_max_nonneg(norms + kNormCw, em);
+    atomic_max_nonneg(norms + 0, am);
+    atomic_max_nonneg(norms + 1, cm);
   }
 }
 
@@ -2559,7 +2584,8 @@ void launch_gemv_a64(const double* A, int64_t ld, const int* permA, int n, const
 void launch_residual(const double* A, int64_t ld, int n, const double* b, const double* x,
                      double* r, unsigned long long* norms, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_resid_norms, dim3(1), dim3(64), 0, s, norms);
-  hipLaunchKernelGGL(k_residual, dim3(nblocks(n, 4)), dim3(256), 0, s, A, ld, n, b, x, r, norms);
+  hipLaunchKernelGGL(k_residual<kResidRows>, dim3(nblocks(n, 4 * kResidRows)), dim3(256), 0, s, A,
+                     ld, n, b, x, r, norms);
 }
 
 template <class F>
