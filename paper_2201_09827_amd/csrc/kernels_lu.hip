@@ -17,6 +17,8 @@
 // Block column = one kernel: every thread keeps one row of the block column
 // in registers while the workgroups agree on each pivot through tagged words
 // in a small exchange buffer (one record per workgroup and column parity).
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace gir {
@@ -268,14 +270,26 @@ struct PanelSmem {
   alignas(16) float rowsave[kMaxNb][kMaxNb];  // pivot rows owned by this workgroup
 };
 
-// Block column k0 .. k0 + kb - 1 over rows k0 .. k0 + h - 1 (logical), run by
-// workgroup g of the G that share it (512 threads each).
+template <class T>
+struct PreSmem;
 template <class F>
+__device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
+                                                    const typename F::T* __restrict__ S,
+                                                    int64_t ld, int uk0, int phys, bool in,
+                                                    const int* __restrict__ perm, int k0,
+                                                    float (&x)[kMaxNb]);
+
+// Block column k0 .. k0 + kb - 1 over rows k0 .. k0 + h - 1 (logical), run by
+// workgroup g of the G that share it (512 threads each).  With kPre, the
+// block column's rows first receive step uk0's trailing update from these
+// same workgroups (block_column_update) instead of a launch before.
+template <class F, bool kPre = false>
 __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restrict__ S,
                                            int64_t ld, int* __restrict__ perm, int k0, int kb,
                                            int h, int G, int g, int* __restrict__ ipiv,
                                            int* __restrict__ perm_copy,
-                                           uint64_t* __restrict__ xch, CycleState* st) {
+                                           uint64_t* __restrict__ xch, CycleState* st,
+                                           PreSmem<typename F::T>* ps = nullptr, int uk0 = 0) {
   using T = typename F::T;
   uint64_t* kw = sm.kw;
   float* rowbuf = sm.rowbuf;
@@ -294,7 +308,10 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
   const int phys = in ? perm[k0 + q] : 0;
   T* row = S + (int64_t)phys * ld + k0;
   float x[kMaxNb];
-  load_panel_row<F>(row, kb, in, x);
+  if constexpr (kPre)
+    block_column_update<F>(*ps, S, ld, uk0, phys, in, perm, k0, x);  // kb == kMaxNb
+  else
+    load_panel_row<F>(row, kb, in, x);
   // materialise the fp32 values now (keeps the compiler from carrying the
   // narrow inputs and converting them at every later use)
 #pragma unroll
@@ -791,6 +808,117 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
   }
 }
 
+// The trailing update of step uk0 restricted to block column k0 (the next
+// one), formed by the block column's own workgroups before its pivot search:
+// the separate launch it replaces sat on the factorisation's critical path
+// (≈ 8.5 µs per block column at n = 8192, mostly memory latency).  Every
+// product is the one gemm_tile forms for the same entries: the same 32 x 32
+// blocks of gfx950's 16-deep fp16 / bf16 products over the same k steps, each
+// row and column at the same position in its block, added to C in fp32 and
+// rounded to u_f once, so the factors are unchanged.  Each wave forms the
+// products of its own 64 rows (2 x 2 blocks) from its own LDS region and
+// hands each row's sums to the row's lane through that region, 32 columns at
+// a time: one workgroup barrier in all (for U12).  x receives the row's
+// updated values (u_f values in fp32).  The block column is a full one (a
+// further block column follows it), so no column is masked: per-column
+// bounds tests here were kept live by the compiler through the whole pivot
+// search, for the write-back's tests, and spilled.
+template <class T>
+struct PreSmem {
+  alignas(16) T As[kRowWaves][kWave][kKP];  // per wave: -L21 of its rows, then the sums
+  alignas(16) T Bt[kMaxNb][kKP];            // U12 transposed: Bt[j][t] = U12(t, k0 + j)
+};
+constexpr int kPreOutLd = 33;  // padded row of a wave's sums (floats), 32 columns at a time
+static_assert(kWave * kPreOutLd * 4 <= kWave * kKP * 2, "a wave's sums fit in its region");
+
+template <class F>
+__device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
+                                                    const typename F::T* __restrict__ S,
+                                                    int64_t ld, int uk0, int phys, bool in,
+                                                    const int* __restrict__ perm, int k0,
+                                                    float (&x)[kMaxNb]) {
+  using T = typename F::T;
+  constexpr int V = 16 / (int)sizeof(T);
+  constexpr int P = kMaxNb / V;  // 16-byte pieces of a 64-element row segment
+  static_assert(kMaxNb * P == kRowThreads, "one piece of U12 per thread");
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const T* srow = S + (int64_t)phys * ld;
+  uint4 cw[P];
+  {
+    uint4 lw[P];
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      lw[v] = in ? *reinterpret_cast<const uint4*>(srow + uk0 + v * V) : make_uint4(0, 0, 0, 0);
+      cw[v] = in ? *reinterpret_cast<const uint4*>(srow + k0 + v * V) : make_uint4(0, 0, 0, 0);
+    }
+    // U12 row t (pivot row t of step uk0), piece pc of block column k0
+    const int t = tid / P, pc = tid % P;
+    const uint4 w =
+        *reinterpret_cast<const uint4*>(S + (int64_t)perm[uk0 + t] * ld + k0 + pc * V);
+    T tv[V];
+    __builtin_memcpy(tv, &w, 16);
+#pragma unroll
+    for (int e = 0; e < V; ++e) ps.Bt[pc * V + e][t] = tv[e];
+    // -L21 of this thread's row, as gemm_tile stages it
+#pragma unroll
+    for (int v = 0; v < P; ++v) {
+      T lv[V];
+      __builtin_memcpy(lv, &lw[v], 16);
+#pragma unroll
+      for (int e = 0; e < V; ++e) lv[e] = in ? F::from_f(-F::to_f(lv[e])) : F::from_f(0.0f);
+      uint4 w2;
+      __builtin_memcpy(&w2, lv, 16);
+      *reinterpret_cast<uint4*>(&ps.As[wave][lane][v * V]) = w2;
+    }
+  }
+  __syncthreads();
+  const int l32 = lane % 32, hi = lane / 32;
+  float16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+#pragma unroll
+  for (int kk = 0; kk < kMaxNb / 16; ++kk) {
+    const int ko = kk * 16 + 8 * hi;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = Mfma<F>::step(&ps.As[wave][i * 32 + l32][ko], &ps.Bt[j * 32 + l32][ko],
+                                  acc[i][j]);
+  }
+  // the wave's region now takes its sums, 32 columns at a time (the wave's
+  // own LDS operations complete in order: no barrier)
+  float* out = reinterpret_cast<float*>(&ps.As[wave][0][0]);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          out[(i * 32 + 8 * gq + 4 * hi + e) * kPreOutLd + l32] = acc[i][j][4 * gq + e];
+#pragma unroll
+    for (int v = 0; v < 32 / V; ++v) {
+      T tv[V];
+      __builtin_memcpy(tv, &cw[j * (32 / V) + v], 16);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int c = v * V + e;  // column within this half
+        const float v = F::to_f(F::from_f(F::to_f(tv[e]) + out[lane * kPreOutLd + c]));
+        x[j * 32 + c] = in ? v : 0.0f;
+      }
+    }
+  }
+  __syncthreads();  // the regions are reused by the pivot search
+}
+
 template <class F>
 __global__ __launch_bounds__(kRowThreads) void k_gemm_update(typename F::T* __restrict__ S,
                                                              int64_t ld,
@@ -809,18 +937,22 @@ __global__ __launch_bounds__(kRowThreads) void k_gemm_update(typename F::T* __re
 // right of block column k + 1, disjoint from it; the trailing rows are
 // located through the permutation copy of step k, since the block column
 // rewrites perm meanwhile).
-template <class F>
+template <class F, bool kPre>
 __global__ __launch_bounds__(kRowThreads) void k_panel_update(
     typename F::T* __restrict__ S, int64_t ld, int* __restrict__ perm, int pk0, int pkb, int ph,
     int G, int* __restrict__ ipiv, int* __restrict__ perm_copy, uint64_t* __restrict__ xch,
     CycleState* st, const int* __restrict__ rows, int k0, int kb, int n, int c_begin, int c_end,
     int tiles_x) {
+  // the staging of the fold only where it is used (fp32 factors would not fit)
+  using Pre = std::conditional_t<kPre, PreSmem<typename F::T>, PanelSmem>;
   __shared__ union {
     PanelSmem p;
     GemmSmem<typename F::T> g;
+    Pre pre;
   } sm;
   if ((int)blockIdx.x < G) {
-    panel_rows<F>(sm.p, S, ld, perm, pk0, pkb, ph, G, (int)blockIdx.x, ipiv, perm_copy, xch, st);
+    panel_rows<F, kPre>(sm.p, S, ld, perm, pk0, pkb, ph, G, (int)blockIdx.x, ipiv, perm_copy, xch,
+                        st, reinterpret_cast<PreSmem<typename F::T>*>(&sm.pre), k0);
   } else {
     const int t = (int)blockIdx.x - G;
     gemm_tile<F>(sm.g, S, ld, perm, rows, k0, kb, n, c_begin, c_end, t % tiles_x, t / tiles_x);
@@ -866,7 +998,7 @@ void panel_step_t(const PanelArgs& a, hipStream_t s) {
                      a.ld, a.perm, a.k0, a.kb, h, a.ipiv, a.perm_copy, a.xch, a.st);
 }
 
-template <class F>
+template <class F, bool kPre>
 void panel_update_t(const PanelArgs& p, const PanelArgs& u, const int* rows, int c_begin,
                     int c_end, hipStream_t s) {
   using T = typename F::T;
@@ -875,7 +1007,7 @@ void panel_update_t(const PanelArgs& p, const PanelArgs& u, const int* rows, int
   const int M = u.n - u.k0 - u.kb;
   const int tx = (c_end - c_begin + kTile - 1) / kTile;
   const int ty = (M + kTile - 1) / kTile;
-  hipLaunchKernelGGL(k_panel_update<F>, dim3(G + tx * ty), dim3(kRowThreads), 0, s,
+  hipLaunchKernelGGL((k_panel_update<F, kPre>), dim3(G + tx * ty), dim3(kRowThreads), 0, s,
                      reinterpret_cast<T*>(p.S), p.ld, p.perm, p.k0, p.kb, h, G, p.ipiv,
                      p.perm_copy, p.xch, p.st, rows, u.k0, u.kb, u.n, c_begin, c_end, tx);
 }
@@ -970,13 +1102,17 @@ void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_be
 
 void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
                          int c_begin, int c_end, hipStream_t s) {
+  // fp16 / bf16 factors: the block column takes step u's update itself; fp32
+  // factors (fp64 matrix-core products) keep the separate update launch
   if (store == kStoreF16)
-    panel_update_t<Fp16>(p, u, rows, c_begin, c_end, s);
+    panel_update_t<Fp16, true>(p, u, rows, c_begin, c_end, s);
   else if (store == kStoreBF16)
-    panel_update_t<Bf16>(p, u, rows, c_begin, c_end, s);
+    panel_update_t<Bf16, true>(p, u, rows, c_begin, c_end, s);
   else
-    panel_update_t<Fp32>(p, u, rows, c_begin, c_end, s);
+    panel_update_t<Fp32, false>(p, u, rows, c_begin, c_end, s);
 }
+
+bool panel_update_folds(int store) { return store != kStoreF32; }
 
 void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s) {
   if (n <= 0) return;

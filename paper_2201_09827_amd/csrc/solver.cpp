@@ -923,14 +923,18 @@ int run_lu(gmresir_ctx* h) {
     const int c2 = std::min(n, c1 + kNb);    // ... and the columns beyond it
     GIR_TRY(timed(h, kKcTrsm, kb * (kb - 1.0) * (n - c1), s0, nullptr, 0,
                   [&] { gir::launch_trsm(a, h->store, c1, n, s0); }));
-    GIR_TRY(timed(h, kKcGemm, 2.0 * M * (c2 - c1) * kb, s0, nullptr,
-                  0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
+    // the next block column's part of this step's update: its own launch, or
+    // (fp16 / bf16 factors) formed by the block column's workgroups
+    const bool fold = c2 < n && gir::panel_update_folds(h->store);
+    if (!fold)
+      GIR_TRY(timed(h, kKcGemm, 2.0 * M * (c2 - c1) * kb, s0, nullptr,
+                    0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
     gir::PanelArgs an = a;
     an.k0 = c1;
     an.kb = std::min(kNb, n - c1);
     an.perm_copy = prow + (size_t)((step + 1) & 1) * n;
     const double hn = (double)(n - c1);
-    const double pflops = panel_flops(hn, an.kb);
+    const double pflops = panel_flops(hn, an.kb) + (fold ? 2.0 * M * (c2 - c1) * kb : 0.0);
     if (c2 < n) {
       const double gflops = 2.0 * M * (n - c2) * kb;
       GIR_TRY(timed(h, kKcPanel, pflops + gflops, s0, nullptr, 0, [&] {
