@@ -443,7 +443,10 @@ def main():
                 "lu_gemm_only": None if not gemm else {
                     "launches_per_step": gemm["launches"], "avg_us": gemm["total_ms"] /
                     max(gemm["launches"], 1) * 1e3, "TFLOPs": rate(gemm),
-                    "frac": rate(gemm) / lu_peak},
+                    "frac": rate(gemm) / lu_peak,
+                    "note": "separate update launches only: with fp16 / bf16 factors the "
+                            "rank-64 updates run inside the block-column launches "
+                            "(lu_panel) but for the last block column's"},
                 "arnoldi_step": arn,
                 "kernels_one_step": kernels}
     log(f"dominant kernel class {dom}: {r['launches']} launches, avg "

@@ -272,6 +272,8 @@ struct PanelSmem {
 
 template <class T>
 struct PreSmem;
+template <class T>
+struct PanelPreSmem;
 template <class F>
 __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
                                                     const typename F::T* __restrict__ S,
@@ -495,6 +497,18 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
       }
     }
   }
+  if constexpr (kPre) {
+    // U12 of the block row of step uk0 in this block column: every
+    // workgroup has read the unsolved values (its prologue precedes its
+    // first pivot record, and all records of the last column are in)
+    if (g == 0) {
+      constexpr int V = 16 / (int)sizeof(T);
+      const auto& pp = *reinterpret_cast<const PanelPreSmem<T>*>(ps);
+      const int t = tid / (kMaxNb / V), pc = tid % (kMaxNb / V);
+      *reinterpret_cast<uint4*>(S + (int64_t)perm[uk0 + t] * ld + k0 + pc * V) =
+          *reinterpret_cast<const uint4*>(&pp.u12[t][pc * V]);
+    }
+  }
   if (in) {
     if (pv) {
 #pragma unroll
@@ -540,39 +554,26 @@ __device__ __forceinline__ float quad_bcast(float v) {
       __builtin_amdgcn_update_dpp(0, __float_as_int(v), P * 0x55, 0xf, 0xf, false));
 }
 
+// L11 (unit lower, pivot rows prow[0 .. 63] of the block column at k0) by row
+// class: Lq[t][r % 4][r / 4] = L(r, t).  Called by threads 0 .. 63 (row = tid).
 template <class F>
-__global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict__ S, int64_t ld,
-                                                       const int* __restrict__ perm, int k0,
-                                                       int c_begin, int c_end) {
-  __shared__ __align__(16) float Lq[kMaxNb][4][kTrsmLq];
-  __shared__ int prow[kMaxNb];
-  const int tid = threadIdx.x;
-  const int p = tid & 3;
-  const int64_t c = (int64_t)c_begin + (int64_t)blockIdx.x * kTrsmCols + (tid >> 2);
-  prow[tid] = perm[k0 + tid];
-  __syncthreads();
-  // this lane's rows of its column, loaded together with the L11 row below
-  // (one memory round trip for both); a lane beyond c_end reads a valid
-  // column and discards it
-  const int64_t cc = c < c_end ? c : (int64_t)c_begin;
-  typename F::T yraw[kMaxNb / 4];
+__device__ __forceinline__ void stage_l11(float (&Lq)[kMaxNb][4][kTrsmLq],
+                                          const typename F::T* __restrict__ S, int64_t ld,
+                                          int prow_t, int k0, int tid) {
+  // entries on and above the diagonal are never read
+  float lrow[kMaxNb];
+  load_panel_row<F>(S + (int64_t)prow_t * ld + k0, kMaxNb, true, lrow);
 #pragma unroll
-  for (int i = 0; i < kMaxNb / 4; ++i) yraw[i] = S[(int64_t)prow[4 * i + p] * ld + cc];
-  {
-    // row r = tid of L11 in 16-byte pieces, written by row class; entries on
-    // and above the diagonal are never read
-    float lrow[kMaxNb];
-    load_panel_row<F>(S + (int64_t)prow[tid] * ld + k0, kMaxNb, true, lrow);
-#pragma unroll
-    for (int t = 0; t < kMaxNb; ++t) Lq[t][tid & 3][tid >> 2] = lrow[t];
-  }
-  __syncthreads();
-  if (c >= c_end) return;  // whole quads: the four lanes of a column leave together
-  float y[kMaxNb / 4];
-#pragma unroll
-  for (int i = 0; i < kMaxNb / 4; ++i) y[i] = F::to_f(yraw[i]);
-#pragma unroll
-  for (int i = 0; i < kMaxNb / 4; ++i) asm volatile("" : "+v"(y[i]));
+  for (int t = 0; t < kMaxNb; ++t) Lq[t][tid & 3][tid >> 2] = lrow[t];
+}
+
+// Forward substitution with the unit lower L11 for one column of the block
+// row, held by a quad of lanes: lane p of the quad keeps rows 4 i + p in
+// y[i].  Row r receives -l_rt y_t for t = 0, 1, ..., r - 1 in that order,
+// one fused multiply-add each in fp32; y_t reaches the quad from its owner by
+// a DPP quad broadcast.
+__device__ __forceinline__ void trsm_quad(float (&y)[kMaxNb / 4],
+                                          const float (&Lq)[kMaxNb][4][kTrsmLq], int p) {
 #define GIR_TRSM_STEP(T)                                                                  \
   {                                                                                       \
     constexpr int ti = (T) >> 2, tp = (T) & 3;                                            \
@@ -598,10 +599,39 @@ __global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict
   GIR_TRSM_STEP(61) GIR_TRSM_STEP(62)
 #undef GIR_TRSM_STEP4
 #undef GIR_TRSM_STEP
-  // the fp32 result is rounded to u_f in a separate step (an fma fused with
-  // the narrowing conversion would round only once)
+  // the fp32 result is rounded to u_f in a separate step by the caller (an
+  // fma fused with the narrowing conversion would round only once)
 #pragma unroll
   for (int i = 0; i < kMaxNb / 4; ++i) asm volatile("" : "+v"(y[i]));
+}
+
+template <class F>
+__global__ __launch_bounds__(kTrsmThreads) void k_trsm(typename F::T* __restrict__ S, int64_t ld,
+                                                       const int* __restrict__ perm, int k0,
+                                                       int c_begin, int c_end) {
+  __shared__ __align__(16) float Lq[kMaxNb][4][kTrsmLq];
+  __shared__ int prow[kMaxNb];
+  const int tid = threadIdx.x;
+  const int p = tid & 3;
+  const int64_t c = (int64_t)c_begin + (int64_t)blockIdx.x * kTrsmCols + (tid >> 2);
+  prow[tid] = perm[k0 + tid];
+  __syncthreads();
+  // this lane's rows of its column, loaded together with the L11 row below
+  // (one memory round trip for both); a lane beyond c_end reads a valid
+  // column and discards it
+  const int64_t cc = c < c_end ? c : (int64_t)c_begin;
+  typename F::T yraw[kMaxNb / 4];
+#pragma unroll
+  for (int i = 0; i < kMaxNb / 4; ++i) yraw[i] = S[(int64_t)prow[4 * i + p] * ld + cc];
+  stage_l11<F>(Lq, S, ld, prow[tid], k0, tid);
+  __syncthreads();
+  if (c >= c_end) return;  // whole quads: the four lanes of a column leave together
+  float y[kMaxNb / 4];
+#pragma unroll
+  for (int i = 0; i < kMaxNb / 4; ++i) y[i] = F::to_f(yraw[i]);
+#pragma unroll
+  for (int i = 0; i < kMaxNb / 4; ++i) asm volatile("" : "+v"(y[i]));
+  trsm_quad(y, Lq, p);
 #pragma unroll
   for (int i = 0; i < kMaxNb / 4; ++i) S[(int64_t)prow[4 * i + p] * ld + c] = F::from_f(y[i]);
 }
@@ -663,15 +693,32 @@ struct GemmSmem {
   int krow[kMaxNb];
 };
 
+// The update tiles of a block column launch that also solve their part of
+// the block row (see gemm_tile)
+template <class T>
+struct GemmTrsmSmem {
+  GemmSmem<T> g;
+  alignas(16) float Lq[kMaxNb][4][kTrsmLq];
+  int arrived;
+};
+
 // One 128 x 128 tile (bx, by) of the trailing update for columns
 // [c_begin, c_end), rows through `rows`, by a workgroup of 512 threads
 // (8 waves: 2 x 4 blocks of 64 x 32).
-template <class F>
+//
+// With kTrsm the tile also solves its 128 columns of the block row (U12 =
+// L11^-1 A12, a quad per column as k_trsm solves them) instead of reading
+// them solved: every tile of a column strip forms the same U12 from the
+// unsolved values, and the last of the strip's tiles to finish (counted in
+// strip_cnt[bx], ty tiles per strip) writes U12 back, when every tile of the
+// strip has read the unsolved values.
+template <class F, bool kTrsm = false>
 __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
                                           typename F::T* __restrict__ S, int64_t ld,
                                           const int* __restrict__ perm,
                                           const int* __restrict__ rows, int k0, int kb, int n,
-                                          int c_begin, int c_end, int bx, int by) {
+                                          int c_begin, int c_end, int bx, int by,
+                                          int* __restrict__ strip_cnt = nullptr, int ty = 0) {
   using T = typename F::T;
   constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte piece
   constexpr int NT = kRowThreads;
@@ -705,16 +752,30 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
     *reinterpret_cast<uint4*>(&As[r][kc * V]) = w2;
   }
   // U12 rows k, columns tn .. tn + 127, stored transposed
-  for (int q = tid; q < kMaxNb * (kTile / V); q += NT) {
-    const int k = q / (kTile / V), cc = q % (kTile / V);
-    const int c = tn + cc * V;
-    T t[V];
-    if (c < ld) {
-      const uint4 w = *reinterpret_cast<const uint4*>(S + (int64_t)krow[k] * ld + c);
-      __builtin_memcpy(t, &w, 16);
-    }
+  [[maybe_unused]] T yraw[kMaxNb / 4];
+  [[maybe_unused]] auto& gt = reinterpret_cast<GemmTrsmSmem<T>&>(sm);
+  if constexpr (!kTrsm) {
+    for (int q = tid; q < kMaxNb * (kTile / V); q += NT) {
+      const int k = q / (kTile / V), cc = q % (kTile / V);
+      const int c = tn + cc * V;
+      T t[V];
+      if (c < ld) {
+        const uint4 w = *reinterpret_cast<const uint4*>(S + (int64_t)krow[k] * ld + c);
+        __builtin_memcpy(t, &w, 16);
+      }
 #pragma unroll
-    for (int e = 0; e < V; ++e) Bt[cc * V + e][k] = (c + e < c_end) ? t[e] : F::from_f(0.0f);
+      for (int e = 0; e < V; ++e) Bt[cc * V + e][k] = (c + e < c_end) ? t[e] : F::from_f(0.0f);
+    }
+  } else {
+    // quad tid / 4 takes column tn + tid / 4 of the unsolved block row (a
+    // quad past c_end reads column tn and discards it), threads 0 .. 63 L11
+    static_assert(kTile * 4 == NT, "a quad per column of the tile");
+    const int c = tn + (tid >> 2);
+    const int cc = c < c_end ? c : tn;
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i)
+      yraw[i] = S[(int64_t)krow[4 * i + (tid & 3)] * ld + cc];
+    if (tid < kMaxNb) stage_l11<F>(gt.Lq, S, ld, krow[tid], k0, tid);
   }
   // C tile
   for (int q = tid; q < kTile * (kTile / V); q += NT) {
@@ -725,6 +786,20 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
     *reinterpret_cast<uint4*>(&Cs[r][cc * V]) = w;
   }
   __syncthreads();
+  if constexpr (kTrsm) {
+    const int cq = tid >> 2, pq = tid & 3;
+    float y[kMaxNb / 4];
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i) y[i] = F::to_f(yraw[i]);
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i) asm volatile("" : "+v"(y[i]));
+    trsm_quad(y, gt.Lq, pq);
+    const bool live = tn + cq < c_end;
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i)
+      Bt[cq][4 * i + pq] = live ? F::from_f(y[i]) : F::from_f(0.0f);
+    __syncthreads();
+  }
   const int wave = tid / kWave;
   const int lane = tid % kWave;
   const int wr = (wave / 4) * 64;
@@ -806,6 +881,30 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
       for (int e = 0; c + e < c_end; ++e) dst[e] = Cs[r][cc * V + e];
     }
   }
+  if constexpr (kTrsm) {
+    // every thread has consumed its unsolved values (the barrier after the
+    // solve): count this tile in, and the strip's last tile writes U12
+    if (tid == 0) gt.arrived = atomicAdd(strip_cnt + bx, 1);
+    __syncthreads();
+    if (gt.arrived == ty - 1) {
+      for (int q = tid; q < kMaxNb * (kTile / V); q += NT) {
+        const int k = q / (kTile / V), cc = q % (kTile / V);
+        const int c = tn + cc * V;
+        if (c >= c_end) continue;
+        T t[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) t[e] = Bt[cc * V + e][k];
+        T* dst = S + (int64_t)krow[k] * ld + c;
+        if (c + V <= c_end) {
+          uint4 w;
+          __builtin_memcpy(&w, t, 16);
+          *reinterpret_cast<uint4*>(dst) = w;
+        } else {
+          for (int e = 0; c + e < c_end; ++e) dst[e] = t[e];
+        }
+      }
+    }
+  }
 }
 
 // The trailing update of step uk0 restricted to block column k0 (the next
@@ -818,16 +917,32 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
 // rounded to u_f once, so the factors are unchanged.  Each wave forms the
 // products of its own 64 rows (2 x 2 blocks) from its own LDS region and
 // hands each row's sums to the row's lane through that region, 32 columns at
-// a time: one workgroup barrier in all (for U12).  x receives the row's
-// updated values (u_f values in fp32).  The block column is a full one (a
-// further block column follows it), so no column is masked: per-column
-// bounds tests here were kept live by the compiler through the whole pivot
-// search, for the write-back's tests, and spilled.
+// a time.  U12 of these 64 columns (the block row's solve with L11) is formed
+// here too, by threads 0 .. 255 as k_trsm forms it (a quad per column, the
+// same order of fused multiply-adds), and kept in PanelPreSmem::u12 for the
+// write-back.  x receives the row's updated values (u_f values in fp32).  The
+// block column is a full one (a further block column follows it), so no
+// column is masked: per-column bounds tests here were kept live by the
+// compiler through the whole pivot search, for the write-back's tests, and
+// spilled.
 template <class T>
 struct PreSmem {
   alignas(16) T As[kRowWaves][kWave][kKP];  // per wave: -L21 of its rows, then the sums
   alignas(16) T Bt[kMaxNb][kKP];            // U12 transposed: Bt[j][t] = U12(t, k0 + j)
+  alignas(16) float Lq[kMaxNb][4][kTrsmLq];  // L11 of step uk0 by row class
 };
+
+// The block column's shared memory with the fold: the pivot search's, then
+// U12 of the block column (step uk0's block row), which workgroup 0 writes
+// back after the pivot search (PreSmem overlaps both and is dead by then)
+template <class T>
+struct PanelPreSmem {
+  PanelSmem p;
+  alignas(16) T u12[kMaxNb][kMaxNb];
+};
+static_assert(sizeof(PanelPreSmem<_Float16>) <= sizeof(PreSmem<_Float16>) &&
+                  sizeof(PanelPreSmem<uint16_t>) <= sizeof(PreSmem<uint16_t>),
+              "the block column's fold staging covers the write-back's U12");
 constexpr int kPreOutLd = 33;  // padded row of a wave's sums (floats), 32 columns at a time
 static_assert(kWave * kPreOutLd * 4 <= kWave * kKP * 2, "a wave's sums fit in its region");
 
@@ -846,6 +961,7 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
   const int lane = tid % kWave;
   const T* srow = S + (int64_t)phys * ld;
   uint4 cw[P];
+  T yraw[kMaxNb / 4];
   {
     uint4 lw[P];
 #pragma unroll
@@ -853,14 +969,15 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
       lw[v] = in ? *reinterpret_cast<const uint4*>(srow + uk0 + v * V) : make_uint4(0, 0, 0, 0);
       cw[v] = in ? *reinterpret_cast<const uint4*>(srow + k0 + v * V) : make_uint4(0, 0, 0, 0);
     }
-    // U12 row t (pivot row t of step uk0), piece pc of block column k0
-    const int t = tid / P, pc = tid % P;
-    const uint4 w =
-        *reinterpret_cast<const uint4*>(S + (int64_t)perm[uk0 + t] * ld + k0 + pc * V);
-    T tv[V];
-    __builtin_memcpy(tv, &w, 16);
+    // this quad's column of the block row (threads 0 .. 255: column tid / 4,
+    // rows 4 i + tid % 4), and L11 (threads 0 .. 63)
+    if (tid < 4 * kMaxNb) {
+      const int c = tid >> 2, pq = tid & 3;
 #pragma unroll
-    for (int e = 0; e < V; ++e) ps.Bt[pc * V + e][t] = tv[e];
+      for (int i = 0; i < kMaxNb / 4; ++i)
+        yraw[i] = S[(int64_t)perm[uk0 + 4 * i + pq] * ld + k0 + c];
+    }
+    if (tid < kMaxNb) stage_l11<F>(ps.Lq, S, ld, perm[uk0 + tid], uk0, tid);
     // -L21 of this thread's row, as gemm_tile stages it
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -872,6 +989,18 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
       __builtin_memcpy(&w2, lv, 16);
       *reinterpret_cast<uint4*>(&ps.As[wave][lane][v * V]) = w2;
     }
+  }
+  __syncthreads();
+  float y[kMaxNb / 4];
+  if (tid < 4 * kMaxNb) {
+    const int c = tid >> 2, pq = tid & 3;
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i) y[i] = F::to_f(yraw[i]);
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i) asm volatile("" : "+v"(y[i]));
+    trsm_quad(y, ps.Lq, pq);
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i) ps.Bt[c][4 * i + pq] = F::from_f(y[i]);
   }
   __syncthreads();
   const int l32 = lane % 32, hi = lane / 32;
@@ -917,6 +1046,13 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
     }
   }
   __syncthreads();  // the regions are reused by the pivot search
+  // U12 kept for the write-back (outside the pivot search's region)
+  if (tid < 4 * kMaxNb) {
+    auto& pp = *reinterpret_cast<PanelPreSmem<T>*>(&ps);
+    const int c = tid >> 2, pq = tid & 3;
+#pragma unroll
+    for (int i = 0; i < kMaxNb / 4; ++i) pp.u12[4 * i + pq][c] = F::from_f(y[i]);
+  }
 }
 
 template <class F>
@@ -942,20 +1078,24 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_update(
     typename F::T* __restrict__ S, int64_t ld, int* __restrict__ perm, int pk0, int pkb, int ph,
     int G, int* __restrict__ ipiv, int* __restrict__ perm_copy, uint64_t* __restrict__ xch,
     CycleState* st, const int* __restrict__ rows, int k0, int kb, int n, int c_begin, int c_end,
-    int tiles_x) {
+    int tiles_x, int* __restrict__ strip_cnt) {
   // the staging of the fold only where it is used (fp32 factors would not fit)
-  using Pre = std::conditional_t<kPre, PreSmem<typename F::T>, PanelSmem>;
+  using T = typename F::T;
+  using Pre = std::conditional_t<kPre, PreSmem<T>, PanelSmem>;
+  using Gem = std::conditional_t<kPre, GemmTrsmSmem<T>, GemmSmem<T>>;
   __shared__ union {
     PanelSmem p;
-    GemmSmem<typename F::T> g;
+    Gem g;
     Pre pre;
   } sm;
   if ((int)blockIdx.x < G) {
     panel_rows<F, kPre>(sm.p, S, ld, perm, pk0, pkb, ph, G, (int)blockIdx.x, ipiv, perm_copy, xch,
-                        st, reinterpret_cast<PreSmem<typename F::T>*>(&sm.pre), k0);
+                        st, reinterpret_cast<PreSmem<T>*>(&sm.pre), k0);
   } else {
     const int t = (int)blockIdx.x - G;
-    gemm_tile<F>(sm.g, S, ld, perm, rows, k0, kb, n, c_begin, c_end, t % tiles_x, t / tiles_x);
+    const int ty = (n - k0 - kb + kTile - 1) / kTile;
+    gemm_tile<F, kPre>(reinterpret_cast<GemmSmem<T>&>(sm.g), S, ld, perm, rows, k0, kb, n,
+                       c_begin, c_end, t % tiles_x, t / tiles_x, strip_cnt, ty);
   }
 }
 
@@ -1000,7 +1140,7 @@ void panel_step_t(const PanelArgs& a, hipStream_t s) {
 
 template <class F, bool kPre>
 void panel_update_t(const PanelArgs& p, const PanelArgs& u, const int* rows, int c_begin,
-                    int c_end, hipStream_t s) {
+                    int c_end, int* strip_cnt, hipStream_t s) {
   using T = typename F::T;
   const int h = p.n - p.k0;
   const int G = (h + kRowThreads - 1) / kRowThreads;
@@ -1009,7 +1149,8 @@ void panel_update_t(const PanelArgs& p, const PanelArgs& u, const int* rows, int
   const int ty = (M + kTile - 1) / kTile;
   hipLaunchKernelGGL((k_panel_update<F, kPre>), dim3(G + tx * ty), dim3(kRowThreads), 0, s,
                      reinterpret_cast<T*>(p.S), p.ld, p.perm, p.k0, p.kb, h, G, p.ipiv,
-                     p.perm_copy, p.xch, p.st, rows, u.k0, u.kb, u.n, c_begin, c_end, tx);
+                     p.perm_copy, p.xch, p.st, rows, u.k0, u.kb, u.n, c_begin, c_end, tx,
+                     strip_cnt);
 }
 
 template <class F>
@@ -1101,15 +1242,16 @@ void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_be
 }
 
 void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
-                         int c_begin, int c_end, hipStream_t s) {
-  // fp16 / bf16 factors: the block column takes step u's update itself; fp32
-  // factors (fp64 matrix-core products) keep the separate update launch
+                         int c_begin, int c_end, int* strip_cnt, hipStream_t s) {
+  // fp16 / bf16 factors: the launch also takes step u's block-row solve and
+  // the next block column's part of its update; fp32 factors (fp64
+  // matrix-core products) keep the separate launches
   if (store == kStoreF16)
-    panel_update_t<Fp16, true>(p, u, rows, c_begin, c_end, s);
+    panel_update_t<Fp16, true>(p, u, rows, c_begin, c_end, strip_cnt, s);
   else if (store == kStoreBF16)
-    panel_update_t<Bf16, true>(p, u, rows, c_begin, c_end, s);
+    panel_update_t<Bf16, true>(p, u, rows, c_begin, c_end, strip_cnt, s);
   else
-    panel_update_t<Fp32, false>(p, u, rows, c_begin, c_end, s);
+    panel_update_t<Fp32, false>(p, u, rows, c_begin, c_end, strip_cnt, s);
 }
 
 bool panel_update_folds(int store) { return store != kStoreF32; }

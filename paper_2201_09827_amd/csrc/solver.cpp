@@ -905,6 +905,13 @@ int run_lu(gmresir_ctx* h) {
   int* prow = nullptr;
   GIR_TRY(dalloc(h->arena, &prow, 2 * (size_t)n));
   h->perm_rest = prow;
+  // arrival counters of the update tiles that also solve the block row: one
+  // row per step, one counter per 128-column strip, zeroed once
+  const int64_t strip_stride = (n + 127) / 128 + 1;
+  const int64_t nstrip = ((int64_t)n / kNb + 2) * strip_stride;
+  int* strip_cnt = nullptr;
+  GIR_TRY(dalloc(h->arena, &strip_cnt, (size_t)nstrip));
+  gir::launch_fill_i32(strip_cnt, 0, nstrip, s0);
   // work of each launch for the timing records: flops (panel GEPP, the
   // block-row solve, the rank-kb trailing products)
   int step = 0;
@@ -921,11 +928,13 @@ int run_lu(gmresir_ctx* h) {
     if (M <= 0) break;
     const int c1 = k0 + a.kb;                // next block column
     const int c2 = std::min(n, c1 + kNb);    // ... and the columns beyond it
-    GIR_TRY(timed(h, kKcTrsm, kb * (kb - 1.0) * (n - c1), s0, nullptr, 0,
-                  [&] { gir::launch_trsm(a, h->store, c1, n, s0); }));
-    // the next block column's part of this step's update: its own launch, or
-    // (fp16 / bf16 factors) formed by the block column's workgroups
+    // the block row's solve and the next block column's part of this step's
+    // update: their own launches, or (fp16 / bf16 factors, a further block
+    // column beyond the next) formed inside the block column's launch
     const bool fold = c2 < n && gir::panel_update_folds(h->store);
+    if (!fold)
+      GIR_TRY(timed(h, kKcTrsm, kb * (kb - 1.0) * (n - c1), s0, nullptr, 0,
+                    [&] { gir::launch_trsm(a, h->store, c1, n, s0); }));
     if (!fold)
       GIR_TRY(timed(h, kKcGemm, 2.0 * M * (c2 - c1) * kb, s0, nullptr,
                     0, [&] { gir::launch_gemm_update(a, h->store, h->perm, c1, c2, s0); }));
@@ -934,11 +943,14 @@ int run_lu(gmresir_ctx* h) {
     an.kb = std::min(kNb, n - c1);
     an.perm_copy = prow + (size_t)((step + 1) & 1) * n;
     const double hn = (double)(n - c1);
-    const double pflops = panel_flops(hn, an.kb) + (fold ? 2.0 * M * (c2 - c1) * kb : 0.0);
+    const double pflops =
+        panel_flops(hn, an.kb) +
+        (fold ? 2.0 * M * (c2 - c1) * kb + kb * (kb - 1.0) * (n - c1) : 0.0);
     if (c2 < n) {
       const double gflops = 2.0 * M * (n - c2) * kb;
       GIR_TRY(timed(h, kKcPanel, pflops + gflops, s0, nullptr, 0, [&] {
-        gir::launch_panel_update(an, a, h->store, pcopy, c2, n, s0);
+        gir::launch_panel_update(an, a, h->store, pcopy, c2, n,
+                                 strip_cnt + (size_t)step * strip_stride, s0);
       }));
     } else {
       GIR_TRY(timed(h, kKcPanel, pflops, s0, nullptr, 0,
