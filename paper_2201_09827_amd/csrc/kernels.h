@@ -49,13 +49,14 @@ void launch_trsm(const PanelArgs& a, int store, int c_begin, int c_end, hipStrea
 void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_begin, int c_end,
                         hipStream_t s);
 // block column p and, in the same launch, the trailing update of step u for
-// columns [c_begin, c_end) (disjoint from block column p), rows through `rows`;
-// where panel_update_folds(store), the launch also solves step u's block row
-// (no launch_trsm) and block column p's own part of step u's update is formed
-// by its workgroups (no launch_gemm_update for it); strip_cnt then holds
-// ceil((c_end - c_begin) / 128) zeroed counters for this launch alone
+// columns [c_begin, c_end) (disjoint from block column p), rows through `rows`.
+// Where panel_update_folds(store): block column p's own part of step u's
+// update is formed by its workgroups (no launch_gemm_update for it), and with
+// fold == 2 the launch also solves step u's block row (no launch_trsm;
+// strip_cnt then holds ceil((c_end - c_begin) / 128) zeroed counters for this
+// launch alone); with fold == 1 launch_trsm(u, c1, n) runs before
 void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
-                         int c_begin, int c_end, int* strip_cnt, hipStream_t s);
+                         int c_begin, int c_end, int fold, int* strip_cnt, hipStream_t s);
 bool panel_update_folds(int store);
 void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s);
 // copy of `words` 4-byte words; either side may be mapped pinned host memory

@@ -274,7 +274,7 @@ template <class T>
 struct PreSmem;
 template <class T>
 struct PanelPreSmem;
-template <class F>
+template <class F, bool kSolve>
 __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
                                                     const typename F::T* __restrict__ S,
                                                     int64_t ld, int uk0, int phys, bool in,
@@ -282,10 +282,11 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
                                                     float (&x)[kMaxNb]);
 
 // Block column k0 .. k0 + kb - 1 over rows k0 .. k0 + h - 1 (logical), run by
-// workgroup g of the G that share it (512 threads each).  With kPre, the
+// workgroup g of the G that share it (512 threads each).  With kFold > 0, the
 // block column's rows first receive step uk0's trailing update from these
-// same workgroups (block_column_update) instead of a launch before.
-template <class F, bool kPre = false>
+// same workgroups (block_column_update) instead of a launch before; with
+// kFold == 2 they also solve step uk0's block row in this block column.
+template <class F, int kFold = 0>
 __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restrict__ S,
                                            int64_t ld, int* __restrict__ perm, int k0, int kb,
                                            int h, int G, int g, int* __restrict__ ipiv,
@@ -310,8 +311,8 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
   const int phys = in ? perm[k0 + q] : 0;
   T* row = S + (int64_t)phys * ld + k0;
   float x[kMaxNb];
-  if constexpr (kPre)
-    block_column_update<F>(*ps, S, ld, uk0, phys, in, perm, k0, x);  // kb == kMaxNb
+  if constexpr (kFold > 0)
+    block_column_update<F, kFold == 2>(*ps, S, ld, uk0, phys, in, perm, k0, x);  // kb == kMaxNb
   else
     load_panel_row<F>(row, kb, in, x);
   // materialise the fp32 values now (keeps the compiler from carrying the
@@ -497,7 +498,7 @@ __device__ __forceinline__ void panel_rows(PanelSmem& sm, typename F::T* __restr
       }
     }
   }
-  if constexpr (kPre) {
+  if constexpr (kFold == 2) {
     // U12 of the block row of step uk0 in this block column: every
     // workgroup has read the unsolved values (its prologue precedes its
     // first pivot record, and all records of the last column are in)
@@ -946,7 +947,7 @@ static_assert(sizeof(PanelPreSmem<_Float16>) <= sizeof(PreSmem<_Float16>) &&
 constexpr int kPreOutLd = 33;  // padded row of a wave's sums (floats), 32 columns at a time
 static_assert(kWave * kPreOutLd * 4 <= kWave * kKP * 2, "a wave's sums fit in its region");
 
-template <class F>
+template <class F, bool kSolve>
 __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
                                                     const typename F::T* __restrict__ S,
                                                     int64_t ld, int uk0, int phys, bool in,
@@ -969,15 +970,27 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
       lw[v] = in ? *reinterpret_cast<const uint4*>(srow + uk0 + v * V) : make_uint4(0, 0, 0, 0);
       cw[v] = in ? *reinterpret_cast<const uint4*>(srow + k0 + v * V) : make_uint4(0, 0, 0, 0);
     }
-    // this quad's column of the block row (threads 0 .. 255: column tid / 4,
-    // rows 4 i + tid % 4), and L11 (threads 0 .. 63)
-    if (tid < 4 * kMaxNb) {
-      const int c = tid >> 2, pq = tid & 3;
+    if constexpr (kSolve) {
+      // this quad's column of the block row (threads 0 .. 255: column
+      // tid / 4, rows 4 i + tid % 4), and L11 (threads 0 .. 63)
+      if (tid < 4 * kMaxNb) {
+        const int c = tid >> 2, pq = tid & 3;
 #pragma unroll
-      for (int i = 0; i < kMaxNb / 4; ++i)
-        yraw[i] = S[(int64_t)perm[uk0 + 4 * i + pq] * ld + k0 + c];
+        for (int i = 0; i < kMaxNb / 4; ++i)
+          yraw[i] = S[(int64_t)perm[uk0 + 4 * i + pq] * ld + k0 + c];
+      }
+      if (tid < kMaxNb) stage_l11<F>(ps.Lq, S, ld, perm[uk0 + tid], uk0, tid);
+    } else {
+      // U12 solved by the launch before: row t (pivot row t of step uk0),
+      // piece pc of this block column
+      const int t = tid / P, pc = tid % P;
+      const uint4 w =
+          *reinterpret_cast<const uint4*>(S + (int64_t)perm[uk0 + t] * ld + k0 + pc * V);
+      T tv[V];
+      __builtin_memcpy(tv, &w, 16);
+#pragma unroll
+      for (int e = 0; e < V; ++e) ps.Bt[pc * V + e][t] = tv[e];
     }
-    if (tid < kMaxNb) stage_l11<F>(ps.Lq, S, ld, perm[uk0 + tid], uk0, tid);
     // -L21 of this thread's row, as gemm_tile stages it
 #pragma unroll
     for (int v = 0; v < P; ++v) {
@@ -991,8 +1004,8 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
     }
   }
   __syncthreads();
-  float y[kMaxNb / 4];
-  if (tid < 4 * kMaxNb) {
+  [[maybe_unused]] float y[kMaxNb / 4];
+  if (kSolve && tid < 4 * kMaxNb) {
     const int c = tid >> 2, pq = tid & 3;
 #pragma unroll
     for (int i = 0; i < kMaxNb / 4; ++i) y[i] = F::to_f(yraw[i]);
@@ -1002,7 +1015,7 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
 #pragma unroll
     for (int i = 0; i < kMaxNb / 4; ++i) ps.Bt[c][4 * i + pq] = F::from_f(y[i]);
   }
-  __syncthreads();
+  if constexpr (kSolve) __syncthreads();
   const int l32 = lane % 32, hi = lane / 32;
   float16_t acc[2][2];
 #pragma unroll
@@ -1047,7 +1060,7 @@ __device__ __forceinline__ void block_column_update(PreSmem<typename F::T>& ps,
   }
   __syncthreads();  // the regions are reused by the pivot search
   // U12 kept for the write-back (outside the pivot search's region)
-  if (tid < 4 * kMaxNb) {
+  if (kSolve && tid < 4 * kMaxNb) {
     auto& pp = *reinterpret_cast<PanelPreSmem<T>*>(&ps);
     const int c = tid >> 2, pq = tid & 3;
 #pragma unroll
@@ -1073,7 +1086,7 @@ __global__ __launch_bounds__(kRowThreads) void k_gemm_update(typename F::T* __re
 // right of block column k + 1, disjoint from it; the trailing rows are
 // located through the permutation copy of step k, since the block column
 // rewrites perm meanwhile).
-template <class F, bool kPre>
+template <class F, int kFold>
 __global__ __launch_bounds__(kRowThreads) void k_panel_update(
     typename F::T* __restrict__ S, int64_t ld, int* __restrict__ perm, int pk0, int pkb, int ph,
     int G, int* __restrict__ ipiv, int* __restrict__ perm_copy, uint64_t* __restrict__ xch,
@@ -1081,20 +1094,20 @@ __global__ __launch_bounds__(kRowThreads) void k_panel_update(
     int tiles_x, int* __restrict__ strip_cnt) {
   // the staging of the fold only where it is used (fp32 factors would not fit)
   using T = typename F::T;
-  using Pre = std::conditional_t<kPre, PreSmem<T>, PanelSmem>;
-  using Gem = std::conditional_t<kPre, GemmTrsmSmem<T>, GemmSmem<T>>;
+  using Pre = std::conditional_t<(kFold > 0), PreSmem<T>, PanelSmem>;
+  using Gem = std::conditional_t<kFold == 2, GemmTrsmSmem<T>, GemmSmem<T>>;
   __shared__ union {
     PanelSmem p;
     Gem g;
     Pre pre;
   } sm;
   if ((int)blockIdx.x < G) {
-    panel_rows<F, kPre>(sm.p, S, ld, perm, pk0, pkb, ph, G, (int)blockIdx.x, ipiv, perm_copy, xch,
+    panel_rows<F, kFold>(sm.p, S, ld, perm, pk0, pkb, ph, G, (int)blockIdx.x, ipiv, perm_copy, xch,
                         st, reinterpret_cast<PreSmem<T>*>(&sm.pre), k0);
   } else {
     const int t = (int)blockIdx.x - G;
     const int ty = (n - k0 - kb + kTile - 1) / kTile;
-    gemm_tile<F, kPre>(reinterpret_cast<GemmSmem<T>&>(sm.g), S, ld, perm, rows, k0, kb, n,
+    gemm_tile<F, kFold == 2>(reinterpret_cast<GemmSmem<T>&>(sm.g), S, ld, perm, rows, k0, kb, n,
                        c_begin, c_end, t % tiles_x, t / tiles_x, strip_cnt, ty);
   }
 }
@@ -1138,7 +1151,7 @@ void panel_step_t(const PanelArgs& a, hipStream_t s) {
                      a.ld, a.perm, a.k0, a.kb, h, a.ipiv, a.perm_copy, a.xch, a.st);
 }
 
-template <class F, bool kPre>
+template <class F, int kFold>
 void panel_update_t(const PanelArgs& p, const PanelArgs& u, const int* rows, int c_begin,
                     int c_end, int* strip_cnt, hipStream_t s) {
   using T = typename F::T;
@@ -1147,7 +1160,7 @@ void panel_update_t(const PanelArgs& p, const PanelArgs& u, const int* rows, int
   const int M = u.n - u.k0 - u.kb;
   const int tx = (c_end - c_begin + kTile - 1) / kTile;
   const int ty = (M + kTile - 1) / kTile;
-  hipLaunchKernelGGL((k_panel_update<F, kPre>), dim3(G + tx * ty), dim3(kRowThreads), 0, s,
+  hipLaunchKernelGGL((k_panel_update<F, kFold>), dim3(G + tx * ty), dim3(kRowThreads), 0, s,
                      reinterpret_cast<T*>(p.S), p.ld, p.perm, p.k0, p.kb, h, G, p.ipiv,
                      p.perm_copy, p.xch, p.st, rows, u.k0, u.kb, u.n, c_begin, c_end, tx,
                      strip_cnt);
@@ -1242,16 +1255,24 @@ void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_be
 }
 
 void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
-                         int c_begin, int c_end, int* strip_cnt, hipStream_t s) {
-  // fp16 / bf16 factors: the launch also takes step u's block-row solve and
-  // the next block column's part of its update; fp32 factors (fp64
-  // matrix-core products) keep the separate launches
-  if (store == kStoreF16)
-    panel_update_t<Fp16, true>(p, u, rows, c_begin, c_end, strip_cnt, s);
-  else if (store == kStoreBF16)
-    panel_update_t<Bf16, true>(p, u, rows, c_begin, c_end, strip_cnt, s);
-  else
-    panel_update_t<Fp32, false>(p, u, rows, c_begin, c_end, strip_cnt, s);
+                         int c_begin, int c_end, int fold, int* strip_cnt, hipStream_t s) {
+  // fp16 / bf16 factors: the block column takes the next block column's part
+  // of step u's update (fold >= 1) and the block-row solve (fold == 2)
+  // itself; fp32 factors (fp64 matrix-core products) keep the separate
+  // launches
+  if (store == kStoreF16) {
+    if (fold == 2)
+      panel_update_t<Fp16, 2>(p, u, rows, c_begin, c_end, strip_cnt, s);
+    else
+      panel_update_t<Fp16, 1>(p, u, rows, c_begin, c_end, strip_cnt, s);
+  } else if (store == kStoreBF16) {
+    if (fold == 2)
+      panel_update_t<Bf16, 2>(p, u, rows, c_begin, c_end, strip_cnt, s);
+    else
+      panel_update_t<Bf16, 1>(p, u, rows, c_begin, c_end, strip_cnt, s);
+  } else {
+    panel_update_t<Fp32, 0>(p, u, rows, c_begin, c_end, strip_cnt, s);
+  }
 }
 
 bool panel_update_folds(int store) { return store != kStoreF32; }

@@ -905,6 +905,9 @@ int run_lu(gmresir_ctx* h) {
   int* prow = nullptr;
   GIR_TRY(dalloc(h->arena, &prow, 2 * (size_t)n));
   h->perm_rest = prow;
+  int dev = 0, cus = 0;
+  GIR_HIP(hipGetDevice(&dev));
+  GIR_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   // arrival counters of the update tiles that also solve the block row: one
   // row per step, one counter per 128-column strip, zeroed once
   const int64_t strip_stride = (n + 127) / 128 + 1;
@@ -930,9 +933,16 @@ int run_lu(gmresir_ctx* h) {
     const int c2 = std::min(n, c1 + kNb);    // ... and the columns beyond it
     // the block row's solve and the next block column's part of this step's
     // update: their own launches, or (fp16 / bf16 factors, a further block
-    // column beyond the next) formed inside the block column's launch
+    // column beyond the next) formed inside the block column's launch.  The
+    // solve moves in only while the update is small: each update tile then
+    // solves its own columns again, and beyond about 5.5 rounds of tiles
+    // over the compute units that work made the update, not the pivot
+    // search, the launch's critical path (measured at n = 8192: from 1 300
+    // tiles on, the separate solve launch is cheaper)
     const bool fold = c2 < n && gir::panel_update_folds(h->store);
-    if (!fold)
+    const int64_t tiles = ((int64_t)(n - c2) + 127) / 128 * (((int64_t)M + 127) / 128);
+    const bool fold_solve = fold && tiles * 2 <= 11 * (int64_t)cus;
+    if (!fold_solve)
       GIR_TRY(timed(h, kKcTrsm, kb * (kb - 1.0) * (n - c1), s0, nullptr, 0,
                     [&] { gir::launch_trsm(a, h->store, c1, n, s0); }));
     if (!fold)
@@ -943,13 +953,12 @@ int run_lu(gmresir_ctx* h) {
     an.kb = std::min(kNb, n - c1);
     an.perm_copy = prow + (size_t)((step + 1) & 1) * n;
     const double hn = (double)(n - c1);
-    const double pflops =
-        panel_flops(hn, an.kb) +
-        (fold ? 2.0 * M * (c2 - c1) * kb + kb * (kb - 1.0) * (n - c1) : 0.0);
+    const double pflops = panel_flops(hn, an.kb) + (fold ? 2.0 * M * (c2 - c1) * kb : 0.0) +
+                          (fold_solve ? kb * (kb - 1.0) * (n - c1) : 0.0);
     if (c2 < n) {
       const double gflops = 2.0 * M * (n - c2) * kb;
       GIR_TRY(timed(h, kKcPanel, pflops + gflops, s0, nullptr, 0, [&] {
-        gir::launch_panel_update(an, a, h->store, pcopy, c2, n,
+        gir::launch_panel_update(an, a, h->store, pcopy, c2, n, fold_solve ? 2 : 1,
                                  strip_cnt + (size_t)step * strip_stride, s0);
       }));
     } else {
