@@ -54,7 +54,8 @@ void launch_gemm_update(const PanelArgs& a, int store, const int* rows, int c_be
 // update is formed by its workgroups (no launch_gemm_update for it), and with
 // fold == 2 the launch also solves step u's block row (no launch_trsm;
 // strip_cnt then holds ceil((c_end - c_begin) / 128) zeroed counters for this
-// launch alone); with fold == 1 launch_trsm(u, c1, n) runs before
+// launch alone); with fold == 1 launch_trsm(u, c1, n) runs before; fold == 0
+// (or fp32 factors): both run as their own launches before
 void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, const int* rows,
                          int c_begin, int c_end, int fold, int* strip_cnt, hipStream_t s);
 bool panel_update_folds(int store);

@@ -1263,13 +1263,17 @@ void launch_panel_update(const PanelArgs& p, const PanelArgs& u, int store, cons
   if (store == kStoreF16) {
     if (fold == 2)
       panel_update_t<Fp16, 2>(p, u, rows, c_begin, c_end, strip_cnt, s);
-    else
+    else if (fold == 1)
       panel_update_t<Fp16, 1>(p, u, rows, c_begin, c_end, strip_cnt, s);
+    else
+      panel_update_t<Fp16, 0>(p, u, rows, c_begin, c_end, strip_cnt, s);
   } else if (store == kStoreBF16) {
     if (fold == 2)
       panel_update_t<Bf16, 2>(p, u, rows, c_begin, c_end, strip_cnt, s);
-    else
+    else if (fold == 1)
       panel_update_t<Bf16, 1>(p, u, rows, c_begin, c_end, strip_cnt, s);
+    else
+      panel_update_t<Bf16, 0>(p, u, rows, c_begin, c_end, strip_cnt, s);
   } else {
     panel_update_t<Fp32, 0>(p, u, rows, c_begin, c_end, strip_cnt, s);
   }

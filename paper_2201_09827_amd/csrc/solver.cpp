@@ -371,6 +371,11 @@ struct gmresir_ctx {
   // it (the same sums as the separate launches); GMRESIR_PERSISTENT=0 at
   // handle creation keeps the separate launches
   bool persistent = true;
+  // the LU's block-row solve and the next block column's part of each
+  // step's update inside the block column's launch (fp16 / bf16 factors;
+  // the same factors bit for bit); GMRESIR_LU_FOLD=0 at handle creation
+  // keeps their separate launches
+  bool lu_fold = true;
   uint64_t *cvw = nullptr, *cpx = nullptr, *cctrl = nullptr;  // its exchange words
   int64_t cycles_run = 0;        // cycles run as one persistent launch
   int64_t cycle_fallbacks = 0;  // persistent launches that gave up (device shared)
@@ -939,7 +944,7 @@ int run_lu(gmresir_ctx* h) {
     // over the compute units that work made the update, not the pivot
     // search, the launch's critical path (measured at n = 8192: from 1 300
     // tiles on, the separate solve launch is cheaper)
-    const bool fold = c2 < n && gir::panel_update_folds(h->store);
+    const bool fold = h->lu_fold && c2 < n && gir::panel_update_folds(h->store);
     const int64_t tiles = ((int64_t)(n - c2) + 127) / 128 * (((int64_t)M + 127) / 128);
     const bool fold_solve = fold && tiles * 2 <= 11 * (int64_t)cus;
     if (!fold_solve)
@@ -958,7 +963,7 @@ int run_lu(gmresir_ctx* h) {
     if (c2 < n) {
       const double gflops = 2.0 * M * (n - c2) * kb;
       GIR_TRY(timed(h, kKcPanel, pflops + gflops, s0, nullptr, 0, [&] {
-        gir::launch_panel_update(an, a, h->store, pcopy, c2, n, fold_solve ? 2 : 1,
+        gir::launch_panel_update(an, a, h->store, pcopy, c2, n, fold_solve ? 2 : fold ? 1 : 0,
                                  strip_cnt + (size_t)step * strip_stride, s0);
       }));
     } else {
@@ -1023,6 +1028,8 @@ int make_ctx(const double* A, int64_t n, int64_t lda, const gmresir_opts* opts, 
     h->fuse_dots = !(fd && std::strcmp(fd, "0") == 0);
     const char* pe = std::getenv("GMRESIR_PERSISTENT");
     h->persistent = !(pe && std::strcmp(pe, "0") == 0);
+    const char* lf = std::getenv("GMRESIR_LU_FOLD");
+    h->lu_fold = !(lf && std::strcmp(lf, "0") == 0);
     const char* au = std::getenv("GMRESIR_CYCLE_ARRIVE_US");
     if (au && *au) h->cycle_arrive_us = std::max(0, std::min(1000000, std::atoi(au)));
     const char* os = std::getenv("GMRESIR_ORTHO_SMALL");
