@@ -51,15 +51,25 @@ __global__ __launch_bounds__(256) void k_ingest(const double* __restrict__ A, in
     const double* a = A + row * lda;
     double* d = A64 + row * ld;
     float* f = Au ? Au + row * ld : nullptr;
-    for (int64_t c = lane; c < ld; c += kWave) {
-      const double v = (c < n) ? a[c] : 0.0;
+    // lane takes columns lane + 64 i in order (the row sum's order); four of
+    // them are loaded before any is used, for more loads in flight
+    auto put = [&](int64_t c, double v) {
       d[c] = v;
       if (f) f[c] = (float)v;
       if (!__builtin_isfinite(v)) bad = 1;
       const double av = fabs(v);
       s += av;
       mx = fmax(mx, av);
+    };
+    int64_t c = lane;
+    for (; c + 3 * kWave < ld; c += 4 * kWave) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (c + u * kWave < n) ? a[c + u * kWave] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) put(c + u * kWave, v[u]);
     }
+    for (; c < ld; c += kWave) put(c, (c < n) ? a[c] : 0.0);
   }
   s = wave_sum(s);
   mx = wave_max_d(mx);
