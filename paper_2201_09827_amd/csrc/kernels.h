@@ -62,6 +62,15 @@ bool panel_update_folds(int store);
 void launch_copy_i32(int* dst, const int* src, int64_t n, hipStream_t s);
 // copy of `words` 4-byte words; either side may be mapped pinned host memory
 void launch_copy_words(void* dst, const void* src, int64_t words, hipStream_t s);
+// up to kCopyPieces such copies in one launch
+constexpr int kCopyPieces = 8;
+struct CopyPieces {
+  void* dst[kCopyPieces];
+  const void* src[kCopyPieces];
+  int64_t words[kCopyPieces];
+  int count;
+};
+void launch_copy_pieces(const CopyPieces& c, hipStream_t s);
 // after the last panel: non-finite check of the factors (S 16-byte aligned,
 // ld a multiple of 8 elements: rows are read as 16-byte vectors)
 void launch_check_factors(const void* S, int64_t n, int64_t ld, int store, int* flag,

@@ -1716,6 +1716,18 @@ __global__ void k_copy_words(uint32_t* __restrict__ dst, const uint32_t* __restr
     dst[i] = src[i];
 }
 
+// several such copies in one launch (grid row p copies piece p)
+__global__ void k_copy_pieces(CopyPieces c) {
+  const int p = blockIdx.y;
+  if (p >= c.count) return;
+  uint32_t* __restrict__ dst = static_cast<uint32_t*>(c.dst[p]);
+  const uint32_t* __restrict__ src = static_cast<const uint32_t*>(c.src[p]);
+  const int64_t n = c.words[p];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 __global__ void k_copy_f32_f64(const float* __restrict__ a, double* __restrict__ b, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (double)a[i];
@@ -2538,6 +2550,16 @@ void launch_copy_words(void* dst, const void* src, int64_t words, hipStream_t s)
   hipLaunchKernelGGL(k_copy_words, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 64)),
                      dim3(256), 0, s, reinterpret_cast<uint32_t*>(dst),
                      reinterpret_cast<const uint32_t*>(src), words);
+}
+
+void launch_copy_pieces(const CopyPieces& c, hipStream_t s) {
+  if (c.count <= 0) return;
+  int64_t most = 0;
+  for (int p = 0; p < c.count; ++p) most = std::max(most, c.words[p]);
+  if (most <= 0) return;
+  hipLaunchKernelGGL(k_copy_pieces,
+                     dim3((unsigned)std::min<int64_t>((most + 255) / 256, 64), (unsigned)c.count),
+                     dim3(256), 0, s, c);
 }
 
 void launch_gemv_au(const float* Au, int64_t ld, const int* permA, int n, const float* v32,

@@ -765,6 +765,11 @@ int alloc_common(gmresir_ctx* h) {
 // Small transfers (whole 4-byte words) are done by a copy kernel that reads or
 // writes the mapped pinned staging memory directly, which keeps them off the
 // copy engines (tens of microseconds of latency each).
+struct Piece {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
 int upload(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
   GIR_TRY(stage_init(h));
   if (bytes > kStageBytes || bytes % 4 != 0) {
@@ -800,28 +805,69 @@ int download(gmresir_ctx* h, void* dst, const void* src, size_t bytes) {
   return 0;
 }
 
-// Several device-to-host copies with one synchronisation: each piece goes
-// through the pinned download staging (hipMemcpyAsync when it does not fit),
-// then the stream is synchronised once.
-struct Piece {
-  void* dst;
-  const void* src;
-  size_t bytes;
-};
+// Several host-to-device copies in stream order: staged pieces go in one copy
+// launch (up to eight per launch); a piece that does not fit is copied as
+// upload copies it, after the staged ones before it have been launched.
+int upload_many(gmresir_ctx* h, std::initializer_list<Piece> pieces) {
+  GIR_TRY(stage_init(h));
+  gir::CopyPieces cp{};
+  auto flush = [&] {
+    gir::launch_copy_pieces(cp, h->stream);
+    cp.count = 0;
+  };
+  for (const Piece& p : pieces) {
+    if (p.bytes == 0) continue;
+    if (p.bytes > kStageBytes || p.bytes % 4 != 0) {
+      flush();
+      GIR_TRY(upload(h, p.dst, p.src, p.bytes));
+      continue;
+    }
+    if (h->up_off + p.bytes > kStageBytes) {
+      flush();
+      GIR_HIP(hipStreamSynchronize(h->stream));
+      h->up_off = 0;
+    }
+    if (cp.count == gir::kCopyPieces) flush();
+    char* st = h->up_stage + h->up_off;
+    std::memcpy(st, p.src, p.bytes);
+    cp.dst[cp.count] = p.dst;
+    cp.src[cp.count] = st;
+    cp.words[cp.count] = (int64_t)(p.bytes / 4);
+    ++cp.count;
+    h->up_off += (p.bytes + 255) & ~size_t(255);
+  }
+  flush();
+  GIR_HIP(hipGetLastError());
+  return 0;
+}
+
+// Several device-to-host copies with one synchronisation: the pieces go
+// through the pinned download staging in one copy launch (up to eight per
+// launch; hipMemcpyAsync for a piece that does not fit), then the stream is
+// synchronised once.
 int download_many(gmresir_ctx* h, std::initializer_list<Piece> pieces) {
   GIR_TRY(stage_init(h));
   size_t off = 0;
   std::vector<std::pair<const Piece*, size_t>> staged;
+  gir::CopyPieces cp{};
   for (const Piece& p : pieces) {
     if (p.bytes == 0) continue;
     if (p.bytes % 4 == 0 && off + p.bytes <= kStageBytes) {
-      gir::launch_copy_words(h->dl_stage + off, p.src, (int64_t)(p.bytes / 4), h->stream);
+      if (cp.count == gir::kCopyPieces) {
+        gir::launch_copy_pieces(cp, h->stream);
+        cp.count = 0;
+      }
+      cp.dst[cp.count] = h->dl_stage + off;
+      cp.src[cp.count] = p.src;
+      cp.words[cp.count] = (int64_t)(p.bytes / 4);
+      ++cp.count;
       staged.push_back({&p, off});
       off += (p.bytes + 255) & ~size_t(255);
     } else {
       GIR_HIP(hipMemcpyAsync(p.dst, p.src, p.bytes, hipMemcpyDeviceToHost, h->stream));
     }
   }
+  gir::launch_copy_pieces(cp, h->stream);
   GIR_HIP(hipGetLastError());
   GIR_HIP(hipStreamSynchronize(h->stream));
   for (const auto& st : staged) std::memcpy(st.first->dst, h->dl_stage + st.second, st.first->bytes);
@@ -1732,13 +1778,13 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     double* hb = h->hbuf;
     std::fill(hb, hb + m + 2, 0.0);
     hb[0] = rn;
-    GIR_TRY(upload(h, h->g, hb, sizeof(double) * (m + 2)));
-    // keep the abort and singular fields of the state
-    GIR_TRY(upload(h, h->st, &st0, offsetof(gir::CycleState, abort)));
     // the orthogonalisation's reduction ticket starts at zero (a launch
     // that gave up on a bounded wait may have left it counted)
     gir::launch_fill_i32(reinterpret_cast<int*>(h->counter), 0, 1, s);
-    GIR_TRY(upload(h, &h->st->tol, &st0.tol, 2 * sizeof(double)));
+    // g, and the state but its abort and singular fields
+    GIR_TRY(upload_many(h, {{h->g, hb, sizeof(double) * (m + 2)},
+                            {h->st, &st0, offsetof(gir::CycleState, abort)},
+                            {&h->st->tol, &st0.tol, 2 * sizeof(double)}}));
     int queued = 0;
     const size_t trec0 = h->trec.size();
     // modified Gram-Schmidt's finish pass applies zero coefficients
@@ -1918,8 +1964,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
     stats.its += J;
     if (kc == 0) {
       std::vector<double> cdv(y.begin(), y.begin() + J);
-      GIR_TRY(upload(h, h->coefA, cdv.data(), sizeof(double) * std::max(J, 1)));
-      GIR_TRY(upload(h, h->coefB, hy.data(), sizeof(double) * (J + 1)));
+      GIR_TRY(upload_many(h, {{h->coefA, cdv.data(), sizeof(double) * std::max(J, 1)},
+                              {h->coefB, hy.data(), sizeof(double) * (J + 1)}}));
       gir::launch_cycle_update(basis(h, nullptr, 0, ld, h->V, J, ld), h->coefA, h->du,
                                basis(h, nullptr, 0, ld, h->V, J + 1, ld), h->coefB, h->ru, n, h->u64, s);
       GIR_HIP(hipGetLastError());
@@ -1955,8 +2001,8 @@ int gcrodr(gmresir_ctx* h, SolveStats& stats) {
       }
       for (int c = 0; c < J; ++c) cdv[kc + c] = y[c];
       for (int i = 0; i <= J; ++i) crv[kc + i] = hy[i];
-      GIR_TRY(upload(h, h->coefA, cdv.data(), sizeof(double) * cdv.size()));
-      GIR_TRY(upload(h, h->coefB, crv.data(), sizeof(double) * crv.size()));
+      GIR_TRY(upload_many(h, {{h->coefA, cdv.data(), sizeof(double) * cdv.size()},
+                              {h->coefB, crv.data(), sizeof(double) * crv.size()}}));
       gir::launch_cycle_update(basis(h, h->U, kc, ld, h->V, J, ld), h->coefA, h->du,
                                basis(h, h->C, kc, ld, h->V, J + 1, ld), h->coefB, h->ru, n, h->u64, s);
       GIR_HIP(hipGetLastError());
