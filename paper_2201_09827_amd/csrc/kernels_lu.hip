@@ -928,10 +928,12 @@ __device__ __forceinline__ void gemm_tile(GemmSmem<typename F::T>& sm,
 // rounded to u_f once, so the factors are unchanged.  Each wave forms the
 // products of its own 64 rows (2 x 2 blocks) from its own LDS region and
 // hands each row's sums to the row's lane through that region, 32 columns at
-// a time.  U12 of these 64 columns (the block row's solve with L11) is formed
-// here too, by threads 0 .. 255 as k_trsm forms it (a quad per column, the
-// same order of fused multiply-adds), and kept in PanelPreSmem::u12 for the
-// write-back.  x receives the row's updated values (u_f values in fp32).  The
+// a time.  With kSolve, U12 of these 64 columns (the block row's solve with
+// L11) is formed here too, by threads 0 .. 255 as k_trsm forms it (a quad per
+// column, the same order of fused multiply-adds), and kept in
+// PanelPreSmem::u12 for the write-back; without it U12 is read as the launch
+// before solved it.  x receives the row's updated values (u_f values in
+// fp32).  The
 // block column is a full one (a further block column follows it), so no
 // column is masked: per-column bounds tests here were kept live by the
 // compiler through the whole pivot search, for the write-back's tests, and
