@@ -6,6 +6,7 @@
 #include <cstring>
 #include <limits>
 #include <numeric>
+#include <type_traits>
 
 namespace gir {
 namespace la {
@@ -206,21 +207,33 @@ struct SchurR {
   }
 
   // T <- P T P on rows k .. k+len-1 (columns c0 .. N-1) and columns
-  // k .. k+len-1 (rows 0 .. r1); the transformation is recorded
-  void apply(const Refl& p, int c0, int r1) {
-    if (p.beta == 0.0) return;
+  // k .. k+len-1 (rows 0 .. r1); the transformation is recorded.  The length
+  // is a template argument so that the short loops unroll (the same
+  // operations in the same order).
+  template <int L>
+  void apply_len(const Refl& p, int c0, int r1) {
+    double* tk = T.data() + p.k;  // row k of column 0
     for (int j = c0; j < N; ++j) {
+      double* col = tk + (size_t)j * N;
       double d = 0.0;
-      for (int i = 0; i < p.len; ++i) d += p.v[i] * t(p.k + i, j);
+      for (int i = 0; i < L; ++i) d += p.v[i] * col[i];
       d *= p.beta;
-      for (int i = 0; i < p.len; ++i) t(p.k + i, j) -= d * p.v[i];
+      for (int i = 0; i < L; ++i) col[i] -= d * p.v[i];
     }
+    double* ck = T.data() + (size_t)p.k * N;  // column k
     for (int i = 0; i <= r1; ++i) {
       double d = 0.0;
-      for (int q = 0; q < p.len; ++q) d += t(i, p.k + q) * p.v[q];
+      for (int q = 0; q < L; ++q) d += ck[(size_t)q * N + i] * p.v[q];
       d *= p.beta;
-      for (int q = 0; q < p.len; ++q) t(i, p.k + q) -= d * p.v[q];
+      for (int q = 0; q < L; ++q) ck[(size_t)q * N + i] -= d * p.v[q];
     }
+  }
+  void apply(const Refl& p, int c0, int r1) {
+    if (p.beta == 0.0) return;
+    if (p.len == 3)
+      apply_len<3>(p, c0, r1);
+    else
+      apply_len<2>(p, c0, r1);
     refl.push_back(p);
   }
 
@@ -230,6 +243,7 @@ struct SchurR {
     hv.assign((size_t)N * N, 0.0);
     hb.assign(N, 0.0);
     refl.clear();
+    refl.reserve((size_t)N * 48);
     w.assign(N, cd(0.0));
     // Householder reduction to upper Hessenberg form
     for (int c = 0; c + 2 < N; ++c) {
@@ -409,13 +423,21 @@ struct SchurR {
     }
     // Z = H_0 .. H_{N-3} P_1 .. P_R: the sweep reflectors last to first,
     // then the Hessenberg reflectors last to first
+    auto replay = [&](const Refl& p, auto len) {
+      constexpr int L = decltype(len)::value;
+      cd* xk = x.data() + p.k;
+      cd d = 0.0;
+      for (int i = 0; i < L; ++i) d += p.v[i] * xk[i];
+      d *= p.beta;
+      for (int i = 0; i < L; ++i) xk[i] -= d * p.v[i];
+    };
     for (size_t q = refl.size(); q-- > 0;) {
       const Refl& p = refl[q];
       if (p.beta == 0.0) continue;
-      cd d = 0.0;
-      for (int i = 0; i < p.len; ++i) d += p.v[i] * x[p.k + i];
-      d *= p.beta;
-      for (int i = 0; i < p.len; ++i) x[p.k + i] -= d * p.v[i];
+      if (p.len == 3)
+        replay(p, std::integral_constant<int, 3>{});
+      else
+        replay(p, std::integral_constant<int, 2>{});
     }
     for (int c = N - 3; c >= 0; --c) {
       if (hb[c] == 0.0) continue;
