@@ -7,7 +7,8 @@ as the separate launches form it (the same matrix-core instruction over the
 same k steps at the same position in its 32 x 32 block, the same order of
 fused multiply-adds in the solve), so the exported factors must agree bit
 for bit with GMRESIR_LU_FOLD=0 at handle creation, which keeps the separate
-launches.  The orders cover one, two and many workgroups per block column,
+launches.  The orders cover one, two and many workgroups per block column (up to the
+exchange's 32 at n = 16384),
 block counts that are not multiples of the tile grid, both fold forms (the
 solve moves in only once the update has at most 5.5 rounds of tiles over the
 compute units: at n = 8192 from step 54 on) and a final partial block
@@ -42,7 +43,8 @@ def _factors(lib, monkeypatch, a, uf, fold):
 
 
 @pytest.mark.parametrize("n,uf", [(300, "fp16"), (700, "bf16"), (1100, "fp16"),
-                                  (3000, "bf16"), (4800, "fp16"), (8192, "fp16")])
+                                  (3000, "bf16"), (4800, "fp16"), (8192, "fp16"),
+                                  (16384, "bf16")])
 def test_folded_block_column_factors_bit_identical(lib, monkeypatch, n, uf):
     log(f"lu fold n={n} uf={uf}")
     a, _, _ = randsvd_problem_torch(n, 1e6, 7, device="cuda")
